@@ -1,0 +1,28 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP path)")
+    config.addinivalue_line("markers", "slow: oracle cases that take tens of seconds")
+
+
+def golden(name):
+    return os.path.join(ROOT, "tests", "golden", name)
+
+
+def read_remarks():
+    out = {}
+    with open(golden("paper_remarks.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            key, val = line.split()[:2]
+            out[key] = float(val)
+    return out

@@ -1,0 +1,166 @@
+"""Seeded synthetic inputs shared by the oracle and the HIP path.
+
+This module holds workload descriptions and random draws only: mesh sizes,
+subdomain cuts, physical parameters, the stimulus indicator and the initial
+perturbation.  It contains none of the solver's arithmetic, so that both the
+oracle and the device path can consume the same inputs without sharing any
+of the method's code.
+
+Unit system (cm, ms, mV, uA/cm^3): conductivities in mS/cm, chi*C_m in
+uF/cm^3, the ionic current per unit volume is chi times the Rogers-McCulloch
+current with G and eta_1 in mS/cm^2.  Parameter values follow the paper's
+table of physiological coefficients (Sec. 6); the conductivities are that
+table's values in mS/cm.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Sequence
+
+import numpy as np
+
+
+@dataclasses.dataclass(frozen=True)
+class Physics:
+    sigma_i: tuple = (3.0, 0.31525, 0.031525)      # l, t, n  (mS/cm)
+    sigma_e: tuple = (2.0, 1.3514, 0.6757)         # l, t, n  (mS/cm)
+    theta0: float = 0.0                             # fibre angle at z = 0 (rad)
+    theta1: float = 2.0 * math.pi / 3.0             # fibre angle at z = L_z (rad)
+    chi: float = 1000.0                             # 1/cm
+    Cm: float = 1.0                                 # uF/cm^2
+    G: float = 1.2                                  # mS/cm^2
+    eta1: float = 4.4                               # mS/cm^2
+    eta2: float = 0.012                             # 1/ms
+    vth: float = 13.0                               # mV
+    vp: float = 100.0                               # mV
+
+
+@dataclasses.dataclass(frozen=True)
+class Mesh:
+    nx: int
+    ny: int
+    nz: int
+    h: float
+    cuts_x: tuple
+    cuts_y: tuple
+    cuts_z: tuple
+
+    @property
+    def nnodes(self) -> int:
+        return (self.nx + 1) * (self.ny + 1) * (self.nz + 1)
+
+    @property
+    def nsub(self) -> int:
+        return (len(self.cuts_x) - 1) * (len(self.cuts_y) - 1) * (len(self.cuts_z) - 1)
+
+
+@dataclasses.dataclass(frozen=True)
+class Solver:
+    dt: float = 0.05
+    newton_rtol: float = 1e-8
+    newton_atol: float = 0.0
+    newton_maxit: int = 20
+    krylov_rtol: float = 1e-10
+    krylov_maxit: int = 500
+    krylov_dtol: float = 1e4
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    name: str
+    mesh: Mesh
+    physics: Physics
+    solver: Solver
+    stim_amplitude: float          # uA/cm^3
+    stim_block: tuple              # elements (bx, by, bz) from the origin corner
+    stim_steps: int                # number of steps carrying the stimulus
+    steps: int
+    perturb_seed: int | None       # seed of the +/-1% initial v perturbation (None: rest)
+
+
+def uniform_cuts(n: int, parts: int) -> tuple:
+    if n % parts:
+        raise ValueError(f"{n} elements do not split into {parts} equal parts")
+    w = n // parts
+    return tuple(range(0, n + 1, w))
+
+
+def uneven_cuts(n: int, parts: int, widths: Sequence[int], seed: int) -> tuple:
+    """Cut positions with per-part widths drawn from ``widths`` and rejection
+    resampled until they sum to ``n`` (tensor partition, conforming faces)."""
+    rng = np.random.default_rng(seed)
+    widths = np.asarray(widths)
+    for _ in range(100000):
+        w = rng.choice(widths, size=parts)
+        if int(w.sum()) == n:
+            return tuple(int(c) for c in np.concatenate([[0], np.cumsum(w)]))
+    raise RuntimeError("could not draw widths summing to n")
+
+
+def box_mesh(nx, ny, nz, h, px, py, pz) -> Mesh:
+    return Mesh(nx, ny, nz, h, uniform_cuts(nx, px), uniform_cuts(ny, py), uniform_cuts(nz, pz))
+
+
+def stimulus_nodal(mesh: Mesh, block: tuple, amplitude: float, origin=(0, 0, 0)) -> np.ndarray:
+    """Nodal stimulus I_s: ``amplitude`` on every node of the element block
+    [origin, origin + block) (closed node range), zero elsewhere."""
+    nx1, ny1 = mesh.nx + 1, mesh.ny + 1
+    out = np.zeros(mesh.nnodes)
+    ox, oy, oz = origin
+    bx, by, bz = block
+    for k in range(oz, oz + bz + 1):
+        for j in range(oy, oy + by + 1):
+            for i in range(ox, ox + bx + 1):
+                out[i + nx1 * (j + ny1 * k)] = amplitude
+    return out
+
+
+def initial_state(mesh: Mesh, physics: Physics, seed: int | None):
+    """Resting state, optionally with an additive v perturbation of
+    0.01 * v_p * U(-1, 1) per node (i.i.d., seeded)."""
+    n = mesh.nnodes
+    v = np.zeros(n)
+    if seed is not None:
+        rng = np.random.default_rng(seed)
+        v = 0.01 * physics.vp * rng.uniform(-1.0, 1.0, size=n)
+    ue = np.zeros(n)
+    w = np.zeros(n)
+    return v, ue, w
+
+
+def random_field(n: int, seed: int, scale: float = 1.0) -> np.ndarray:
+    return scale * np.random.default_rng(seed).standard_normal(n)
+
+
+PAPER_STIM = 1.0e5     # 100 mA/cm^3 expressed in uA/cm^3
+
+
+def workload(name: str) -> Workload:
+    """Named workloads: the parity-size slab (8^3, 2x2x2), the 32^3 slab in
+    4x4x4 subdomains, the 128x128x64 slab with uneven cuts, and the
+    256x256x128 slab in 32x32x16 subdomains (about 17.04M dofs)."""
+    ph = Physics()
+    if name == "slab8":
+        m = box_mesh(8, 8, 8, 0.01, 2, 2, 2)
+        return Workload(name, m, ph, Solver(), 250.0, (2, 2, 2), 20, 5, None)
+    if name == "slab8_supra":
+        m = box_mesh(8, 8, 8, 0.01, 2, 2, 2)
+        return Workload(name, m, ph, Solver(), PAPER_STIM, (2, 2, 2), 20, 5, None)
+    if name == "slab32":
+        m = box_mesh(32, 32, 32, 0.01, 4, 4, 4)
+        return Workload(name, m, ph, Solver(), PAPER_STIM, (2, 2, 2), 20, 40, 1)
+    if name == "slab128_uneven":
+        m = Mesh(128, 128, 64, 0.01,
+                 uneven_cuts(128, 16, range(6, 11), 2),
+                 uneven_cuts(128, 16, range(6, 11), 3),
+                 uneven_cuts(64, 8, range(6, 11), 4))
+        return Workload(name, m, ph, Solver(), PAPER_STIM, (2, 2, 2), 20, 20, 1)
+    if name == "slab256":
+        m = box_mesh(256, 256, 128, 0.01, 32, 32, 16)
+        return Workload(name, m, ph, Solver(), PAPER_STIM, (2, 2, 2), 20, 50, None)
+    raise KeyError(name)
+
+
+def small_mesh(n: Sequence[int], parts: Sequence[int], h: float = 0.01) -> Mesh:
+    return box_mesh(n[0], n[1], n[2], h, parts[0], parts[1], parts[2])
