@@ -1,0 +1,188 @@
+/*
+ * bidomain.h -- C ABI of libbidomain: Newton-Krylov BDDC / FETI-DP deluxe
+ * solver for the segregated implicit Bidomain time step on one MI355X.
+ *
+ * Method: Huynh, Pavarino, Scacchi, "Parallel Newton-Krylov-BDDC and FETI-DP
+ * deluxe solvers for implicit time discretizations of the cardiac Bidomain
+ * equations" (arXiv:2101.02959).  Section numbers below refer to that paper.
+ *
+ * Conventions (all calls):
+ *   - Return 0 on success or a negative BDM_E_* code; bdm_last_error() gives
+ *     a thread-local message for the last failure.  No C++ exception crosses
+ *     this interface.
+ *   - Global node numbering is lexicographic, x fastest:
+ *       node(i,j,k) = i + (nx+1)*(j + (ny+1)*k),  N = (nx+1)(ny+1)(nz+1).
+ *     "2N vectors" are blocked [v (N doubles) ; u_e (N doubles)].
+ *   - Unknowns are (v, u_e) with v = u_i - u_e.  The library solves the
+ *     congruent form T^T (F(T x) - G) = 0 of the paper's Step-2 system
+ *     (Sec. 3b), T = [[I, I], [0, I]]: first row is the u_i equation, second
+ *     row the sum of the two equations.  The Jacobian is symmetric positive
+ *     semidefinite with kernel (v = 0, u_e = const); u_e is gauged to zero
+ *     nodal mean.
+ *   - Pointers marked "device" must be device memory of the context's GPU;
+ *     work is ordered on the context's HIP stream and the call returns after
+ *     the stream has been synchronised unless stated otherwise.  The caller
+ *     owns every array passed in; the library owns the context and all of its
+ *     workspace.
+ *   - Unit system: cm, ms, mV, uA/cm^3; sigma in mS/cm; chi in 1/cm;
+ *     C_m in uF/cm^2; G, eta_1 in mS/cm^2 (the ionic current per unit volume
+ *     is chi * I_ion); eta_2 in 1/ms.
+ */
+#ifndef BIDOMAIN_H
+#define BIDOMAIN_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    BDM_OK = 0,
+    BDM_E_ARG = -1,              /* invalid argument or unsupported layout   */
+    BDM_E_OOM = -2,              /* device allocation failed                 */
+    BDM_E_HIP = -3,              /* HIP runtime error                        */
+    BDM_E_NOT_SPD = -4,          /* a local, deluxe or coarse factor failed  */
+    BDM_E_KRYLOV_DIVERGED = -5,  /* ||r_k|| > dtol ||r_0||                   */
+    BDM_E_KRYLOV_MAXIT = -6,     /* Krylov iteration limit reached           */
+    BDM_E_NEWTON_MAXIT = -7,     /* Newton iteration limit reached           */
+    BDM_E_COERCIVITY = -8,       /* reaction diagonal <= 0 (Sec. 3c lemma)   */
+    BDM_E_STATE = -9             /* call order violated (e.g. no linearize)  */
+};
+
+enum { BDM_SOLVER_BDDC = 0, BDM_SOLVER_FETIDP = 1 };
+enum { BDM_PREC_FP64 = 0, BDM_PREC_MIXED = 1 };
+enum { BDM_GUESS_PREV = 0, BDM_GUESS_EXTRAP = 1 };
+enum { BDM_FETI_F = 0, BDM_FETI_PRECOND = 1, BDM_FETI_RHS = 2, BDM_FETI_RECOVER = 3 };
+
+/* Structured hexahedral Q1 mesh of nx*ny*nz cubes of side h (Sec. 3a) and a
+ * tensor-product partition into non-overlapping box subdomains (Sec. 4.1):
+ * cuts_x[0..px] are element indices with cuts_x[0] = 0, cuts_x[px] = nx,
+ * strictly increasing; likewise y, z.  px, py, pz >= 2 (every subdomain must
+ * touch an interior cross point for the vertex + edge primal space). */
+typedef struct bdm_mesh {
+    int nx, ny, nz;
+    double h;
+    int px, py, pz;
+    const int* cuts_x;
+    const int* cuts_y;
+    const int* cuts_z;
+} bdm_mesh;
+
+/* Conductivities along (l, t, n) (Sec. 2, D = sum sigma a a^T), fibre angle
+ * rotating linearly in the xy-plane from theta0 at z = 0 to theta1 at the top,
+ * evaluated at element centroids; Rogers-McCulloch parameters (Sec. 2). */
+typedef struct bdm_physics {
+    double sigma_i[3];
+    double sigma_e[3];
+    double theta0, theta1;
+    double chi, Cm;
+    double G, eta1, eta2, vth, vp;
+} bdm_physics;
+
+/* Time step and solver options (Sec. 3b-c, Sec. 6 tolerances). */
+typedef struct bdm_opts {
+    double dt;                  /* tau (ms)                                  */
+    double newton_rtol;         /* stop: ||R(u^k)|| <= rtol ||R(u^n)||       */
+    double newton_atol;         /*   or  ||R(u^k)|| <= atol                  */
+    int newton_maxit;
+    double krylov_rtol;         /* ||r_k||_2 <= rtol ||r_0||_2               */
+    double krylov_dtol;         /* divergence when ||r_k|| > dtol ||r_0||    */
+    int krylov_maxit;
+    int solver;                 /* BDM_SOLVER_*                              */
+    int precision;              /* BDM_PREC_*: local factors in FP64 or FP32 */
+    int guess;                  /* BDM_GUESS_*                               */
+} bdm_opts;
+
+/* Per-step statistics filled by bdm_step (for its last step). */
+typedef struct bdm_step_stats {
+    int newton_its;
+    int krylov_its[32];         /* per Newton iteration                      */
+    double res_hist[33];        /* ||R|| before each Newton iteration        */
+    double cond[32];            /* Lanczos estimate per Krylov solve         */
+    double t_setup_ms;          /* preconditioner setup time (all Newton its)*/
+    double t_krylov_ms;         /* Krylov loop time                          */
+    double t_step_ms;           /* whole step                                */
+    int bad_subdomain;          /* first subdomain whose factor failed or -1 */
+} bdm_step_stats;
+
+typedef struct bdm_ctx bdm_ctx;
+
+/* Create a context on the current HIP device.  hip_stream is a hipStream_t
+ * (NULL = default stream).  Builds the partition, the N_x classification
+ * into faces / edges / vertices (Sec. 4.1), index maps and element
+ * matrices, and allocates all device workspace.  The state is set to rest
+ * (v = u_e = w = 0), no stimulus. */
+int bdm_create(const bdm_mesh* mesh, const bdm_physics* phys, const bdm_opts* opts,
+               void* hip_stream, bdm_ctx** out);
+
+/* Free every device allocation owned by the context. */
+int bdm_destroy(bdm_ctx* ctx);
+
+/* Copy the state (v, u_e, w: N doubles each, host or device pointers per
+ * on_device) into / out of the context.  u_e is gauged to zero mean on input.
+ * The previous-step history used for extrapolated guesses is reset. */
+int bdm_set_state(bdm_ctx* ctx, const double* v, const double* ue, const double* w,
+                  double t, int on_device);
+int bdm_get_state(bdm_ctx* ctx, double* v, double* ue, double* w, double* t, int on_device);
+
+/* Nodal transmembrane stimulus I_s (N doubles, uA/cm^3; host or device per
+ * on_device), applied in the steps n with step_on <= n < step_off, evaluated
+ * at t_{n+1}: it enters the first residual row as -tau * M * I_s. */
+int bdm_set_stimulus(bdm_ctx* ctx, const double* Is, int step_on, int step_off, int on_device);
+
+/* Step 1 of the decoupled scheme (Sec. 3b): w <- (w + tau eta_2 v / v_p) /
+ * (1 + tau eta_2), the exact solution of w - tau R(v^n, w) = w^n. */
+int bdm_ionic_update(bdm_ctx* ctx);
+
+/* Residual R(v, u_e) of Step 2 (Sec. 3b) at the given iterate (device, N
+ * each) with v^n, w^{n+1} and the stimulus taken from the context's state.
+ * Outputs Rv, Re (device, N each). */
+int bdm_residual(bdm_ctx* ctx, const double* v, const double* ue, double* Rv, double* Re);
+
+/* Build the Jacobian (Sec. 3c) at (v_lin, w_lin) (device, N each) and every
+ * preconditioner factor: local Dirichlet factors of K_II, local Schur
+ * complements, constrained Neumann factors with edge-average constraints,
+ * the coarse basis and coarse matrix (Sec. 4.4), and the deluxe face / edge
+ * factors (Sec. 4.2).  Returns BDM_E_COERCIVITY if a reaction diagonal is
+ * not positive and BDM_E_NOT_SPD if a factorisation fails. */
+int bdm_linearize(bdm_ctx* ctx, const double* v_lin, const double* w_lin);
+
+/* y = J x for 2N device vectors (matrix-free Q1 stencils, Sec. 3a-c). */
+int bdm_jacobian_apply(bdm_ctx* ctx, const double* x, double* y);
+
+/* z = M^{-1}_BDDC r on the full system (2N device vectors) at the last
+ * linearisation (Sec. 4.4 with static condensation, Sec. 4.1): interior
+ * Dirichlet correction, deluxe E_D^T, constrained local Neumann solves plus
+ * coarse solve, deluxe E_D, discrete harmonic extension.  z is defined up to
+ * the kernel (v = 0, u_e = const). */
+int bdm_bddc_apply(bdm_ctx* ctx, const double* r, double* z);
+
+/* Number of FETI-DP multipliers: one per face dof and one per dof and per
+ * pair of subdomains sharing an edge (fully redundant), Sec. 4.3. */
+int bdm_fetidp_size(bdm_ctx* ctx, long* n_lambda);
+
+/* FETI-DP operators at the last linearisation (Sec. 4.3), device pointers:
+ *   BDM_FETI_F        in = lambda (n_lambda), out = F lambda = B S~^{-1} B^T lambda
+ *   BDM_FETI_PRECOND  in = lambda, out = B_D S_Gamma B_D^T lambda
+ *   BDM_FETI_RHS      in = r (2N), out = d = B S~^{-1} f~ (n_lambda), where f~
+ *                     is the interior-condensed residual split 1/|N_x|
+ *   BDM_FETI_RECOVER  in = [r (2N) ; lambda (n_lambda)], out = z (2N):
+ *                     w = S~^{-1}(f~ - B^T lambda), z_I by a Dirichlet solve */
+int bdm_fetidp_apply(bdm_ctx* ctx, int op, const double* in, double* out);
+
+/* Advance nsteps time steps: Step 1 then Newton (line search on ||R||^2,
+ * Armijo alpha = 1e-4) with PCG preconditioned by BDDC, or FETI-DP PCG on
+ * the multipliers plus recovery, per opts.solver.  stats may be NULL. */
+int bdm_step(bdm_ctx* ctx, int nsteps, bdm_step_stats* stats);
+
+/* Sizes for callers that allocate vectors: N, number of subdomains, global
+ * primal (coarse) dimension. */
+int bdm_sizes(bdm_ctx* ctx, long* n_nodes, long* n_sub, long* n_primal);
+
+/* Thread-local message describing the last error ("" if none). */
+const char* bdm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BIDOMAIN_H */

@@ -1,0 +1,464 @@
+// Per-iteration kernels of the BDDC and FETI-DP deluxe preconditioners
+// (paper Sec. 4.2 - 4.4): gathers / scatters between the global (v, u_e)
+// vectors and the per-subdomain local vectors, deluxe averaging on faces
+// and edges, the coarse right-hand side and prolongation, and the FETI-DP
+// jump operators.  Every reduction runs in a fixed order, so results are
+// bitwise reproducible from run to run.
+#include "bddc_kernels.hpp"
+#include "common.hpp"
+
+namespace bdm {
+
+constexpr int MAXO = 512;       // largest face / edge object (dofs)
+constexpr int MAXC = 24;
+constexpr int MAXP = 40;
+
+namespace {
+
+__device__ inline double wsum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <typename T>
+__global__ void k_gather_I(int n, const int* __restrict__ list, int64_t N, const double* __restrict__ r,
+                           const double* __restrict__ q, T* __restrict__ x) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int64_t g = list[t];
+    double a = r[g], b = r[N + g];
+    if (q) { a -= q[g]; b -= q[N + g]; }
+    x[2 * (int64_t)t] = (T)a;
+    x[2 * (int64_t)t + 1] = (T)b;
+}
+
+template <typename T>
+__global__ void k_scatter_I(int n, const int* __restrict__ list, int64_t N, const T* __restrict__ x,
+                            double* __restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int64_t g = list[t];
+    out[g] = (double)x[2 * (int64_t)t];
+    out[N + g] = (double)x[2 * (int64_t)t + 1];
+}
+
+// In-LDS solve (L L^T) h = h with a dense lower factor (n x n, col-major).
+template <typename T>
+__device__ void chol_solve_lds(const T* __restrict__ L, int n, double* h) {
+    const int tid = threadIdx.x;
+    for (int k = 0; k < n; ++k) {
+        if (tid == 0) h[k] /= (double)L[k + (int64_t)k * n];
+        __syncthreads();
+        const double hk = h[k];
+        for (int i = k + 1 + tid; i < n; i += blockDim.x) h[i] -= (double)L[i + (int64_t)k * n] * hk;
+        __syncthreads();
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        // h[k] = (h[k] - sum_{i>k} L[i][k] h[i]) / L[k][k]
+        double part = 0.0;
+        for (int i = k + 1 + tid; i < n; i += blockDim.x) part += (double)L[i + (int64_t)k * n] * h[i];
+        part = wsum(part);
+        __shared__ double red[kWG / 64];
+        if ((tid & 63) == 0) red[tid >> 6] = part;
+        __syncthreads();
+        if (tid == 0) {
+            double acc = 0.0;
+            for (int q = 0; q < (int)(blockDim.x >> 6); ++q) acc += red[q];
+            h[k] = (h[k] - acc) / (double)L[k + (int64_t)k * n];
+        }
+        __syncthreads();
+    }
+}
+
+// Residual side of the deluxe scaling, E_D^T: for an object shared by
+// subdomains m, g^(m) = S^(m) (sum S)^{-1} g.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_deluxe_res(ObjDesc o, int64_t N, const double* __restrict__ g,
+                                                   const T* __restrict__ slots, const T* __restrict__ fac,
+                                                   T* __restrict__ xr, const int64_t* __restrict__ xoff) {
+    const int ob = blockIdx.x, tid = threadIdx.x;
+    const int n = o.n[ob];
+    __shared__ double h[MAXO];
+    const int* nodes = o.nodes + o.node_off[ob];
+    for (int i = tid; i < n; i += kWG) h[i] = g[(i & 1) * N + nodes[i >> 1]];
+    __syncthreads();
+    chol_solve_lds(fac + o.fac_off[ob], n, h);
+    for (int q = o.sh_ptr[ob]; q < o.sh_ptr[ob + 1]; ++q) {
+        const T* S = slots + o.sh_slot[q];
+        T* dst = xr + xoff[o.sh_sub[q]] + o.sh_roff[q];
+        for (int i = tid; i < n; i += kWG) {
+            double acc = 0.0;
+            for (int j = 0; j < n; ++j) acc += (double)S[i + (int64_t)j * n] * h[j];
+            dst[i] = (T)acc;
+        }
+    }
+}
+
+// Value side of the deluxe scaling, E_D: u = (sum S)^{-1} sum_m S^(m) u^(m).
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_deluxe_val(ObjDesc o, int64_t N, const T* __restrict__ slots,
+                                                   const T* __restrict__ fac, const T* __restrict__ xr,
+                                                   const int64_t* __restrict__ xoff, double* __restrict__ z) {
+    const int ob = blockIdx.x, tid = threadIdx.x;
+    const int n = o.n[ob];
+    __shared__ double h[MAXO];
+    for (int i = tid; i < n; i += kWG) {
+        double acc = 0.0;
+        for (int q = o.sh_ptr[ob]; q < o.sh_ptr[ob + 1]; ++q) {
+            const T* S = slots + o.sh_slot[q];
+            const T* u = xr + xoff[o.sh_sub[q]] + o.sh_roff[q];
+            for (int j = 0; j < n; ++j) acc += (double)S[i + (int64_t)j * n] * (double)u[j];
+        }
+        h[i] = acc;
+    }
+    __syncthreads();
+    chol_solve_lds(fac + o.fac_off[ob], n, h);
+    const int* nodes = o.nodes + o.node_off[ob];
+    for (int i = tid; i < n; i += kWG) z[(i & 1) * N + nodes[i >> 1]] = h[i];
+}
+
+// Per subdomain after the forward Neumann solve x1 = L_rr^{-1} g_r:
+//   cP = Z^T x1 (the local coarse right-hand side Phi^T g),
+//   mu = G^{-1} Y^T x1 (edge-average multipliers).
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_coarse_rhs_local(SubVecDesc d, const T* __restrict__ xr,
+                                                         const T* __restrict__ Fb, const T* __restrict__ Zb,
+                                                         const T* __restrict__ Gib, double* __restrict__ cP,
+                                                         double* __restrict__ mu) {
+    const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int nr = d.nr[s], nV = d.nV[s], nc = d.nc[s], nP = nV + nc;
+    const T* x = xr + d.xoff[s];
+    const T* Y = Fb + d.F_off[s];
+    const T* Z = Zb + d.Z_off[s];
+    __shared__ double ytx[MAXC];
+    for (int o = wv; o < nP + nc; o += kWG / 64) {
+        const T* col = (o < nP) ? Z + (int64_t)o * nr : Y + (int64_t)(o - nP) * nr;
+        double acc = 0.0;
+        for (int r = lane; r < nr; r += 64) acc += (double)col[r] * (double)x[r];
+        acc = wsum(acc);
+        if (lane == 0) {
+            if (o < nP) cP[(int64_t)s * MAXP + o] = acc;
+            else ytx[o - nP] = acc;
+        }
+    }
+    __syncthreads();
+    const T* Gi = Gib + (int64_t)s * MAXC * MAXC;
+    if (tid < nc) {
+        double acc = 0.0;
+        for (int m = 0; m < nc; ++m) acc += (double)Gi[tid + m * nc] * ytx[m];
+        mu[(int64_t)s * MAXC + tid] = acc;
+    }
+}
+
+// Coarse right-hand side: the assembled vertex residual plus the gathered
+// local contributions Phi_j^T g^(j) (fixed order per primal dof).
+__global__ void k_coarse_rhs_gather(CoarseDesc c, int64_t N, const double* __restrict__ g,
+                                    const double* __restrict__ cP, double* __restrict__ b) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= c.np) return;
+    double acc = (p < 2 * c.nverts) ? g[(p & 1) * N + c.vnode[p >> 1]] : 0.0;
+    for (int q = c.cp_ptr[p]; q < c.cp_ptr[p + 1]; ++q) acc += cP[(int64_t)c.cp_sub[q] * MAXP + c.cp_loc[q]];
+    b[p] = acc;
+}
+
+// Remove the kernel component (u_e-primal constant) and pin one u_e primal.
+__global__ void k_coarse_project(int np, int pin, double* __restrict__ b) {
+    const int tid = threadIdx.x;
+    double part = 0.0;
+    for (int p = 1 + 2 * tid; p < np; p += 2 * kWG) part += b[p];
+    part = wsum(part);
+    __shared__ double red[kWG / 64];
+    if ((tid & 63) == 0) red[tid >> 6] = part;
+    __syncthreads();
+    double tot = 0.0;
+    for (int q = 0; q < kWG / 64; ++q) tot += red[q];
+    const double mean = tot / (np / 2);
+    for (int p = 1 + 2 * tid; p < np; p += 2 * kWG) b[p] -= mean;
+    __syncthreads();
+    if (tid == 0) b[pin] = 0.0;
+}
+
+// x_r <- x1 - Y mu + Z u_c(primal of s): right-hand side of the combined
+// backward solve that yields the Neumann correction plus the coarse
+// prolongation Phi_r u_c.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_neumann_rhs(SubVecDesc d, const T* __restrict__ Fb,
+                                                    const T* __restrict__ Zb, const double* __restrict__ mu,
+                                                    const double* __restrict__ uc, T* __restrict__ xr,
+                                                    int with_mu) {
+    const int s = blockIdx.x, tid = threadIdx.x;
+    const int nr = d.nr[s], nV = d.nV[s], nc = d.nc[s], nP = nV + nc;
+    const T* Y = Fb + d.F_off[s];
+    const T* Z = Zb + d.Z_off[s];
+    const int* prim = d.primal + d.P_off[s];
+    __shared__ double m[MAXC];
+    __shared__ double u[MAXP];
+    if (tid < nc) m[tid] = with_mu ? mu[(int64_t)s * MAXC + tid] : 0.0;
+    if (tid < nP) u[tid] = uc ? uc[prim[tid]] : 0.0;
+    __syncthreads();
+    T* x = xr + d.xoff[s];
+    for (int r = tid; r < nr; r += kWG) {
+        double acc = (double)x[r];
+        for (int e = 0; e < nc; ++e) acc -= (double)Y[r + (int64_t)e * nr] * m[e];
+        for (int p = 0; p < nP; ++p) acc += (double)Z[r + (int64_t)p * nr] * u[p];
+        x[r] = (T)acc;
+    }
+}
+
+__global__ void k_vertex_val(int nv, const int* __restrict__ vnode, int64_t N, const double* __restrict__ uc,
+                             double* __restrict__ z) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    z[vnode[v]] = uc[2 * v];
+    z[N + vnode[v]] = uc[2 * v + 1];
+}
+
+// ------------------------------------------------------------- FETI-DP
+// Multiplier blocks: (object, pair a < b); lam_ab = w^(a) - w^(b) on the
+// object's dofs.  B^T: subdomain m receives sum_{(m,b)} lam - sum_{(a,m)} lam.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_feti_BT(ObjDesc o, FetiDesc f, const double* __restrict__ lam,
+                                                T* __restrict__ xr, const int64_t* __restrict__ xoff) {
+    const int ob = blockIdx.x, tid = threadIdx.x;
+    const int n = o.n[ob];
+    for (int q = o.sh_ptr[ob]; q < o.sh_ptr[ob + 1]; ++q) {
+        const int m = o.sh_sub[q];
+        T* dst = xr + xoff[m] + o.sh_roff[q];
+        for (int i = tid; i < n; i += kWG) {
+            double acc = 0.0;
+            for (int pq = f.pr_ptr[ob]; pq < f.pr_ptr[ob + 1]; ++pq) {
+                const double l = lam[f.pr_off[pq] + i];
+                if (f.pr_a[pq] == m) acc += l;
+                else if (f.pr_b[pq] == m) acc -= l;
+            }
+            dst[i] = (T)acc;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_feti_B(ObjDesc o, FetiDesc f, const T* __restrict__ xr,
+                                               const int64_t* __restrict__ xoff, double* __restrict__ lam) {
+    const int ob = blockIdx.x, tid = threadIdx.x;
+    const int n = o.n[ob];
+    for (int pq = f.pr_ptr[ob]; pq < f.pr_ptr[ob + 1]; ++pq) {
+        const T* wa = xr + xoff[o.sh_sub[f.pr_qa[pq]]] + o.sh_roff[f.pr_qa[pq]];
+        const T* wb = xr + xoff[o.sh_sub[f.pr_qb[pq]]] + o.sh_roff[f.pr_qb[pq]];
+        for (int i = tid; i < n; i += kWG) lam[f.pr_off[pq] + i] = (double)wa[i] - (double)wb[i];
+    }
+}
+
+// B_D^T: subdomain m receives (sum S)^{-1} [ sum_{(m,b)} S^(b) lam_mb - sum_{(a,m)} S^(a) lam_am ].
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_feti_BDT(ObjDesc o, FetiDesc f, const double* __restrict__ lam,
+                                                 const T* __restrict__ slots, const T* __restrict__ fac,
+                                                 T* __restrict__ xr, const int64_t* __restrict__ xoff) {
+    const int ob = blockIdx.x, tid = threadIdx.x;
+    const int n = o.n[ob];
+    __shared__ double h[MAXO];
+    for (int q = o.sh_ptr[ob]; q < o.sh_ptr[ob + 1]; ++q) {
+        const int m = o.sh_sub[q];
+        for (int i = tid; i < n; i += kWG) {
+            double acc = 0.0;
+            for (int pq = f.pr_ptr[ob]; pq < f.pr_ptr[ob + 1]; ++pq) {
+                int other, sgn;
+                if (f.pr_a[pq] == m) { other = f.pr_qb[pq]; sgn = 1; }
+                else if (f.pr_b[pq] == m) { other = f.pr_qa[pq]; sgn = -1; }
+                else continue;
+                const T* S = slots + o.sh_slot[other];
+                const double* l = lam + f.pr_off[pq];
+                double a = 0.0;
+                for (int j = 0; j < n; ++j) a += (double)S[i + (int64_t)j * n] * l[j];
+                acc += sgn * a;
+            }
+            h[i] = acc;
+        }
+        __syncthreads();
+        chol_solve_lds(fac + o.fac_off[ob], n, h);
+        T* dst = xr + xoff[m] + o.sh_roff[q];
+        for (int i = tid; i < n; i += kWG) dst[i] = (T)h[i];
+        __syncthreads();
+    }
+}
+
+// B_D: lam_ab = S^(b) (sum S)^{-1} w^(a) - S^(a) (sum S)^{-1} w^(b).
+// The per-share solves y_m = (sum S)^{-1} w^(m) are staged in ybuf.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_feti_BD(ObjDesc o, FetiDesc f, const T* __restrict__ xr,
+                                                const int64_t* __restrict__ xoff, const T* __restrict__ slots,
+                                                const T* __restrict__ fac, double* __restrict__ ybuf,
+                                                double* __restrict__ lam) {
+    const int ob = blockIdx.x, tid = threadIdx.x;
+    const int n = o.n[ob];
+    __shared__ double h[MAXO];
+    for (int q = o.sh_ptr[ob]; q < o.sh_ptr[ob + 1]; ++q) {
+        const T* u = xr + xoff[o.sh_sub[q]] + o.sh_roff[q];
+        for (int i = tid; i < n; i += kWG) h[i] = (double)u[i];
+        __syncthreads();
+        chol_solve_lds(fac + o.fac_off[ob], n, h);
+        double* y = ybuf + f.sh_yoff[q];
+        for (int i = tid; i < n; i += kWG) y[i] = h[i];
+        __syncthreads();
+    }
+    for (int pq = f.pr_ptr[ob]; pq < f.pr_ptr[ob + 1]; ++pq) {
+        const int qa = f.pr_qa[pq], qb = f.pr_qb[pq];
+        const T* Sa = slots + o.sh_slot[qa];
+        const T* Sb = slots + o.sh_slot[qb];
+        const double* ya = ybuf + f.sh_yoff[qa];
+        const double* yb = ybuf + f.sh_yoff[qb];
+        for (int i = tid; i < n; i += kWG) {
+            double acc = 0.0;
+            for (int j = 0; j < n; ++j)
+                acc += (double)Sb[i + (int64_t)j * n] * ya[j] - (double)Sa[i + (int64_t)j * n] * yb[j];
+            lam[f.pr_off[pq] + i] = acc;
+        }
+    }
+}
+
+// y_r = S_rr x_r per subdomain (dense saved copy of the Schur block).
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_schur_mv(SubVecDesc d, const T* __restrict__ Srr,
+                                                 const int64_t* __restrict__ Soff, const T* __restrict__ x,
+                                                 T* __restrict__ y) {
+    const int s = blockIdx.x, tid = threadIdx.x;
+    const int nr = d.nr[s];
+    const T* S = Srr + Soff[s];
+    const T* xs = x + d.xoff[s];
+    T* ys = y + d.xoff[s];
+    for (int i = tid; i < nr; i += kWG) {
+        double acc = 0.0;
+        for (int j = 0; j < nr; ++j) acc += (double)S[i + (int64_t)j * nr] * (double)xs[j];
+        ys[i] = (T)acc;
+    }
+}
+
+// Split the condensed residual 1/|N_x| over the sharing subdomains (f~ of
+// the FETI-DP right-hand side): every share of an object gets g / nshare.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_split_res(ObjDesc o, int64_t N, const double* __restrict__ g,
+                                                  T* __restrict__ xr, const int64_t* __restrict__ xoff) {
+    const int ob = blockIdx.x, tid = threadIdx.x;
+    const int n = o.n[ob];
+    const int* nodes = o.nodes + o.node_off[ob];
+    const int ns = o.sh_ptr[ob + 1] - o.sh_ptr[ob];
+    for (int q = o.sh_ptr[ob]; q < o.sh_ptr[ob + 1]; ++q) {
+        T* dst = xr + xoff[o.sh_sub[q]] + o.sh_roff[q];
+        for (int i = tid; i < n; i += kWG) dst[i] = (T)(g[(i & 1) * N + nodes[i >> 1]] / ns);
+    }
+}
+
+// Recovered interface values: every share of a continuous solution holds
+// the same values; take the first share's.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_take_first(ObjDesc o, int64_t N, const T* __restrict__ xr,
+                                                   const int64_t* __restrict__ xoff, double* __restrict__ z) {
+    const int ob = blockIdx.x, tid = threadIdx.x;
+    const int n = o.n[ob];
+    const int* nodes = o.nodes + o.node_off[ob];
+    const int q = o.sh_ptr[ob];
+    const T* u = xr + xoff[o.sh_sub[q]] + o.sh_roff[q];
+    for (int i = tid; i < n; i += kWG) z[(i & 1) * N + nodes[i >> 1]] = (double)u[i];
+}
+
+}  // namespace
+
+static inline unsigned nb(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <typename T>
+void launch_gather_I(hipStream_t s, int n, const int* list, int64_t N, const double* r, const double* q, T* x) {
+    hipLaunchKernelGGL(k_gather_I<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, list, N, r, q, x);
+}
+template <typename T>
+void launch_scatter_I(hipStream_t s, int n, const int* list, int64_t N, const T* x, double* out) {
+    hipLaunchKernelGGL(k_scatter_I<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, list, N, x, out);
+}
+template <typename T>
+void launch_deluxe_res(hipStream_t s, const ObjDesc& o, int64_t N, const double* g, const T* slots,
+                       const T* fac, T* xr, const int64_t* xoff) {
+    hipLaunchKernelGGL(k_deluxe_res<T>, dim3(o.nobj), dim3(kWG), 0, s, o, N, g, slots, fac, xr, xoff);
+}
+template <typename T>
+void launch_deluxe_val(hipStream_t s, const ObjDesc& o, int64_t N, const T* slots, const T* fac,
+                       const T* xr, const int64_t* xoff, double* z) {
+    hipLaunchKernelGGL(k_deluxe_val<T>, dim3(o.nobj), dim3(kWG), 0, s, o, N, slots, fac, xr, xoff, z);
+}
+template <typename T>
+void launch_coarse_rhs_local(hipStream_t s, const SubVecDesc& d, const T* xr, const T* F, const T* Z,
+                             const T* Gi, double* cP, double* mu) {
+    hipLaunchKernelGGL(k_coarse_rhs_local<T>, dim3(d.nsub), dim3(kWG), 0, s, d, xr, F, Z, Gi, cP, mu);
+}
+void launch_coarse_rhs_gather(hipStream_t s, const CoarseDesc& c, int64_t N, const double* g,
+                              const double* cP, double* b) {
+    hipLaunchKernelGGL(k_coarse_rhs_gather, dim3(nb(c.np, 256)), dim3(256), 0, s, c, N, g, cP, b);
+}
+void launch_coarse_project(hipStream_t s, int np, int pin, double* b) {
+    hipLaunchKernelGGL(k_coarse_project, dim3(1), dim3(kWG), 0, s, np, pin, b);
+}
+template <typename T>
+void launch_neumann_rhs(hipStream_t s, const SubVecDesc& d, const T* F, const T* Z, const double* mu,
+                        const double* uc, T* xr, int with_mu) {
+    hipLaunchKernelGGL(k_neumann_rhs<T>, dim3(d.nsub), dim3(kWG), 0, s, d, F, Z, mu, uc, xr, with_mu);
+}
+void launch_vertex_val(hipStream_t s, int nv, const int* vnode, int64_t N, const double* uc, double* z) {
+    if (nv > 0) hipLaunchKernelGGL(k_vertex_val, dim3(nb(nv, 256)), dim3(256), 0, s, nv, vnode, N, uc, z);
+}
+template <typename T>
+void launch_feti_BT(hipStream_t s, const ObjDesc& o, const FetiDesc& f, const double* lam, T* xr,
+                    const int64_t* xoff) {
+    hipLaunchKernelGGL(k_feti_BT<T>, dim3(o.nobj), dim3(kWG), 0, s, o, f, lam, xr, xoff);
+}
+template <typename T>
+void launch_feti_B(hipStream_t s, const ObjDesc& o, const FetiDesc& f, const T* xr, const int64_t* xoff,
+                   double* lam) {
+    hipLaunchKernelGGL(k_feti_B<T>, dim3(o.nobj), dim3(kWG), 0, s, o, f, xr, xoff, lam);
+}
+template <typename T>
+void launch_feti_BDT(hipStream_t s, const ObjDesc& o, const FetiDesc& f, const double* lam, const T* slots,
+                     const T* fac, T* xr, const int64_t* xoff) {
+    hipLaunchKernelGGL(k_feti_BDT<T>, dim3(o.nobj), dim3(kWG), 0, s, o, f, lam, slots, fac, xr, xoff);
+}
+template <typename T>
+void launch_feti_BD(hipStream_t s, const ObjDesc& o, const FetiDesc& f, const T* xr, const int64_t* xoff,
+                    const T* slots, const T* fac, double* ybuf, double* lam) {
+    hipLaunchKernelGGL(k_feti_BD<T>, dim3(o.nobj), dim3(kWG), 0, s, o, f, xr, xoff, slots, fac, ybuf, lam);
+}
+template <typename T>
+void launch_schur_mv(hipStream_t s, const SubVecDesc& d, const T* Srr, const int64_t* Soff, const T* x, T* y) {
+    hipLaunchKernelGGL(k_schur_mv<T>, dim3(d.nsub), dim3(kWG), 0, s, d, Srr, Soff, x, y);
+}
+template <typename T>
+void launch_split_res(hipStream_t s, const ObjDesc& o, int64_t N, const double* g, T* xr, const int64_t* xoff) {
+    hipLaunchKernelGGL(k_split_res<T>, dim3(o.nobj), dim3(kWG), 0, s, o, N, g, xr, xoff);
+}
+template <typename T>
+void launch_take_first(hipStream_t s, const ObjDesc& o, int64_t N, const T* xr, const int64_t* xoff, double* z) {
+    hipLaunchKernelGGL(k_take_first<T>, dim3(o.nobj), dim3(kWG), 0, s, o, N, xr, xoff, z);
+}
+
+#define BDM_INST(T)                                                                                         \
+    template void launch_gather_I<T>(hipStream_t, int, const int*, int64_t, const double*, const double*, T*); \
+    template void launch_scatter_I<T>(hipStream_t, int, const int*, int64_t, const T*, double*);            \
+    template void launch_deluxe_res<T>(hipStream_t, const ObjDesc&, int64_t, const double*, const T*,       \
+                                       const T*, T*, const int64_t*);                                       \
+    template void launch_deluxe_val<T>(hipStream_t, const ObjDesc&, int64_t, const T*, const T*, const T*,  \
+                                       const int64_t*, double*);                                            \
+    template void launch_coarse_rhs_local<T>(hipStream_t, const SubVecDesc&, const T*, const T*, const T*,  \
+                                             const T*, double*, double*);                                   \
+    template void launch_neumann_rhs<T>(hipStream_t, const SubVecDesc&, const T*, const T*, const double*,  \
+                                        const double*, T*, int);                                            \
+    template void launch_feti_BT<T>(hipStream_t, const ObjDesc&, const FetiDesc&, const double*, T*,        \
+                                    const int64_t*);                                                        \
+    template void launch_feti_B<T>(hipStream_t, const ObjDesc&, const FetiDesc&, const T*, const int64_t*,  \
+                                   double*);                                                                \
+    template void launch_feti_BDT<T>(hipStream_t, const ObjDesc&, const FetiDesc&, const double*, const T*, \
+                                     const T*, T*, const int64_t*);                                         \
+    template void launch_feti_BD<T>(hipStream_t, const ObjDesc&, const FetiDesc&, const T*, const int64_t*, \
+                                    const T*, const T*, double*, double*);                                  \
+    template void launch_schur_mv<T>(hipStream_t, const SubVecDesc&, const T*, const int64_t*, const T*, T*); \
+    template void launch_split_res<T>(hipStream_t, const ObjDesc&, int64_t, const double*, T*, const int64_t*); \
+    template void launch_take_first<T>(hipStream_t, const ObjDesc&, int64_t, const T*, const int64_t*, double*);
+BDM_INST(double)
+BDM_INST(float)
+#undef BDM_INST
+
+}  // namespace bdm

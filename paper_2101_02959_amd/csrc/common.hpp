@@ -1,0 +1,32 @@
+// Shared definitions for the HIP kernels and the host orchestration.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+namespace bdm {
+
+// Threads per workgroup for batched per-subdomain kernels (4 wave64).
+constexpr int kWG = 256;
+
+// Pointwise and stencil parameters of the Bidomain step.
+struct FEParams {
+    int nx, ny, nz;             // elements per axis
+    int nx1, ny1;               // nodes per axis (x, y)
+    int64_t N;                  // nodes
+    double h, tau, c;           // mesh size, time step, chi*C_m
+    double chiG, chieta1, eta2, vth, vp;
+};
+
+__host__ __device__ inline double rmc_iion(const FEParams& p, double v, double w) {
+    return p.chiG * v * (1.0 - v / p.vth) * (1.0 - v / p.vp) + p.chieta1 * v * w;
+}
+
+// d(chi I_ion)/dv = chi G (1 - 2v/v_th - 2v/v_p + 3 v^2/(v_th v_p)) + chi eta_1 w
+__host__ __device__ inline double rmc_diion(const FEParams& p, double v, double w) {
+    const double a = 1.0 / p.vth, b = 1.0 / p.vp;
+    return p.chiG * (1.0 - 2.0 * v * (a + b) + 3.0 * v * v * a * b) + p.chieta1 * w;
+}
+
+}  // namespace bdm

@@ -1,0 +1,255 @@
+// Pointwise ionic kernels and the matrix-free Q1 stencils of the Bidomain
+// Jacobian and residual (paper Sec. 2, 3a-c).
+//
+// The stiffness of a structured Q1 mesh with one conductivity tensor per
+// z-layer is a 27-point stencil whose coefficients depend only on the node's
+// z-level k and on whether it sits on the low / interior / high boundary in x
+// and in y (nine classes).  The host builds these tables once, scaled by tau,
+// for both media; the kernels read them from a small global table that stays
+// resident in L2.
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace bdm {
+
+// ---------------------------------------------------------------- host side
+// Closed-form Q1 element stiffness on a cube of side h for a constant tensor
+// D: integrals factor per axis into
+//   int psi_a' psi_b' = s_a s_b / h,  int psi_a psi_b = h/3 (a==b) or h/6,
+//   int psi_a' psi_b  = s_a / 2,       s_0 = -1, s_1 = +1.
+void element_stiffness(const double D[3][3], double h, double Ke[8][8]) {
+    for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < 8; ++b) {
+            const int ad[3] = {a & 1, (a >> 1) & 1, (a >> 2) & 1};
+            const int bd[3] = {b & 1, (b >> 1) & 1, (b >> 2) & 1};
+            double acc = 0.0;
+            for (int p = 0; p < 3; ++p)
+                for (int q = 0; q < 3; ++q) {
+                    double prod = 1.0;
+                    for (int d = 0; d < 3; ++d) {
+                        const double sa = ad[d] ? 1.0 : -1.0, sb = bd[d] ? 1.0 : -1.0;
+                        double f;
+                        if (d == p && d == q) f = sa * sb / h;
+                        else if (d == p) f = 0.5 * sa;
+                        else if (d == q) f = 0.5 * sb;
+                        else f = (ad[d] == bd[d]) ? h / 3.0 : h / 6.0;
+                        prod *= f;
+                    }
+                    acc += D[p][q] * prod;
+                }
+            Ke[a][b] = acc;
+        }
+}
+
+void conductivity_tensor(const double sig[3], double theta, double D[3][3]) {
+    const double c = std::cos(theta), s = std::sin(theta);
+    D[0][0] = sig[0] * c * c + sig[1] * s * s;
+    D[1][1] = sig[0] * s * s + sig[1] * c * c;
+    D[0][1] = D[1][0] = (sig[0] - sig[1]) * c * s;
+    D[0][2] = D[2][0] = D[1][2] = D[2][1] = 0.0;
+    D[2][2] = sig[2];
+}
+
+// tau-scaled element matrices per z-layer: ke[(layer*2 + medium)*64 + a*8 + b]
+std::vector<double> layer_matrices(int nz, double h, double tau, const double sig_i[3],
+                                   const double sig_e[3], double th0, double th1) {
+    std::vector<double> ke((size_t)nz * 128);
+    for (int L = 0; L < nz; ++L) {
+        const double th = th0 + (th1 - th0) * (L + 0.5) / nz;
+        for (int m = 0; m < 2; ++m) {
+            double D[3][3], K[8][8];
+            conductivity_tensor(m == 0 ? sig_i : sig_e, th, D);
+            element_stiffness(D, h, K);
+            for (int a = 0; a < 8; ++a)
+                for (int b = 0; b < 8; ++b) ke[((size_t)L * 2 + m) * 64 + a * 8 + b] = tau * K[a][b];
+        }
+    }
+    return ke;
+}
+
+// 27-point tables st[((k*9 + xc + 3*yc)*2 + m)*27 + d], d = (dx+1) + 3(dy+1) + 9(dz+1):
+// the sum over the elements adjacent to both the node and its neighbour.
+std::vector<double> stencil_tables(int nz, const std::vector<double>& ke) {
+    std::vector<double> st((size_t)(nz + 1) * 9 * 2 * 27, 0.0);
+    for (int k = 0; k <= nz; ++k)
+        for (int yc = 0; yc < 3; ++yc)
+            for (int xc = 0; xc < 3; ++xc)
+                for (int m = 0; m < 2; ++m) {
+                    double* t = &st[(((size_t)k * 9 + xc + 3 * yc) * 2 + m) * 27];
+                    for (int oz = 0; oz < 2; ++oz) {
+                        const int L = k - 1 + oz;
+                        if (L < 0 || L >= nz) continue;
+                        for (int oy = 0; oy < 2; ++oy) {
+                            if ((yc == 0 && oy == 0) || (yc == 2 && oy == 1)) continue;
+                            for (int ox = 0; ox < 2; ++ox) {
+                                if ((xc == 0 && ox == 0) || (xc == 2 && ox == 1)) continue;
+                                const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
+                                for (int bz = 0; bz < 2; ++bz)
+                                    for (int by = 0; by < 2; ++by)
+                                        for (int bx = 0; bx < 2; ++bx) {
+                                            const int b = bx + 2 * by + 4 * bz;
+                                            const int dx = bx - (1 - ox), dy = by - (1 - oy),
+                                                      dz = bz - (1 - oz);
+                                            t[(dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)] +=
+                                                ke[((size_t)L * 2 + m) * 64 + a * 8 + b];
+                                        }
+                            }
+                        }
+                    }
+                }
+    return st;
+}
+
+// --------------------------------------------------------------- device side
+namespace {
+
+struct NodeIdx {
+    int i, j, k;
+    int cls;
+    int64_t off[3][3];   // neighbour offsets per axis (clamped to 0 off-mesh)
+};
+
+__device__ inline void node_index(const FEParams& p, int64_t n, int& i, int& j, int& k) {
+    const int64_t t = n / p.nx1;
+    i = (int)(n - t * p.nx1);
+    k = (int)(t / p.ny1);
+    j = (int)(t - (int64_t)k * p.ny1);
+}
+
+// si = (tau A_i)(xv + xe), se = (tau A_e) xe at node n.
+__device__ inline void stencil2(const FEParams& p, const double* __restrict__ st, int64_t n,
+                                int i, int j, int k, const double* __restrict__ xv,
+                                const double* __restrict__ xe, double& si, double& se) {
+    const int xc = (i == 0) ? 0 : (i == p.nx ? 2 : 1);
+    const int yc = (j == 0) ? 0 : (j == p.ny ? 2 : 1);
+    const double* ti = st + (((int64_t)k * 9 + xc + 3 * yc) * 2) * 27;
+    const double* te = ti + 27;
+    const int64_t pl = (int64_t)p.nx1 * p.ny1;
+    const int64_t ox[3] = {i > 0 ? -1 : 0, 0, i < p.nx ? 1 : 0};
+    const int64_t oy[3] = {j > 0 ? -(int64_t)p.nx1 : 0, 0, j < p.ny ? (int64_t)p.nx1 : 0};
+    const int64_t oz[3] = {k > 0 ? -pl : 0, 0, k < p.nz ? pl : 0};
+    double ai = 0.0, ae = 0.0;
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int64_t q = n + ox[dx] + oy[dy] + oz[dz];
+                const int d = dx + 3 * dy + 9 * dz;
+                const double e = xe[q];
+                ai = fma(ti[d], xv[q] + e, ai);
+                ae = fma(te[d], e, ae);
+            }
+    si = ai;
+    se = ae;
+}
+
+__device__ inline double lumped_mass(const FEParams& p, int i, int j, int k) {
+    const double fx = (i == 0 || i == p.nx) ? 0.5 : 1.0;
+    const double fy = (j == 0 || j == p.ny) ? 0.5 : 1.0;
+    const double fz = (k == 0 || k == p.nz) ? 0.5 : 1.0;
+    return p.h * p.h * p.h * fx * fy * fz;
+}
+
+__global__ void k_ionic_update(int64_t N, double tau, double eta2, double vp,
+                               const double* __restrict__ v, double* __restrict__ w) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    w[n] = (w[n] + tau * eta2 * v[n] / vp) / (1.0 + tau * eta2);
+}
+
+__global__ void k_residual(FEParams p, const double* __restrict__ st, const double* __restrict__ v,
+                           const double* __restrict__ ue, const double* __restrict__ vn,
+                           const double* __restrict__ w, const double* __restrict__ Is, double stim,
+                           double* __restrict__ Rv, double* __restrict__ Re) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= p.N) return;
+    int i, j, k;
+    node_index(p, n, i, j, k);
+    double si, se;
+    stencil2(p, st, n, i, j, k, v, ue, si, se);
+    const double m = lumped_mass(p, i, j, k);
+    const double vv = v[n];
+    const double ion = rmc_iion(p, vv, w[n]);
+    const double is = (stim != 0.0 && Is) ? Is[n] : 0.0;
+    Rv[n] = m * (p.c * (vv - vn[n]) + p.tau * (ion - is)) + si;
+    Re[n] = si + se;
+}
+
+__global__ void k_reaction_diag(FEParams p, const double* __restrict__ v, const double* __restrict__ w,
+                                double* __restrict__ dg, int* __restrict__ bad) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= p.N) return;
+    int i, j, k;
+    node_index(p, n, i, j, k);
+    const double d = lumped_mass(p, i, j, k) * (p.c + p.tau * rmc_diion(p, v[n], w[n]));
+    dg[n] = d;
+    if (!(d > 0.0)) atomicOr(bad, 1);
+}
+
+__global__ void k_jac_apply(FEParams p, const double* __restrict__ st, const double* __restrict__ dg,
+                            const double* __restrict__ xv, const double* __restrict__ xe,
+                            double* __restrict__ yv, double* __restrict__ ye) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= p.N) return;
+    int i, j, k;
+    node_index(p, n, i, j, k);
+    double si, se;
+    stencil2(p, st, n, i, j, k, xv, xe, si, se);
+    yv[n] = dg[n] * xv[n] + si;
+    ye[n] = si + se;
+}
+
+// y = r - J x  (used for condensed residuals: only some rows are read)
+__global__ void k_res_minus_jac(FEParams p, const double* __restrict__ st, const double* __restrict__ dg,
+                                const double* __restrict__ xv, const double* __restrict__ xe,
+                                const double* __restrict__ rv, const double* __restrict__ re,
+                                double* __restrict__ yv, double* __restrict__ ye) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= p.N) return;
+    int i, j, k;
+    node_index(p, n, i, j, k);
+    double si, se;
+    stencil2(p, st, n, i, j, k, xv, xe, si, se);
+    yv[n] = rv[n] - (dg[n] * xv[n] + si);
+    ye[n] = re[n] - (si + se);
+}
+
+}  // namespace
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+void launch_ionic_update(hipStream_t s, const FEParams& p, const double* v, double* w) {
+    hipLaunchKernelGGL(k_ionic_update, dim3(nblk(p.N, 256)), dim3(256), 0, s, p.N, p.tau, p.eta2,
+                       p.vp, v, w);
+}
+
+void launch_residual(hipStream_t s, const FEParams& p, const double* st, const double* v,
+                     const double* ue, const double* vn, const double* w, const double* Is,
+                     double stim, double* Rv, double* Re) {
+    hipLaunchKernelGGL(k_residual, dim3(nblk(p.N, 256)), dim3(256), 0, s, p, st, v, ue, vn, w, Is,
+                       stim, Rv, Re);
+}
+
+void launch_reaction_diag(hipStream_t s, const FEParams& p, const double* v, const double* w,
+                          double* dg, int* bad) {
+    hipLaunchKernelGGL(k_reaction_diag, dim3(nblk(p.N, 256)), dim3(256), 0, s, p, v, w, dg, bad);
+}
+
+void launch_jac_apply(hipStream_t s, const FEParams& p, const double* st, const double* dg,
+                      const double* x, double* y) {
+    hipLaunchKernelGGL(k_jac_apply, dim3(nblk(p.N, 256)), dim3(256), 0, s, p, st, dg, x, x + p.N, y,
+                       y + p.N);
+}
+
+void launch_res_minus_jac(hipStream_t s, const FEParams& p, const double* st, const double* dg,
+                          const double* x, const double* r, double* y) {
+    hipLaunchKernelGGL(k_res_minus_jac, dim3(nblk(p.N, 256)), dim3(256), 0, s, p, st, dg, x,
+                       x + p.N, r, r + p.N, y, y + p.N);
+}
+
+}  // namespace bdm

@@ -1,0 +1,88 @@
+// Launch wrappers of the HIP kernels (host-callable).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "common.hpp"
+
+namespace bdm {
+
+// ---- fe.hip
+std::vector<double> layer_matrices(int nz, double h, double tau, const double sig_i[3],
+                                   const double sig_e[3], double th0, double th1);
+std::vector<double> stencil_tables(int nz, const std::vector<double>& ke);
+void launch_ionic_update(hipStream_t s, const FEParams& p, const double* v, double* w);
+void launch_residual(hipStream_t s, const FEParams& p, const double* st, const double* v,
+                     const double* ue, const double* vn, const double* w, const double* Is,
+                     double stim, double* Rv, double* Re);
+void launch_reaction_diag(hipStream_t s, const FEParams& p, const double* v, const double* w,
+                          double* dg, int* bad);
+void launch_jac_apply(hipStream_t s, const FEParams& p, const double* st, const double* dg,
+                      const double* x, double* y);
+void launch_res_minus_jac(hipStream_t s, const FEParams& p, const double* st, const double* dg,
+                          const double* x, const double* r, double* y);
+
+// ---- dense.hip: batched dense linear algebra, one workgroup per matrix.
+// Per-subdomain layout descriptor (device arrays, length nsub).
+struct BatchDesc {
+    int nsub;
+    const int* n;          // local dofs nI + nG (= leading dimension of K)
+    const int* nI;
+    const int* nr;
+    const int* nV;
+    const int* nc;
+    const int64_t* K_off;  // start of the local matrix K in the K buffer
+    const int* box;        // ex0, ey0, ez0, Lx, Ly, Lz per subdomain
+    const int64_t* lmap_off;
+    const int* lmap;       // box node -> local node index in [I | r | V]
+    const int64_t* F_off;  // start of the nr x (nc + nV) RHS / solution block
+    const int64_t* Z_off;  // start of Z (nr x nP)
+    const int64_t* Gi_off; // start of G^{-1} (nc x nc)
+    const int64_t* Sp_off; // start of the local coarse matrix (nP x nP, double)
+    const int64_t* so_ptr; // per-subdomain object list (CSR) ...
+    const int* so_roff;    //   object offset in the local r-dofs
+    const int* so_n;       //   object dofs
+    const int64_t* so_slot;//   start of this subdomain's copy of the object block
+    const int* so_kind;    //   0 face, 1 edge
+    const int* so_nnode;   //   edge nodes (for the constraint rows)
+    const int* so_eidx;    //   local edge index (constraint rows 2e, 2e+1) or -1
+    const int64_t* Srr_off;// start of the saved S_rr copy (FETI-DP) or null
+};
+
+template <typename T>
+void launch_assemble(hipStream_t s, const BatchDesc& d, int maxbox, const FEParams& p,
+                     const double* ke, const double* v, const double* w, T* K);
+template <typename T>
+void launch_potrf(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* c0,
+                  const int* c1, const int* c2, int* info);
+template <typename T>
+void launch_extract(hipStream_t s, const BatchDesc& d, const T* K, T* slots, T* F, double* Svv,
+                    T* Srr);
+template <typename T>
+void launch_trsm_fwd(hipStream_t s, int nb, const T* L, const int64_t* Loff, const int* n,
+                     const int* ld, T* B, const int64_t* Boff, const int* ldb, const int* k);
+template <typename T>
+void launch_coarse_local(hipStream_t s, const BatchDesc& d, const T* F, const double* Svv, T* Z,
+                         T* Gi, double* Sp, int* info);
+template <typename T>
+void launch_trsv(hipStream_t s, int nb, bool trans, const T* L, const int64_t* Loff, const int* n,
+                 const int* ld, T* x, const int64_t* xoff);
+
+// Deluxe objects (faces and edges), one workgroup per object.
+struct ObjDesc {
+    int nobj;
+    const int* n;          // dofs of the object (2 per node)
+    const int64_t* node_off;
+    const int* nodes;      // global node ids
+    const int64_t* fac_off;// factor of sum_m S^(m) (n x n)
+    const int* sh_ptr;     // shares (CSR over objects)
+    const int* sh_sub;     // sharing subdomain
+    const int* sh_roff;    // offset of the object in that subdomain's r-dofs
+    const int64_t* sh_slot;// that subdomain's block S^(m) (n x n)
+};
+template <typename T>
+void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, const T* slots, T* fac, int* info);
+
+}  // namespace bdm

@@ -1,0 +1,815 @@
+// Host-side control of the Newton-Krylov BDDC / FETI-DP deluxe time step
+// (paper Sec. 3b-c, 4, 6).  Every numerical step runs in the HIP kernels of
+// fe.hip, dense.hip, bddc.hip and vec.hip; this file builds the index maps,
+// owns the device workspace and sequences the launches.
+#include "solver.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+
+namespace bdm {
+
+namespace {
+thread_local std::string g_err;
+
+constexpr int MAXC = 24, MAXV = 16, MAXP = 40;
+constexpr int SVV_STRIDE = MAXV * MAXV, GI_STRIDE = MAXC * MAXC, SP_STRIDE = MAXP * MAXP;
+constexpr int MAXOBJ = 512;
+
+__global__ void k_coarse_assemble(const int* __restrict__ list, const int* __restrict__ nPv,
+                                  const int64_t* __restrict__ P_off, const int* __restrict__ primal,
+                                  const double* __restrict__ Sp, int np, double* __restrict__ C) {
+    const int s = list[blockIdx.x];
+    const int nP = nPv[s];
+    const int* pr = primal + P_off[s];
+    const double* S = Sp + (int64_t)s * SP_STRIDE;
+    for (int idx = threadIdx.x; idx < nP * nP; idx += blockDim.x) {
+        const int a = idx % nP, b = idx / nP;
+        C[pr[a] + (int64_t)pr[b] * np] += S[a + b * nP];
+    }
+}
+
+// Pin one u_e primal of the singular coarse matrix: zero its row / column
+// and put 1 on the diagonal.
+__global__ void k_coarse_pin(double* __restrict__ C, int np, int pin) {
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        C[pin + (int64_t)i * np] = 0.0;
+        C[i + (int64_t)pin * np] = 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) C[pin + (int64_t)pin * np] = 1.0;
+}
+
+template <typename T>
+__global__ void k_sub_t(int64_t n, const T* __restrict__ x, T* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] -= x[i];
+}
+
+__global__ void k_lin_comb(int64_t n, double a, const double* __restrict__ x, double b,
+                           const double* __restrict__ y, double* __restrict__ z) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) z[i] = a * x[i] + b * y[i];
+}
+
+inline unsigned nb(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// Extreme eigenvalues of the symmetric tridiagonal Lanczos matrix by
+// bisection on Sturm sequences.
+double sturm_count(const std::vector<double>& d, const std::vector<double>& e, double x) {
+    int cnt = 0;
+    double q = 1.0;
+    for (size_t i = 0; i < d.size(); ++i) {
+        const double off = (i == 0) ? 0.0 : e[i - 1] * e[i - 1];
+        q = d[i] - x - (i == 0 ? 0.0 : off / (q == 0.0 ? 1e-300 : q));
+        if (q < 0) ++cnt;
+    }
+    return cnt;
+}
+double tri_eig(const std::vector<double>& d, const std::vector<double>& e, int k) {
+    double lo = 1e300, hi = -1e300;
+    for (size_t i = 0; i < d.size(); ++i) {
+        const double r = (i > 0 ? std::fabs(e[i - 1]) : 0) + (i + 1 < d.size() ? std::fabs(e[i]) : 0);
+        lo = std::min(lo, d[i] - r);
+        hi = std::max(hi, d[i] + r);
+    }
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (sturm_count(d, e, mid) > k) hi = mid;
+        else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+double lanczos_cond(const std::vector<double>& a, const std::vector<double>& b) {
+    const size_t k = a.size();
+    if (k == 0) return 1.0;
+    std::vector<double> d(k), e(k > 0 ? k - 1 : 0);
+    for (size_t i = 0; i < k; ++i) {
+        d[i] = 1.0 / a[i] + (i > 0 ? b[i - 1] / a[i - 1] : 0.0);
+        if (i + 1 < k) e[i] = std::sqrt(std::max(b[i], 0.0)) / a[i];
+    }
+    const double lmin = tri_eig(d, e, 0), lmax = tri_eig(d, e, (int)k - 1);
+    return lmax / lmin;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_err = msg; }
+const char* last_error() { return g_err.c_str(); }
+
+#define HIPOK(x)                                                                      \
+    do {                                                                              \
+        hipError_t e_ = (x);                                                          \
+        if (e_ != hipSuccess) {                                                       \
+            set_error(std::string("HIP error: ") + hipGetErrorString(e_) + " at " #x); \
+            return BDM_E_HIP;                                                         \
+        }                                                                             \
+    } while (0)
+
+Context::~Context() {
+    for (void* p : allocs_) hipFree(p);
+}
+
+void* Context::dalloc(size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 8;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    allocs_.push_back(p);
+    return p;
+}
+
+template <typename V>
+V* Context::upload(const std::vector<V>& h) {
+    V* d = (V*)dalloc(h.size() * sizeof(V));
+    if (d && !h.empty()) hipMemcpy(d, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice);
+    return d;
+}
+
+int Context::sync() {
+    HIPOK(hipStreamSynchronize(stream_));
+    return 0;
+}
+
+double Context::dot(int64_t n, const double* x, const double* y) {
+    launch_dot(stream_, n, x, y, part_, scal_);
+    double h = 0.0;
+    hipMemcpyAsync(&h, scal_, sizeof(double), hipMemcpyDeviceToHost, stream_);
+    hipStreamSynchronize(stream_);
+    return h;
+}
+
+int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o, hipStream_t s) {
+    stream_ = s;
+    opts = *o;
+    phys = *ph;
+    if (!(o->dt > 0) || o->newton_maxit < 1 || o->krylov_maxit < 1) {
+        set_error("invalid options");
+        return BDM_E_ARG;
+    }
+    std::string err = topo.build(m->nx, m->ny, m->nz, m->h, m->px, m->py, m->pz, m->cuts_x, m->cuts_y,
+                                 m->cuts_z);
+    if (!err.empty()) {
+        set_error(err);
+        return BDM_E_ARG;
+    }
+    prec_ = (o->precision == BDM_PREC_MIXED) ? 1 : 0;
+    tsize_ = prec_ ? sizeof(float) : sizeof(double);
+    N = topo.N;
+    fp.nx = m->nx; fp.ny = m->ny; fp.nz = m->nz;
+    fp.nx1 = m->nx + 1; fp.ny1 = m->ny + 1;
+    fp.N = N;
+    fp.h = m->h; fp.tau = o->dt; fp.c = ph->chi * ph->Cm;
+    fp.chiG = ph->chi * ph->G; fp.chieta1 = ph->chi * ph->eta1; fp.eta2 = ph->eta2;
+    fp.vth = ph->vth; fp.vp = ph->vp;
+
+    std::vector<double> ke = layer_matrices(m->nz, m->h, o->dt, ph->sigma_i, ph->sigma_e, ph->theta0, ph->theta1);
+    std::vector<double> st = stencil_tables(m->nz, ke);
+    ke_ = upload(ke);
+    st_ = upload(st);
+
+    const int nsub = (int)topo.subs.size();
+    // ---------------- per-subdomain descriptors
+    std::vector<int> n(nsub), nI(nsub), nr(nsub), nV(nsub), nc(nsub), nP(nsub), box(6 * nsub), kF(nsub);
+    std::vector<int64_t> lmap_off(nsub), K_off(nsub), F_off(nsub), Z_off(nsub), P_off(nsub);
+    std::vector<int64_t> xI_off(nsub), xr_off(nsub), LII(nsub), Lrr(nsub), Srr_off(nsub);
+    std::vector<int> lmap, primal, Ilist;
+    std::vector<int> st1c0(nsub, 0), st1c1(nsub), st1c2(nsub), st2c1(nsub);
+    int64_t accK = 0, accF = 0, accZ = 0, accP = 0, accI = 0, accR = 0, accS = 0;
+    for (int q = 0; q < nsub; ++q) {
+        const SubInfo& sb = topo.subs[q];
+        if (sb.nc > MAXC || sb.nV > MAXV) {
+            set_error("subdomain has too many primal constraints");
+            return BDM_E_ARG;
+        }
+        n[q] = sb.n(); nI[q] = sb.nI; nr[q] = sb.nr; nV[q] = sb.nV; nc[q] = sb.nc; nP[q] = sb.nP;
+        kF[q] = sb.nc + sb.nV;
+        box[6 * q + 0] = sb.ex0; box[6 * q + 1] = sb.ey0; box[6 * q + 2] = sb.ez0;
+        box[6 * q + 3] = sb.Lx(); box[6 * q + 4] = sb.Ly(); box[6 * q + 5] = sb.Lz();
+        maxbox_ = std::max(maxbox_, (sb.Lx() + 1) * (sb.Ly() + 1) * (sb.Lz() + 1));
+        lmap_off[q] = (int64_t)lmap.size();
+        lmap.insert(lmap.end(), sb.lmap.begin(), sb.lmap.end());
+        K_off[q] = accK; accK += (int64_t)sb.n() * sb.n();
+        LII[q] = K_off[q];
+        Lrr[q] = K_off[q] + (int64_t)sb.nI * (sb.n() + 1);
+        F_off[q] = accF; accF += (int64_t)sb.nr * (sb.nc + sb.nV);
+        Z_off[q] = accZ; accZ += (int64_t)sb.nr * sb.nP;
+        P_off[q] = accP; accP += sb.nP;
+        primal.insert(primal.end(), sb.primal.begin(), sb.primal.end());
+        xI_off[q] = accI; accI += sb.nI;
+        Ilist.insert(Ilist.end(), sb.I_nodes.begin(), sb.I_nodes.end());
+        xr_off[q] = accR; accR += sb.nr;
+        Srr_off[q] = accS; accS += (int64_t)sb.nr * sb.nr;
+        st1c1[q] = sb.nI; st1c2[q] = sb.n(); st2c1[q] = sb.nI + sb.nr;
+    }
+    nK_ = accK; nF_ = accF; nZ_ = accZ; nxI_ = accI; nxr_ = accR; nSrr_ = accS;
+    nInodes_ = (int)Ilist.size();
+
+    // ---------------- objects (faces then edges) and their shares
+    const int nF = (int)topo.faces.size(), nE = (int)topo.edges.size();
+    const int nobj = nF + nE;
+    std::vector<int> on(nobj), onodes, sh_ptr(nobj + 1, 0), sh_sub, sh_roff;
+    std::vector<int64_t> onode_off(nobj), ofac(nobj), sh_slot, sh_yoff;
+    std::map<std::pair<int, int>, int64_t> slot_of;   // (object, sub) -> slot offset
+    std::map<std::pair<int, int>, int> roff_of;       // (object, sub) -> r offset
+    for (int q = 0; q < nsub; ++q) {
+        const SubInfo& sb = topo.subs[q];
+        for (size_t t = 0; t < sb.faces.size(); ++t) roff_of[{sb.faces[t], q}] = sb.face_off[t];
+        for (size_t t = 0; t < sb.edges.size(); ++t) roff_of[{nF + sb.edges[t], q}] = sb.edge_off[t];
+    }
+    int64_t accSlot = 0, accFac = 0, accY = 0;
+    for (int ob = 0; ob < nobj; ++ob) {
+        const Object& O = ob < nF ? topo.faces[ob] : topo.edges[ob - nF];
+        on[ob] = 2 * (int)O.nodes.size();
+        if (on[ob] > MAXOBJ) {
+            set_error("interface object larger than supported");
+            return BDM_E_ARG;
+        }
+        onode_off[ob] = (int64_t)onodes.size();
+        onodes.insert(onodes.end(), O.nodes.begin(), O.nodes.end());
+        ofac[ob] = accFac; accFac += (int64_t)on[ob] * on[ob];
+        for (int sbi : O.subs) {
+            slot_of[{ob, sbi}] = accSlot;
+            sh_sub.push_back(sbi);
+            sh_roff.push_back(roff_of.at({ob, sbi}));
+            sh_slot.push_back(accSlot);
+            sh_yoff.push_back(accY);
+            accSlot += (int64_t)on[ob] * on[ob];
+            accY += on[ob];
+        }
+        sh_ptr[ob + 1] = (int)sh_sub.size();
+    }
+    nslot_ = accSlot; nfac_ = accFac; nyb_ = accY;
+    // per-subdomain object lists
+    std::vector<int64_t> so_ptr(nsub + 1, 0), so_slot;
+    std::vector<int> so_roff, so_n, so_kind, so_nnode, so_eidx;
+    for (int q = 0; q < nsub; ++q) {
+        const SubInfo& sb = topo.subs[q];
+        for (size_t t = 0; t < sb.faces.size(); ++t) {
+            const int ob = sb.faces[t];
+            so_roff.push_back(sb.face_off[t]); so_n.push_back(on[ob]);
+            so_slot.push_back(slot_of.at({ob, q})); so_kind.push_back(0);
+            so_nnode.push_back(on[ob] / 2); so_eidx.push_back(-1);
+        }
+        for (size_t t = 0; t < sb.edges.size(); ++t) {
+            const int ob = nF + sb.edges[t];
+            so_roff.push_back(sb.edge_off[t]); so_n.push_back(on[ob]);
+            so_slot.push_back(slot_of.at({ob, q})); so_kind.push_back(1);
+            so_nnode.push_back(on[ob] / 2); so_eidx.push_back((int)t);
+        }
+        so_ptr[q + 1] = (int64_t)so_roff.size();
+    }
+    // FETI-DP pairs
+    std::vector<int> pr_ptr(nobj + 1, 0), pr_a, pr_b, pr_qa, pr_qb;
+    std::vector<int64_t> pr_off;
+    int64_t accL = 0;
+    for (int ob = 0; ob < nobj; ++ob) {
+        const int b0 = sh_ptr[ob], b1 = sh_ptr[ob + 1];
+        for (int qa = b0; qa < b1; ++qa)
+            for (int qb = qa + 1; qb < b1; ++qb) {
+                pr_a.push_back(sh_sub[qa]); pr_b.push_back(sh_sub[qb]);
+                pr_qa.push_back(qa); pr_qb.push_back(qb);
+                pr_off.push_back(accL);
+                accL += on[ob];
+            }
+        pr_ptr[ob + 1] = (int)pr_a.size();
+    }
+    nlam_ = (long)accL;
+    // coarse gather lists
+    const int np = topo.nprimal;
+    std::vector<std::vector<std::pair<int, int>>> contrib(np);
+    for (int q = 0; q < nsub; ++q)
+        for (int a = 0; a < topo.subs[q].nP; ++a) contrib[topo.subs[q].primal[a]].push_back({q, a});
+    std::vector<int> cp_ptr(np + 1, 0), cp_sub, cp_loc, vnode;
+    for (int p = 0; p < np; ++p) {
+        for (auto& c : contrib[p]) { cp_sub.push_back(c.first); cp_loc.push_back(c.second); }
+        cp_ptr[p + 1] = (int)cp_sub.size();
+    }
+    for (auto& vo : topo.verts) vnode.push_back(vo.nodes[0]);
+    // colours of the subdomain grid (same colour => no shared primal object)
+    colors_.assign(8, {});
+    for (int q = 0; q < nsub; ++q) {
+        const SubInfo& sb = topo.subs[q];
+        colors_[(sb.a & 1) + 2 * (sb.b & 1) + 4 * (sb.c & 1)].push_back(q);
+    }
+    std::vector<int> clist;
+    color_ptr_.assign(1, 0);
+    for (auto& c : colors_) {
+        clist.insert(clist.end(), c.begin(), c.end());
+        color_ptr_.push_back((int)clist.size());
+    }
+
+    // ---------------- upload descriptors
+    bd_.nsub = nsub;
+    bd_.n = upload(n); bd_.nI = upload(nI); bd_.nr = upload(nr); bd_.nV = upload(nV); bd_.nc = upload(nc);
+    bd_.K_off = upload(K_off); bd_.box = upload(box); bd_.lmap_off = upload(lmap_off); bd_.lmap = upload(lmap);
+    bd_.F_off = upload(F_off); bd_.Z_off = upload(Z_off);
+    bd_.so_ptr = upload(so_ptr); bd_.so_roff = upload(so_roff); bd_.so_n = upload(so_n);
+    bd_.so_slot = upload(so_slot); bd_.so_kind = upload(so_kind); bd_.so_nnode = upload(so_nnode);
+    bd_.so_eidx = upload(so_eidx); bd_.Srr_off = upload(Srr_off);
+    od_.nobj = nobj; od_.n = upload(on); od_.node_off = upload(onode_off); od_.nodes = upload(onodes);
+    od_.fac_off = upload(ofac); od_.sh_ptr = upload(sh_ptr); od_.sh_sub = upload(sh_sub);
+    od_.sh_roff = upload(sh_roff); od_.sh_slot = upload(sh_slot);
+    sv_.nsub = nsub; sv_.nr = bd_.nr; sv_.nV = bd_.nV; sv_.nc = bd_.nc;
+    xr_off_ = upload(xr_off); sv_.xoff = xr_off_; sv_.F_off = bd_.F_off; sv_.Z_off = bd_.Z_off;
+    sv_.P_off = upload(P_off); sv_.primal = upload(primal);
+    cd_.np = np; cd_.nverts = (int)topo.verts.size(); cd_.vnode = upload(vnode);
+    cd_.cp_ptr = upload(cp_ptr); cd_.cp_sub = upload(cp_sub); cd_.cp_loc = upload(cp_loc);
+    fd_.pr_ptr = upload(pr_ptr); fd_.pr_a = upload(pr_a); fd_.pr_b = upload(pr_b);
+    fd_.pr_qa = upload(pr_qa); fd_.pr_qb = upload(pr_qb); fd_.pr_off = upload(pr_off);
+    fd_.sh_yoff = upload(sh_yoff);
+    Ilist_ = upload(Ilist);
+    LII_off_ = upload(LII); Lrr_off_ = upload(Lrr); xI_off_ = upload(xI_off); Srr_off_ = bd_.Srr_off;
+    nI_ = bd_.nI; nr_ = bd_.nr; ld_ = bd_.n; kF_ = upload(kF); nP_ = upload(nP);
+    st1c0_ = upload(st1c0); st1c1_ = upload(st1c1); st1c2_ = upload(st1c2); st2c1_ = upload(st2c1);
+    color_list_ = upload(clist);
+    std::vector<int64_t> z64(1, 0);
+    std::vector<int> zi(1, 0), npv(1, np);
+    zero64_ = upload(z64); cpin_ = upload(zi); np_ = upload(npv);
+    one_ = upload(npv);
+    // pin: the u_e dof of the first vertex (or of the first edge average)
+    pin_ = 1;
+
+    // ---------------- global vectors and workspace
+    const size_t vb = (size_t)N * sizeof(double);
+    v_ = (double*)dalloc(vb); ue_ = (double*)dalloc(vb); w_ = (double*)dalloc(vb); vn_ = (double*)dalloc(vb);
+    vprev_ = (double*)dalloc(vb); ueprev_ = (double*)dalloc(vb); Is_ = (double*)dalloc(vb);
+    dg_ = (double*)dalloc(vb); vlin_ = (double*)dalloc(vb); wlin_ = (double*)dalloc(vb);
+    bad_ = (int*)dalloc(sizeof(int));
+    const size_t kb = (size_t)std::max<int64_t>(2 * N, nlam_ + 2 * N) * sizeof(double);
+    kx_ = (double*)dalloc(kb); kr_ = (double*)dalloc(kb); kz_ = (double*)dalloc(kb);
+    kp_ = (double*)dalloc(kb); kq_ = (double*)dalloc(kb); kro_ = (double*)dalloc(kb);
+    t1_ = (double*)dalloc(2 * vb); t2_ = (double*)dalloc(2 * vb); t3_ = (double*)dalloc(2 * vb);
+    gzero_ = (double*)dalloc(2 * vb);
+    R_ = (double*)dalloc(2 * vb); S_ = (double*)dalloc(2 * vb); U_ = (double*)dalloc(2 * vb);
+    Rt_ = (double*)dalloc(2 * vb);
+    part_ = (double*)dalloc(dot_partials() * sizeof(double));
+    scal_ = (double*)dalloc(8 * sizeof(double));
+    if (!v_ || !ue_ || !w_ || !kx_ || !R_ || !Rt_ || !part_ || !scal_) {
+        set_error("device allocation failed (global vectors)");
+        return BDM_E_OOM;
+    }
+    HIPOK(hipMemsetAsync(gzero_, 0, 2 * vb, stream_));
+    int rc = prec_ ? alloc_local<float>() : alloc_local<double>();
+    if (rc) return rc;
+    return set_state(nullptr, nullptr, nullptr, 0.0, false);
+}
+
+template <typename T>
+int Context::alloc_local() {
+    const int nsub = (int)topo.subs.size();
+    const bool feti = opts.solver == BDM_SOLVER_FETIDP;
+    K_ = dalloc(nK_ * sizeof(T));
+    slots_ = dalloc(nslot_ * sizeof(T));
+    F_ = dalloc(nF_ * sizeof(T));
+    Z_ = dalloc(nZ_ * sizeof(T));
+    Gi_ = dalloc((size_t)nsub * GI_STRIDE * sizeof(T));
+    fac_ = dalloc(nfac_ * sizeof(T));
+    Srr_ = feti ? dalloc(nSrr_ * sizeof(T)) : nullptr;
+    xI_ = dalloc(nxI_ * sizeof(T));
+    xr_ = dalloc(nxr_ * sizeof(T));
+    xr2_ = dalloc(nxr_ * sizeof(T));
+    Svv_ = (double*)dalloc((size_t)nsub * SVV_STRIDE * sizeof(double));
+    Sp_ = (double*)dalloc((size_t)nsub * SP_STRIDE * sizeof(double));
+    cP_ = (double*)dalloc((size_t)nsub * MAXP * sizeof(double));
+    mu_ = (double*)dalloc((size_t)nsub * MAXC * sizeof(double));
+    const int np = topo.nprimal;
+    Cm_ = (double*)dalloc((size_t)np * np * sizeof(double));
+    cb_ = (double*)dalloc((size_t)np * sizeof(double));
+    ybuf_ = (double*)dalloc(nyb_ * sizeof(double));
+    info_sub_ = (int*)dalloc(nsub * sizeof(int));
+    info_obj_ = (int*)dalloc((size_t)od_.nobj * sizeof(int));
+    info_c_ = (int*)dalloc(sizeof(int));
+    if (!K_ || !slots_ || !F_ || !Z_ || !Gi_ || !fac_ || (feti && !Srr_) || !xI_ || !xr_ || !xr2_ || !Svv_ ||
+        !Sp_ || !cP_ || !mu_ || !Cm_ || !cb_ || !ybuf_ || !info_sub_ || !info_obj_ || !info_c_) {
+        set_error("device allocation failed (local factors)");
+        return BDM_E_OOM;
+    }
+    return 0;
+}
+
+int Context::set_state(const double* v, const double* ue, const double* w, double t, bool dev) {
+    const size_t vb = (size_t)N * sizeof(double);
+    const hipMemcpyKind k = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (v) HIPOK(hipMemcpyAsync(v_, v, vb, k, stream_)); else HIPOK(hipMemsetAsync(v_, 0, vb, stream_));
+    if (ue) HIPOK(hipMemcpyAsync(ue_, ue, vb, k, stream_)); else HIPOK(hipMemsetAsync(ue_, 0, vb, stream_));
+    if (w) HIPOK(hipMemcpyAsync(w_, w, vb, k, stream_)); else HIPOK(hipMemsetAsync(w_, 0, vb, stream_));
+    launch_sub_mean(stream_, N, ue_, part_, scal_);
+    HIPOK(hipMemcpyAsync(vn_, v_, vb, hipMemcpyDeviceToDevice, stream_));
+    t_ = t;
+    have_prev_ = false;
+    return sync();
+}
+
+int Context::get_state(double* v, double* ue, double* w, double* t, bool dev) {
+    const size_t vb = (size_t)N * sizeof(double);
+    const hipMemcpyKind k = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (v) HIPOK(hipMemcpyAsync(v, v_, vb, k, stream_));
+    if (ue) HIPOK(hipMemcpyAsync(ue, ue_, vb, k, stream_));
+    if (w) HIPOK(hipMemcpyAsync(w, w_, vb, k, stream_));
+    if (t) *t = t_;
+    return sync();
+}
+
+int Context::set_stimulus(const double* Is, int on, int off, bool dev) {
+    const size_t vb = (size_t)N * sizeof(double);
+    if (Is) {
+        HIPOK(hipMemcpyAsync(Is_, Is, vb, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, stream_));
+        have_stim_ = true;
+    } else {
+        HIPOK(hipMemsetAsync(Is_, 0, vb, stream_));
+        have_stim_ = false;
+    }
+    stim_on_ = on;
+    stim_off_ = off;
+    return sync();
+}
+
+int Context::ionic_update() {
+    launch_ionic_update(stream_, fp, v_, w_);
+    return sync();
+}
+
+int Context::residual(const double* v, const double* ue, double* Rv, double* Re) {
+    HIPOK(hipMemcpyAsync(vn_, v_, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
+    const double stim = (have_stim_ && nstep_ >= stim_on_ && nstep_ < stim_off_) ? 1.0 : 0.0;
+    launch_residual(stream_, fp, st_, v, ue, vn_, w_, Is_, stim, Rv, Re);
+    return sync();
+}
+
+int Context::jacobian_apply(const double* x, double* y) {
+    if (!linearized_) {
+        set_error("bdm_jacobian_apply before bdm_linearize");
+        return BDM_E_STATE;
+    }
+    launch_jac_apply(stream_, fp, st_, dg_, x, y);
+    return sync();
+}
+
+int Context::linearize(const double* v, const double* w) {
+    const size_t vb = (size_t)N * sizeof(double);
+    HIPOK(hipMemcpyAsync(vlin_, v, vb, hipMemcpyDeviceToDevice, stream_));
+    HIPOK(hipMemcpyAsync(wlin_, w, vb, hipMemcpyDeviceToDevice, stream_));
+    int rc = prec_ ? linearize_t<float>() : linearize_t<double>();
+    if (rc == 0) linearized_ = true;
+    return rc;
+}
+
+template <typename T>
+int Context::linearize_t() {
+    const int nsub = (int)topo.subs.size();
+    const int np = topo.nprimal;
+    HIPOK(hipMemsetAsync(bad_, 0, sizeof(int), stream_));
+    launch_reaction_diag(stream_, fp, vlin_, wlin_, dg_, bad_);
+    T* K = (T*)K_;
+    HIPOK(hipMemsetAsync(K, 0, nK_ * sizeof(T), stream_));
+    HIPOK(hipMemsetAsync(info_sub_, 0, nsub * sizeof(int), stream_));
+    HIPOK(hipMemsetAsync(info_obj_, 0, od_.nobj * sizeof(int), stream_));
+    HIPOK(hipMemsetAsync(info_c_, 0, sizeof(int), stream_));
+    launch_assemble<T>(stream_, bd_, maxbox_, fp, ke_, vlin_, wlin_, K);
+    // interior elimination: L_II, and S_Gamma in the trailing block
+    launch_potrf<T>(stream_, nsub, K, bd_.K_off, ld_, st1c0_, st1c1_, st1c2_, info_sub_);
+    HIPOK(hipMemsetAsync(F_, 0, nF_ * sizeof(T), stream_));
+    launch_extract<T>(stream_, bd_, K, (T*)slots_, (T*)F_, Svv_, (T*)Srr_);
+    // constrained Neumann factor L_rr of S_rr
+    launch_potrf<T>(stream_, nsub, K, bd_.K_off, ld_, st1c1_, st2c1_, st2c1_, info_sub_);
+    launch_trsm_fwd<T>(stream_, nsub, K, Lrr_off_, nr_, ld_, (T*)F_, bd_.F_off, nr_, kF_);
+    launch_coarse_local<T>(stream_, bd_, (const T*)F_, Svv_, (T*)Z_, (T*)Gi_, Sp_, info_sub_);
+    launch_deluxe_setup<T>(stream_, od_, (const T*)slots_, (T*)fac_, info_obj_);
+    HIPOK(hipMemsetAsync(Cm_, 0, (size_t)np * np * sizeof(double), stream_));
+    for (int c = 0; c < 8; ++c) {
+        const int cnt = color_ptr_[c + 1] - color_ptr_[c];
+        if (cnt == 0) continue;
+        hipLaunchKernelGGL(k_coarse_assemble, dim3(cnt), dim3(kWG), 0, stream_, color_list_ + color_ptr_[c],
+                           nP_, sv_.P_off, sv_.primal, Sp_, np, Cm_);
+    }
+    hipLaunchKernelGGL(k_coarse_pin, dim3(1), dim3(kWG), 0, stream_, Cm_, np, pin_);
+    launch_potrf<double>(stream_, 1, Cm_, zero64_, np_, cpin_, np_, np_, info_c_);
+    int hb = 0, hc = 0;
+    std::vector<int> hs(nsub), ho(od_.nobj);
+    HIPOK(hipMemcpyAsync(&hb, bad_, sizeof(int), hipMemcpyDeviceToHost, stream_));
+    HIPOK(hipMemcpyAsync(hs.data(), info_sub_, nsub * sizeof(int), hipMemcpyDeviceToHost, stream_));
+    HIPOK(hipMemcpyAsync(ho.data(), info_obj_, od_.nobj * sizeof(int), hipMemcpyDeviceToHost, stream_));
+    HIPOK(hipMemcpyAsync(&hc, info_c_, sizeof(int), hipMemcpyDeviceToHost, stream_));
+    HIPOK(hipStreamSynchronize(stream_));
+    HIPOK(hipGetLastError());
+    if (hb) {
+        set_error("reaction diagonal not positive: the coercivity hypothesis chi*Cm + tau dI/dv > 0 fails");
+        return BDM_E_COERCIVITY;
+    }
+    for (int q = 0; q < nsub; ++q)
+        if (hs[q]) {
+            set_error("local factorisation failed in subdomain " + std::to_string(q));
+            return BDM_E_NOT_SPD;
+        }
+    for (int q = 0; q < od_.nobj; ++q)
+        if (ho[q]) {
+            set_error("deluxe factorisation failed for object " + std::to_string(q));
+            return BDM_E_NOT_SPD;
+        }
+    if (hc) {
+        set_error("coarse factorisation failed");
+        return BDM_E_NOT_SPD;
+    }
+    return 0;
+}
+
+// out(interior dofs) = K_II^{-1} (r - q)_I per subdomain (q may be null).
+template <typename T>
+void Context::dirichlet(const double* r, const double* q, double* out) {
+    T* xI = (T*)xI_;
+    launch_gather_I<T>(stream_, nInodes_, Ilist_, N, r, q, xI);
+    launch_trsv<T>(stream_, bd_.nsub, false, (const T*)K_, LII_off_, nI_, ld_, xI, xI_off_);
+    launch_trsv<T>(stream_, bd_.nsub, true, (const T*)K_, LII_off_, nI_, ld_, xI, xI_off_);
+    launch_scatter_I<T>(stream_, nInodes_, Ilist_, N, xI, out);
+}
+
+// g = r - sum_j R_j^T K_GI K_II^{-1} r_I (interface rows of g are used)
+template <typename T>
+void Context::condense(const double* r, double* g) {
+    hipMemsetAsync(t1_, 0, 2 * N * sizeof(double), stream_);
+    dirichlet<T>(r, nullptr, t1_);
+    launch_res_minus_jac(stream_, fp, st_, dg_, t1_, r, g);
+}
+
+// S~^{-1} on local r-residuals in xr (Sec. 4.4): forward Neumann solve,
+// coarse right-hand side (vertex residuals from gvert), coarse solve, and one
+// backward solve for the Neumann correction plus the coarse prolongation.
+template <typename T>
+void Context::stilde_inv(T* xr, const double* gvert, double* uc) {
+    launch_trsv<T>(stream_, bd_.nsub, false, (const T*)K_, Lrr_off_, nr_, ld_, xr, xr_off_);
+    launch_coarse_rhs_local<T>(stream_, sv_, xr, (const T*)F_, (const T*)Z_, (const T*)Gi_, cP_, mu_);
+    launch_coarse_rhs_gather(stream_, cd_, N, gvert, cP_, uc);
+    launch_coarse_project(stream_, cd_.np, pin_, uc);
+    launch_trsv<double>(stream_, 1, false, Cm_, zero64_, np_, np_, uc, zero64_);
+    launch_trsv<double>(stream_, 1, true, Cm_, zero64_, np_, np_, uc, zero64_);
+    launch_neumann_rhs<T>(stream_, sv_, (const T*)F_, (const T*)Z_, mu_, uc, xr, 1);
+    launch_trsv<T>(stream_, bd_.nsub, true, (const T*)K_, Lrr_off_, nr_, ld_, xr, xr_off_);
+}
+
+// zbuf holds interface values (zero interior); fill the interior by the
+// discrete harmonic extension plus the interior correction:
+// z_I = K_II^{-1} (r_I - K_IG z_G).
+template <typename T>
+void Context::interior_extend(const double* r, double* zbuf) {
+    launch_jac_apply(stream_, fp, st_, dg_, zbuf, t1_);
+    dirichlet<T>(r, t1_, zbuf);
+}
+
+int Context::bddc_apply(const double* r, double* z) {
+    if (!linearized_) {
+        set_error("bdm_bddc_apply before bdm_linearize");
+        return BDM_E_STATE;
+    }
+    int rc = prec_ ? bddc_apply_t<float>(r, z) : bddc_apply_t<double>(r, z);
+    if (rc) return rc;
+    return sync();
+}
+
+template <typename T>
+int Context::bddc_apply_t(const double* r, double* z) {
+    condense<T>(r, t2_);
+    launch_deluxe_res<T>(stream_, od_, N, t2_, (const T*)slots_, (const T*)fac_, (T*)xr_, xr_off_);
+    stilde_inv<T>((T*)xr_, t2_, cb_);
+    HIPOK(hipMemsetAsync(t3_, 0, 2 * N * sizeof(double), stream_));
+    launch_deluxe_val<T>(stream_, od_, N, (const T*)slots_, (const T*)fac_, (const T*)xr_, xr_off_, t3_);
+    launch_vertex_val(stream_, cd_.nverts, cd_.vnode, N, cb_, t3_);
+    interior_extend<T>(r, t3_);
+    HIPOK(hipMemcpyAsync(z, t3_, 2 * N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
+    return 0;
+}
+
+int Context::fetidp_apply(int op, const double* in, double* out) {
+    if (!linearized_) {
+        set_error("bdm_fetidp_apply before bdm_linearize");
+        return BDM_E_STATE;
+    }
+    if (opts.solver != BDM_SOLVER_FETIDP) {
+        set_error("context was created without FETI-DP workspace (opts.solver)");
+        return BDM_E_STATE;
+    }
+    int rc = prec_ ? fetidp_apply_t<float>(op, in, out) : fetidp_apply_t<double>(op, in, out);
+    if (rc) return rc;
+    return sync();
+}
+
+template <typename T>
+int Context::fetidp_apply_t(int op, const double* in, double* out) {
+    T* xr = (T*)xr_;
+    T* xr2 = (T*)xr2_;
+    switch (op) {
+        case BDM_FETI_F:
+            launch_feti_BT<T>(stream_, od_, fd_, in, xr, xr_off_);
+            stilde_inv<T>(xr, gzero_, cb_);
+            launch_feti_B<T>(stream_, od_, fd_, xr, xr_off_, out);
+            return 0;
+        case BDM_FETI_PRECOND:
+            launch_feti_BDT<T>(stream_, od_, fd_, in, (const T*)slots_, (const T*)fac_, xr, xr_off_);
+            launch_schur_mv<T>(stream_, sv_, (const T*)Srr_, Srr_off_, xr, xr2);
+            launch_feti_BD<T>(stream_, od_, fd_, xr2, xr_off_, (const T*)slots_, (const T*)fac_, ybuf_, out);
+            return 0;
+        case BDM_FETI_RHS:
+            condense<T>(in, t2_);
+            launch_split_res<T>(stream_, od_, N, t2_, xr, xr_off_);
+            stilde_inv<T>(xr, t2_, cb_);
+            launch_feti_B<T>(stream_, od_, fd_, xr, xr_off_, out);
+            return 0;
+        case BDM_FETI_RECOVER: {
+            condense<T>(in, t2_);
+            launch_split_res<T>(stream_, od_, N, t2_, xr, xr_off_);
+            launch_feti_BT<T>(stream_, od_, fd_, in + 2 * N, xr2, xr_off_);
+            hipLaunchKernelGGL(k_sub_t<T>, dim3(nb(nxr_, 256)), dim3(256), 0, stream_, nxr_, (const T*)xr2, xr);
+            stilde_inv<T>(xr, t2_, cb_);
+            HIPOK(hipMemsetAsync(t3_, 0, 2 * N * sizeof(double), stream_));
+            launch_take_first<T>(stream_, od_, N, xr, xr_off_, t3_);
+            launch_vertex_val(stream_, cd_.nverts, cd_.vnode, N, cb_, t3_);
+            interior_extend<T>(in, t3_);
+            HIPOK(hipMemcpyAsync(out, t3_, 2 * N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
+            return 0;
+        }
+        default:
+            set_error("unknown FETI-DP operator");
+            return BDM_E_ARG;
+    }
+}
+
+// PCG (zero initial guess, unpreconditioned residual norm test, Polak-Ribiere
+// beta), on the full Jacobian with BDDC or on the FETI-DP multiplier system.
+int Context::pcg(int n, const double* b, double* x, bool feti, KrylovOut& out) {
+    out = KrylovOut();
+    const size_t bytes = (size_t)n * sizeof(double);
+    HIPOK(hipMemsetAsync(x, 0, bytes, stream_));
+    HIPOK(hipMemcpyAsync(kr_, b, bytes, hipMemcpyDeviceToDevice, stream_));
+    const double r0 = std::sqrt(dot(n, kr_, kr_));
+    out.hist.push_back(r0);
+    if (r0 == 0.0) return 0;
+    auto A = [&](const double* in, double* o) -> int {
+        if (feti) return prec_ ? fetidp_apply_t<float>(BDM_FETI_F, in, o) : fetidp_apply_t<double>(BDM_FETI_F, in, o);
+        launch_jac_apply(stream_, fp, st_, dg_, in, o);
+        return 0;
+    };
+    auto M = [&](const double* in, double* o) -> int {
+        if (feti)
+            return prec_ ? fetidp_apply_t<float>(BDM_FETI_PRECOND, in, o)
+                         : fetidp_apply_t<double>(BDM_FETI_PRECOND, in, o);
+        return prec_ ? bddc_apply_t<float>(in, o) : bddc_apply_t<double>(in, o);
+    };
+    int rc = M(kr_, kz_);
+    if (rc) return rc;
+    HIPOK(hipMemcpyAsync(kp_, kz_, bytes, hipMemcpyDeviceToDevice, stream_));
+    double rz = dot(n, kr_, kz_);
+    out.status = 1;
+    for (int it = 0; it < opts.krylov_maxit; ++it) {
+        if ((rc = A(kp_, kq_))) return rc;
+        const double pq = dot(n, kp_, kq_);
+        const double alpha = rz / pq;
+        launch_axpy(stream_, n, alpha, kp_, x);
+        HIPOK(hipMemcpyAsync(kro_, kr_, bytes, hipMemcpyDeviceToDevice, stream_));
+        launch_axpy(stream_, n, -alpha, kq_, kr_);
+        out.alpha.push_back(alpha);
+        out.its = it + 1;
+        const double rn = std::sqrt(dot(n, kr_, kr_));
+        out.hist.push_back(rn);
+        if (!(rn == rn)) { out.status = 2; break; }
+        if (rn <= opts.krylov_rtol * r0) { out.status = 0; break; }
+        if (rn > opts.krylov_dtol * r0) { out.status = 2; break; }
+        if ((rc = M(kr_, kz_))) return rc;
+        const double zr = dot(n, kz_, kr_);
+        const double zro = dot(n, kz_, kro_);
+        const double beta = (zr - zro) / rz;
+        rz = zr;
+        out.beta.push_back(beta);
+        launch_scale_add(stream_, n, kz_, beta, kp_);
+    }
+    out.cond = lanczos_cond(out.alpha, out.beta);
+    return 0;
+}
+
+// J s = b with the configured preconditioner.
+int Context::newton_solve(const double* b, double* s, KrylovOut& out) {
+    // project the u_e block of b onto the range (zero sum)
+    HIPOK(hipMemcpyAsync(Rt_, b, 2 * N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
+    launch_sub_mean(stream_, N, Rt_ + N, part_, scal_);
+    if (opts.solver != BDM_SOLVER_FETIDP) return pcg((int)(2 * N), Rt_, s, false, out);
+    // FETI-DP: d = B S~^{-1} f~, PCG on F lambda = d, then recovery.
+    int rc = prec_ ? fetidp_apply_t<float>(BDM_FETI_RHS, Rt_, kq_) : fetidp_apply_t<double>(BDM_FETI_RHS, Rt_, kq_);
+    if (rc) return rc;
+    double* d = S_;   // S_ is free until the solution is written
+    HIPOK(hipMemcpyAsync(d, kq_, nlam_ * sizeof(double), hipMemcpyDeviceToDevice, stream_));
+    rc = pcg((int)nlam_, d, kx_, true, out);
+    if (rc) return rc;
+    // recover: input [b ; lambda]
+    HIPOK(hipMemcpyAsync(kq_, Rt_, 2 * N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
+    HIPOK(hipMemcpyAsync(kq_ + 2 * N, kx_, nlam_ * sizeof(double), hipMemcpyDeviceToDevice, stream_));
+    rc = prec_ ? fetidp_apply_t<float>(BDM_FETI_RECOVER, kq_, s) : fetidp_apply_t<double>(BDM_FETI_RECOVER, kq_, s);
+    return rc;
+}
+
+int Context::step(int nsteps, bdm_step_stats* st) {
+    using clk = std::chrono::steady_clock;
+    const size_t vb = (size_t)N * sizeof(double);
+    for (int ks = 0; ks < nsteps; ++ks) {
+        bdm_step_stats S{};
+        S.bad_subdomain = -1;
+        const auto t0 = clk::now();
+        double tsetup = 0, tkry = 0;
+        // Step 1: gating update from v^n (Sec. 3b)
+        HIPOK(hipMemcpyAsync(vn_, v_, vb, hipMemcpyDeviceToDevice, stream_));
+        launch_ionic_update(stream_, fp, v_, w_);
+        const double stim = (have_stim_ && nstep_ >= stim_on_ && nstep_ < stim_off_) ? 1.0 : 0.0;
+        // reference residual ||R(u^n)||
+        launch_residual(stream_, fp, st_, v_, ue_, vn_, w_, Is_, stim, R_, R_ + N);
+        const double ref = std::sqrt(dot(2 * N, R_, R_));
+        // initial guess
+        if (opts.guess == BDM_GUESS_EXTRAP && have_prev_) {
+            hipLaunchKernelGGL(k_lin_comb, dim3(nb(N, 256)), dim3(256), 0, stream_, N, 2.0, v_, -1.0, vprev_, U_);
+            hipLaunchKernelGGL(k_lin_comb, dim3(nb(N, 256)), dim3(256), 0, stream_, N, 2.0, ue_, -1.0, ueprev_, U_ + N);
+        } else {
+            HIPOK(hipMemcpyAsync(U_, v_, vb, hipMemcpyDeviceToDevice, stream_));
+            HIPOK(hipMemcpyAsync(U_ + N, ue_, vb, hipMemcpyDeviceToDevice, stream_));
+        }
+        launch_residual(stream_, fp, st_, U_, U_ + N, vn_, w_, Is_, stim, R_, R_ + N);
+        double rn = std::sqrt(dot(2 * N, R_, R_));
+        S.res_hist[0] = rn;
+        int it = 0;
+        int status = 0;
+        for (; it < opts.newton_maxit; ++it) {
+            if (rn <= std::max(opts.newton_rtol * ref, opts.newton_atol)) break;
+            if (it >= 32) break;
+            const auto ts = clk::now();
+            int rc = linearize(U_, w_);
+            tsetup += std::chrono::duration<double, std::milli>(clk::now() - ts).count();
+            if (rc) return rc;
+            // s = J^{-1} (-R)
+            launch_scale_add(stream_, 2 * N, gzero_, -1.0, R_);   // R <- -R
+            KrylovOut ko;
+            const auto tk = clk::now();
+            rc = newton_solve(R_, S_, ko);
+            tkry += std::chrono::duration<double, std::milli>(clk::now() - tk).count();
+            if (rc) return rc;
+            launch_scale_add(stream_, 2 * N, gzero_, -1.0, R_);   // restore R
+            S.krylov_its[it] = ko.its;
+            S.cond[it] = ko.cond;
+            if (ko.status == 2) {
+                set_error("Krylov iteration diverged");
+                status = BDM_E_KRYLOV_DIVERGED;
+                break;
+            }
+            if (ko.status == 1) status = BDM_E_KRYLOV_MAXIT;
+            // line search on f = ||R||^2 / 2 (Armijo, quadratic then cubic backtracking)
+            const double f0 = 0.5 * rn * rn, g0 = -2.0 * f0, alpha = 1e-4;
+            double lam = 1.0, lam_prev = 0.0, f_prev = 0.0, f = 0.0;
+            for (int ls = 0; ls < 20; ++ls) {
+                HIPOK(hipMemcpyAsync(Rt_, U_, 2 * vb, hipMemcpyDeviceToDevice, stream_));
+                launch_axpy(stream_, 2 * N, lam, S_, Rt_);
+                launch_residual(stream_, fp, st_, Rt_, Rt_ + N, vn_, w_, Is_, stim, kq_, kq_ + N);
+                f = 0.5 * dot(2 * N, kq_, kq_);
+                if (f <= f0 + alpha * lam * g0) break;
+                double lt;
+                if (ls == 0) {
+                    lt = -g0 / (2.0 * (f - f0 - g0));
+                } else {
+                    const double r1 = f - f0 - lam * g0, r2 = f_prev - f0 - lam_prev * g0;
+                    const double a = (r1 / (lam * lam) - r2 / (lam_prev * lam_prev)) / (lam - lam_prev);
+                    const double b = (-lam_prev * r1 / (lam * lam) + lam * r2 / (lam_prev * lam_prev)) / (lam - lam_prev);
+                    if (a == 0.0) lt = -g0 / (2.0 * b);
+                    else lt = (-b + std::sqrt(std::max(b * b - 3.0 * a * g0, 0.0))) / (3.0 * a);
+                }
+                lam_prev = lam;
+                f_prev = f;
+                lam = std::min(std::max(lt, 0.1 * lam), 0.5 * lam);
+            }
+            HIPOK(hipMemcpyAsync(U_, Rt_, 2 * vb, hipMemcpyDeviceToDevice, stream_));
+            HIPOK(hipMemcpyAsync(R_, kq_, 2 * vb, hipMemcpyDeviceToDevice, stream_));
+            launch_sub_mean(stream_, N, U_ + N, part_, scal_);
+            rn = std::sqrt(2.0 * f);
+            S.res_hist[it + 1] = rn;
+        }
+        S.newton_its = it;
+        if (status == 0 && it >= opts.newton_maxit && rn > std::max(opts.newton_rtol * ref, opts.newton_atol)) {
+            set_error("Newton iteration limit reached");
+            status = BDM_E_NEWTON_MAXIT;
+        }
+        // history for extrapolation, then the new state
+        HIPOK(hipMemcpyAsync(vprev_, v_, vb, hipMemcpyDeviceToDevice, stream_));
+        HIPOK(hipMemcpyAsync(ueprev_, ue_, vb, hipMemcpyDeviceToDevice, stream_));
+        have_prev_ = true;
+        HIPOK(hipMemcpyAsync(v_, U_, vb, hipMemcpyDeviceToDevice, stream_));
+        HIPOK(hipMemcpyAsync(ue_, U_ + N, vb, hipMemcpyDeviceToDevice, stream_));
+        int rc = sync();
+        if (rc) return rc;
+        ++nstep_;
+        t_ += opts.dt;
+        S.t_setup_ms = tsetup;
+        S.t_krylov_ms = tkry;
+        S.t_step_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+        if (st) *st = S;
+        if (status) return status;
+    }
+    return 0;
+}
+
+}  // namespace bdm

@@ -1,0 +1,118 @@
+// Solver context: topology, device workspace and the host-side control of
+// the Newton-Krylov BDDC / FETI-DP deluxe iteration.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/bidomain.h"
+#include "bddc_kernels.hpp"
+#include "common.hpp"
+#include "kernels.hpp"
+#include "topology.hpp"
+
+namespace bdm {
+
+struct KrylovOut {
+    int its = 0;
+    int status = 0;            // 0 converged, 1 maxit, 2 diverged
+    std::vector<double> alpha, beta, hist;
+    double cond = 1.0;
+};
+
+class Context {
+  public:
+    Context() = default;
+    ~Context();
+    int create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o, hipStream_t s);
+
+    int set_state(const double* v, const double* ue, const double* w, double t, bool dev);
+    int get_state(double* v, double* ue, double* w, double* t, bool dev);
+    int set_stimulus(const double* Is, int on, int off, bool dev);
+    int ionic_update();
+    int residual(const double* v, const double* ue, double* Rv, double* Re);
+    int linearize(const double* v, const double* w);
+    int jacobian_apply(const double* x, double* y);
+    int bddc_apply(const double* r, double* z);
+    int fetidp_apply(int op, const double* in, double* out);
+    int step(int nsteps, bdm_step_stats* st);
+    long n_lambda() const { return nlam_; }
+
+    Topology topo;
+    FEParams fp{};
+    bdm_opts opts{};
+    bdm_physics phys{};
+    int64_t N = 0;
+
+  private:
+    template <typename T> int alloc_local();
+    template <typename T> int linearize_t();
+    template <typename T> void dirichlet(const double* r, const double* q, double* out);
+    template <typename T> void condense(const double* r, double* g);
+    template <typename T> void stilde_inv(T* xr, const double* gvert, double* uc);
+    template <typename T> void interior_extend(const double* r, double* zbuf);
+    template <typename T> int bddc_apply_t(const double* r, double* z);
+    template <typename T> int fetidp_apply_t(int op, const double* in, double* out);
+    int pcg(int n, const double* b, double* x, bool feti, KrylovOut& out);
+    int newton_solve(const double* b, double* s, KrylovOut& out);
+    int sync();
+    double dot(int64_t n, const double* x, const double* y);
+    void* dalloc(size_t bytes);
+    template <typename V> V* upload(const std::vector<V>& h);
+
+    hipStream_t stream_ = nullptr;
+    std::vector<void*> allocs_;
+    bool linearized_ = false;
+    int prec_ = 0;
+    size_t tsize_ = 8;
+
+    // fe
+    double *st_ = nullptr, *ke_ = nullptr;
+    double *v_ = nullptr, *ue_ = nullptr, *w_ = nullptr, *vn_ = nullptr;
+    double *vprev_ = nullptr, *ueprev_ = nullptr, *Is_ = nullptr;
+    double *dg_ = nullptr, *vlin_ = nullptr, *wlin_ = nullptr;
+    int* bad_ = nullptr;
+    int stim_on_ = 0, stim_off_ = 0, nstep_ = 0;
+    bool have_prev_ = false, have_stim_ = false;
+    double t_ = 0.0;
+
+    // batched local storage (element type per precision)
+    void *K_ = nullptr, *slots_ = nullptr, *F_ = nullptr, *Z_ = nullptr, *Gi_ = nullptr;
+    void *fac_ = nullptr, *Srr_ = nullptr, *xI_ = nullptr, *xr_ = nullptr, *xr2_ = nullptr;
+    double *Svv_ = nullptr, *Sp_ = nullptr, *cP_ = nullptr, *mu_ = nullptr;
+    double *Cm_ = nullptr, *cb_ = nullptr, *ybuf_ = nullptr;
+    int *info_sub_ = nullptr, *info_obj_ = nullptr, *info_c_ = nullptr;
+
+    // descriptors (device arrays) and host copies of sizes
+    BatchDesc bd_{};
+    ObjDesc od_{};
+    SubVecDesc sv_{};
+    CoarseDesc cd_{};
+    FetiDesc fd_{};
+    int maxbox_ = 0, nInodes_ = 0;
+    int *Ilist_ = nullptr;
+    int64_t *LII_off_ = nullptr, *Lrr_off_ = nullptr, *xI_off_ = nullptr, *xr_off_ = nullptr;
+    const int64_t *Srr_off_ = nullptr;
+    const int *nI_ = nullptr, *nr_ = nullptr, *ld_ = nullptr, *kF_ = nullptr, *nP_ = nullptr;
+    int *st1c0_ = nullptr, *st1c1_ = nullptr, *st1c2_ = nullptr, *st2c1_ = nullptr;
+    std::vector<std::vector<int>> colors_;   // subdomains per colour (disjoint primal sets)
+    int *color_list_ = nullptr;
+    std::vector<int> color_ptr_;
+    int *cpin_ = nullptr;
+    int64_t *zero64_ = nullptr;
+    int *one_ = nullptr, *np_ = nullptr;
+    int64_t nK_ = 0, nslot_ = 0, nF_ = 0, nZ_ = 0, nfac_ = 0, nSrr_ = 0, nxI_ = 0, nxr_ = 0, nyb_ = 0;
+    int pin_ = 1;
+    long nlam_ = 0;
+
+    // Krylov / Newton workspace (2N or n_lambda doubles)
+    double *kx_ = nullptr, *kr_ = nullptr, *kz_ = nullptr, *kp_ = nullptr, *kq_ = nullptr, *kro_ = nullptr;
+    double *t1_ = nullptr, *t2_ = nullptr, *t3_ = nullptr, *gzero_ = nullptr;
+    double *R_ = nullptr, *S_ = nullptr, *U_ = nullptr, *Rt_ = nullptr;
+    double *part_ = nullptr, *scal_ = nullptr;
+};
+
+void set_error(const std::string& msg);
+
+}  // namespace bdm

@@ -1,0 +1,95 @@
+// FP64 vector kernels of the Krylov and Newton loops.  Dot products use a
+// fixed two-stage reduction (per-block partial sums, then one block), so
+// they are deterministic.
+#include "bddc_kernels.hpp"
+#include "common.hpp"
+
+namespace bdm {
+
+constexpr int kDotBlocks = 1024;
+int dot_partials() { return kDotBlocks; }
+
+namespace {
+
+__device__ inline double wsum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ inline double block_sum(double v) {
+    __shared__ double red[kWG / 64];
+    v = wsum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int q = 0; q < kWG / 64; ++q) t += red[q];
+    __syncthreads();
+    return t;
+}
+
+__global__ __launch_bounds__(kWG) void k_dot_partial(int64_t n, const double* __restrict__ x,
+                                                    const double* __restrict__ y, double* __restrict__ part) {
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG)
+        acc = fma(x[i], y[i], acc);
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(kWG) void k_sum_partials(int np, const double* __restrict__ part,
+                                                     double* __restrict__ out) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += kWG) acc += part[i];
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) out[0] = acc;
+}
+
+__global__ void k_axpy(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = fma(a, x[i], y[i]);
+}
+
+__global__ void k_scale_add(int64_t n, const double* __restrict__ z, double b, double* __restrict__ p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = fma(b, p[i], z[i]);
+}
+
+__global__ void k_sub_scalar(int64_t n, const double* __restrict__ sum, double* __restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] -= sum[0] / (double)n;
+}
+
+__global__ __launch_bounds__(kWG) void k_sum_partial(int64_t n, const double* __restrict__ x,
+                                                    double* __restrict__ part) {
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG)
+        acc += x[i];
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+}  // namespace
+
+static inline unsigned nb(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+void launch_dot(hipStream_t s, int64_t n, const double* x, const double* y, double* partial, double* out) {
+    hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(kWG), 0, s, n, x, y, partial);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kWG), 0, s, kDotBlocks, partial, out);
+}
+void launch_axpy(hipStream_t s, int64_t n, double a, const double* x, double* y) {
+    hipLaunchKernelGGL(k_axpy, dim3(nb(n, 256)), dim3(256), 0, s, n, a, x, y);
+}
+void launch_copy(hipStream_t s, int64_t n, const double* x, double* y) {
+    hipMemcpyAsync(y, x, n * sizeof(double), hipMemcpyDeviceToDevice, s);
+}
+void launch_scale_add(hipStream_t s, int64_t n, const double* z, double b, double* p) {
+    hipLaunchKernelGGL(k_scale_add, dim3(nb(n, 256)), dim3(256), 0, s, n, z, b, p);
+}
+// x <- x - mean(x)
+void launch_sub_mean(hipStream_t s, int64_t n, double* x, double* partial, double* tmp) {
+    hipLaunchKernelGGL(k_sum_partial, dim3(kDotBlocks), dim3(kWG), 0, s, n, x, partial);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kWG), 0, s, kDotBlocks, partial, tmp);
+    hipLaunchKernelGGL(k_sub_scalar, dim3(nb(n, 256)), dim3(256), 0, s, n, tmp, x);
+}
+
+}  // namespace bdm

@@ -1,0 +1,146 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Sizes span several tiles and ragged (uneven) subdomains; comparisons are
+element by element.  FP64 path: relative 1e-11 on operator outputs and 1e-8
+on the Newton solution.  Mixed path (FP32 local factors): relative 5e-5 on a
+single preconditioner application (FP32 round-off amplified by the local
+condition numbers, ~1e3), and 1e-8 on the Newton solution, which the FP64
+outer iteration corrects.
+"""
+import numpy as np
+import pytest
+
+from oracle import bddc, bidomain, dd, fetidp, newton
+from workload import Mesh, Physics, Solver as SolverOpts, stimulus_nodal, workload
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _solver_mod():
+    import paper_2101_02959_amd as P
+    return P
+
+
+MESHES = {
+    "cube8": Mesh(8, 8, 8, 0.01, (0, 4, 8), (0, 4, 8), (0, 4, 8)),
+    "ragged": Mesh(11, 9, 10, 0.01, (0, 3, 7, 11), (0, 5, 9), (0, 4, 10)),
+}
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _gauge(x, N):
+    x = np.array(x, dtype=np.float64).copy()
+    x[N:] -= x[N:].mean()
+    return x
+
+
+def _state(N, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-10, 40, N), rng.uniform(-5, 5, N), rng.uniform(0, 0.2, N)
+
+
+@pytest.mark.parametrize("mname", list(MESHES))
+def test_residual_and_jacobian(mname):
+    P = _solver_mod()
+    mesh = MESHES[mname]
+    ph = Physics()
+    so = SolverOpts()
+    S = P.Solver(mesh, ph, so)
+    prob = bidomain.Problem(mesh, ph, so.dt)
+    N = prob.N
+    vn, ue, w = _state(N, 1)
+    v = vn + np.random.default_rng(2).uniform(-3, 3, N)
+    Is = stimulus_nodal(mesh, (2, 2, 2), 1e5)
+    S.bdm_set_state(vn, np.zeros(N), w)
+    S.bdm_set_stimulus(Is, 0, 1)
+    R = S.bdm_residual(v, ue).cpu().numpy()
+    Rref = prob.residual(v, ue - ue.mean(), vn, w, Is)
+    assert _rel(R, Rref) < 1e-12
+    S.bdm_linearize(v, w)
+    x = np.random.default_rng(3).standard_normal(2 * N)
+    y = S.bdm_jacobian_apply(x).cpu().numpy()
+    yref = prob.jacobian(v, w) @ x
+    assert _rel(y, yref) < 1e-12
+
+
+@pytest.fixture(scope="module", params=list(MESHES))
+def lin(request):
+    mesh = MESHES[request.param]
+    ph = Physics()
+    so = SolverOpts()
+    prob = bidomain.Problem(mesh, ph, so.dt)
+    N = prob.N
+    v, ue, w = _state(N, 4)
+    dec = dd.Decomposition(mesh)
+    B = bddc.BDDC(prob, dec, v, w)
+    return mesh, ph, so, prob, dec, B, v, w
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 5e-5)])
+def test_bddc_apply(lin, prec, tol):
+    P = _solver_mod()
+    mesh, ph, so, prob, dec, B, v, w = lin
+    N = prob.N
+    S = P.Solver(mesh, ph, so, precision=prec)
+    S.bdm_linearize(v, w)
+    for seed in (5, 6):
+        r = newton.project_range(np.random.default_rng(seed).standard_normal(2 * N), N)
+        z = _gauge(S.bdm_bddc_apply(r).cpu().numpy(), N)
+        zref = _gauge(B.apply(r), N)
+        assert _rel(z, zref) < tol, (seed, _rel(z, zref))
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 5e-5)])
+def test_fetidp_operators(lin, prec, tol):
+    P = _solver_mod()
+    mesh, ph, so, prob, dec, B, v, w = lin
+    N = prob.N
+    F = fetidp.FETIDP(B)
+    S = P.Solver(mesh, ph, so, precision=prec, method=P.BDM_SOLVER_FETIDP)
+    S.bdm_linearize(v, w)
+    assert S.bdm_fetidp_size() == F.nlam
+    rng = np.random.default_rng(7)
+    lam = rng.standard_normal(F.nlam)
+    out = S.bdm_fetidp_apply(P.BDM_FETI_F, lam).cpu().numpy()
+    assert _rel(out, F.F(lam)) < tol
+    out = S.bdm_fetidp_apply(P.BDM_FETI_PRECOND, lam).cpu().numpy()
+    assert _rel(out, F.precond(lam)) < tol
+    r = newton.project_range(rng.standard_normal(2 * N), N)
+    g = F.condense(r)
+    d = S.bdm_fetidp_apply(P.BDM_FETI_RHS, r).cpu().numpy()
+    assert _rel(d, F.rhs(g)) < tol
+    z = S.bdm_fetidp_apply(P.BDM_FETI_RECOVER, np.concatenate([r, lam])).cpu().numpy()
+    zref = F.expand(r, F.recover(g, lam))
+    assert _rel(_gauge(z, N), _gauge(zref, N)) < tol
+
+
+@pytest.mark.parametrize("method,prec", [(0, 0), (1, 0), (0, 1)])
+def test_time_steps_match_direct_newton(method, prec):
+    """Newton solution of each step within 1e-8 relative per field of the
+    oracle's direct sparse Newton root, the oracle fed the GPU's u^n."""
+    P = _solver_mod()
+    wl = workload("slab8_supra")
+    mesh = MESHES["ragged"] if method == 0 and prec == 0 else wl.mesh
+    prob = bidomain.Problem(mesh, wl.physics, wl.solver.dt)
+    N = prob.N
+    S = P.Solver(mesh, wl.physics, wl.solver, precision=prec, method=method)
+    Is = stimulus_nodal(mesh, (2, 2, 2), 1e5)
+    S.bdm_set_state(np.zeros(N), np.zeros(N), np.zeros(N))
+    S.bdm_set_stimulus(Is, 0, 20)
+    v, ue, w = np.zeros(N), np.zeros(N), np.zeros(N)
+    for step in range(3):
+        st = S.bdm_step(1)
+        vg, ueg, wg, _ = S.bdm_get_state()
+        vg, ueg, wg = vg.cpu().numpy(), ueg.cpu().numpy(), wg.cpu().numpy()
+        vr, uer, wr, _ = bidomain.time_step_direct(prob, v, ue, w, Is)
+        assert _rel(vg, vr) <= 1e-8, (step, _rel(vg, vr))
+        assert _rel(ueg, uer) <= 1e-8, (step, _rel(ueg, uer))
+        assert _rel(wg, wr) <= 1e-14
+        assert 1 <= st.newton_its <= 5
+        assert all(3 <= st.krylov_its[k] <= 60 for k in range(st.newton_its))
+        v, ue, w = vg, ueg, wg
