@@ -44,7 +44,7 @@ template <typename T>
 __global__ void k_assemble(BatchDesc d, FEParams p, const double* __restrict__ ke,
                            const double* __restrict__ v, const double* __restrict__ w,
                            T* __restrict__ K) {
-    const int s = blockIdx.y;
+    const int s = d.sub0 + blockIdx.y;
     const int* bx = d.box + 6 * s;
     const int ex0 = bx[0], ey0 = bx[1], ez0 = bx[2], Lx = bx[3], Ly = bx[4], Lz = bx[5];
     const int nbox = (Lx + 1) * (Ly + 1) * (Lz + 1);
@@ -207,7 +207,7 @@ template <typename T>
 __global__ __launch_bounds__(kWG) void k_extract(BatchDesc d, const T* __restrict__ K, T* __restrict__ slots,
                                                 T* __restrict__ F, double* __restrict__ Svv,
                                                 T* __restrict__ Srr) {
-    const int s = blockIdx.x;
+    const int s = d.sub0 + blockIdx.x;
     const int tid = threadIdx.x;
     const int64_t ld = d.n[s];
     const int nI = d.nI[s], nr = d.nr[s], nV = d.nV[s], nc = d.nc[s];
@@ -246,6 +246,29 @@ __global__ __launch_bounds__(kWG) void k_extract(BatchDesc d, const T* __restric
             const int a = idx % nr, b = idx / nr;
             dst[idx] = Sat(a, b);
         }
+    }
+}
+
+// Copy the lower triangles of the Dirichlet factor L_II and the Neumann
+// factor L_rr out of the chunk workspace into compact square storage.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_copy_out(BatchDesc d, const T* __restrict__ K, T* __restrict__ LII,
+                                                 const int64_t* __restrict__ LIIoff, T* __restrict__ Lrr,
+                                                 const int64_t* __restrict__ Lrroff) {
+    const int s = d.sub0 + blockIdx.x;
+    const int64_t ld = d.n[s];
+    const int nI = d.nI[s], nr = d.nr[s];
+    const T* A = K + d.K_off[s];
+    T* a = LII + LIIoff[s];
+    for (int64_t idx = threadIdx.x; idx < (int64_t)nI * nI; idx += kWG) {
+        const int i = (int)(idx % nI), j = (int)(idx / nI);
+        a[idx] = (i >= j) ? A[i + (int64_t)j * ld] : (T)0;
+    }
+    const T* B = A + (int64_t)nI * (ld + 1);
+    T* b = Lrr + Lrroff[s];
+    for (int64_t idx = threadIdx.x; idx < (int64_t)nr * nr; idx += kWG) {
+        const int i = (int)(idx % nr), j = (int)(idx / nr);
+        b[idx] = (i >= j) ? B[i + (int64_t)j * ld] : (T)0;
     }
 }
 
@@ -311,7 +334,7 @@ __global__ __launch_bounds__(kWG) void k_coarse_local(BatchDesc d, const T* __re
                                                      const double* __restrict__ Svv, T* __restrict__ Zb,
                                                      T* __restrict__ Gib, double* __restrict__ Spb,
                                                      int* __restrict__ info) {
-    const int s = blockIdx.x;
+    const int s = d.sub0 + blockIdx.x;
     const int tid = threadIdx.x;
     const int nr = d.nr[s], nV = d.nV[s], nc = d.nc[s], nP = nV + nc;
     const T* Y = Fb + d.F_off[s];
@@ -416,15 +439,22 @@ __global__ __launch_bounds__(kWG) void k_trsv_fwd(const T* __restrict__ Lb, cons
     const int n = nv[s];
     const int64_t ld = ldv[s];
     const int tid = threadIdx.x, lane = tid & 63;
+    __shared__ T D[NB][NB + 1];
     __shared__ T xs[NB];
     for (int j0 = 0; j0 < n; j0 += NB) {
         const int jb = min(NB, n - j0);
+        // stage the diagonal block (coalesced along columns)
+        for (int idx = tid; idx < NB * NB; idx += kWG) {
+            const int i = idx % NB, j = idx / NB;
+            D[i][j] = (i < jb && j < jb && j <= i) ? L[(j0 + i) + (j0 + j) * ld] : (T)(i == j);
+        }
+        __syncthreads();
         if (tid < 64) {
             T xv = (lane < jb) ? x[j0 + lane] : (T)0;
             for (int c = 0; c < jb; ++c) {
-                const T xc = __shfl(xv, c) / L[(j0 + c) * (ld + 1)];
+                const T xc = __shfl(xv, c) / D[c][c];
                 if (lane == c) xv = xc;
-                else if (lane > c && lane < jb) xv -= L[(j0 + lane) + (j0 + c) * ld] * xc;
+                else if (lane > c && lane < NB) xv -= D[lane][c] * xc;
             }
             if (lane < jb) { xs[lane] = xv; x[j0 + lane] = xv; }
         }
@@ -449,9 +479,14 @@ __global__ __launch_bounds__(kWG) void k_trsv_bwd(const T* __restrict__ Lb, cons
     const int64_t ld = ldv[s];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     __shared__ T red[kWG / 64][NB];
+    __shared__ T D[NB][NB + 1];
     const int nblk = (n + NB - 1) / NB;
     for (int bi = nblk - 1; bi >= 0; --bi) {
         const int j0 = bi * NB, jb = min(NB, n - j0);
+        for (int idx = tid; idx < NB * NB; idx += kWG) {
+            const int i = idx % NB, j = idx / NB;
+            D[i][j] = (i < jb && j < jb && j <= i) ? L[(j0 + i) + (j0 + j) * ld] : (T)(i == j);
+        }
         T acc[NB];
 #pragma unroll
         for (int c = 0; c < NB; ++c) acc[c] = (T)0;
@@ -474,9 +509,9 @@ __global__ __launch_bounds__(kWG) void k_trsv_bwd(const T* __restrict__ Lb, cons
                 for (int q = 0; q < kWG / 64; ++q) rhs -= red[q][lane];
             }
             for (int c = jb - 1; c >= 0; --c) {
-                const T xc = __shfl(rhs, c) / L[(j0 + c) * (ld + 1)];
+                const T xc = __shfl(rhs, c) / D[c][c];
                 if (lane == c) rhs = xc;
-                else if (lane < c) rhs -= L[(j0 + c) + (j0 + lane) * ld] * xc;
+                else if (lane < c) rhs -= D[c][lane] * xc;
             }
             if (lane < jb) x[j0 + lane] = rhs;
         }
@@ -540,6 +575,11 @@ void launch_extract(hipStream_t s, const BatchDesc& d, const T* K, T* slots, T* 
     hipLaunchKernelGGL(k_extract<T>, dim3(d.nsub), dim3(kWG), 0, s, d, K, slots, F, Svv, Srr);
 }
 template <typename T>
+void launch_copy_out(hipStream_t s, const BatchDesc& d, int nb, const T* K, T* LII, const int64_t* LIIoff, T* Lrr,
+                     const int64_t* Lrroff) {
+    hipLaunchKernelGGL(k_copy_out<T>, dim3(nb), dim3(kWG), 0, s, d, K, LII, LIIoff, Lrr, Lrroff);
+}
+template <typename T>
 void launch_trsm_fwd(hipStream_t s, int nb, const T* L, const int64_t* Loff, const int* n, const int* ld,
                      T* B, const int64_t* Boff, const int* ldb, const int* k) {
     hipLaunchKernelGGL(k_trsm_fwd<T>, dim3(nb), dim3(kWG), 0, s, L, Loff, n, ld, B, Boff, ldb, k);
@@ -568,6 +608,8 @@ void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, const T* slots, T* fac
     template void launch_potrf<T>(hipStream_t, int, T*, const int64_t*, const int*, const int*,         \
                                   const int*, const int*, int*);                                         \
     template void launch_extract<T>(hipStream_t, const BatchDesc&, const T*, T*, T*, double*, T*);      \
+    template void launch_copy_out<T>(hipStream_t, const BatchDesc&, int, const T*, T*, const int64_t*, T*,    \
+                                     const int64_t*);                                                    \
     template void launch_trsm_fwd<T>(hipStream_t, int, const T*, const int64_t*, const int*, const int*, \
                                      T*, const int64_t*, const int*, const int*);                        \
     template void launch_coarse_local<T>(hipStream_t, const BatchDesc&, const T*, const double*, T*, T*, \

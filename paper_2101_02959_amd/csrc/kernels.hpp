@@ -28,12 +28,13 @@ void launch_res_minus_jac(hipStream_t s, const FEParams& p, const double* st, co
 // Per-subdomain layout descriptor (device arrays, length nsub).
 struct BatchDesc {
     int nsub;
+    int sub0;              // first subdomain of the batch (chunked setup)
     const int* n;          // local dofs nI + nG (= leading dimension of K)
     const int* nI;
     const int* nr;
     const int* nV;
     const int* nc;
-    const int64_t* K_off;  // start of the local matrix K in the K buffer
+    const int64_t* K_off;  // start of the local matrix K in the (chunk) K buffer
     const int* box;        // ex0, ey0, ez0, Lx, Ly, Lz per subdomain
     const int64_t* lmap_off;
     const int* lmap;       // box node -> local node index in [I | r | V]
@@ -60,6 +61,9 @@ void launch_potrf(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld
 template <typename T>
 void launch_extract(hipStream_t s, const BatchDesc& d, const T* K, T* slots, T* F, double* Svv,
                     T* Srr);
+template <typename T>
+void launch_copy_out(hipStream_t s, const BatchDesc& d, int nb, const T* K, T* LII, const int64_t* LIIoff, T* Lrr,
+                     const int64_t* Lrroff);
 template <typename T>
 void launch_trsm_fwd(hipStream_t s, int nb, const T* L, const int64_t* Loff, const int* n,
                      const int* ld, T* B, const int64_t* Boff, const int* ldb, const int* k);

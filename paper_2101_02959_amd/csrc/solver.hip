@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <numeric>
+#include <cstdlib>
 
 namespace bdm {
 
@@ -19,30 +20,6 @@ thread_local std::string g_err;
 constexpr int MAXC = 24, MAXV = 16, MAXP = 40;
 constexpr int SVV_STRIDE = MAXV * MAXV, GI_STRIDE = MAXC * MAXC, SP_STRIDE = MAXP * MAXP;
 constexpr int MAXOBJ = 512;
-
-__global__ void k_coarse_assemble(const int* __restrict__ list, const int* __restrict__ nPv,
-                                  const int64_t* __restrict__ P_off, const int* __restrict__ primal,
-                                  const double* __restrict__ Sp, int np, double* __restrict__ C) {
-    const int s = list[blockIdx.x];
-    const int nP = nPv[s];
-    const int* pr = primal + P_off[s];
-    const double* S = Sp + (int64_t)s * SP_STRIDE;
-    for (int idx = threadIdx.x; idx < nP * nP; idx += blockDim.x) {
-        const int a = idx % nP, b = idx / nP;
-        C[pr[a] + (int64_t)pr[b] * np] += S[a + b * nP];
-    }
-}
-
-// Pin one u_e primal of the singular coarse matrix: zero its row / column
-// and put 1 on the diagonal.
-__global__ void k_coarse_pin(double* __restrict__ C, int np, int pin) {
-    for (int i = threadIdx.x; i < np; i += blockDim.x) {
-        C[pin + (int64_t)i * np] = 0.0;
-        C[i + (int64_t)pin * np] = 0.0;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) C[pin + (int64_t)pin * np] = 1.0;
-}
 
 template <typename T>
 __global__ void k_sub_t(int64_t n, const T* __restrict__ x, T* __restrict__ y) {
@@ -178,7 +155,7 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
     std::vector<int64_t> xI_off(nsub), xr_off(nsub), LII(nsub), Lrr(nsub), Srr_off(nsub);
     std::vector<int> lmap, primal, Ilist;
     std::vector<int> st1c0(nsub, 0), st1c1(nsub), st1c2(nsub), st2c1(nsub);
-    int64_t accK = 0, accF = 0, accZ = 0, accP = 0, accI = 0, accR = 0, accS = 0;
+    int64_t accK = 0, accF = 0, accZ = 0, accP = 0, accI = 0, accR = 0, accS = 0, accLII = 0, accLrr = 0;
     for (int q = 0; q < nsub; ++q) {
         const SubInfo& sb = topo.subs[q];
         if (sb.nc > MAXC || sb.nV > MAXV) {
@@ -193,8 +170,8 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
         lmap_off[q] = (int64_t)lmap.size();
         lmap.insert(lmap.end(), sb.lmap.begin(), sb.lmap.end());
         K_off[q] = accK; accK += (int64_t)sb.n() * sb.n();
-        LII[q] = K_off[q];
-        Lrr[q] = K_off[q] + (int64_t)sb.nI * (sb.n() + 1);
+        LII[q] = accLII; accLII += (int64_t)sb.nI * sb.nI;
+        Lrr[q] = accLrr; accLrr += (int64_t)sb.nr * sb.nr;
         F_off[q] = accF; accF += (int64_t)sb.nr * (sb.nc + sb.nV);
         Z_off[q] = accZ; accZ += (int64_t)sb.nr * sb.nP;
         P_off[q] = accP; accP += sb.nP;
@@ -206,6 +183,30 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
         st1c1[q] = sb.nI; st1c2[q] = sb.n(); st2c1[q] = sb.nI + sb.nr;
     }
     nK_ = accK; nF_ = accF; nZ_ = accZ; nxI_ = accI; nxr_ = accR; nSrr_ = accS;
+    nLII_ = accLII; nLrr_ = accLrr;
+    // chunks of subdomains whose local matrices fit the setup workspace
+    {
+        double gb = 16.0;
+        if (const char* e = std::getenv("BDM_SETUP_WORKSPACE_GB")) gb = std::atof(e);
+        const int64_t budget = std::max<int64_t>((int64_t)(gb * 1e9) / (int64_t)tsize_, 1);
+        std::vector<int64_t> kc(nsub);
+        chunks_.clear();
+        int start = 0;
+        int64_t acc = 0;
+        for (int q = 0; q < nsub; ++q) {
+            const int64_t sz = (int64_t)n[q] * n[q];
+            if (q > start && acc + sz > budget) {
+                chunks_.push_back({start, q});
+                start = q;
+                acc = 0;
+            }
+            kc[q] = acc;
+            acc += sz;
+            nKwork_ = std::max(nKwork_, acc);
+        }
+        chunks_.push_back({start, nsub});
+        Kc_off_ = upload(kc);
+    }
     nInodes_ = (int)Ilist.size();
 
     // ---------------- objects (faces then edges) and their shares
@@ -304,8 +305,9 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
 
     // ---------------- upload descriptors
     bd_.nsub = nsub;
+    bd_.sub0 = 0;
     bd_.n = upload(n); bd_.nI = upload(nI); bd_.nr = upload(nr); bd_.nV = upload(nV); bd_.nc = upload(nc);
-    bd_.K_off = upload(K_off); bd_.box = upload(box); bd_.lmap_off = upload(lmap_off); bd_.lmap = upload(lmap);
+    bd_.K_off = Kc_off_; bd_.box = upload(box); bd_.lmap_off = upload(lmap_off); bd_.lmap = upload(lmap);
     bd_.F_off = upload(F_off); bd_.Z_off = upload(Z_off);
     bd_.so_ptr = upload(so_ptr); bd_.so_roff = upload(so_roff); bd_.so_n = upload(so_n);
     bd_.so_slot = upload(so_slot); bd_.so_kind = upload(so_kind); bd_.so_nnode = upload(so_nnode);
@@ -332,6 +334,52 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
     one_ = upload(npv);
     // pin: the u_e dof of the first vertex (or of the first edge average)
     pin_ = 1;
+    // coarse groups: position along x of each primal object (cut a -> 2a-1,
+    // slab a -> 2a), pairs (cut a, slab a) form group a; consecutive groups are
+    // merged up to a minimum block size.
+    {
+        std::vector<char> xcut(topo.nx + 1, 0);
+        for (int a = 1; a < topo.px; ++a) xcut[topo.cx[a]] = 1;
+        auto gpos = [&](int node) {
+            const int i = node % (topo.nx + 1);
+            if (xcut[i]) {
+                int a = 0;
+                while (topo.cx[a] != i) ++a;
+                return a;          // cut a belongs to group a
+            }
+            int a = 0;
+            while (!(topo.cx[a] <= i && i < topo.cx[a + 1])) ++a;
+            return a;              // slab a belongs to group a
+        };
+        std::vector<int> g0(np);
+        for (int v = 0; v < (int)topo.verts.size(); ++v) g0[2 * v] = g0[2 * v + 1] = gpos(topo.verts[v].nodes[0]);
+        const int nv2 = 2 * (int)topo.verts.size();
+        for (int e = 0; e < (int)topo.edges.size(); ++e)
+            g0[nv2 + 2 * e] = g0[nv2 + 2 * e + 1] = gpos(topo.edges[e].nodes[0]);
+        int minsz = 1024;
+        if (const char* ev = std::getenv("BDM_COARSE_MIN_BLOCK")) minsz = std::atoi(ev);
+        std::vector<int> cnt(topo.px, 0), remap(topo.px, 0);
+        for (int p = 0; p < np; ++p) ++cnt[g0[p]];
+        int G = 0, acc = 0;
+        for (int a = 0; a < topo.px; ++a) {
+            remap[a] = G;
+            acc += cnt[a];
+            if (acc >= minsz) { ++G; acc = 0; }
+        }
+        if (acc > 0) ++G;
+        for (int a = 0; a < topo.px; ++a) remap[a] = std::min(remap[a], G - 1);
+        std::vector<int> gof(np);
+        for (int p = 0; p < np; ++p) gof[p] = remap[g0[p]];
+        coarse_.init(gof, pin_, np);
+        for (int q = 0; q < nsub; ++q) {
+            int lo = 1 << 30, hi = -1;
+            for (int p : topo.subs[q].primal) { lo = std::min(lo, gof[p]); hi = std::max(hi, gof[p]); }
+            if (hi - lo > 1) {
+                set_error("internal error: coarse ordering is not block tridiagonal");
+                return BDM_E_ARG;
+            }
+        }
+    }
 
     // ---------------- global vectors and workspace
     const size_t vb = (size_t)N * sizeof(double);
@@ -362,7 +410,9 @@ template <typename T>
 int Context::alloc_local() {
     const int nsub = (int)topo.subs.size();
     const bool feti = opts.solver == BDM_SOLVER_FETIDP;
-    K_ = dalloc(nK_ * sizeof(T));
+    K_ = dalloc(nKwork_ * sizeof(T));
+    LIIs_ = dalloc(nLII_ * sizeof(T));
+    Lrrs_ = dalloc(nLrr_ * sizeof(T));
     slots_ = dalloc(nslot_ * sizeof(T));
     F_ = dalloc(nF_ * sizeof(T));
     Z_ = dalloc(nZ_ * sizeof(T));
@@ -377,14 +427,31 @@ int Context::alloc_local() {
     cP_ = (double*)dalloc((size_t)nsub * MAXP * sizeof(double));
     mu_ = (double*)dalloc((size_t)nsub * MAXC * sizeof(double));
     const int np = topo.nprimal;
-    Cm_ = (double*)dalloc((size_t)np * np * sizeof(double));
     cb_ = (double*)dalloc((size_t)np * sizeof(double));
+    {
+        CoarseSolver& c = coarse_;
+        c.D = (double*)dalloc(c.nD * sizeof(double));
+        c.E = (double*)dalloc(std::max<int64_t>(c.nE, 1) * sizeof(double));
+        c.Cb = (double*)dalloc(std::max<int64_t>(c.nE, 1) * sizeof(double));
+        c.yb = (double*)dalloc((size_t)np * sizeof(double));
+        c.zb = (double*)dalloc((size_t)np * sizeof(double));
+        c.Bw = (double*)dalloc(32 * 32 * sizeof(double));
+        c.Tw = (double*)dalloc((size_t)c.maxn * 32 * sizeof(double));
+        c.Rw = (double*)dalloc((size_t)c.maxn * 32 * sizeof(double));
+        c.info = (int*)dalloc(sizeof(int));
+        c.d_grp = upload(c.grp); c.d_pos = upload(c.pos); c.d_ng = upload(c.ng);
+        c.d_Doff = upload(c.D_off); c.d_Eoff = upload(c.E_off); c.d_goff = upload(c.goff);
+        if (!c.D || !c.E || !c.Cb || !c.yb || !c.zb || !c.Bw || !c.Tw || !c.Rw || !c.info) {
+            set_error("device allocation failed (coarse)");
+            return BDM_E_OOM;
+        }
+    }
     ybuf_ = (double*)dalloc(nyb_ * sizeof(double));
     info_sub_ = (int*)dalloc(nsub * sizeof(int));
     info_obj_ = (int*)dalloc((size_t)od_.nobj * sizeof(int));
     info_c_ = (int*)dalloc(sizeof(int));
-    if (!K_ || !slots_ || !F_ || !Z_ || !Gi_ || !fac_ || (feti && !Srr_) || !xI_ || !xr_ || !xr2_ || !Svv_ ||
-        !Sp_ || !cP_ || !mu_ || !Cm_ || !cb_ || !ybuf_ || !info_sub_ || !info_obj_ || !info_c_) {
+    if (!K_ || !LIIs_ || !Lrrs_ || !slots_ || !F_ || !Z_ || !Gi_ || !fac_ || (feti && !Srr_) || !xI_ || !xr_ ||
+        !xr2_ || !Svv_ || !Sp_ || !cP_ || !mu_ || !cb_ || !ybuf_ || !info_sub_ || !info_obj_ || !info_c_) {
         set_error("device allocation failed (local factors)");
         return BDM_E_OOM;
     }
@@ -465,35 +532,36 @@ int Context::linearize_t() {
     HIPOK(hipMemsetAsync(bad_, 0, sizeof(int), stream_));
     launch_reaction_diag(stream_, fp, vlin_, wlin_, dg_, bad_);
     T* K = (T*)K_;
-    HIPOK(hipMemsetAsync(K, 0, nK_ * sizeof(T), stream_));
     HIPOK(hipMemsetAsync(info_sub_, 0, nsub * sizeof(int), stream_));
     HIPOK(hipMemsetAsync(info_obj_, 0, od_.nobj * sizeof(int), stream_));
     HIPOK(hipMemsetAsync(info_c_, 0, sizeof(int), stream_));
-    launch_assemble<T>(stream_, bd_, maxbox_, fp, ke_, vlin_, wlin_, K);
-    // interior elimination: L_II, and S_Gamma in the trailing block
-    launch_potrf<T>(stream_, nsub, K, bd_.K_off, ld_, st1c0_, st1c1_, st1c2_, info_sub_);
     HIPOK(hipMemsetAsync(F_, 0, nF_ * sizeof(T), stream_));
-    launch_extract<T>(stream_, bd_, K, (T*)slots_, (T*)F_, Svv_, (T*)Srr_);
-    // constrained Neumann factor L_rr of S_rr
-    launch_potrf<T>(stream_, nsub, K, bd_.K_off, ld_, st1c1_, st2c1_, st2c1_, info_sub_);
-    launch_trsm_fwd<T>(stream_, nsub, K, Lrr_off_, nr_, ld_, (T*)F_, bd_.F_off, nr_, kF_);
+    for (const auto& ch : chunks_) {
+        const int s0 = ch.first, cnt = ch.second - ch.first;
+        BatchDesc cd = bd_;
+        cd.nsub = cnt;
+        cd.sub0 = s0;
+        HIPOK(hipMemsetAsync(K, 0, nKwork_ * sizeof(T), stream_));
+        launch_assemble<T>(stream_, cd, maxbox_, fp, ke_, vlin_, wlin_, K);
+        // interior elimination: L_II, and S_Gamma in the trailing block
+        launch_potrf<T>(stream_, cnt, K, Kc_off_ + s0, ld_ + s0, st1c0_ + s0, st1c1_ + s0, st1c2_ + s0,
+                        info_sub_ + s0);
+        launch_extract<T>(stream_, cd, K, (T*)slots_, (T*)F_, Svv_, (T*)Srr_);
+        // constrained Neumann factor L_rr of S_rr
+        launch_potrf<T>(stream_, cnt, K, Kc_off_ + s0, ld_ + s0, st1c1_ + s0, st2c1_ + s0, st2c1_ + s0,
+                        info_sub_ + s0);
+        launch_copy_out<T>(stream_, cd, cnt, K, (T*)LIIs_, LII_off_, (T*)Lrrs_, Lrr_off_);
+    }
+    launch_trsm_fwd<T>(stream_, nsub, (const T*)Lrrs_, Lrr_off_, nr_, nr_, (T*)F_, bd_.F_off, nr_, kF_);
     launch_coarse_local<T>(stream_, bd_, (const T*)F_, Svv_, (T*)Z_, (T*)Gi_, Sp_, info_sub_);
     launch_deluxe_setup<T>(stream_, od_, (const T*)slots_, (T*)fac_, info_obj_);
-    HIPOK(hipMemsetAsync(Cm_, 0, (size_t)np * np * sizeof(double), stream_));
-    for (int c = 0; c < 8; ++c) {
-        const int cnt = color_ptr_[c + 1] - color_ptr_[c];
-        if (cnt == 0) continue;
-        hipLaunchKernelGGL(k_coarse_assemble, dim3(cnt), dim3(kWG), 0, stream_, color_list_ + color_ptr_[c],
-                           nP_, sv_.P_off, sv_.primal, Sp_, np, Cm_);
-    }
-    hipLaunchKernelGGL(k_coarse_pin, dim3(1), dim3(kWG), 0, stream_, Cm_, np, pin_);
-    launch_potrf<double>(stream_, 1, Cm_, zero64_, np_, cpin_, np_, np_, info_c_);
+    coarse_.factor(stream_, color_list_, color_ptr_, nP_, sv_.P_off, sv_.primal, Sp_, SP_STRIDE);
     int hb = 0, hc = 0;
     std::vector<int> hs(nsub), ho(od_.nobj);
     HIPOK(hipMemcpyAsync(&hb, bad_, sizeof(int), hipMemcpyDeviceToHost, stream_));
     HIPOK(hipMemcpyAsync(hs.data(), info_sub_, nsub * sizeof(int), hipMemcpyDeviceToHost, stream_));
     HIPOK(hipMemcpyAsync(ho.data(), info_obj_, od_.nobj * sizeof(int), hipMemcpyDeviceToHost, stream_));
-    HIPOK(hipMemcpyAsync(&hc, info_c_, sizeof(int), hipMemcpyDeviceToHost, stream_));
+    HIPOK(hipMemcpyAsync(&hc, coarse_.info, sizeof(int), hipMemcpyDeviceToHost, stream_));
     HIPOK(hipStreamSynchronize(stream_));
     HIPOK(hipGetLastError());
     if (hb) {
@@ -522,8 +590,8 @@ template <typename T>
 void Context::dirichlet(const double* r, const double* q, double* out) {
     T* xI = (T*)xI_;
     launch_gather_I<T>(stream_, nInodes_, Ilist_, N, r, q, xI);
-    launch_trsv<T>(stream_, bd_.nsub, false, (const T*)K_, LII_off_, nI_, ld_, xI, xI_off_);
-    launch_trsv<T>(stream_, bd_.nsub, true, (const T*)K_, LII_off_, nI_, ld_, xI, xI_off_);
+    launch_trsv<T>(stream_, bd_.nsub, false, (const T*)LIIs_, LII_off_, nI_, nI_, xI, xI_off_);
+    launch_trsv<T>(stream_, bd_.nsub, true, (const T*)LIIs_, LII_off_, nI_, nI_, xI, xI_off_);
     launch_scatter_I<T>(stream_, nInodes_, Ilist_, N, xI, out);
 }
 
@@ -540,14 +608,13 @@ void Context::condense(const double* r, double* g) {
 // backward solve for the Neumann correction plus the coarse prolongation.
 template <typename T>
 void Context::stilde_inv(T* xr, const double* gvert, double* uc) {
-    launch_trsv<T>(stream_, bd_.nsub, false, (const T*)K_, Lrr_off_, nr_, ld_, xr, xr_off_);
+    launch_trsv<T>(stream_, bd_.nsub, false, (const T*)Lrrs_, Lrr_off_, nr_, nr_, xr, xr_off_);
     launch_coarse_rhs_local<T>(stream_, sv_, xr, (const T*)F_, (const T*)Z_, (const T*)Gi_, cP_, mu_);
     launch_coarse_rhs_gather(stream_, cd_, N, gvert, cP_, uc);
     launch_coarse_project(stream_, cd_.np, pin_, uc);
-    launch_trsv<double>(stream_, 1, false, Cm_, zero64_, np_, np_, uc, zero64_);
-    launch_trsv<double>(stream_, 1, true, Cm_, zero64_, np_, np_, uc, zero64_);
+    coarse_.solve(stream_, uc);
     launch_neumann_rhs<T>(stream_, sv_, (const T*)F_, (const T*)Z_, mu_, uc, xr, 1);
-    launch_trsv<T>(stream_, bd_.nsub, true, (const T*)K_, Lrr_off_, nr_, ld_, xr, xr_off_);
+    launch_trsv<T>(stream_, bd_.nsub, true, (const T*)Lrrs_, Lrr_off_, nr_, nr_, xr, xr_off_);
 }
 
 // zbuf holds interface values (zero interior); fill the interior by the

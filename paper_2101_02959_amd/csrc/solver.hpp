@@ -8,6 +8,7 @@
 
 #include "../../include/bidomain.h"
 #include "bddc_kernels.hpp"
+#include "coarse.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
 #include "topology.hpp"
@@ -81,7 +82,12 @@ class Context {
     void *K_ = nullptr, *slots_ = nullptr, *F_ = nullptr, *Z_ = nullptr, *Gi_ = nullptr;
     void *fac_ = nullptr, *Srr_ = nullptr, *xI_ = nullptr, *xr_ = nullptr, *xr2_ = nullptr;
     double *Svv_ = nullptr, *Sp_ = nullptr, *cP_ = nullptr, *mu_ = nullptr;
-    double *Cm_ = nullptr, *cb_ = nullptr, *ybuf_ = nullptr;
+    double *cb_ = nullptr, *ybuf_ = nullptr;
+    void *LIIs_ = nullptr, *Lrrs_ = nullptr;   // compact Dirichlet / Neumann factors
+    CoarseSolver coarse_;
+    std::vector<std::pair<int, int>> chunks_;  // subdomain ranges of the chunked setup
+    const int64_t* Kc_off_ = nullptr;           // chunk-relative offsets of the local matrices
+    int64_t nKwork_ = 0, nLII_ = 0, nLrr_ = 0;
     int *info_sub_ = nullptr, *info_obj_ = nullptr, *info_c_ = nullptr;
 
     // descriptors (device arrays) and host copies of sizes

@@ -144,3 +144,18 @@ def test_time_steps_match_direct_newton(method, prec):
         assert 1 <= st.newton_its <= 5
         assert all(3 <= st.krylov_its[k] <= 60 for k in range(st.newton_its))
         v, ue, w = vg, ueg, wg
+
+
+def test_bddc_chunked_setup_and_block_coarse(lin, monkeypatch):
+    """Setup in chunks of a few subdomains and a coarse solve split into one
+    block per subdomain-grid x position give the same operator."""
+    P = _solver_mod()
+    mesh, ph, so, prob, dec, B, v, w = lin
+    N = prob.N
+    monkeypatch.setenv("BDM_SETUP_WORKSPACE_GB", "1e-6")
+    monkeypatch.setenv("BDM_COARSE_MIN_BLOCK", "1")
+    S = P.Solver(mesh, ph, so)
+    S.bdm_linearize(v, w)
+    r = newton.project_range(np.random.default_rng(8).standard_normal(2 * N), N)
+    z = _gauge(S.bdm_bddc_apply(r).cpu().numpy(), N)
+    assert _rel(z, _gauge(B.apply(r), N)) < 1e-11
