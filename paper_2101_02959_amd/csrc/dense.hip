@@ -25,6 +25,27 @@ constexpr int SP_STRIDE = MAXP * MAXP;
 
 namespace {
 
+// 16x16x4 MFMA helpers.  Operand lanes (both precisions): A lane l holds
+// A[l%16][l/16], B lane l holds B[l/16][l%16].  Accumulator register v of
+// lane l holds row 4*(l/16)+v (f32) or row l/16+4v (f64) of column l%16.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+    typedef f32x4 acc;
+    static __device__ inline acc mac(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+template <> struct Mfma<double> {
+    typedef f64x4 acc;
+    static __device__ inline acc mac(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+
 __device__ inline double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
@@ -90,6 +111,59 @@ __global__ void k_assemble(BatchDesc d, FEParams p, const double* __restrict__ k
 }
 
 // ------------------------------------------------------ partial Cholesky
+constexpr int NBO = 128;        // outer panel width
+
+// C[i][j] -= sum_{k in [k0,k1)} A[i][k] A[j][k] for j in [cb, ce), i in [j, re),
+// 32x32 tiles (lower trapezoid), one wave per tile, 2x2 MFMA 16x16x4 blocks.
+template <typename T>
+__device__ void syrk_update(T* __restrict__ A, int64_t ld, int cb, int ce, int re, int k0, int k1) {
+    const int tid = threadIdx.x;
+    const int wv = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+    const int nct = (ce - cb + 31) / 32, nrt = (re - cb + 31) / 32;
+    // tiles (ti >= tj): column tj has nrt - tj tiles
+    const int ntiles = nct * nrt - nct * (nct - 1) / 2;
+    for (int tile = wv; tile < ntiles; tile += kWG / 64) {
+        // locate (tj, ti): columns are laid out one after another
+        int tj = 0, rem = tile;
+        while (rem >= nrt - tj) { rem -= nrt - tj; ++tj; }
+        const int ti = tj + rem;
+        const int I0 = cb + ti * 32, J0 = cb + tj * 32;
+        typename Mfma<T>::acc acc[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[a][b] = (typename Mfma<T>::acc){0, 0, 0, 0};
+        for (int kk = k0; kk < k1; kk += 4) {
+            const int c = kk + lk;
+            const T* col = A + (int64_t)(c < k1 ? c : k0) * ld;
+            T av[2], bv[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int ra = I0 + 16 * q + lr, rb = J0 + 16 * q + lr;
+                av[q] = (c < k1 && ra < re) ? col[ra] : (T)0;
+                bv[q] = (c < k1 && rb < ce) ? col[rb] : (T)0;
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    if (!(ti == tj && a < b)) acc[a][b] = Mfma<T>::mac(av[a], bv[b], acc[a][b]);
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                if (ti == tj && a < b) continue;
+                const int j = J0 + 16 * b + lr;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = I0 + 16 * a + Mfma<T>::row(lane, v);
+                    if (i < re && j < ce && i >= j) A[i + (int64_t)j * ld] -= acc[a][b][v];
+                }
+            }
+    }
+}
+
 // Right-looking blocked Cholesky of columns [c0, c1) of a symmetric matrix
 // (lower triangle), with the trailing update applied to rows/cols < c2.
 // After eliminating the interior block the trailing block holds the Schur
@@ -104,18 +178,18 @@ __global__ __launch_bounds__(kWG) void k_potrf(T* __restrict__ Abase, const int6
     const int64_t ld = ldv[s];
     const int cbeg = c0v[s], cend = c1v[s], c2 = c2v[s];
     const int tid = threadIdx.x;
-    __shared__ T D[NB][NB + 1];
+    const int wv = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+    __shared__ T D[NB][NB + 1];     // diagonal block, then its Cholesky factor
+    __shared__ T W[NB][NB + 1];     // inverse of the factor
     __shared__ int bad;
     if (tid == 0) bad = 0;
+    int p0 = cbeg;                  // start of the current outer panel
     for (int j0 = cbeg; j0 < cend; j0 += NB) {
         const int jb = min(NB, cend - j0);
-        // 1. diagonal block
+        // 1. factor the diagonal block in LDS (identity padding beyond jb)
         for (int idx = tid; idx < NB * NB; idx += kWG) {
             const int i = idx % NB, j = idx / NB;
-            T val = (T)0;
-            if (i < jb && j < jb && j <= i) val = A[(j0 + i) + (j0 + j) * ld];
-            else if (i == j) val = (T)1;
-            D[i][j] = val;
+            D[i][j] = (i < jb && j < jb && j <= i) ? A[(j0 + i) + (j0 + j) * ld] : (T)(i == j);
         }
         __syncthreads();
         for (int k = 0; k < jb; ++k) {
@@ -135,63 +209,57 @@ __global__ __launch_bounds__(kWG) void k_potrf(T* __restrict__ Abase, const int6
             }
             __syncthreads();
         }
+        // W = D^{-1} (lower triangular), one column per thread
+        if (tid < NB) {
+            const int c = tid;
+            for (int i = 0; i < NB; ++i) {
+                T acc = (i == c) ? (T)1 : (T)0;
+                for (int k = c; k < i; ++k) acc -= D[i][k] * W[k][c];
+                W[i][c] = (i >= c) ? acc / D[i][i] : (T)0;
+            }
+        }
         for (int idx = tid; idx < jb * jb; idx += kWG) {
             const int i = idx % jb, j = idx / jb;
             if (j <= i) A[(j0 + i) + (j0 + j) * ld] = D[i][j];
         }
-        // 2. panel below: row r <- row r * L_d^{-T}
+        __syncthreads();
+        // 2. panel below the block: X = P W^T on MFMA, 16-row tiles per wave
         const int t0 = j0 + jb;
-        for (int r = t0 + tid; r < c2; r += kWG) {
-            T x[NB];
+        const int nrt = (c2 - t0 + 15) / 16;
+        for (int tile = wv; tile < nrt; tile += kWG / 64) {
+            const int R0 = t0 + 16 * tile;
+            typename Mfma<T>::acc acc[2];
+            acc[0] = (typename Mfma<T>::acc){0, 0, 0, 0};
+            acc[1] = acc[0];
+            const int r = R0 + lr;
+            for (int kk = 0; kk < NB; kk += 4) {
+                const int k = kk + lk;
+                const T a = (r < c2 && k < jb) ? A[r + (int64_t)(j0 + k) * ld] : (T)0;
 #pragma unroll
-            for (int c = 0; c < NB; ++c) x[c] = (c < jb) ? A[r + (j0 + c) * ld] : (T)0;
-#pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                T acc = x[c];
-#pragma unroll
-                for (int k = 0; k < c; ++k) acc -= x[k] * D[c][k];
-                x[c] = acc / D[c][c];
+                for (int h = 0; h < 2; ++h) {
+                    const int j = 16 * h + lr;
+                    const T b = (k < jb && j < jb) ? W[j][k] : (T)0;
+                    acc[h] = Mfma<T>::mac(a, b, acc[h]);
+                }
             }
 #pragma unroll
-            for (int c = 0; c < NB; ++c)
-                if (c < jb) A[r + (j0 + c) * ld] = x[c];
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = R0 + Mfma<T>::row(lane, v), col = 16 * h + lr;
+                    if (row < c2 && col < jb) A[row + (int64_t)(j0 + col) * ld] = acc[h][v];
+                }
         }
         __syncthreads();
-        // 3. trailing update (lower triangle), 32x32 tiles, one wave per tile
-        const int nt = (c2 - t0 + 31) / 32;
-        const int ntiles = nt * (nt + 1) / 2;
-        const int wv = tid / 64, lane = tid % 64, tx = lane % 8, ty = lane / 8;
-        for (int tile = wv; tile < ntiles; tile += kWG / 64) {
-            int ti = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
-            while (ti * (ti + 1) / 2 > tile) --ti;
-            while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
-            const int tj = tile - ti * (ti + 1) / 2;
-            const int I0 = t0 + ti * 32 + 4 * ty, J0 = t0 + tj * 32 + 4 * tx;
-            T acc[4][4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
-            for (int c = 0; c < jb; ++c) {
-                const T* col = A + (j0 + c) * ld;
-                T av[4], bv[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    av[q] = (I0 + q < c2) ? col[I0 + q] : (T)0;
-                    bv[q] = (J0 + q < c2) ? col[J0 + q] : (T)0;
-                }
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
-            }
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int i = I0 + a, j = J0 + b;
-                    if (i < c2 && j < c2 && i >= j) A[i + (int64_t)j * ld] -= acc[a][b];
-                }
+        // 3. trailing update.  Inner: only the remaining columns of the current
+        //    outer panel; at the end of an outer panel: everything to its right
+        //    with k = the whole outer panel (fewer passes over the matrix).
+        const int pend = min(p0 + NBO, cend);
+        if (t0 < pend) {
+            syrk_update<T>(A, ld, t0, pend, c2, j0, j0 + jb);
+        } else {
+            syrk_update<T>(A, ld, t0, c2, c2, p0, pend);
+            p0 = pend;
         }
         __syncthreads();
     }
@@ -456,12 +524,18 @@ __global__ __launch_bounds__(kWG) void k_trsv_fwd(const T* __restrict__ Lb, cons
                 if (lane == c) xv = xc;
                 else if (lane > c && lane < NB) xv -= D[lane][c] * xc;
             }
-            if (lane < jb) { xs[lane] = xv; x[j0 + lane] = xv; }
+            if (lane < NB) xs[lane] = (lane < jb) ? xv : (T)0;
+            if (lane < jb) x[j0 + lane] = xv;
         }
         __syncthreads();
         for (int r = j0 + jb + tid; r < n; r += kWG) {
+            // branch-free, fully unrolled so all column loads are in flight together
+            T lv[NB];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) lv[c] = L[r + (j0 + min(c, jb - 1)) * ld];
             T acc = (T)0;
-            for (int c = 0; c < jb; ++c) acc += L[r + (j0 + c) * ld] * xs[c];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) acc += (c < jb ? lv[c] : (T)0) * xs[c];
             x[r] -= acc;
         }
         __syncthreads();
@@ -492,9 +566,11 @@ __global__ __launch_bounds__(kWG) void k_trsv_bwd(const T* __restrict__ Lb, cons
         for (int c = 0; c < NB; ++c) acc[c] = (T)0;
         for (int r = j0 + jb + tid; r < n; r += kWG) {
             const T xr = x[r];
+            T lv[NB];
 #pragma unroll
-            for (int c = 0; c < NB; ++c)
-                if (c < jb) acc[c] += L[r + (j0 + c) * ld] * xr;
+            for (int c = 0; c < NB; ++c) lv[c] = L[r + (j0 + min(c, jb - 1)) * ld];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) acc[c] += (c < jb ? lv[c] : (T)0) * xr;
         }
 #pragma unroll
         for (int c = 0; c < NB; ++c) {
