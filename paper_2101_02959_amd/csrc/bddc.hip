@@ -42,79 +42,48 @@ __global__ void k_scatter_I(int n, const int* __restrict__ list, int64_t N, cons
     out[N + g] = (double)x[2 * (int64_t)t + 1];
 }
 
-// In-LDS solve (L L^T) h = h with a dense lower factor (n x n, col-major).
-template <typename T>
-__device__ void chol_solve_lds(const T* __restrict__ L, int n, double* h) {
-    const int tid = threadIdx.x;
-    for (int k = 0; k < n; ++k) {
-        if (tid == 0) h[k] /= (double)L[k + (int64_t)k * n];
-        __syncthreads();
-        const double hk = h[k];
-        for (int i = k + 1 + tid; i < n; i += blockDim.x) h[i] -= (double)L[i + (int64_t)k * n] * hk;
-        __syncthreads();
-    }
-    for (int k = n - 1; k >= 0; --k) {
-        // h[k] = (h[k] - sum_{i>k} L[i][k] h[i]) / L[k][k]
-        double part = 0.0;
-        for (int i = k + 1 + tid; i < n; i += blockDim.x) part += (double)L[i + (int64_t)k * n] * h[i];
-        part = wsum(part);
-        __shared__ double red[kWG / 64];
-        if ((tid & 63) == 0) red[tid >> 6] = part;
-        __syncthreads();
-        if (tid == 0) {
-            double acc = 0.0;
-            for (int q = 0; q < (int)(blockDim.x >> 6); ++q) acc += red[q];
-            h[k] = (h[k] - acc) / (double)L[k + (int64_t)k * n];
-        }
-        __syncthreads();
-    }
-}
-
 // Residual side of the deluxe scaling, E_D^T: for an object shared by
-// subdomains m, g^(m) = S^(m) (sum S)^{-1} g.
+// subdomains m, g^(m) = S^(m) (sum S)^{-1} g = E_m g.
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_deluxe_res(ObjDesc o, int64_t N, const double* __restrict__ g,
-                                                   const T* __restrict__ slots, const T* __restrict__ fac,
-                                                   T* __restrict__ xr, const int64_t* __restrict__ xoff) {
+                                                   const T* __restrict__ dmat, T* __restrict__ xr,
+                                                   const int64_t* __restrict__ xoff) {
     const int ob = blockIdx.x, tid = threadIdx.x;
     const int n = o.n[ob];
     __shared__ double h[MAXO];
     const int* nodes = o.nodes + o.node_off[ob];
     for (int i = tid; i < n; i += kWG) h[i] = g[(i & 1) * N + nodes[i >> 1]];
     __syncthreads();
-    chol_solve_lds(fac + o.fac_off[ob], n, h);
     for (int q = o.sh_ptr[ob]; q < o.sh_ptr[ob + 1]; ++q) {
-        const T* S = slots + o.sh_slot[q];
+        const T* E = dmat + o.sh_slot[q];
         T* dst = xr + xoff[o.sh_sub[q]] + o.sh_roff[q];
         for (int i = tid; i < n; i += kWG) {
             double acc = 0.0;
-            for (int j = 0; j < n; ++j) acc += (double)S[i + (int64_t)j * n] * h[j];
+            for (int j = 0; j < n; ++j) acc += (double)E[i + (int64_t)j * n] * h[j];
             dst[i] = (T)acc;
         }
     }
 }
 
-// Value side of the deluxe scaling, E_D: u = (sum S)^{-1} sum_m S^(m) u^(m).
+// Value side of the deluxe scaling, E_D: u = (sum S)^{-1} sum_m S^(m) u^(m)
+// = sum_m E_m^T u^(m); one wave per output entry (lanes run along E's columns).
 template <typename T>
-__global__ __launch_bounds__(kWG) void k_deluxe_val(ObjDesc o, int64_t N, const T* __restrict__ slots,
-                                                   const T* __restrict__ fac, const T* __restrict__ xr,
-                                                   const int64_t* __restrict__ xoff, double* __restrict__ z) {
-    const int ob = blockIdx.x, tid = threadIdx.x;
+__global__ __launch_bounds__(kWG) void k_deluxe_val(ObjDesc o, int64_t N, const T* __restrict__ dmat,
+                                                   const T* __restrict__ xr, const int64_t* __restrict__ xoff,
+                                                   double* __restrict__ z) {
+    const int ob = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int n = o.n[ob];
-    __shared__ double h[MAXO];
-    for (int i = tid; i < n; i += kWG) {
+    const int* nodes = o.nodes + o.node_off[ob];
+    for (int i = wv; i < n; i += kWG / 64) {
         double acc = 0.0;
         for (int q = o.sh_ptr[ob]; q < o.sh_ptr[ob + 1]; ++q) {
-            const T* S = slots + o.sh_slot[q];
+            const T* E = dmat + o.sh_slot[q] + (int64_t)i * n;
             const T* u = xr + xoff[o.sh_sub[q]] + o.sh_roff[q];
-            for (int j = 0; j < n; ++j) acc += (double)S[i + (int64_t)j * n] * (double)u[j];
+            for (int j = lane; j < n; j += 64) acc += (double)E[j] * (double)u[j];
         }
-        h[i] = acc;
+        acc = wsum(acc);
+        if (lane == 0) z[(i & 1) * N + nodes[i >> 1]] = acc;
     }
-    __syncthreads();
-    chol_solve_lds(fac + o.fac_off[ob], n, h);
-    const int* nodes = o.nodes + o.node_off[ob];
-    for (int i = tid; i < n; i += kWG) z[(i & 1) * N + nodes[i >> 1]] = h[i];
 }
 
 // Per subdomain after the forward Neumann solve x1 = L_rr^{-1} g_r:
@@ -248,68 +217,54 @@ __global__ __launch_bounds__(kWG) void k_feti_B(ObjDesc o, FetiDesc f, const T* 
     }
 }
 
-// B_D^T: subdomain m receives (sum S)^{-1} [ sum_{(m,b)} S^(b) lam_mb - sum_{(a,m)} S^(a) lam_am ].
+// B_D^T: subdomain m receives sum_{(m,b)} D^(b) lam_mb - sum_{(a,m)} D^(a) lam_am,
+// D^(x) = (sum S)^{-1} S^(x) = E_x^T; one wave per output entry.
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_feti_BDT(ObjDesc o, FetiDesc f, const double* __restrict__ lam,
-                                                 const T* __restrict__ slots, const T* __restrict__ fac,
-                                                 T* __restrict__ xr, const int64_t* __restrict__ xoff) {
-    const int ob = blockIdx.x, tid = threadIdx.x;
+                                                 const T* __restrict__ dmat, T* __restrict__ xr,
+                                                 const int64_t* __restrict__ xoff) {
+    const int ob = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int n = o.n[ob];
-    __shared__ double h[MAXO];
     for (int q = o.sh_ptr[ob]; q < o.sh_ptr[ob + 1]; ++q) {
         const int m = o.sh_sub[q];
-        for (int i = tid; i < n; i += kWG) {
+        T* dst = xr + xoff[m] + o.sh_roff[q];
+        for (int i = wv; i < n; i += kWG / 64) {
             double acc = 0.0;
             for (int pq = f.pr_ptr[ob]; pq < f.pr_ptr[ob + 1]; ++pq) {
-                int other, sgn;
-                if (f.pr_a[pq] == m) { other = f.pr_qb[pq]; sgn = 1; }
-                else if (f.pr_b[pq] == m) { other = f.pr_qa[pq]; sgn = -1; }
+                int other;
+                double sgn;
+                if (f.pr_a[pq] == m) { other = f.pr_qb[pq]; sgn = 1.0; }
+                else if (f.pr_b[pq] == m) { other = f.pr_qa[pq]; sgn = -1.0; }
                 else continue;
-                const T* S = slots + o.sh_slot[other];
+                const T* E = dmat + o.sh_slot[other] + (int64_t)i * n;
                 const double* l = lam + f.pr_off[pq];
                 double a = 0.0;
-                for (int j = 0; j < n; ++j) a += (double)S[i + (int64_t)j * n] * l[j];
+                for (int j = lane; j < n; j += 64) a += (double)E[j] * l[j];
                 acc += sgn * a;
             }
-            h[i] = acc;
+            acc = wsum(acc);
+            if (lane == 0) dst[i] = (T)acc;
         }
-        __syncthreads();
-        chol_solve_lds(fac + o.fac_off[ob], n, h);
-        T* dst = xr + xoff[m] + o.sh_roff[q];
-        for (int i = tid; i < n; i += kWG) dst[i] = (T)h[i];
-        __syncthreads();
     }
 }
 
-// B_D: lam_ab = S^(b) (sum S)^{-1} w^(a) - S^(a) (sum S)^{-1} w^(b).
-// The per-share solves y_m = (sum S)^{-1} w^(m) are staged in ybuf.
+// B_D: lam_ab = D^(b)T w^(a) - D^(a)T w^(b) = E_b w^(a) - E_a w^(b).
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_feti_BD(ObjDesc o, FetiDesc f, const T* __restrict__ xr,
-                                                const int64_t* __restrict__ xoff, const T* __restrict__ slots,
-                                                const T* __restrict__ fac, double* __restrict__ ybuf,
+                                                const int64_t* __restrict__ xoff, const T* __restrict__ dmat,
                                                 double* __restrict__ lam) {
     const int ob = blockIdx.x, tid = threadIdx.x;
     const int n = o.n[ob];
-    __shared__ double h[MAXO];
-    for (int q = o.sh_ptr[ob]; q < o.sh_ptr[ob + 1]; ++q) {
-        const T* u = xr + xoff[o.sh_sub[q]] + o.sh_roff[q];
-        for (int i = tid; i < n; i += kWG) h[i] = (double)u[i];
-        __syncthreads();
-        chol_solve_lds(fac + o.fac_off[ob], n, h);
-        double* y = ybuf + f.sh_yoff[q];
-        for (int i = tid; i < n; i += kWG) y[i] = h[i];
-        __syncthreads();
-    }
     for (int pq = f.pr_ptr[ob]; pq < f.pr_ptr[ob + 1]; ++pq) {
         const int qa = f.pr_qa[pq], qb = f.pr_qb[pq];
-        const T* Sa = slots + o.sh_slot[qa];
-        const T* Sb = slots + o.sh_slot[qb];
-        const double* ya = ybuf + f.sh_yoff[qa];
-        const double* yb = ybuf + f.sh_yoff[qb];
+        const T* Ea = dmat + o.sh_slot[qa];
+        const T* Eb = dmat + o.sh_slot[qb];
+        const T* wa = xr + xoff[o.sh_sub[qa]] + o.sh_roff[qa];
+        const T* wb = xr + xoff[o.sh_sub[qb]] + o.sh_roff[qb];
         for (int i = tid; i < n; i += kWG) {
             double acc = 0.0;
             for (int j = 0; j < n; ++j)
-                acc += (double)Sb[i + (int64_t)j * n] * ya[j] - (double)Sa[i + (int64_t)j * n] * yb[j];
+                acc += (double)Eb[i + (int64_t)j * n] * (double)wa[j] - (double)Ea[i + (int64_t)j * n] * (double)wb[j];
             lam[f.pr_off[pq] + i] = acc;
         }
     }
@@ -373,14 +328,14 @@ void launch_scatter_I(hipStream_t s, int n, const int* list, int64_t N, const T*
     hipLaunchKernelGGL(k_scatter_I<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, list, N, x, out);
 }
 template <typename T>
-void launch_deluxe_res(hipStream_t s, const ObjDesc& o, int64_t N, const double* g, const T* slots,
-                       const T* fac, T* xr, const int64_t* xoff) {
-    hipLaunchKernelGGL(k_deluxe_res<T>, dim3(o.nobj), dim3(kWG), 0, s, o, N, g, slots, fac, xr, xoff);
+void launch_deluxe_res(hipStream_t s, const ObjDesc& o, int64_t N, const double* g, const T* dmat, T* xr,
+                       const int64_t* xoff) {
+    hipLaunchKernelGGL(k_deluxe_res<T>, dim3(o.nobj), dim3(kWG), 0, s, o, N, g, dmat, xr, xoff);
 }
 template <typename T>
-void launch_deluxe_val(hipStream_t s, const ObjDesc& o, int64_t N, const T* slots, const T* fac,
-                       const T* xr, const int64_t* xoff, double* z) {
-    hipLaunchKernelGGL(k_deluxe_val<T>, dim3(o.nobj), dim3(kWG), 0, s, o, N, slots, fac, xr, xoff, z);
+void launch_deluxe_val(hipStream_t s, const ObjDesc& o, int64_t N, const T* dmat, const T* xr,
+                       const int64_t* xoff, double* z) {
+    hipLaunchKernelGGL(k_deluxe_val<T>, dim3(o.nobj), dim3(kWG), 0, s, o, N, dmat, xr, xoff, z);
 }
 template <typename T>
 void launch_coarse_rhs_local(hipStream_t s, const SubVecDesc& d, const T* xr, const T* F, const T* Z,
@@ -413,14 +368,14 @@ void launch_feti_B(hipStream_t s, const ObjDesc& o, const FetiDesc& f, const T* 
     hipLaunchKernelGGL(k_feti_B<T>, dim3(o.nobj), dim3(kWG), 0, s, o, f, xr, xoff, lam);
 }
 template <typename T>
-void launch_feti_BDT(hipStream_t s, const ObjDesc& o, const FetiDesc& f, const double* lam, const T* slots,
-                     const T* fac, T* xr, const int64_t* xoff) {
-    hipLaunchKernelGGL(k_feti_BDT<T>, dim3(o.nobj), dim3(kWG), 0, s, o, f, lam, slots, fac, xr, xoff);
+void launch_feti_BDT(hipStream_t s, const ObjDesc& o, const FetiDesc& f, const double* lam, const T* dmat, T* xr,
+                     const int64_t* xoff) {
+    hipLaunchKernelGGL(k_feti_BDT<T>, dim3(o.nobj), dim3(kWG), 0, s, o, f, lam, dmat, xr, xoff);
 }
 template <typename T>
 void launch_feti_BD(hipStream_t s, const ObjDesc& o, const FetiDesc& f, const T* xr, const int64_t* xoff,
-                    const T* slots, const T* fac, double* ybuf, double* lam) {
-    hipLaunchKernelGGL(k_feti_BD<T>, dim3(o.nobj), dim3(kWG), 0, s, o, f, xr, xoff, slots, fac, ybuf, lam);
+                    const T* dmat, double* lam) {
+    hipLaunchKernelGGL(k_feti_BD<T>, dim3(o.nobj), dim3(kWG), 0, s, o, f, xr, xoff, dmat, lam);
 }
 template <typename T>
 void launch_schur_mv(hipStream_t s, const SubVecDesc& d, const T* Srr, const int64_t* Soff, const T* x, T* y) {
@@ -438,9 +393,9 @@ void launch_take_first(hipStream_t s, const ObjDesc& o, int64_t N, const T* xr, 
 #define BDM_INST(T)                                                                                         \
     template void launch_gather_I<T>(hipStream_t, int, const int*, int64_t, const double*, const double*, T*); \
     template void launch_scatter_I<T>(hipStream_t, int, const int*, int64_t, const T*, double*);            \
-    template void launch_deluxe_res<T>(hipStream_t, const ObjDesc&, int64_t, const double*, const T*,       \
-                                       const T*, T*, const int64_t*);                                       \
-    template void launch_deluxe_val<T>(hipStream_t, const ObjDesc&, int64_t, const T*, const T*, const T*,  \
+    template void launch_deluxe_res<T>(hipStream_t, const ObjDesc&, int64_t, const double*, const T*, T*,   \
+                                       const int64_t*);                                                     \
+    template void launch_deluxe_val<T>(hipStream_t, const ObjDesc&, int64_t, const T*, const T*,            \
                                        const int64_t*, double*);                                            \
     template void launch_coarse_rhs_local<T>(hipStream_t, const SubVecDesc&, const T*, const T*, const T*,  \
                                              const T*, double*, double*);                                   \
@@ -451,9 +406,9 @@ void launch_take_first(hipStream_t s, const ObjDesc& o, int64_t N, const T* xr, 
     template void launch_feti_B<T>(hipStream_t, const ObjDesc&, const FetiDesc&, const T*, const int64_t*,  \
                                    double*);                                                                \
     template void launch_feti_BDT<T>(hipStream_t, const ObjDesc&, const FetiDesc&, const double*, const T*, \
-                                     const T*, T*, const int64_t*);                                         \
+                                     T*, const int64_t*);                                                   \
     template void launch_feti_BD<T>(hipStream_t, const ObjDesc&, const FetiDesc&, const T*, const int64_t*, \
-                                    const T*, const T*, double*, double*);                                  \
+                                    const T*, double*);                                                     \
     template void launch_schur_mv<T>(hipStream_t, const SubVecDesc&, const T*, const int64_t*, const T*, T*); \
     template void launch_split_res<T>(hipStream_t, const ObjDesc&, int64_t, const double*, T*, const int64_t*); \
     template void launch_take_first<T>(hipStream_t, const ObjDesc&, int64_t, const T*, const int64_t*, double*);

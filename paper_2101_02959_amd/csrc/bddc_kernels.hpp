@@ -48,11 +48,11 @@ void launch_gather_I(hipStream_t s, int n, const int* list, int64_t N, const dou
 template <typename T>
 void launch_scatter_I(hipStream_t s, int n, const int* list, int64_t N, const T* x, double* out);
 template <typename T>
-void launch_deluxe_res(hipStream_t s, const ObjDesc& o, int64_t N, const double* g, const T* slots,
-                       const T* fac, T* xr, const int64_t* xoff);
+void launch_deluxe_res(hipStream_t s, const ObjDesc& o, int64_t N, const double* g, const T* dmat, T* xr,
+                       const int64_t* xoff);
 template <typename T>
-void launch_deluxe_val(hipStream_t s, const ObjDesc& o, int64_t N, const T* slots, const T* fac,
-                       const T* xr, const int64_t* xoff, double* z);
+void launch_deluxe_val(hipStream_t s, const ObjDesc& o, int64_t N, const T* dmat, const T* xr,
+                       const int64_t* xoff, double* z);
 template <typename T>
 void launch_coarse_rhs_local(hipStream_t s, const SubVecDesc& d, const T* xr, const T* F, const T* Z,
                              const T* Gi, double* cP, double* mu);
@@ -70,11 +70,11 @@ template <typename T>
 void launch_feti_B(hipStream_t s, const ObjDesc& o, const FetiDesc& f, const T* xr, const int64_t* xoff,
                    double* lam);
 template <typename T>
-void launch_feti_BDT(hipStream_t s, const ObjDesc& o, const FetiDesc& f, const double* lam, const T* slots,
-                     const T* fac, T* xr, const int64_t* xoff);
+void launch_feti_BDT(hipStream_t s, const ObjDesc& o, const FetiDesc& f, const double* lam, const T* dmat, T* xr,
+                     const int64_t* xoff);
 template <typename T>
 void launch_feti_BD(hipStream_t s, const ObjDesc& o, const FetiDesc& f, const T* xr, const int64_t* xoff,
-                    const T* slots, const T* fac, double* ybuf, double* lam);
+                    const T* dmat, double* lam);
 template <typename T>
 void launch_schur_mv(hipStream_t s, const SubVecDesc& d, const T* Srr, const int64_t* Soff, const T* x, T* y);
 template <typename T>

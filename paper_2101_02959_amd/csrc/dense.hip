@@ -595,15 +595,20 @@ __global__ __launch_bounds__(kWG) void k_trsv_bwd(const T* __restrict__ Lb, cons
     }
 }
 
-// --------------------------------------------------------- deluxe factors
-// Per face: S_F^j + S_F^k; per edge: sum_m S_E^(m) (Sec. 4.2); then an
-// unblocked Cholesky (objects hold at most a few hundred dofs).
+// --------------------------------------------------------- deluxe operators
+// Per face: S_F^j + S_F^k; per edge: sum_m S_E^(m) (Sec. 4.2).  The sum is
+// factored and inverted (Cholesky, triangular inverse, W^T W), and for every
+// sharing subdomain m the operator E_m = S^(m) (sum S)^{-1} is formed:
+// E_m g is the residual-side split and E_m^T u the value-side average term,
+// so the per-iteration deluxe scaling is a set of dense GEMVs.
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_deluxe_setup(ObjDesc o, const T* __restrict__ slots,
-                                                     T* __restrict__ fac, int* __restrict__ info) {
+                                                     T* __restrict__ fac, T* __restrict__ inv,
+                                                     T* __restrict__ dmat, int* __restrict__ info) {
     const int ob = blockIdx.x;
     const int n = o.n[ob];
     T* A = fac + o.fac_off[ob];
+    T* W = inv + o.fac_off[ob];
     const int tid = threadIdx.x;
     for (int idx = tid; idx < n * n; idx += kWG) {
         T acc = (T)0;
@@ -629,6 +634,36 @@ __global__ __launch_bounds__(kWG) void k_deluxe_setup(ObjDesc o, const T* __rest
             if (j <= i) A[i + j * n] -= A[i + k * n] * A[j + k * n];
         }
         __syncthreads();
+    }
+    // W = L^{-1}, one column per thread (forward substitution)
+    for (int c = tid; c < n; c += kWG) {
+        for (int i = 0; i < n; ++i) {
+            T acc = (i == c) ? (T)1 : (T)0;
+            if (i > c)
+                for (int k = c; k < i; ++k) acc -= A[i + k * n] * W[k + c * n];
+            W[i + c * n] = (i >= c) ? acc / A[i + i * n] : (T)0;
+        }
+    }
+    __syncthreads();
+    // (sum S)^{-1} = W^T W, written over the factor
+    for (int idx = tid; idx < n * n; idx += kWG) {
+        const int i = idx % n, j = idx / n;
+        const int k0 = i > j ? i : j;
+        T acc = (T)0;
+        for (int k = k0; k < n; ++k) acc += W[k + i * n] * W[k + j * n];
+        A[idx] = acc;
+    }
+    __syncthreads();
+    // E_m = S^(m) (sum S)^{-1}
+    for (int q = o.sh_ptr[ob]; q < o.sh_ptr[ob + 1]; ++q) {
+        const T* S = slots + o.sh_slot[q];
+        T* E = dmat + o.sh_slot[q];
+        for (int idx = tid; idx < n * n; idx += kWG) {
+            const int i = idx % n, j = idx / n;
+            T acc = (T)0;
+            for (int k = 0; k < n; ++k) acc += S[i + k * n] * A[k + j * n];
+            E[idx] = acc;
+        }
     }
     if (tid == 0 && bad) info[ob] = 1;
 }
@@ -674,8 +709,8 @@ void launch_trsv(hipStream_t s, int nb, bool trans, const T* L, const int64_t* L
         hipLaunchKernelGGL(k_trsv_fwd<T>, dim3(nb), dim3(kWG), 0, s, L, Loff, n, ld, x, xoff);
 }
 template <typename T>
-void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, const T* slots, T* fac, int* info) {
-    hipLaunchKernelGGL(k_deluxe_setup<T>, dim3(o.nobj), dim3(kWG), 0, s, o, slots, fac, info);
+void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, const T* slots, T* fac, T* inv, T* dmat, int* info) {
+    hipLaunchKernelGGL(k_deluxe_setup<T>, dim3(o.nobj), dim3(kWG), 0, s, o, slots, fac, inv, dmat, info);
 }
 
 #define BDM_INST(T)                                                                                     \
@@ -692,7 +727,7 @@ void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, const T* slots, T* fac
                                          double*, int*);                                                 \
     template void launch_trsv<T>(hipStream_t, int, bool, const T*, const int64_t*, const int*,          \
                                  const int*, T*, const int64_t*);                                        \
-    template void launch_deluxe_setup<T>(hipStream_t, const ObjDesc&, const T*, T*, int*);
+    template void launch_deluxe_setup<T>(hipStream_t, const ObjDesc&, const T*, T*, T*, T*, int*);
 BDM_INST(double)
 BDM_INST(float)
 #undef BDM_INST

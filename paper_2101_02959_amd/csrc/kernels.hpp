@@ -87,6 +87,6 @@ struct ObjDesc {
     const int64_t* sh_slot;// that subdomain's block S^(m) (n x n)
 };
 template <typename T>
-void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, const T* slots, T* fac, int* info);
+void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, const T* slots, T* fac, T* inv, T* dmat, int* info);
 
 }  // namespace bdm

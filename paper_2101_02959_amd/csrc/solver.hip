@@ -418,6 +418,8 @@ int Context::alloc_local() {
     Z_ = dalloc(nZ_ * sizeof(T));
     Gi_ = dalloc((size_t)nsub * GI_STRIDE * sizeof(T));
     fac_ = dalloc(nfac_ * sizeof(T));
+    inv_ = dalloc(nfac_ * sizeof(T));
+    dmat_ = dalloc(nslot_ * sizeof(T));
     Srr_ = feti ? dalloc(nSrr_ * sizeof(T)) : nullptr;
     xI_ = dalloc(nxI_ * sizeof(T));
     xr_ = dalloc(nxr_ * sizeof(T));
@@ -450,7 +452,7 @@ int Context::alloc_local() {
     info_sub_ = (int*)dalloc(nsub * sizeof(int));
     info_obj_ = (int*)dalloc((size_t)od_.nobj * sizeof(int));
     info_c_ = (int*)dalloc(sizeof(int));
-    if (!K_ || !LIIs_ || !Lrrs_ || !slots_ || !F_ || !Z_ || !Gi_ || !fac_ || (feti && !Srr_) || !xI_ || !xr_ ||
+    if (!K_ || !LIIs_ || !Lrrs_ || !slots_ || !inv_ || !dmat_ || !F_ || !Z_ || !Gi_ || !fac_ || (feti && !Srr_) || !xI_ || !xr_ ||
         !xr2_ || !Svv_ || !Sp_ || !cP_ || !mu_ || !cb_ || !ybuf_ || !info_sub_ || !info_obj_ || !info_c_) {
         set_error("device allocation failed (local factors)");
         return BDM_E_OOM;
@@ -554,7 +556,7 @@ int Context::linearize_t() {
     }
     launch_trsm_fwd<T>(stream_, nsub, (const T*)Lrrs_, Lrr_off_, nr_, nr_, (T*)F_, bd_.F_off, nr_, kF_);
     launch_coarse_local<T>(stream_, bd_, (const T*)F_, Svv_, (T*)Z_, (T*)Gi_, Sp_, info_sub_);
-    launch_deluxe_setup<T>(stream_, od_, (const T*)slots_, (T*)fac_, info_obj_);
+    launch_deluxe_setup<T>(stream_, od_, (const T*)slots_, (T*)fac_, (T*)inv_, (T*)dmat_, info_obj_);
     coarse_.factor(stream_, color_list_, color_ptr_, nP_, sv_.P_off, sv_.primal, Sp_, SP_STRIDE);
     int hb = 0, hc = 0;
     std::vector<int> hs(nsub), ho(od_.nobj);
@@ -639,10 +641,10 @@ int Context::bddc_apply(const double* r, double* z) {
 template <typename T>
 int Context::bddc_apply_t(const double* r, double* z) {
     condense<T>(r, t2_);
-    launch_deluxe_res<T>(stream_, od_, N, t2_, (const T*)slots_, (const T*)fac_, (T*)xr_, xr_off_);
+    launch_deluxe_res<T>(stream_, od_, N, t2_, (const T*)dmat_, (T*)xr_, xr_off_);
     stilde_inv<T>((T*)xr_, t2_, cb_);
     HIPOK(hipMemsetAsync(t3_, 0, 2 * N * sizeof(double), stream_));
-    launch_deluxe_val<T>(stream_, od_, N, (const T*)slots_, (const T*)fac_, (const T*)xr_, xr_off_, t3_);
+    launch_deluxe_val<T>(stream_, od_, N, (const T*)dmat_, (const T*)xr_, xr_off_, t3_);
     launch_vertex_val(stream_, cd_.nverts, cd_.vnode, N, cb_, t3_);
     interior_extend<T>(r, t3_);
     HIPOK(hipMemcpyAsync(z, t3_, 2 * N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
@@ -674,9 +676,9 @@ int Context::fetidp_apply_t(int op, const double* in, double* out) {
             launch_feti_B<T>(stream_, od_, fd_, xr, xr_off_, out);
             return 0;
         case BDM_FETI_PRECOND:
-            launch_feti_BDT<T>(stream_, od_, fd_, in, (const T*)slots_, (const T*)fac_, xr, xr_off_);
+            launch_feti_BDT<T>(stream_, od_, fd_, in, (const T*)dmat_, xr, xr_off_);
             launch_schur_mv<T>(stream_, sv_, (const T*)Srr_, Srr_off_, xr, xr2);
-            launch_feti_BD<T>(stream_, od_, fd_, xr2, xr_off_, (const T*)slots_, (const T*)fac_, ybuf_, out);
+            launch_feti_BD<T>(stream_, od_, fd_, xr2, xr_off_, (const T*)dmat_, out);
             return 0;
         case BDM_FETI_RHS:
             condense<T>(in, t2_);

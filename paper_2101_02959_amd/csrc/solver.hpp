@@ -84,6 +84,7 @@ class Context {
     double *Svv_ = nullptr, *Sp_ = nullptr, *cP_ = nullptr, *mu_ = nullptr;
     double *cb_ = nullptr, *ybuf_ = nullptr;
     void *LIIs_ = nullptr, *Lrrs_ = nullptr;   // compact Dirichlet / Neumann factors
+    void *inv_ = nullptr, *dmat_ = nullptr;    // deluxe (sum S)^{-1} and E_m = S^(m) (sum S)^{-1}
     CoarseSolver coarse_;
     std::vector<std::pair<int, int>> chunks_;  // subdomain ranges of the chunked setup
     const int64_t* Kc_off_ = nullptr;           // chunk-relative offsets of the local matrices
