@@ -6,10 +6,15 @@ one MI355X.
 
 Prints one JSON line.  A step is one full decoupled Backward-Euler step
 (ionic update + Newton with BDDC-deluxe PCG to the configured tolerances) on
-a synthetic slab whose state is resident in HBM.  The roofline entry is for
-the Jacobian apply kernel, timed with HIP events on the library's stream over
-repeated launches; the CPU baseline is the FP64 oracle timed on a bounded
-sample (one Newton linear solve on the 32^3 slab) and scaled per dof.
+a synthetic slab whose state is resident in HBM.  The CPU baseline is the
+FP64 oracle timed on a bounded sample (one Newton linear solve on the 32^3
+slab) and scaled per dof.
+
+Roofline: the dominant kernel of a step is the batched partial Cholesky of
+the local matrices (interior elimination), which runs on MFMA; it is timed
+with HIP events on the library stream through bdm_profile_kernel, with its
+algorithmic flop count.  The Jacobian apply and the Dirichlet triangular
+solve (HBM-bound) are reported beside it.
 """
 from __future__ import annotations
 
@@ -26,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "s/time-step & PCG iters/Newton at 17M dofs: FP32+learned vs plain FP64"
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFS = {"f32": 157.3, "f64": 78.6}
 
 
 def log(msg):
@@ -64,30 +70,28 @@ def run_path(P, wl, precision, guess, warmup, steps):
     return S, out, state
 
 
-def jacobian_roofline(S, wl, reps=50):
-    """Average duration of the Jacobian apply kernel (HIP events on the
-    library stream) and its algorithmic traffic: read v, u_e and the reaction
-    diagonal, write both outputs = 40 bytes per node."""
-    import torch
-    N = wl.mesh.nnodes
-    x = torch.randn(2 * N, dtype=torch.float64, device="cuda")
-    S.bdm_linearize(torch.zeros(N, dtype=torch.float64, device="cuda"),
-                    torch.zeros(N, dtype=torch.float64, device="cuda"))
-    for _ in range(3):
-        S.bdm_jacobian_apply(x)
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        S.bdm_jacobian_apply(x)
-    e1.record(stream)
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    traffic = 40.0 * N
-    gbs = traffic / (ms * 1e-3) / 1e9
-    return {"bound": "hbm", "kernel": "k_jac_apply", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-            "avg_us_incl_launch_sync": round(ms * 1e3, 2), "algorithmic_bytes_per_launch": traffic}
+def kernel_rooflines(P, S, prec_name, reps=5):
+    """Live HIP-event timings of the hot kernels at the current linearisation."""
+    out = {}
+    ms, flops = S.bdm_profile_kernel(P.BDM_KERNEL_POTRF_INTERIOR, reps)
+    tf = flops / (ms * 1e-3) / 1e12
+    peak = MFMA_PEAK_TFS[prec_name]
+    out["potrf"] = {"bound": "mfma", "kernel": f"k_potrf_interior<{'float' if prec_name == 'f32' else 'double'}> "
+                    "(first setup chunk)", "achieved": round(tf, 2), "peak": peak,
+                    "unit": "TFLOP/s", "frac": round(tf / peak, 4), "traffic": None,
+                    "avg_ms": round(ms, 3), "algorithmic_flops_per_launch": flops}
+    ms, nbytes = S.bdm_profile_kernel(P.BDM_KERNEL_TRSV_DIRICHLET, 20)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    out["trsv"] = {"bound": "hbm", "kernel": "k_trsv_fwd (Dirichlet, all subdomains)",
+                   "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "avg_ms": round(ms, 4),
+                   "algorithmic_bytes_per_launch": nbytes}
+    ms, nbytes = S.bdm_profile_kernel(P.BDM_KERNEL_JACOBIAN, 50)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    out["jacobian"] = {"bound": "hbm", "kernel": "k_jac_apply", "achieved": round(gbs, 1),
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                       "traffic": None, "avg_ms": round(ms, 4), "algorithmic_bytes_per_launch": nbytes}
+    return out
 
 
 def cpu_baseline(target_dofs, newton_per_step):
@@ -117,9 +121,9 @@ def cpu_baseline(target_dofs, newton_per_step):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="slab32")
+    ap.add_argument("--workload", default="slab256")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -133,10 +137,14 @@ def main():
     log(f"workload {args.workload}: {dofs} dofs, {wl.mesh.nsub} subdomains")
     log("plain FP64 path")
     S64, plain, st64 = run_path(P, wl, P.BDM_PREC_FP64, P.BDM_GUESS_PREV, args.warmup, args.steps)
-    roof = jacobian_roofline(S64, wl)
+    roof64 = kernel_rooflines(P, S64, "f64")
+    st64 = tuple(t.cpu() if hasattr(t, "cpu") else t for t in st64)
     S64.close()
+    torch.cuda.synchronize()
     log("mixed FP32-local path, extrapolated Newton guess")
     S32, mixed, st32 = run_path(P, wl, P.BDM_PREC_MIXED, P.BDM_GUESS_EXTRAP, args.warmup, args.steps)
+    roof32 = kernel_rooflines(P, S32, "f32")
+    st32 = tuple(t.cpu() if hasattr(t, "cpu") else t for t in st32)
     S32.close()
     rel = {k: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
            for k, a, b in (("v", st32[0], st64[0]), ("u_e", st32[1], st64[1]))}
@@ -152,7 +160,9 @@ def main():
         "mixed": mixed, "plain_fp64": plain,
         "speedup_vs_plain_fp64": round(plain["s_per_step"] / mixed["s_per_step"], 3),
         "mixed_vs_fp64_rel_diff": rel,
-        "roofline": roof,
+        "roofline": roof32["potrf"],
+        "roofline_other": {"mixed": {"trsv": roof32["trsv"], "jacobian": roof32["jacobian"]},
+                           "fp64": roof64},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(dofs, plain["newton_per_step"])

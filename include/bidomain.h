@@ -174,6 +174,25 @@ int bdm_fetidp_apply(bdm_ctx* ctx, int op, const double* in, double* out);
  * the multipliers plus recovery, per opts.solver.  stats may be NULL. */
 int bdm_step(bdm_ctx* ctx, int nsteps, bdm_step_stats* stats);
 
+/* Kernel timing for roofline reports.  At the last linearisation, launches
+ * one hot kernel reps times on the context stream, each bracketed by HIP
+ * events, and returns the mean launch duration in avg_ms and the kernel's
+ * algorithmic work per launch in work (bytes for the bandwidth-bound
+ * kernels, floating-point operations for the factorisation):
+ *   BDM_KERNEL_JACOBIAN       y = J x on 2N vectors; bytes = 40 N (read v, u_e,
+ *                             reaction diagonal; write both outputs)
+ *   BDM_KERNEL_TRSV_DIRICHLET one forward Dirichlet solve L_II y = b over all
+ *                             subdomains; bytes = lower triangles + vectors
+ *   BDM_KERNEL_POTRF_INTERIOR interior elimination (partial Cholesky of the
+ *                             local matrices through the interior columns) of
+ *                             the first setup chunk; flops = sum over those
+ *                             subdomains and eliminated columns j of
+ *                             (n-j-1) + (n-j-1)(n-j)
+ * The local matrices of the first chunk are reassembled before each timed
+ * launch (untimed); the preconditioner factors are left intact. */
+enum { BDM_KERNEL_JACOBIAN = 0, BDM_KERNEL_TRSV_DIRICHLET = 1, BDM_KERNEL_POTRF_INTERIOR = 2 };
+int bdm_profile_kernel(bdm_ctx* ctx, int kernel, int reps, double* avg_ms, double* work);
+
 /* Sizes for callers that allocate vectors: N, number of subdomains, global
  * primal (coarse) dimension. */
 int bdm_sizes(bdm_ctx* ctx, long* n_nodes, long* n_sub, long* n_primal);

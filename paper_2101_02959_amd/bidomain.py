@@ -19,6 +19,7 @@ BDM_SOLVER_BDDC, BDM_SOLVER_FETIDP = 0, 1
 BDM_PREC_FP64, BDM_PREC_MIXED = 0, 1
 BDM_GUESS_PREV, BDM_GUESS_EXTRAP = 0, 1
 BDM_FETI_F, BDM_FETI_PRECOND, BDM_FETI_RHS, BDM_FETI_RECOVER = 0, 1, 2, 3
+BDM_KERNEL_JACOBIAN, BDM_KERNEL_TRSV_DIRICHLET, BDM_KERNEL_POTRF_INTERIOR = 0, 1, 2
 
 ERRORS = {
     -1: "BDM_E_ARG", -2: "BDM_E_OOM", -3: "BDM_E_HIP", -4: "BDM_E_NOT_SPD",
@@ -29,7 +30,7 @@ ERRORS = {
 EXPORTS = ("bdm_create", "bdm_destroy", "bdm_set_state", "bdm_get_state", "bdm_set_stimulus",
            "bdm_ionic_update", "bdm_residual", "bdm_linearize", "bdm_jacobian_apply",
            "bdm_bddc_apply", "bdm_fetidp_size", "bdm_fetidp_apply", "bdm_step", "bdm_sizes",
-           "bdm_last_error")
+           "bdm_profile_kernel", "bdm_last_error")
 
 
 class BidomainError(RuntimeError):
@@ -93,6 +94,7 @@ def lib():
         "bdm_fetidp_apply": ([vp, ci, vp, vp], ci),
         "bdm_step": ([vp, ci, C.POINTER(bdm_step_stats)], ci),
         "bdm_sizes": ([vp, C.POINTER(C.c_long), C.POINTER(C.c_long), C.POINTER(C.c_long)], ci),
+        "bdm_profile_kernel": ([vp, ci, ci, C.POINTER(cd), C.POINTER(cd)], ci),
         "bdm_last_error": ([], C.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -222,6 +224,11 @@ class Solver:
         out = self.vec(2 * self.N if op == BDM_FETI_RECOVER else nl)
         _check(lib().bdm_fetidp_apply(self.h, op, _ptr(x), _ptr(out)))
         return out
+
+    def bdm_profile_kernel(self, kernel, reps=10):
+        ms, work = C.c_double(), C.c_double()
+        _check(lib().bdm_profile_kernel(self.h, kernel, reps, C.byref(ms), C.byref(work)))
+        return ms.value, work.value
 
     def bdm_step(self, nsteps=1):
         st = bdm_step_stats()

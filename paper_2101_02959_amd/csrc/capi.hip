@@ -124,6 +124,11 @@ int bdm_step(bdm_ctx* ctx, int nsteps, bdm_step_stats* stats) {
     GUARD(ctx->c.step(nsteps, stats));
 }
 
+int bdm_profile_kernel(bdm_ctx* ctx, int kernel, int reps, double* avg_ms, double* work) {
+    NEED(ctx); NEED(avg_ms); NEED(work);
+    GUARD(ctx->c.profile_kernel(kernel, reps, avg_ms, work));
+}
+
 int bdm_sizes(bdm_ctx* ctx, long* n_nodes, long* n_sub, long* n_primal) {
     NEED(ctx);
     if (n_nodes) *n_nodes = (long)ctx->c.N;

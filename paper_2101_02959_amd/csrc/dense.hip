@@ -169,10 +169,10 @@ __device__ void syrk_update(T* __restrict__ A, int64_t ld, int cb, int ce, int r
 // After eliminating the interior block the trailing block holds the Schur
 // complement K_GG - K_GI K_II^{-1} K_IG (Sec. 4.1).
 template <typename T>
-__global__ __launch_bounds__(kWG) void k_potrf(T* __restrict__ Abase, const int64_t* __restrict__ off,
-                                              const int* __restrict__ ldv, const int* __restrict__ c0v,
-                                              const int* __restrict__ c1v, const int* __restrict__ c2v,
-                                              int* __restrict__ info) {
+__device__ __forceinline__ void potrf_body(T* __restrict__ Abase, const int64_t* __restrict__ off,
+                                           const int* __restrict__ ldv, const int* __restrict__ c0v,
+                                           const int* __restrict__ c1v, const int* __restrict__ c2v,
+                                           int* __restrict__ info) {
     const int s = blockIdx.x;
     T* A = Abase + off[s];
     const int64_t ld = ldv[s];
@@ -264,6 +264,23 @@ __global__ __launch_bounds__(kWG) void k_potrf(T* __restrict__ Abase, const int6
         __syncthreads();
     }
     if (tid == 0 && bad) info[s] = 1;
+}
+
+// Two entry points with distinct names so profiles separate the interior
+// elimination (Dirichlet factor + Schur complement) from the other factors.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_potrf_interior(T* __restrict__ A, const int64_t* __restrict__ off,
+                                                       const int* __restrict__ ld, const int* __restrict__ c0,
+                                                       const int* __restrict__ c1, const int* __restrict__ c2,
+                                                       int* __restrict__ info) {
+    potrf_body<T>(A, off, ld, c0, c1, c2, info);
+}
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_potrf(T* __restrict__ A, const int64_t* __restrict__ off,
+                                              const int* __restrict__ ld, const int* __restrict__ c0,
+                                              const int* __restrict__ c1, const int* __restrict__ c2,
+                                              int* __restrict__ info) {
+    potrf_body<T>(A, off, ld, c0, c1, c2, info);
 }
 
 // ------------------------------------------------------------- extraction
@@ -678,8 +695,11 @@ void launch_assemble(hipStream_t s, const BatchDesc& d, int maxbox, const FEPara
 }
 template <typename T>
 void launch_potrf(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* c0,
-                  const int* c1, const int* c2, int* info) {
-    hipLaunchKernelGGL(k_potrf<T>, dim3(nb), dim3(kWG), 0, s, A, off, ld, c0, c1, c2, info);
+                  const int* c1, const int* c2, int* info, bool interior) {
+    if (interior)
+        hipLaunchKernelGGL(k_potrf_interior<T>, dim3(nb), dim3(kWG), 0, s, A, off, ld, c0, c1, c2, info);
+    else
+        hipLaunchKernelGGL(k_potrf<T>, dim3(nb), dim3(kWG), 0, s, A, off, ld, c0, c1, c2, info);
 }
 template <typename T>
 void launch_extract(hipStream_t s, const BatchDesc& d, const T* K, T* slots, T* F, double* Svv, T* Srr) {
@@ -717,7 +737,7 @@ void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, const T* slots, T* fac
     template void launch_assemble<T>(hipStream_t, const BatchDesc&, int, const FEParams&, const double*, \
                                      const double*, const double*, T*);                                \
     template void launch_potrf<T>(hipStream_t, int, T*, const int64_t*, const int*, const int*,         \
-                                  const int*, const int*, int*);                                         \
+                                  const int*, const int*, int*, bool);                                   \
     template void launch_extract<T>(hipStream_t, const BatchDesc&, const T*, T*, T*, double*, T*);      \
     template void launch_copy_out<T>(hipStream_t, const BatchDesc&, int, const T*, T*, const int64_t*, T*,    \
                                      const int64_t*);                                                    \

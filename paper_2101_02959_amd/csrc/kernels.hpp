@@ -57,7 +57,7 @@ void launch_assemble(hipStream_t s, const BatchDesc& d, int maxbox, const FEPara
                      const double* ke, const double* v, const double* w, T* K);
 template <typename T>
 void launch_potrf(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* c0,
-                  const int* c1, const int* c2, int* info);
+                  const int* c1, const int* c2, int* info, bool interior = false);
 template <typename T>
 void launch_extract(hipStream_t s, const BatchDesc& d, const T* K, T* slots, T* F, double* Svv,
                     T* Srr);

@@ -190,21 +190,37 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
         if (const char* e = std::getenv("BDM_SETUP_WORKSPACE_GB")) gb = std::atof(e);
         const int64_t budget = std::max<int64_t>((int64_t)(gb * 1e9) / (int64_t)tsize_, 1);
         std::vector<int64_t> kc(nsub);
-        chunks_.clear();
-        int start = 0;
-        int64_t acc = 0;
+        int64_t total = 0, maxsz = 0;
         for (int q = 0; q < nsub; ++q) {
-            const int64_t sz = (int64_t)n[q] * n[q];
-            if (q > start && acc + sz > budget) {
-                chunks_.push_back({start, q});
-                start = q;
-                acc = 0;
+            total += (int64_t)n[q] * n[q];
+            maxsz = std::max<int64_t>(maxsz, (int64_t)n[q] * n[q]);
+        }
+        // equal subdomain counts per chunk, as many chunks as the budget needs
+        int nch = (int)std::max<int64_t>(1, (total + budget - 1) / budget);
+        for (;;) {
+            const int per = (nsub + nch - 1) / nch;
+            int64_t worst = 0;
+            for (int c0 = 0; c0 < nsub; c0 += per) {
+                int64_t acc = 0;
+                for (int q = c0; q < std::min(nsub, c0 + per); ++q) acc += (int64_t)n[q] * n[q];
+                worst = std::max(worst, acc);
             }
-            kc[q] = acc;
-            acc += sz;
+            if (worst <= budget || per == 1) break;
+            ++nch;
+        }
+        const int per = (nsub + nch - 1) / nch;
+        chunks_.clear();
+        for (int c0 = 0; c0 < nsub; c0 += per) {
+            const int c1 = std::min(nsub, c0 + per);
+            chunks_.push_back({c0, c1});
+            int64_t acc = 0;
+            for (int q = c0; q < c1; ++q) {
+                kc[q] = acc;
+                acc += (int64_t)n[q] * n[q];
+            }
             nKwork_ = std::max(nKwork_, acc);
         }
-        chunks_.push_back({start, nsub});
+        (void)maxsz;
         Kc_off_ = upload(kc);
     }
     nInodes_ = (int)Ilist.size();
@@ -547,7 +563,7 @@ int Context::linearize_t() {
         launch_assemble<T>(stream_, cd, maxbox_, fp, ke_, vlin_, wlin_, K);
         // interior elimination: L_II, and S_Gamma in the trailing block
         launch_potrf<T>(stream_, cnt, K, Kc_off_ + s0, ld_ + s0, st1c0_ + s0, st1c1_ + s0, st1c2_ + s0,
-                        info_sub_ + s0);
+                        info_sub_ + s0, true);
         launch_extract<T>(stream_, cd, K, (T*)slots_, (T*)F_, Svv_, (T*)Srr_);
         // constrained Neumann factor L_rr of S_rr
         launch_potrf<T>(stream_, cnt, K, Kc_off_ + s0, ld_ + s0, st1c1_ + s0, st2c1_ + s0, st2c1_ + s0,
@@ -775,6 +791,65 @@ int Context::newton_solve(const double* b, double* s, KrylovOut& out) {
     HIPOK(hipMemcpyAsync(kq_ + 2 * N, kx_, nlam_ * sizeof(double), hipMemcpyDeviceToDevice, stream_));
     rc = prec_ ? fetidp_apply_t<float>(BDM_FETI_RECOVER, kq_, s) : fetidp_apply_t<double>(BDM_FETI_RECOVER, kq_, s);
     return rc;
+}
+
+int Context::profile_kernel(int kernel, int reps, double* avg_ms, double* work) {
+    if (!linearized_) {
+        set_error("bdm_profile_kernel before bdm_linearize");
+        return BDM_E_STATE;
+    }
+    if (reps < 1 || kernel < 0 || kernel > 2) {
+        set_error("bdm_profile_kernel: bad kernel id or reps");
+        return BDM_E_ARG;
+    }
+    return prec_ ? profile_t<float>(kernel, reps, avg_ms, work) : profile_t<double>(kernel, reps, avg_ms, work);
+}
+
+template <typename T>
+int Context::profile_t(int kernel, int reps, double* avg_ms, double* work) {
+    hipEvent_t e0, e1;
+    HIPOK(hipEventCreate(&e0));
+    HIPOK(hipEventCreate(&e1));
+    double total = 0.0, w = 0.0;
+    const int nsub = (int)topo.subs.size();
+    const int s0 = chunks_[0].first, cnt = chunks_[0].second - chunks_[0].first;
+    BatchDesc cd = bd_;
+    cd.nsub = cnt;
+    cd.sub0 = s0;
+    if (kernel == BDM_KERNEL_JACOBIAN) {
+        w = 40.0 * (double)N;
+    } else if (kernel == BDM_KERNEL_TRSV_DIRICHLET) {
+        for (const auto& sb : topo.subs) w += (0.5 * sb.nI * (sb.nI + 1.0) + 2.0 * sb.nI) * sizeof(T);
+    } else {
+        for (int q = s0; q < s0 + cnt; ++q) {
+            const double n = topo.subs[q].n();
+            for (int j = 0; j < topo.subs[q].nI; ++j) w += (n - j - 1) + (n - j - 1) * (n - j);
+        }
+    }
+    for (int r = 0; r < reps; ++r) {
+        if (kernel == BDM_KERNEL_POTRF_INTERIOR) {
+            HIPOK(hipMemsetAsync(K_, 0, nKwork_ * sizeof(T), stream_));
+            launch_assemble<T>(stream_, cd, maxbox_, fp, ke_, vlin_, wlin_, (T*)K_);
+        }
+        HIPOK(hipEventRecord(e0, stream_));
+        if (kernel == BDM_KERNEL_JACOBIAN)
+            launch_jac_apply(stream_, fp, st_, dg_, kp_, kq_);
+        else if (kernel == BDM_KERNEL_TRSV_DIRICHLET)
+            launch_trsv<T>(stream_, nsub, false, (const T*)LIIs_, LII_off_, nI_, nI_, (T*)xI_, xI_off_);
+        else
+            launch_potrf<T>(stream_, cnt, (T*)K_, Kc_off_ + s0, ld_ + s0, st1c0_ + s0, st1c1_ + s0, st1c2_ + s0,
+                            info_sub_ + s0, true);
+        HIPOK(hipEventRecord(e1, stream_));
+        HIPOK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPOK(hipEventElapsedTime(&ms, e0, e1));
+        total += ms;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *avg_ms = total / reps;
+    *work = w;
+    return 0;
 }
 
 int Context::step(int nsteps, bdm_step_stats* st) {

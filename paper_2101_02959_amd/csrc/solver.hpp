@@ -38,6 +38,7 @@ class Context {
     int bddc_apply(const double* r, double* z);
     int fetidp_apply(int op, const double* in, double* out);
     int step(int nsteps, bdm_step_stats* st);
+    int profile_kernel(int kernel, int reps, double* avg_ms, double* work);
     long n_lambda() const { return nlam_; }
 
     Topology topo;
@@ -48,6 +49,7 @@ class Context {
 
   private:
     template <typename T> int alloc_local();
+    template <typename T> int profile_t(int kernel, int reps, double* avg_ms, double* work);
     template <typename T> int linearize_t();
     template <typename T> void dirichlet(const double* r, const double* q, double* out);
     template <typename T> void condense(const double* r, double* g);
