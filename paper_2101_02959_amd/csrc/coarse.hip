@@ -21,57 +21,110 @@ namespace bdm {
 namespace {
 
 constexpr int TB = 64;     // GEMM tile
-constexpr int TK = 16;     // GEMM k-step
-constexpr int SB = 32;     // sweep block
+constexpr int TK = 32;     // GEMM k-step
+constexpr int SB = 64;     // sweep block
+constexpr int GV_ROWS = 256, GV_COLS = 128;   // GEMV stage-1 tile
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // C = beta C + alpha op(A) op(B); column-major; op = transpose when flag set.
+// 64x64 tile per workgroup, k staged through LDS; each wave owns a 32x32
+// quarter computed with 2x2 MFMA f64 16x16x4 blocks.  Operand lanes: A lane l
+// holds A[l%16][l/16], B lane l holds B[l/16][l%16]; accumulator register v
+// of lane l holds row l/16 + 4v of column l%16.
 __global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, double alpha, const double* __restrict__ A,
                                               int64_t lda, int ta, const double* __restrict__ B, int64_t ldb,
                                               int tb, double beta, double* __restrict__ C, int64_t ldc) {
     __shared__ double As[TK][TB + 1];
     __shared__ double Bs[TK][TB + 1];
     const int tid = threadIdx.x;
-    const int tx = tid % 16, ty = tid / 16;
+    const int wv = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+    const int wr = wv & 1, wc = wv >> 1;
     const int i0 = blockIdx.x * TB, j0 = blockIdx.y * TB;
-    double acc[4][4] = {};
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = (f64x4){0, 0, 0, 0};
     for (int kk = 0; kk < k; kk += TK) {
         for (int idx = tid; idx < TK * TB; idx += 256) {
-            const int r = idx % TB, c = idx / TB;   // r: row within tile, c: k index
+            int r, c;
+            if (ta) { c = idx % TK; r = idx / TK; } else { r = idx % TB; c = idx / TB; }
             const int gi = i0 + r, gk = kk + c;
             double a = 0.0;
             if (gi < m && gk < k) a = ta ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda];
             As[c][r] = a;
-            const int gj = j0 + r;
+        }
+        for (int idx = tid; idx < TK * TB; idx += 256) {
+            int r, c;
+            if (tb) { r = idx % TB; c = idx / TB; } else { c = idx % TK; r = idx / TK; }
+            const int gj = j0 + r, gk = kk + c;
             double b = 0.0;
             if (gj < n && gk < k) b = tb ? B[gj + (int64_t)gk * ldb] : B[gk + (int64_t)gj * ldb];
             Bs[c][r] = b;
         }
         __syncthreads();
 #pragma unroll
-        for (int c = 0; c < TK; ++c) {
-            double av[4], bv[4];
+        for (int c = 0; c < TK; c += 4) {
+            double av[2], bv[2];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                av[q] = As[c][ty + 16 * q];
-                bv[q] = Bs[c][tx + 16 * q];
+            for (int q = 0; q < 2; ++q) {
+                av[q] = As[c + lk][wr * 32 + 16 * q + lr];
+                bv[q] = Bs[c + lk][wc * 32 + 16 * q + lr];
             }
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int gi = i0 + ty + 16 * a, gj = j0 + tx + 16 * b;
-            if (gi < m && gj < n) {
-                double* cp = C + gi + (int64_t)gj * ldc;
-                *cp = (beta == 0.0 ? 0.0 : beta * *cp) + alpha * acc[a][b];
+        for (int b = 0; b < 2; ++b) {
+            const int gj = j0 + wc * 32 + 16 * b + lr;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gi = i0 + wr * 32 + 16 * a + lk + 4 * v;
+                if (gi < m && gj < n) {
+                    double* cp = C + gi + (int64_t)gj * ldc;
+                    *cp = (beta == 0.0 ? 0.0 : beta * *cp) + alpha * acc[a][b][v];
+                }
             }
         }
+}
+
+// Stage 1 of y = A x (A m x n): partial sums over column chunks of GV_COLS,
+// threads along rows (coalesced); stage 2 adds the partials in a fixed order.
+__global__ __launch_bounds__(GV_ROWS) void k_gemv_part(int m, int n, const double* __restrict__ A, int64_t lda,
+                                                        const double* __restrict__ x, double* __restrict__ part) {
+    __shared__ double xs[GV_COLS];
+    const int c0 = blockIdx.y * GV_COLS;
+    const int cn = min(GV_COLS, n - c0);
+    for (int t = threadIdx.x; t < cn; t += GV_ROWS) xs[t] = x[c0 + t];
+    __syncthreads();
+    const int i = blockIdx.x * GV_ROWS + threadIdx.x;
+    if (i >= m) return;
+    const double* a = A + i + (int64_t)c0 * lda;
+    double acc0 = 0.0, acc1 = 0.0;
+    int j = 0;
+    for (; j + 1 < cn; j += 2) {
+        acc0 = fma(a[(int64_t)j * lda], xs[j], acc0);
+        acc1 = fma(a[(int64_t)(j + 1) * lda], xs[j + 1], acc1);
+    }
+    if (j < cn) acc0 = fma(a[(int64_t)j * lda], xs[j], acc0);
+    part[(int64_t)blockIdx.y * m + i] = acc0 + acc1;
+}
+
+__global__ void k_gemv_sum(int m, int nchunk, double alpha, const double* __restrict__ part, double beta,
+                           double* __restrict__ y) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    double s = 0.0;
+    for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * m + i];
+    y[i] = (beta == 0.0 ? 0.0 : beta * y[i]) + alpha * s;
 }
 
 // y = beta y + alpha op(A) x, one wave per output row block; deterministic.
@@ -122,15 +175,13 @@ __global__ __launch_bounds__(256) void k_block_inv(const double* __restrict__ A,
             return;
         }
         // sweep on pivot p: S_ij -= S_ip S_pj / d (i,j != p); S_ip /= d; S_pj /= d; S_pp = -1/d
-        double upd[4];
+        const double rd = 1.0 / d;
+        double upd[SB * SB / 256];
         int cnt = 0;
         for (int idx = tid; idx < SB * SB; idx += 256, ++cnt) {
             const int i = idx % SB, j = idx / SB;
-            double v = S[i][j];
-            if (i != p && j != p) v -= S[i][p] * S[p][j] / d;
-            else if (i == p && j == p) v = -1.0 / d;
-            else v = v / d;
-            upd[cnt] = v;
+            const double v = S[i][j];
+            upd[cnt] = (i != p && j != p) ? fma(-S[i][p], S[p][j] * rd, v) : ((i == p && j == p) ? -rd : v * rd);
         }
         __syncthreads();
         cnt = 0;
@@ -141,22 +192,6 @@ __global__ __launch_bounds__(256) void k_block_inv(const double* __restrict__ A,
     for (int idx = tid; idx < SB * SB; idx += 256) {
         const int i = idx % SB, j = idx / SB;
         B[i + j * SB] = -S[i][j];
-    }
-}
-
-// T = A[:, K] * B  (n x kb), K = columns k0..k0+kb
-__global__ void k_panel_times(int n, const double* __restrict__ A, int64_t lda, int k0, int kb,
-                              const double* __restrict__ B, double* __restrict__ T) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double a[SB];
-#pragma unroll
-    for (int c = 0; c < SB; ++c) a[c] = (c < kb) ? A[i + (int64_t)(k0 + c) * lda] : 0.0;
-    for (int c = 0; c < kb; ++c) {
-        double acc = 0.0;
-#pragma unroll
-        for (int q = 0; q < SB; ++q) acc = fma(a[q], B[q + c * SB], acc);
-        T[i + (int64_t)c * n] = acc;
     }
 }
 
@@ -232,11 +267,20 @@ void gemm(hipStream_t s, int m, int n, int k, double alpha, const double* A, int
 }
 
 void gemv(hipStream_t s, int m, int n, double alpha, const double* A, int64_t lda, bool ta, const double* x,
-          double beta, double* y) {
+          double beta, double* y, double* part) {
     // ta = false: y (m) = A (m x n) x;  ta = true: y (m) = A^T x with A (n x m)
     if (m <= 0) return;
-    if (!ta) hipLaunchKernelGGL(k_gemv, dim3(nb(m, 64)), dim3(256), 0, s, m, n, alpha, A, lda, 0, x, beta, y);
-    else hipLaunchKernelGGL(k_gemv, dim3(nb(m, 4)), dim3(256), 0, s, m, n, alpha, A, lda, 1, x, beta, y);
+    if (!ta) {
+        const int nch = (n + GV_COLS - 1) / GV_COLS;
+        if (nch == 0) {
+            hipLaunchKernelGGL(k_gemv_sum, dim3(nb(m, 256)), dim3(256), 0, s, m, 0, alpha, part, beta, y);
+            return;
+        }
+        hipLaunchKernelGGL(k_gemv_part, dim3(nb(m, GV_ROWS), nch), dim3(GV_ROWS), 0, s, m, n, A, lda, x, part);
+        hipLaunchKernelGGL(k_gemv_sum, dim3(nb(m, 256)), dim3(256), 0, s, m, nch, alpha, part, beta, y);
+    } else {
+        hipLaunchKernelGGL(k_gemv, dim3(nb(m, 4)), dim3(256), 0, s, m, n, alpha, A, lda, 1, x, beta, y);
+    }
 }
 
 // In-place inverse of an SPD matrix (n x n, ld) by block sweeps.
@@ -245,7 +289,8 @@ void spd_inverse(hipStream_t s, int n, double* A, int64_t lda, double* Bwork, do
     for (int k0 = 0; k0 < n; k0 += SB) {
         const int kb = std::min(SB, n - k0);
         hipLaunchKernelGGL(k_block_inv, dim3(1), dim3(256), 0, s, A, lda, k0, kb, Bwork, info);
-        hipLaunchKernelGGL(k_panel_times, dim3(nb(n, 256)), dim3(256), 0, s, n, A, lda, k0, kb, Bwork, Twork);
+        // T = A[:, K] B
+        gemm(s, n, kb, kb, 1.0, A + (int64_t)k0 * lda, lda, false, Bwork, SB, false, 0.0, Twork, n);
         // R = A[K, :] copied out (kb x n, ld SB) so the in-place update reads no row it writes
         hipLaunchKernelGGL(k_copy_rows, dim3(nb(n, 256)), dim3(256), 0, s, n, A, lda, k0, kb, Rwork);
         // A -= T R
@@ -287,11 +332,11 @@ void CoarseSolver::factor(hipStream_t s, const int* color_list, const std::vecto
 void CoarseSolver::solve(hipStream_t s, double* b) {
     hipLaunchKernelGGL(k_perm, dim3(nb(np, 256)), dim3(256), 0, s, np, d_grp, d_pos, d_goff, b, yb, 1);
     for (int g = 1; g < G; ++g)
-        gemv(s, ng[g], ng[g - 1], -1.0, Cb + E_off[g], ng[g], false, yb + goff[g - 1], 1.0, yb + goff[g]);
+        gemv(s, ng[g], ng[g - 1], -1.0, Cb + E_off[g], ng[g], false, yb + goff[g - 1], 1.0, yb + goff[g], Pw);
     for (int g = 0; g < G; ++g)
-        gemv(s, ng[g], ng[g], 1.0, D + D_off[g], ng[g], false, yb + goff[g], 0.0, zb + goff[g]);
+        gemv(s, ng[g], ng[g], 1.0, D + D_off[g], ng[g], false, yb + goff[g], 0.0, zb + goff[g], Pw);
     for (int g = G - 2; g >= 0; --g)
-        gemv(s, ng[g], ng[g + 1], -1.0, Cb + E_off[g + 1], ng[g + 1], true, zb + goff[g + 1], 1.0, zb + goff[g]);
+        gemv(s, ng[g], ng[g + 1], -1.0, Cb + E_off[g + 1], ng[g + 1], true, zb + goff[g + 1], 1.0, zb + goff[g], Pw);
     hipLaunchKernelGGL(k_perm, dim3(nb(np, 256)), dim3(256), 0, s, np, d_grp, d_pos, d_goff, zb, b, 0);
 }
 

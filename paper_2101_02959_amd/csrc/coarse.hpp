@@ -19,8 +19,10 @@ struct CoarseMap {
 
 void gemm(hipStream_t s, int m, int n, int k, double alpha, const double* A, int64_t lda, bool ta,
           const double* B, int64_t ldb, bool tb, double beta, double* C, int64_t ldc);
+// part: workspace of m * ceil(n / 128) doubles (non-transposed case)
 void gemv(hipStream_t s, int m, int n, double alpha, const double* A, int64_t lda, bool ta, const double* x,
-          double beta, double* y);
+          double beta, double* y, double* part);
+constexpr int kCoarseSweepBlock = 64;
 void spd_inverse(hipStream_t s, int n, double* A, int64_t lda, double* Bwork, double* Twork, double* Rwork,
                  int* info);
 
@@ -31,7 +33,7 @@ struct CoarseSolver {
     int64_t nD = 0, nE = 0;
     // device
     double *D = nullptr, *E = nullptr, *Cb = nullptr, *yb = nullptr, *zb = nullptr;
-    double *Bw = nullptr, *Tw = nullptr, *Rw = nullptr;
+    double *Bw = nullptr, *Tw = nullptr, *Rw = nullptr, *Pw = nullptr;
     int *d_grp = nullptr, *d_pos = nullptr, *d_ng = nullptr, *info = nullptr;
     int64_t *d_Doff = nullptr, *d_Eoff = nullptr, *d_goff = nullptr;
 

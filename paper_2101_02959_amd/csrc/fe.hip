@@ -5,8 +5,8 @@
 // z-layer is a 27-point stencil whose coefficients depend only on the node's
 // z-level k and on whether it sits on the low / interior / high boundary in x
 // and in y (nine classes).  The host builds these tables once, scaled by tau,
-// for both media; the kernels read them from a small global table that stays
-// resident in L2.
+// for both media; the kernels stage the tables of one z-level at a time in
+// LDS.
 #include <cmath>
 #include <vector>
 
@@ -106,53 +106,105 @@ std::vector<double> stencil_tables(int nz, const std::vector<double>& ke) {
 // --------------------------------------------------------------- device side
 namespace {
 
-struct NodeIdx {
-    int i, j, k;
-    int cls;
-    int64_t off[3][3];   // neighbour offsets per axis (clamped to 0 off-mesh)
-};
-
-__device__ inline void node_index(const FEParams& p, int64_t n, int& i, int& j, int& k) {
-    const int64_t t = n / p.nx1;
-    i = (int)(n - t * p.nx1);
-    k = (int)(t / p.ny1);
-    j = (int)(t - (int64_t)k * p.ny1);
-}
-
-// si = (tau A_i)(xv + xe), se = (tau A_e) xe at node n.
-__device__ inline void stencil2(const FEParams& p, const double* __restrict__ st, int64_t n,
-                                int i, int j, int k, const double* __restrict__ xv,
-                                const double* __restrict__ xe, double& si, double& se) {
-    const int xc = (i == 0) ? 0 : (i == p.nx ? 2 : 1);
-    const int yc = (j == 0) ? 0 : (j == p.ny ? 2 : 1);
-    const double* ti = st + (((int64_t)k * 9 + xc + 3 * yc) * 2) * 27;
-    const double* te = ti + 27;
-    const int64_t pl = (int64_t)p.nx1 * p.ny1;
-    const int64_t ox[3] = {i > 0 ? -1 : 0, 0, i < p.nx ? 1 : 0};
-    const int64_t oy[3] = {j > 0 ? -(int64_t)p.nx1 : 0, 0, j < p.ny ? (int64_t)p.nx1 : 0};
-    const int64_t oz[3] = {k > 0 ? -pl : 0, 0, k < p.nz ? pl : 0};
-    double ai = 0.0, ae = 0.0;
-#pragma unroll
-    for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                const int64_t q = n + ox[dx] + oy[dy] + oz[dz];
-                const int d = dx + 3 * dy + 9 * dz;
-                const double e = xe[q];
-                ai = fma(ti[d], xv[q] + e, ai);
-                ae = fma(te[d], e, ae);
-            }
-    si = ai;
-    se = ae;
-}
+constexpr int SX = 64, SY = 4, SZ = 16;    // block: 64 x 4 nodes, 16 z-levels per thread
 
 __device__ inline double lumped_mass(const FEParams& p, int i, int j, int k) {
     const double fx = (i == 0 || i == p.nx) ? 0.5 : 1.0;
     const double fy = (j == 0 || j == p.ny) ? 0.5 : 1.0;
     const double fz = (k == 0 || k == p.nz) ? 0.5 : 1.0;
     return p.h * p.h * p.h * fx * fy * fz;
+}
+
+enum { ST_JAC = 0, ST_RES_MINUS_JAC = 1, ST_RESIDUAL = 2 };
+
+// One fused 27-point stencil pass over the mesh.  si = (tau A_i)(xv + xe),
+// se = (tau A_e) xe; then
+//   ST_JAC:            y = [d xv + si ; si + se]
+//   ST_RES_MINUS_JAC:  y = r - [d xv + si ; si + se]
+//   ST_RESIDUAL:       y = [m (c (v - v^n) + tau (I_ion - I_s)) + si ; si + se]
+// A block owns a 64 x 4 column of nodes and walks SZ z-levels.  The planes
+// k-1, k, k+1 of (xv + xe) and xe, with a one-node halo, live in a rotating
+// LDS buffer, so each input value is fetched from memory about once; the
+// coefficient tables of level k (9 boundary classes x 2 media) are staged too.
+constexpr int PX = SX + 2, PY = SY + 2;
+
+template <int MODE>
+__global__ __launch_bounds__(SX * SY) void k_stencil(FEParams p, const double* __restrict__ st,
+                                                     const double* __restrict__ dg, const double* __restrict__ xv,
+                                                     const double* __restrict__ xe, const double* __restrict__ rv,
+                                                     const double* __restrict__ re, const double* __restrict__ vn,
+                                                     const double* __restrict__ w, const double* __restrict__ Is,
+                                                     double stim, double* __restrict__ yv, double* __restrict__ ye) {
+    __shared__ double tab[9 * 2 * 27];
+    __shared__ double ps[3][PY][PX];
+    __shared__ double pe[3][PY][PX];
+    const int tid = threadIdx.x + SX * threadIdx.y;
+    const int i0 = blockIdx.x * SX, j0 = blockIdx.y * SY;
+    const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
+    const int kbeg = blockIdx.z * SZ;
+    const int kend = min(kbeg + SZ, p.nz + 1);
+    const bool act = (i <= p.nx) && (j <= p.ny);
+    const int xc = (i == 0) ? 0 : (i == p.nx ? 2 : 1);
+    const int yc = (j == 0) ? 0 : (j == p.ny ? 2 : 1);
+    const int cls = xc + 3 * yc;
+    const int64_t plane = (int64_t)p.nx1 * p.ny1;
+    auto load_plane = [&](int k) {
+        const int sl = (k + 3) % 3;
+        for (int t = tid; t < PX * PY; t += SX * SY) {
+            const int lx = t % PX, ly = t / PX;
+            const int gi = i0 - 1 + lx, gj = j0 - 1 + ly;
+            double a = 0.0, b = 0.0;
+            if (k >= 0 && k <= p.nz && gi >= 0 && gi <= p.nx && gj >= 0 && gj <= p.ny) {
+                const int64_t q = gi + (int64_t)p.nx1 * gj + plane * k;
+                b = xe[q];
+                a = xv[q] + b;
+            }
+            ps[sl][ly][lx] = a;
+            pe[sl][ly][lx] = b;
+        }
+    };
+    load_plane(kbeg - 1);
+    load_plane(kbeg);
+    for (int k = kbeg; k < kend; ++k) {
+        load_plane(k + 1);
+        for (int t = tid; t < 9 * 2 * 27; t += SX * SY) tab[t] = st[(int64_t)k * 9 * 2 * 27 + t];
+        __syncthreads();
+        if (act) {
+            const double* ti = tab + cls * 54;
+            const double* te = ti + 27;
+            double ai = 0.0, ae = 0.0;
+#pragma unroll
+            for (int dz = 0; dz < 3; ++dz) {
+                const int sl = (k + dz + 2) % 3;
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                    for (int dx = 0; dx < 3; ++dx) {
+                        const int d = dx + 3 * dy + 9 * dz;
+                        ai = fma(ti[d], ps[sl][threadIdx.y + dy][threadIdx.x + dx], ai);
+                        ae = fma(te[d], pe[sl][threadIdx.y + dy][threadIdx.x + dx], ae);
+                    }
+            }
+            const int64_t n = i + (int64_t)p.nx1 * j + plane * k;
+            if (MODE == ST_RESIDUAL) {
+                const double vv = xv[n];
+                const double m = lumped_mass(p, i, j, k);
+                const double is = (stim != 0.0 && Is) ? Is[n] : 0.0;
+                yv[n] = m * (p.c * (vv - vn[n]) + p.tau * (rmc_iion(p, vv, w[n]) - is)) + ai;
+                ye[n] = ai + ae;
+            } else {
+                const double a = dg[n] * xv[n] + ai, b = ai + ae;
+                if (MODE == ST_JAC) {
+                    yv[n] = a;
+                    ye[n] = b;
+                } else {
+                    yv[n] = rv[n] - a;
+                    ye[n] = re[n] - b;
+                }
+            }
+        }
+        __syncthreads();
+    }
 }
 
 __global__ void k_ionic_update(int64_t N, double tau, double eta2, double vp,
@@ -162,61 +214,22 @@ __global__ void k_ionic_update(int64_t N, double tau, double eta2, double vp,
     w[n] = (w[n] + tau * eta2 * v[n] / vp) / (1.0 + tau * eta2);
 }
 
-__global__ void k_residual(FEParams p, const double* __restrict__ st, const double* __restrict__ v,
-                           const double* __restrict__ ue, const double* __restrict__ vn,
-                           const double* __restrict__ w, const double* __restrict__ Is, double stim,
-                           double* __restrict__ Rv, double* __restrict__ Re) {
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= p.N) return;
-    int i, j, k;
-    node_index(p, n, i, j, k);
-    double si, se;
-    stencil2(p, st, n, i, j, k, v, ue, si, se);
-    const double m = lumped_mass(p, i, j, k);
-    const double vv = v[n];
-    const double ion = rmc_iion(p, vv, w[n]);
-    const double is = (stim != 0.0 && Is) ? Is[n] : 0.0;
-    Rv[n] = m * (p.c * (vv - vn[n]) + p.tau * (ion - is)) + si;
-    Re[n] = si + se;
-}
-
 __global__ void k_reaction_diag(FEParams p, const double* __restrict__ v, const double* __restrict__ w,
                                 double* __restrict__ dg, int* __restrict__ bad) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= p.N) return;
-    int i, j, k;
-    node_index(p, n, i, j, k);
+    const int64_t t = n / p.nx1;
+    const int i = (int)(n - t * p.nx1);
+    const int k = (int)(t / p.ny1);
+    const int j = (int)(t - (int64_t)k * p.ny1);
     const double d = lumped_mass(p, i, j, k) * (p.c + p.tau * rmc_diion(p, v[n], w[n]));
     dg[n] = d;
     if (!(d > 0.0)) atomicOr(bad, 1);
 }
 
-__global__ void k_jac_apply(FEParams p, const double* __restrict__ st, const double* __restrict__ dg,
-                            const double* __restrict__ xv, const double* __restrict__ xe,
-                            double* __restrict__ yv, double* __restrict__ ye) {
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= p.N) return;
-    int i, j, k;
-    node_index(p, n, i, j, k);
-    double si, se;
-    stencil2(p, st, n, i, j, k, xv, xe, si, se);
-    yv[n] = dg[n] * xv[n] + si;
-    ye[n] = si + se;
-}
-
-// y = r - J x  (used for condensed residuals: only some rows are read)
-__global__ void k_res_minus_jac(FEParams p, const double* __restrict__ st, const double* __restrict__ dg,
-                                const double* __restrict__ xv, const double* __restrict__ xe,
-                                const double* __restrict__ rv, const double* __restrict__ re,
-                                double* __restrict__ yv, double* __restrict__ ye) {
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= p.N) return;
-    int i, j, k;
-    node_index(p, n, i, j, k);
-    double si, se;
-    stencil2(p, st, n, i, j, k, xv, xe, si, se);
-    yv[n] = rv[n] - (dg[n] * xv[n] + si);
-    ye[n] = re[n] - (si + se);
+inline dim3 stencil_grid(const FEParams& p) {
+    return dim3((unsigned)((p.nx1 + SX - 1) / SX), (unsigned)((p.ny1 + SY - 1) / SY),
+                (unsigned)((p.nz + 1 + SZ - 1) / SZ));
 }
 
 }  // namespace
@@ -231,8 +244,8 @@ void launch_ionic_update(hipStream_t s, const FEParams& p, const double* v, doub
 void launch_residual(hipStream_t s, const FEParams& p, const double* st, const double* v,
                      const double* ue, const double* vn, const double* w, const double* Is,
                      double stim, double* Rv, double* Re) {
-    hipLaunchKernelGGL(k_residual, dim3(nblk(p.N, 256)), dim3(256), 0, s, p, st, v, ue, vn, w, Is,
-                       stim, Rv, Re);
+    hipLaunchKernelGGL(k_stencil<ST_RESIDUAL>, stencil_grid(p), dim3(SX, SY), 0, s, p, st, nullptr, v, ue,
+                       nullptr, nullptr, vn, w, Is, stim, Rv, Re);
 }
 
 void launch_reaction_diag(hipStream_t s, const FEParams& p, const double* v, const double* w,
@@ -242,14 +255,14 @@ void launch_reaction_diag(hipStream_t s, const FEParams& p, const double* v, con
 
 void launch_jac_apply(hipStream_t s, const FEParams& p, const double* st, const double* dg,
                       const double* x, double* y) {
-    hipLaunchKernelGGL(k_jac_apply, dim3(nblk(p.N, 256)), dim3(256), 0, s, p, st, dg, x, x + p.N, y,
-                       y + p.N);
+    hipLaunchKernelGGL(k_stencil<ST_JAC>, stencil_grid(p), dim3(SX, SY), 0, s, p, st, dg, x, x + p.N, nullptr,
+                       nullptr, nullptr, nullptr, nullptr, 0.0, y, y + p.N);
 }
 
 void launch_res_minus_jac(hipStream_t s, const FEParams& p, const double* st, const double* dg,
                           const double* x, const double* r, double* y) {
-    hipLaunchKernelGGL(k_res_minus_jac, dim3(nblk(p.N, 256)), dim3(256), 0, s, p, st, dg, x,
-                       x + p.N, r, r + p.N, y, y + p.N);
+    hipLaunchKernelGGL(k_stencil<ST_RES_MINUS_JAC>, stencil_grid(p), dim3(SX, SY), 0, s, p, st, dg, x, x + p.N,
+                       r, r + p.N, nullptr, nullptr, nullptr, 0.0, y, y + p.N);
 }
 
 }  // namespace bdm

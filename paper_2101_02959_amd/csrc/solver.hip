@@ -453,13 +453,15 @@ int Context::alloc_local() {
         c.Cb = (double*)dalloc(std::max<int64_t>(c.nE, 1) * sizeof(double));
         c.yb = (double*)dalloc((size_t)np * sizeof(double));
         c.zb = (double*)dalloc((size_t)np * sizeof(double));
-        c.Bw = (double*)dalloc(32 * 32 * sizeof(double));
-        c.Tw = (double*)dalloc((size_t)c.maxn * 32 * sizeof(double));
-        c.Rw = (double*)dalloc((size_t)c.maxn * 32 * sizeof(double));
+        const int sb = kCoarseSweepBlock;
+        c.Bw = (double*)dalloc((size_t)sb * sb * sizeof(double));
+        c.Tw = (double*)dalloc((size_t)c.maxn * sb * sizeof(double));
+        c.Rw = (double*)dalloc((size_t)c.maxn * sb * sizeof(double));
+        c.Pw = (double*)dalloc((size_t)c.maxn * ((c.maxn + 127) / 128 + 1) * sizeof(double));
         c.info = (int*)dalloc(sizeof(int));
         c.d_grp = upload(c.grp); c.d_pos = upload(c.pos); c.d_ng = upload(c.ng);
         c.d_Doff = upload(c.D_off); c.d_Eoff = upload(c.E_off); c.d_goff = upload(c.goff);
-        if (!c.D || !c.E || !c.Cb || !c.yb || !c.zb || !c.Bw || !c.Tw || !c.Rw || !c.info) {
+        if (!c.D || !c.E || !c.Cb || !c.yb || !c.zb || !c.Bw || !c.Tw || !c.Rw || !c.Pw || !c.info) {
             set_error("device allocation failed (coarse)");
             return BDM_E_OOM;
         }
