@@ -1,0 +1,97 @@
+"""Host logic of libbidomain without a GPU: the C++ partition and N_x
+classification, built with g++, against the oracle's decomposition; and the
+C ABI library exporting every entry point its header declares."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from conftest import ROOT
+from oracle import dd
+from workload import Mesh
+
+EXE = os.path.join(ROOT, "_build", "topo_dump")
+
+
+@pytest.fixture(scope="module")
+def topo_exe():
+    os.makedirs(os.path.dirname(EXE), exist_ok=True)
+    src = [os.path.join(ROOT, "tests", "host", "topo_dump.cpp"),
+           os.path.join(ROOT, "paper_2101_02959_amd", "csrc", "topology.cpp")]
+    r = subprocess.run(["g++", "-O1", "-std=c++17", "-o", EXE] + src, capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.fail(r.stderr)
+    return EXE
+
+
+def _dump(exe, mesh):
+    args = [mesh.nx, mesh.ny, mesh.nz, len(mesh.cuts_x) - 1, len(mesh.cuts_y) - 1,
+            len(mesh.cuts_z) - 1] + list(mesh.cuts_x) + list(mesh.cuts_y) + list(mesh.cuts_z)
+    out = subprocess.run([exe] + [str(a) for a in args], capture_output=True, text=True, check=True).stdout
+    objs, subs = [], []
+    for line in out.splitlines():
+        if line.startswith("OBJ"):
+            head, nodes = line[4:].split("|")
+            h = head.split()
+            objs.append((h[0], tuple(int(x) for x in h[1:]), tuple(int(x) for x in nodes.split())))
+        elif line.startswith("SUB"):
+            parts = line[4:].split("|")
+            h = [int(x) for x in parts[0].split()]
+            subs.append((h, [int(x) for x in parts[1].split()], [int(x) for x in parts[2].split()],
+                         [int(x) for x in parts[3].split()]))
+    return objs, subs
+
+
+MESHES = [
+    Mesh(8, 8, 8, 0.01, (0, 4, 8), (0, 4, 8), (0, 4, 8)),
+    Mesh(11, 9, 10, 0.01, (0, 3, 7, 11), (0, 5, 9), (0, 4, 10)),
+    Mesh(12, 12, 8, 0.01, (0, 4, 8, 12), (0, 3, 6, 12), (0, 4, 8)),
+]
+
+
+@pytest.mark.parametrize("mesh", MESHES, ids=["cube8", "ragged", "uneven3x3x2"])
+def test_partition_matches_oracle(topo_exe, mesh):
+    """Same faces / edges / vertices (sharing subdomains and nodes, in the same
+    order), same interior and interface node lists per subdomain, same primal
+    numbering as the oracle's N_x classification (Sec. 4.1)."""
+    objs, subs = _dump(topo_exe, mesh)
+    dec = dd.Decomposition(mesh)
+    ref = ([("F", o.subs, tuple(o.nodes)) for o in dec.faces]
+           + [("E", o.subs, tuple(o.nodes)) for o in dec.edges]
+           + [("V", o.subs, tuple(o.nodes)) for o in dec.verts])
+    assert objs == ref
+    assert len(subs) == dec.nsub
+    for s, (h, I, r, prim) in enumerate(subs):
+        info = dec.sub[s]
+        assert h[0] == s
+        assert h[1:6] == [info.nI, info.nr, info.nV, 2 * len(info.edges), info.nV + 2 * len(info.edges)]
+        assert I == list(info.I_nodes)
+        assert r == list(info.r_nodes)
+        assert prim == list(info.primal)
+
+
+def test_partition_rejects_bad_cuts(topo_exe):
+    r = subprocess.run([topo_exe, "8", "8", "8", "2", "2", "1", "0", "4", "8", "0", "4", "8", "0", "8"],
+                       capture_output=True, text=True)
+    assert r.returncode == 1 and "ERROR" in r.stdout
+
+
+def test_library_exports_every_declared_entry_point():
+    """libbidomain.so loads on a machine without a GPU and exports every
+    function declared in include/bidomain.h (no compute call is made)."""
+    lib_path = os.path.join(ROOT, "paper_2101_02959_amd", "libbidomain.so")
+    if not os.path.exists(lib_path):
+        pytest.skip("library not built")
+    with open(os.path.join(ROOT, "include", "bidomain.h")) as f:
+        hdr = f.read()
+    names = sorted(set(re.findall(r"\b(bdm_[a-z_]+)\s*\(", hdr)))
+    assert "bdm_step" in names and "bdm_bddc_apply" in names and "bdm_fetidp_apply" in names
+    lib = ctypes.CDLL(lib_path)
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_2101_02959_amd import bidomain
+    assert set(bidomain.EXPORTS) == set(names)
+    lib.bdm_last_error.restype = ctypes.c_char_p
+    assert lib.bdm_last_error() is not None
