@@ -50,7 +50,7 @@ enum {
 
 enum { BDM_SOLVER_BDDC = 0, BDM_SOLVER_FETIDP = 1 };
 enum { BDM_PREC_FP64 = 0, BDM_PREC_MIXED = 1 };
-enum { BDM_GUESS_PREV = 0, BDM_GUESS_EXTRAP = 1 };
+enum { BDM_GUESS_PREV = 0, BDM_GUESS_EXTRAP = 1, BDM_GUESS_CNN = 2 };
 enum { BDM_FETI_F = 0, BDM_FETI_PRECOND = 1, BDM_FETI_RHS = 2, BDM_FETI_RECOVER = 3 };
 
 /* Structured hexahedral Q1 mesh of nx*ny*nz cubes of side h (Sec. 3a) and a
@@ -102,6 +102,10 @@ typedef struct bdm_step_stats {
     double t_krylov_ms;         /* Krylov loop time                          */
     double t_step_ms;           /* whole step                                */
     int bad_subdomain;          /* first subdomain whose factor failed or -1 */
+    int guess_used;             /* 0 u^n, 1 extrapolation, 2 learned guess   */
+    double guess_res_extrap;    /* ||R|| of the extrapolated guess (or -1)   */
+    double guess_res_cnn;       /* ||R|| of the learned guess (or -1)        */
+    double res_ref;             /* ||R(u^n)||, the reference of newton_rtol  */
 } bdm_step_stats;
 
 typedef struct bdm_ctx bdm_ctx;
@@ -173,6 +177,40 @@ int bdm_fetidp_apply(bdm_ctx* ctx, int op, const double* in, double* out);
  * Armijo alpha = 1e-4) with PCG preconditioned by BDDC, or FETI-DP PCG on
  * the multipliers plus recovery, per opts.solver.  stats may be NULL. */
 int bdm_step(bdm_ctx* ctx, int nsteps, bdm_step_stats* stats);
+
+/* Learned Newton initial guess (an addition to the paper's method: it only
+ * changes the starting point of Newton; the tolerance and hence the converged
+ * solution are unchanged).  A 3-D CNN on the node grid, four 3x3x3 zero-padded
+ * convolutions with channels 4 -> 16 -> 16 -> 16 -> 2 and GELU after the first
+ * three, FP16 weights and activations with FP32 accumulation.  Inputs
+ * (v^n/s_v, u_e^n/s_e, (v^n - v^{n-1})/s_dv, (u_e^n - u_e^{n-1})/s_de); output
+ * y; the guess is
+ *   u^{(0)} = u^n + (u^n - u^{n-1}) + (s_yv y_0, s_ye y_1).
+ * Parameters: one float vector, layer by layer, weights [Cout][Cin][27] (tap
+ * dx + 3 dy + 9 dz) then biases; scales = {s_v, s_e, s_dv, s_de, s_yv, s_ye},
+ * all positive (host, 6 doubles).
+ * With opts.guess = BDM_GUESS_CNN, bdm_step evaluates the residual of the
+ * learned and of the extrapolated guess and starts Newton from the smaller
+ * (without weights it behaves as BDM_GUESS_EXTRAP).
+ * The first bdm_predictor_set allocates the network's device buffers (about
+ * 340 N bytes); set resets the Adam moments.  Errors: BDM_E_ARG for a
+ * non-positive scale, learning rate or an order index outside [0, nsamples);
+ * BDM_E_STATE for guess, loss_grad, train or get before weights were set;
+ * BDM_E_OOM when the buffers cannot be allocated. */
+long bdm_predictor_size(void);
+int bdm_predictor_set(bdm_ctx* ctx, const float* params, const double* scales);   /* host */
+int bdm_predictor_get(bdm_ctx* ctx, float* params, double* scales);               /* host */
+/* guess (device, 2N) from v^n, u_e^n, v^{n-1}, u_e^{n-1} (device, N each) */
+int bdm_predictor_guess(bdm_ctx* ctx, const double* vn, const double* uen, const double* vprev,
+                        const double* ueprev, double* guess);
+/* Mean-squared loss of one sample (device, 6N: v^n, u_e^n, v^{n-1}, u_e^{n-1},
+ * v^{n+1}, u_e^{n+1}) against the target ((u^{n+1}-u^n)-(u^n-u^{n-1}))/s_y and
+ * its gradient (host, bdm_predictor_size() floats). */
+int bdm_predictor_loss_grad(bdm_ctx* ctx, const double* sample, float* grad, double* loss);
+/* Adam (beta 0.9, 0.999, eps 1e-8, learning rate lr) over nsteps samples
+ * samples + order[t] * 6N (device), losses (host, nsteps) before each update. */
+int bdm_predictor_train(bdm_ctx* ctx, const double* samples, int nsamples, const int* order, int nsteps,
+                        double lr, double* losses);
 
 /* Kernel timing for roofline reports.  At the last linearisation, launches
  * one hot kernel reps times on the context stream, each bracketed by HIP

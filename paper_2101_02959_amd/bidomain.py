@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libbidomain.so")
 
 BDM_SOLVER_BDDC, BDM_SOLVER_FETIDP = 0, 1
 BDM_PREC_FP64, BDM_PREC_MIXED = 0, 1
-BDM_GUESS_PREV, BDM_GUESS_EXTRAP = 0, 1
+BDM_GUESS_PREV, BDM_GUESS_EXTRAP, BDM_GUESS_CNN = 0, 1, 2
 BDM_FETI_F, BDM_FETI_PRECOND, BDM_FETI_RHS, BDM_FETI_RECOVER = 0, 1, 2, 3
 BDM_KERNEL_JACOBIAN, BDM_KERNEL_TRSV_DIRICHLET, BDM_KERNEL_POTRF_INTERIOR = 0, 1, 2
 
@@ -30,7 +30,8 @@ ERRORS = {
 EXPORTS = ("bdm_create", "bdm_destroy", "bdm_set_state", "bdm_get_state", "bdm_set_stimulus",
            "bdm_ionic_update", "bdm_residual", "bdm_linearize", "bdm_jacobian_apply",
            "bdm_bddc_apply", "bdm_fetidp_size", "bdm_fetidp_apply", "bdm_step", "bdm_sizes",
-           "bdm_profile_kernel", "bdm_last_error")
+           "bdm_profile_kernel", "bdm_predictor_size", "bdm_predictor_set", "bdm_predictor_get",
+           "bdm_predictor_guess", "bdm_predictor_loss_grad", "bdm_predictor_train", "bdm_last_error")
 
 
 class BidomainError(RuntimeError):
@@ -63,7 +64,8 @@ class bdm_opts(C.Structure):
 class bdm_step_stats(C.Structure):
     _fields_ = [("newton_its", C.c_int), ("krylov_its", C.c_int * 32), ("res_hist", C.c_double * 33),
                 ("cond", C.c_double * 32), ("t_setup_ms", C.c_double), ("t_krylov_ms", C.c_double),
-                ("t_step_ms", C.c_double), ("bad_subdomain", C.c_int)]
+                ("t_step_ms", C.c_double), ("bad_subdomain", C.c_int), ("guess_used", C.c_int),
+                ("guess_res_extrap", C.c_double), ("guess_res_cnn", C.c_double), ("res_ref", C.c_double)]
 
 
 _lib = None
@@ -95,6 +97,12 @@ def lib():
         "bdm_step": ([vp, ci, C.POINTER(bdm_step_stats)], ci),
         "bdm_sizes": ([vp, C.POINTER(C.c_long), C.POINTER(C.c_long), C.POINTER(C.c_long)], ci),
         "bdm_profile_kernel": ([vp, ci, ci, C.POINTER(cd), C.POINTER(cd)], ci),
+        "bdm_predictor_size": ([], C.c_long),
+        "bdm_predictor_set": ([vp, C.POINTER(C.c_float), C.POINTER(cd)], ci),
+        "bdm_predictor_get": ([vp, C.POINTER(C.c_float), C.POINTER(cd)], ci),
+        "bdm_predictor_guess": ([vp, vp, vp, vp, vp, vp], ci),
+        "bdm_predictor_loss_grad": ([vp, vp, C.POINTER(C.c_float), C.POINTER(cd)], ci),
+        "bdm_predictor_train": ([vp, vp, ci, C.POINTER(ci), ci, cd, C.POINTER(cd)], ci),
         "bdm_last_error": ([], C.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -229,6 +237,55 @@ class Solver:
         ms, work = C.c_double(), C.c_double()
         _check(lib().bdm_profile_kernel(self.h, kernel, reps, C.byref(ms), C.byref(work)))
         return ms.value, work.value
+
+    # --- learned initial guess
+    @staticmethod
+    def bdm_predictor_size():
+        return int(lib().bdm_predictor_size())
+
+    def bdm_predictor_set(self, params, scales):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.bdm_predictor_size():
+            raise ValueError(f"expected {self.bdm_predictor_size()} parameters, got {p.size}")
+        sc = np.ascontiguousarray(scales, dtype=np.float64)
+        if sc.size != 6:
+            raise ValueError("expected 6 scales (s_v, s_e, s_dv, s_de, s_yv, s_ye)")
+        _check(lib().bdm_predictor_set(self.h, p.ctypes.data_as(C.POINTER(C.c_float)),
+                                       sc.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def bdm_predictor_get(self):
+        p = np.zeros(self.bdm_predictor_size(), dtype=np.float32)
+        sc = np.zeros(6)
+        _check(lib().bdm_predictor_get(self.h, p.ctypes.data_as(C.POINTER(C.c_float)),
+                                       sc.ctypes.data_as(C.POINTER(C.c_double))))
+        return p, sc
+
+    def bdm_predictor_guess(self, vn, uen, vprev, ueprev):
+        a = [self._dev(x) for x in (vn, uen, vprev, ueprev)]
+        out = self.vec()
+        _check(lib().bdm_predictor_guess(self.h, *[_ptr(x) for x in a], _ptr(out)))
+        return out
+
+    def bdm_predictor_loss_grad(self, sample):
+        s6 = self._dev(sample)
+        if s6.numel() != 6 * self.N:
+            raise ValueError("a sample holds 6 N values")
+        g = np.zeros(self.bdm_predictor_size(), dtype=np.float32)
+        loss = C.c_double()
+        _check(lib().bdm_predictor_loss_grad(self.h, _ptr(s6), g.ctypes.data_as(C.POINTER(C.c_float)),
+                                             C.byref(loss)))
+        return loss.value, g
+
+    def bdm_predictor_train(self, samples, order, lr):
+        S = self._dev(samples)
+        if S.numel() % (6 * self.N):
+            raise ValueError("samples must hold whole 6 N blocks")
+        ns = S.numel() // (6 * self.N)
+        o = np.ascontiguousarray(order, dtype=np.int32)
+        losses = np.zeros(o.size)
+        _check(lib().bdm_predictor_train(self.h, _ptr(S), int(ns), o.ctypes.data_as(C.POINTER(C.c_int)),
+                                         int(o.size), float(lr), losses.ctypes.data_as(C.POINTER(C.c_double))))
+        return losses
 
     def bdm_step(self, nsteps=1):
         st = bdm_step_stats()

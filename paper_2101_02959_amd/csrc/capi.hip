@@ -129,6 +129,39 @@ int bdm_profile_kernel(bdm_ctx* ctx, int kernel, int reps, double* avg_ms, doubl
     GUARD(ctx->c.profile_kernel(kernel, reps, avg_ms, work));
 }
 
+long bdm_predictor_size(void) { return bdm::Predictor::n_params(); }
+
+int bdm_predictor_set(bdm_ctx* ctx, const float* params, const double* scales) {
+    NEED(ctx); NEED(params); NEED(scales);
+    GUARD(ctx->c.predictor_set(params, scales));
+}
+
+int bdm_predictor_get(bdm_ctx* ctx, float* params, double* scales) {
+    NEED(ctx); NEED(params); NEED(scales);
+    GUARD(ctx->c.predictor_get(params, scales));
+}
+
+int bdm_predictor_guess(bdm_ctx* ctx, const double* vn, const double* uen, const double* vprev, const double* ueprev,
+                        double* guess) {
+    NEED(ctx); NEED(vn); NEED(uen); NEED(vprev); NEED(ueprev); NEED(guess);
+    GUARD(ctx->c.predictor_guess(vn, uen, vprev, ueprev, guess));
+}
+
+int bdm_predictor_loss_grad(bdm_ctx* ctx, const double* sample, float* grad, double* loss) {
+    NEED(ctx); NEED(sample); NEED(grad); NEED(loss);
+    GUARD(ctx->c.predictor_loss_grad(sample, grad, loss));
+}
+
+int bdm_predictor_train(bdm_ctx* ctx, const double* samples, int nsamples, const int* order, int nsteps, double lr,
+                        double* losses) {
+    NEED(ctx); NEED(samples); NEED(order);
+    if (nsamples <= 0 || nsteps < 0 || !(lr > 0)) {
+        bdm::set_error("bdm_predictor_train: nsamples > 0, nsteps >= 0 and lr > 0 required");
+        return BDM_E_ARG;
+    }
+    GUARD(ctx->c.predictor_train(samples, nsamples, order, nsteps, lr, losses));
+}
+
 int bdm_sizes(bdm_ctx* ctx, long* n_nodes, long* n_sub, long* n_primal) {
     NEED(ctx);
     if (n_nodes) *n_nodes = (long)ctx->c.N;

@@ -854,6 +854,82 @@ int Context::profile_t(int kernel, int reps, double* avg_ms, double* work) {
     return 0;
 }
 
+static void* ctx_alloc(void* c, size_t bytes) {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes ? bytes : 8) != hipSuccess) return nullptr;
+    static_cast<std::vector<void*>*>(c)->push_back(p);
+    return p;
+}
+
+int Context::ensure_predictor() {
+    if (pred_.ready) return 0;
+    const std::string e = pred_.init(N, fp.nx1, fp.ny1, fp.nz + 1, ctx_alloc, &allocs_);
+    if (!e.empty()) {
+        set_error(e);
+        return BDM_E_OOM;
+    }
+    return 0;
+}
+
+int Context::predictor_set(const float* params, const double* scales) {
+    int rc = ensure_predictor();
+    if (rc) return rc;
+    for (int q = 0; q < kScales; ++q)
+        if (!(scales[q] > 0)) {
+            set_error("predictor scales must be positive");
+            return BDM_E_ARG;
+        }
+    pred_.set(stream_, params, scales);
+    HIPOK(hipGetLastError());
+    return 0;
+}
+
+int Context::predictor_get(float* params, double* scales) {
+    if (!pred_.has_weights) {
+        set_error("predictor has no weights");
+        return BDM_E_STATE;
+    }
+    pred_.get(stream_, params, scales);
+    return 0;
+}
+
+int Context::predictor_guess(const double* vn, const double* uen, const double* vp, const double* uep, double* out) {
+    if (!pred_.has_weights) {
+        set_error("predictor has no weights");
+        return BDM_E_STATE;
+    }
+    pred_.guess(stream_, vn, uen, vp, uep, out);
+    return sync();
+}
+
+int Context::predictor_loss_grad(const double* sample, float* grad, double* loss) {
+    if (!pred_.has_weights) {
+        set_error("predictor has no weights");
+        return BDM_E_STATE;
+    }
+    *loss = pred_.loss_grad(stream_, sample);
+    HIPOK(hipMemcpyAsync(grad, pred_.grad, Predictor::n_params() * sizeof(float), hipMemcpyDeviceToHost, stream_));
+    return sync();
+}
+
+int Context::predictor_train(const double* samples, int nsamples, const int* order, int nsteps, double lr,
+                             double* losses) {
+    if (!pred_.has_weights) {
+        set_error("predictor has no weights");
+        return BDM_E_STATE;
+    }
+    for (int t = 0; t < nsteps; ++t) {
+        if (order[t] < 0 || order[t] >= nsamples) {
+            set_error("training order index out of range");
+            return BDM_E_ARG;
+        }
+        const double l = pred_.train_step(stream_, samples + (int64_t)order[t] * 6 * N, lr);
+        if (losses) losses[t] = l;
+    }
+    HIPOK(hipGetLastError());
+    return sync();
+}
+
 int Context::step(int nsteps, bdm_step_stats* st) {
     using clk = std::chrono::steady_clock;
     const size_t vb = (size_t)N * sizeof(double);
@@ -869,16 +945,38 @@ int Context::step(int nsteps, bdm_step_stats* st) {
         // reference residual ||R(u^n)||
         launch_residual(stream_, fp, st_, v_, ue_, vn_, w_, Is_, stim, R_, R_ + N);
         const double ref = std::sqrt(dot(2 * N, R_, R_));
-        // initial guess
-        if (opts.guess == BDM_GUESS_EXTRAP && have_prev_) {
+        S.res_ref = ref;
+        // initial guess: u^n, extrapolation, or the better (smaller ||R||) of the
+        // learned and the extrapolated guess
+        S.guess_used = 0;
+        S.guess_res_extrap = -1.0;
+        S.guess_res_cnn = -1.0;
+        double rn;
+        if (opts.guess != BDM_GUESS_PREV && have_prev_) {
             hipLaunchKernelGGL(k_lin_comb, dim3(nb(N, 256)), dim3(256), 0, stream_, N, 2.0, v_, -1.0, vprev_, U_);
             hipLaunchKernelGGL(k_lin_comb, dim3(nb(N, 256)), dim3(256), 0, stream_, N, 2.0, ue_, -1.0, ueprev_, U_ + N);
+            launch_residual(stream_, fp, st_, U_, U_ + N, vn_, w_, Is_, stim, R_, R_ + N);
+            rn = std::sqrt(dot(2 * N, R_, R_));
+            S.guess_used = 1;
+            S.guess_res_extrap = rn;
+            if (opts.guess == BDM_GUESS_CNN && pred_.has_weights) {
+                pred_.guess(stream_, v_, ue_, vprev_, ueprev_, Rt_);
+                launch_residual(stream_, fp, st_, Rt_, Rt_ + N, vn_, w_, Is_, stim, kq_, kq_ + N);
+                const double rc = std::sqrt(dot(2 * N, kq_, kq_));
+                S.guess_res_cnn = rc;
+                if (rc < rn) {
+                    HIPOK(hipMemcpyAsync(U_, Rt_, 2 * vb, hipMemcpyDeviceToDevice, stream_));
+                    HIPOK(hipMemcpyAsync(R_, kq_, 2 * vb, hipMemcpyDeviceToDevice, stream_));
+                    rn = rc;
+                    S.guess_used = 2;
+                }
+            }
         } else {
             HIPOK(hipMemcpyAsync(U_, v_, vb, hipMemcpyDeviceToDevice, stream_));
             HIPOK(hipMemcpyAsync(U_ + N, ue_, vb, hipMemcpyDeviceToDevice, stream_));
+            launch_residual(stream_, fp, st_, U_, U_ + N, vn_, w_, Is_, stim, R_, R_ + N);
+            rn = std::sqrt(dot(2 * N, R_, R_));
         }
-        launch_residual(stream_, fp, st_, U_, U_ + N, vn_, w_, Is_, stim, R_, R_ + N);
-        double rn = std::sqrt(dot(2 * N, R_, R_));
         S.res_hist[0] = rn;
         int it = 0;
         int status = 0;

@@ -9,6 +9,7 @@
 #include "../../include/bidomain.h"
 #include "bddc_kernels.hpp"
 #include "coarse.hpp"
+#include "learned.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
 #include "topology.hpp"
@@ -39,6 +40,12 @@ class Context {
     int fetidp_apply(int op, const double* in, double* out);
     int step(int nsteps, bdm_step_stats* st);
     int profile_kernel(int kernel, int reps, double* avg_ms, double* work);
+    int predictor_set(const float* params, const double* scales);
+    int predictor_get(float* params, double* scales);
+    int predictor_guess(const double* vn, const double* uen, const double* vp, const double* uep, double* out);
+    int predictor_loss_grad(const double* sample, float* grad, double* loss);
+    int predictor_train(const double* samples, int nsamples, const int* order, int nsteps, double lr,
+                        double* losses);
     long n_lambda() const { return nlam_; }
 
     Topology topo;
@@ -88,6 +95,8 @@ class Context {
     void *LIIs_ = nullptr, *Lrrs_ = nullptr;   // compact Dirichlet / Neumann factors
     void *inv_ = nullptr, *dmat_ = nullptr;    // deluxe (sum S)^{-1} and E_m = S^(m) (sum S)^{-1}
     CoarseSolver coarse_;
+    Predictor pred_;
+    int ensure_predictor();
     std::vector<std::pair<int, int>> chunks_;  // subdomain ranges of the chunked setup
     const int64_t* Kc_off_ = nullptr;           // chunk-relative offsets of the local matrices
     int64_t nKwork_ = 0, nLII_ = 0, nLrr_ = 0;

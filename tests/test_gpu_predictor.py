@@ -1,0 +1,182 @@
+"""Learned Newton initial guess: the HIP network against the FP64 reference
+network (oracle/cnn.py), and its effect on the time step.
+
+The device path stores weights and activations in FP16 and accumulates in
+FP32; the reference is fed the same FP16-rounded weights and inputs and keeps
+everything else in FP64.  Each FP16 rounding of an activation is a relative
+error of at most 2^-11 (about 4.9e-4); four layers and the backward pass
+compound a handful of them, so the output and the loss agree to 5e-3 and the
+gradient to 1e-2 in the relative 2-norm (about 20 roundings).
+"""
+import numpy as np
+import pytest
+
+from oracle import cnn
+from workload import Mesh, PAPER_STIM, Physics, Solver as SolverOpts, small_mesh
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+RAGGED = Mesh(11, 9, 10, 0.01, (0, 3, 7, 11), (0, 5, 9), (0, 4, 10))
+
+
+def _P():
+    import paper_2101_02959_amd as P
+    return P
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _fp16(x):
+    return np.asarray(x, dtype=np.float64).astype(np.float16).astype(np.float64)
+
+
+def _params(seed):
+    from paper_2101_02959_amd.predictor import init_params
+    p = init_params(seed, last_gain=1.0).astype(np.float64)
+    # non-zero biases so that their gradients are exercised
+    rng = np.random.default_rng(seed + 100)
+    k = 0
+    for shape in cnn.param_shapes():
+        n = int(np.prod(shape))
+        if len(shape) == 1:
+            p[k:k + n] = rng.uniform(-0.2, 0.2, n)
+        k += n
+    return p.astype(np.float32)
+
+
+def _ref_params(p32):
+    """FP16-rounded weights, FP32 biases, as the device path holds them."""
+    out = p32.astype(np.float64).copy()
+    k = 0
+    for shape in cnn.param_shapes():
+        n = int(np.prod(shape))
+        if len(shape) > 1:
+            out[k:k + n] = _fp16(out[k:k + n])
+        k += n
+    return out
+
+
+def _sample(mesh, seed):
+    N = (mesh.nx + 1) * (mesh.ny + 1) * (mesh.nz + 1)
+    rng = np.random.default_rng(seed)
+    vn = rng.uniform(-10, 90, N)
+    uen = rng.uniform(-20, 20, N)
+    vp = vn - rng.uniform(-3, 3, N)
+    uep = uen - rng.uniform(-1, 1, N)
+    vx = 2 * vn - vp + rng.uniform(-0.5, 0.5, N)
+    uex = 2 * uen - uep + rng.uniform(-0.2, 0.2, N)
+    return N, (vn, uen, vp, uep, vx, uex)
+
+
+def _ref_input(mesh, f, sc):
+    vn, uen, vp, uep = f[:4]
+    X = np.stack([_fp16(vn / sc[0]), _fp16(uen / sc[1]), _fp16((vn - vp) / sc[2]),
+                  _fp16((uen - uep) / sc[3])])
+    return X.reshape(4, mesh.nz + 1, mesh.ny + 1, mesh.nx + 1)
+
+
+def _ref_target(mesh, f, sc):
+    vn, uen, vp, uep, vx, uex = f
+    t = np.stack([((vx - vn) - (vn - vp)) / sc[4], ((uex - uen) - (uen - uep)) / sc[5]])
+    return t.reshape(2, mesh.nz + 1, mesh.ny + 1, mesh.nx + 1)
+
+
+SCALES = np.array([50.0, 10.0, 2.0, 0.5, 0.3, 0.1])
+
+
+@pytest.mark.parametrize("mesh", [RAGGED, small_mesh((16, 12, 6), (2, 2, 2))], ids=["ragged", "flat"])
+def test_forward_loss_and_gradient_match_reference(mesh):
+    P = _P()
+    S = P.Solver(mesh, Physics(), SolverOpts())
+    N, f = _sample(mesh, 11)
+    p = _params(3)
+    S.bdm_predictor_set(p, SCALES)
+    theta = _ref_params(p)
+    X = _ref_input(mesh, f, SCALES)
+    # forward: the guess is extrapolation + scaled network output
+    g = S.bdm_predictor_guess(*f[:4]).cpu().numpy()
+    y_ref, _ = cnn.forward(theta, X)
+    y_ref = y_ref.reshape(2, N)
+    extrap = np.concatenate([2 * f[0] - f[2], 2 * f[1] - f[3]])
+    y_dev = np.stack([(g[:N] - extrap[:N]) / SCALES[4], (g[N:] - extrap[N:]) / SCALES[5]])
+    assert _rel(y_dev, y_ref) < 5e-3
+    assert np.abs(y_dev - y_ref).max() < 5e-3 * np.abs(y_ref).max()
+    # loss and gradient
+    loss, grad = S.bdm_predictor_loss_grad(np.concatenate(f))
+    loss_ref, grad_ref = cnn.loss_and_grad(theta, X, _ref_target(mesh, f, SCALES))
+    assert abs(loss - loss_ref) < 5e-3 * loss_ref
+    assert _rel(grad.astype(np.float64), grad_ref) < 1e-2
+    # per layer, so that a small layer cannot hide behind a large one
+    k = 0
+    for shape in cnn.param_shapes():
+        n = int(np.prod(shape))
+        assert _rel(grad[k:k + n].astype(np.float64), grad_ref[k:k + n]) < 2e-2, shape
+        k += n
+
+
+def test_get_returns_set_and_adam_first_step():
+    P = _P()
+    mesh = RAGGED
+    S = P.Solver(mesh, Physics(), SolverOpts())
+    N, f = _sample(mesh, 12)
+    p = _params(5)
+    S.bdm_predictor_set(p, SCALES)
+    p_back, sc_back = S.bdm_predictor_get()
+    assert np.array_equal(p_back, p) and np.array_equal(sc_back, SCALES)
+    theta = _ref_params(p)
+    _, grad_ref = cnn.loss_and_grad(theta, _ref_input(mesh, f, SCALES), _ref_target(mesh, f, SCALES))
+    lr = 1e-3
+    losses = S.bdm_predictor_train(np.concatenate(f), [0], lr)
+    assert losses.shape == (1,)
+    p1, _ = S.bdm_predictor_get()
+    th1, _, _ = cnn.adam_step(p.astype(np.float64), np.zeros_like(theta), np.zeros_like(theta), grad_ref, 1, lr=lr)
+    step_dev = p1.astype(np.float64) - p
+    step_ref = th1 - p
+    # Adam's bias-corrected first step has magnitude lr |g| / (|g| + eps) <= lr
+    assert np.all(np.abs(step_dev) <= lr * (1 + 1e-3))
+    # where the gradient is well resolved the step is -lr sign(g), as in the reference
+    big = np.abs(grad_ref) > 0.05 * np.abs(grad_ref).max()
+    assert big.sum() > 100
+    np.testing.assert_allclose(step_dev[big], step_ref[big], rtol=1e-3, atol=lr * 1e-3)
+
+
+def test_training_reduces_loss():
+    """The target is a fixed linear map of the difference inputs, which the
+    network can represent; Adam must at least halve the loss in 200 steps."""
+    P = _P()
+    mesh = RAGGED
+    S = P.Solver(mesh, Physics(), SolverOpts())
+    samples = []
+    for s in range(4):
+        N, f = _sample(mesh, 20 + s)
+        vn, uen, vp, uep = f[:4]
+        vx = 2 * vn - vp + 0.1 * (vn - vp)
+        uex = 2 * uen - uep - 0.05 * (uen - uep)
+        samples.append(np.concatenate([vn, uen, vp, uep, vx, uex]))
+    S.bdm_predictor_set(_params(7), SCALES)
+    order = np.arange(200) % 4
+    losses = S.bdm_predictor_train(np.concatenate(samples), order, 3e-3)
+    assert np.all(np.isfinite(losses))
+    assert losses[-8:].mean() < 0.5 * losses[:8].mean()
+
+
+def test_predictor_errors():
+    P = _P()
+    S = P.Solver(RAGGED, Physics(), SolverOpts())
+    N = S.N
+    z = np.zeros(N)
+    with pytest.raises(P.BidomainError, match="BDM_E_STATE"):
+        S.bdm_predictor_guess(z, z, z, z)
+    with pytest.raises(P.BidomainError, match="BDM_E_STATE"):
+        S.bdm_predictor_get()
+    bad = SCALES.copy()
+    bad[2] = 0.0
+    with pytest.raises(P.BidomainError, match="BDM_E_ARG"):
+        S.bdm_predictor_set(_params(1), bad)
+    S.bdm_predictor_set(_params(1), SCALES)
+    with pytest.raises(P.BidomainError, match="BDM_E_ARG"):
+        S.bdm_predictor_train(np.zeros(6 * N), [1], 1e-3)
