@@ -10,8 +10,9 @@ u_e^{n+1}]`` and the network learns the scaled second difference
 ``(u^{n+1} - 2 u^n + u^{n-1}) / s_y``, i.e. the error of the linear
 extrapolation that the guess corrects.
 
-Usage (writes the default weights):
-    python -m paper_2101_02959_amd.predictor --out paper_2101_02959_amd/weights/predictor.npz
+Usage (trains on the 32^3 slab from 50 seeded stimulus sites, writes the
+default weights and evaluates on 5 held-out sites):
+    python -m paper_2101_02959_amd.predictor
 """
 from __future__ import annotations
 
@@ -115,50 +116,135 @@ def load(path: str = DEFAULT_WEIGHTS):
         return z["params"].copy(), z["scales"].copy()
 
 
-def training_solver(mesh, physics, solver_opts, stim_amp, stim_block, stim_steps, precision):
-    from workload import initial_state, stimulus_nodal
-    S = B.Solver(mesh, physics, solver_opts, precision=precision, guess=B.BDM_GUESS_EXTRAP)
+def site_solver(mesh, physics, solver_opts, origin, stim_amp=None, stim_block=(2, 2, 2), stim_steps=20,
+                precision=B.BDM_PREC_MIXED, guess=B.BDM_GUESS_EXTRAP):
+    """A solver at rest with a stimulus on the element block at ``origin``."""
+    from workload import PAPER_STIM, initial_state, stimulus_nodal
+    S = B.Solver(mesh, physics, solver_opts, precision=precision, guess=guess)
     v0, ue0, w0 = initial_state(mesh, physics, None)
     S.bdm_set_state(v0, ue0, w0)
-    S.bdm_set_stimulus(stimulus_nodal(mesh, stim_block, stim_amp), 0, stim_steps)
+    amp = PAPER_STIM if stim_amp is None else stim_amp
+    S.bdm_set_stimulus(stimulus_nodal(mesh, stim_block, amp, origin), 0, stim_steps)
     return S
+
+
+def dataset(mesh, physics, opts, origins, steps, stim_steps=20, log=print):
+    """Trajectories from every stimulus site, packed as samples (the sample
+    that straddles the stimulus switch-off is skipped), and the scales fitted
+    on the first trajectory."""
+    import torch
+    samples, scales = [], None
+    for q, o in enumerate(origins):
+        S = site_solver(mesh, physics, opts, o, stim_steps=stim_steps)
+        t0 = time.time()
+        states, stats = trajectory(S, steps)
+        S.close()
+        if scales is None:
+            scales = fit_scales(states)
+        samples.append(make_samples(states, skip=(stim_steps,)))
+        log(f"  site {q} {o}: {steps} steps in {time.time() - t0:.1f} s, Newton "
+            f"{sum(s.newton_its for s in stats)}, setup {sum(s.t_setup_ms for s in stats):.0f} ms, "
+            f"Krylov {sum(s.t_krylov_ms for s in stats):.0f} ms")
+        del states
+    return torch.cat(samples), scales
+
+
+def evaluate(mesh, physics, opts, origins, steps, params, scales, stim_steps=20):
+    """Held-out comparison of the extrapolated and the learned (judged) guess.
+    Per step: Newton and PCG iterations, initial and final residual, the
+    guess used and the wall time; and the largest relative difference of the
+    final states (the tolerance is unchanged, so they agree to it)."""
+    rows, worst = [], 0.0
+    for o in origins:
+        per = {}
+        for name, guess in (("extrap", B.BDM_GUESS_EXTRAP), ("cnn", B.BDM_GUESS_CNN)):
+            S = site_solver(mesh, physics, opts, o, stim_steps=stim_steps, guess=guess)
+            if guess == B.BDM_GUESS_CNN:
+                S.bdm_predictor_set(params, scales)
+            out = []
+            for k in range(steps):
+                st = S.bdm_step(1)
+                nit = st.newton_its
+                out.append({"newton": nit, "pcg": int(sum(list(st.krylov_its)[:nit])),
+                            "r0": st.res_hist[0], "rfinal": st.res_hist[nit], "tol": 1e-8 * st.res_ref,
+                            "used": st.guess_used, "ms": st.t_step_ms})
+            v, ue, _, _ = S.bdm_get_state()
+            per[name] = (out, v.cpu().numpy(), ue.cpu().numpy())
+            S.close()
+        for f in (1, 2):
+            a, b = per["cnn"][f], per["extrap"][f]
+            worst = max(worst, float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)))
+        for k in range(steps):
+            rows.append({"site": o, "step": k, "extrap": per["extrap"][0][k], "cnn": per["cnn"][0][k]})
+    return rows, worst
+
+
+def summarize(rows):
+    """Totals and the geometric-mean reduction of the initial residual over
+    steps that have a previous step (k >= 1)."""
+    e = [r["extrap"] for r in rows]
+    c = [r["cnn"] for r in rows]
+    g = [np.log(r["extrap"]["r0"] / r["cnn"]["r0"]) for r in rows if r["step"] >= 1]
+    return {"steps": len(rows),
+            "newton": (sum(x["newton"] for x in e), sum(x["newton"] for x in c)),
+            "pcg": (sum(x["pcg"] for x in e), sum(x["pcg"] for x in c)),
+            "ms": (sum(x["ms"] for x in e), sum(x["ms"] for x in c)),
+            "r0_gain_geomean": float(np.exp(np.mean(g))) if g else 1.0,
+            "cnn_used": sum(1 for x in c if x["used"] == 2)}
 
 
 def main(argv=None):
     import torch
-    from workload import PAPER_STIM, Physics, Solver as Opts, small_mesh
+    from workload import Physics, Solver as Opts, small_mesh, stimulus_sites
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
-    ap.add_argument("--elements", default="48,48,24")
-    ap.add_argument("--parts", default="6,6,3")
-    ap.add_argument("--traj-steps", type=int, default=80)
-    ap.add_argument("--train-steps", type=int, default=4000)
-    ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--lr-final", type=float, default=1e-4)
+    ap.add_argument("--elements", default="32,32,32")
+    ap.add_argument("--parts", default="4,4,4")
+    ap.add_argument("--sites", type=int, default=50)
+    ap.add_argument("--site-seed", type=int, default=7)
+    ap.add_argument("--steps-per-site", type=int, default=40)
+    ap.add_argument("--heldout-sites", type=int, default=5)
+    ap.add_argument("--heldout-seed", type=int, default=8)
+    ap.add_argument("--train-steps", type=int, default=60000)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr-final", type=float, default=1e-5)
     ap.add_argument("--seed", type=int, default=0)
     a = ap.parse_args(argv)
     torch.cuda.init()
+    log = lambda *x: print(*x, flush=True)  # noqa: E731
     ne = tuple(int(x) for x in a.elements.split(","))
     pa = tuple(int(x) for x in a.parts.split(","))
-    mesh = small_mesh(ne, pa)
-    S = training_solver(mesh, Physics(), Opts(), PAPER_STIM, (2, 2, 2), 20, B.BDM_PREC_MIXED)
+    mesh, ph, opts = small_mesh(ne, pa), Physics(), Opts()
+    sites = stimulus_sites(mesh, a.sites, a.site_seed)
+    log(f"dataset: {a.sites} sites x {a.steps_per_site} steps on {ne} elements")
+    samples, scales = dataset(mesh, ph, opts, sites, a.steps_per_site, log=log)
+    log(f"  {samples.shape[0]} samples, scales {np.array2string(scales, precision=4)}")
+    S = B.Solver(mesh, ph, opts)
+    S.bdm_predictor_set(init_params(a.seed), scales)
     t0 = time.time()
-    states, _ = trajectory(S, a.traj_steps)
-    print(f"trajectory: {a.traj_steps} steps on {ne} elements in {time.time() - t0:.1f} s", flush=True)
-    scales = fit_scales(states)
-    samples = make_samples(states)
-    p0 = init_params(a.seed)
-    S.bdm_predictor_set(p0, scales)
-    t0 = time.time()
-    losses = train(S, samples, a.train_steps, a.lr, a.seed + 1, a.lr_final)
-    print(f"training: {a.train_steps} Adam steps in {time.time() - t0:.1f} s, loss "
-          f"{losses[:50].mean():.4g} -> {losses[-200:].mean():.4g}", flush=True)
+    seg = 20
+    rng = np.random.default_rng(a.seed + 1)
+    order = rng.integers(0, samples.shape[0], size=a.train_steps).astype(np.int32)
+    bounds = np.linspace(0, a.train_steps, seg + 1).astype(int)
+    for k in range(seg):
+        lr_k = a.lr * (a.lr_final / a.lr) ** (k / (seg - 1))
+        L = S.bdm_predictor_train(samples, order[bounds[k]:bounds[k + 1]], lr_k)
+        log(f"  train segment {k}: lr {lr_k:.2e} mean loss {L.mean():.4g} ({time.time() - t0:.0f} s)")
     params, sc = S.bdm_predictor_get()
-    save(a.out, params, sc, {"elements": ne, "parts": pa, "traj_steps": a.traj_steps,
-                            "train_steps": a.train_steps, "lr": a.lr, "lr_final": a.lr_final,
-                            "seed": a.seed, "stimulus": PAPER_STIM, "stim_block": (2, 2, 2),
-                            "stim_steps": 20})
-    print(f"wrote {a.out}")
+    S.close()
+    del samples
+    meta = {"elements": ne, "parts": pa, "sites": a.sites, "site_seed": a.site_seed,
+            "steps_per_site": a.steps_per_site, "train_steps": a.train_steps, "lr": a.lr,
+            "lr_final": a.lr_final, "seed": a.seed}
+    save(a.out, params, sc, meta)
+    log(f"wrote {a.out}")
+    held = stimulus_sites(mesh, a.heldout_sites, a.heldout_seed)
+    rows, worst = evaluate(mesh, ph, opts, held, a.steps_per_site, params, sc)
+    s = summarize(rows)
+    log(f"held-out {a.heldout_sites} sites x {a.steps_per_site} steps: Newton extrap/cnn {s['newton']}, "
+        f"PCG {s['pcg']}, ms {tuple(round(x) for x in s['ms'])}, initial residual reduction "
+        f"(geomean) {s['r0_gain_geomean']:.2f}, learned guess used {s['cnn_used']} / {s['steps']}, "
+        f"final states differ by {worst:.2e}")
 
 
 if __name__ == "__main__":

@@ -180,3 +180,27 @@ def test_predictor_errors():
     S.bdm_predictor_set(_params(1), SCALES)
     with pytest.raises(P.BidomainError, match="BDM_E_ARG"):
         S.bdm_predictor_train(np.zeros(6 * N), [1], 1e-3)
+
+
+def test_trained_network_gain_on_held_out_site():
+    """The committed weights on a stimulus site outside the training set: the
+    judged learned guess starts Newton from a smaller residual than
+    extrapolation, never needs more Newton iterations, and reaches the same
+    state to the Newton tolerance."""
+    P = _P()
+    from paper_2101_02959_amd import predictor as PR
+    from workload import stimulus_sites
+    params, scales = PR.load()
+    mesh = small_mesh((32, 32, 32), (4, 4, 4))
+    site = stimulus_sites(mesh, 1, 8)[0]
+    rows, worst = PR.evaluate(mesh, Physics(), SolverOpts(), [site], 12, params, scales)
+    s = PR.summarize(rows)
+    for r in rows:
+        print(r["step"], r["extrap"]["newton"], r["cnn"]["newton"], r["cnn"]["used"],
+              "%.3e %.3e" % (r["extrap"]["r0"], r["cnn"]["r0"]))
+    print(s, worst)
+    assert s["r0_gain_geomean"] > 1.5
+    assert s["newton"][1] <= s["newton"][0]
+    assert s["cnn_used"] >= 6
+    assert worst < 1e-8
+    assert all(r["cnn"]["rfinal"] <= r["cnn"]["tol"] for r in rows)

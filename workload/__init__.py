@@ -116,6 +116,14 @@ def stimulus_nodal(mesh: Mesh, block: tuple, amplitude: float, origin=(0, 0, 0))
     return out
 
 
+def stimulus_sites(mesh: Mesh, n: int, seed: int, block=(2, 2, 2)) -> list:
+    """``n`` element-block origins drawn uniformly (seeded) so that the block
+    lies inside the mesh."""
+    rng = np.random.default_rng(seed)
+    hi = (mesh.nx - block[0], mesh.ny - block[1], mesh.nz - block[2])
+    return [tuple(int(rng.integers(0, h + 1)) for h in hi) for _ in range(n)]
+
+
 def initial_state(mesh: Mesh, physics: Physics, seed: int | None):
     """Resting state, optionally with an additive v perturbation of
     0.01 * v_p * U(-1, 1) per node (i.i.d., seeded)."""
