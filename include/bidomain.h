@@ -221,14 +221,27 @@ int bdm_predictor_train(bdm_ctx* ctx, const double* samples, int nsamples, const
  *                             reaction diagonal; write both outputs)
  *   BDM_KERNEL_TRSV_DIRICHLET one forward Dirichlet solve L_II y = b over all
  *                             subdomains; bytes = lower triangles + vectors
- *   BDM_KERNEL_POTRF_INTERIOR interior elimination (partial Cholesky of the
- *                             local matrices through the interior columns) of
- *                             the first setup chunk; flops = sum over those
- *                             subdomains and eliminated columns j of
- *                             (n-j-1) + (n-j-1)(n-j)
- * The local matrices of the first chunk are reassembled before each timed
- * launch (untimed); the preconditioner factors are left intact. */
-enum { BDM_KERNEL_JACOBIAN = 0, BDM_KERNEL_TRSV_DIRICHLET = 1, BDM_KERNEL_POTRF_INTERIOR = 2 };
+ *   BDM_KERNEL_POTRF_INTERIOR the panel kernel of the interior elimination
+ *                             (partial Cholesky through the interior columns,
+ *                             right looking in 128-column panels, Sec. 4.1)
+ *                             on the first setup chunk: all its launches of
+ *                             one elimination; flops = divisions plus 2 per
+ *                             entry updated inside the panels
+ *   BDM_KERNEL_SYRK_UPDATE    the batched rank-k update kernel of the same
+ *                             elimination: the trailing updates right of each
+ *                             panel and the Schur update S_Gamma = K_GG -
+ *                             L_GI L_GI^T; flops = 2 per updated entry per
+ *                             inner index (lower triangles only)
+ * For these two, avg_ms is the summed duration of the kernel's launches in
+ * one elimination, averaged over reps; the local matrices of the chunk are
+ * reassembled before each elimination (untimed); the preconditioner factors
+ * are left intact.  BDM_E_ARG for another id. */
+enum {
+    BDM_KERNEL_JACOBIAN = 0,
+    BDM_KERNEL_TRSV_DIRICHLET = 1,
+    BDM_KERNEL_POTRF_INTERIOR = 2,
+    BDM_KERNEL_SYRK_UPDATE = 3
+};
 int bdm_profile_kernel(bdm_ctx* ctx, int kernel, int reps, double* avg_ms, double* work);
 
 /* Sizes for callers that allocate vectors: N, number of subdomains, global

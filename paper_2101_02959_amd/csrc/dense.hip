@@ -165,18 +165,15 @@ __device__ void syrk_update(T* __restrict__ A, int64_t ld, int cb, int ce, int r
 }
 
 // Right-looking blocked Cholesky of columns [c0, c1) of a symmetric matrix
-// (lower triangle), with the trailing update applied to rows/cols < c2.
-// After eliminating the interior block the trailing block holds the Schur
-// complement K_GG - K_GI K_II^{-1} K_IG (Sec. 4.1).
+// (lower triangle).  Rows [c1, c2) below the eliminated block receive the
+// panel L_GI = K_GI L_II^{-T}; the trailing updates stop at column c1, so the
+// block [c1, c2)^2 is left untouched: k_syrk_schur turns it into the Schur
+// complement K_GG - L_GI L_GI^T = K_GG - K_GI K_II^{-1} K_IG (Sec. 4.1) in one
+// pass with the full inner dimension.
 template <typename T>
-__device__ __forceinline__ void potrf_body(T* __restrict__ Abase, const int64_t* __restrict__ off,
-                                           const int* __restrict__ ldv, const int* __restrict__ c0v,
-                                           const int* __restrict__ c1v, const int* __restrict__ c2v,
+__device__ __forceinline__ void potrf_body(T* __restrict__ A, int64_t ld, int cbeg, int cend, int c2,
                                            int* __restrict__ info) {
     const int s = blockIdx.x;
-    T* A = Abase + off[s];
-    const int64_t ld = ldv[s];
-    const int cbeg = c0v[s], cend = c1v[s], c2 = c2v[s];
     const int tid = threadIdx.x;
     const int wv = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
     __shared__ T D[NB][NB + 1];     // diagonal block, then its Cholesky factor
@@ -258,7 +255,7 @@ __device__ __forceinline__ void potrf_body(T* __restrict__ Abase, const int64_t*
         if (t0 < pend) {
             syrk_update<T>(A, ld, t0, pend, c2, j0, j0 + jb);
         } else {
-            syrk_update<T>(A, ld, t0, c2, c2, p0, pend);
+            syrk_update<T>(A, ld, t0, cend, c2, p0, pend);
             p0 = pend;
         }
         __syncthreads();
@@ -266,21 +263,138 @@ __device__ __forceinline__ void potrf_body(T* __restrict__ Abase, const int64_t*
     if (tid == 0 && bad) info[s] = 1;
 }
 
-// Two entry points with distinct names so profiles separate the interior
-// elimination (Dirichlet factor + Schur complement) from the other factors.
-template <typename T>
-__global__ __launch_bounds__(kWG) void k_potrf_interior(T* __restrict__ A, const int64_t* __restrict__ off,
-                                                       const int* __restrict__ ld, const int* __restrict__ c0,
-                                                       const int* __restrict__ c1, const int* __restrict__ c2,
-                                                       int* __restrict__ info) {
-    potrf_body<T>(A, off, ld, c0, c1, c2, info);
-}
+// Factorisation of the local matrices' constrained Neumann block (columns
+// [c0, c1), trailing update within them).
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_potrf(T* __restrict__ A, const int64_t* __restrict__ off,
                                               const int* __restrict__ ld, const int* __restrict__ c0,
                                               const int* __restrict__ c1, const int* __restrict__ c2,
                                               int* __restrict__ info) {
-    potrf_body<T>(A, off, ld, c0, c1, c2, info);
+    const int s = blockIdx.x;
+    potrf_body<T>(A + off[s], ld[s], c0[s], c1[s], c2[s], info);
+}
+
+// One panel of the interior elimination: columns [J, min(J + NBO, nI)) of
+// every local matrix, rows down to n (the K_II rows and the L_GI rows).  The
+// update of the columns to the right of the panel is left to k_syrk_batched.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_potrf_interior(T* __restrict__ A, const int64_t* __restrict__ off,
+                                                       const int* __restrict__ ld, const int* __restrict__ nIv,
+                                                       const int* __restrict__ nv, int J, int* __restrict__ info) {
+    const int s = blockIdx.x;
+    const int nI = nIv[s];
+    if (J >= nI) return;
+    potrf_body<T>(A + off[s], ld[s], J, min(J + NBO, nI), nv[s], info);
+}
+
+// Batched symmetric rank-k update C -= P P^T of a lower trapezoid of every
+// local matrix: columns [cb, ce), rows [cb, re), lower part (row >= column),
+// P = A[:, k0:k1).  Two uses, selected by mode:
+//   SY_TRAIL  after the interior panel [J, J + NBO): cb = J + NBO, ce = nI,
+//             re = n, k = the panel (K_II trailing block and the L_GI rows);
+//   SY_SCHUR  after the last panel: cb = nI, ce = re = n, k = [0, nI), which
+//             turns K_GG into S_Gamma = K_GG - L_GI L_GI^T (Sec. 4.1).
+// 128x128 output tiles per workgroup (64x64 per wave, 4x4 MFMA 16x16x4
+// blocks), the inner dimension staged through LDS in chunks of 16 columns
+// with a register prefetch of the next chunk.  The workgroup id is mapped so
+// that all tiles of one subdomain run on the same XCD (dispatch assigns
+// consecutive ids round robin to the 8 XCDs), which keeps P in that XCD's L2.
+constexpr int SY_TM = 128, SY_KC = 16, SY_LS = SY_TM + 16, SY_XCD = 8;
+constexpr int SY_TRAIL = 0, SY_SCHUR = 1;
+
+__host__ __device__ inline int trapezoid_tiles(int cb, int ce, int re) {
+    if (ce <= cb || re <= cb) return 0;
+    const int nct = (ce - cb + SY_TM - 1) / SY_TM, nrt = (re - cb + SY_TM - 1) / SY_TM;
+    return nct * nrt - nct * (nct - 1) / 2;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, const int64_t* __restrict__ off,
+                                                      const int* __restrict__ ldv, const int* __restrict__ nIv,
+                                                      const int* __restrict__ nv, int nsub, int tiles, int mode,
+                                                      int J) {
+    __shared__ T As[SY_KC][SY_LS];    // P rows of the output tile's rows (i)
+    __shared__ T Bs[SY_KC][SY_LS];    // P rows of the output tile's columns (j)
+    const int g = blockIdx.x;
+    const int q = g / SY_XCD;
+    const int s = (q / tiles) * SY_XCD + g % SY_XCD;
+    int tile = q % tiles;
+    if (s >= nsub) return;
+    T* A = Abase + off[s];
+    const int64_t ld = ldv[s];
+    const int nI = nIv[s], n = nv[s];
+    int cb, ce, re, k0, k1;
+    if (mode == SY_SCHUR) {
+        cb = nI; ce = n; re = n; k0 = 0; k1 = nI;
+    } else {
+        cb = J + NBO; ce = nI; re = n; k0 = J; k1 = min(J + NBO, nI);
+    }
+    if (k1 <= k0 || tile >= trapezoid_tiles(cb, ce, re)) return;
+    const int nrt = (re - cb + SY_TM - 1) / SY_TM;
+    int tj = 0;
+    while (tile >= nrt - tj) { tile -= nrt - tj; ++tj; }
+    const int ti = tj + tile;
+    const int I0 = cb + ti * SY_TM, J0 = cb + tj * SY_TM;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+    const int wr = wv & 1, wc = wv >> 1;                 // wave's 64x64 quadrant (rows i, cols j)
+    const bool active = !(ti == tj && wr < wc);          // strictly upper quadrant of a diagonal tile
+    // each thread stages 8 elements of each operand per chunk: row tid % 128, k = tid / 128 + 2 e
+    const int lrow = tid % SY_TM, lk0 = tid / SY_TM;
+    const int ri = I0 + lrow, rj = J0 + lrow;
+    T pa[8], pb[8];
+    auto fetch = [&](int kc) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = kc + lk0 + 2 * e;
+            const bool kin = k < k1;
+            pa[e] = (kin && ri < re) ? A[ri + (int64_t)k * ld] : (T)0;
+            pb[e] = (kin && rj < ce) ? A[rj + (int64_t)k * ld] : (T)0;
+        }
+    };
+    typename Mfma<T>::acc acc[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) acc[b][a] = (typename Mfma<T>::acc){0, 0, 0, 0};
+    fetch(k0);
+    for (int kc = k0; kc < k1; kc += SY_KC) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            As[lk0 + 2 * e][lrow] = pa[e];
+            Bs[lk0 + 2 * e][lrow] = pb[e];
+        }
+        __syncthreads();
+        if (kc + SY_KC < k1) fetch(kc + SY_KC);
+        if (active) {
+#pragma unroll
+            for (int kk = 0; kk < SY_KC; kk += 4) {
+                T fa[4], fb[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) fa[a] = As[kk + lk][wr * 64 + 16 * a + lr];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) fb[b] = Bs[kk + lk][wc * 64 + 16 * b + lr];
+                // output row index = j (A operand), column index = i (B operand), so
+                // that the 16 lanes of an accumulator row hold consecutive i
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) acc[b][a] = Mfma<T>::mac(fb[b], fa[a], acc[b][a]);
+            }
+        }
+    }
+    if (!active) return;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int i = I0 + wr * 64 + 16 * a + lr;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int j = J0 + wc * 64 + 16 * b + Mfma<T>::row(lane, v);
+                if (i < re && j < ce && j <= i) A[i + (int64_t)j * ld] -= acc[b][a][v];
+            }
+        }
 }
 
 // ------------------------------------------------------------- extraction
@@ -695,11 +809,25 @@ void launch_assemble(hipStream_t s, const BatchDesc& d, int maxbox, const FEPara
 }
 template <typename T>
 void launch_potrf(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* c0,
-                  const int* c1, const int* c2, int* info, bool interior) {
-    if (interior)
-        hipLaunchKernelGGL(k_potrf_interior<T>, dim3(nb), dim3(kWG), 0, s, A, off, ld, c0, c1, c2, info);
-    else
-        hipLaunchKernelGGL(k_potrf<T>, dim3(nb), dim3(kWG), 0, s, A, off, ld, c0, c1, c2, info);
+                  const int* c1, const int* c2, int* info) {
+    hipLaunchKernelGGL(k_potrf<T>, dim3(nb), dim3(kWG), 0, s, A, off, ld, c0, c1, c2, info);
+}
+template <typename T>
+void launch_potrf_interior_panel(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* nI,
+                                 const int* n, int J, int* info) {
+    hipLaunchKernelGGL(k_potrf_interior<T>, dim3(nb), dim3(kWG), 0, s, A, off, ld, nI, n, J, info);
+}
+template <typename T>
+void launch_syrk_update(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* nI, const int* n,
+                        bool schur, int J, int tiles) {
+    if (nb <= 0 || tiles <= 0) return;
+    const int groups = (nb + SY_XCD - 1) / SY_XCD;
+    hipLaunchKernelGGL(k_syrk_batched<T>, dim3(groups * tiles * SY_XCD), dim3(kWG), 0, s, A, off, ld, nI, n, nb,
+                       tiles, schur ? SY_SCHUR : SY_TRAIL, J);
+}
+int interior_panel_width() { return NBO; }
+int syrk_tiles(bool schur, int J, int nI, int n) {
+    return schur ? trapezoid_tiles(nI, n, n) : (J < nI ? trapezoid_tiles(J + NBO, nI, n) : 0);
 }
 template <typename T>
 void launch_extract(hipStream_t s, const BatchDesc& d, const T* K, T* slots, T* F, double* Svv, T* Srr) {
@@ -737,7 +865,11 @@ void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, const T* slots, T* fac
     template void launch_assemble<T>(hipStream_t, const BatchDesc&, int, const FEParams&, const double*, \
                                      const double*, const double*, T*);                                \
     template void launch_potrf<T>(hipStream_t, int, T*, const int64_t*, const int*, const int*,         \
-                                  const int*, const int*, int*, bool);                                   \
+                                  const int*, const int*, int*);                                         \
+    template void launch_potrf_interior_panel<T>(hipStream_t, int, T*, const int64_t*, const int*,      \
+                                                 const int*, const int*, int, int*);                     \
+    template void launch_syrk_update<T>(hipStream_t, int, T*, const int64_t*, const int*, const int*,    \
+                                        const int*, bool, int, int);                                     \
     template void launch_extract<T>(hipStream_t, const BatchDesc&, const T*, T*, T*, double*, T*);      \
     template void launch_copy_out<T>(hipStream_t, const BatchDesc&, int, const T*, T*, const int64_t*, T*,    \
                                      const int64_t*);                                                    \

@@ -167,6 +167,8 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
         box[6 * q + 0] = sb.ex0; box[6 * q + 1] = sb.ey0; box[6 * q + 2] = sb.ez0;
         box[6 * q + 3] = sb.Lx(); box[6 * q + 4] = sb.Ly(); box[6 * q + 5] = sb.Lz();
         maxbox_ = std::max(maxbox_, (sb.Lx() + 1) * (sb.Ly() + 1) * (sb.Lz() + 1));
+        maxG_ = std::max(maxG_, sb.n() - sb.nI);
+        maxnI_ = std::max(maxnI_, sb.nI);
         lmap_off[q] = (int64_t)lmap.size();
         lmap.insert(lmap.end(), sb.lmap.begin(), sb.lmap.end());
         K_off[q] = accK; accK += (int64_t)sb.n() * sb.n();
@@ -222,6 +224,15 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
         }
         (void)maxsz;
         Kc_off_ = upload(kc);
+        // launch sizes of the interior elimination (tiles per subdomain, max over the batch)
+        const int wp = interior_panel_width();
+        trail_tiles_.assign((maxnI_ + wp - 1) / wp, 0);
+        schur_tiles_ = 0;
+        for (const auto& sb : topo.subs) {
+            for (size_t q = 0; q < trail_tiles_.size(); ++q)
+                trail_tiles_[q] = std::max(trail_tiles_[q], syrk_tiles(false, (int)q * wp, sb.nI, sb.n()));
+            schur_tiles_ = std::max(schur_tiles_, syrk_tiles(true, 0, sb.nI, sb.n()));
+        }
     }
     nInodes_ = (int)Ilist.size();
 
@@ -545,6 +556,52 @@ int Context::linearize(const double* v, const double* w) {
     return rc;
 }
 
+// Interior elimination of the local matrices of one chunk (Sec. 4.1): L_II,
+// the panel L_GI and the Schur complement S_Gamma in the trailing block.
+// Right looking in panels; with timing events, the durations of the panel
+// kernel and of the update kernel are added to tm[0] and tm[1] (ms).
+template <typename T>
+int Context::eliminate_interior(T* K, int s0, int cnt, double* tm) {
+    const int w = interior_panel_width();
+    hipEvent_t ev[3];
+    if (tm)
+        for (auto& e : ev) HIPOK(hipEventCreate(&e));
+    auto mark = [&](int q) -> int {
+        if (tm) HIPOK(hipEventRecord(ev[q], stream_));
+        return 0;
+    };
+    auto lap = [&](int a, int b, double& acc) -> int {
+        if (!tm) return 0;
+        HIPOK(hipEventSynchronize(ev[b]));
+        float ms = 0.f;
+        HIPOK(hipEventElapsedTime(&ms, ev[a], ev[b]));
+        acc += ms;
+        return 0;
+    };
+    for (int q = 0; q * w < maxnI_; ++q) {
+        const int J = q * w;
+        mark(0);
+        launch_potrf_interior_panel<T>(stream_, cnt, K, Kc_off_ + s0, ld_ + s0, st1c1_ + s0, st1c2_ + s0, J,
+                                       info_sub_ + s0);
+        mark(1);
+        launch_syrk_update<T>(stream_, cnt, K, Kc_off_ + s0, ld_ + s0, st1c1_ + s0, st1c2_ + s0, false, J,
+                              trail_tiles_[q]);
+        mark(2);
+        if (tm) {
+            lap(0, 1, tm[0]);
+            lap(1, 2, tm[1]);
+        }
+    }
+    mark(0);
+    launch_syrk_update<T>(stream_, cnt, K, Kc_off_ + s0, ld_ + s0, st1c1_ + s0, st1c2_ + s0, true, 0, schur_tiles_);
+    mark(1);
+    if (tm) {
+        lap(0, 1, tm[1]);
+        for (auto& e : ev) hipEventDestroy(e);
+    }
+    return 0;
+}
+
 template <typename T>
 int Context::linearize_t() {
     const int nsub = (int)topo.subs.size();
@@ -564,8 +621,7 @@ int Context::linearize_t() {
         HIPOK(hipMemsetAsync(K, 0, nKwork_ * sizeof(T), stream_));
         launch_assemble<T>(stream_, cd, maxbox_, fp, ke_, vlin_, wlin_, K);
         // interior elimination: L_II, and S_Gamma in the trailing block
-        launch_potrf<T>(stream_, cnt, K, Kc_off_ + s0, ld_ + s0, st1c0_ + s0, st1c1_ + s0, st1c2_ + s0,
-                        info_sub_ + s0, true);
+        eliminate_interior<T>(K, s0, cnt, nullptr);
         launch_extract<T>(stream_, cd, K, (T*)slots_, (T*)F_, Svv_, (T*)Srr_);
         // constrained Neumann factor L_rr of S_rr
         launch_potrf<T>(stream_, cnt, K, Kc_off_ + s0, ld_ + s0, st1c1_ + s0, st2c1_ + s0, st2c1_ + s0,
@@ -800,7 +856,7 @@ int Context::profile_kernel(int kernel, int reps, double* avg_ms, double* work) 
         set_error("bdm_profile_kernel before bdm_linearize");
         return BDM_E_STATE;
     }
-    if (reps < 1 || kernel < 0 || kernel > 2) {
+    if (reps < 1 || kernel < 0 || kernel > BDM_KERNEL_SYRK_UPDATE) {
         set_error("bdm_profile_kernel: bad kernel id or reps");
         return BDM_E_ARG;
     }
@@ -823,29 +879,46 @@ int Context::profile_t(int kernel, int reps, double* avg_ms, double* work) {
     } else if (kernel == BDM_KERNEL_TRSV_DIRICHLET) {
         for (const auto& sb : topo.subs) w += (0.5 * sb.nI * (sb.nI + 1.0) + 2.0 * sb.nI) * sizeof(T);
     } else {
+        // interior elimination flops: the panel kernel (divisions and the
+        // updates inside each panel) and the update kernel (trailing updates
+        // right of each panel and the Schur update), 2 flops per updated entry
+        const int wp = interior_panel_width();
+        auto tri = [](double c0, double c1, double n) {     // sum over columns [c0, c1) of (n - c)
+            const double m = c1 - c0;
+            return m > 0 ? m * n - (c0 + c1 - 1) * m / 2.0 : 0.0;
+        };
         for (int q = s0; q < s0 + cnt; ++q) {
-            const double n = topo.subs[q].n();
-            for (int j = 0; j < topo.subs[q].nI; ++j) w += (n - j - 1) + (n - j - 1) * (n - j);
+            const double n = topo.subs[q].n(), nI = topo.subs[q].nI;
+            double wpanel = 0, wupd = 0;
+            for (int J = 0; J < nI; J += wp) {
+                const double pe = std::min<double>(J + wp, nI);
+                for (int j = J; j < pe; ++j) wpanel += (n - j - 1) + 2.0 * tri(j + 1, pe, n);
+                wupd += 2.0 * (pe - J) * tri(J + wp, nI, n);
+            }
+            wupd += nI * (n - nI) * (n - nI + 1.0);
+            w += (kernel == BDM_KERNEL_POTRF_INTERIOR) ? wpanel : wupd;
         }
     }
     for (int r = 0; r < reps; ++r) {
-        if (kernel == BDM_KERNEL_POTRF_INTERIOR) {
+        if (kernel == BDM_KERNEL_JACOBIAN || kernel == BDM_KERNEL_TRSV_DIRICHLET) {
+            HIPOK(hipEventRecord(e0, stream_));
+            if (kernel == BDM_KERNEL_JACOBIAN)
+                launch_jac_apply(stream_, fp, st_, dg_, kp_, kq_);
+            else
+                launch_trsv<T>(stream_, nsub, false, (const T*)LIIs_, LII_off_, nI_, nI_, (T*)xI_, xI_off_);
+            HIPOK(hipEventRecord(e1, stream_));
+            HIPOK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPOK(hipEventElapsedTime(&ms, e0, e1));
+            total += ms;
+        } else {
             HIPOK(hipMemsetAsync(K_, 0, nKwork_ * sizeof(T), stream_));
             launch_assemble<T>(stream_, cd, maxbox_, fp, ke_, vlin_, wlin_, (T*)K_);
+            double tm[2] = {0.0, 0.0};
+            int rc = eliminate_interior<T>((T*)K_, s0, cnt, tm);
+            if (rc) return rc;
+            total += (kernel == BDM_KERNEL_POTRF_INTERIOR) ? tm[0] : tm[1];
         }
-        HIPOK(hipEventRecord(e0, stream_));
-        if (kernel == BDM_KERNEL_JACOBIAN)
-            launch_jac_apply(stream_, fp, st_, dg_, kp_, kq_);
-        else if (kernel == BDM_KERNEL_TRSV_DIRICHLET)
-            launch_trsv<T>(stream_, nsub, false, (const T*)LIIs_, LII_off_, nI_, nI_, (T*)xI_, xI_off_);
-        else
-            launch_potrf<T>(stream_, cnt, (T*)K_, Kc_off_ + s0, ld_ + s0, st1c0_ + s0, st1c1_ + s0, st1c2_ + s0,
-                            info_sub_ + s0, true);
-        HIPOK(hipEventRecord(e1, stream_));
-        HIPOK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPOK(hipEventElapsedTime(&ms, e0, e1));
-        total += ms;
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);

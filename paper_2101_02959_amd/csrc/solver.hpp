@@ -40,6 +40,8 @@ class Context {
     int fetidp_apply(int op, const double* in, double* out);
     int step(int nsteps, bdm_step_stats* st);
     int profile_kernel(int kernel, int reps, double* avg_ms, double* work);
+    template <typename T>
+    int eliminate_interior(T* K, int s0, int cnt, double* tm);
     int predictor_set(const float* params, const double* scales);
     int predictor_get(float* params, double* scales);
     int predictor_guess(const double* vn, const double* uen, const double* vp, const double* uep, double* out);
@@ -108,7 +110,9 @@ class Context {
     SubVecDesc sv_{};
     CoarseDesc cd_{};
     FetiDesc fd_{};
-    int maxbox_ = 0, nInodes_ = 0;
+    int maxbox_ = 0, maxG_ = 0, maxnI_ = 0, nInodes_ = 0;
+    std::vector<int> trail_tiles_;
+    int schur_tiles_ = 0;
     int *Ilist_ = nullptr;
     int64_t *LII_off_ = nullptr, *Lrr_off_ = nullptr, *xI_off_ = nullptr, *xr_off_ = nullptr;
     const int64_t *Srr_off_ = nullptr;
