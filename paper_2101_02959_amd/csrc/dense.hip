@@ -8,6 +8,7 @@
 // One workgroup owns one matrix; matrices are column-major with a per-matrix
 // leading dimension.  Templates are instantiated for double (plain path) and
 // float (local factors in FP32 under the FP64 outer iteration).
+#include <algorithm>
 #include <cmath>
 
 #include "common.hpp"
@@ -172,7 +173,7 @@ __device__ void syrk_update(T* __restrict__ A, int64_t ld, int cb, int ce, int r
 // pass with the full inner dimension.
 template <typename T>
 __device__ __forceinline__ void potrf_body(T* __restrict__ A, int64_t ld, int cbeg, int cend, int c2,
-                                           int* __restrict__ info) {
+                                           int* __restrict__ info, T* __restrict__ Wout = nullptr) {
     const int s = blockIdx.x;
     const int tid = threadIdx.x;
     const int wv = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
@@ -220,6 +221,13 @@ __device__ __forceinline__ void potrf_body(T* __restrict__ A, int64_t ld, int cb
             if (j <= i) A[(j0 + i) + (j0 + j) * ld] = D[i][j];
         }
         __syncthreads();
+        if (Wout) {
+            T* Wb = Wout + (int64_t)((j0 - cbeg) / NB) * NB * NB;
+            for (int idx = tid; idx < NB * NB; idx += kWG) {
+                const int i = idx % NB, j = idx / NB;
+                Wb[i + j * NB] = (i < jb && j < jb) ? W[i][j] : (T)0;
+            }
+        }
         // 2. panel below the block: X = P W^T on MFMA, 16-row tiles per wave
         const int t0 = j0 + jb;
         const int nrt = (c2 - t0 + 15) / 16;
@@ -274,17 +282,99 @@ __global__ __launch_bounds__(kWG) void k_potrf(T* __restrict__ A, const int64_t*
     potrf_body<T>(A + off[s], ld[s], c0[s], c1[s], c2[s], info);
 }
 
-// One panel of the interior elimination: columns [J, min(J + NBO, nI)) of
-// every local matrix, rows down to n (the K_II rows and the L_GI rows).  The
-// update of the columns to the right of the panel is left to k_syrk_batched.
+// One panel of the interior elimination, columns [J, J + w), w = min(NBO,
+// nI - J), in two kernels:
+//  k_panel_diag  one workgroup per matrix factors the w x w diagonal block
+//                and stores the inverses W_b of its 32x32 diagonal factors;
+//  k_panel_trsm  the rows below, [J + w, n), in blocks of PT_RB rows per
+//                workgroup: X L_JJ^T = P by block forward substitution,
+//                X_b = (P_b - sum_{c<b} X_c L_bc^T) W_b^T, on MFMA.
+// The update of the columns right of the panel is left to k_syrk_batched.
+constexpr int PT_RB = 64, PT_XS = NBO + 4;
+
 template <typename T>
-__global__ __launch_bounds__(kWG) void k_potrf_interior(T* __restrict__ A, const int64_t* __restrict__ off,
-                                                       const int* __restrict__ ld, const int* __restrict__ nIv,
-                                                       const int* __restrict__ nv, int J, int* __restrict__ info) {
+__global__ __launch_bounds__(kWG) void k_panel_diag(T* __restrict__ A, const int64_t* __restrict__ off,
+                                                   const int* __restrict__ ld, const int* __restrict__ nIv, int J,
+                                                   T* __restrict__ Wbuf, int* __restrict__ info) {
     const int s = blockIdx.x;
     const int nI = nIv[s];
     if (J >= nI) return;
-    potrf_body<T>(A + off[s], ld[s], J, min(J + NBO, nI), nv[s], info);
+    const int w = min(NBO, nI - J);
+    potrf_body<T>(A + off[s], ld[s], J, J + w, J + w, info, Wbuf + (int64_t)s * NBO * NB);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_panel_trsm(T* __restrict__ Abase, const int64_t* __restrict__ off,
+                                                   const int* __restrict__ ldv, const int* __restrict__ nIv,
+                                                   const int* __restrict__ nv, int J, const T* __restrict__ Wbuf) {
+    __shared__ T Xs[PT_RB][PT_XS];
+    __shared__ T Ls[NB][NB + 1];
+    const int s = blockIdx.y;
+    const int nI = nIv[s], n = nv[s];
+    if (J >= nI) return;
+    const int w = min(NBO, nI - J);
+    const int R0 = J + w + blockIdx.x * PT_RB;
+    if (R0 >= n) return;
+    const int rows = min(PT_RB, n - R0);
+    T* A = Abase + off[s];
+    const int64_t ld = ldv[s];
+    const T* W = Wbuf + (int64_t)s * NBO * NB;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+    for (int idx = tid; idx < PT_RB * NBO; idx += kWG) {
+        const int r = idx % PT_RB, c = idx / PT_RB;
+        Xs[r][c] = (r < rows && c < w) ? A[(R0 + r) + (int64_t)(J + c) * ld] : (T)0;
+    }
+    const int nb = (w + NB - 1) / NB;
+    for (int b = 0; b < nb; ++b) {
+        typename Mfma<T>::acc acc[2];
+        acc[0] = (typename Mfma<T>::acc){0, 0, 0, 0};
+        acc[1] = acc[0];
+        // acc = sum_{c<b} X_c L_bc^T  (wave wv: rows 16 wv .. 16 wv + 15, 32 columns)
+        for (int c = 0; c < b; ++c) {
+            __syncthreads();
+            for (int idx = tid; idx < NB * NB; idx += kWG) {
+                const int i = idx % NB, j = idx / NB;   // L_bc[i][j] = L[J + 32 b + i][J + 32 c + j]
+                const int gi = NB * b + i, gj = NB * c + j;
+                Ls[i][j] = (gi < w && gj < w) ? A[(J + gi) + (int64_t)(J + gj) * ld] : (T)0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < NB; kk += 4) {
+                const T a = Xs[16 * wv + lr][NB * c + kk + lk];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) acc[h] = Mfma<T>::mac(a, Ls[16 * h + lr][kk + lk], acc[h]);
+            }
+        }
+        __syncthreads();
+        // Y_b = P_b - acc in place; then X_b = Y_b W_b^T
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Xs[16 * wv + Mfma<T>::row(lane, v)][NB * b + 16 * h + lr] -= acc[h][v];
+        for (int idx = tid; idx < NB * NB; idx += kWG) {
+            const int i = idx % NB, j = idx / NB;
+            Ls[i][j] = W[(int64_t)b * NB * NB + i + j * NB];
+        }
+        __syncthreads();
+        acc[0] = (typename Mfma<T>::acc){0, 0, 0, 0};
+        acc[1] = acc[0];
+#pragma unroll
+        for (int kk = 0; kk < NB; kk += 4) {
+            const T a = Xs[16 * wv + lr][NB * b + kk + lk];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) acc[h] = Mfma<T>::mac(a, Ls[16 * h + lr][kk + lk], acc[h]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Xs[16 * wv + Mfma<T>::row(lane, v)][NB * b + 16 * h + lr] = acc[h][v];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < PT_RB * NBO; idx += kWG) {
+        const int r = idx % PT_RB, c = idx / PT_RB;
+        if (r < rows && c < w) A[(R0 + r) + (int64_t)(J + c) * ld] = Xs[r][c];
+    }
 }
 
 // Batched symmetric rank-k update C -= P P^T of a lower trapezoid of every
@@ -813,9 +903,12 @@ void launch_potrf(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld
     hipLaunchKernelGGL(k_potrf<T>, dim3(nb), dim3(kWG), 0, s, A, off, ld, c0, c1, c2, info);
 }
 template <typename T>
-void launch_potrf_interior_panel(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* nI,
-                                 const int* n, int J, int* info) {
-    hipLaunchKernelGGL(k_potrf_interior<T>, dim3(nb), dim3(kWG), 0, s, A, off, ld, nI, n, J, info);
+void launch_interior_panel(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* nI,
+                           const int* n, int J, T* Wbuf, int rowblocks, int* info) {
+    if (nb <= 0) return;
+    hipLaunchKernelGGL(k_panel_diag<T>, dim3(nb), dim3(kWG), 0, s, A, off, ld, nI, J, Wbuf, info);
+    if (rowblocks > 0)
+        hipLaunchKernelGGL(k_panel_trsm<T>, dim3(rowblocks, nb), dim3(kWG), 0, s, A, off, ld, nI, n, J, Wbuf);
 }
 template <typename T>
 void launch_syrk_update(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* nI, const int* n,
@@ -826,6 +919,12 @@ void launch_syrk_update(hipStream_t s, int nb, T* A, const int64_t* off, const i
                        tiles, schur ? SY_SCHUR : SY_TRAIL, J);
 }
 int interior_panel_width() { return NBO; }
+int panel_wbuf_stride() { return NBO * NB; }
+int panel_rowblocks(int J, int nI, int n) {
+    if (J >= nI) return 0;
+    const int r0 = J + std::min(NBO, nI - J);
+    return r0 < n ? (n - r0 + PT_RB - 1) / PT_RB : 0;
+}
 int syrk_tiles(bool schur, int J, int nI, int n) {
     return schur ? trapezoid_tiles(nI, n, n) : (J < nI ? trapezoid_tiles(J + NBO, nI, n) : 0);
 }
@@ -866,8 +965,8 @@ void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, const T* slots, T* fac
                                      const double*, const double*, T*);                                \
     template void launch_potrf<T>(hipStream_t, int, T*, const int64_t*, const int*, const int*,         \
                                   const int*, const int*, int*);                                         \
-    template void launch_potrf_interior_panel<T>(hipStream_t, int, T*, const int64_t*, const int*,      \
-                                                 const int*, const int*, int, int*);                     \
+    template void launch_interior_panel<T>(hipStream_t, int, T*, const int64_t*, const int*, const int*, \
+                                           const int*, int, T*, int, int*);                              \
     template void launch_syrk_update<T>(hipStream_t, int, T*, const int64_t*, const int*, const int*,    \
                                         const int*, bool, int, int);                                     \
     template void launch_extract<T>(hipStream_t, const BatchDesc&, const T*, T*, T*, double*, T*);      \

@@ -60,16 +60,20 @@ template <typename T>
 void launch_potrf(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* c0,
                   const int* c1, const int* c2, int* info);
 // Interior elimination, right looking in panels of interior_panel_width()
-// columns: for J = 0, w, 2w, ...: the panel, then the trailing update
+// columns: for J = 0, w, 2w, ...: the panel (diagonal block, then the rows
+// below; Wbuf holds panel_wbuf_stride() values per matrix, rowblocks = max
+// over the batch of panel_rowblocks(...)), then the trailing update
 // (schur = false); finally the Schur update of the interface block
 // (schur = true).  tiles = max over the batch of syrk_tiles(...).
 template <typename T>
-void launch_potrf_interior_panel(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* nI,
-                                 const int* n, int J, int* info);
+void launch_interior_panel(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* nI,
+                           const int* n, int J, T* Wbuf, int rowblocks, int* info);
 template <typename T>
 void launch_syrk_update(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* nI, const int* n,
                         bool schur, int J, int tiles);
 int interior_panel_width();
+int panel_wbuf_stride();
+int panel_rowblocks(int J, int nI, int n);
 int syrk_tiles(bool schur, int J, int nI, int n);
 template <typename T>
 void launch_extract(hipStream_t s, const BatchDesc& d, const T* K, T* slots, T* F, double* Svv,

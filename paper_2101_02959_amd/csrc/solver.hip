@@ -227,10 +227,13 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
         // launch sizes of the interior elimination (tiles per subdomain, max over the batch)
         const int wp = interior_panel_width();
         trail_tiles_.assign((maxnI_ + wp - 1) / wp, 0);
+        panel_rows_.assign(trail_tiles_.size(), 0);
         schur_tiles_ = 0;
         for (const auto& sb : topo.subs) {
-            for (size_t q = 0; q < trail_tiles_.size(); ++q)
+            for (size_t q = 0; q < trail_tiles_.size(); ++q) {
                 trail_tiles_[q] = std::max(trail_tiles_[q], syrk_tiles(false, (int)q * wp, sb.nI, sb.n()));
+                panel_rows_[q] = std::max(panel_rows_[q], panel_rowblocks((int)q * wp, sb.nI, sb.n()));
+            }
             schur_tiles_ = std::max(schur_tiles_, syrk_tiles(true, 0, sb.nI, sb.n()));
         }
     }
@@ -438,6 +441,11 @@ int Context::alloc_local() {
     const int nsub = (int)topo.subs.size();
     const bool feti = opts.solver == BDM_SOLVER_FETIDP;
     K_ = dalloc(nKwork_ * sizeof(T));
+    {
+        int maxc = 1;
+        for (const auto& ch : chunks_) maxc = std::max(maxc, ch.second - ch.first);
+        Wbuf_ = dalloc((size_t)maxc * panel_wbuf_stride() * sizeof(T));
+    }
     LIIs_ = dalloc(nLII_ * sizeof(T));
     Lrrs_ = dalloc(nLrr_ * sizeof(T));
     slots_ = dalloc(nslot_ * sizeof(T));
@@ -481,7 +489,7 @@ int Context::alloc_local() {
     info_sub_ = (int*)dalloc(nsub * sizeof(int));
     info_obj_ = (int*)dalloc((size_t)od_.nobj * sizeof(int));
     info_c_ = (int*)dalloc(sizeof(int));
-    if (!K_ || !LIIs_ || !Lrrs_ || !slots_ || !inv_ || !dmat_ || !F_ || !Z_ || !Gi_ || !fac_ || (feti && !Srr_) || !xI_ || !xr_ ||
+    if (!K_ || !Wbuf_ || !LIIs_ || !Lrrs_ || !slots_ || !inv_ || !dmat_ || !F_ || !Z_ || !Gi_ || !fac_ || (feti && !Srr_) || !xI_ || !xr_ ||
         !xr2_ || !Svv_ || !Sp_ || !cP_ || !mu_ || !cb_ || !ybuf_ || !info_sub_ || !info_obj_ || !info_c_) {
         set_error("device allocation failed (local factors)");
         return BDM_E_OOM;
@@ -581,8 +589,8 @@ int Context::eliminate_interior(T* K, int s0, int cnt, double* tm) {
     for (int q = 0; q * w < maxnI_; ++q) {
         const int J = q * w;
         mark(0);
-        launch_potrf_interior_panel<T>(stream_, cnt, K, Kc_off_ + s0, ld_ + s0, st1c1_ + s0, st1c2_ + s0, J,
-                                       info_sub_ + s0);
+        launch_interior_panel<T>(stream_, cnt, K, Kc_off_ + s0, ld_ + s0, st1c1_ + s0, st1c2_ + s0, J, (T*)Wbuf_,
+                                 panel_rows_[q], info_sub_ + s0);
         mark(1);
         launch_syrk_update<T>(stream_, cnt, K, Kc_off_ + s0, ld_ + s0, st1c1_ + s0, st1c2_ + s0, false, J,
                               trail_tiles_[q]);

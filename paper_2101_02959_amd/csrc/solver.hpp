@@ -111,7 +111,8 @@ class Context {
     CoarseDesc cd_{};
     FetiDesc fd_{};
     int maxbox_ = 0, maxG_ = 0, maxnI_ = 0, nInodes_ = 0;
-    std::vector<int> trail_tiles_;
+    std::vector<int> trail_tiles_, panel_rows_;
+    void* Wbuf_ = nullptr;
     int schur_tiles_ = 0;
     int *Ilist_ = nullptr;
     int64_t *LII_off_ = nullptr, *Lrr_off_ = nullptr, *xI_off_ = nullptr, *xr_off_ = nullptr;
