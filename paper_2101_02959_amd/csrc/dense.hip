@@ -10,6 +10,7 @@
 // float (local factors in FP32 under the FP64 outer iteration).
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -441,11 +442,15 @@ __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, con
             pb[e] = (kin && rj < ce) ? A[rj + (int64_t)k * ld] : (T)0;
         }
     };
-    typename Mfma<T>::acc acc[4][4];
+    // FP32: each chunk of SY_KC products is summed on its own and then added
+    // to a running total, so rounding grows with the number of chunks plus
+    // the chunk length rather than with the whole inner dimension.
+    constexpr bool two_level = std::is_same<T, float>::value;
+    typename Mfma<T>::acc acc[4][4], tot[4][4];
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int a = 0; a < 4; ++a) acc[b][a] = (typename Mfma<T>::acc){0, 0, 0, 0};
+        for (int a = 0; a < 4; ++a) acc[b][a] = tot[b][a] = (typename Mfma<T>::acc){0, 0, 0, 0};
     fetch(k0);
     for (int kc = k0; kc < k1; kc += SY_KC) {
         __syncthreads();
@@ -471,6 +476,15 @@ __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, con
 #pragma unroll
                     for (int a = 0; a < 4; ++a) acc[b][a] = Mfma<T>::mac(fb[b], fa[a], acc[b][a]);
             }
+            if (two_level) {
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        tot[b][a] += acc[b][a];
+                        acc[b][a] = (typename Mfma<T>::acc){0, 0, 0, 0};
+                    }
+            }
         }
     }
     if (!active) return;
@@ -482,7 +496,8 @@ __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, con
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int j = J0 + wc * 64 + 16 * b + Mfma<T>::row(lane, v);
-                if (i < re && j < ce && j <= i) A[i + (int64_t)j * ld] -= acc[b][a][v];
+                const T upd = two_level ? tot[b][a][v] : acc[b][a][v];
+                if (i < re && j < ce && j <= i) A[i + (int64_t)j * ld] -= upd;
             }
         }
 }
@@ -721,11 +736,13 @@ __global__ __launch_bounds__(kWG) void k_coarse_local(BatchDesc d, const T* __re
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_trsv_fwd(const T* __restrict__ Lb, const int64_t* __restrict__ Loff,
                                                  const int* __restrict__ nv, const int* __restrict__ ldv,
-                                                 T* __restrict__ xb, const int64_t* __restrict__ xoff) {
+                                                 T* __restrict__ xb, const int64_t* __restrict__ xoff,
+                                                 const int* __restrict__ mv) {
     const int s = blockIdx.x;
     const T* L = Lb + Loff[s];
     T* x = xb + xoff[s];
     const int n = nv[s];
+    const int m = mv ? mv[s] : n;   // rows: [n, m) receive x_r -= L_r,0:n y
     const int64_t ld = ldv[s];
     const int tid = threadIdx.x, lane = tid & 63;
     __shared__ T D[NB][NB + 1];
@@ -749,7 +766,7 @@ __global__ __launch_bounds__(kWG) void k_trsv_fwd(const T* __restrict__ Lb, cons
             if (lane < jb) x[j0 + lane] = xv;
         }
         __syncthreads();
-        for (int r = j0 + jb + tid; r < n; r += kWG) {
+        for (int r = j0 + jb + tid; r < m; r += kWG) {
             // branch-free, fully unrolled so all column loads are in flight together
             T lv[NB];
 #pragma unroll
@@ -766,11 +783,13 @@ __global__ __launch_bounds__(kWG) void k_trsv_fwd(const T* __restrict__ Lb, cons
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_trsv_bwd(const T* __restrict__ Lb, const int64_t* __restrict__ Loff,
                                                  const int* __restrict__ nv, const int* __restrict__ ldv,
-                                                 T* __restrict__ xb, const int64_t* __restrict__ xoff) {
+                                                 T* __restrict__ xb, const int64_t* __restrict__ xoff,
+                                                 const int* __restrict__ mv) {
     const int s = blockIdx.x;
     const T* L = Lb + Loff[s];
     T* x = xb + xoff[s];
     const int n = nv[s];
+    const int m = mv ? mv[s] : n;   // known values x_[n, m) enter as x_0:n -= L_[n,m),0:n^T x_[n,m)
     const int64_t ld = ldv[s];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     __shared__ T red[kWG / 64][NB];
@@ -785,7 +804,7 @@ __global__ __launch_bounds__(kWG) void k_trsv_bwd(const T* __restrict__ Lb, cons
         T acc[NB];
 #pragma unroll
         for (int c = 0; c < NB; ++c) acc[c] = (T)0;
-        for (int r = j0 + jb + tid; r < n; r += kWG) {
+        for (int r = j0 + jb + tid; r < m; r += kWG) {
             const T xr = x[r];
             T lv[NB];
 #pragma unroll
@@ -949,11 +968,12 @@ void launch_coarse_local(hipStream_t s, const BatchDesc& d, const T* F, const do
 }
 template <typename T>
 void launch_trsv(hipStream_t s, int nb, bool trans, const T* L, const int64_t* Loff, const int* n,
-                 const int* ld, T* x, const int64_t* xoff) {
+                 const int* ld, T* x, const int64_t* xoff, const int* rows) {
+    if (nb <= 0) return;
     if (trans)
-        hipLaunchKernelGGL(k_trsv_bwd<T>, dim3(nb), dim3(kWG), 0, s, L, Loff, n, ld, x, xoff);
+        hipLaunchKernelGGL(k_trsv_bwd<T>, dim3(nb), dim3(kWG), 0, s, L, Loff, n, ld, x, xoff, rows);
     else
-        hipLaunchKernelGGL(k_trsv_fwd<T>, dim3(nb), dim3(kWG), 0, s, L, Loff, n, ld, x, xoff);
+        hipLaunchKernelGGL(k_trsv_fwd<T>, dim3(nb), dim3(kWG), 0, s, L, Loff, n, ld, x, xoff, rows);
 }
 template <typename T>
 void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, const T* slots, T* fac, T* inv, T* dmat, int* info) {
@@ -977,7 +997,7 @@ void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, const T* slots, T* fac
     template void launch_coarse_local<T>(hipStream_t, const BatchDesc&, const T*, const double*, T*, T*, \
                                          double*, int*);                                                 \
     template void launch_trsv<T>(hipStream_t, int, bool, const T*, const int64_t*, const int*,          \
-                                 const int*, T*, const int64_t*);                                        \
+                                 const int*, T*, const int64_t*, const int*);                            \
     template void launch_deluxe_setup<T>(hipStream_t, const ObjDesc&, const T*, T*, T*, T*, int*);
 BDM_INST(double)
 BDM_INST(float)

@@ -19,6 +19,14 @@ thread_local std::string g_err;
 
 constexpr int MAXC = 24, MAXV = 16, MAXP = 40;
 constexpr int SVV_STRIDE = MAXV * MAXV, GI_STRIDE = MAXC * MAXC, SP_STRIDE = MAXP * MAXP;
+
+// Device allocation recorded in the context list c (freed with the context).
+static void* ctx_alloc(void* c, size_t bytes) {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes ? bytes : 8) != hipSuccess) return nullptr;
+    static_cast<std::vector<void*>*>(c)->push_back(p);
+    return p;
+}
 constexpr int MAXOBJ = 512;
 
 template <typename T>
@@ -364,50 +372,12 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
     one_ = upload(npv);
     // pin: the u_e dof of the first vertex (or of the first edge average)
     pin_ = 1;
-    // coarse groups: position along x of each primal object (cut a -> 2a-1,
-    // slab a -> 2a), pairs (cut a, slab a) form group a; consecutive groups are
-    // merged up to a minimum block size.
+    // coarse problem: nested dissection of the subdomain grid
     {
-        std::vector<char> xcut(topo.nx + 1, 0);
-        for (int a = 1; a < topo.px; ++a) xcut[topo.cx[a]] = 1;
-        auto gpos = [&](int node) {
-            const int i = node % (topo.nx + 1);
-            if (xcut[i]) {
-                int a = 0;
-                while (topo.cx[a] != i) ++a;
-                return a;          // cut a belongs to group a
-            }
-            int a = 0;
-            while (!(topo.cx[a] <= i && i < topo.cx[a + 1])) ++a;
-            return a;              // slab a belongs to group a
-        };
-        std::vector<int> g0(np);
-        for (int v = 0; v < (int)topo.verts.size(); ++v) g0[2 * v] = g0[2 * v + 1] = gpos(topo.verts[v].nodes[0]);
-        const int nv2 = 2 * (int)topo.verts.size();
-        for (int e = 0; e < (int)topo.edges.size(); ++e)
-            g0[nv2 + 2 * e] = g0[nv2 + 2 * e + 1] = gpos(topo.edges[e].nodes[0]);
-        int minsz = 1024;
-        if (const char* ev = std::getenv("BDM_COARSE_MIN_BLOCK")) minsz = std::atoi(ev);
-        std::vector<int> cnt(topo.px, 0), remap(topo.px, 0);
-        for (int p = 0; p < np; ++p) ++cnt[g0[p]];
-        int G = 0, acc = 0;
-        for (int a = 0; a < topo.px; ++a) {
-            remap[a] = G;
-            acc += cnt[a];
-            if (acc >= minsz) { ++G; acc = 0; }
-        }
-        if (acc > 0) ++G;
-        for (int a = 0; a < topo.px; ++a) remap[a] = std::min(remap[a], G - 1);
-        std::vector<int> gof(np);
-        for (int p = 0; p < np; ++p) gof[p] = remap[g0[p]];
-        coarse_.init(gof, pin_, np);
-        for (int q = 0; q < nsub; ++q) {
-            int lo = 1 << 30, hi = -1;
-            for (int p : topo.subs[q].primal) { lo = std::min(lo, gof[p]); hi = std::max(hi, gof[p]); }
-            if (hi - lo > 1) {
-                set_error("internal error: coarse ordering is not block tridiagonal");
-                return BDM_E_ARG;
-            }
+        const std::string e = coarse_.init(topo, pin_, MAXP);
+        if (!e.empty()) {
+            set_error(e);
+            return BDM_E_ARG;
         }
     }
 
@@ -466,22 +436,9 @@ int Context::alloc_local() {
     const int np = topo.nprimal;
     cb_ = (double*)dalloc((size_t)np * sizeof(double));
     {
-        CoarseSolver& c = coarse_;
-        c.D = (double*)dalloc(c.nD * sizeof(double));
-        c.E = (double*)dalloc(std::max<int64_t>(c.nE, 1) * sizeof(double));
-        c.Cb = (double*)dalloc(std::max<int64_t>(c.nE, 1) * sizeof(double));
-        c.yb = (double*)dalloc((size_t)np * sizeof(double));
-        c.zb = (double*)dalloc((size_t)np * sizeof(double));
-        const int sb = kCoarseSweepBlock;
-        c.Bw = (double*)dalloc((size_t)sb * sb * sizeof(double));
-        c.Tw = (double*)dalloc((size_t)c.maxn * sb * sizeof(double));
-        c.Rw = (double*)dalloc((size_t)c.maxn * sb * sizeof(double));
-        c.Pw = (double*)dalloc((size_t)c.maxn * ((c.maxn + 127) / 128 + 1) * sizeof(double));
-        c.info = (int*)dalloc(sizeof(int));
-        c.d_grp = upload(c.grp); c.d_pos = upload(c.pos); c.d_ng = upload(c.ng);
-        c.d_Doff = upload(c.D_off); c.d_Eoff = upload(c.E_off); c.d_goff = upload(c.goff);
-        if (!c.D || !c.E || !c.Cb || !c.yb || !c.zb || !c.Bw || !c.Tw || !c.Rw || !c.Pw || !c.info) {
-            set_error("device allocation failed (coarse)");
+        const std::string e = coarse_.alloc(ctx_alloc, &allocs_, stream_);
+        if (!e.empty()) {
+            set_error(e);
             return BDM_E_OOM;
         }
     }
@@ -639,7 +596,7 @@ int Context::linearize_t() {
     launch_trsm_fwd<T>(stream_, nsub, (const T*)Lrrs_, Lrr_off_, nr_, nr_, (T*)F_, bd_.F_off, nr_, kF_);
     launch_coarse_local<T>(stream_, bd_, (const T*)F_, Svv_, (T*)Z_, (T*)Gi_, Sp_, info_sub_);
     launch_deluxe_setup<T>(stream_, od_, (const T*)slots_, (T*)fac_, (T*)inv_, (T*)dmat_, info_obj_);
-    coarse_.factor(stream_, color_list_, color_ptr_, nP_, sv_.P_off, sv_.primal, Sp_, SP_STRIDE);
+    coarse_.factor(stream_, color_list_, color_ptr_, nP_, Sp_, SP_STRIDE);
     int hb = 0, hc = 0;
     std::vector<int> hs(nsub), ho(od_.nobj);
     HIPOK(hipMemcpyAsync(&hb, bad_, sizeof(int), hipMemcpyDeviceToHost, stream_));
@@ -935,12 +892,6 @@ int Context::profile_t(int kernel, int reps, double* avg_ms, double* work) {
     return 0;
 }
 
-static void* ctx_alloc(void* c, size_t bytes) {
-    void* p = nullptr;
-    if (hipMalloc(&p, bytes ? bytes : 8) != hipSuccess) return nullptr;
-    static_cast<std::vector<void*>*>(c)->push_back(p);
-    return p;
-}
 
 int Context::ensure_predictor() {
     if (pred_.ready) return 0;
