@@ -732,41 +732,59 @@ __global__ __launch_bounds__(kWG) void k_coarse_local(BatchDesc d, const T* __re
 }
 
 // ------------------------------------------------- single-RHS triangular
-// Forward L x = b or backward L^T x = b, in place, one workgroup per vector.
+// Forward L x = b or backward L^T x = b, in place, one workgroup per vector;
+// x lives in LDS (dynamic, n values) for the whole solve.  Per 32-column
+// block one wave solves the diagonal block from registers (lane i holds row i
+// of the block for the forward solve, column i for the backward solve;
+// reciprocal pivots; broadcasts by lane reads), then all waves stream the
+// rows below: forward x_r -= L_r,blk x_blk, backward the dot products
+// L_blk^T x_below that enter the block's right-hand side.
+__device__ inline float lane_read(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ inline double lane_read(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_trsv_fwd(const T* __restrict__ Lb, const int64_t* __restrict__ Loff,
                                                  const int* __restrict__ nv, const int* __restrict__ ldv,
-                                                 T* __restrict__ xb, const int64_t* __restrict__ xoff,
-                                                 const int* __restrict__ mv) {
+                                                 T* __restrict__ xb, const int64_t* __restrict__ xoff) {
+    extern __shared__ double trsv_lds[];
+    T* xl = reinterpret_cast<T*>(trsv_lds);
+    __shared__ T xs[NB];
     const int s = blockIdx.x;
     const T* L = Lb + Loff[s];
     T* x = xb + xoff[s];
     const int n = nv[s];
-    const int m = mv ? mv[s] : n;   // rows: [n, m) receive x_r -= L_r,0:n y
     const int64_t ld = ldv[s];
     const int tid = threadIdx.x, lane = tid & 63;
-    __shared__ T D[NB][NB + 1];
-    __shared__ T xs[NB];
+    for (int i = tid; i < n; i += kWG) xl[i] = x[i];
+    __syncthreads();
     for (int j0 = 0; j0 < n; j0 += NB) {
         const int jb = min(NB, n - j0);
-        // stage the diagonal block (coalesced along columns)
-        for (int idx = tid; idx < NB * NB; idx += kWG) {
-            const int i = idx % NB, j = idx / NB;
-            D[i][j] = (i < jb && j < jb && j <= i) ? L[(j0 + i) + (j0 + j) * ld] : (T)(i == j);
-        }
-        __syncthreads();
         if (tid < 64) {
-            T xv = (lane < jb) ? x[j0 + lane] : (T)0;
-            for (int c = 0; c < jb; ++c) {
-                const T xc = __shfl(xv, c) / D[c][c];
-                if (lane == c) xv = xc;
-                else if (lane > c && lane < NB) xv -= D[lane][c] * xc;
+            const int i = min(lane, jb - 1);
+            T drow[NB];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) drow[c] = L[(j0 + i) + (j0 + min(c, jb - 1)) * ld];
+            const T rinv = (lane < jb) ? (T)1 / L[(j0 + i) + (j0 + i) * ld] : (T)0;
+            T xv = (lane < jb) ? xl[j0 + lane] : (T)0;
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                if (c < jb) {
+                    const T xc = lane_read(xv, c) * lane_read(rinv, c);
+                    xv = (lane == c) ? xc : ((lane > c) ? xv - drow[c] * xc : xv);
+                }
             }
             if (lane < NB) xs[lane] = (lane < jb) ? xv : (T)0;
-            if (lane < jb) x[j0 + lane] = xv;
+            if (lane < jb) xl[j0 + lane] = xv;
         }
         __syncthreads();
-        for (int r = j0 + jb + tid; r < m; r += kWG) {
+        for (int r = j0 + jb + tid; r < n; r += kWG) {
             // branch-free, fully unrolled so all column loads are in flight together
             T lv[NB];
 #pragma unroll
@@ -774,38 +792,36 @@ __global__ __launch_bounds__(kWG) void k_trsv_fwd(const T* __restrict__ Lb, cons
             T acc = (T)0;
 #pragma unroll
             for (int c = 0; c < NB; ++c) acc += (c < jb ? lv[c] : (T)0) * xs[c];
-            x[r] -= acc;
+            xl[r] -= acc;
         }
         __syncthreads();
     }
+    for (int i = tid; i < n; i += kWG) x[i] = xl[i];
 }
 
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_trsv_bwd(const T* __restrict__ Lb, const int64_t* __restrict__ Loff,
                                                  const int* __restrict__ nv, const int* __restrict__ ldv,
-                                                 T* __restrict__ xb, const int64_t* __restrict__ xoff,
-                                                 const int* __restrict__ mv) {
+                                                 T* __restrict__ xb, const int64_t* __restrict__ xoff) {
+    extern __shared__ double trsv_lds[];
+    T* xl = reinterpret_cast<T*>(trsv_lds);
+    __shared__ T red[kWG / 64][NB];
     const int s = blockIdx.x;
     const T* L = Lb + Loff[s];
     T* x = xb + xoff[s];
     const int n = nv[s];
-    const int m = mv ? mv[s] : n;   // known values x_[n, m) enter as x_0:n -= L_[n,m),0:n^T x_[n,m)
     const int64_t ld = ldv[s];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    __shared__ T red[kWG / 64][NB];
-    __shared__ T D[NB][NB + 1];
+    for (int i = tid; i < n; i += kWG) xl[i] = x[i];
+    __syncthreads();
     const int nblk = (n + NB - 1) / NB;
     for (int bi = nblk - 1; bi >= 0; --bi) {
         const int j0 = bi * NB, jb = min(NB, n - j0);
-        for (int idx = tid; idx < NB * NB; idx += kWG) {
-            const int i = idx % NB, j = idx / NB;
-            D[i][j] = (i < jb && j < jb && j <= i) ? L[(j0 + i) + (j0 + j) * ld] : (T)(i == j);
-        }
         T acc[NB];
 #pragma unroll
         for (int c = 0; c < NB; ++c) acc[c] = (T)0;
-        for (int r = j0 + jb + tid; r < m; r += kWG) {
-            const T xr = x[r];
+        for (int r = j0 + jb + tid; r < n; r += kWG) {
+            const T xr = xl[r];
             T lv[NB];
 #pragma unroll
             for (int c = 0; c < NB; ++c) lv[c] = L[r + (j0 + min(c, jb - 1)) * ld];
@@ -819,20 +835,28 @@ __global__ __launch_bounds__(kWG) void k_trsv_bwd(const T* __restrict__ Lb, cons
         }
         __syncthreads();
         if (tid < 64) {
+            const int i = min(lane, jb - 1);
+            T dcol[NB];   // dcol[c] = L[j0 + c][j0 + i], used for c > i only
+#pragma unroll
+            for (int c = 0; c < NB; ++c) dcol[c] = L[(j0 + min(c, jb - 1)) + (j0 + i) * ld];
+            const T rinv = (lane < jb) ? (T)1 / L[(j0 + i) + (j0 + i) * ld] : (T)0;
             T rhs = (T)0;
             if (lane < jb) {
-                rhs = x[j0 + lane];
+                rhs = xl[j0 + lane];
                 for (int q = 0; q < kWG / 64; ++q) rhs -= red[q][lane];
             }
-            for (int c = jb - 1; c >= 0; --c) {
-                const T xc = __shfl(rhs, c) / D[c][c];
-                if (lane == c) rhs = xc;
-                else if (lane < c) rhs -= D[c][lane] * xc;
+#pragma unroll
+            for (int c = NB - 1; c >= 0; --c) {
+                if (c < jb) {
+                    const T xc = lane_read(rhs, c) * lane_read(rinv, c);
+                    rhs = (lane == c) ? xc : ((lane < c) ? rhs - dcol[c] * xc : rhs);
+                }
             }
-            if (lane < jb) x[j0 + lane] = rhs;
+            if (lane < jb) xl[j0 + lane] = rhs;
         }
         __syncthreads();
     }
+    for (int i = tid; i < n; i += kWG) x[i] = xl[i];
 }
 
 // --------------------------------------------------------- deluxe operators
@@ -968,12 +992,13 @@ void launch_coarse_local(hipStream_t s, const BatchDesc& d, const T* F, const do
 }
 template <typename T>
 void launch_trsv(hipStream_t s, int nb, bool trans, const T* L, const int64_t* Loff, const int* n,
-                 const int* ld, T* x, const int64_t* xoff, const int* rows) {
-    if (nb <= 0) return;
+                 const int* ld, T* x, const int64_t* xoff, int maxn) {
+    if (nb <= 0 || maxn <= 0) return;
+    const size_t lds = (size_t)maxn * sizeof(T);
     if (trans)
-        hipLaunchKernelGGL(k_trsv_bwd<T>, dim3(nb), dim3(kWG), 0, s, L, Loff, n, ld, x, xoff, rows);
+        hipLaunchKernelGGL(k_trsv_bwd<T>, dim3(nb), dim3(kWG), lds, s, L, Loff, n, ld, x, xoff);
     else
-        hipLaunchKernelGGL(k_trsv_fwd<T>, dim3(nb), dim3(kWG), 0, s, L, Loff, n, ld, x, xoff, rows);
+        hipLaunchKernelGGL(k_trsv_fwd<T>, dim3(nb), dim3(kWG), lds, s, L, Loff, n, ld, x, xoff);
 }
 template <typename T>
 void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, const T* slots, T* fac, T* inv, T* dmat, int* info) {
@@ -997,7 +1022,7 @@ void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, const T* slots, T* fac
     template void launch_coarse_local<T>(hipStream_t, const BatchDesc&, const T*, const double*, T*, T*, \
                                          double*, int*);                                                 \
     template void launch_trsv<T>(hipStream_t, int, bool, const T*, const int64_t*, const int*,          \
-                                 const int*, T*, const int64_t*, const int*);                            \
+                                 const int*, T*, const int64_t*, int);                                   \
     template void launch_deluxe_setup<T>(hipStream_t, const ObjDesc&, const T*, T*, T*, T*, int*);
 BDM_INST(double)
 BDM_INST(float)

@@ -88,13 +88,10 @@ template <typename T>
 void launch_coarse_local(hipStream_t s, const BatchDesc& d, const T* F, const double* Svv, T* Z,
                          T* Gi, double* Sp, int* info);
 // Batched triangular solves with the n x n lower factor of each matrix
-// (leading dimension ld), in place on x.  With rows (rows >= n per matrix),
-// the rectangular block below the factor takes part: the forward solve also
-// updates x_[n, rows) -= L_[n,rows),0:n y, the backward solve first subtracts
-// L_[n,rows),0:n^T x_[n,rows) from the right-hand side.
+// (leading dimension ld), in place on x; maxn bounds n over the batch.
 template <typename T>
 void launch_trsv(hipStream_t s, int nb, bool trans, const T* L, const int64_t* Loff, const int* n,
-                 const int* ld, T* x, const int64_t* xoff, const int* rows = nullptr);
+                 const int* ld, T* x, const int64_t* xoff, int maxn);
 
 // Deluxe objects (faces and edges), one workgroup per object.
 struct ObjDesc {

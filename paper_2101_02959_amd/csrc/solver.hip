@@ -177,6 +177,7 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
         maxbox_ = std::max(maxbox_, (sb.Lx() + 1) * (sb.Ly() + 1) * (sb.Lz() + 1));
         maxG_ = std::max(maxG_, sb.n() - sb.nI);
         maxnI_ = std::max(maxnI_, sb.nI);
+        maxnr_ = std::max(maxnr_, sb.nr);
         lmap_off[q] = (int64_t)lmap.size();
         lmap.insert(lmap.end(), sb.lmap.begin(), sb.lmap.end());
         K_off[q] = accK; accK += (int64_t)sb.n() * sb.n();
@@ -631,8 +632,8 @@ template <typename T>
 void Context::dirichlet(const double* r, const double* q, double* out) {
     T* xI = (T*)xI_;
     launch_gather_I<T>(stream_, nInodes_, Ilist_, N, r, q, xI);
-    launch_trsv<T>(stream_, bd_.nsub, false, (const T*)LIIs_, LII_off_, nI_, nI_, xI, xI_off_);
-    launch_trsv<T>(stream_, bd_.nsub, true, (const T*)LIIs_, LII_off_, nI_, nI_, xI, xI_off_);
+    launch_trsv<T>(stream_, bd_.nsub, false, (const T*)LIIs_, LII_off_, nI_, nI_, xI, xI_off_, maxnI_);
+    launch_trsv<T>(stream_, bd_.nsub, true, (const T*)LIIs_, LII_off_, nI_, nI_, xI, xI_off_, maxnI_);
     launch_scatter_I<T>(stream_, nInodes_, Ilist_, N, xI, out);
 }
 
@@ -649,13 +650,13 @@ void Context::condense(const double* r, double* g) {
 // backward solve for the Neumann correction plus the coarse prolongation.
 template <typename T>
 void Context::stilde_inv(T* xr, const double* gvert, double* uc) {
-    launch_trsv<T>(stream_, bd_.nsub, false, (const T*)Lrrs_, Lrr_off_, nr_, nr_, xr, xr_off_);
+    launch_trsv<T>(stream_, bd_.nsub, false, (const T*)Lrrs_, Lrr_off_, nr_, nr_, xr, xr_off_, maxnr_);
     launch_coarse_rhs_local<T>(stream_, sv_, xr, (const T*)F_, (const T*)Z_, (const T*)Gi_, cP_, mu_);
     launch_coarse_rhs_gather(stream_, cd_, N, gvert, cP_, uc);
     launch_coarse_project(stream_, cd_.np, pin_, uc);
     coarse_.solve(stream_, uc);
     launch_neumann_rhs<T>(stream_, sv_, (const T*)F_, (const T*)Z_, mu_, uc, xr, 1);
-    launch_trsv<T>(stream_, bd_.nsub, true, (const T*)Lrrs_, Lrr_off_, nr_, nr_, xr, xr_off_);
+    launch_trsv<T>(stream_, bd_.nsub, true, (const T*)Lrrs_, Lrr_off_, nr_, nr_, xr, xr_off_, maxnr_);
 }
 
 // zbuf holds interface values (zero interior); fill the interior by the
@@ -870,7 +871,7 @@ int Context::profile_t(int kernel, int reps, double* avg_ms, double* work) {
             if (kernel == BDM_KERNEL_JACOBIAN)
                 launch_jac_apply(stream_, fp, st_, dg_, kp_, kq_);
             else
-                launch_trsv<T>(stream_, nsub, false, (const T*)LIIs_, LII_off_, nI_, nI_, (T*)xI_, xI_off_);
+                launch_trsv<T>(stream_, nsub, false, (const T*)LIIs_, LII_off_, nI_, nI_, (T*)xI_, xI_off_, maxnI_);
             HIPOK(hipEventRecord(e1, stream_));
             HIPOK(hipEventSynchronize(e1));
             float ms = 0.f;

@@ -110,7 +110,7 @@ class Context {
     SubVecDesc sv_{};
     CoarseDesc cd_{};
     FetiDesc fd_{};
-    int maxbox_ = 0, maxG_ = 0, maxnI_ = 0, nInodes_ = 0;
+    int maxbox_ = 0, maxG_ = 0, maxnI_ = 0, maxnr_ = 0, nInodes_ = 0;
     std::vector<int> trail_tiles_, panel_rows_;
     void* Wbuf_ = nullptr;
     int schur_tiles_ = 0;
