@@ -10,11 +10,11 @@ a synthetic slab whose state is resident in HBM.  The CPU baseline is the
 FP64 oracle timed on a bounded sample (one Newton linear solve on the 32^3
 slab) and scaled per dof.
 
-Roofline: the dominant kernel of a step is the batched partial Cholesky of
-the local matrices (interior elimination), which runs on MFMA; it is timed
-with HIP events on the library stream through bdm_profile_kernel, with its
-algorithmic flop count.  The Jacobian apply and the Dirichlet triangular
-solve (HBM-bound) are reported beside it.
+Roofline: the dominant kernel of the FP32-local step is the batched rank-k
+update of the local interior elimination (k_syrk_batched<float>, MFMA); it is
+timed with HIP events on the library stream through bdm_profile_kernel (mean
+duration and algorithmic flops of one launch).  The panel kernels, the
+Dirichlet triangular solves and the Jacobian apply are reported beside it.
 """
 from __future__ import annotations
 
@@ -80,26 +80,33 @@ def run_path(P, wl, precision, guess, warmup, steps, predictor=None):
 
 
 def kernel_rooflines(P, S, prec_name, reps=5):
-    """Live HIP-event timings of the hot kernels at the current linearisation."""
-    out = {}
-    ms, flops = S.bdm_profile_kernel(P.BDM_KERNEL_POTRF_INTERIOR, reps)
-    tf = flops / (ms * 1e-3) / 1e12
+    """Live HIP-event timings of the hot kernels at the current linearisation:
+    mean duration of one launch and algorithmic work per launch."""
+    tname = "float" if prec_name == "f32" else "double"
     peak = MFMA_PEAK_TFS[prec_name]
-    out["potrf"] = {"bound": "mfma", "kernel": f"k_potrf_interior<{'float' if prec_name == 'f32' else 'double'}> "
-                    "(first setup chunk)", "achieved": round(tf, 2), "peak": peak,
-                    "unit": "TFLOP/s", "frac": round(tf / peak, 4), "traffic": None,
-                    "avg_ms": round(ms, 3), "algorithmic_flops_per_launch": flops}
-    ms, nbytes = S.bdm_profile_kernel(P.BDM_KERNEL_TRSV_DIRICHLET, 20)
-    gbs = nbytes / (ms * 1e-3) / 1e9
-    out["trsv"] = {"bound": "hbm", "kernel": "k_trsv_fwd (Dirichlet, all subdomains)",
-                   "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                   "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "avg_ms": round(ms, 4),
-                   "algorithmic_bytes_per_launch": nbytes}
-    ms, nbytes = S.bdm_profile_kernel(P.BDM_KERNEL_JACOBIAN, 50)
-    gbs = nbytes / (ms * 1e-3) / 1e9
-    out["jacobian"] = {"bound": "hbm", "kernel": "k_jac_apply", "achieved": round(gbs, 1),
-                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                       "traffic": None, "avg_ms": round(ms, 4), "algorithmic_bytes_per_launch": nbytes}
+    out = {}
+
+    def mfma(key, kid, kernel):
+        ms, flops = S.bdm_profile_kernel(kid, reps)
+        tf = flops / (ms * 1e-3) / 1e12
+        out[key] = {"bound": "mfma", "kernel": kernel, "achieved": round(tf, 2), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(tf / peak, 4), "traffic": None, "avg_ms": round(ms, 4),
+                    "algorithmic_flops_per_launch": flops}
+
+    def hbm(key, kid, kernel, r):
+        ms, nbytes = S.bdm_profile_kernel(kid, r)
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        out[key] = {"bound": "hbm", "kernel": kernel, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "avg_ms": round(ms, 4),
+                    "algorithmic_bytes_per_launch": nbytes}
+
+    mfma("syrk", P.BDM_KERNEL_SYRK_UPDATE,
+         f"k_syrk_batched<{tname}> (rank-k updates of the interior elimination, first setup chunk)")
+    mfma("panel", P.BDM_KERNEL_POTRF_INTERIOR,
+         f"k_panel_diag<{tname}> + k_panel_trsm<{tname}> (first setup chunk)")
+    hbm("trsv_fwd", P.BDM_KERNEL_TRSV_DIRICHLET, f"k_trsv_fwd<{tname}> (Dirichlet, all subdomains)", 20)
+    hbm("trsv_bwd", P.BDM_KERNEL_TRSV_DIRICHLET_T, f"k_trsv_bwd<{tname}> (Dirichlet, all subdomains)", 20)
+    hbm("jacobian", P.BDM_KERNEL_JACOBIAN, "k_stencil<0> (Jacobian apply)", 50)
     return out
 
 
@@ -172,9 +179,8 @@ def main():
         "mixed": mixed, "plain_fp64": plain,
         "speedup_vs_plain_fp64": round(plain["s_per_step"] / mixed["s_per_step"], 3),
         "mixed_vs_fp64_rel_diff": rel,
-        "roofline": roof32["potrf"],
-        "roofline_other": {"mixed": {"trsv": roof32["trsv"], "jacobian": roof32["jacobian"]},
-                           "fp64": roof64},
+        "roofline": roof32["syrk"],
+        "roofline_other": {"mixed": {k: v for k, v in roof32.items() if k != "syrk"}, "fp64": roof64},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(dofs, plain["newton_per_step"])

@@ -213,34 +213,38 @@ int bdm_predictor_train(bdm_ctx* ctx, const double* samples, int nsamples, const
                         double lr, double* losses);
 
 /* Kernel timing for roofline reports.  At the last linearisation, launches
- * one hot kernel reps times on the context stream, each bracketed by HIP
- * events, and returns the mean launch duration in avg_ms and the kernel's
- * algorithmic work per launch in work (bytes for the bandwidth-bound
- * kernels, floating-point operations for the factorisation):
- *   BDM_KERNEL_JACOBIAN       y = J x on 2N vectors; bytes = 40 N (read v, u_e,
- *                             reaction diagonal; write both outputs)
- *   BDM_KERNEL_TRSV_DIRICHLET one forward Dirichlet solve L_II y = b over all
- *                             subdomains; bytes = lower triangles + vectors
- *   BDM_KERNEL_POTRF_INTERIOR the panel kernel of the interior elimination
- *                             (partial Cholesky through the interior columns,
- *                             right looking in 128-column panels, Sec. 4.1)
- *                             on the first setup chunk: all its launches of
- *                             one elimination; flops = divisions plus 2 per
- *                             entry updated inside the panels
- *   BDM_KERNEL_SYRK_UPDATE    the batched rank-k update kernel of the same
- *                             elimination: the trailing updates right of each
- *                             panel and the Schur update S_Gamma = K_GG -
- *                             L_GI L_GI^T; flops = 2 per updated entry per
- *                             inner index (lower triangles only)
- * For these two, avg_ms is the summed duration of the kernel's launches in
- * one elimination, averaged over reps; the local matrices of the chunk are
- * reassembled before each elimination (untimed); the preconditioner factors
- * are left intact.  BDM_E_ARG for another id. */
+ * one hot kernel reps times on the context stream, bracketed by HIP events,
+ * and returns the mean duration of one launch in avg_ms and the kernel's
+ * algorithmic work per launch in work (bytes for the bandwidth-bound kernels,
+ * floating-point operations for the factorisation kernels):
+ *   BDM_KERNEL_JACOBIAN         y = J x on 2N vectors; bytes = 40 N (read v,
+ *                               u_e, reaction diagonal; write both outputs)
+ *   BDM_KERNEL_TRSV_DIRICHLET   one forward Dirichlet solve L_II y = b over
+ *                               all subdomains; bytes = lower triangles +
+ *                               vectors
+ *   BDM_KERNEL_TRSV_DIRICHLET_T the backward solve L_II^T x = y, same bytes
+ *   BDM_KERNEL_POTRF_INTERIOR   the panel kernels of the interior elimination
+ *                               (partial Cholesky through the interior
+ *                               columns, right looking in 128-column panels,
+ *                               Sec. 4.1) on the first setup chunk: the
+ *                               diagonal-block factor and the row-block TRSM;
+ *                               flops = divisions plus 2 per entry updated
+ *                               inside the panels
+ *   BDM_KERNEL_SYRK_UPDATE      the batched rank-k update kernel of the same
+ *                               elimination: the trailing updates right of
+ *                               each panel and the Schur update S_Gamma =
+ *                               K_GG - L_GI L_GI^T; flops = 2 per updated
+ *                               entry per inner index (lower triangles only)
+ * For the last two, work and time are averaged over the kernel's launches in
+ * one elimination (the launches differ in size); the local matrices of the
+ * chunk are reassembled before each elimination (untimed).  The
+ * preconditioner factors are left intact.  BDM_E_ARG for another id. */
 enum {
     BDM_KERNEL_JACOBIAN = 0,
     BDM_KERNEL_TRSV_DIRICHLET = 1,
     BDM_KERNEL_POTRF_INTERIOR = 2,
-    BDM_KERNEL_SYRK_UPDATE = 3
+    BDM_KERNEL_SYRK_UPDATE = 3,
+    BDM_KERNEL_TRSV_DIRICHLET_T = 4
 };
 int bdm_profile_kernel(bdm_ctx* ctx, int kernel, int reps, double* avg_ms, double* work);
 

@@ -19,7 +19,8 @@ BDM_SOLVER_BDDC, BDM_SOLVER_FETIDP = 0, 1
 BDM_PREC_FP64, BDM_PREC_MIXED = 0, 1
 BDM_GUESS_PREV, BDM_GUESS_EXTRAP, BDM_GUESS_CNN = 0, 1, 2
 BDM_FETI_F, BDM_FETI_PRECOND, BDM_FETI_RHS, BDM_FETI_RECOVER = 0, 1, 2, 3
-BDM_KERNEL_JACOBIAN, BDM_KERNEL_TRSV_DIRICHLET, BDM_KERNEL_POTRF_INTERIOR, BDM_KERNEL_SYRK_UPDATE = 0, 1, 2, 3
+(BDM_KERNEL_JACOBIAN, BDM_KERNEL_TRSV_DIRICHLET, BDM_KERNEL_POTRF_INTERIOR, BDM_KERNEL_SYRK_UPDATE,
+ BDM_KERNEL_TRSV_DIRICHLET_T) = 0, 1, 2, 3, 4
 
 ERRORS = {
     -1: "BDM_E_ARG", -2: "BDM_E_OOM", -3: "BDM_E_HIP", -4: "BDM_E_NOT_SPD",

@@ -233,18 +233,31 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
         }
         (void)maxsz;
         Kc_off_ = upload(kc);
-        // launch sizes of the interior elimination (tiles per subdomain, max over the batch)
+        // elimination plans (launch sizes: tiles per matrix, max over the batch):
+        // the interior block with the Schur update, and the r-block of S_Gamma
+        // viewed as its own matrix at offset (nI, nI)
+        std::vector<int64_t> kr(nsub);
+        for (int q = 0; q < nsub; ++q) kr[q] = kc[q] + (int64_t)nI[q] + (int64_t)nI[q] * n[q];
+        plan_int_.off = Kc_off_;
+        plan_rr_.off = upload(kr);
         const int wp = interior_panel_width();
-        trail_tiles_.assign((maxnI_ + wp - 1) / wp, 0);
-        panel_rows_.assign(trail_tiles_.size(), 0);
-        schur_tiles_ = 0;
-        for (const auto& sb : topo.subs) {
-            for (size_t q = 0; q < trail_tiles_.size(); ++q) {
-                trail_tiles_[q] = std::max(trail_tiles_[q], syrk_tiles(false, (int)q * wp, sb.nI, sb.n()));
-                panel_rows_[q] = std::max(panel_rows_[q], panel_rowblocks((int)q * wp, sb.nI, sb.n()));
+        auto plan = [&](ElimPlan& pl, bool interior) {
+            int maxne = 0;
+            for (const auto& sb : topo.subs) maxne = std::max(maxne, interior ? sb.nI : sb.nr);
+            pl.trail.assign((maxne + wp - 1) / wp, 0);
+            pl.rows.assign(pl.trail.size(), 0);
+            pl.schur = 0;
+            for (const auto& sb : topo.subs) {
+                const int e = interior ? sb.nI : sb.nr, m = interior ? sb.n() : sb.nr;
+                for (size_t q = 0; q < pl.trail.size(); ++q) {
+                    pl.trail[q] = std::max(pl.trail[q], syrk_tiles(false, (int)q * wp, e, m));
+                    pl.rows[q] = std::max(pl.rows[q], panel_rowblocks((int)q * wp, e, m));
+                }
+                pl.schur = std::max(pl.schur, syrk_tiles(true, 0, e, m));
             }
-            schur_tiles_ = std::max(schur_tiles_, syrk_tiles(true, 0, sb.nI, sb.n()));
-        }
+        };
+        plan(plan_int_, true);
+        plan(plan_rr_, false);
     }
     nInodes_ = (int)Ilist.size();
 
@@ -366,6 +379,8 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
     LII_off_ = upload(LII); Lrr_off_ = upload(Lrr); xI_off_ = upload(xI_off); Srr_off_ = bd_.Srr_off;
     nI_ = bd_.nI; nr_ = bd_.nr; ld_ = bd_.n; kF_ = upload(kF); nP_ = upload(nP);
     st1c0_ = upload(st1c0); st1c1_ = upload(st1c1); st1c2_ = upload(st1c2); st2c1_ = upload(st2c1);
+    plan_int_.ne = st1c1_; plan_int_.n = st1c2_;
+    plan_rr_.ne = nr_; plan_rr_.n = nr_;
     color_list_ = upload(clist);
     std::vector<int64_t> z64(1, 0);
     std::vector<int> zi(1, 0), npv(1, np);
@@ -522,12 +537,12 @@ int Context::linearize(const double* v, const double* w) {
     return rc;
 }
 
-// Interior elimination of the local matrices of one chunk (Sec. 4.1): L_II,
-// the panel L_GI and the Schur complement S_Gamma in the trailing block.
-// Right looking in panels; with timing events, the durations of the panel
-// kernel and of the update kernel are added to tm[0] and tm[1] (ms).
+// Right-looking blocked Cholesky of the local matrices of one chunk in
+// panels (see ElimPlan).  With timing, tm[0] and tm[1] accumulate the
+// durations (ms) of the panel kernels and of the rank-k update kernel, tm[2]
+// and tm[3] count their launches.
 template <typename T>
-int Context::eliminate_interior(T* K, int s0, int cnt, double* tm) {
+int Context::eliminate(T* K, int s0, int cnt, const ElimPlan& pl, double* tm) {
     const int w = interior_panel_width();
     hipEvent_t ev[3];
     if (tm)
@@ -544,27 +559,32 @@ int Context::eliminate_interior(T* K, int s0, int cnt, double* tm) {
         acc += ms;
         return 0;
     };
-    for (int q = 0; q * w < maxnI_; ++q) {
+    for (int q = 0; q < (int)pl.trail.size(); ++q) {
         const int J = q * w;
         mark(0);
-        launch_interior_panel<T>(stream_, cnt, K, Kc_off_ + s0, ld_ + s0, st1c1_ + s0, st1c2_ + s0, J, (T*)Wbuf_,
-                                 panel_rows_[q], info_sub_ + s0);
+        launch_interior_panel<T>(stream_, cnt, K, pl.off + s0, ld_ + s0, pl.ne + s0, pl.n + s0, J, (T*)Wbuf_,
+                                 pl.rows[q], info_sub_ + s0);
         mark(1);
-        launch_syrk_update<T>(stream_, cnt, K, Kc_off_ + s0, ld_ + s0, st1c1_ + s0, st1c2_ + s0, false, J,
-                              trail_tiles_[q]);
+        launch_syrk_update<T>(stream_, cnt, K, pl.off + s0, ld_ + s0, pl.ne + s0, pl.n + s0, false, J, pl.trail[q]);
         mark(2);
         if (tm) {
             lap(0, 1, tm[0]);
             lap(1, 2, tm[1]);
+            tm[2] += pl.rows[q] > 0 ? 2 : 1;
+            tm[3] += pl.trail[q] > 0 ? 1 : 0;
         }
     }
-    mark(0);
-    launch_syrk_update<T>(stream_, cnt, K, Kc_off_ + s0, ld_ + s0, st1c1_ + s0, st1c2_ + s0, true, 0, schur_tiles_);
-    mark(1);
-    if (tm) {
-        lap(0, 1, tm[1]);
-        for (auto& e : ev) hipEventDestroy(e);
+    if (pl.schur > 0) {
+        mark(0);
+        launch_syrk_update<T>(stream_, cnt, K, pl.off + s0, ld_ + s0, pl.ne + s0, pl.n + s0, true, 0, pl.schur);
+        mark(1);
+        if (tm) {
+            lap(0, 1, tm[1]);
+            tm[3] += 1;
+        }
     }
+    if (tm)
+        for (auto& e : ev) hipEventDestroy(e);
     return 0;
 }
 
@@ -587,11 +607,11 @@ int Context::linearize_t() {
         HIPOK(hipMemsetAsync(K, 0, nKwork_ * sizeof(T), stream_));
         launch_assemble<T>(stream_, cd, maxbox_, fp, ke_, vlin_, wlin_, K);
         // interior elimination: L_II, and S_Gamma in the trailing block
-        eliminate_interior<T>(K, s0, cnt, nullptr);
+        // interior elimination: L_II, L_GI and S_Gamma in the trailing block (Sec. 4.1)
+        eliminate<T>(K, s0, cnt, plan_int_, nullptr);
         launch_extract<T>(stream_, cd, K, (T*)slots_, (T*)F_, Svv_, (T*)Srr_);
-        // constrained Neumann factor L_rr of S_rr
-        launch_potrf<T>(stream_, cnt, K, Kc_off_ + s0, ld_ + s0, st1c1_ + s0, st2c1_ + s0, st2c1_ + s0,
-                        info_sub_ + s0);
+        // constrained Neumann factor L_rr of S_rr (the leading r-block of S_Gamma)
+        eliminate<T>(K, s0, cnt, plan_rr_, nullptr);
         launch_copy_out<T>(stream_, cd, cnt, K, (T*)LIIs_, LII_off_, (T*)Lrrs_, Lrr_off_);
     }
     launch_trsm_fwd<T>(stream_, nsub, (const T*)Lrrs_, Lrr_off_, nr_, nr_, (T*)F_, bd_.F_off, nr_, kF_);
@@ -822,7 +842,7 @@ int Context::profile_kernel(int kernel, int reps, double* avg_ms, double* work) 
         set_error("bdm_profile_kernel before bdm_linearize");
         return BDM_E_STATE;
     }
-    if (reps < 1 || kernel < 0 || kernel > BDM_KERNEL_SYRK_UPDATE) {
+    if (reps < 1 || kernel < 0 || kernel > BDM_KERNEL_TRSV_DIRICHLET_T) {
         set_error("bdm_profile_kernel: bad kernel id or reps");
         return BDM_E_ARG;
     }
@@ -842,7 +862,7 @@ int Context::profile_t(int kernel, int reps, double* avg_ms, double* work) {
     cd.sub0 = s0;
     if (kernel == BDM_KERNEL_JACOBIAN) {
         w = 40.0 * (double)N;
-    } else if (kernel == BDM_KERNEL_TRSV_DIRICHLET) {
+    } else if (kernel == BDM_KERNEL_TRSV_DIRICHLET || kernel == BDM_KERNEL_TRSV_DIRICHLET_T) {
         for (const auto& sb : topo.subs) w += (0.5 * sb.nI * (sb.nI + 1.0) + 2.0 * sb.nI) * sizeof(T);
     } else {
         // interior elimination flops: the panel kernel (divisions and the
@@ -865,13 +885,16 @@ int Context::profile_t(int kernel, int reps, double* avg_ms, double* work) {
             w += (kernel == BDM_KERNEL_POTRF_INTERIOR) ? wpanel : wupd;
         }
     }
+    double launches = 1.0;
     for (int r = 0; r < reps; ++r) {
-        if (kernel == BDM_KERNEL_JACOBIAN || kernel == BDM_KERNEL_TRSV_DIRICHLET) {
+        if (kernel == BDM_KERNEL_JACOBIAN || kernel == BDM_KERNEL_TRSV_DIRICHLET ||
+            kernel == BDM_KERNEL_TRSV_DIRICHLET_T) {
             HIPOK(hipEventRecord(e0, stream_));
             if (kernel == BDM_KERNEL_JACOBIAN)
                 launch_jac_apply(stream_, fp, st_, dg_, kp_, kq_);
             else
-                launch_trsv<T>(stream_, nsub, false, (const T*)LIIs_, LII_off_, nI_, nI_, (T*)xI_, xI_off_, maxnI_);
+                launch_trsv<T>(stream_, nsub, kernel == BDM_KERNEL_TRSV_DIRICHLET_T, (const T*)LIIs_, LII_off_, nI_,
+                               nI_, (T*)xI_, xI_off_, maxnI_);
             HIPOK(hipEventRecord(e1, stream_));
             HIPOK(hipEventSynchronize(e1));
             float ms = 0.f;
@@ -880,16 +903,18 @@ int Context::profile_t(int kernel, int reps, double* avg_ms, double* work) {
         } else {
             HIPOK(hipMemsetAsync(K_, 0, nKwork_ * sizeof(T), stream_));
             launch_assemble<T>(stream_, cd, maxbox_, fp, ke_, vlin_, wlin_, (T*)K_);
-            double tm[2] = {0.0, 0.0};
-            int rc = eliminate_interior<T>((T*)K_, s0, cnt, tm);
+            double tm[4] = {0.0, 0.0, 0.0, 0.0};
+            int rc = eliminate<T>((T*)K_, s0, cnt, plan_int_, tm);
             if (rc) return rc;
-            total += (kernel == BDM_KERNEL_POTRF_INTERIOR) ? tm[0] : tm[1];
+            const bool panel = kernel == BDM_KERNEL_POTRF_INTERIOR;
+            total += panel ? tm[0] : tm[1];
+            launches = std::max(1.0, panel ? tm[2] : tm[3]);
         }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    *avg_ms = total / reps;
-    *work = w;
+    *avg_ms = total / (reps * launches);
+    *work = w / launches;
     return 0;
 }
 

@@ -40,8 +40,20 @@ class Context {
     int fetidp_apply(int op, const double* in, double* out);
     int step(int nsteps, bdm_step_stats* st);
     int profile_kernel(int kernel, int reps, double* avg_ms, double* work);
+    // A right-looking elimination over the columns [0, ne) of a view of each
+    // local matrix (offset off, leading dimension the matrix size, n rows),
+    // with launch sizes per 128-column panel and, when schur > 0, the Schur
+    // update of the trailing block [ne, n)^2.
+    struct ElimPlan {
+        const int64_t* off = nullptr;
+        const int* ne = nullptr;
+        const int* n = nullptr;
+        std::vector<int> trail, rows;
+        int schur = 0;
+    };
+    ElimPlan plan_int_, plan_rr_;
     template <typename T>
-    int eliminate_interior(T* K, int s0, int cnt, double* tm);
+    int eliminate(T* K, int s0, int cnt, const ElimPlan& pl, double* tm);
     int predictor_set(const float* params, const double* scales);
     int predictor_get(float* params, double* scales);
     int predictor_guess(const double* vn, const double* uen, const double* vp, const double* uep, double* out);
@@ -111,9 +123,7 @@ class Context {
     CoarseDesc cd_{};
     FetiDesc fd_{};
     int maxbox_ = 0, maxG_ = 0, maxnI_ = 0, maxnr_ = 0, nInodes_ = 0;
-    std::vector<int> trail_tiles_, panel_rows_;
     void* Wbuf_ = nullptr;
-    int schur_tiles_ = 0;
     int *Ilist_ = nullptr;
     int64_t *LII_off_ = nullptr, *Lrr_off_ = nullptr, *xI_off_ = nullptr, *xr_off_ = nullptr;
     const int64_t *Srr_off_ = nullptr;
