@@ -805,7 +805,7 @@ __global__ __launch_bounds__(kWG) void k_trsv_bwd(const T* __restrict__ Lb, cons
                                                  T* __restrict__ xb, const int64_t* __restrict__ xoff) {
     extern __shared__ double trsv_lds[];
     T* xl = reinterpret_cast<T*>(trsv_lds);
-    __shared__ T red[kWG / 64][NB];
+    __shared__ T red[1][NB];
     const int s = blockIdx.x;
     const T* L = Lb + Loff[s];
     T* x = xb + xoff[s];
@@ -817,21 +817,24 @@ __global__ __launch_bounds__(kWG) void k_trsv_bwd(const T* __restrict__ Lb, cons
     const int nblk = (n + NB - 1) / NB;
     for (int bi = nblk - 1; bi >= 0; --bi) {
         const int j0 = bi * NB, jb = min(NB, n - j0);
-        T acc[NB];
+        // wave wv owns columns [8 wv, 8 wv + 8) of the block: coalesced column
+        // segments below the block, dotted with x, one wave reduction each
+        constexpr int CW = NB / (kWG / 64);
+        T acc[CW];
 #pragma unroll
-        for (int c = 0; c < NB; ++c) acc[c] = (T)0;
-        for (int r = j0 + jb + tid; r < n; r += kWG) {
+        for (int k = 0; k < CW; ++k) acc[k] = (T)0;
+        for (int r = j0 + jb + lane; r < n; r += 64) {
             const T xr = xl[r];
-            T lv[NB];
 #pragma unroll
-            for (int c = 0; c < NB; ++c) lv[c] = L[r + (j0 + min(c, jb - 1)) * ld];
-#pragma unroll
-            for (int c = 0; c < NB; ++c) acc[c] += (c < jb ? lv[c] : (T)0) * xr;
+            for (int k = 0; k < CW; ++k) {
+                const int c = min(CW * wv + k, jb - 1);
+                acc[k] += L[r + (j0 + c) * ld] * xr;
+            }
         }
 #pragma unroll
-        for (int c = 0; c < NB; ++c) {
-            const T sred = wave_sum(acc[c]);
-            if (lane == 0) red[wv][c] = sred;
+        for (int k = 0; k < CW; ++k) {
+            const T sred = wave_sum(acc[k]);
+            if (lane == 0) red[0][CW * wv + k] = sred;
         }
         __syncthreads();
         if (tid < 64) {
@@ -841,10 +844,7 @@ __global__ __launch_bounds__(kWG) void k_trsv_bwd(const T* __restrict__ Lb, cons
             for (int c = 0; c < NB; ++c) dcol[c] = L[(j0 + min(c, jb - 1)) + (j0 + i) * ld];
             const T rinv = (lane < jb) ? (T)1 / L[(j0 + i) + (j0 + i) * ld] : (T)0;
             T rhs = (T)0;
-            if (lane < jb) {
-                rhs = xl[j0 + lane];
-                for (int q = 0; q < kWG / 64; ++q) rhs -= red[q][lane];
-            }
+            if (lane < jb) rhs = xl[j0 + lane] - red[0][lane];
 #pragma unroll
             for (int c = NB - 1; c >= 0; --c) {
                 if (c < jb) {
