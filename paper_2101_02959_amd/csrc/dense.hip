@@ -390,7 +390,8 @@ __global__ __launch_bounds__(kWG) void k_panel_trsm(T* __restrict__ Abase, const
 // with a register prefetch of the next chunk.  The workgroup id is mapped so
 // that all tiles of one subdomain run on the same XCD (dispatch assigns
 // consecutive ids round robin to the 8 XCDs), which keeps P in that XCD's L2.
-constexpr int SY_TM = 128, SY_KC = 16, SY_LS = SY_TM + 16, SY_XCD = 8;
+constexpr int SY_TM = 128, SY_KC = 32, SY_LS = SY_TM + 16, SY_XCD = 8;
+constexpr int SY_EPT = SY_TM * SY_KC / kWG;   // staged elements per thread and operand
 constexpr int SY_TRAIL = 0, SY_SCHUR = 1;
 
 __host__ __device__ inline int trapezoid_tiles(int cb, int ce, int re) {
@@ -429,20 +430,20 @@ __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, con
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
     const int wr = wv & 1, wc = wv >> 1;                 // wave's 64x64 quadrant (rows i, cols j)
     const bool active = !(ti == tj && wr < wc);          // strictly upper quadrant of a diagonal tile
-    // each thread stages 8 elements of each operand per chunk: row tid % 128, k = tid / 128 + 2 e
+    // each thread stages SY_EPT elements of each operand per chunk: row tid % 128, k = tid / 128 + 2 e
     const int lrow = tid % SY_TM, lk0 = tid / SY_TM;
     const int ri = I0 + lrow, rj = J0 + lrow;
-    T pa[8], pb[8];
+    T pa[SY_EPT], pb[SY_EPT];
     auto fetch = [&](int kc) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < SY_EPT; ++e) {
             const int k = kc + lk0 + 2 * e;
             const bool kin = k < k1;
             pa[e] = (kin && ri < re) ? A[ri + (int64_t)k * ld] : (T)0;
             pb[e] = (kin && rj < ce) ? A[rj + (int64_t)k * ld] : (T)0;
         }
     };
-    // FP32: each chunk of SY_KC products is summed on its own and then added
+    // FP32: each chunk of SY_KC inner indices is summed on its own and then added
     // to a running total, so rounding grows with the number of chunks plus
     // the chunk length rather than with the whole inner dimension.
     constexpr bool two_level = std::is_same<T, float>::value;
@@ -455,7 +456,7 @@ __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, con
     for (int kc = k0; kc < k1; kc += SY_KC) {
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < SY_EPT; ++e) {
             As[lk0 + 2 * e][lrow] = pa[e];
             Bs[lk0 + 2 * e][lrow] = pb[e];
         }

@@ -106,7 +106,7 @@ std::vector<double> stencil_tables(int nz, const std::vector<double>& ke) {
 // --------------------------------------------------------------- device side
 namespace {
 
-constexpr int SX = 64, SY = 4, SZ = 16;    // block: 64 x 4 nodes, 16 z-levels per thread
+constexpr int SX = 32, SY = 8, SZ = 8;     // block: 32 x 8 nodes, 8 z-levels per thread
 
 __device__ inline double lumped_mass(const FEParams& p, int i, int j, int k) {
     const double fx = (i == 0 || i == p.nx) ? 0.5 : 1.0;
@@ -122,7 +122,7 @@ enum { ST_JAC = 0, ST_RES_MINUS_JAC = 1, ST_RESIDUAL = 2 };
 //   ST_JAC:            y = [d xv + si ; si + se]
 //   ST_RES_MINUS_JAC:  y = r - [d xv + si ; si + se]
 //   ST_RESIDUAL:       y = [m (c (v - v^n) + tau (I_ion - I_s)) + si ; si + se]
-// A block owns a 64 x 4 column of nodes and walks SZ z-levels.  The planes
+// A block owns a 32 x 8 column of nodes and walks SZ z-levels.  The planes
 // k-1, k, k+1 of (xv + xe) and xe, with a one-node halo, live in a rotating
 // LDS buffer, so each input value is fetched from memory about once; the
 // coefficient tables of level k (9 boundary classes x 2 media) are staged too.
@@ -135,7 +135,8 @@ __global__ __launch_bounds__(SX * SY) void k_stencil(FEParams p, const double* _
                                                      const double* __restrict__ re, const double* __restrict__ vn,
                                                      const double* __restrict__ w, const double* __restrict__ Is,
                                                      double stim, double* __restrict__ yv, double* __restrict__ ye) {
-    __shared__ double tab[9 * 2 * 27];
+    constexpr int NT = SX * SY, NPT = (PX * PY + NT - 1) / NT, TABN = 9 * 2 * 27, NTB = (TABN + NT - 1) / NT;
+    __shared__ double tab[TABN];
     __shared__ double ps[3][PY][PX];
     __shared__ double pe[3][PY][PX];
     const int tid = threadIdx.x + SX * threadIdx.y;
@@ -148,26 +149,60 @@ __global__ __launch_bounds__(SX * SY) void k_stencil(FEParams p, const double* _
     const int yc = (j == 0) ? 0 : (j == p.ny ? 2 : 1);
     const int cls = xc + 3 * yc;
     const int64_t plane = (int64_t)p.nx1 * p.ny1;
-    auto load_plane = [&](int k) {
-        const int sl = (k + 3) % 3;
-        for (int t = tid; t < PX * PY; t += SX * SY) {
+    // Planes are fetched into registers one iteration ahead and stored into a
+    // three-plane LDS ring (with the level's coefficient table) after the
+    // compute of the previous plane.  The loads are branch free (clamped
+    // index, mask applied at the LDS store), so they stay in flight across
+    // the compute instead of being waited for inside a bounds branch.
+    double ra[NPT], rb[NPT], rt[NTB];
+    bool rok[NPT];
+    auto fetch = [&](int k) {
+#pragma unroll
+        for (int q = 0; q < NPT; ++q) {
+            const int t = tid + q * NT;
             const int lx = t % PX, ly = t / PX;
             const int gi = i0 - 1 + lx, gj = j0 - 1 + ly;
-            double a = 0.0, b = 0.0;
-            if (k >= 0 && k <= p.nz && gi >= 0 && gi <= p.nx && gj >= 0 && gj <= p.ny) {
-                const int64_t q = gi + (int64_t)p.nx1 * gj + plane * k;
-                b = xe[q];
-                a = xv[q] + b;
-            }
-            ps[sl][ly][lx] = a;
-            pe[sl][ly][lx] = b;
+            const bool ok = t < PX * PY && k >= 0 && k <= p.nz && gi >= 0 && gi <= p.nx && gj >= 0 && gj <= p.ny;
+            const int64_t n = ok ? gi + (int64_t)p.nx1 * gj + plane * k : 0;
+            ra[q] = xv[n];
+            rb[q] = xe[n];
+            rok[q] = ok;
         }
     };
-    load_plane(kbeg - 1);
-    load_plane(kbeg);
+    auto store = [&](int k) {
+        const int sl = (k + 3) % 3;
+#pragma unroll
+        for (int q = 0; q < NPT; ++q) {
+            const int t = tid + q * NT;
+            if (t < PX * PY) {
+                ps[sl][t / PX][t % PX] = rok[q] ? ra[q] + rb[q] : 0.0;
+                pe[sl][t / PX][t % PX] = rok[q] ? rb[q] : 0.0;
+            }
+        }
+    };
+    auto fetch_tab = [&](int k) {
+#pragma unroll
+        for (int q = 0; q < NTB; ++q) {
+            const int t = tid + q * NT;
+            const bool ok = t < TABN && k <= p.nz;
+            rt[q] = st[ok ? (int64_t)k * TABN + t : 0];
+        }
+    };
+    fetch(kbeg - 1);
+    store(kbeg - 1);
+    fetch(kbeg);
+    store(kbeg);
+    fetch(kbeg + 1);
+    fetch_tab(kbeg);
     for (int k = kbeg; k < kend; ++k) {
-        load_plane(k + 1);
-        for (int t = tid; t < 9 * 2 * 27; t += SX * SY) tab[t] = st[(int64_t)k * 9 * 2 * 27 + t];
+        store(k + 1);
+#pragma unroll
+        for (int q = 0; q < NTB; ++q)
+            if (tid + q * NT < TABN) tab[tid + q * NT] = rt[q];
+        if (k + 1 < kend) {
+            fetch(k + 2);
+            fetch_tab(k + 1);
+        }
         __syncthreads();
         if (act) {
             const double* ti = tab + cls * 54;
