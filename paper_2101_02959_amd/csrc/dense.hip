@@ -592,15 +592,16 @@ __global__ __launch_bounds__(kWG) void k_trsm_fwd(const T* __restrict__ Lb, cons
     const int tid = threadIdx.x;
     __shared__ T D[NB][NB + 1];
     __shared__ T X[NB][64 + 1];
+    __shared__ int live[64];
     for (int j0 = 0; j0 < n; j0 += NB) {
         const int jb = min(NB, n - j0);
         for (int idx = tid; idx < NB * NB; idx += kWG) {
             const int i = idx % NB, j = idx / NB;
             D[i][j] = (i < jb && j <= i) ? L[(j0 + i) + (j0 + j) * ld] : (T)0;
         }
-        for (int idx = tid; idx < jb * k; idx += kWG) {
-            const int i = idx % jb, c = idx / jb;
-            X[i][c] = B[(j0 + i) + c * ldb];
+        for (int idx = tid; idx < NB * 64; idx += kWG) {
+            const int i = idx % NB, c = idx / NB;
+            X[i][c] = (i < jb && c < k) ? B[(j0 + i) + c * ldb] : (T)0;
         }
         __syncthreads();
         if (tid < k) {
@@ -615,12 +616,29 @@ __global__ __launch_bounds__(kWG) void k_trsm_fwd(const T* __restrict__ Lb, cons
             const int i = idx % jb, c = idx / jb;
             B[(j0 + i) + c * ldb] = X[i][c];
         }
-        const int t0 = j0 + jb, nrow = n - t0;
-        for (int idx = tid; idx < nrow * k; idx += kWG) {
-            const int r = t0 + idx % nrow, c = idx / nrow;
-            T acc = (T)0;
-            for (int m = 0; m < jb; ++m) acc += L[r + (j0 + m) * ld] * X[m][c];
-            B[r + c * ldb] -= acc;
+        // columns whose solution is still zero (a right-hand side that starts
+        // further down, such as a constraint column) need no update
+        if (tid < 64) {
+            bool nz = false;
+            if (tid < k)
+                for (int i = 0; i < jb; ++i) nz = nz || (X[i][tid] != (T)0);
+            live[tid] = nz ? 1 : 0;
+        }
+        __syncthreads();
+        // rows below the block: each thread loads its row of the column block
+        // once and updates every live right-hand side
+        const int t0 = j0 + jb;
+        for (int r = t0 + tid; r < n; r += kWG) {
+            T lv[NB];
+#pragma unroll
+            for (int m = 0; m < NB; ++m) lv[m] = (m < jb) ? L[r + (j0 + m) * ld] : (T)0;
+            for (int c = 0; c < k; ++c) {
+                if (!live[c]) continue;
+                T acc = (T)0;
+#pragma unroll
+                for (int m = 0; m < NB; ++m) acc += lv[m] * X[m][c];
+                B[r + c * ldb] -= acc;
+            }
         }
         __syncthreads();
     }
