@@ -880,72 +880,64 @@ __global__ __launch_bounds__(kWG) void k_trsv_bwd(const T* __restrict__ Lb, cons
 
 // --------------------------------------------------------- deluxe operators
 // Per face: S_F^j + S_F^k; per edge: sum_m S_E^(m) (Sec. 4.2).  The sum is
-// factored and inverted (Cholesky, triangular inverse, W^T W), and for every
-// sharing subdomain m the operator E_m = S^(m) (sum S)^{-1} is formed:
-// E_m g is the residual-side split and E_m^T u the value-side average term,
-// so the per-iteration deluxe scaling is a set of dense GEMVs.
+// inverted by the symmetric sweep (Gauss-Jordan) operator, which needs no
+// pivoting for an SPD matrix: sweeping pivot k maps
+//   a_ij -> a_ij - a_ik a_kj / a_kk,  a_ik, a_kj -> a_ik / a_kk,  a_kk -> -1 / a_kk,
+// and sweeping every pivot leaves -(sum S)^{-1}; each step is one parallel
+// pass over the matrix.  The matrix lives in LDS when it fits (else in the
+// object's global workspace).  Then, for every sharing subdomain m, the
+// operator E_m = S^(m) (sum S)^{-1} is formed: E_m g is the residual-side
+// split and E_m^T u the value-side average term, so the per-iteration deluxe
+// scaling is a set of dense GEMVs.  A non-positive pivot flags the object.
+constexpr int DLX_MAXN = 512;
+
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_deluxe_setup(ObjDesc o, const T* __restrict__ slots,
-                                                     T* __restrict__ fac, T* __restrict__ inv,
-                                                     T* __restrict__ dmat, int* __restrict__ info) {
+                                                     T* __restrict__ fac, T* __restrict__ dmat,
+                                                     int* __restrict__ info, int lds_cap) {
+    extern __shared__ double dlx_lds[];
+    __shared__ T ck[DLX_MAXN];
+    __shared__ int bad;
     const int ob = blockIdx.x;
     const int n = o.n[ob];
-    T* A = fac + o.fac_off[ob];
-    T* W = inv + o.fac_off[ob];
     const int tid = threadIdx.x;
+    T* M = (n * n <= lds_cap) ? reinterpret_cast<T*>(dlx_lds) : fac + o.fac_off[ob];
+    if (tid == 0) bad = 0;
     for (int idx = tid; idx < n * n; idx += kWG) {
         T acc = (T)0;
         for (int q = o.sh_ptr[ob]; q < o.sh_ptr[ob + 1]; ++q) acc += slots[o.sh_slot[q] + idx];
-        A[idx] = acc;
+        M[idx] = acc;
     }
     __syncthreads();
-    __shared__ int bad;
-    if (tid == 0) bad = 0;
     for (int k = 0; k < n; ++k) {
-        if (tid == 0) {
-            T dk = A[k + k * n];
-            if (!(dk > (T)0)) { bad = 1; dk = (T)1; }
-            A[k + k * n] = sqrt(dk);
+        for (int i = tid; i < n; i += kWG) ck[i] = M[i + k * n];
+        __syncthreads();
+        T d = ck[k];
+        if (!(d > (T)0)) {
+            if (tid == 0) bad = 1;
+            d = (T)1;
         }
-        __syncthreads();
-        const T piv = A[k + k * n];
-        for (int i = k + 1 + tid; i < n; i += kWG) A[i + k * n] /= piv;
-        __syncthreads();
-        const int m = n - k - 1;
-        for (int idx = tid; idx < m * m; idx += kWG) {
-            const int i = k + 1 + idx % m, j = k + 1 + idx / m;
-            if (j <= i) A[i + j * n] -= A[i + k * n] * A[j + k * n];
+        const T rd = (T)1 / d;
+        for (int idx = tid; idx < n * n; idx += kWG) {
+            const int i = idx % n, j = idx / n;
+            const T ci = ck[i], cj = ck[j];
+            T v;
+            if (i == k) v = (j == k) ? -rd : cj * rd;
+            else if (j == k) v = ci * rd;
+            else v = M[idx] - ci * cj * rd;
+            M[idx] = v;
         }
         __syncthreads();
     }
-    // W = L^{-1}, one column per thread (forward substitution)
-    for (int c = tid; c < n; c += kWG) {
-        for (int i = 0; i < n; ++i) {
-            T acc = (i == c) ? (T)1 : (T)0;
-            if (i > c)
-                for (int k = c; k < i; ++k) acc -= A[i + k * n] * W[k + c * n];
-            W[i + c * n] = (i >= c) ? acc / A[i + i * n] : (T)0;
-        }
-    }
-    __syncthreads();
-    // (sum S)^{-1} = W^T W, written over the factor
-    for (int idx = tid; idx < n * n; idx += kWG) {
-        const int i = idx % n, j = idx / n;
-        const int k0 = i > j ? i : j;
-        T acc = (T)0;
-        for (int k = k0; k < n; ++k) acc += W[k + i * n] * W[k + j * n];
-        A[idx] = acc;
-    }
-    __syncthreads();
-    // E_m = S^(m) (sum S)^{-1}
+    // M = -(sum S)^{-1};  E_m = S^(m) (sum S)^{-1} = -S^(m) M
     for (int q = o.sh_ptr[ob]; q < o.sh_ptr[ob + 1]; ++q) {
         const T* S = slots + o.sh_slot[q];
         T* E = dmat + o.sh_slot[q];
         for (int idx = tid; idx < n * n; idx += kWG) {
             const int i = idx % n, j = idx / n;
             T acc = (T)0;
-            for (int k = 0; k < n; ++k) acc += S[i + k * n] * A[k + j * n];
-            E[idx] = acc;
+            for (int k = 0; k < n; ++k) acc += S[i + k * n] * M[k + j * n];
+            E[idx] = -acc;
         }
     }
     if (tid == 0 && bad) info[ob] = 1;
@@ -1020,9 +1012,21 @@ void launch_trsv(hipStream_t s, int nb, bool trans, const T* L, const int64_t* L
         hipLaunchKernelGGL(k_trsv_fwd<T>, dim3(nb), dim3(kWG), lds, s, L, Loff, n, ld, x, xoff);
 }
 template <typename T>
-void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, const T* slots, T* fac, T* inv, T* dmat, int* info) {
-    hipLaunchKernelGGL(k_deluxe_setup<T>, dim3(o.nobj), dim3(kWG), 0, s, o, slots, fac, inv, dmat, info);
+void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, int maxn, const T* slots, T* fac, T* dmat, int* info) {
+    static int lds_max = -1;   // bytes of LDS a workgroup may use on this device
+    if (lds_max < 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            v = 65536;
+        lds_max = v;
+    }
+    const int avail = lds_max - (int)(DLX_MAXN * sizeof(T)) - 64;
+    const int cap = std::max(0, std::min(maxn * maxn, avail / (int)sizeof(T)));
+    hipLaunchKernelGGL(k_deluxe_setup<T>, dim3(o.nobj), dim3(kWG), (size_t)cap * sizeof(T), s, o, slots, fac, dmat,
+                       info, cap);
 }
+int deluxe_max_object() { return DLX_MAXN; }
 
 #define BDM_INST(T)                                                                                     \
     template void launch_assemble<T>(hipStream_t, const BatchDesc&, int, const FEParams&, const double*, \
@@ -1042,7 +1046,7 @@ void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, const T* slots, T* fac
                                          double*, int*);                                                 \
     template void launch_trsv<T>(hipStream_t, int, bool, const T*, const int64_t*, const int*,          \
                                  const int*, T*, const int64_t*, int);                                   \
-    template void launch_deluxe_setup<T>(hipStream_t, const ObjDesc&, const T*, T*, T*, T*, int*);
+    template void launch_deluxe_setup<T>(hipStream_t, const ObjDesc&, int, const T*, T*, T*, int*);
 BDM_INST(double)
 BDM_INST(float)
 #undef BDM_INST

@@ -277,6 +277,7 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
     for (int ob = 0; ob < nobj; ++ob) {
         const Object& O = ob < nF ? topo.faces[ob] : topo.edges[ob - nF];
         on[ob] = 2 * (int)O.nodes.size();
+        maxobjn_ = std::max(maxobjn_, on[ob]);
         if (on[ob] > MAXOBJ) {
             set_error("interface object larger than supported");
             return BDM_E_ARG;
@@ -296,6 +297,10 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
         sh_ptr[ob + 1] = (int)sh_sub.size();
     }
     nslot_ = accSlot; nfac_ = accFac; nyb_ = accY;
+    if (maxobjn_ > deluxe_max_object()) {
+        set_error("a face or edge has more than " + std::to_string(deluxe_max_object()) + " dofs");
+        return BDM_E_ARG;
+    }
     // per-subdomain object lists
     std::vector<int64_t> so_ptr(nsub + 1, 0), so_slot;
     std::vector<int> so_roff, so_n, so_kind, so_nnode, so_eidx;
@@ -616,7 +621,7 @@ int Context::linearize_t() {
     }
     launch_trsm_fwd<T>(stream_, nsub, (const T*)Lrrs_, Lrr_off_, nr_, nr_, (T*)F_, bd_.F_off, nr_, kF_);
     launch_coarse_local<T>(stream_, bd_, (const T*)F_, Svv_, (T*)Z_, (T*)Gi_, Sp_, info_sub_);
-    launch_deluxe_setup<T>(stream_, od_, (const T*)slots_, (T*)fac_, (T*)inv_, (T*)dmat_, info_obj_);
+    launch_deluxe_setup<T>(stream_, od_, maxobjn_, (const T*)slots_, (T*)fac_, (T*)dmat_, info_obj_);
     coarse_.factor(stream_, color_list_, color_ptr_, nP_, Sp_, SP_STRIDE);
     int hb = 0, hc = 0;
     std::vector<int> hs(nsub), ho(od_.nobj);

@@ -122,7 +122,7 @@ class Context {
     SubVecDesc sv_{};
     CoarseDesc cd_{};
     FetiDesc fd_{};
-    int maxbox_ = 0, maxG_ = 0, maxnI_ = 0, maxnr_ = 0, nInodes_ = 0;
+    int maxbox_ = 0, maxG_ = 0, maxnI_ = 0, maxnr_ = 0, maxobjn_ = 0, nInodes_ = 0;
     void* Wbuf_ = nullptr;
     int *Ilist_ = nullptr;
     int64_t *LII_off_ = nullptr, *Lrr_off_ = nullptr, *xI_off_ = nullptr, *xr_off_ = nullptr;
