@@ -884,7 +884,7 @@ __global__ __launch_bounds__(kWG) void k_trsv_bwd(const T* __restrict__ Lb, cons
 // pivoting for an SPD matrix: sweeping pivot k maps
 //   a_ij -> a_ij - a_ik a_kj / a_kk,  a_ik, a_kj -> a_ik / a_kk,  a_kk -> -1 / a_kk,
 // and sweeping every pivot leaves -(sum S)^{-1}; each step is one parallel
-// pass over the matrix.  The matrix lives in LDS when it fits (else in the
+// pass over the matrix (the matrix is symmetric, so row k equals column k).  The matrix lives in LDS when it fits (else in the
 // object's global workspace).  Then, for every sharing subdomain m, the
 // operator E_m = S^(m) (sum S)^{-1} is formed: E_m g is the residual-side
 // split and E_m^T u the value-side average term, so the per-iteration deluxe
@@ -929,15 +929,38 @@ __global__ __launch_bounds__(kWG) void k_deluxe_setup(ObjDesc o, const T* __rest
         }
         __syncthreads();
     }
-    // M = -(sum S)^{-1};  E_m = S^(m) (sum S)^{-1} = -S^(m) M
-    for (int q = o.sh_ptr[ob]; q < o.sh_ptr[ob + 1]; ++q) {
+    // M = -(sum S)^{-1};  E_m = S^(m) (sum S)^{-1} = -S^(m) M on MFMA 16x16x4
+    // tiles (one wave per tile, S^(m) streamed from L2, M from LDS), for all
+    // shares but the last; the E_m sum to the identity, which gives the last.
+    const int wv = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+    const int q0 = o.sh_ptr[ob], q1 = o.sh_ptr[ob + 1];
+    const int nt = (n + 15) / 16;
+    for (int q = q0; q < q1 - 1; ++q) {
         const T* S = slots + o.sh_slot[q];
         T* E = dmat + o.sh_slot[q];
+        for (int tile = wv; tile < nt * nt; tile += kWG / 64) {
+            const int i = (tile % nt) * 16 + lr, j = (tile / nt) * 16 + lr;
+            typename Mfma<T>::acc acc = {0, 0, 0, 0};
+            for (int k0 = 0; k0 < n; k0 += 4) {
+                const int k = k0 + lk;
+                const T a = (i < n && k < n) ? S[i + k * n] : (T)0;
+                const T b = (k < n && j < n) ? M[k + j * n] : (T)0;
+                acc = Mfma<T>::mac(a, b, acc);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = (tile % nt) * 16 + Mfma<T>::row(lane, v);
+                if (r < n && j < n) E[r + j * n] = -acc[v];
+            }
+        }
+    }
+    __syncthreads();
+    {
+        T* E = dmat + o.sh_slot[q1 - 1];
         for (int idx = tid; idx < n * n; idx += kWG) {
-            const int i = idx % n, j = idx / n;
-            T acc = (T)0;
-            for (int k = 0; k < n; ++k) acc += S[i + k * n] * M[k + j * n];
-            E[idx] = -acc;
+            T acc = (idx % n == idx / n) ? (T)1 : (T)0;
+            for (int q = q0; q < q1 - 1; ++q) acc -= dmat[o.sh_slot[q] + idx];
+            E[idx] = acc;
         }
     }
     if (tid == 0 && bad) info[ob] = 1;
