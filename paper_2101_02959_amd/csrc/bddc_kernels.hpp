@@ -86,6 +86,14 @@ void launch_take_first(hipStream_t s, const ObjDesc& o, int64_t N, const T* xr, 
 void launch_dot(hipStream_t s, int64_t n, const double* x, const double* y, double* partial, double* out);
 void launch_axpy(hipStream_t s, int64_t n, double a, const double* x, double* y);
 void launch_copy(hipStream_t s, int64_t n, const double* x, double* y);
+// device-scalar and capture-safe vector operations (graph-captured PCG)
+void launch_axpy_dev(hipStream_t s, int64_t n, const double* a, double sgn, const double* x, double* y);
+void launch_scale_add_dev(hipStream_t s, int64_t n, const double* z, const double* b, double* p);
+void launch_fill(hipStream_t s, int64_t n, double v, double* x);
+void launch_copy_kernel(hipStream_t s, int64_t n, const double* x, double* y);
+void launch_pcg_alpha(hipStream_t s, double* sc);
+void launch_pcg_check(hipStream_t s, double* sc, double* hist, double* ah, int maxit);
+void launch_pcg_beta(hipStream_t s, double* sc, double* bh);
 void launch_scale_add(hipStream_t s, int64_t n, const double* z, double b, double* p);  // p = z + b p
 void launch_sub_mean(hipStream_t s, int64_t n, double* x, double* partial, double* tmp);
 int dot_partials();

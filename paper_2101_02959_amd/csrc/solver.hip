@@ -3,6 +3,7 @@
 // fe.hip, dense.hip, bddc.hip and vec.hip; this file builds the index maps,
 // owns the device workspace and sequences the launches.
 #include "solver.hpp"
+#include "pcg_slots.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -96,6 +97,8 @@ const char* last_error() { return g_err.c_str(); }
     } while (0)
 
 Context::~Context() {
+    if (kry_exec_) hipGraphExecDestroy(kry_exec_);
+    if (kry_stream_) hipStreamDestroy(kry_stream_);
     for (void* p : allocs_) hipFree(p);
 }
 
@@ -417,6 +420,15 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
     Rt_ = (double*)dalloc(2 * vb);
     part_ = (double*)dalloc(dot_partials() * sizeof(double));
     scal_ = (double*)dalloc(8 * sizeof(double));
+    kry_hcap_ = std::max(opts.krylov_maxit, 1) + 1;
+    kry_sc_ = (double*)dalloc(PCG_NSLOT * sizeof(double));
+    kry_hist_ = (double*)dalloc((kry_hcap_ + 1) * sizeof(double));
+    kry_ah_ = (double*)dalloc(kry_hcap_ * sizeof(double));
+    kry_bh_ = (double*)dalloc(kry_hcap_ * sizeof(double));
+    if (!kry_sc_ || !kry_hist_ || !kry_ah_ || !kry_bh_) {
+        set_error("device allocation failed (Krylov history)");
+        return BDM_E_OOM;
+    }
     if (!v_ || !ue_ || !w_ || !kx_ || !R_ || !Rt_ || !part_ || !scal_) {
         set_error("device allocation failed (global vectors)");
         return BDM_E_OOM;
@@ -665,7 +677,7 @@ void Context::dirichlet(const double* r, const double* q, double* out) {
 // g = r - sum_j R_j^T K_GI K_II^{-1} r_I (interface rows of g are used)
 template <typename T>
 void Context::condense(const double* r, double* g) {
-    hipMemsetAsync(t1_, 0, 2 * N * sizeof(double), stream_);
+    launch_fill(stream_, 2 * N, 0.0, t1_);
     dirichlet<T>(r, nullptr, t1_);
     launch_res_minus_jac(stream_, fp, st_, dg_, t1_, r, g);
 }
@@ -708,7 +720,7 @@ int Context::bddc_apply_t(const double* r, double* z) {
     condense<T>(r, t2_);
     launch_deluxe_res<T>(stream_, od_, N, t2_, (const T*)dmat_, (T*)xr_, xr_off_);
     stilde_inv<T>((T*)xr_, t2_, cb_);
-    HIPOK(hipMemsetAsync(t3_, 0, 2 * N * sizeof(double), stream_));
+    launch_fill(stream_, 2 * N, 0.0, t3_);
     launch_deluxe_val<T>(stream_, od_, N, (const T*)dmat_, (const T*)xr_, xr_off_, t3_);
     launch_vertex_val(stream_, cd_.nverts, cd_.vnode, N, cb_, t3_);
     interior_extend<T>(r, t3_);
@@ -757,7 +769,7 @@ int Context::fetidp_apply_t(int op, const double* in, double* out) {
             launch_feti_BT<T>(stream_, od_, fd_, in + 2 * N, xr2, xr_off_);
             hipLaunchKernelGGL(k_sub_t<T>, dim3(nb(nxr_, 256)), dim3(256), 0, stream_, nxr_, (const T*)xr2, xr);
             stilde_inv<T>(xr, t2_, cb_);
-            HIPOK(hipMemsetAsync(t3_, 0, 2 * N * sizeof(double), stream_));
+            launch_fill(stream_, 2 * N, 0.0, t3_);
             launch_take_first<T>(stream_, od_, N, xr, xr_off_, t3_);
             launch_vertex_val(stream_, cd_.nverts, cd_.vnode, N, cb_, t3_);
             interior_extend<T>(in, t3_);
@@ -768,6 +780,120 @@ int Context::fetidp_apply_t(int op, const double* in, double* out) {
             set_error("unknown FETI-DP operator");
             return BDM_E_ARG;
     }
+}
+
+// The same PCG with one iteration captured as a HIP graph and replayed: the
+// scalars (alpha, beta, norms, state) stay on the device, the body has no
+// host synchronisation and no memset nodes, and the host reads the state
+// back once per replay.  Identical arithmetic, kernels and order to pcg().
+int Context::pcg_graph(int n, const double* b, double* x, bool feti, KrylovOut& out) {
+    out = KrylovOut();
+    const int maxit = opts.krylov_maxit;
+    if (maxit > kry_hcap_) {
+        set_error("krylov_maxit exceeds the graph iteration history");
+        return BDM_E_ARG;
+    }
+    auto A = [&](const double* in, double* o) -> int {
+        if (feti) return prec_ ? fetidp_apply_t<float>(BDM_FETI_F, in, o) : fetidp_apply_t<double>(BDM_FETI_F, in, o);
+        launch_jac_apply(stream_, fp, st_, dg_, in, o);
+        return 0;
+    };
+    auto M = [&](const double* in, double* o) -> int {
+        if (feti)
+            return prec_ ? fetidp_apply_t<float>(BDM_FETI_PRECOND, in, o)
+                         : fetidp_apply_t<double>(BDM_FETI_PRECOND, in, o);
+        return prec_ ? bddc_apply_t<float>(in, o) : bddc_apply_t<double>(in, o);
+    };
+    // set-up, eager
+    launch_fill(stream_, n, 0.0, x);
+    launch_copy_kernel(stream_, n, b, kr_);
+    const double r0 = std::sqrt(dot(n, kr_, kr_));
+    out.hist.push_back(r0);
+    if (r0 == 0.0) return 0;
+    int rc = M(kr_, kz_);
+    if (rc) return rc;
+    launch_copy_kernel(stream_, n, kz_, kp_);
+    launch_dot(stream_, n, kr_, kz_, part_, kry_sc_ + PCG_RZ);
+    {
+        double init[PCG_NSLOT] = {0};
+        init[PCG_STATE] = PCG_RUNNING;
+        init[PCG_IT] = 0;
+        init[PCG_TOL] = opts.krylov_rtol * r0;
+        init[PCG_DTOL] = opts.krylov_dtol * r0;
+        // keep PCG_RZ (computed on the device above): copy the other slots only
+        HIPOK(hipMemcpyAsync(kry_sc_ + PCG_PQ, init + PCG_PQ, (PCG_NSLOT - PCG_PQ) * sizeof(double),
+                             hipMemcpyHostToDevice, stream_));
+        HIPOK(hipStreamSynchronize(stream_));   // init lives on this host stack
+    }
+    // capture the iteration body once per (operator, size)
+    const int key = (feti ? 1 : 0) + 2 * n;
+    if (!kry_exec_ || kry_key_ != key) {
+        if (kry_exec_) {
+            hipGraphExecDestroy(kry_exec_);
+            kry_exec_ = nullptr;
+        }
+        if (!kry_stream_) HIPOK(hipStreamCreateWithFlags(&kry_stream_, hipStreamNonBlocking));
+        HIPOK(hipStreamSynchronize(stream_));
+        hipStream_t saved = stream_;
+        stream_ = kry_stream_;
+        HIPOK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
+        int brc = A(kp_, kq_);
+        if (!brc) {
+            launch_dot(stream_, n, kp_, kq_, part_, kry_sc_ + PCG_PQ);
+            launch_pcg_alpha(stream_, kry_sc_);
+            launch_axpy_dev(stream_, n, kry_sc_ + PCG_ALPHA, 1.0, kp_, x);
+            launch_copy_kernel(stream_, n, kr_, kro_);
+            launch_axpy_dev(stream_, n, kry_sc_ + PCG_ALPHA, -1.0, kq_, kr_);
+            launch_dot(stream_, n, kr_, kr_, part_, kry_sc_ + PCG_RN2);
+            launch_pcg_check(stream_, kry_sc_, kry_hist_, kry_ah_, maxit);
+            brc = M(kr_, kz_);
+        }
+        if (!brc) {
+            launch_dot(stream_, n, kz_, kr_, part_, kry_sc_ + PCG_ZR);
+            launch_dot(stream_, n, kz_, kro_, part_, kry_sc_ + PCG_ZRO);
+            launch_pcg_beta(stream_, kry_sc_, kry_bh_);
+            launch_scale_add_dev(stream_, n, kz_, kry_sc_ + PCG_BETA, kp_);
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(stream_, &g);
+        stream_ = saved;
+        if (brc) {
+            if (g) hipGraphDestroy(g);
+            return brc;
+        }
+        HIPOK(ce);
+        const hipError_t ie = hipGraphInstantiate(&kry_exec_, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        HIPOK(ie);
+        kry_key_ = key;
+        kry_x_ = x;
+    }
+    // the body writes x: its pointer is part of the captured graph
+    if (x != kry_x_) {
+        set_error("internal error: graph PCG called with a different solution vector");
+        return BDM_E_STATE;
+    }
+    double st[2] = {PCG_RUNNING, 0.0};
+    for (int it = 0; it < maxit; ++it) {
+        HIPOK(hipGraphLaunch(kry_exec_, stream_));
+        HIPOK(hipMemcpyAsync(st, kry_sc_ + PCG_STATE, 2 * sizeof(double), hipMemcpyDeviceToHost, stream_));
+        HIPOK(hipStreamSynchronize(stream_));
+        if (st[0] != PCG_RUNNING) break;
+    }
+    const int its = (int)st[1];
+    out.its = its;
+    out.status = (st[0] == PCG_CONVERGED) ? 0 : (st[0] == PCG_DIVERGED ? 2 : 1);
+    std::vector<double> h(its + 1), a(its), bb(std::max(its - 1, 0));
+    HIPOK(hipMemcpyAsync(h.data(), kry_hist_, (its + 1) * sizeof(double), hipMemcpyDeviceToHost, stream_));
+    if (its) HIPOK(hipMemcpyAsync(a.data(), kry_ah_, its * sizeof(double), hipMemcpyDeviceToHost, stream_));
+    if (its > 1) HIPOK(hipMemcpyAsync(bb.data(), kry_bh_, (its - 1) * sizeof(double), hipMemcpyDeviceToHost, stream_));
+    HIPOK(hipStreamSynchronize(stream_));
+    h[0] = r0;
+    out.hist = h;
+    out.alpha = a;
+    out.beta = bb;
+    out.cond = lanczos_cond(out.alpha, out.beta);
+    return 0;
 }
 
 // PCG (zero initial guess, unpreconditioned residual norm test, Polak-Ribiere
@@ -822,18 +948,22 @@ int Context::pcg(int n, const double* b, double* x, bool feti, KrylovOut& out) {
     return 0;
 }
 
+int Context::krylov(int n, const double* b, double* x, bool feti, KrylovOut& out) {
+    return opts.krylov_graph ? pcg_graph(n, b, x, feti, out) : pcg(n, b, x, feti, out);
+}
+
 // J s = b with the configured preconditioner.
 int Context::newton_solve(const double* b, double* s, KrylovOut& out) {
     // project the u_e block of b onto the range (zero sum)
     HIPOK(hipMemcpyAsync(Rt_, b, 2 * N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
     launch_sub_mean(stream_, N, Rt_ + N, part_, scal_);
-    if (opts.solver != BDM_SOLVER_FETIDP) return pcg((int)(2 * N), Rt_, s, false, out);
+    if (opts.solver != BDM_SOLVER_FETIDP) return krylov((int)(2 * N), Rt_, s, false, out);
     // FETI-DP: d = B S~^{-1} f~, PCG on F lambda = d, then recovery.
     int rc = prec_ ? fetidp_apply_t<float>(BDM_FETI_RHS, Rt_, kq_) : fetidp_apply_t<double>(BDM_FETI_RHS, Rt_, kq_);
     if (rc) return rc;
     double* d = S_;   // S_ is free until the solution is written
     HIPOK(hipMemcpyAsync(d, kq_, nlam_ * sizeof(double), hipMemcpyDeviceToDevice, stream_));
-    rc = pcg((int)nlam_, d, kx_, true, out);
+    rc = krylov((int)nlam_, d, kx_, true, out);
     if (rc) return rc;
     // recover: input [b ; lambda]
     HIPOK(hipMemcpyAsync(kq_, Rt_, 2 * N * sizeof(double), hipMemcpyDeviceToDevice, stream_));

@@ -79,6 +79,8 @@ class Context {
     template <typename T> int bddc_apply_t(const double* r, double* z);
     template <typename T> int fetidp_apply_t(int op, const double* in, double* out);
     int pcg(int n, const double* b, double* x, bool feti, KrylovOut& out);
+    int pcg_graph(int n, const double* b, double* x, bool feti, KrylovOut& out);
+    int krylov(int n, const double* b, double* x, bool feti, KrylovOut& out);
     int newton_solve(const double* b, double* s, KrylovOut& out);
     int sync();
     double dot(int64_t n, const double* x, const double* y);
@@ -144,6 +146,12 @@ class Context {
     double *t1_ = nullptr, *t2_ = nullptr, *t3_ = nullptr, *gzero_ = nullptr;
     double *R_ = nullptr, *S_ = nullptr, *U_ = nullptr, *Rt_ = nullptr;
     double *part_ = nullptr, *scal_ = nullptr;
+    // graph-captured PCG: device scalars and histories, the cached graph
+    double *kry_sc_ = nullptr, *kry_hist_ = nullptr, *kry_ah_ = nullptr, *kry_bh_ = nullptr;
+    int kry_hcap_ = 0, kry_key_ = -1;
+    double* kry_x_ = nullptr;
+    hipGraphExec_t kry_exec_ = nullptr;
+    hipStream_t kry_stream_ = nullptr;
 };
 
 void set_error(const std::string& msg);

@@ -3,6 +3,7 @@
 // they are deterministic.
 #include "bddc_kernels.hpp"
 #include "common.hpp"
+#include "pcg_slots.hpp"
 
 namespace bdm {
 
@@ -68,9 +69,85 @@ __global__ __launch_bounds__(kWG) void k_sum_partial(int64_t n, const double* __
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
+// Device-scalar variants for the graph-captured Krylov iteration.
+__global__ void k_axpy_dev(int64_t n, const double* __restrict__ a, double sgn, const double* __restrict__ x,
+                           double* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = fma(sgn * a[0], x[i], y[i]);
+}
+
+__global__ void k_scale_add_dev(int64_t n, const double* __restrict__ z, const double* __restrict__ b,
+                                double* __restrict__ p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = fma(b[0], p[i], z[i]);
+}
+
+__global__ void k_fill(int64_t n, double v, double* __restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+__global__ void k_copy(int64_t n, const double* __restrict__ x, double* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = x[i];
+}
+
+// PCG scalar steps on device (slots in pcg_slots.hpp order).  Once the state
+// is no longer PCG_RUNNING the iteration is frozen: alpha = beta = 0, so x and
+// r stop changing while the captured body keeps being replayed.
+__global__ void k_pcg_alpha(double* __restrict__ sc) {
+    // a breakdown (p . q = 0) gives a non-finite alpha and residual, which the
+    // check below reports as divergence, as the host-driven loop does
+    sc[PCG_ALPHA] = (sc[PCG_STATE] == PCG_RUNNING) ? sc[PCG_RZ] / sc[PCG_PQ] : 0.0;
+}
+
+__global__ void k_pcg_check(double* __restrict__ sc, double* __restrict__ hist, double* __restrict__ ah,
+                            int maxit) {
+    if (sc[PCG_STATE] != PCG_RUNNING) return;
+    const int it = (int)sc[PCG_IT];
+    const double rn = sqrt(sc[PCG_RN2]);
+    ah[it] = sc[PCG_ALPHA];
+    hist[it + 1] = rn;
+    sc[PCG_IT] = it + 1;
+    if (!(rn == rn) || rn > sc[PCG_DTOL]) sc[PCG_STATE] = PCG_DIVERGED;
+    else if (rn <= sc[PCG_TOL]) sc[PCG_STATE] = PCG_CONVERGED;
+    else if (it + 1 >= maxit) sc[PCG_STATE] = PCG_MAXIT;
+}
+
+__global__ void k_pcg_beta(double* __restrict__ sc, double* __restrict__ bh) {
+    double b = 0.0;
+    if (sc[PCG_STATE] == PCG_RUNNING) {
+        // Polak-Ribiere: (z_new . r_new - z_new . r_old) / (z_old . r_old)
+        b = (sc[PCG_ZR] - sc[PCG_ZRO]) / sc[PCG_RZ];
+        sc[PCG_RZ] = sc[PCG_ZR];
+        bh[(int)sc[PCG_IT] - 1] = b;
+    }
+    sc[PCG_BETA] = b;
+}
+
 }  // namespace
 
 static inline unsigned nb(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+void launch_axpy_dev(hipStream_t s, int64_t n, const double* a, double sgn, const double* x, double* y) {
+    hipLaunchKernelGGL(k_axpy_dev, dim3(nb(n, 256)), dim3(256), 0, s, n, a, sgn, x, y);
+}
+void launch_scale_add_dev(hipStream_t s, int64_t n, const double* z, const double* b, double* p) {
+    hipLaunchKernelGGL(k_scale_add_dev, dim3(nb(n, 256)), dim3(256), 0, s, n, z, b, p);
+}
+void launch_fill(hipStream_t s, int64_t n, double v, double* x) {
+    if (n > 0) hipLaunchKernelGGL(k_fill, dim3(nb(n, 256)), dim3(256), 0, s, n, v, x);
+}
+void launch_copy_kernel(hipStream_t s, int64_t n, const double* x, double* y) {
+    if (n > 0) hipLaunchKernelGGL(k_copy, dim3(nb(n, 256)), dim3(256), 0, s, n, x, y);
+}
+void launch_pcg_alpha(hipStream_t s, double* sc) { hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(1), 0, s, sc); }
+void launch_pcg_check(hipStream_t s, double* sc, double* hist, double* ah, int maxit) {
+    hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(1), 0, s, sc, hist, ah, maxit);
+}
+void launch_pcg_beta(hipStream_t s, double* sc, double* bh) {
+    hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(1), 0, s, sc, bh);
+}
 
 void launch_dot(hipStream_t s, int64_t n, const double* x, const double* y, double* partial, double* out) {
     hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(kWG), 0, s, n, x, y, partial);
