@@ -90,9 +90,11 @@ typedef struct bdm_opts {
     int solver;                 /* BDM_SOLVER_*                              */
     int precision;              /* BDM_PREC_*: local factors in FP64 or FP32 */
     int guess;                  /* BDM_GUESS_*                               */
-    int krylov_graph;           /* 1: each PCG iteration is one replay of a  */
-                                /* captured HIP graph with device scalars    */
-                                /* (same arithmetic); 0: host-driven loop    */
+    int krylov_graph;           /* 1: each PCG iteration replays captured    */
+                                /* HIP graphs (operator half, then the       */
+                                /* preconditioner half while running) with   */
+                                /* device scalars, same arithmetic and       */
+                                /* iterates; 0: host-driven loop             */
 } bdm_opts;
 
 /* Per-step statistics filled by bdm_step (for its last step). */

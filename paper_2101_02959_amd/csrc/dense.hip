@@ -291,7 +291,7 @@ __global__ __launch_bounds__(kWG) void k_potrf(T* __restrict__ A, const int64_t*
 //                workgroup: X L_JJ^T = P by block forward substitution,
 //                X_b = (P_b - sum_{c<b} X_c L_bc^T) W_b^T, on MFMA.
 // The update of the columns right of the panel is left to k_syrk_batched.
-constexpr int PT_RB = 64, PT_XS = NBO + 4;
+constexpr int PT_RB = 64, PT_XS = NBO + 4, PT_XCD = 8;
 
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_panel_diag(T* __restrict__ A, const int64_t* __restrict__ off,
@@ -307,36 +307,75 @@ __global__ __launch_bounds__(kWG) void k_panel_diag(T* __restrict__ A, const int
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_panel_trsm(T* __restrict__ Abase, const int64_t* __restrict__ off,
                                                    const int* __restrict__ ldv, const int* __restrict__ nIv,
-                                                   const int* __restrict__ nv, int J, const T* __restrict__ Wbuf) {
+                                                   const int* __restrict__ nv, int nsub, int rowblocks, int J,
+                                                   const T* __restrict__ Wbuf) {
     __shared__ T Xs[PT_RB][PT_XS];
     __shared__ T Ls[NB][NB + 1];
-    const int s = blockIdx.y;
+    // all row blocks of one matrix run on one XCD (dispatch assigns
+    // consecutive ids round robin to the 8 XCDs), so its factor blocks are
+    // fetched from HBM once and then served by that XCD's L2
+    const int g = blockIdx.x, q = g / PT_XCD;
+    const int s = (q / rowblocks) * PT_XCD + g % PT_XCD;
+    const int rb = q % rowblocks;
+    if (s >= nsub) return;
     const int nI = nIv[s], n = nv[s];
     if (J >= nI) return;
     const int w = min(NBO, nI - J);
-    const int R0 = J + w + blockIdx.x * PT_RB;
+    const int R0 = J + w + rb * PT_RB;
     if (R0 >= n) return;
     const int rows = min(PT_RB, n - R0);
     T* A = Abase + off[s];
     const int64_t ld = ldv[s];
     const T* W = Wbuf + (int64_t)s * NBO * NB;
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
-    for (int idx = tid; idx < PT_RB * NBO; idx += kWG) {
-        const int r = idx % PT_RB, c = idx / PT_RB;
-        Xs[r][c] = (r < rows && c < w) ? A[(R0 + r) + (int64_t)(J + c) * ld] : (T)0;
+    const int nb = (w + NB - 1) / NB;   // 32-column blocks of this panel
+    // Every global read is issued up front into registers: the rows of the
+    // panel (XPT values per thread) and, for each 32-column block b, the
+    // factor blocks L_bc (c < b) and the inverse W_b of the diagonal factor
+    // (BPT values per thread and block).  Addresses are clamped into the
+    // panel; out-of-range entries are zeroed when they are written to LDS.
+    constexpr int XPT = PT_RB * NBO / kWG, BPT = NB * NB / kWG, NLB = NBO / NB * (NBO / NB - 1) / 2;
+    T xr[XPT], lb[NLB][BPT], wb[NBO / NB][BPT];
+#pragma unroll
+    for (int e = 0; e < XPT; ++e) {
+        const int idx = tid + e * kWG, r = idx % PT_RB, c = idx / PT_RB;
+        xr[e] = A[(R0 + min(r, rows - 1)) + (int64_t)(J + min(c, w - 1)) * ld];
     }
-    const int nb = (w + NB - 1) / NB;
-    for (int b = 0; b < nb; ++b) {
+#pragma unroll
+    for (int b = 1; b < NBO / NB; ++b)
+#pragma unroll
+        for (int c = 0; c < b; ++c)
+#pragma unroll
+            for (int e = 0; e < BPT; ++e) {
+                const int idx = tid + e * kWG, i = idx % NB, j = idx / NB;
+                const int gi = min(NB * b + i, w - 1), gj = min(NB * c + j, w - 1);
+                lb[b * (b - 1) / 2 + c][e] = A[(J + gi) + (int64_t)(J + gj) * ld];
+            }
+#pragma unroll
+    for (int b = 0; b < NBO / NB; ++b)
+#pragma unroll
+        for (int e = 0; e < BPT; ++e) wb[b][e] = W[(int64_t)b * NB * NB + tid + e * kWG];
+    // keep every load above this point (the blocks are all consumed below
+    // without branches: blocks at or beyond nb are zero and never stored)
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int e = 0; e < XPT; ++e) {
+        const int idx = tid + e * kWG, r = idx % PT_RB, c = idx / PT_RB;
+        Xs[r][c] = (r < rows && c < w) ? xr[e] : (T)0;
+    }
+#pragma unroll
+    for (int b = 0; b < NBO / NB; ++b) {
         typename Mfma<T>::acc acc[2];
         acc[0] = (typename Mfma<T>::acc){0, 0, 0, 0};
         acc[1] = acc[0];
         // acc = sum_{c<b} X_c L_bc^T  (wave wv: rows 16 wv .. 16 wv + 15, 32 columns)
+#pragma unroll
         for (int c = 0; c < b; ++c) {
             __syncthreads();
-            for (int idx = tid; idx < NB * NB; idx += kWG) {
-                const int i = idx % NB, j = idx / NB;   // L_bc[i][j] = L[J + 32 b + i][J + 32 c + j]
-                const int gi = NB * b + i, gj = NB * c + j;
-                Ls[i][j] = (gi < w && gj < w) ? A[(J + gi) + (int64_t)(J + gj) * ld] : (T)0;
+#pragma unroll
+            for (int e = 0; e < BPT; ++e) {
+                const int idx = tid + e * kWG, i = idx % NB, j = idx / NB;
+                Ls[i][j] = (NB * b + i < w && NB * c + j < w) ? lb[b * (b - 1) / 2 + c][e] : (T)0;
             }
             __syncthreads();
 #pragma unroll
@@ -352,9 +391,10 @@ __global__ __launch_bounds__(kWG) void k_panel_trsm(T* __restrict__ Abase, const
         for (int h = 0; h < 2; ++h)
 #pragma unroll
             for (int v = 0; v < 4; ++v) Xs[16 * wv + Mfma<T>::row(lane, v)][NB * b + 16 * h + lr] -= acc[h][v];
-        for (int idx = tid; idx < NB * NB; idx += kWG) {
-            const int i = idx % NB, j = idx / NB;
-            Ls[i][j] = W[(int64_t)b * NB * NB + i + j * NB];
+#pragma unroll
+        for (int e = 0; e < BPT; ++e) {
+            const int idx = tid + e * kWG, i = idx % NB, j = idx / NB;
+            Ls[i][j] = (b < nb) ? wb[b][e] : (T)0;
         }
         __syncthreads();
         acc[0] = (typename Mfma<T>::acc){0, 0, 0, 0};
@@ -386,7 +426,7 @@ __global__ __launch_bounds__(kWG) void k_panel_trsm(T* __restrict__ Abase, const
 //   SY_SCHUR  after the last panel: cb = nI, ce = re = n, k = [0, nI), which
 //             turns K_GG into S_Gamma = K_GG - L_GI L_GI^T (Sec. 4.1).
 // 128x128 output tiles per workgroup (64x64 per wave, 4x4 MFMA 16x16x4
-// blocks), the inner dimension staged through LDS in chunks of 16 columns
+// blocks), the inner dimension staged through LDS in chunks of 32 columns
 // with a register prefetch of the next chunk.  The workgroup id is mapped so
 // that all tiles of one subdomain run on the same XCD (dispatch assigns
 // consecutive ids round robin to the 8 XCDs), which keeps P in that XCD's L2.
@@ -430,35 +470,57 @@ __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, con
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
     const int wr = wv & 1, wc = wv >> 1;                 // wave's 64x64 quadrant (rows i, cols j)
     const bool active = !(ti == tj && wr < wc);          // strictly upper quadrant of a diagonal tile
-    // each thread stages SY_EPT elements of each operand per chunk: row tid % 128, k = tid / 128 + 2 e
+    // each thread stages SY_EPT elements of each operand per chunk: row tid % 128, k = tid / 128 + 2 e.
+    // The loads are branch-free: rows beyond the trapezoid are clamped to its
+    // last row (they only reach outputs that are never stored) and the inner
+    // index to k1 - 1; the k mask is applied when the chunk is written to LDS,
+    // so no load has to complete before the next one is issued.
     const int lrow = tid % SY_TM, lk0 = tid / SY_TM;
-    const int ri = I0 + lrow, rj = J0 + lrow;
+    const int ri = min(I0 + lrow, re - 1), rj = min(J0 + lrow, ce - 1);
     T pa[SY_EPT], pb[SY_EPT];
     auto fetch = [&](int kc) {
 #pragma unroll
         for (int e = 0; e < SY_EPT; ++e) {
-            const int k = kc + lk0 + 2 * e;
-            const bool kin = k < k1;
-            pa[e] = (kin && ri < re) ? A[ri + (int64_t)k * ld] : (T)0;
-            pb[e] = (kin && rj < ce) ? A[rj + (int64_t)k * ld] : (T)0;
+            const int64_t k = min(kc + lk0 + 2 * e, k1 - 1);
+            pa[e] = A[ri + k * ld];
+            pb[e] = A[rj + k * ld];
         }
     };
-    // FP32: each chunk of SY_KC inner indices is summed on its own and then added
-    // to a running total, so rounding grows with the number of chunks plus
-    // the chunk length rather than with the whole inner dimension.
+    // FP64: the output tile starts from C, loaded in the accumulator layout
+    // before the first chunk so that its latency overlaps the first fetch of
+    // P; the column operand is staged negated, so the chunks add -P P^T and
+    // the tile is stored without reading it again (this also keeps the
+    // kernel at two waves per SIMD).  FP32: each chunk of SY_KC inner indices
+    // is summed on its own and added to a running total that starts at zero
+    // and is subtracted from C at the end, so rounding grows with the number
+    // of chunks plus the chunk length rather than with the whole inner
+    // dimension.
     constexpr bool two_level = std::is_same<T, float>::value;
+    const T sgn = two_level ? (T)1 : (T)-1;
     typename Mfma<T>::acc acc[4][4], tot[4][4];
+    auto c_at = [&](int a, int b, int v) -> T {       // C entry of accumulator (b, a, v), clamped address
+        const int i = min(I0 + wr * 64 + 16 * a + lr, re - 1);
+        const int j = min(J0 + wc * 64 + 16 * b + Mfma<T>::row(lane, v), ce - 1);
+        return A[i + (int64_t)j * ld];
+    };
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int a = 0; a < 4; ++a) acc[b][a] = tot[b][a] = (typename Mfma<T>::acc){0, 0, 0, 0};
+        for (int a = 0; a < 4; ++a) {
+            acc[b][a] = tot[b][a] = (typename Mfma<T>::acc){0, 0, 0, 0};
+            if (!two_level && active) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[b][a][v] = c_at(a, b, v);
+            }
+        }
     fetch(k0);
     for (int kc = k0; kc < k1; kc += SY_KC) {
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < SY_EPT; ++e) {
-            As[lk0 + 2 * e][lrow] = pa[e];
-            Bs[lk0 + 2 * e][lrow] = pb[e];
+            const bool kin = kc + lk0 + 2 * e < k1;
+            As[lk0 + 2 * e][lrow] = kin ? pa[e] : (T)0;
+            Bs[lk0 + 2 * e][lrow] = kin ? sgn * pb[e] : (T)0;
         }
         __syncthreads();
         if (kc + SY_KC < k1) fetch(kc + SY_KC);
@@ -489,6 +551,14 @@ __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, con
         }
     }
     if (!active) return;
+    if (two_level) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) tot[b][a][v] = c_at(a, b, v) - tot[b][a][v];
+    }
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -497,8 +567,7 @@ __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, con
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int j = J0 + wc * 64 + 16 * b + Mfma<T>::row(lane, v);
-                const T upd = two_level ? tot[b][a][v] : acc[b][a][v];
-                if (i < re && j < ce && j <= i) A[i + (int64_t)j * ld] -= upd;
+                if (i < re && j < ce && j <= i) A[i + (int64_t)j * ld] = two_level ? tot[b][a][v] : acc[b][a][v];
             }
         }
 }
@@ -984,8 +1053,11 @@ void launch_interior_panel(hipStream_t s, int nb, T* A, const int64_t* off, cons
                            const int* n, int J, T* Wbuf, int rowblocks, int* info) {
     if (nb <= 0) return;
     hipLaunchKernelGGL(k_panel_diag<T>, dim3(nb), dim3(kWG), 0, s, A, off, ld, nI, J, Wbuf, info);
-    if (rowblocks > 0)
-        hipLaunchKernelGGL(k_panel_trsm<T>, dim3(rowblocks, nb), dim3(kWG), 0, s, A, off, ld, nI, n, J, Wbuf);
+    if (rowblocks > 0) {
+        const int groups = (nb + PT_XCD - 1) / PT_XCD;
+        hipLaunchKernelGGL(k_panel_trsm<T>, dim3(groups * rowblocks * PT_XCD), dim3(kWG), 0, s, A, off, ld, nI, n, nb,
+                           rowblocks, J, Wbuf);
+    }
 }
 template <typename T>
 void launch_syrk_update(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* nI, const int* n,

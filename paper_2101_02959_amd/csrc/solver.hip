@@ -97,7 +97,8 @@ const char* last_error() { return g_err.c_str(); }
     } while (0)
 
 Context::~Context() {
-    if (kry_exec_) hipGraphExecDestroy(kry_exec_);
+    for (auto& g : kry_exec_)
+        if (g) hipGraphExecDestroy(g);
     if (kry_stream_) hipStreamDestroy(kry_stream_);
     for (void* p : allocs_) hipFree(p);
 }
@@ -782,10 +783,13 @@ int Context::fetidp_apply_t(int op, const double* in, double* out) {
     }
 }
 
-// The same PCG with one iteration captured as a HIP graph and replayed: the
-// scalars (alpha, beta, norms, state) stay on the device, the body has no
-// host synchronisation and no memset nodes, and the host reads the state
-// back once per replay.  Identical arithmetic, kernels and order to pcg().
+// The same PCG with one iteration captured as two HIP graphs and replayed:
+// the operator half (A p, alpha, the updates of x and r, the stopping test)
+// and the preconditioner half (z = M r, beta, the update of p), which runs
+// only while the iteration continues.  The scalars (alpha, beta, norms,
+// state) stay on the device, neither half holds a host synchronisation or a
+// memset node, and the host reads the state back once per iteration.
+// Identical arithmetic, kernels and order to pcg().
 int Context::pcg_graph(int n, const double* b, double* x, bool feti, KrylovOut& out) {
     out = KrylovOut();
     const int maxit = opts.krylov_maxit;
@@ -825,60 +829,69 @@ int Context::pcg_graph(int n, const double* b, double* x, bool feti, KrylovOut& 
                              hipMemcpyHostToDevice, stream_));
         HIPOK(hipStreamSynchronize(stream_));   // init lives on this host stack
     }
-    // capture the iteration body once per (operator, size)
+    // capture both halves once per (operator, size)
     const int key = (feti ? 1 : 0) + 2 * n;
-    if (!kry_exec_ || kry_key_ != key) {
-        if (kry_exec_) {
-            hipGraphExecDestroy(kry_exec_);
-            kry_exec_ = nullptr;
-        }
+    if (!kry_exec_[0] || !kry_exec_[1] || kry_key_ != key) {
+        for (auto& g : kry_exec_)
+            if (g) {
+                hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+        kry_key_ = -1;
         if (!kry_stream_) HIPOK(hipStreamCreateWithFlags(&kry_stream_, hipStreamNonBlocking));
         HIPOK(hipStreamSynchronize(stream_));
-        hipStream_t saved = stream_;
-        stream_ = kry_stream_;
-        HIPOK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
-        int brc = A(kp_, kq_);
-        if (!brc) {
-            launch_dot(stream_, n, kp_, kq_, part_, kry_sc_ + PCG_PQ);
-            launch_pcg_alpha(stream_, kry_sc_);
-            launch_axpy_dev(stream_, n, kry_sc_ + PCG_ALPHA, 1.0, kp_, x);
-            launch_copy_kernel(stream_, n, kr_, kro_);
-            launch_axpy_dev(stream_, n, kry_sc_ + PCG_ALPHA, -1.0, kq_, kr_);
-            launch_dot(stream_, n, kr_, kr_, part_, kry_sc_ + PCG_RN2);
-            launch_pcg_check(stream_, kry_sc_, kry_hist_, kry_ah_, maxit);
-            brc = M(kr_, kz_);
+        for (int half = 0; half < 2; ++half) {
+            hipStream_t saved = stream_;
+            stream_ = kry_stream_;
+            HIPOK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
+            int brc = 0;
+            if (half == 0) {
+                brc = A(kp_, kq_);
+                if (!brc) {
+                    launch_dot(stream_, n, kp_, kq_, part_, kry_sc_ + PCG_PQ);
+                    launch_pcg_alpha(stream_, kry_sc_);
+                    launch_axpy_dev(stream_, n, kry_sc_ + PCG_ALPHA, 1.0, kp_, x);
+                    launch_copy_kernel(stream_, n, kr_, kro_);
+                    launch_axpy_dev(stream_, n, kry_sc_ + PCG_ALPHA, -1.0, kq_, kr_);
+                    launch_dot(stream_, n, kr_, kr_, part_, kry_sc_ + PCG_RN2);
+                    launch_pcg_check(stream_, kry_sc_, kry_hist_, kry_ah_, maxit);
+                }
+            } else {
+                brc = M(kr_, kz_);
+                if (!brc) {
+                    launch_dot(stream_, n, kz_, kr_, part_, kry_sc_ + PCG_ZR);
+                    launch_dot(stream_, n, kz_, kro_, part_, kry_sc_ + PCG_ZRO);
+                    launch_pcg_beta(stream_, kry_sc_, kry_bh_);
+                    launch_scale_add_dev(stream_, n, kz_, kry_sc_ + PCG_BETA, kp_);
+                }
+            }
+            hipGraph_t g = nullptr;
+            const hipError_t ce = hipStreamEndCapture(stream_, &g);
+            stream_ = saved;
+            if (brc) {
+                if (g) hipGraphDestroy(g);
+                return brc;
+            }
+            HIPOK(ce);
+            const hipError_t ie = hipGraphInstantiate(&kry_exec_[half], g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            HIPOK(ie);
         }
-        if (!brc) {
-            launch_dot(stream_, n, kz_, kr_, part_, kry_sc_ + PCG_ZR);
-            launch_dot(stream_, n, kz_, kro_, part_, kry_sc_ + PCG_ZRO);
-            launch_pcg_beta(stream_, kry_sc_, kry_bh_);
-            launch_scale_add_dev(stream_, n, kz_, kry_sc_ + PCG_BETA, kp_);
-        }
-        hipGraph_t g = nullptr;
-        const hipError_t ce = hipStreamEndCapture(stream_, &g);
-        stream_ = saved;
-        if (brc) {
-            if (g) hipGraphDestroy(g);
-            return brc;
-        }
-        HIPOK(ce);
-        const hipError_t ie = hipGraphInstantiate(&kry_exec_, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
-        HIPOK(ie);
         kry_key_ = key;
         kry_x_ = x;
     }
-    // the body writes x: its pointer is part of the captured graph
+    // the operator half writes x: its pointer is part of the captured graph
     if (x != kry_x_) {
         set_error("internal error: graph PCG called with a different solution vector");
         return BDM_E_STATE;
     }
     double st[2] = {PCG_RUNNING, 0.0};
     for (int it = 0; it < maxit; ++it) {
-        HIPOK(hipGraphLaunch(kry_exec_, stream_));
+        HIPOK(hipGraphLaunch(kry_exec_[0], stream_));
         HIPOK(hipMemcpyAsync(st, kry_sc_ + PCG_STATE, 2 * sizeof(double), hipMemcpyDeviceToHost, stream_));
         HIPOK(hipStreamSynchronize(stream_));
         if (st[0] != PCG_RUNNING) break;
+        HIPOK(hipGraphLaunch(kry_exec_[1], stream_));
     }
     const int its = (int)st[1];
     out.its = its;

@@ -150,7 +150,7 @@ class Context {
     double *kry_sc_ = nullptr, *kry_hist_ = nullptr, *kry_ah_ = nullptr, *kry_bh_ = nullptr;
     int kry_hcap_ = 0, kry_key_ = -1;
     double* kry_x_ = nullptr;
-    hipGraphExec_t kry_exec_ = nullptr;
+    hipGraphExec_t kry_exec_[2] = {nullptr, nullptr};   // operator half, preconditioner half
     hipStream_t kry_stream_ = nullptr;
 };
 

@@ -93,8 +93,8 @@ __global__ void k_copy(int64_t n, const double* __restrict__ x, double* __restri
 }
 
 // PCG scalar steps on device (slots in pcg_slots.hpp order).  Once the state
-// is no longer PCG_RUNNING the iteration is frozen: alpha = beta = 0, so x and
-// r stop changing while the captured body keeps being replayed.
+// is no longer PCG_RUNNING the iteration is frozen: alpha = beta = 0, so a
+// replay after the stop leaves x and r unchanged.
 __global__ void k_pcg_alpha(double* __restrict__ sc) {
     // a breakdown (p . q = 0) gives a non-finite alpha and residual, which the
     // check below reports as divergence, as the host-driven loop does
