@@ -51,6 +51,12 @@ enum {
 enum { BDM_SOLVER_BDDC = 0, BDM_SOLVER_FETIDP = 1 };
 enum { BDM_PREC_FP64 = 0, BDM_PREC_MIXED = 1 };
 enum { BDM_GUESS_PREV = 0, BDM_GUESS_EXTRAP = 1, BDM_GUESS_CNN = 2 };
+/* Schedule of the batched per-subdomain triangular solves (uneven sizes):
+ * QUEUE  one persistent launch per solve whose workgroups draw subdomains
+ *        from a device work queue in decreasing factor size (LPT);
+ * GRID   one workgroup per subdomain in subdomain order.
+ * Both give bitwise identical results. */
+enum { BDM_SCHED_QUEUE = 0, BDM_SCHED_GRID = 1 };
 enum { BDM_FETI_F = 0, BDM_FETI_PRECOND = 1, BDM_FETI_RHS = 2, BDM_FETI_RECOVER = 3 };
 
 /* Structured hexahedral Q1 mesh of nx*ny*nz cubes of side h (Sec. 3a) and a
@@ -95,6 +101,7 @@ typedef struct bdm_opts {
                                 /* preconditioner half while running) with   */
                                 /* device scalars, same arithmetic and       */
                                 /* iterates; 0: host-driven loop             */
+    int schedule;               /* BDM_SCHED_*                               */
 } bdm_opts;
 
 /* Per-step statistics filled by bdm_step (for its last step). */

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libbidomain.so")
 BDM_SOLVER_BDDC, BDM_SOLVER_FETIDP = 0, 1
 BDM_PREC_FP64, BDM_PREC_MIXED = 0, 1
 BDM_GUESS_PREV, BDM_GUESS_EXTRAP, BDM_GUESS_CNN = 0, 1, 2
+BDM_SCHED_QUEUE, BDM_SCHED_GRID = 0, 1
 BDM_FETI_F, BDM_FETI_PRECOND, BDM_FETI_RHS, BDM_FETI_RECOVER = 0, 1, 2, 3
 (BDM_KERNEL_JACOBIAN, BDM_KERNEL_TRSV_DIRICHLET, BDM_KERNEL_POTRF_INTERIOR, BDM_KERNEL_SYRK_UPDATE,
  BDM_KERNEL_TRSV_DIRICHLET_T) = 0, 1, 2, 3, 4
@@ -59,7 +60,7 @@ class bdm_opts(C.Structure):
     _fields_ = [("dt", C.c_double), ("newton_rtol", C.c_double), ("newton_atol", C.c_double),
                 ("newton_maxit", C.c_int), ("krylov_rtol", C.c_double), ("krylov_dtol", C.c_double),
                 ("krylov_maxit", C.c_int), ("solver", C.c_int), ("precision", C.c_int),
-                ("guess", C.c_int), ("krylov_graph", C.c_int)]
+                ("guess", C.c_int), ("krylov_graph", C.c_int), ("schedule", C.c_int)]
 
 
 class bdm_step_stats(C.Structure):
@@ -124,7 +125,7 @@ def _ptr(t):
 
 
 def make_structs(mesh, physics, solver, precision=BDM_PREC_FP64, method=BDM_SOLVER_BDDC,
-                 guess=BDM_GUESS_PREV, krylov_graph=False):
+                 guess=BDM_GUESS_PREV, krylov_graph=False, schedule=0):
     """Build the C structs from workload descriptions (duck-typed)."""
     cx = (C.c_int * len(mesh.cuts_x))(*mesh.cuts_x)
     cy = (C.c_int * len(mesh.cuts_y))(*mesh.cuts_y)
@@ -136,7 +137,7 @@ def make_structs(mesh, physics, solver, precision=BDM_PREC_FP64, method=BDM_SOLV
                      physics.eta1, physics.eta2, physics.vth, physics.vp)
     op = bdm_opts(solver.dt, solver.newton_rtol, solver.newton_atol, solver.newton_maxit,
                   solver.krylov_rtol, solver.krylov_dtol, solver.krylov_maxit, method, precision,
-                  guess, int(bool(krylov_graph)))
+                  guess, int(bool(krylov_graph)), schedule)
     return m, ph, op, (cx, cy, cz)
 
 
@@ -144,12 +145,12 @@ class Solver:
     """One libbidomain context on the current torch CUDA device and stream."""
 
     def __init__(self, mesh, physics, solver, precision=BDM_PREC_FP64, method=BDM_SOLVER_BDDC,
-                 guess=BDM_GUESS_PREV, stream=None, krylov_graph=False):
+                 guess=BDM_GUESS_PREV, stream=None, krylov_graph=False, schedule=0):
         import torch
         self.torch = torch
         L = lib()
         self.m, self.ph, self.op, self._keep = make_structs(mesh, physics, solver, precision,
-                                                            method, guess, krylov_graph)
+                                                            method, guess, krylov_graph, schedule)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream

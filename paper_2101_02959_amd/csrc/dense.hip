@@ -837,14 +837,40 @@ __device__ inline double lane_read(double v, int l) {
     return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
 }
 
+// Next matrix of a one-workgroup-per-matrix kernel: from the work queue when
+// the launch is persistent, else the workgroup's own index (first pass only).
+// Returns -1 when the workgroup is done; the last workgroup to finish resets
+// the queue.  Contains barriers: every thread of the workgroup calls it.
+__device__ inline int next_item(const int* __restrict__ order, int* __restrict__ ctr, int nb, int pass) {
+    __shared__ int item;
+    if (!ctr) return pass == 0 && (int)blockIdx.x < nb ? (order ? order[blockIdx.x] : (int)blockIdx.x) : -1;
+    __syncthreads();                    // every thread has read the previous item
+    if (threadIdx.x == 0) {
+        int k = atomicAdd(&ctr[0], 1);
+        if (k >= nb) {
+            k = -1;
+            if (atomicAdd(&ctr[1], 1) == (int)gridDim.x - 1) {   // last workgroup out
+                atomicExch(&ctr[0], 0);
+                atomicExch(&ctr[1], 0);
+            }
+        }
+        item = k < 0 ? -1 : order[k];
+    }
+    __syncthreads();
+    return item;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_trsv_fwd(const T* __restrict__ Lb, const int64_t* __restrict__ Loff,
                                                  const int* __restrict__ nv, const int* __restrict__ ldv,
-                                                 T* __restrict__ xb, const int64_t* __restrict__ xoff) {
+                                                 T* __restrict__ xb, const int64_t* __restrict__ xoff, int nb,
+                                                 const int* __restrict__ order, int* __restrict__ ctr) {
     extern __shared__ double trsv_lds[];
     T* xl = reinterpret_cast<T*>(trsv_lds);
     __shared__ T xs[NB];
-    const int s = blockIdx.x;
+    for (int pass = 0;; ++pass) {
+    const int s = next_item(order, ctr, nb, pass);
+    if (s < 0) break;
     const T* L = Lb + Loff[s];
     T* x = xb + xoff[s];
     const int n = nv[s];
@@ -885,16 +911,20 @@ __global__ __launch_bounds__(kWG) void k_trsv_fwd(const T* __restrict__ Lb, cons
         __syncthreads();
     }
     for (int i = tid; i < n; i += kWG) x[i] = xl[i];
+    }
 }
 
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_trsv_bwd(const T* __restrict__ Lb, const int64_t* __restrict__ Loff,
                                                  const int* __restrict__ nv, const int* __restrict__ ldv,
-                                                 T* __restrict__ xb, const int64_t* __restrict__ xoff) {
+                                                 T* __restrict__ xb, const int64_t* __restrict__ xoff, int nb,
+                                                 const int* __restrict__ order, int* __restrict__ ctr) {
     extern __shared__ double trsv_lds[];
     T* xl = reinterpret_cast<T*>(trsv_lds);
     __shared__ T red[1][NB];
-    const int s = blockIdx.x;
+    for (int pass = 0;; ++pass) {
+    const int s = next_item(order, ctr, nb, pass);
+    if (s < 0) break;
     const T* L = Lb + Loff[s];
     T* x = xb + xoff[s];
     const int n = nv[s];
@@ -945,6 +975,7 @@ __global__ __launch_bounds__(kWG) void k_trsv_bwd(const T* __restrict__ Lb, cons
         __syncthreads();
     }
     for (int i = tid; i < n; i += kWG) x[i] = xl[i];
+    }
 }
 
 // --------------------------------------------------------- deluxe operators
@@ -1098,13 +1129,22 @@ void launch_coarse_local(hipStream_t s, const BatchDesc& d, const T* F, const do
 }
 template <typename T>
 void launch_trsv(hipStream_t s, int nb, bool trans, const T* L, const int64_t* Loff, const int* n,
-                 const int* ld, T* x, const int64_t* xoff, int maxn) {
+                 const int* ld, T* x, const int64_t* xoff, int maxn, const WorkQueue& q) {
     if (nb <= 0 || maxn <= 0) return;
     const size_t lds = (size_t)maxn * sizeof(T);
-    if (trans)
-        hipLaunchKernelGGL(k_trsv_bwd<T>, dim3(nb), dim3(kWG), lds, s, L, Loff, n, ld, x, xoff);
-    else
-        hipLaunchKernelGGL(k_trsv_fwd<T>, dim3(nb), dim3(kWG), lds, s, L, Loff, n, ld, x, xoff);
+    auto kern = trans ? k_trsv_bwd<T> : k_trsv_fwd<T>;
+    int grid = nb;
+    if (q.order && q.counter) {
+        // persistent: as many workgroups as are resident at once (at least one)
+        int dev = 0, cus = 0, per = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kWG, lds) == hipSuccess)
+            grid = std::max(1, std::min(nb, cus * per));
+    }
+    const int* ord = q.order;
+    int* ctr = (q.order && q.counter) ? q.counter : nullptr;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWG), lds, s, L, Loff, n, ld, x, xoff, nb, ord, ctr);
 }
 template <typename T>
 void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, int maxn, const T* slots, T* fac, T* dmat, int* info) {
@@ -1140,7 +1180,7 @@ int deluxe_max_object() { return DLX_MAXN; }
     template void launch_coarse_local<T>(hipStream_t, const BatchDesc&, const T*, const double*, T*, T*, \
                                          double*, int*);                                                 \
     template void launch_trsv<T>(hipStream_t, int, bool, const T*, const int64_t*, const int*,          \
-                                 const int*, T*, const int64_t*, int);                                   \
+                                 const int*, T*, const int64_t*, int, const WorkQueue&);                 \
     template void launch_deluxe_setup<T>(hipStream_t, const ObjDesc&, int, const T*, T*, T*, int*);
 BDM_INST(double)
 BDM_INST(float)

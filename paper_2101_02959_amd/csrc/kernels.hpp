@@ -87,11 +87,21 @@ void launch_trsm_fwd(hipStream_t s, int nb, const T* L, const int64_t* Loff, con
 template <typename T>
 void launch_coarse_local(hipStream_t s, const BatchDesc& d, const T* F, const double* Svv, T* Z,
                          T* Gi, double* Sp, int* info);
+// Schedule of a batched one-workgroup-per-matrix kernel over uneven matrices.
+// With order and counter set, the launch is persistent (as many workgroups
+// as fit on the device) and each workgroup draws the next matrix from the
+// counter, in the given order (largest cost first: LPT); the last workgroup
+// to finish resets the two counters to zero for the next launch.  Without
+// them, one workgroup per matrix in index order.
+struct WorkQueue {
+    const int* order = nullptr;   // device: nb matrix indices, decreasing cost
+    int* counter = nullptr;       // device: 2 ints (next item, finished workgroups), zero between launches
+};
 // Batched triangular solves with the n x n lower factor of each matrix
 // (leading dimension ld), in place on x; maxn bounds n over the batch.
 template <typename T>
 void launch_trsv(hipStream_t s, int nb, bool trans, const T* L, const int64_t* Loff, const int* n,
-                 const int* ld, T* x, const int64_t* xoff, int maxn);
+                 const int* ld, T* x, const int64_t* xoff, int maxn, const WorkQueue& q);
 
 // Deluxe objects (faces and edges), one workgroup per object.
 struct ObjDesc {

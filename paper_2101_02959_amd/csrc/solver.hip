@@ -135,7 +135,8 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
     stream_ = s;
     opts = *o;
     phys = *ph;
-    if (!(o->dt > 0) || o->newton_maxit < 1 || o->krylov_maxit < 1) {
+    if (!(o->dt > 0) || o->newton_maxit < 1 || o->krylov_maxit < 1 ||
+        (o->schedule != BDM_SCHED_QUEUE && o->schedule != BDM_SCHED_GRID)) {
         set_error("invalid options");
         return BDM_E_ARG;
     }
@@ -387,6 +388,26 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
     Ilist_ = upload(Ilist);
     LII_off_ = upload(LII); Lrr_off_ = upload(Lrr); xI_off_ = upload(xI_off); Srr_off_ = bd_.Srr_off;
     nI_ = bd_.nI; nr_ = bd_.nr; ld_ = bd_.n; kF_ = upload(kF); nP_ = upload(nP);
+    // work queues of the per-iteration triangular solves: subdomains in
+    // decreasing factor size (cost n^2), longest first
+    if (opts.schedule == BDM_SCHED_QUEUE) {
+        auto lpt = [&](const std::vector<int>& sz) {
+            std::vector<int> o(nsub);
+            for (int q = 0; q < nsub; ++q) o[q] = q;
+            std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return sz[a] > sz[b]; });
+            return o;
+        };
+        qctr_ = (int*)dalloc(2 * sizeof(int));
+        if (!qctr_) {
+            set_error("device allocation failed (work queue)");
+            return BDM_E_OOM;
+        }
+        HIPOK(hipMemsetAsync(qctr_, 0, 2 * sizeof(int), stream_));
+        qI_.order = upload(lpt(nI));
+        qI_.counter = qctr_;
+        qr_.order = upload(lpt(nr));
+        qr_.counter = qctr_;
+    }
     st1c0_ = upload(st1c0); st1c1_ = upload(st1c1); st1c2_ = upload(st1c2); st2c1_ = upload(st2c1);
     plan_int_.ne = st1c1_; plan_int_.n = st1c2_;
     plan_rr_.ne = nr_; plan_rr_.n = nr_;
@@ -670,8 +691,8 @@ template <typename T>
 void Context::dirichlet(const double* r, const double* q, double* out) {
     T* xI = (T*)xI_;
     launch_gather_I<T>(stream_, nInodes_, Ilist_, N, r, q, xI);
-    launch_trsv<T>(stream_, bd_.nsub, false, (const T*)LIIs_, LII_off_, nI_, nI_, xI, xI_off_, maxnI_);
-    launch_trsv<T>(stream_, bd_.nsub, true, (const T*)LIIs_, LII_off_, nI_, nI_, xI, xI_off_, maxnI_);
+    launch_trsv<T>(stream_, bd_.nsub, false, (const T*)LIIs_, LII_off_, nI_, nI_, xI, xI_off_, maxnI_, qI_);
+    launch_trsv<T>(stream_, bd_.nsub, true, (const T*)LIIs_, LII_off_, nI_, nI_, xI, xI_off_, maxnI_, qI_);
     launch_scatter_I<T>(stream_, nInodes_, Ilist_, N, xI, out);
 }
 
@@ -688,13 +709,13 @@ void Context::condense(const double* r, double* g) {
 // backward solve for the Neumann correction plus the coarse prolongation.
 template <typename T>
 void Context::stilde_inv(T* xr, const double* gvert, double* uc) {
-    launch_trsv<T>(stream_, bd_.nsub, false, (const T*)Lrrs_, Lrr_off_, nr_, nr_, xr, xr_off_, maxnr_);
+    launch_trsv<T>(stream_, bd_.nsub, false, (const T*)Lrrs_, Lrr_off_, nr_, nr_, xr, xr_off_, maxnr_, qr_);
     launch_coarse_rhs_local<T>(stream_, sv_, xr, (const T*)F_, (const T*)Z_, (const T*)Gi_, cP_, mu_);
     launch_coarse_rhs_gather(stream_, cd_, N, gvert, cP_, uc);
     launch_coarse_project(stream_, cd_.np, pin_, uc);
     coarse_.solve(stream_, uc);
     launch_neumann_rhs<T>(stream_, sv_, (const T*)F_, (const T*)Z_, mu_, uc, xr, 1);
-    launch_trsv<T>(stream_, bd_.nsub, true, (const T*)Lrrs_, Lrr_off_, nr_, nr_, xr, xr_off_, maxnr_);
+    launch_trsv<T>(stream_, bd_.nsub, true, (const T*)Lrrs_, Lrr_off_, nr_, nr_, xr, xr_off_, maxnr_, qr_);
 }
 
 // zbuf holds interface values (zero interior); fill the interior by the
@@ -1042,7 +1063,7 @@ int Context::profile_t(int kernel, int reps, double* avg_ms, double* work) {
                 launch_jac_apply(stream_, fp, st_, dg_, kp_, kq_);
             else
                 launch_trsv<T>(stream_, nsub, kernel == BDM_KERNEL_TRSV_DIRICHLET_T, (const T*)LIIs_, LII_off_, nI_,
-                               nI_, (T*)xI_, xI_off_, maxnI_);
+                               nI_, (T*)xI_, xI_off_, maxnI_, qI_);
             HIPOK(hipEventRecord(e1, stream_));
             HIPOK(hipEventSynchronize(e1));
             float ms = 0.f;

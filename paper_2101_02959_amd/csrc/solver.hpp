@@ -151,6 +151,9 @@ class Context {
     int kry_hcap_ = 0, kry_key_ = -1;
     double* kry_x_ = nullptr;
     hipGraphExec_t kry_exec_[2] = {nullptr, nullptr};   // operator half, preconditioner half
+    // persistent LPT work queues of the Dirichlet and Neumann triangular solves
+    int* qctr_ = nullptr;
+    WorkQueue qI_, qr_;
     hipStream_t kry_stream_ = nullptr;
 };
 

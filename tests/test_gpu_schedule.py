@@ -1,0 +1,79 @@
+"""Persistent LPT work queue of the per-subdomain triangular solves against
+one workgroup per subdomain in index order.
+
+Each subdomain's solve is the same arithmetic whichever workgroup takes it,
+so the two schedules must agree bitwise.  Consecutive applications check that
+the queue resets itself between launches: a queue left non-zero would skip
+subdomains and leave their values unsolved.
+"""
+import numpy as np
+import pytest
+
+from workload import Mesh, Physics, Solver as SolverOpts, initial_state, stimulus_nodal
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+MESHES = {
+    "ragged": Mesh(11, 9, 10, 0.01, (0, 3, 7, 11), (0, 5, 9), (0, 4, 10)),
+    "uneven442": Mesh(20, 18, 12, 0.01, (0, 4, 9, 13, 20), (0, 5, 9, 14, 18), (0, 5, 12)),
+}
+
+
+def _lin_state(mesh, seed):
+    N = mesh.nnodes
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-80, 20, N), rng.uniform(0, 0.1, N)
+
+
+@pytest.mark.parametrize("mesh", list(MESHES))
+@pytest.mark.parametrize("prec", [0, 1])
+def test_queue_matches_grid_order(mesh, prec):
+    import paper_2101_02959_amd as P
+    m = MESHES[mesh]
+    N = m.nnodes
+    v, w = _lin_state(m, 3)
+    rs = [np.random.default_rng(s).standard_normal(2 * N) for s in (11, 12, 13)]
+    outs = {}
+    for sched in (P.BDM_SCHED_GRID, P.BDM_SCHED_QUEUE):
+        S = P.Solver(m, Physics(), SolverOpts(), precision=prec, schedule=sched)
+        S.bdm_linearize(v, w)
+        outs[sched] = [S.bdm_bddc_apply(r).cpu().numpy() for r in rs]
+        S.close()
+        F = P.Solver(m, Physics(), SolverOpts(), precision=prec, method=P.BDM_SOLVER_FETIDP, schedule=sched)
+        F.bdm_linearize(v, w)
+        nl = F.bdm_fetidp_size()
+        lam = np.random.default_rng(14).standard_normal(nl)
+        outs[sched] += [F.bdm_fetidp_apply(op, lam).cpu().numpy() for op in (P.BDM_FETI_F, P.BDM_FETI_PRECOND)]
+        F.close()
+    for a, b in zip(outs[P.BDM_SCHED_GRID], outs[P.BDM_SCHED_QUEUE]):
+        assert np.array_equal(a, b)
+        assert np.all(np.isfinite(a))
+
+
+def test_time_steps_identical_under_both_schedules():
+    import paper_2101_02959_amd as P
+    m = MESHES["uneven442"]
+    res = {}
+    for sched in (P.BDM_SCHED_GRID, P.BDM_SCHED_QUEUE):
+        S = P.Solver(m, Physics(), SolverOpts(), precision=1, schedule=sched, guess=P.BDM_GUESS_EXTRAP)
+        v0, ue0, w0 = initial_state(m, Physics(), 1)
+        S.bdm_set_state(v0, ue0, w0)
+        S.bdm_set_stimulus(stimulus_nodal(m, (2, 2, 2), 1e5), 0, 20)
+        its = []
+        for _ in range(3):
+            st = S.bdm_step(1)
+            its.append(list(st.krylov_its)[:st.newton_its])
+        v, ue, _, _ = S.bdm_get_state()
+        res[sched] = (its, v.cpu().numpy(), ue.cpu().numpy())
+        S.close()
+    g, q = res[P.BDM_SCHED_GRID], res[P.BDM_SCHED_QUEUE]
+    assert g[0] == q[0]
+    assert np.array_equal(g[1], q[1]) and np.array_equal(g[2], q[2])
+
+
+def test_invalid_schedule_rejected():
+    import paper_2101_02959_amd as P
+    with pytest.raises(P.BidomainError, match="BDM_E_ARG"):
+        P.Solver(MESHES["ragged"], Physics(), SolverOpts(), schedule=7)
