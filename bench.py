@@ -164,6 +164,7 @@ def main():
     log("plain FP64 path")
     S64, plain, st64 = run_path(P, wl, P.BDM_PREC_FP64, P.BDM_GUESS_PREV, args.warmup, args.steps)
     roof64 = kernel_rooflines(P, S64, "f64")
+    tune64 = S64.bdm_tune_report()["entries"]
     st64 = tuple(t.cpu() if hasattr(t, "cpu") else t for t in st64)
     S64.close()
     torch.cuda.synchronize()
@@ -172,6 +173,7 @@ def main():
     S32, mixed, st32 = run_path(P, wl, P.BDM_PREC_MIXED, P.BDM_GUESS_CNN, args.warmup, args.steps,
                                 predictor=PR.load())
     roof32 = kernel_rooflines(P, S32, "f32")
+    tune32 = S32.bdm_tune_report()["entries"]
     st32 = tuple(t.cpu() if hasattr(t, "cpu") else t for t in st32)
     S32.close()
     rel = {k: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
@@ -191,6 +193,9 @@ def main():
         "mixed_vs_fp64_rel_diff": rel,
         "roofline": roof32["syrk"],
         "roofline_other": {"mixed": {k: v for k, v in roof32.items() if k != "syrk"}, "fp64": roof64},
+        "autotune": {name: [{"family": e["family"], "class": e["class"], "choice": e["choice"],
+                             "ms": e["ms"], "cached": e["cached"]} for e in ent]
+                     for name, ent in (("mixed", tune32), ("fp64", tune64))},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(dofs, plain["newton_per_step"])

@@ -260,6 +260,25 @@ enum {
 };
 int bdm_profile_kernel(bdm_ctx* ctx, int kernel, int reps, double* avg_ms, double* work);
 
+/* Autotuned kernel variants of the context (not part of the paper's method;
+ * every variant computes the same operator).  Tuned families:
+ *   "stencil"  tile shape of the fused 27-point stencil kernel, per mesh,
+ *              chosen at bdm_create by timing the Jacobian apply;
+ *   "syrk"     output tile and inner chunk of the batched rank-k update of
+ *              the interior and r-block eliminations, per size class,
+ *              chosen at the first bdm_linearize by timing the first setup
+ *              chunk's updates (before its assembly).
+ * If the environment variable BDM_TUNE_CACHE names a file, bdm_create reads
+ * earlier results from it (JSON; a missing file is created) and new results
+ * are written back, so a later context on the same device and sizes reuses
+ * them without timing; an unreadable cache is BDM_E_ARG at bdm_create.
+ * bdm_tune_report writes the JSON of the entries this context used (device,
+ * family, size class, choice, time per variant in ms, cached flag) into the
+ * caller's buffer buf of cap bytes, NUL-terminated, and sets *len to the
+ * length without the NUL; if cap <= *len nothing is written and BDM_E_ARG is
+ * returned, so a caller can size its buffer from *len. */
+int bdm_tune_report(bdm_ctx* ctx, char* buf, long cap, long* len);
+
 /* Sizes for callers that allocate vectors: N, number of subdomains, global
  * primal (coarse) dimension. */
 int bdm_sizes(bdm_ctx* ctx, long* n_nodes, long* n_sub, long* n_primal);

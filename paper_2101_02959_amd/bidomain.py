@@ -32,7 +32,7 @@ ERRORS = {
 EXPORTS = ("bdm_create", "bdm_destroy", "bdm_set_state", "bdm_get_state", "bdm_set_stimulus",
            "bdm_ionic_update", "bdm_residual", "bdm_linearize", "bdm_jacobian_apply",
            "bdm_bddc_apply", "bdm_fetidp_size", "bdm_fetidp_apply", "bdm_step", "bdm_sizes",
-           "bdm_profile_kernel", "bdm_predictor_size", "bdm_predictor_set", "bdm_predictor_get",
+           "bdm_profile_kernel", "bdm_tune_report", "bdm_predictor_size", "bdm_predictor_set", "bdm_predictor_get",
            "bdm_predictor_guess", "bdm_predictor_loss_grad", "bdm_predictor_train", "bdm_last_error")
 
 
@@ -86,6 +86,7 @@ def lib():
         "bdm_create": ([C.POINTER(bdm_mesh), C.POINTER(bdm_physics), C.POINTER(bdm_opts), vp,
                         C.POINTER(vp)], ci),
         "bdm_destroy": ([vp], ci),
+        "bdm_tune_report": ([vp, C.c_char_p, C.c_long, C.POINTER(C.c_long)], ci),
         "bdm_set_state": ([vp, vp, vp, vp, cd, ci], ci),
         "bdm_get_state": ([vp, vp, vp, vp, C.POINTER(cd), ci], ci),
         "bdm_set_stimulus": ([vp, vp, ci, ci, ci], ci),
@@ -288,6 +289,18 @@ class Solver:
         _check(lib().bdm_predictor_train(self.h, _ptr(S), int(ns), o.ctypes.data_as(C.POINTER(C.c_int)),
                                          int(o.size), float(lr), losses.ctypes.data_as(C.POINTER(C.c_double))))
         return losses
+
+    def bdm_tune_report(self):
+        """Autotuner entries this context used, as a dict (JSON from the library)."""
+        import json
+        n = C.c_long()
+        buf = C.create_string_buffer(1 << 14)
+        rc = lib().bdm_tune_report(self.h, buf, len(buf), C.byref(n))
+        if rc != 0 and n.value >= len(buf):
+            buf = C.create_string_buffer(n.value + 1)
+            rc = lib().bdm_tune_report(self.h, buf, len(buf), C.byref(n))
+        _check(rc)
+        return json.loads(buf.value.decode())
 
     def bdm_step(self, nsteps=1):
         st = bdm_step_stats()

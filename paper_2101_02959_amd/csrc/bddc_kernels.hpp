@@ -90,6 +90,8 @@ void launch_copy(hipStream_t s, int64_t n, const double* x, double* y);
 void launch_axpy_dev(hipStream_t s, int64_t n, const double* a, double sgn, const double* x, double* y);
 void launch_scale_add_dev(hipStream_t s, int64_t n, const double* z, const double* b, double* p);
 void launch_fill(hipStream_t s, int64_t n, double v, double* x);
+template <typename T>
+void launch_fill_t(hipStream_t s, int64_t n, T v, T* x);
 void launch_copy_kernel(hipStream_t s, int64_t n, const double* x, double* y);
 void launch_pcg_alpha(hipStream_t s, double* sc);
 void launch_pcg_check(hipStream_t s, double* sc, double* hist, double* ah, int maxit);

@@ -1,5 +1,6 @@
 // extern "C" entry points of libbidomain (declared in include/bidomain.h).
 // No C++ exception crosses this boundary.
+#include <cstring>
 #include <exception>
 #include <new>
 
@@ -127,6 +128,23 @@ int bdm_step(bdm_ctx* ctx, int nsteps, bdm_step_stats* stats) {
 int bdm_profile_kernel(bdm_ctx* ctx, int kernel, int reps, double* avg_ms, double* work) {
     NEED(ctx); NEED(avg_ms); NEED(work);
     GUARD(ctx->c.profile_kernel(kernel, reps, avg_ms, work));
+}
+
+int bdm_tune_report(bdm_ctx* ctx, char* buf, long cap, long* len) {
+    NEED(ctx); NEED(len);
+    try {
+        const std::string r = ctx->c.tune_report();
+        *len = (long)r.size();
+        if (!buf || cap <= (long)r.size()) {
+            bdm::set_error("bdm_tune_report: buffer too small");
+            return BDM_E_ARG;
+        }
+        std::memcpy(buf, r.c_str(), r.size() + 1);
+        return BDM_OK;
+    } catch (...) {
+        bdm::set_error("host allocation failed");
+        return BDM_E_OOM;
+    }
 }
 
 long bdm_predictor_size(void) { return bdm::Predictor::n_params(); }

@@ -17,6 +17,7 @@ struct FEParams {
     int64_t N;                  // nodes
     double h, tau, c;           // mesh size, time step, chi*C_m
     double chiG, chieta1, eta2, vth, vp;
+    int stencil_variant = 0;    // tile shape of the stencil kernel (autotuned)
 };
 
 __host__ __device__ inline double rmc_iion(const FEParams& p, double v, double w) {

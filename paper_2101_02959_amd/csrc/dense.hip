@@ -425,28 +425,36 @@ __global__ __launch_bounds__(kWG) void k_panel_trsm(T* __restrict__ Abase, const
 //             re = n, k = the panel (K_II trailing block and the L_GI rows);
 //   SY_SCHUR  after the last panel: cb = nI, ce = re = n, k = [0, nI), which
 //             turns K_GG into S_Gamma = K_GG - L_GI L_GI^T (Sec. 4.1).
-// 128x128 output tiles per workgroup (64x64 per wave, 4x4 MFMA 16x16x4
-// blocks), the inner dimension staged through LDS in chunks of 32 columns
-// with a register prefetch of the next chunk.  The workgroup id is mapped so
-// that all tiles of one subdomain run on the same XCD (dispatch assigns
-// consecutive ids round robin to the 8 XCDs), which keeps P in that XCD's L2.
-constexpr int SY_TM = 128, SY_KC = 32, SY_LS = SY_TM + 16, SY_XCD = 8;
-constexpr int SY_EPT = SY_TM * SY_KC / kWG;   // staged elements per thread and operand
+// TM x TM output tiles per workgroup (TM/2 x TM/2 per wave, in 16x16x4 MFMA
+// blocks), the inner dimension staged through LDS in chunks of KC columns
+// with a register prefetch of the next chunk; (TM, KC) is one of the tuned
+// variants below.  The workgroup id is mapped so that all tiles of one
+// subdomain run on the same XCD (dispatch assigns consecutive ids round
+// robin to the 8 XCDs), which keeps P in that XCD's L2.
+constexpr int SY_XCD = 8;
 constexpr int SY_TRAIL = 0, SY_SCHUR = 1;
+// variants: 0 = (128, 32), 1 = (128, 16), 2 = (64, 32), 3 = (64, 16)
+constexpr int SY_NVAR = 4;
+__host__ __device__ constexpr int syrk_tm(int v) { return v < 2 ? 128 : 64; }
+__host__ __device__ constexpr int syrk_kc(int v) { return (v & 1) ? 16 : 32; }
 
-__host__ __device__ inline int trapezoid_tiles(int cb, int ce, int re) {
+__host__ __device__ inline int trapezoid_tiles(int cb, int ce, int re, int TM) {
     if (ce <= cb || re <= cb) return 0;
-    const int nct = (ce - cb + SY_TM - 1) / SY_TM, nrt = (re - cb + SY_TM - 1) / SY_TM;
+    const int nct = (ce - cb + TM - 1) / TM, nrt = (re - cb + TM - 1) / TM;
     return nct * nrt - nct * (nct - 1) / 2;
 }
 
-template <typename T>
+template <typename T, int TM, int KC>
 __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, const int64_t* __restrict__ off,
                                                       const int* __restrict__ ldv, const int* __restrict__ nIv,
                                                       const int* __restrict__ nv, int nsub, int tiles, int mode,
                                                       int J) {
-    __shared__ T As[SY_KC][SY_LS];    // P rows of the output tile's rows (i)
-    __shared__ T Bs[SY_KC][SY_LS];    // P rows of the output tile's columns (j)
+    constexpr int LS = TM + 16;                // padded LDS row
+    constexpr int KS = kWG / TM;               // inner indices staged per pass of the workgroup
+    constexpr int EPT = TM * KC / kWG;         // staged elements per thread and operand
+    constexpr int WT = TM / 2, NBK = WT / 16;  // wave tile and its MFMA blocks per side
+    __shared__ T As[KC][LS];    // P rows of the output tile's rows (i)
+    __shared__ T Bs[KC][LS];    // P rows of the output tile's columns (j)
     const int g = blockIdx.x;
     const int q = g / SY_XCD;
     const int s = (q / tiles) * SY_XCD + g % SY_XCD;
@@ -461,27 +469,27 @@ __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, con
     } else {
         cb = J + NBO; ce = nI; re = n; k0 = J; k1 = min(J + NBO, nI);
     }
-    if (k1 <= k0 || tile >= trapezoid_tiles(cb, ce, re)) return;
-    const int nrt = (re - cb + SY_TM - 1) / SY_TM;
+    if (k1 <= k0 || tile >= trapezoid_tiles(cb, ce, re, TM)) return;
+    const int nrt = (re - cb + TM - 1) / TM;
     int tj = 0;
     while (tile >= nrt - tj) { tile -= nrt - tj; ++tj; }
     const int ti = tj + tile;
-    const int I0 = cb + ti * SY_TM, J0 = cb + tj * SY_TM;
+    const int I0 = cb + ti * TM, J0 = cb + tj * TM;
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
-    const int wr = wv & 1, wc = wv >> 1;                 // wave's 64x64 quadrant (rows i, cols j)
+    const int wr = wv & 1, wc = wv >> 1;                 // wave's quadrant (rows i, cols j)
     const bool active = !(ti == tj && wr < wc);          // strictly upper quadrant of a diagonal tile
-    // each thread stages SY_EPT elements of each operand per chunk: row tid % 128, k = tid / 128 + 2 e.
+    // each thread stages EPT elements of each operand per chunk: row tid % TM, k = tid / TM + KS e.
     // The loads are branch-free: rows beyond the trapezoid are clamped to its
     // last row (they only reach outputs that are never stored) and the inner
     // index to k1 - 1; the k mask is applied when the chunk is written to LDS,
     // so no load has to complete before the next one is issued.
-    const int lrow = tid % SY_TM, lk0 = tid / SY_TM;
+    const int lrow = tid % TM, lk0 = tid / TM;
     const int ri = min(I0 + lrow, re - 1), rj = min(J0 + lrow, ce - 1);
-    T pa[SY_EPT], pb[SY_EPT];
+    T pa[EPT], pb[EPT];
     auto fetch = [&](int kc) {
 #pragma unroll
-        for (int e = 0; e < SY_EPT; ++e) {
-            const int64_t k = min(kc + lk0 + 2 * e, k1 - 1);
+        for (int e = 0; e < EPT; ++e) {
+            const int64_t k = min(kc + lk0 + KS * e, k1 - 1);
             pa[e] = A[ri + k * ld];
             pb[e] = A[rj + k * ld];
         }
@@ -497,16 +505,16 @@ __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, con
     // dimension.
     constexpr bool two_level = std::is_same<T, float>::value;
     const T sgn = two_level ? (T)1 : (T)-1;
-    typename Mfma<T>::acc acc[4][4], tot[4][4];
+    typename Mfma<T>::acc acc[NBK][NBK], tot[NBK][NBK];
     auto c_at = [&](int a, int b, int v) -> T {       // C entry of accumulator (b, a, v), clamped address
-        const int i = min(I0 + wr * 64 + 16 * a + lr, re - 1);
-        const int j = min(J0 + wc * 64 + 16 * b + Mfma<T>::row(lane, v), ce - 1);
+        const int i = min(I0 + wr * WT + 16 * a + lr, re - 1);
+        const int j = min(J0 + wc * WT + 16 * b + Mfma<T>::row(lane, v), ce - 1);
         return A[i + (int64_t)j * ld];
     };
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < NBK; ++b)
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
+        for (int a = 0; a < NBK; ++a) {
             acc[b][a] = tot[b][a] = (typename Mfma<T>::acc){0, 0, 0, 0};
             if (!two_level && active) {
 #pragma unroll
@@ -514,36 +522,36 @@ __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, con
             }
         }
     fetch(k0);
-    for (int kc = k0; kc < k1; kc += SY_KC) {
+    for (int kc = k0; kc < k1; kc += KC) {
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < SY_EPT; ++e) {
-            const bool kin = kc + lk0 + 2 * e < k1;
-            As[lk0 + 2 * e][lrow] = kin ? pa[e] : (T)0;
-            Bs[lk0 + 2 * e][lrow] = kin ? sgn * pb[e] : (T)0;
+        for (int e = 0; e < EPT; ++e) {
+            const bool kin = kc + lk0 + KS * e < k1;
+            As[lk0 + KS * e][lrow] = kin ? pa[e] : (T)0;
+            Bs[lk0 + KS * e][lrow] = kin ? sgn * pb[e] : (T)0;
         }
         __syncthreads();
-        if (kc + SY_KC < k1) fetch(kc + SY_KC);
+        if (kc + KC < k1) fetch(kc + KC);
         if (active) {
 #pragma unroll
-            for (int kk = 0; kk < SY_KC; kk += 4) {
-                T fa[4], fb[4];
+            for (int kk = 0; kk < KC; kk += 4) {
+                T fa[NBK], fb[NBK];
 #pragma unroll
-                for (int a = 0; a < 4; ++a) fa[a] = As[kk + lk][wr * 64 + 16 * a + lr];
+                for (int a = 0; a < NBK; ++a) fa[a] = As[kk + lk][wr * WT + 16 * a + lr];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) fb[b] = Bs[kk + lk][wc * 64 + 16 * b + lr];
+                for (int b = 0; b < NBK; ++b) fb[b] = Bs[kk + lk][wc * WT + 16 * b + lr];
                 // output row index = j (A operand), column index = i (B operand), so
                 // that the 16 lanes of an accumulator row hold consecutive i
 #pragma unroll
-                for (int b = 0; b < 4; ++b)
+                for (int b = 0; b < NBK; ++b)
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) acc[b][a] = Mfma<T>::mac(fb[b], fa[a], acc[b][a]);
+                    for (int a = 0; a < NBK; ++a) acc[b][a] = Mfma<T>::mac(fb[b], fa[a], acc[b][a]);
             }
             if (two_level) {
 #pragma unroll
-                for (int b = 0; b < 4; ++b)
+                for (int b = 0; b < NBK; ++b)
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) {
+                    for (int a = 0; a < NBK; ++a) {
                         tot[b][a] += acc[b][a];
                         acc[b][a] = (typename Mfma<T>::acc){0, 0, 0, 0};
                     }
@@ -553,20 +561,20 @@ __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, con
     if (!active) return;
     if (two_level) {
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < NBK; ++b)
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < NBK; ++a)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) tot[b][a][v] = c_at(a, b, v) - tot[b][a][v];
     }
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < NBK; ++b)
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int i = I0 + wr * 64 + 16 * a + lr;
+        for (int a = 0; a < NBK; ++a) {
+            const int i = I0 + wr * WT + 16 * a + lr;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int j = J0 + wc * 64 + 16 * b + Mfma<T>::row(lane, v);
+                const int j = J0 + wc * WT + 16 * b + Mfma<T>::row(lane, v);
                 if (i < re && j < ce && j <= i) A[i + (int64_t)j * ld] = two_level ? tot[b][a][v] : acc[b][a][v];
             }
         }
@@ -1092,12 +1100,21 @@ void launch_interior_panel(hipStream_t s, int nb, T* A, const int64_t* off, cons
 }
 template <typename T>
 void launch_syrk_update(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* nI, const int* n,
-                        bool schur, int J, int tiles) {
+                        bool schur, int J, int tiles, int variant) {
     if (nb <= 0 || tiles <= 0) return;
     const int groups = (nb + SY_XCD - 1) / SY_XCD;
-    hipLaunchKernelGGL(k_syrk_batched<T>, dim3(groups * tiles * SY_XCD), dim3(kWG), 0, s, A, off, ld, nI, n, nb,
-                       tiles, schur ? SY_SCHUR : SY_TRAIL, J);
+    const dim3 grid(groups * tiles * SY_XCD);
+    const int mode = schur ? SY_SCHUR : SY_TRAIL;
+    switch (variant) {
+        case 1: hipLaunchKernelGGL((k_syrk_batched<T, 128, 16>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nb, tiles, mode, J); break;
+        case 2: hipLaunchKernelGGL((k_syrk_batched<T, 64, 32>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nb, tiles, mode, J); break;
+        case 3: hipLaunchKernelGGL((k_syrk_batched<T, 64, 16>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nb, tiles, mode, J); break;
+        default: hipLaunchKernelGGL((k_syrk_batched<T, 128, 32>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nb, tiles, mode, J);
+    }
 }
+int syrk_variants() { return SY_NVAR; }
+int syrk_variant_tm(int v) { return syrk_tm(v); }
+int syrk_variant_kc(int v) { return syrk_kc(v); }
 int interior_panel_width() { return NBO; }
 int panel_wbuf_stride() { return NBO * NB; }
 int panel_rowblocks(int J, int nI, int n) {
@@ -1105,8 +1122,9 @@ int panel_rowblocks(int J, int nI, int n) {
     const int r0 = J + std::min(NBO, nI - J);
     return r0 < n ? (n - r0 + PT_RB - 1) / PT_RB : 0;
 }
-int syrk_tiles(bool schur, int J, int nI, int n) {
-    return schur ? trapezoid_tiles(nI, n, n) : (J < nI ? trapezoid_tiles(J + NBO, nI, n) : 0);
+int syrk_tiles(bool schur, int J, int nI, int n, int variant) {
+    const int TM = syrk_tm(variant);
+    return schur ? trapezoid_tiles(nI, n, n, TM) : (J < nI ? trapezoid_tiles(J + NBO, nI, n, TM) : 0);
 }
 template <typename T>
 void launch_extract(hipStream_t s, const BatchDesc& d, const T* K, T* slots, T* F, double* Svv, T* Srr) {
@@ -1171,7 +1189,7 @@ int deluxe_max_object() { return DLX_MAXN; }
     template void launch_interior_panel<T>(hipStream_t, int, T*, const int64_t*, const int*, const int*, \
                                            const int*, int, T*, int, int*);                              \
     template void launch_syrk_update<T>(hipStream_t, int, T*, const int64_t*, const int*, const int*,    \
-                                        const int*, bool, int, int);                                     \
+                                        const int*, bool, int, int, int);                                \
     template void launch_extract<T>(hipStream_t, const BatchDesc&, const T*, T*, T*, double*, T*);      \
     template void launch_copy_out<T>(hipStream_t, const BatchDesc&, int, const T*, T*, const int64_t*, T*,    \
                                      const int64_t*);                                                    \

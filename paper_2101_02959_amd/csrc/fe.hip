@@ -106,7 +106,6 @@ std::vector<double> stencil_tables(int nz, const std::vector<double>& ke) {
 // --------------------------------------------------------------- device side
 namespace {
 
-constexpr int SX = 32, SY = 8, SZ = 8;     // block: 32 x 8 nodes, 8 z-levels per thread
 
 __device__ inline double lumped_mass(const FEParams& p, int i, int j, int k) {
     const double fx = (i == 0 || i == p.nx) ? 0.5 : 1.0;
@@ -122,19 +121,19 @@ enum { ST_JAC = 0, ST_RES_MINUS_JAC = 1, ST_RESIDUAL = 2 };
 //   ST_JAC:            y = [d xv + si ; si + se]
 //   ST_RES_MINUS_JAC:  y = r - [d xv + si ; si + se]
 //   ST_RESIDUAL:       y = [m (c (v - v^n) + tau (I_ion - I_s)) + si ; si + se]
-// A block owns a 32 x 8 column of nodes and walks SZ z-levels.  The planes
-// k-1, k, k+1 of (xv + xe) and xe, with a one-node halo, live in a rotating
-// LDS buffer, so each input value is fetched from memory about once; the
-// coefficient tables of level k (9 boundary classes x 2 media) are staged too.
-constexpr int PX = SX + 2, PY = SY + 2;
-
-template <int MODE>
+// A block owns an SX x SY column of nodes and walks SZ z-levels (the tile
+// shape is one of the autotuned variants below).  The planes k-1, k, k+1 of
+// (xv + xe) and xe, with a one-node halo, live in a rotating LDS buffer, so
+// each input value is fetched from memory about once; the coefficient tables
+// of level k (9 boundary classes x 2 media) are staged too.
+template <int MODE, int SX, int SY, int SZ>
 __global__ __launch_bounds__(SX * SY) void k_stencil(FEParams p, const double* __restrict__ st,
                                                      const double* __restrict__ dg, const double* __restrict__ xv,
                                                      const double* __restrict__ xe, const double* __restrict__ rv,
                                                      const double* __restrict__ re, const double* __restrict__ vn,
                                                      const double* __restrict__ w, const double* __restrict__ Is,
                                                      double stim, double* __restrict__ yv, double* __restrict__ ye) {
+    constexpr int PX = SX + 2, PY = SY + 2;
     constexpr int NT = SX * SY, NPT = (PX * PY + NT - 1) / NT, TABN = 9 * 2 * 27, NTB = (TABN + NT - 1) / NT;
     __shared__ double tab[TABN];
     __shared__ double ps[3][PY][PX];
@@ -262,9 +261,26 @@ __global__ void k_reaction_diag(FEParams p, const double* __restrict__ v, const 
     if (!(d > 0.0)) atomicOr(bad, 1);
 }
 
-inline dim3 stencil_grid(const FEParams& p) {
-    return dim3((unsigned)((p.nx1 + SX - 1) / SX), (unsigned)((p.ny1 + SY - 1) / SY),
-                (unsigned)((p.nz + 1 + SZ - 1) / SZ));
+// tile variants (SX, SY, SZ)
+constexpr int ST_NVAR = 5;
+constexpr int ST_SHAPE[ST_NVAR][3] = {{32, 8, 8}, {32, 8, 16}, {64, 4, 8}, {32, 4, 16}, {16, 16, 8}};
+
+template <int MODE, int SX, int SY, int SZ, typename... Args>
+void launch_stencil_shape(hipStream_t s, const FEParams& p, Args... args) {
+    const dim3 grid((unsigned)((p.nx1 + SX - 1) / SX), (unsigned)((p.ny1 + SY - 1) / SY),
+                    (unsigned)((p.nz + 1 + SZ - 1) / SZ));
+    hipLaunchKernelGGL((k_stencil<MODE, SX, SY, SZ>), grid, dim3(SX, SY), 0, s, p, args...);
+}
+
+template <int MODE, typename... Args>
+void launch_stencil(hipStream_t s, const FEParams& p, Args... args) {
+    switch (p.stencil_variant) {
+        case 1: launch_stencil_shape<MODE, 32, 8, 16>(s, p, args...); break;
+        case 2: launch_stencil_shape<MODE, 64, 4, 8>(s, p, args...); break;
+        case 3: launch_stencil_shape<MODE, 32, 4, 16>(s, p, args...); break;
+        case 4: launch_stencil_shape<MODE, 16, 16, 8>(s, p, args...); break;
+        default: launch_stencil_shape<MODE, 32, 8, 8>(s, p, args...);
+    }
 }
 
 }  // namespace
@@ -279,8 +295,8 @@ void launch_ionic_update(hipStream_t s, const FEParams& p, const double* v, doub
 void launch_residual(hipStream_t s, const FEParams& p, const double* st, const double* v,
                      const double* ue, const double* vn, const double* w, const double* Is,
                      double stim, double* Rv, double* Re) {
-    hipLaunchKernelGGL(k_stencil<ST_RESIDUAL>, stencil_grid(p), dim3(SX, SY), 0, s, p, st, nullptr, v, ue,
-                       nullptr, nullptr, vn, w, Is, stim, Rv, Re);
+    launch_stencil<ST_RESIDUAL>(s, p, st, (const double*)nullptr, v, ue, (const double*)nullptr,
+                                (const double*)nullptr, vn, w, Is, stim, Rv, Re);
 }
 
 void launch_reaction_diag(hipStream_t s, const FEParams& p, const double* v, const double* w,
@@ -290,14 +306,21 @@ void launch_reaction_diag(hipStream_t s, const FEParams& p, const double* v, con
 
 void launch_jac_apply(hipStream_t s, const FEParams& p, const double* st, const double* dg,
                       const double* x, double* y) {
-    hipLaunchKernelGGL(k_stencil<ST_JAC>, stencil_grid(p), dim3(SX, SY), 0, s, p, st, dg, x, x + p.N, nullptr,
-                       nullptr, nullptr, nullptr, nullptr, 0.0, y, y + p.N);
+    launch_stencil<ST_JAC>(s, p, st, dg, x, x + p.N, (const double*)nullptr, (const double*)nullptr,
+                           (const double*)nullptr, (const double*)nullptr, (const double*)nullptr, 0.0, y, y + p.N);
 }
 
 void launch_res_minus_jac(hipStream_t s, const FEParams& p, const double* st, const double* dg,
                           const double* x, const double* r, double* y) {
-    hipLaunchKernelGGL(k_stencil<ST_RES_MINUS_JAC>, stencil_grid(p), dim3(SX, SY), 0, s, p, st, dg, x, x + p.N,
-                       r, r + p.N, nullptr, nullptr, nullptr, 0.0, y, y + p.N);
+    launch_stencil<ST_RES_MINUS_JAC>(s, p, st, dg, x, x + p.N, r, r + p.N, (const double*)nullptr,
+                                     (const double*)nullptr, (const double*)nullptr, 0.0, y, y + p.N);
+}
+
+int stencil_variants() { return ST_NVAR; }
+void stencil_variant_shape(int v, int* sx, int* sy, int* sz) {
+    *sx = ST_SHAPE[v][0];
+    *sy = ST_SHAPE[v][1];
+    *sz = ST_SHAPE[v][2];
 }
 
 }  // namespace bdm

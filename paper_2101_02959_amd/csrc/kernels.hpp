@@ -23,6 +23,10 @@ void launch_jac_apply(hipStream_t s, const FEParams& p, const double* st, const 
                       const double* x, double* y);
 void launch_res_minus_jac(hipStream_t s, const FEParams& p, const double* st, const double* dg,
                           const double* x, const double* r, double* y);
+// Tile shapes of the stencil kernel (FEParams::stencil_variant); the
+// autotuner picks one per mesh.
+int stencil_variants();
+void stencil_variant_shape(int v, int* sx, int* sy, int* sz);
 
 // ---- dense.hip: batched dense linear algebra, one workgroup per matrix.
 // Per-subdomain layout descriptor (device arrays, length nsub).
@@ -64,17 +68,22 @@ void launch_potrf(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld
 // below; Wbuf holds panel_wbuf_stride() values per matrix, rowblocks = max
 // over the batch of panel_rowblocks(...)), then the trailing update
 // (schur = false); finally the Schur update of the interface block
-// (schur = true).  tiles = max over the batch of syrk_tiles(...).
+// (schur = true).  tiles = max over the batch of syrk_tiles(...) for the
+// same variant of the rank-k kernel (its output tile and inner chunk; the
+// variants are chosen by the autotuner, 0 is the default).
 template <typename T>
 void launch_interior_panel(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* nI,
                            const int* n, int J, T* Wbuf, int rowblocks, int* info);
 template <typename T>
 void launch_syrk_update(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* nI, const int* n,
-                        bool schur, int J, int tiles);
+                        bool schur, int J, int tiles, int variant = 0);
 int interior_panel_width();
 int panel_wbuf_stride();
 int panel_rowblocks(int J, int nI, int n);
-int syrk_tiles(bool schur, int J, int nI, int n);
+int syrk_tiles(bool schur, int J, int nI, int n, int variant = 0);
+int syrk_variants();          // number of rank-k variants
+int syrk_variant_tm(int v);   // output tile edge of variant v
+int syrk_variant_kc(int v);   // inner chunk of variant v
 template <typename T>
 void launch_extract(hipStream_t s, const BatchDesc& d, const T* K, T* slots, T* F, double* Svv,
                     T* Srr);

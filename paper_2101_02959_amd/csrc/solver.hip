@@ -6,6 +6,7 @@
 #include "pcg_slots.hpp"
 
 #include <algorithm>
+#include <functional>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -245,24 +246,8 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
         for (int q = 0; q < nsub; ++q) kr[q] = kc[q] + (int64_t)nI[q] + (int64_t)nI[q] * n[q];
         plan_int_.off = Kc_off_;
         plan_rr_.off = upload(kr);
-        const int wp = interior_panel_width();
-        auto plan = [&](ElimPlan& pl, bool interior) {
-            int maxne = 0;
-            for (const auto& sb : topo.subs) maxne = std::max(maxne, interior ? sb.nI : sb.nr);
-            pl.trail.assign((maxne + wp - 1) / wp, 0);
-            pl.rows.assign(pl.trail.size(), 0);
-            pl.schur = 0;
-            for (const auto& sb : topo.subs) {
-                const int e = interior ? sb.nI : sb.nr, m = interior ? sb.n() : sb.nr;
-                for (size_t q = 0; q < pl.trail.size(); ++q) {
-                    pl.trail[q] = std::max(pl.trail[q], syrk_tiles(false, (int)q * wp, e, m));
-                    pl.rows[q] = std::max(pl.rows[q], panel_rowblocks((int)q * wp, e, m));
-                }
-                pl.schur = std::max(pl.schur, syrk_tiles(true, 0, e, m));
-            }
-        };
-        plan(plan_int_, true);
-        plan(plan_rr_, false);
+        build_plan(plan_int_, true, 0);
+        build_plan(plan_rr_, false, 0);
     }
     nInodes_ = (int)Ilist.size();
 
@@ -458,6 +443,24 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
     HIPOK(hipMemsetAsync(gzero_, 0, 2 * vb, stream_));
     int rc = prec_ ? alloc_local<float>() : alloc_local<double>();
     if (rc) return rc;
+    // autotuner: device name, optional JSON cache, stencil tile shape
+    {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        HIPOK(hipGetDevice(&dev));
+        HIPOK(hipGetDeviceProperties(&prop, dev));
+        tuner_.device = prop.gcnArchName;
+        if (const char* e = std::getenv("BDM_TUNE_CACHE")) tune_path_ = e;
+        if (!tune_path_.empty()) {
+            const std::string err = tuner_.load(tune_path_);
+            if (!err.empty()) {
+                set_error(err + " (" + tune_path_ + ")");
+                return BDM_E_ARG;
+            }
+        }
+        if ((rc = tune_stencil())) return rc;
+        if ((rc = save_tuning())) return rc;
+    }
     return set_state(nullptr, nullptr, nullptr, 0.0, false);
 }
 
@@ -567,6 +570,127 @@ int Context::jacobian_apply(const double* x, double* y) {
     return sync();
 }
 
+// Launch sizes of an elimination plan for rank-k variant `variant`: tiles
+// per matrix and panel row blocks, max over the subdomains.
+void Context::build_plan(ElimPlan& pl, bool interior, int variant) {
+    const int wp = interior_panel_width();
+    int maxne = 0;
+    for (const auto& sb : topo.subs) maxne = std::max(maxne, interior ? sb.nI : sb.nr);
+    pl.variant = variant;
+    pl.trail.assign((maxne + wp - 1) / wp, 0);
+    pl.rows.assign(pl.trail.size(), 0);
+    pl.schur = 0;
+    for (const auto& sb : topo.subs) {
+        const int e = interior ? sb.nI : sb.nr, m = interior ? sb.n() : sb.nr;
+        for (size_t q = 0; q < pl.trail.size(); ++q) {
+            pl.trail[q] = std::max(pl.trail[q], syrk_tiles(false, (int)q * wp, e, m, variant));
+            pl.rows[q] = std::max(pl.rows[q], panel_rowblocks((int)q * wp, e, m));
+        }
+        if (interior) pl.schur = std::max(pl.schur, syrk_tiles(true, 0, e, m, variant));
+    }
+}
+
+// Median of `reps` timed launches of fn on the context stream (ms), after
+// one untimed launch.
+static double time_launches(hipStream_t s, int reps, const std::function<void()>& fn) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return -1.0;
+    if (hipEventCreate(&b) != hipSuccess) {
+        hipEventDestroy(a);
+        return -1.0;
+    }
+    fn();
+    std::vector<double> t;
+    for (int r = 0; r < reps; ++r) {
+        hipEventRecord(a, s);
+        fn();
+        hipEventRecord(b, s);
+        float ms = -1.f;
+        if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) ms = -1.f;
+        t.push_back(ms);
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    std::sort(t.begin(), t.end());
+    return (hipGetLastError() == hipSuccess) ? t[t.size() / 2] : -1.0;
+}
+
+// Stencil tile shape for this mesh: the fused Jacobian apply timed with
+// every shape (it only reads its inputs, so the timing is repeatable).
+int Context::tune_stencil() {
+    char cls[96];
+    std::snprintf(cls, sizeof cls, "mesh %dx%dx%d", fp.nx, fp.ny, fp.nz);
+    launch_fill(stream_, 2 * N, 0.0, kp_);
+    launch_fill(stream_, N, 0.0, dg_);
+    fp.stencil_variant = tuner_.pick("stencil", cls, stencil_variants(), [&](int v) {
+        fp.stencil_variant = v;
+        return time_launches(stream_, 5, [&] { launch_jac_apply(stream_, fp, st_, dg_, kp_, kq_); });
+    });
+    HIPOK(hipStreamSynchronize(stream_));
+    HIPOK(hipGetLastError());
+    return 0;
+}
+
+// Rank-k variants of the interior and r-block elimination plans, timed on the
+// first chunk's workspace before its first assembly (the trailing update after
+// the first panel and, for the interior plan, the Schur update; the workspace
+// is cleared again by the assembly).
+template <typename T>
+int Context::tune_syrk() {
+    const int s0 = chunks_[0].first, cnt = chunks_[0].second - chunks_[0].first;
+    T* K = (T*)K_;
+    int maxnI = 0, maxn = 0, maxnr = 0;
+    for (int q = s0; q < s0 + cnt; ++q) {
+        maxnI = std::max(maxnI, topo.subs[q].nI);
+        maxn = std::max(maxn, topo.subs[q].n());
+        maxnr = std::max(maxnr, topo.subs[q].nr);
+    }
+    launch_fill_t<T>(stream_, nKwork_, (T)1e-3, K);
+    for (int interior = 1; interior >= 0; --interior) {
+        ElimPlan& pl = interior ? plan_int_ : plan_rr_;
+        char cls[128];
+        std::snprintf(cls, sizeof cls, "%s %s nsub=%d ne<=%d n<=%d", prec_ ? "f32" : "f64",
+                      interior ? "interior" : "rblock", cnt, interior ? maxnI : maxnr, interior ? maxn : maxnr);
+        const int v = tuner_.pick("syrk", cls, syrk_variants(), [&](int var) {
+            ElimPlan tp = pl;
+            tp.off = pl.off;
+            tp.ne = pl.ne;
+            tp.n = pl.n;
+            build_plan(tp, interior != 0, var);
+            if (tp.trail.empty() || (tp.trail[0] <= 0 && tp.schur <= 0)) return -1.0;
+            return time_launches(stream_, 3, [&] {
+                if (tp.trail[0] > 0)
+                    launch_syrk_update<T>(stream_, cnt, K, tp.off + s0, ld_ + s0, tp.ne + s0, tp.n + s0, false, 0,
+                                          tp.trail[0], var);
+                if (tp.schur > 0)
+                    launch_syrk_update<T>(stream_, cnt, K, tp.off + s0, ld_ + s0, tp.ne + s0, tp.n + s0, true, 0,
+                                          tp.schur, var);
+            });
+        });
+        const int64_t* off = pl.off;
+        const int *ne = pl.ne, *n = pl.n;
+        build_plan(pl, interior != 0, v);
+        pl.off = off;
+        pl.ne = ne;
+        pl.n = n;
+    }
+    HIPOK(hipStreamSynchronize(stream_));
+    HIPOK(hipGetLastError());
+    syrk_tuned_ = true;
+    return save_tuning();
+}
+
+int Context::save_tuning() {
+    if (tune_path_.empty() || !tuner_.dirty) return 0;
+    const std::string e = tuner_.save(tune_path_);
+    if (!e.empty()) {
+        set_error(e);
+        return BDM_E_ARG;
+    }
+    tuner_.dirty = false;
+    return 0;
+}
+
 int Context::linearize(const double* v, const double* w) {
     const size_t vb = (size_t)N * sizeof(double);
     HIPOK(hipMemcpyAsync(vlin_, v, vb, hipMemcpyDeviceToDevice, stream_));
@@ -604,7 +728,8 @@ int Context::eliminate(T* K, int s0, int cnt, const ElimPlan& pl, double* tm) {
         launch_interior_panel<T>(stream_, cnt, K, pl.off + s0, ld_ + s0, pl.ne + s0, pl.n + s0, J, (T*)Wbuf_,
                                  pl.rows[q], info_sub_ + s0);
         mark(1);
-        launch_syrk_update<T>(stream_, cnt, K, pl.off + s0, ld_ + s0, pl.ne + s0, pl.n + s0, false, J, pl.trail[q]);
+        launch_syrk_update<T>(stream_, cnt, K, pl.off + s0, ld_ + s0, pl.ne + s0, pl.n + s0, false, J, pl.trail[q],
+                              pl.variant);
         mark(2);
         if (tm) {
             lap(0, 1, tm[0]);
@@ -615,7 +740,8 @@ int Context::eliminate(T* K, int s0, int cnt, const ElimPlan& pl, double* tm) {
     }
     if (pl.schur > 0) {
         mark(0);
-        launch_syrk_update<T>(stream_, cnt, K, pl.off + s0, ld_ + s0, pl.ne + s0, pl.n + s0, true, 0, pl.schur);
+        launch_syrk_update<T>(stream_, cnt, K, pl.off + s0, ld_ + s0, pl.ne + s0, pl.n + s0, true, 0, pl.schur,
+                              pl.variant);
         mark(1);
         if (tm) {
             lap(0, 1, tm[1]);
@@ -629,6 +755,10 @@ int Context::eliminate(T* K, int s0, int cnt, const ElimPlan& pl, double* tm) {
 
 template <typename T>
 int Context::linearize_t() {
+    if (!syrk_tuned_) {
+        const int trc = tune_syrk<T>();
+        if (trc) return trc;
+    }
     const int nsub = (int)topo.subs.size();
     const int np = topo.nprimal;
     HIPOK(hipMemsetAsync(bad_, 0, sizeof(int), stream_));

@@ -13,6 +13,7 @@
 #include "common.hpp"
 #include "kernels.hpp"
 #include "topology.hpp"
+#include "tune.hpp"
 
 namespace bdm {
 
@@ -50,8 +51,20 @@ class Context {
         const int* n = nullptr;
         std::vector<int> trail, rows;
         int schur = 0;
+        int variant = 0;        // rank-k kernel variant (autotuned)
     };
     ElimPlan plan_int_, plan_rr_;
+    void build_plan(ElimPlan& pl, bool interior, int variant);
+    // autotuner: stencil tile shape at creation, rank-k variants of the two
+    // elimination plans at the first linearisation (timed on the first chunk)
+    Tuner tuner_;
+    std::string tune_path_;
+    bool syrk_tuned_ = false;
+    int tune_stencil();
+    template <typename T>
+    int tune_syrk();
+    int save_tuning();
+    std::string tune_report() const { return tuner_.report(); }
     template <typename T>
     int eliminate(T* K, int s0, int cnt, const ElimPlan& pl, double* tm);
     int predictor_set(const float* params, const double* scales);

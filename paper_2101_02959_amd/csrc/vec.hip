@@ -87,6 +87,12 @@ __global__ void k_fill(int64_t n, double v, double* __restrict__ x) {
     if (i < n) x[i] = v;
 }
 
+template <typename T>
+__global__ void k_fill_t(int64_t n, T v, T* __restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
 __global__ void k_copy(int64_t n, const double* __restrict__ x, double* __restrict__ y) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) y[i] = x[i];
@@ -138,6 +144,12 @@ void launch_scale_add_dev(hipStream_t s, int64_t n, const double* z, const doubl
 void launch_fill(hipStream_t s, int64_t n, double v, double* x) {
     if (n > 0) hipLaunchKernelGGL(k_fill, dim3(nb(n, 256)), dim3(256), 0, s, n, v, x);
 }
+template <typename T>
+void launch_fill_t(hipStream_t s, int64_t n, T v, T* x) {
+    if (n > 0) hipLaunchKernelGGL(k_fill_t<T>, dim3(nb(n, 256)), dim3(256), 0, s, n, v, x);
+}
+template void launch_fill_t<float>(hipStream_t, int64_t, float, float*);
+template void launch_fill_t<double>(hipStream_t, int64_t, double, double*);
 void launch_copy_kernel(hipStream_t s, int64_t n, const double* x, double* y) {
     if (n > 0) hipLaunchKernelGGL(k_copy, dim3(nb(n, 256)), dim3(256), 0, s, n, x, y);
 }
