@@ -30,6 +30,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "s/time-step & PCG iters/Newton at 17M dofs: FP32+learned vs plain FP64"
+# HBM bytes (read + written) per launch of the dominant kernel, from the two
+# counter runs summarised in profiles/slab256_hbm_traffic_counters.md (FETCH_SIZE
+# and WRITE_SIZE, calibrated by a plain copy).  They hold only for the kernel
+# source and variant they were taken on, so the figure is reported only while
+# dense.hip still has this hash and the autotuner picked the same variant.
+SYRK_TRAFFIC = {"workload": "slab256", "precision": "f32", "variant": 3, "bytes_per_launch": 4951.719e6,
+                "dense_hip_sha256": "a67e881a87a13f0131adc0e93c2c0fbe6c2af78408e0549447ddf9ea05f3b79c"}
+
+
+def _dense_sha256():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2101_02959_amd", "csrc", "dense.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _syrk_variant(tune_entries):
+    """(variant, tile, chunk) of the interior elimination's rank-k kernel."""
+    for e in tune_entries:
+        if e["family"] == "syrk" and " interior " in e["class"]:
+            v = e["choice"]
+            return v, (128 if v < 2 else 64), (16 if v & 1 else 32)
+    return 0, 128, 32
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFS = {"f32": 157.3, "f64": 78.6}
 
@@ -79,10 +102,11 @@ def run_path(P, wl, precision, guess, warmup, steps, predictor=None):
     return S, out, state
 
 
-def kernel_rooflines(P, S, prec_name, reps=5):
+def kernel_rooflines(P, S, prec_name, workload_name, reps=5):
     """Live HIP-event timings of the hot kernels at the current linearisation:
     mean duration of one launch and algorithmic work per launch."""
     tname = "float" if prec_name == "f32" else "double"
+    var, tm, kc = _syrk_variant(S.bdm_tune_report()["entries"])
     peak = MFMA_PEAK_TFS[prec_name]
     out = {}
 
@@ -101,12 +125,17 @@ def kernel_rooflines(P, S, prec_name, reps=5):
                     "algorithmic_bytes_per_launch": nbytes}
 
     mfma("syrk", P.BDM_KERNEL_SYRK_UPDATE,
-         f"k_syrk_batched<{tname}> (rank-k updates of the interior elimination, first setup chunk)")
+         f"k_syrk_batched<{tname}, {tm}, {kc}> (rank-k updates of the interior elimination, first setup chunk)")
+    t = SYRK_TRAFFIC
+    if (prec_name == t["precision"] and workload_name == t["workload"] and var == t["variant"]
+            and _dense_sha256() == t["dense_hip_sha256"]):
+        out["syrk"]["traffic"] = t["bytes_per_launch"]
+        out["syrk"]["traffic_unit"] = "bytes per launch (HBM read + write, calibrated counters)"
     mfma("panel", P.BDM_KERNEL_POTRF_INTERIOR,
          f"k_panel_diag<{tname}> + k_panel_trsm<{tname}> (first setup chunk)")
     hbm("trsv_fwd", P.BDM_KERNEL_TRSV_DIRICHLET, f"k_trsv_fwd<{tname}> (Dirichlet, all subdomains)", 20)
     hbm("trsv_bwd", P.BDM_KERNEL_TRSV_DIRICHLET_T, f"k_trsv_bwd<{tname}> (Dirichlet, all subdomains)", 20)
-    hbm("jacobian", P.BDM_KERNEL_JACOBIAN, "k_stencil<0> (Jacobian apply)", 50)
+    hbm("jacobian", P.BDM_KERNEL_JACOBIAN, "k_stencil<0> (Jacobian apply, autotuned tile shape)", 50)
     return out
 
 
@@ -163,7 +192,7 @@ def main():
     log(f"workload {args.workload}: {dofs} dofs, {wl.mesh.nsub} subdomains")
     log("plain FP64 path")
     S64, plain, st64 = run_path(P, wl, P.BDM_PREC_FP64, P.BDM_GUESS_PREV, args.warmup, args.steps)
-    roof64 = kernel_rooflines(P, S64, "f64")
+    roof64 = kernel_rooflines(P, S64, "f64", args.workload)
     tune64 = S64.bdm_tune_report()["entries"]
     st64 = tuple(t.cpu() if hasattr(t, "cpu") else t for t in st64)
     S64.close()
@@ -172,7 +201,7 @@ def main():
     from paper_2101_02959_amd import predictor as PR
     S32, mixed, st32 = run_path(P, wl, P.BDM_PREC_MIXED, P.BDM_GUESS_CNN, args.warmup, args.steps,
                                 predictor=PR.load())
-    roof32 = kernel_rooflines(P, S32, "f32")
+    roof32 = kernel_rooflines(P, S32, "f32", args.workload)
     tune32 = S32.bdm_tune_report()["entries"]
     st32 = tuple(t.cpu() if hasattr(t, "cpu") else t for t in st32)
     S32.close()
