@@ -80,11 +80,13 @@ def run_path(P, wl, precision, guess, warmup, steps, predictor=None):
     per = []
     nit, lit = 0, 0
     guesses = []
+    true_res = []
     for k in range(steps):
         st = S.bdm_step(1)
         per.append(st.t_step_ms / 1e3)
         nit += st.newton_its
         lit += sum(list(st.krylov_its)[:st.newton_its])
+        true_res += list(st.krylov_true_res)[:st.newton_its]
         guesses.append((st.guess_used, st.guess_res_extrap, st.guess_res_cnn))
         log(f"  step {k}: newton {st.newton_its} pcg {list(st.krylov_its)[:st.newton_its]} "
             f"cond {[round(c, 2) for c in list(st.cond)[:st.newton_its]]} "
@@ -93,7 +95,8 @@ def run_path(P, wl, precision, guess, warmup, steps, predictor=None):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     out = {"s_per_step": wall / steps, "median_s_per_step": float(np.median(per)),
-           "newton_per_step": nit / steps, "pcg_per_newton": lit / max(nit, 1)}
+           "newton_per_step": nit / steps, "pcg_per_newton": lit / max(nit, 1),
+           "linear_solve_true_residual_max": max(true_res) if true_res else None}
     if predictor is not None:
         gains = [e / c for u, e, c in guesses if e > 0 and c > 0]
         out["learned_guess_used"] = sum(1 for g in guesses if g[0] == 2)

@@ -118,6 +118,11 @@ typedef struct bdm_step_stats {
     double guess_res_extrap;    /* ||R|| of the extrapolated guess (or -1)   */
     double guess_res_cnn;       /* ||R|| of the learned guess (or -1)        */
     double res_ref;             /* ||R(u^n)||, the reference of newton_rtol  */
+    double krylov_true_res[32]; /* per Newton iteration: ||b - J s|| / ||b||  */
+                                /* of the linear solve, recomputed in FP64   */
+                                /* on the full system after the solve (the   */
+                                /* error of the result under FP32 local      */
+                                /* factors; b is the projected -R)           */
 } bdm_step_stats;
 
 typedef struct bdm_ctx bdm_ctx;

@@ -67,7 +67,8 @@ class bdm_step_stats(C.Structure):
     _fields_ = [("newton_its", C.c_int), ("krylov_its", C.c_int * 32), ("res_hist", C.c_double * 33),
                 ("cond", C.c_double * 32), ("t_setup_ms", C.c_double), ("t_krylov_ms", C.c_double),
                 ("t_step_ms", C.c_double), ("bad_subdomain", C.c_int), ("guess_used", C.c_int),
-                ("guess_res_extrap", C.c_double), ("guess_res_cnn", C.c_double), ("res_ref", C.c_double)]
+                ("guess_res_extrap", C.c_double), ("guess_res_cnn", C.c_double), ("res_ref", C.c_double),
+                ("krylov_true_res", C.c_double * 32)]
 
 
 _lib = None

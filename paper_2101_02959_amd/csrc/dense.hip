@@ -1002,19 +1002,33 @@ constexpr int DLX_MAXN = 512;
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_deluxe_setup(ObjDesc o, const T* __restrict__ slots,
                                                      T* __restrict__ fac, T* __restrict__ dmat,
-                                                     int* __restrict__ info, int lds_cap) {
+                                                     int* __restrict__ info, int lds_cap, int ob0) {
     extern __shared__ double dlx_lds[];
     __shared__ T ck[DLX_MAXN];
     __shared__ int bad;
-    const int ob = blockIdx.x;
+    const int ob = ob0 + blockIdx.x;
     const int n = o.n[ob];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, wv0 = tid >> 6, lane0 = tid & 63;
     T* M = (n * n <= lds_cap) ? reinterpret_cast<T*>(dlx_lds) : fac + o.fac_off[ob];
     if (tid == 0) bad = 0;
-    for (int idx = tid; idx < n * n; idx += kWG) {
-        T acc = (T)0;
-        for (int q = o.sh_ptr[ob]; q < o.sh_ptr[ob + 1]; ++q) acc += slots[o.sh_slot[q] + idx];
-        M[idx] = acc;
+    // sum of the shares, DS_U entries per thread and pass with all their
+    // loads issued together (clamped addresses, masked stores)
+    {
+        constexpr int DS_U = 8;
+        const int nn = n * n;
+        for (int base = 0; base < nn; base += kWG * DS_U) {
+            T acc[DS_U];
+#pragma unroll
+            for (int u = 0; u < DS_U; ++u) acc[u] = (T)0;
+            for (int q = o.sh_ptr[ob]; q < o.sh_ptr[ob + 1]; ++q) {
+                const T* Sq = slots + o.sh_slot[q];
+#pragma unroll
+                for (int u = 0; u < DS_U; ++u) acc[u] += Sq[min(base + tid + u * kWG, nn - 1)];
+            }
+#pragma unroll
+            for (int u = 0; u < DS_U; ++u)
+                if (base + tid + u * kWG < nn) M[base + tid + u * kWG] = acc[u];
+        }
     }
     __syncthreads();
     for (int k = 0; k < n; ++k) {
@@ -1026,14 +1040,18 @@ __global__ __launch_bounds__(kWG) void k_deluxe_setup(ObjDesc o, const T* __rest
             d = (T)1;
         }
         const T rd = (T)1 / d;
-        for (int idx = tid; idx < n * n; idx += kWG) {
-            const int i = idx % n, j = idx / n;
-            const T ci = ck[i], cj = ck[j];
-            T v;
-            if (i == k) v = (j == k) ? -rd : cj * rd;
-            else if (j == k) v = ci * rd;
-            else v = M[idx] - ci * cj * rd;
-            M[idx] = v;
+        // waves over columns, lanes over rows (no integer division per entry)
+        for (int j = wv0; j < n; j += kWG / 64) {
+            const T cj = ck[j];
+            T* Mj = M + (int64_t)j * n;
+            for (int i = lane0; i < n; i += 64) {
+                const T ci = ck[i];
+                T v;
+                if (i == k) v = (j == k) ? -rd : cj * rd;
+                else if (j == k) v = ci * rd;
+                else v = Mj[i] - ci * cj * rd;
+                Mj[i] = v;
+            }
         }
         __syncthreads();
     }
@@ -1043,9 +1061,39 @@ __global__ __launch_bounds__(kWG) void k_deluxe_setup(ObjDesc o, const T* __rest
     const int wv = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
     const int q0 = o.sh_ptr[ob], q1 = o.sh_ptr[ob + 1];
     const int nt = (n + 15) / 16;
+    constexpr int DS_K = 32;   // k-steps of 4 held in registers: objects up to 128 dofs
     for (int q = q0; q < q1 - 1; ++q) {
         const T* S = slots + o.sh_slot[q];
         T* E = dmat + o.sh_slot[q];
+        if (n <= 4 * DS_K) {
+            // one 16-row strip of S^(m) per wave, loaded into registers once
+            // (one exposed latency) and reused for every column tile of E_m
+            for (int ti = wv; ti < nt; ti += kWG / 64) {
+                const int i = ti * 16 + lr, ic = min(i, n - 1);
+                T a[DS_K];
+#pragma unroll
+                for (int s2 = 0; s2 < DS_K; ++s2) a[s2] = S[ic + (int64_t)min(4 * s2 + lk, n - 1) * n];
+                for (int tj = 0; tj < nt; ++tj) {
+                    const int j = tj * 16 + lr;
+                    typename Mfma<T>::acc acc = {0, 0, 0, 0};
+#pragma unroll
+                    for (int s2 = 0; s2 < DS_K; ++s2) {
+                        if (4 * s2 < n) {
+                            const int k = 4 * s2 + lk;
+                            const T av = (i < n && k < n) ? a[s2] : (T)0;
+                            const T b = (k < n && j < n) ? M[k + j * n] : (T)0;
+                            acc = Mfma<T>::mac(av, b, acc);
+                        }
+                    }
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = ti * 16 + Mfma<T>::row(lane, v);
+                        if (r < n && j < n) E[r + j * n] = -acc[v];
+                    }
+                }
+            }
+            continue;
+        }
         for (int tile = wv; tile < nt * nt; tile += kWG / 64) {
             const int i = (tile % nt) * 16 + lr, j = (tile / nt) * 16 + lr;
             typename Mfma<T>::acc acc = {0, 0, 0, 0};
@@ -1065,12 +1113,141 @@ __global__ __launch_bounds__(kWG) void k_deluxe_setup(ObjDesc o, const T* __rest
     __syncthreads();
     {
         T* E = dmat + o.sh_slot[q1 - 1];
-        for (int idx = tid; idx < n * n; idx += kWG) {
-            T acc = (idx % n == idx / n) ? (T)1 : (T)0;
-            for (int q = q0; q < q1 - 1; ++q) acc -= dmat[o.sh_slot[q] + idx];
-            E[idx] = acc;
+        for (int j = wv0; j < n; j += kWG / 64)
+            for (int i = lane0; i < n; i += 64) {
+                const int64_t idx = i + (int64_t)j * n;
+                T acc = (i == j) ? (T)1 : (T)0;
+                for (int q = q0; q < q1 - 1; ++q) acc -= dmat[o.sh_slot[q] + idx];
+                E[idx] = acc;
+            }
+    }
+    if (tid == 0 && bad) info[ob] = 1;
+}
+
+// Objects of DS_MIN < n <= DS_N dofs (the faces of subdomains up to H/h = 8,
+// with their boundary nodes): the sweep runs in registers.  Thread (wave w,
+// lane l) holds the entries (i = l + 64 a, j = w + 4 b) of sum S; for each
+// pivot k the lane holding row k publishes it (the matrix stays symmetric,
+// so row k is column k) into one of two LDS vectors, one barrier, and every
+// thread updates its own entries.  The code is straight-line: indices are
+// clamped into the object and entries beyond n are carried along but never
+// stored.  The result -(sum S)^{-1} goes to LDS for the MFMA products
+// E_m = -S^(m) M (per wave a 16-row strip of S^(m), per 16x16 tile all the
+// strip's loads issued together); the last share's E is the identity minus
+// the others, formed from the same product tiles without reading them back.
+constexpr int DS_N = 128, DS_MIN = 32;
+
+template <typename T>
+__global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 2 : 1) void k_deluxe_small(
+    ObjDesc o, const T* __restrict__ slots, T* __restrict__ fac, T* __restrict__ dmat, int* __restrict__ info,
+    int lds_cap, int ob0) {
+    extern __shared__ double dlx_lds[];
+    __shared__ T ck[2][DS_N];
+    __shared__ int bad;
+    constexpr int NA = DS_N / 64, NBW = DS_N / (kWG / 64), DS_K = DS_N / 4;
+    const int ob = ob0 + blockIdx.x;
+    const int n = o.n[ob];
+    // the wave index is uniform within a wave: column indices, offsets and
+    // tests derived from it stay in scalar registers
+    const int tid = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int wvv = tid >> 6;   // the same wave index as a per-lane value: tests on it compile to selects
+    T* M = (n * n <= lds_cap) ? reinterpret_cast<T*>(dlx_lds) : fac + o.fac_off[ob];
+    if (tid == 0) bad = 0;
+    const int q0 = o.sh_ptr[ob], q1 = o.sh_ptr[ob + 1];
+    int ri[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) ri[a] = min(lane + 64 * a, n - 1);
+    T r[NA][NBW];
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+        for (int b = 0; b < NBW; ++b) r[a][b] = (T)0;
+    for (int q = q0; q < q1; ++q) {
+        const T* Sq = slots + o.sh_slot[q];
+#pragma unroll
+        for (int b = 0; b < NBW; ++b) {
+            const T* col = Sq + (int64_t)min(wv + 4 * b, n - 1) * n;
+#pragma unroll
+            for (int a = 0; a < NA; ++a) r[a][b] += col[ri[a]];
         }
     }
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        const int buf = k & 1;
+        if (lane == (k & 63)) {
+            const bool hi = k >= 64;
+#pragma unroll
+            for (int b = 0; b < NBW; ++b) ck[buf][wv + 4 * b] = hi ? r[NA - 1][b] : r[0][b];
+        }
+        __syncthreads();
+        T d = ck[buf][k];
+        if (!(d > (T)0)) {
+            if (tid == 0) bad = 1;
+            d = (T)1;
+        }
+        const T rd = (T)1 / d;
+        T ci[NA];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) ci[a] = ck[buf][ri[a]];
+#pragma unroll
+        for (int b = 0; b < NBW; ++b) {
+            const T cj = ck[buf][min(wv + 4 * b, n - 1)];
+            const bool jk = wvv + 4 * b == k;
+#pragma unroll
+            for (int a = 0; a < NA; ++a) {
+                const bool ik = lane + 64 * a == k;
+                const T v = r[a][b];
+                const T g = v - ci[a] * cj * rd;                 // entries off row and column k
+                const T e = ik ? (jk ? -rd : cj * rd) : ci[a] * rd;
+                r[a][b] = (ik || jk) ? e : g;
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+        for (int b = 0; b < NBW; ++b) {
+            const int i = lane + 64 * a, j = wv + 4 * b;
+            if (i < n && j < n) M[i + j * n] = r[a][b];
+        }
+    __syncthreads();
+    const int nt = (n + 15) / 16;
+    for (int ti = wv; ti < nt; ti += kWG / 64) {
+        const int i = ti * 16 + lr, ic = min(i, n - 1);
+        for (int tj = 0; tj < nt; ++tj) {
+            const int j = tj * 16 + lr, jc = min(j, n - 1);
+            typename Mfma<T>::acc esum = {0, 0, 0, 0};
+            for (int q = q0; q < q1 - 1; ++q) {
+                const T* S = slots + o.sh_slot[q];
+                T av[DS_K];
+#pragma unroll
+                for (int s2 = 0; s2 < DS_K; ++s2) av[s2] = S[ic + (int64_t)min(4 * s2 + lk, n - 1) * n];
+                typename Mfma<T>::acc acc = {0, 0, 0, 0};
+#pragma unroll
+                for (int s2 = 0; s2 < DS_K; ++s2) {
+                    const int k = 4 * s2 + lk;
+                    const T y = M[min(k, n - 1) + jc * n];
+                    const bool in = k < n;
+                    acc = Mfma<T>::mac((in && i < n) ? av[s2] : (T)0, (in && j < n) ? y : (T)0, acc);
+                }
+                T* E = dmat + o.sh_slot[q];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int rr = ti * 16 + Mfma<T>::row(lane, v);
+                    if (rr < n && j < n) E[rr + j * n] = -acc[v];
+                }
+                esum += acc;
+            }
+            T* E = dmat + o.sh_slot[q1 - 1];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rr = ti * 16 + Mfma<T>::row(lane, v);
+                if (rr < n && j < n) E[rr + j * n] = (rr == j ? (T)1 : (T)0) + esum[v];
+            }
+        }
+    }
+    __syncthreads();
     if (tid == 0 && bad) info[ob] = 1;
 }
 
@@ -1165,7 +1342,9 @@ void launch_trsv(hipStream_t s, int nb, bool trans, const T* L, const int64_t* L
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kWG), lds, s, L, Loff, n, ld, x, xoff, nb, ord, ctr);
 }
 template <typename T>
-void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, int maxn, const T* slots, T* fac, T* dmat, int* info) {
+void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, int ob0, int nob, int maxn, const T* slots, T* fac, T* dmat,
+                         int* info) {
+    if (nob <= 0) return;
     static int lds_max = -1;   // bytes of LDS a workgroup may use on this device
     if (lds_max < 0) {
         int dev = 0, v = 0;
@@ -1174,10 +1353,17 @@ void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, int maxn, const T* slo
             v = 65536;
         lds_max = v;
     }
+    if (maxn > DS_MIN && maxn <= DS_N) {
+        const int avail = lds_max - (int)(2 * DS_N * sizeof(T)) - 64;
+        const int cap = std::max(0, std::min(maxn * maxn, avail / (int)sizeof(T)));
+        hipLaunchKernelGGL(k_deluxe_small<T>, dim3(nob), dim3(kWG), (size_t)cap * sizeof(T), s, o, slots, fac, dmat,
+                           info, cap, ob0);
+        return;
+    }
     const int avail = lds_max - (int)(DLX_MAXN * sizeof(T)) - 64;
     const int cap = std::max(0, std::min(maxn * maxn, avail / (int)sizeof(T)));
-    hipLaunchKernelGGL(k_deluxe_setup<T>, dim3(o.nobj), dim3(kWG), (size_t)cap * sizeof(T), s, o, slots, fac, dmat,
-                       info, cap);
+    hipLaunchKernelGGL(k_deluxe_setup<T>, dim3(nob), dim3(kWG), (size_t)cap * sizeof(T), s, o, slots, fac, dmat,
+                       info, cap, ob0);
 }
 int deluxe_max_object() { return DLX_MAXN; }
 
@@ -1199,7 +1385,7 @@ int deluxe_max_object() { return DLX_MAXN; }
                                          double*, int*);                                                 \
     template void launch_trsv<T>(hipStream_t, int, bool, const T*, const int64_t*, const int*,          \
                                  const int*, T*, const int64_t*, int, const WorkQueue&);                 \
-    template void launch_deluxe_setup<T>(hipStream_t, const ObjDesc&, int, const T*, T*, T*, int*);
+    template void launch_deluxe_setup<T>(hipStream_t, const ObjDesc&, int, int, int, const T*, T*, T*, int*);
 BDM_INST(double)
 BDM_INST(float)
 #undef BDM_INST

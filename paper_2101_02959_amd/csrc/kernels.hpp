@@ -124,11 +124,13 @@ struct ObjDesc {
     const int* sh_roff;    // offset of the object in that subdomain's r-dofs
     const int64_t* sh_slot;// that subdomain's block S^(m) (n x n)
 };
-// Deluxe setup of every face / edge: E_m = S^(m) (sum S)^{-1} into dmat;
-// maxn bounds the object sizes (at most deluxe_max_object()); fac is the
-// per-object workspace for objects too large for LDS.
+// Deluxe setup of the objects [ob0, ob0 + nob): E_m = S^(m) (sum S)^{-1}
+// into dmat; maxn bounds their sizes (at most deluxe_max_object()) and sets
+// the LDS each workgroup reserves, so faces and edges are launched
+// separately; fac is the per-object workspace for objects too large for LDS.
 template <typename T>
-void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, int maxn, const T* slots, T* fac, T* dmat, int* info);
+void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, int ob0, int nob, int maxn, const T* slots, T* fac,
+                         T* dmat, int* info);
 int deluxe_max_object();
 
 }  // namespace bdm

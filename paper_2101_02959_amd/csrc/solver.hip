@@ -264,10 +264,13 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
         for (size_t t = 0; t < sb.edges.size(); ++t) roff_of[{nF + sb.edges[t], q}] = sb.edge_off[t];
     }
     int64_t accSlot = 0, accFac = 0, accY = 0;
+    nface_obj_ = nF;
     for (int ob = 0; ob < nobj; ++ob) {
         const Object& O = ob < nF ? topo.faces[ob] : topo.edges[ob - nF];
         on[ob] = 2 * (int)O.nodes.size();
         maxobjn_ = std::max(maxobjn_, on[ob]);
+        if (ob < nF) maxface_n_ = std::max(maxface_n_, on[ob]);
+        else maxedge_n_ = std::max(maxedge_n_, on[ob]);
         if (on[ob] > MAXOBJ) {
             set_error("interface object larger than supported");
             return BDM_E_ARG;
@@ -785,7 +788,10 @@ int Context::linearize_t() {
     }
     launch_trsm_fwd<T>(stream_, nsub, (const T*)Lrrs_, Lrr_off_, nr_, nr_, (T*)F_, bd_.F_off, nr_, kF_);
     launch_coarse_local<T>(stream_, bd_, (const T*)F_, Svv_, (T*)Z_, (T*)Gi_, Sp_, info_sub_);
-    launch_deluxe_setup<T>(stream_, od_, maxobjn_, (const T*)slots_, (T*)fac_, (T*)dmat_, info_obj_);
+    // faces and edges separately: each launch reserves LDS for its own largest object
+    launch_deluxe_setup<T>(stream_, od_, 0, nface_obj_, maxface_n_, (const T*)slots_, (T*)fac_, (T*)dmat_, info_obj_);
+    launch_deluxe_setup<T>(stream_, od_, nface_obj_, od_.nobj - nface_obj_, maxedge_n_, (const T*)slots_, (T*)fac_,
+                           (T*)dmat_, info_obj_);
     coarse_.factor(stream_, color_list_, color_ptr_, nP_, Sp_, SP_STRIDE);
     int hb = 0, hc = 0;
     std::vector<int> hs(nsub), ho(od_.nobj);
@@ -1351,6 +1357,11 @@ int Context::step(int nsteps, bdm_step_stats* st) {
             rc = newton_solve(R_, S_, ko);
             tkry += std::chrono::duration<double, std::milli>(clk::now() - tk).count();
             if (rc) return rc;
+            // error of this solve, recomputed in FP64 on the full system:
+            // ||b - J s|| / ||b|| with b the projected right-hand side (Rt_)
+            launch_res_minus_jac(stream_, fp, st_, dg_, S_, Rt_, t1_);
+            const double bn = std::sqrt(dot(2 * N, Rt_, Rt_));
+            S.krylov_true_res[it] = bn > 0 ? std::sqrt(dot(2 * N, t1_, t1_)) / bn : 0.0;
             launch_scale_add(stream_, 2 * N, gzero_, -1.0, R_);   // restore R
             S.krylov_its[it] = ko.its;
             S.cond[it] = ko.cond;

@@ -145,6 +145,12 @@ def test_time_steps_match_direct_newton(method, prec):
         assert _rel(wg, wr) <= 1e-14
         assert 1 <= st.newton_its <= 5
         assert all(3 <= st.krylov_its[k] <= 60 for k in range(st.newton_its))
+        # error of each Newton linear solve, recomputed in FP64 after the solve:
+        # PCG stops at 1e-10 on its own residual (BDDC: the full system; FETI-DP:
+        # the multiplier system, whose recovery adds the local solves' rounding)
+        true_res = [st.krylov_true_res[k] for k in range(st.newton_its)]
+        print(step, method, prec, true_res)
+        assert all(0 <= t <= (1e-9 if method == 0 else 1e-6) for t in true_res), true_res
         v, ue, w = vg, ueg, wg
 
 
