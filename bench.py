@@ -34,16 +34,20 @@ METRIC = "s/time-step & PCG iters/Newton at 17M dofs: FP32+learned vs plain FP64
 # counter runs summarised in profiles/slab256_hbm_traffic_counters.md (FETCH_SIZE
 # and WRITE_SIZE, calibrated by a plain copy).  They hold only for the kernel
 # source and variant they were taken on, so the figure is reported only while
-# dense.hip still has this hash and the autotuner picked the same variant.
+# the rank-k kernel's source (its constants through the end of the kernel in
+# dense.hip) still has this hash and the autotuner picked the same variant.
 SYRK_TRAFFIC = {"workload": "slab256", "precision": "f32", "variant": 3, "bytes_per_launch": 4951.719e6,
-                "dense_hip_sha256": "a67e881a87a13f0131adc0e93c2c0fbe6c2af78408e0549447ddf9ea05f3b79c"}
+                "kernel_source_sha256": "eb79a1710126ef95aa90b6794425f7900a0a24efd6a48a719feb9319ac7def47"}
 
 
-def _dense_sha256():
+def _syrk_source_sha256():
     import hashlib
     path = os.path.join(ROOT, "paper_2101_02959_amd", "csrc", "dense.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    with open(path) as f:
+        src = f.read()
+    a = src.index("constexpr int SY_XCD")
+    b = src.index("\n}\n", src.index("void k_syrk_batched(", a)) + 3
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
 def _syrk_variant(tune_entries):
@@ -131,7 +135,7 @@ def kernel_rooflines(P, S, prec_name, workload_name, reps=5):
          f"k_syrk_batched<{tname}, {tm}, {kc}> (rank-k updates of the interior elimination, first setup chunk)")
     t = SYRK_TRAFFIC
     if (prec_name == t["precision"] and workload_name == t["workload"] and var == t["variant"]
-            and _dense_sha256() == t["dense_hip_sha256"]):
+            and _syrk_source_sha256() == t["kernel_source_sha256"]):
         out["syrk"]["traffic"] = t["bytes_per_launch"]
         out["syrk"]["traffic_unit"] = "bytes per launch (HBM read + write, calibrated counters)"
     mfma("panel", P.BDM_KERNEL_POTRF_INTERIOR,
