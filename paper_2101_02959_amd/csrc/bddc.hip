@@ -42,8 +42,11 @@ __global__ void k_scatter_I(int n, const int* __restrict__ list, int64_t N, cons
     out[N + g] = (double)x[2 * (int64_t)t + 1];
 }
 
-// Residual side of the deluxe scaling, E_D^T: for an object shared by
-// subdomains m, g^(m) = S^(m) (sum S)^{-1} g = E_m g.
+// Residual side of the deluxe scaling, E_D^T: for every share m of the
+// object, y^(m) = E_m g (g gathered once into LDS).  One thread per (share,
+// row) pair, four independent accumulators along the row, so a face's two
+// shares keep two thirds of the workgroup busy and the reads of E_m are
+// coalesced across the rows.
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_deluxe_res(ObjDesc o, int64_t N, const double* __restrict__ g,
                                                    const T* __restrict__ dmat, T* __restrict__ xr,
@@ -54,35 +57,93 @@ __global__ __launch_bounds__(kWG) void k_deluxe_res(ObjDesc o, int64_t N, const 
     const int* nodes = o.nodes + o.node_off[ob];
     for (int i = tid; i < n; i += kWG) h[i] = g[(i & 1) * N + nodes[i >> 1]];
     __syncthreads();
-    for (int q = o.sh_ptr[ob]; q < o.sh_ptr[ob + 1]; ++q) {
-        const T* E = dmat + o.sh_slot[q];
-        T* dst = xr + xoff[o.sh_sub[q]] + o.sh_roff[q];
-        for (int i = tid; i < n; i += kWG) {
-            double acc = 0.0;
-            for (int j = 0; j < n; ++j) acc += (double)E[i + (int64_t)j * n] * h[j];
-            dst[i] = (T)acc;
+    const int q0 = o.sh_ptr[ob], nsh = o.sh_ptr[ob + 1] - q0;
+    for (int t = tid; t < nsh * n; t += kWG) {
+        const int q = q0 + t / n, i = t % n;
+        const T* E = dmat + o.sh_slot[q] + i;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int j = 0;
+        for (; j + 4 <= n; j += 4) {
+            a0 += (double)E[(int64_t)j * n] * h[j];
+            a1 += (double)E[(int64_t)(j + 1) * n] * h[j + 1];
+            a2 += (double)E[(int64_t)(j + 2) * n] * h[j + 2];
+            a3 += (double)E[(int64_t)(j + 3) * n] * h[j + 3];
         }
+        for (; j < n; ++j) a0 += (double)E[(int64_t)j * n] * h[j];
+        xr[xoff[o.sh_sub[q]] + o.sh_roff[q] + i] = (T)((a0 + a1) + (a2 + a3));
     }
 }
 
 // Value side of the deluxe scaling, E_D: u = (sum S)^{-1} sum_m S^(m) u^(m)
-// = sum_m E_m^T u^(m); one wave per output entry (lanes run along E's columns).
+// = sum_m E_m^T u^(m), with the transposes E_m^T stored beside E_m (Et), so
+// the reads are coalesced across the output rows.  The shares' u^(m) are
+// staged in LDS; threads take (row, half of the inner range), four
+// accumulators each, and the two halves are added through LDS.
+constexpr int DV_SH = 4;   // shares per object: 2 on a face, up to 4 on an edge
 template <typename T>
-__global__ __launch_bounds__(kWG) void k_deluxe_val(ObjDesc o, int64_t N, const T* __restrict__ dmat,
+__global__ __launch_bounds__(kWG) void k_deluxe_val(ObjDesc o, int64_t N, const T* __restrict__ Et,
                                                    const T* __restrict__ xr, const int64_t* __restrict__ xoff,
                                                    double* __restrict__ z) {
-    const int ob = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int ob = blockIdx.x, tid = threadIdx.x;
     const int n = o.n[ob];
     const int* nodes = o.nodes + o.node_off[ob];
-    for (int i = wv; i < n; i += kWG / 64) {
-        double acc = 0.0;
-        for (int q = o.sh_ptr[ob]; q < o.sh_ptr[ob + 1]; ++q) {
-            const T* E = dmat + o.sh_slot[q] + (int64_t)i * n;
-            const T* u = xr + xoff[o.sh_sub[q]] + o.sh_roff[q];
-            for (int j = lane; j < n; j += 64) acc += (double)E[j] * (double)u[j];
+    const int q0 = o.sh_ptr[ob], nsh = o.sh_ptr[ob + 1] - q0;
+    __shared__ double us[DV_SH][MAXO];
+    __shared__ double part[kWG];
+    for (int t = tid; t < nsh * n; t += kWG) {
+        const int q = t / n, j = t % n;
+        us[q][j] = (double)xr[xoff[o.sh_sub[q0 + q]] + o.sh_roff[q0 + q] + j];
+    }
+    __syncthreads();
+    const int half = (n + 1) / 2, hp = tid / (kWG / 2), il = tid % (kWG / 2);
+    for (int i0 = 0; i0 < n; i0 += kWG / 2) {
+        const int i = i0 + il;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        if (i < n) {
+            const int jb = hp * half, je = min(n, jb + half);
+            for (int q = 0; q < nsh; ++q) {
+                const T* F = Et + o.sh_slot[q0 + q] + i;
+                const double* u = us[q];
+                int j = jb;
+                for (; j + 4 <= je; j += 4) {
+                    a0 += (double)F[(int64_t)j * n] * u[j];
+                    a1 += (double)F[(int64_t)(j + 1) * n] * u[j + 1];
+                    a2 += (double)F[(int64_t)(j + 2) * n] * u[j + 2];
+                    a3 += (double)F[(int64_t)(j + 3) * n] * u[j + 3];
+                }
+                for (; j < je; ++j) a0 += (double)F[(int64_t)j * n] * u[j];
+            }
         }
-        acc = wsum(acc);
-        if (lane == 0) z[(i & 1) * N + nodes[i >> 1]] = acc;
+        part[tid] = (a0 + a1) + (a2 + a3);
+        __syncthreads();
+        if (hp == 0 && i < n) z[(i & 1) * N + nodes[i >> 1]] = part[tid] + part[tid + kWG / 2];
+        __syncthreads();
+    }
+}
+
+// E_m^T beside every E_m (one workgroup per object, 32 x 32 tiles through
+// LDS so that reads and writes are both coalesced).
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_deluxe_transpose(ObjDesc o, const T* __restrict__ dmat, T* __restrict__ Et) {
+    __shared__ T tl[32][33];
+    const int ob = blockIdx.x, tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+    const int n = o.n[ob];
+    for (int q = o.sh_ptr[ob]; q < o.sh_ptr[ob + 1]; ++q) {
+        const T* E = dmat + o.sh_slot[q];
+        T* F = Et + o.sh_slot[q];
+        for (int bj = 0; bj < n; bj += 32)
+            for (int bi = 0; bi < n; bi += 32) {
+                for (int y = ty; y < 32; y += kWG / 32) {
+                    const int i = bi + tx, j = bj + y;
+                    if (i < n && j < n) tl[y][tx] = E[i + (int64_t)j * n];
+                }
+                __syncthreads();
+                for (int y = ty; y < 32; y += kWG / 32) {
+                    const int j = bj + tx, i = bi + y;   // F(j, i) = E(i, j), F column-major
+                    if (i < n && j < n) F[j + (int64_t)i * n] = tl[tx][y];
+                }
+                __syncthreads();
+            }
     }
 }
 
@@ -333,10 +394,15 @@ void launch_deluxe_res(hipStream_t s, const ObjDesc& o, int64_t N, const double*
     hipLaunchKernelGGL(k_deluxe_res<T>, dim3(o.nobj), dim3(kWG), 0, s, o, N, g, dmat, xr, xoff);
 }
 template <typename T>
-void launch_deluxe_val(hipStream_t s, const ObjDesc& o, int64_t N, const T* dmat, const T* xr,
+void launch_deluxe_val(hipStream_t s, const ObjDesc& o, int64_t N, const T* dmatT, const T* xr,
                        const int64_t* xoff, double* z) {
-    hipLaunchKernelGGL(k_deluxe_val<T>, dim3(o.nobj), dim3(kWG), 0, s, o, N, dmat, xr, xoff, z);
+    hipLaunchKernelGGL(k_deluxe_val<T>, dim3(o.nobj), dim3(kWG), 0, s, o, N, dmatT, xr, xoff, z);
 }
+template <typename T>
+void launch_deluxe_transpose(hipStream_t s, const ObjDesc& o, const T* dmat, T* dmatT) {
+    hipLaunchKernelGGL(k_deluxe_transpose<T>, dim3(o.nobj), dim3(kWG), 0, s, o, dmat, dmatT);
+}
+int deluxe_max_shares() { return DV_SH; }
 template <typename T>
 void launch_coarse_rhs_local(hipStream_t s, const SubVecDesc& d, const T* xr, const T* F, const T* Z,
                              const T* Gi, double* cP, double* mu) {
@@ -397,6 +463,7 @@ void launch_take_first(hipStream_t s, const ObjDesc& o, int64_t N, const T* xr, 
                                        const int64_t*);                                                     \
     template void launch_deluxe_val<T>(hipStream_t, const ObjDesc&, int64_t, const T*, const T*,            \
                                        const int64_t*, double*);                                            \
+    template void launch_deluxe_transpose<T>(hipStream_t, const ObjDesc&, const T*, T*);                   \
     template void launch_coarse_rhs_local<T>(hipStream_t, const SubVecDesc&, const T*, const T*, const T*,  \
                                              const T*, double*, double*);                                   \
     template void launch_neumann_rhs<T>(hipStream_t, const SubVecDesc&, const T*, const T*, const double*,  \

@@ -51,8 +51,13 @@ template <typename T>
 void launch_deluxe_res(hipStream_t s, const ObjDesc& o, int64_t N, const double* g, const T* dmat, T* xr,
                        const int64_t* xoff);
 template <typename T>
-void launch_deluxe_val(hipStream_t s, const ObjDesc& o, int64_t N, const T* dmat, const T* xr,
+void launch_deluxe_val(hipStream_t s, const ObjDesc& o, int64_t N, const T* dmatT, const T* xr,
                        const int64_t* xoff, double* z);
+// dmatT <- the transpose of every E_m block of dmat (same offsets), for the
+// value side; deluxe_max_shares() bounds the shares of one object.
+template <typename T>
+void launch_deluxe_transpose(hipStream_t s, const ObjDesc& o, const T* dmat, T* dmatT);
+int deluxe_max_shares();
 template <typename T>
 void launch_coarse_rhs_local(hipStream_t s, const SubVecDesc& d, const T* xr, const T* F, const T* Z,
                              const T* Gi, double* cP, double* mu);

@@ -271,8 +271,8 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
         maxobjn_ = std::max(maxobjn_, on[ob]);
         if (ob < nF) maxface_n_ = std::max(maxface_n_, on[ob]);
         else maxedge_n_ = std::max(maxedge_n_, on[ob]);
-        if (on[ob] > MAXOBJ) {
-            set_error("interface object larger than supported");
+        if (on[ob] > MAXOBJ || (int)O.subs.size() > deluxe_max_shares()) {
+            set_error("interface object larger or more widely shared than supported");
             return BDM_E_ARG;
         }
         onode_off[ob] = (int64_t)onodes.size();
@@ -486,6 +486,7 @@ int Context::alloc_local() {
     fac_ = dalloc(nfac_ * sizeof(T));
     inv_ = dalloc(nfac_ * sizeof(T));
     dmat_ = dalloc(nslot_ * sizeof(T));
+    dmatT_ = dalloc(nslot_ * sizeof(T));
     Srr_ = feti ? dalloc(nSrr_ * sizeof(T)) : nullptr;
     xI_ = dalloc(nxI_ * sizeof(T));
     xr_ = dalloc(nxr_ * sizeof(T));
@@ -507,7 +508,7 @@ int Context::alloc_local() {
     info_sub_ = (int*)dalloc(nsub * sizeof(int));
     info_obj_ = (int*)dalloc((size_t)od_.nobj * sizeof(int));
     info_c_ = (int*)dalloc(sizeof(int));
-    if (!K_ || !Wbuf_ || !LIIs_ || !Lrrs_ || !slots_ || !inv_ || !dmat_ || !F_ || !Z_ || !Gi_ || !fac_ || (feti && !Srr_) || !xI_ || !xr_ ||
+    if (!K_ || !Wbuf_ || !LIIs_ || !Lrrs_ || !slots_ || !inv_ || !dmat_ || !dmatT_ || !F_ || !Z_ || !Gi_ || !fac_ || (feti && !Srr_) || !xI_ || !xr_ ||
         !xr2_ || !Svv_ || !Sp_ || !cP_ || !mu_ || !cb_ || !ybuf_ || !info_sub_ || !info_obj_ || !info_c_) {
         set_error("device allocation failed (local factors)");
         return BDM_E_OOM;
@@ -792,6 +793,7 @@ int Context::linearize_t() {
     launch_deluxe_setup<T>(stream_, od_, 0, nface_obj_, maxface_n_, (const T*)slots_, (T*)fac_, (T*)dmat_, info_obj_);
     launch_deluxe_setup<T>(stream_, od_, nface_obj_, od_.nobj - nface_obj_, maxedge_n_, (const T*)slots_, (T*)fac_,
                            (T*)dmat_, info_obj_);
+    launch_deluxe_transpose<T>(stream_, od_, (const T*)dmat_, (T*)dmatT_);
     coarse_.factor(stream_, color_list_, color_ptr_, nP_, Sp_, SP_STRIDE);
     int hb = 0, hc = 0;
     std::vector<int> hs(nsub), ho(od_.nobj);
@@ -879,7 +881,7 @@ int Context::bddc_apply_t(const double* r, double* z) {
     launch_deluxe_res<T>(stream_, od_, N, t2_, (const T*)dmat_, (T*)xr_, xr_off_);
     stilde_inv<T>((T*)xr_, t2_, cb_);
     launch_fill(stream_, 2 * N, 0.0, t3_);
-    launch_deluxe_val<T>(stream_, od_, N, (const T*)dmat_, (const T*)xr_, xr_off_, t3_);
+    launch_deluxe_val<T>(stream_, od_, N, (const T*)dmatT_, (const T*)xr_, xr_off_, t3_);
     launch_vertex_val(stream_, cd_.nverts, cd_.vnode, N, cb_, t3_);
     interior_extend<T>(r, t3_);
     HIPOK(hipMemcpyAsync(z, t3_, 2 * N * sizeof(double), hipMemcpyDeviceToDevice, stream_));

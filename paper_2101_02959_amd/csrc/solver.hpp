@@ -123,6 +123,7 @@ class Context {
     double *cb_ = nullptr, *ybuf_ = nullptr;
     void *LIIs_ = nullptr, *Lrrs_ = nullptr;   // compact Dirichlet / Neumann factors
     void *inv_ = nullptr, *dmat_ = nullptr;    // deluxe (sum S)^{-1} and E_m = S^(m) (sum S)^{-1}
+    void* dmatT_ = nullptr;                    // E_m^T (value side of the scaling)
     CoarseSolver coarse_;
     Predictor pred_;
     int ensure_predictor();
