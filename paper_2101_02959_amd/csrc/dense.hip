@@ -632,7 +632,9 @@ __global__ __launch_bounds__(kWG) void k_extract(BatchDesc d, const T* __restric
 }
 
 // Copy the lower triangles of the Dirichlet factor L_II and the Neumann
-// factor L_rr out of the chunk workspace into compact square storage.
+// factor L_rr out of the chunk workspace into compact square storage (the
+// strict upper parts are never read).  Waves run over columns, lanes down a
+// column.
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_copy_out(BatchDesc d, const T* __restrict__ K, T* __restrict__ LII,
                                                  const int64_t* __restrict__ LIIoff, T* __restrict__ Lrr,
@@ -640,18 +642,30 @@ __global__ __launch_bounds__(kWG) void k_copy_out(BatchDesc d, const T* __restri
     const int s = d.sub0 + blockIdx.x;
     const int64_t ld = d.n[s];
     const int nI = d.nI[s], nr = d.nr[s];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const T* A = K + d.K_off[s];
     T* a = LII + LIIoff[s];
-    for (int64_t idx = threadIdx.x; idx < (int64_t)nI * nI; idx += kWG) {
-        const int i = (int)(idx % nI), j = (int)(idx / nI);
-        a[idx] = (i >= j) ? A[i + (int64_t)j * ld] : (T)0;
-    }
+    for (int j = wv; j < nI; j += kWG / 64)
+        for (int i = j + lane; i < nI; i += 64) a[i + (int64_t)j * nI] = A[i + (int64_t)j * ld];
     const T* B = A + (int64_t)nI * (ld + 1);
     T* b = Lrr + Lrroff[s];
-    for (int64_t idx = threadIdx.x; idx < (int64_t)nr * nr; idx += kWG) {
-        const int i = (int)(idx % nr), j = (int)(idx / nr);
-        b[idx] = (i >= j) ? B[i + (int64_t)j * ld] : (T)0;
-    }
+    for (int j = wv; j < nr; j += kWG / 64)
+        for (int i = j + lane; i < nr; i += 64) b[i + (int64_t)j * nr] = B[i + (int64_t)j * ld];
+}
+
+// Zero the lower triangle (diagonal included) of every local matrix of a
+// chunk before its assembly: the elimination, extraction and copy-out read
+// and write lower-triangle entries only.  Grid: (column blocks of CL_COLS,
+// matrices).
+constexpr int CL_COLS = 16;
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_clear_lower(BatchDesc d, T* __restrict__ K) {
+    const int s = d.sub0 + blockIdx.y;
+    const int n = d.n[s];
+    T* A = K + d.K_off[s];
+    const int j1 = min(n, ((int)blockIdx.x + 1) * CL_COLS);
+    for (int j = blockIdx.x * CL_COLS; j < j1; ++j)
+        for (int i = j + (int)threadIdx.x; i < n; i += kWG) A[i + (int64_t)j * n] = (T)0;
 }
 
 // ----------------------------------------------------- multi-RHS forward
@@ -1308,6 +1322,12 @@ void launch_extract(hipStream_t s, const BatchDesc& d, const T* K, T* slots, T* 
     hipLaunchKernelGGL(k_extract<T>, dim3(d.nsub), dim3(kWG), 0, s, d, K, slots, F, Svv, Srr);
 }
 template <typename T>
+void launch_clear_lower(hipStream_t s, const BatchDesc& d, int maxn, T* K) {
+    if (d.nsub <= 0 || maxn <= 0) return;
+    hipLaunchKernelGGL(k_clear_lower<T>, dim3((unsigned)((maxn + CL_COLS - 1) / CL_COLS), (unsigned)d.nsub),
+                       dim3(kWG), 0, s, d, K);
+}
+template <typename T>
 void launch_copy_out(hipStream_t s, const BatchDesc& d, int nb, const T* K, T* LII, const int64_t* LIIoff, T* Lrr,
                      const int64_t* Lrroff) {
     hipLaunchKernelGGL(k_copy_out<T>, dim3(nb), dim3(kWG), 0, s, d, K, LII, LIIoff, Lrr, Lrroff);
@@ -1377,6 +1397,7 @@ int deluxe_max_object() { return DLX_MAXN; }
     template void launch_syrk_update<T>(hipStream_t, int, T*, const int64_t*, const int*, const int*,    \
                                         const int*, bool, int, int, int);                                \
     template void launch_extract<T>(hipStream_t, const BatchDesc&, const T*, T*, T*, double*, T*);      \
+    template void launch_clear_lower<T>(hipStream_t, const BatchDesc&, int, T*);                       \
     template void launch_copy_out<T>(hipStream_t, const BatchDesc&, int, const T*, T*, const int64_t*, T*,    \
                                      const int64_t*);                                                    \
     template void launch_trsm_fwd<T>(hipStream_t, int, const T*, const int64_t*, const int*, const int*, \

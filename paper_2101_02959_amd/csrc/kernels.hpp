@@ -87,6 +87,9 @@ int syrk_variant_kc(int v);   // inner chunk of variant v
 template <typename T>
 void launch_extract(hipStream_t s, const BatchDesc& d, const T* K, T* slots, T* F, double* Svv,
                     T* Srr);
+// Zero the lower triangles of the chunk's local matrices (maxn bounds n).
+template <typename T>
+void launch_clear_lower(hipStream_t s, const BatchDesc& d, int maxn, T* K);
 template <typename T>
 void launch_copy_out(hipStream_t s, const BatchDesc& d, int nb, const T* K, T* LII, const int64_t* LIIoff, T* Lrr,
                      const int64_t* Lrroff);

@@ -183,6 +183,7 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
         maxbox_ = std::max(maxbox_, (sb.Lx() + 1) * (sb.Ly() + 1) * (sb.Lz() + 1));
         maxG_ = std::max(maxG_, sb.n() - sb.nI);
         maxnI_ = std::max(maxnI_, sb.nI);
+        maxn_ = std::max(maxn_, sb.n());
         maxnr_ = std::max(maxnr_, sb.nr);
         lmap_off[q] = (int64_t)lmap.size();
         lmap.insert(lmap.end(), sb.lmap.begin(), sb.lmap.end());
@@ -777,7 +778,7 @@ int Context::linearize_t() {
         BatchDesc cd = bd_;
         cd.nsub = cnt;
         cd.sub0 = s0;
-        HIPOK(hipMemsetAsync(K, 0, nKwork_ * sizeof(T), stream_));
+        launch_clear_lower<T>(stream_, cd, maxn_, K);
         launch_assemble<T>(stream_, cd, maxbox_, fp, ke_, vlin_, wlin_, K);
         // interior elimination: L_II, and S_Gamma in the trailing block
         // interior elimination: L_II, L_GI and S_Gamma in the trailing block (Sec. 4.1)
@@ -1208,7 +1209,7 @@ int Context::profile_t(int kernel, int reps, double* avg_ms, double* work) {
             HIPOK(hipEventElapsedTime(&ms, e0, e1));
             total += ms;
         } else {
-            HIPOK(hipMemsetAsync(K_, 0, nKwork_ * sizeof(T), stream_));
+            launch_clear_lower<T>(stream_, cd, maxn_, (T*)K_);
             launch_assemble<T>(stream_, cd, maxbox_, fp, ke_, vlin_, wlin_, (T*)K_);
             double tm[4] = {0.0, 0.0, 0.0, 0.0};
             int rc = eliminate<T>((T*)K_, s0, cnt, plan_int_, tm);

@@ -17,6 +17,18 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
+
+@pytest.fixture(autouse=True, scope="module")
+def _shared_tuning(tmp_path_factory):
+    """The contexts compared here share one tune cache: in FP32 the rank-k
+    variants round differently, and a timing-based choice on a small mesh
+    may differ between two contexts."""
+    mp = pytest.MonkeyPatch()
+    mp.setenv("BDM_TUNE_CACHE", str(tmp_path_factory.mktemp("tune") / "tune.json"))
+    yield
+    mp.undo()
+
+
 CASES = {
     "bddc_fp64_ragged": (Mesh(11, 9, 10, 0.01, (0, 3, 7, 11), (0, 5, 9), (0, 4, 10)), 0, 0),
     "bddc_mixed_uneven442": (Mesh(20, 18, 12, 0.01, (0, 4, 9, 13, 20), (0, 5, 9, 14, 18), (0, 5, 12)), 1, 0),
