@@ -898,16 +898,26 @@ __global__ __launch_bounds__(kWG) void k_trsv_fwd(const T* __restrict__ Lb, cons
     const int n = nv[s];
     const int64_t ld = ldv[s];
     const int tid = threadIdx.x, lane = tid & 63;
+    // wave 0 holds the diagonal block of the current step in drow.  FP32:
+    // loaded during the previous step's update so that its latency is hidden
+    // (at no cost in occupancy); FP64: loaded at the step itself, which keeps
+    // the register count down.
+    constexpr bool early = sizeof(T) == 4;
+    T drow[NB], rdiag = (T)1;
+    auto load_diag = [&](int j0) {
+        const int jb = min(NB, n - j0), i = min(lane, jb - 1);
+#pragma unroll
+        for (int c = 0; c < NB; ++c) drow[c] = L[(j0 + i) + (j0 + min(c, jb - 1)) * ld];
+        rdiag = L[(j0 + i) + (j0 + i) * ld];
+    };
+    if (early && tid < 64) load_diag(0);
     for (int i = tid; i < n; i += kWG) xl[i] = x[i];
     __syncthreads();
     for (int j0 = 0; j0 < n; j0 += NB) {
         const int jb = min(NB, n - j0);
         if (tid < 64) {
-            const int i = min(lane, jb - 1);
-            T drow[NB];
-#pragma unroll
-            for (int c = 0; c < NB; ++c) drow[c] = L[(j0 + i) + (j0 + min(c, jb - 1)) * ld];
-            const T rinv = (lane < jb) ? (T)1 / L[(j0 + i) + (j0 + i) * ld] : (T)0;
+            if (!early) load_diag(j0);
+            const T rinv = (lane < jb) ? (T)1 / rdiag : (T)0;
             T xv = (lane < jb) ? xl[j0 + lane] : (T)0;
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
@@ -920,6 +930,7 @@ __global__ __launch_bounds__(kWG) void k_trsv_fwd(const T* __restrict__ Lb, cons
             if (lane < jb) xl[j0 + lane] = xv;
         }
         __syncthreads();
+        if (early && tid < 64 && j0 + NB < n) load_diag(j0 + NB);
         for (int r = j0 + jb + tid; r < n; r += kWG) {
             // branch-free, fully unrolled so all column loads are in flight together
             T lv[NB];
