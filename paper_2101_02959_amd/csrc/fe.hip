@@ -126,6 +126,8 @@ enum { ST_JAC = 0, ST_RES_MINUS_JAC = 1, ST_RESIDUAL = 2 };
 // (xv + xe) and xe, with a one-node halo, live in a rotating LDS buffer, so
 // each input value is fetched from memory about once; the coefficient tables
 // of level k (9 boundary classes x 2 media) are staged too.
+constexpr int ST_XCD = 8;
+
 template <int MODE, int SX, int SY, int SZ>
 __global__ __launch_bounds__(SX * SY) void k_stencil(FEParams p, const double* __restrict__ st,
                                                      const double* __restrict__ dg, const double* __restrict__ xv,
@@ -138,16 +140,30 @@ __global__ __launch_bounds__(SX * SY) void k_stencil(FEParams p, const double* _
     __shared__ double tab[TABN];
     __shared__ double ps[3][PY][PX];
     __shared__ double pe[3][PY][PX];
+    // Tile of this workgroup: the launch is one-dimensional and consecutive
+    // ids go round robin to the 8 XCDs, so XCD x takes the contiguous run of
+    // tiles [x * per, (x + 1) * per) in x-fastest order; tiles that share halo
+    // rows then share that XCD's L2 and are processed close together.
+    const int gx = (p.nx1 + SX - 1) / SX, gy = (p.ny1 + SY - 1) / SY, gz = (p.nz + 1 + SZ - 1) / SZ;
+    const int ntile = gx * gy * gz, per = (ntile + ST_XCD - 1) / ST_XCD;
+    const int tile = ((int)blockIdx.x % ST_XCD) * per + (int)blockIdx.x / ST_XCD;
+    if (tile >= ntile) return;
+    const int bxi = tile % gx, byi = (tile / gx) % gy, bzi = tile / (gx * gy);
     const int tid = threadIdx.x + SX * threadIdx.y;
-    const int i0 = blockIdx.x * SX, j0 = blockIdx.y * SY;
+    const int i0 = bxi * SX, j0 = byi * SY;
     const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
-    const int kbeg = blockIdx.z * SZ;
+    const int kbeg = bzi * SZ;
     const int kend = min(kbeg + SZ, p.nz + 1);
     const bool act = (i <= p.nx) && (j <= p.ny);
     const int xc = (i == 0) ? 0 : (i == p.nx ? 2 : 1);
     const int yc = (j == 0) ? 0 : (j == p.ny ? 2 : 1);
     const int cls = xc + 3 * yc;
     const int64_t plane = (int64_t)p.nx1 * p.ny1;
+    // A block whose nodes all lie off the x and y boundaries has one
+    // boundary class (the interior one): its coefficients are read at a
+    // wave-uniform address (scalar loads) instead of being staged in LDS and
+    // read per lane, which halves the LDS reads per node.
+    const bool inner = i0 >= 1 && i0 + SX <= p.nx && j0 >= 1 && j0 + SY <= p.ny;
     // Planes are fetched into registers one iteration ahead and stored into a
     // three-plane LDS ring (with the level's coefficient table) after the
     // compute of the previous plane.  The loads are branch free (clamped
@@ -192,32 +208,40 @@ __global__ __launch_bounds__(SX * SY) void k_stencil(FEParams p, const double* _
     fetch(kbeg);
     store(kbeg);
     fetch(kbeg + 1);
-    fetch_tab(kbeg);
+    if (!inner) fetch_tab(kbeg);
     for (int k = kbeg; k < kend; ++k) {
         store(k + 1);
+        if (!inner) {
 #pragma unroll
-        for (int q = 0; q < NTB; ++q)
-            if (tid + q * NT < TABN) tab[tid + q * NT] = rt[q];
+            for (int q = 0; q < NTB; ++q)
+                if (tid + q * NT < TABN) tab[tid + q * NT] = rt[q];
+        }
         if (k + 1 < kend) {
             fetch(k + 2);
-            fetch_tab(k + 1);
+            if (!inner) fetch_tab(k + 1);
         }
         __syncthreads();
         if (act) {
-            const double* ti = tab + cls * 54;
-            const double* te = ti + 27;
             double ai = 0.0, ae = 0.0;
+            auto sum27 = [&](const double* ti, const double* te) {
 #pragma unroll
-            for (int dz = 0; dz < 3; ++dz) {
-                const int sl = (k + dz + 2) % 3;
+                for (int dz = 0; dz < 3; ++dz) {
+                    const int sl = (k + dz + 2) % 3;
 #pragma unroll
-                for (int dy = 0; dy < 3; ++dy)
+                    for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-                    for (int dx = 0; dx < 3; ++dx) {
-                        const int d = dx + 3 * dy + 9 * dz;
-                        ai = fma(ti[d], ps[sl][threadIdx.y + dy][threadIdx.x + dx], ai);
-                        ae = fma(te[d], pe[sl][threadIdx.y + dy][threadIdx.x + dx], ae);
-                    }
+                        for (int dx = 0; dx < 3; ++dx) {
+                            const int d = dx + 3 * dy + 9 * dz;
+                            ai = fma(ti[d], ps[sl][threadIdx.y + dy][threadIdx.x + dx], ai);
+                            ae = fma(te[d], pe[sl][threadIdx.y + dy][threadIdx.x + dx], ae);
+                        }
+                }
+            };
+            if (inner) {
+                const double* tg = st + (int64_t)k * TABN + 4 * 54;   // class 4: interior in x and y
+                sum27(tg, tg + 27);
+            } else {
+                sum27(tab + cls * 54, tab + cls * 54 + 27);
             }
             const int64_t n = i + (int64_t)p.nx1 * j + plane * k;
             if (MODE == ST_RESIDUAL) {
@@ -267,9 +291,9 @@ constexpr int ST_SHAPE[ST_NVAR][3] = {{32, 8, 8}, {32, 8, 16}, {64, 4, 8}, {32, 
 
 template <int MODE, int SX, int SY, int SZ, typename... Args>
 void launch_stencil_shape(hipStream_t s, const FEParams& p, Args... args) {
-    const dim3 grid((unsigned)((p.nx1 + SX - 1) / SX), (unsigned)((p.ny1 + SY - 1) / SY),
-                    (unsigned)((p.nz + 1 + SZ - 1) / SZ));
-    hipLaunchKernelGGL((k_stencil<MODE, SX, SY, SZ>), grid, dim3(SX, SY), 0, s, p, args...);
+    const int ntile = ((p.nx1 + SX - 1) / SX) * ((p.ny1 + SY - 1) / SY) * ((p.nz + 1 + SZ - 1) / SZ);
+    const int per = (ntile + ST_XCD - 1) / ST_XCD;
+    hipLaunchKernelGGL((k_stencil<MODE, SX, SY, SZ>), dim3((unsigned)(per * ST_XCD)), dim3(SX, SY), 0, s, p, args...);
 }
 
 template <int MODE, typename... Args>
