@@ -265,6 +265,315 @@ __global__ __launch_bounds__(SX * SY) void k_stencil(FEParams p, const double* _
     }
 }
 
+// The same stencil pass without LDS or barriers.  A wave spans 64
+// consecutive x columns, of which the inner 62 produce output (the two edge
+// lanes only carry the halo), and each thread owns RY consecutive rows in y.
+// The thread marches up z over SZ levels: per plane it loads its RY + 2 rows
+// of (v, u_e) (coalesced along x), takes the x neighbours from the adjacent
+// lanes over DPP wave shifts, and adds the plane to three running sums per
+// row: the node below (its dz = +1 coefficients), the node itself (dz = 0)
+// and the node above (dz = -1); node m - 1 is complete once plane m is in.
+// Each sum takes the 27 products in the order of k_stencil, and planes
+// outside the mesh add nothing there (their values are zero), so the two
+// kernels agree bitwise.
+//
+// The launch has two parts.  Boundary tiles (first, so their short
+// latency-bound columns start early) give one thread to each node column on
+// the x or y faces, ZB levels deep, and read the coefficients of its class
+// per lane.  Interior tiles cover the x-y interior 1..nx-1 x 1..ny-1, where
+// every neighbour is inside the mesh and all nodes share one boundary class,
+// so their coefficients are read at wave-uniform addresses (scalar loads).
+template <int MODE>
+__device__ __forceinline__ void stencil_out(const FEParams& p, int i, int j, int k, int64_t n, double ai, double ae,
+                                            const double* __restrict__ dg, const double* __restrict__ xv,
+                                            const double* __restrict__ rv, const double* __restrict__ re,
+                                            const double* __restrict__ vn, const double* __restrict__ w,
+                                            const double* __restrict__ Is, double stim, double* __restrict__ yv,
+                                            double* __restrict__ ye) {
+    if (MODE == ST_RESIDUAL) {
+        const double vv = xv[n];
+        const double mm = lumped_mass(p, i, j, k);
+        const double is = (stim != 0.0 && Is) ? Is[n] : 0.0;
+        yv[n] = mm * (p.c * (vv - vn[n]) + p.tau * (rmc_iion(p, vv, w[n]) - is)) + ai;
+        ye[n] = ai + ae;
+    } else {
+        const double a = dg[n] * xv[n] + ai, b = ai + ae;
+        if (MODE == ST_JAC) {
+            yv[n] = a;
+            ye[n] = b;
+        } else {
+            yv[n] = rv[n] - a;
+            ye[n] = re[n] - b;
+        }
+    }
+}
+
+// Per-node operands of the stencil output besides the sums, loaded one plane
+// ahead in the register march: JAC the diagonal; RES_MINUS_JAC the diagonal
+// and both right-hand sides; RESIDUAL the previous potential, the gating
+// variable and the stimulus.  out_store computes what stencil_out does.
+struct OutOps {
+    double a = 0.0, b = 0.0, c = 0.0;
+};
+
+template <int MODE>
+__device__ __forceinline__ void out_load(OutOps& o, int64_t n, const double* __restrict__ dg,
+                                         const double* __restrict__ rv, const double* __restrict__ re,
+                                         const double* __restrict__ vn, const double* __restrict__ w,
+                                         const double* __restrict__ Is, double stim) {
+    if (MODE == ST_RESIDUAL) {
+        o.a = vn[n];
+        o.b = w[n];
+        o.c = (stim != 0.0 && Is) ? Is[n] : 0.0;
+    } else {
+        o.a = dg[n];
+        if (MODE == ST_RES_MINUS_JAC) {
+            o.b = rv[n];
+            o.c = re[n];
+        }
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void out_store(const FEParams& p, int i, int j, int k, int64_t n, double xvn,
+                                          const OutOps& o, double ai, double ae, double* __restrict__ yv,
+                                          double* __restrict__ ye) {
+    if (MODE == ST_RESIDUAL) {
+        const double mm = lumped_mass(p, i, j, k);
+        yv[n] = mm * (p.c * (xvn - o.a) + p.tau * (rmc_iion(p, xvn, o.b) - o.c)) + ai;
+        ye[n] = ai + ae;
+    } else {
+        const double a = o.a * xvn + ai, b = ai + ae;
+        if (MODE == ST_JAC) {
+            yv[n] = a;
+            ye[n] = b;
+        } else {
+            yv[n] = o.b - a;
+            ye[n] = o.c - b;
+        }
+    }
+}
+
+// DPP wave shifts of a double: dpp_lo(x) holds lane l - 1's x, dpp_hi(x)
+// lane l + 1's (lanes without a source get 0).
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double x) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double dpp_lo(double x) { return dpp64<0x138>(x); }   // wave_shr:1
+__device__ __forceinline__ double dpp_hi(double x) { return dpp64<0x130>(x); }   // wave_shl:1
+
+constexpr int ZM_OUT = 62;   // output columns per wave
+constexpr int ZM_ZB = 4;     // levels per boundary thread
+
+struct ZmGrid {
+    int gx, gy, gz, nbnd, nbt, gzb, nboundary, ntile, per;
+};
+
+template <int RY, int W, int SZ>
+__host__ __device__ inline ZmGrid zm_grid(const FEParams& p) {
+    ZmGrid g;
+    g.gx = (p.nx - 1 + ZM_OUT - 1) / ZM_OUT;   // interior columns 1..nx-1
+    g.gy = (p.ny - 1 + RY * W - 1) / (RY * W);
+    g.gz = (p.nz + 1 + SZ - 1) / SZ;
+    g.nbnd = 2 * (p.ny + 1) + 2 * (p.nx - 1);   // node columns on the x and y faces
+    g.nbt = (g.nbnd + 64 * W - 1) / (64 * W);
+    g.gzb = (p.nz + 1 + ZM_ZB - 1) / ZM_ZB;
+    g.nboundary = g.nbt * g.gzb;
+    g.ntile = g.nboundary + g.gx * g.gy * g.gz;
+    g.per = (g.ntile + ST_XCD - 1) / ST_XCD;
+    return g;
+}
+
+template <int MODE, int RY, int W, int SZ>
+__global__ __launch_bounds__(64 * W) void k_stencil_zm(FEParams p, const double* __restrict__ st,
+                                                       const double* __restrict__ dg, const double* __restrict__ xv,
+                                                       const double* __restrict__ xe, const double* __restrict__ rv,
+                                                       const double* __restrict__ re, const double* __restrict__ vn,
+                                                       const double* __restrict__ w, const double* __restrict__ Is,
+                                                       double stim, double* __restrict__ yv,
+                                                       double* __restrict__ ye) {
+    constexpr int TABN = 9 * 2 * 27;
+    const ZmGrid g = zm_grid<RY, W, SZ>(p);
+    // consecutive ids go round robin to the 8 XCDs; XCD x takes the run of
+    // tiles [x * per, (x + 1) * per) so neighbouring tiles share its L2
+    const int tile = ((int)blockIdx.x % ST_XCD) * g.per + (int)blockIdx.x / ST_XCD;
+    if (tile >= g.ntile) return;
+    const int64_t plane = (int64_t)p.nx1 * p.ny1;
+    if (tile < g.nboundary) {
+        const int b = (tile % g.nbt) * (64 * W) + (int)(threadIdx.x + 64 * threadIdx.y);
+        const int bzi = tile / g.nbt;
+        const bool act = b < g.nbnd;
+        const int bb = act ? b : 0;
+        int i, j;
+        if (bb < p.ny + 1) {
+            i = 0; j = bb;
+        } else if (bb < 2 * (p.ny + 1)) {
+            i = p.nx; j = bb - (p.ny + 1);
+        } else if (bb < 2 * (p.ny + 1) + (p.nx - 1)) {
+            j = 0; i = 1 + bb - 2 * (p.ny + 1);
+        } else {
+            j = p.ny; i = 1 + bb - 2 * (p.ny + 1) - (p.nx - 1);
+        }
+        const int xc = (i == 0) ? 0 : (i == p.nx ? 2 : 1);
+        const int yc = (j == 0) ? 0 : (j == p.ny ? 2 : 1);
+        const int c54 = (xc + 3 * yc) * 54;
+        const int kbeg = bzi * ZM_ZB, kend = min(kbeg + ZM_ZB, p.nz + 1);
+        double aAi = 0.0, aAe = 0.0, aBi = 0.0, aBe = 0.0, aCi = 0.0, aCe = 0.0;   // nodes m - 1, m, m + 1
+        for (int m = max(kbeg - 1, 0); m <= min(kend, p.nz); ++m) {
+            const double* tC = st + (int64_t)min(m + 1, p.nz) * TABN + c54;
+            const double* tB = st + (int64_t)m * TABN + c54 + 9;
+            const double* tA = st + (int64_t)max(m - 1, 0) * TABN + c54 + 18;
+#pragma unroll 1
+            for (int dy = 0; dy < 3; ++dy) {
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    const int d = dx + 3 * dy;
+                    const int gi = i - 1 + dx, gj = j - 1 + dy;
+                    const bool ok = gi >= 0 && gi <= p.nx && gj >= 0 && gj <= p.ny;
+                    const int64_t n = ok ? gi + (int64_t)p.nx1 * gj + plane * m : 0;
+                    const double e0 = xe[n], v0 = xv[n];
+                    const double e = ok ? e0 : 0.0, v = ok ? v0 + e0 : 0.0;
+                    aCi = fma(tC[d], v, aCi);
+                    aCe = fma(tC[27 + d], e, aCe);
+                    aBi = fma(tB[d], v, aBi);
+                    aBe = fma(tB[27 + d], e, aBe);
+                    aAi = fma(tA[d], v, aAi);
+                    aAe = fma(tA[27 + d], e, aAe);
+                }
+            }
+            const int k = m - 1;
+            if (act && k >= kbeg && k < kend)
+                stencil_out<MODE>(p, i, j, k, i + (int64_t)p.nx1 * j + plane * k, aAi, aAe, dg, xv, rv, re, vn, w,
+                                  Is, stim, yv, ye);
+            aAi = aBi; aAe = aBe;
+            aBi = aCi; aBe = aCe;
+            aCi = 0.0; aCe = 0.0;
+        }
+        // the top node of the mesh has no plane above it
+        if (act && kend == p.nz + 1)
+            stencil_out<MODE>(p, i, j, p.nz, i + (int64_t)p.nx1 * j + plane * p.nz, aAi, aAe, dg, xv, rv, re, vn, w,
+                              Is, stim, yv, ye);
+        return;
+    }
+    const int t = tile - g.nboundary;
+    const int bxi = t % g.gx, byi = (t / g.gx) % g.gy, bzi = t / (g.gx * g.gy);
+    const int lane = (int)threadIdx.x;
+    const int i = bxi * ZM_OUT + lane;   // lane 0 is the column left of the first output
+    const bool xout = lane >= 1 && lane <= ZM_OUT && i <= p.nx - 1;
+    const int ic = min(i, p.nx);
+    const int jb = 1 + RY * ((int)threadIdx.y + W * byi);   // first output row (wave-uniform)
+    const int kbeg = bzi * SZ, kend = min(kbeg + SZ, p.nz + 1);
+    double aAi[RY], aAe[RY], aBi[RY], aBe[RY], aCi[RY], aCe[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) aAi[r] = aAe[r] = aBi[r] = aBe[r] = aCi[r] = aCe[r] = 0.0;
+    // rows jb - 1 .. jb + RY of a plane (rows past ny only feed unused sums);
+    // the next plane is fetched while the current one is summed
+    const int m0 = max(kbeg - 1, 0), m1 = min(kend, p.nz);
+    int64_t roff[RY + 2];
+#pragma unroll
+    for (int q = 0; q < RY + 2; ++q) roff[q] = ic + (int64_t)p.nx1 * min(jb - 1 + q, p.ny);
+    double nv_[RY + 2], ne_[RY + 2];
+    auto fetch = [&](int m) {
+#pragma unroll
+        for (int q = 0; q < RY + 2; ++q) {
+            nv_[q] = xv[roff[q] + plane * m];
+            ne_[q] = xe[roff[q] + plane * m];
+        }
+    };
+    // output operands of node m are fetched with plane m + 1; the potential
+    // at the output node is the centre row value of the previous plane
+    OutOps onx[RY], ocur[RY];
+    double xprev[RY];
+    auto fetch_out = [&](int m) {
+#pragma unroll
+        for (int r = 0; r < RY; ++r)
+            out_load<MODE>(onx[r], roff[r + 1] + plane * m, dg, rv, re, vn, w, Is, stim);
+    };
+#pragma unroll
+    for (int r = 0; r < RY; ++r) xprev[r] = 0.0;
+    fetch(m0);
+    for (int m = m0; m <= m1; ++m) {
+        const double* tC = st + (int64_t)min(m + 1, p.nz) * TABN + 4 * 54;
+        const double* tB = st + (int64_t)m * TABN + 4 * 54 + 9;
+        const double* tA = st + (int64_t)max(m - 1, 0) * TABN + 4 * 54 + 18;
+        double rv_[RY + 2], re_[RY + 2], xcen[RY];
+#pragma unroll
+        for (int q = 0; q < RY + 2; ++q) {
+            re_[q] = ne_[q];
+            rv_[q] = nv_[q] + ne_[q];   // v + u_e for the intracellular operator
+        }
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            xcen[r] = nv_[r + 1];
+            ocur[r] = onx[r];
+        }
+        fetch_out(m);
+        fetch(min(m + 1, m1));
+        double vx[RY + 2][3], ex[RY + 2][3];
+#pragma unroll
+        for (int q = 0; q < RY + 2; ++q) {
+            vx[q][0] = dpp_lo(rv_[q]); vx[q][1] = rv_[q]; vx[q][2] = dpp_hi(rv_[q]);
+            ex[q][0] = dpp_lo(re_[q]); ex[q][1] = re_[q]; ex[q][2] = dpp_hi(re_[q]);
+        }
+        // One target level at a time, so only its 18 coefficients are live:
+        // the empty asm statements route the table pointer and the finished
+        // sums through the (ordered) volatile statements, so the scalar loads
+        // of one target cannot be hoisted above the previous target's
+        // products and the products cannot sink into the store branch.
+        // Without them all 54 coefficients are loaded at the top of the
+        // plane, more than the scalar register file holds.
+        // The table is read-only during the kernel, so it is read through
+        // the constant address space, which keeps the loads scalar.
+        auto add = [&](const double* tb, double (&si)[RY], double (&se)[RY]) {
+            asm volatile("" : "+s"(tb));
+            const __attribute__((address_space(4))) double* tk =
+                (const __attribute__((address_space(4))) double*)tb;
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    const int d = dx + 3 * dy;
+                    const double ci = tk[d], ce = tk[27 + d];
+#pragma unroll
+                    for (int r = 0; r < RY; ++r) {
+                        si[r] = fma(ci, vx[r + dy][dx], si[r]);
+                        se[r] = fma(ce, ex[r + dy][dx], se[r]);
+                    }
+                }
+#pragma unroll
+            for (int r = 0; r < RY; ++r) asm volatile("" : "+v"(si[r]), "+v"(se[r]));
+        };
+        add(tC, aCi, aCe);
+        add(tB, aBi, aBe);
+        add(tA, aAi, aAe);
+        const int k = m - 1;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const int j = jb + r;
+            if (xout && j <= p.ny - 1 && k >= kbeg && k < kend)
+                out_store<MODE>(p, i, j, k, i + (int64_t)p.nx1 * j + plane * k, xprev[r], ocur[r], aAi[r], aAe[r],
+                                yv, ye);
+            xprev[r] = xcen[r];
+            aAi[r] = aBi[r]; aAe[r] = aBe[r];
+            aBi[r] = aCi[r]; aBe[r] = aCe[r];
+            aCi[r] = 0.0; aCe[r] = 0.0;
+        }
+    }
+    if (kend == p.nz + 1) {
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const int j = jb + r;
+            if (xout && j <= p.ny - 1)
+                out_store<MODE>(p, i, j, p.nz, i + (int64_t)p.nx1 * j + plane * p.nz, xprev[r], onx[r], aAi[r],
+                                aAe[r], yv, ye);
+        }
+    }
+}
+
 __global__ void k_ionic_update(int64_t N, double tau, double eta2, double vp,
                                const double* __restrict__ v, double* __restrict__ w) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -286,14 +595,24 @@ __global__ void k_reaction_diag(FEParams p, const double* __restrict__ v, const 
 }
 
 // tile variants (SX, SY, SZ)
-constexpr int ST_NVAR = 5;
-constexpr int ST_SHAPE[ST_NVAR][3] = {{32, 8, 8}, {32, 8, 16}, {64, 4, 8}, {32, 4, 16}, {16, 16, 8}};
+// Variants: 0-6 the LDS kernel with tiles (SX, SY, SZ) = (32, 8, 8),
+// (32, 8, 16), (64, 4, 8), (32, 4, 16), (16, 16, 8), (32, 8, 4), (16, 16, 4);
+// 7-10 the register march with (RY, W, SZ) = (1, 4, 8), (2, 4, 8),
+// (2, 4, 16), (4, 4, 8).
+constexpr int ST_NVAR = 11;
 
 template <int MODE, int SX, int SY, int SZ, typename... Args>
 void launch_stencil_shape(hipStream_t s, const FEParams& p, Args... args) {
     const int ntile = ((p.nx1 + SX - 1) / SX) * ((p.ny1 + SY - 1) / SY) * ((p.nz + 1 + SZ - 1) / SZ);
     const int per = (ntile + ST_XCD - 1) / ST_XCD;
     hipLaunchKernelGGL((k_stencil<MODE, SX, SY, SZ>), dim3((unsigned)(per * ST_XCD)), dim3(SX, SY), 0, s, p, args...);
+}
+
+template <int MODE, int RY, int W, int SZ, typename... Args>
+void launch_stencil_zm(hipStream_t s, const FEParams& p, Args... args) {
+    const ZmGrid g = zm_grid<RY, W, SZ>(p);
+    hipLaunchKernelGGL((k_stencil_zm<MODE, RY, W, SZ>), dim3((unsigned)(g.per * ST_XCD)), dim3(64, W), 0, s, p,
+                       args...);
 }
 
 template <int MODE, typename... Args>
@@ -303,6 +622,12 @@ void launch_stencil(hipStream_t s, const FEParams& p, Args... args) {
         case 2: launch_stencil_shape<MODE, 64, 4, 8>(s, p, args...); break;
         case 3: launch_stencil_shape<MODE, 32, 4, 16>(s, p, args...); break;
         case 4: launch_stencil_shape<MODE, 16, 16, 8>(s, p, args...); break;
+        case 5: launch_stencil_shape<MODE, 32, 8, 4>(s, p, args...); break;
+        case 6: launch_stencil_shape<MODE, 16, 16, 4>(s, p, args...); break;
+        case 7: launch_stencil_zm<MODE, 1, 4, 8>(s, p, args...); break;
+        case 8: launch_stencil_zm<MODE, 2, 4, 8>(s, p, args...); break;
+        case 9: launch_stencil_zm<MODE, 2, 4, 16>(s, p, args...); break;
+        case 10: launch_stencil_zm<MODE, 4, 4, 8>(s, p, args...); break;
         default: launch_stencil_shape<MODE, 32, 8, 8>(s, p, args...);
     }
 }
@@ -341,10 +666,5 @@ void launch_res_minus_jac(hipStream_t s, const FEParams& p, const double* st, co
 }
 
 int stencil_variants() { return ST_NVAR; }
-void stencil_variant_shape(int v, int* sx, int* sy, int* sz) {
-    *sx = ST_SHAPE[v][0];
-    *sy = ST_SHAPE[v][1];
-    *sz = ST_SHAPE[v][2];
-}
 
 }  // namespace bdm

@@ -23,10 +23,10 @@ void launch_jac_apply(hipStream_t s, const FEParams& p, const double* st, const 
                       const double* x, double* y);
 void launch_res_minus_jac(hipStream_t s, const FEParams& p, const double* st, const double* dg,
                           const double* x, const double* r, double* y);
-// Tile shapes of the stencil kernel (FEParams::stencil_variant); the
+// Variants of the stencil pass (FEParams::stencil_variant: LDS tile shapes
+// and register z-march shapes, all with the same summation order); the
 // autotuner picks one per mesh.
 int stencil_variants();
-void stencil_variant_shape(int v, int* sx, int* sy, int* sz);
 
 // ---- dense.hip: batched dense linear algebra, one workgroup per matrix.
 // Per-subdomain layout descriptor (device arrays, length nsub).

@@ -5,8 +5,9 @@ without timing).
 The variants are forced through the cache file: each entry names the device,
 family and size class that a context reports, and the choice.  In FP64 the
 rank-k variants differ only in tiling (every entry accumulates its inner
-products in the same order), and the stencil variants only in the block
-shape, so all of them must agree bitwise; in FP32 the inner chunk length
+products in the same order), and the stencil variants (LDS tiles of several
+shapes, and the register z-march) take each node's 27 products in the same
+order, so all of them must agree bitwise; in FP32 the inner chunk length
 changes the two-level accumulation, so those are held to the FP32 bar.
 """
 import json
@@ -25,7 +26,7 @@ MESHES = {
     "ragged": Mesh(11, 9, 10, 0.01, (0, 3, 7, 11), (0, 5, 9), (0, 4, 10)),
     "uneven442": Mesh(20, 18, 12, 0.01, (0, 4, 9, 13, 20), (0, 5, 9, 14, 18), (0, 5, 12)),
 }
-NSTENCIL, NSYRK = 5, 4
+NSTENCIL, NSYRK = 11, 4
 
 
 def _rel(a, b):
@@ -99,7 +100,8 @@ def test_every_variant_matches_oracle(mname, prec, tol, tmp_path, monkeypatch):
     S.bdm_linearize(v, w)
     classes = [(e["device"], e["family"], e["class"]) for e in S.bdm_tune_report()["entries"]]
     S.close()
-    combos = [(sv, yv) for yv in range(NSYRK) for sv in (yv,)] + [(4, 0)]
+    # every stencil shape and every rank-k variant at least once
+    combos = [(v, v) for v in range(NSYRK)] + [(sv, sv % NSYRK) for sv in range(NSYRK, NSTENCIL)]
     first = None
     for sv, yv in combos:
         forced = tmp_path / f"forced_{sv}_{yv}.json"
