@@ -266,11 +266,12 @@ __global__ __launch_bounds__(SX * SY) void k_stencil(FEParams p, const double* _
 }
 
 // The same stencil pass without LDS or barriers.  A wave spans 64
-// consecutive x columns, of which the inner 62 produce output (the two edge
-// lanes only carry the halo), and each thread owns RY consecutive rows in y.
-// The thread marches up z over SZ levels: per plane it loads its RY + 2 rows
-// of (v, u_e) (coalesced along x), takes the x neighbours from the adjacent
-// lanes over DPP wave shifts, and adds the plane to three running sums per
+// consecutive x columns and each thread owns RY consecutive rows in y.  The
+// thread marches up z over SZ levels: per plane it loads its RY + 2 rows of
+// (v, u_e) (coalesced along x), takes the x neighbours from the adjacent
+// lanes over DPP wave shifts (the two columns beyond the wave come from one
+// extra load per row, at one address for lanes 0-62 and another for lane
+// 63), and adds the plane to three running sums per
 // row: the node below (its dz = +1 coefficients), the node itself (dz = 0)
 // and the node above (dz = -1); node m - 1 is complete once plane m is in.
 // Each sum takes the 27 products in the order of k_stencil, and planes
@@ -366,8 +367,8 @@ __device__ __forceinline__ double dpp64(double x) {
 __device__ __forceinline__ double dpp_lo(double x) { return dpp64<0x138>(x); }   // wave_shr:1
 __device__ __forceinline__ double dpp_hi(double x) { return dpp64<0x130>(x); }   // wave_shl:1
 
-constexpr int ZM_OUT = 62;   // output columns per wave
-constexpr int ZM_ZB = 4;     // levels per boundary thread
+constexpr int ZM_OUT = 64;   // output columns per wave
+constexpr int ZM_ZB = 2;     // levels per boundary thread
 
 struct ZmGrid {
     int gx, gy, gz, nbnd, nbt, gzb, nboundary, ntile, per;
@@ -388,7 +389,7 @@ __host__ __device__ inline ZmGrid zm_grid(const FEParams& p) {
     return g;
 }
 
-template <int MODE, int RY, int W, int SZ>
+template <int MODE, int RY, int W, int SZ, int PF>
 __global__ __launch_bounds__(64 * W) void k_stencil_zm(FEParams p, const double* __restrict__ st,
                                                        const double* __restrict__ dg, const double* __restrict__ xv,
                                                        const double* __restrict__ xe, const double* __restrict__ rv,
@@ -462,26 +463,36 @@ __global__ __launch_bounds__(64 * W) void k_stencil_zm(FEParams p, const double*
     const int t = tile - g.nboundary;
     const int bxi = t % g.gx, byi = (t / g.gx) % g.gy, bzi = t / (g.gx * g.gy);
     const int lane = (int)threadIdx.x;
-    const int i = bxi * ZM_OUT + lane;   // lane 0 is the column left of the first output
-    const bool xout = lane >= 1 && lane <= ZM_OUT && i <= p.nx - 1;
+    const int i = 1 + bxi * ZM_OUT + lane;
+    const bool xout = i <= p.nx - 1;
     const int ic = min(i, p.nx);
+    // halo column: left of lane 0 for lanes 0-62, right of lane 63 for 63
+    const int hc = lane == 63 ? min(1 + bxi * ZM_OUT + 64, p.nx) : bxi * ZM_OUT;
     const int jb = 1 + RY * ((int)threadIdx.y + W * byi);   // first output row (wave-uniform)
     const int kbeg = bzi * SZ, kend = min(kbeg + SZ, p.nz + 1);
     double aAi[RY], aAe[RY], aBi[RY], aBe[RY], aCi[RY], aCe[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) aAi[r] = aAe[r] = aBi[r] = aBe[r] = aCi[r] = aCe[r] = 0.0;
-    // rows jb - 1 .. jb + RY of a plane (rows past ny only feed unused sums);
-    // the next plane is fetched while the current one is summed
+    // rows jb - 1 .. jb + RY of a plane (rows past ny only feed unused sums)
+    // and their halo values; planes are fetched two ahead of the one summed
     const int m0 = max(kbeg - 1, 0), m1 = min(kend, p.nz);
-    int64_t roff[RY + 2];
+    int64_t roff[RY + 2], hoff[RY + 2];
 #pragma unroll
-    for (int q = 0; q < RY + 2; ++q) roff[q] = ic + (int64_t)p.nx1 * min(jb - 1 + q, p.ny);
-    double nv_[RY + 2], ne_[RY + 2];
-    auto fetch = [&](int m) {
+    for (int q = 0; q < RY + 2; ++q) {
+        roff[q] = ic + (int64_t)p.nx1 * min(jb - 1 + q, p.ny);
+        hoff[q] = hc + (int64_t)p.nx1 * min(jb - 1 + q, p.ny);
+    }
+    struct Plane {
+        double v[RY + 2], e[RY + 2], hv[RY + 2], he[RY + 2];
+    };
+    Plane nv_, n2_;
+    auto fetch = [&](Plane& b, int m) {
 #pragma unroll
         for (int q = 0; q < RY + 2; ++q) {
-            nv_[q] = xv[roff[q] + plane * m];
-            ne_[q] = xe[roff[q] + plane * m];
+            b.v[q] = xv[roff[q] + plane * m];
+            b.e[q] = xe[roff[q] + plane * m];
+            b.hv[q] = xv[hoff[q] + plane * m];
+            b.he[q] = xe[hoff[q] + plane * m];
         }
     };
     // output operands of node m are fetched with plane m + 1; the potential
@@ -495,29 +506,35 @@ __global__ __launch_bounds__(64 * W) void k_stencil_zm(FEParams p, const double*
     };
 #pragma unroll
     for (int r = 0; r < RY; ++r) xprev[r] = 0.0;
-    fetch(m0);
+    fetch(nv_, m0);
+    if (PF == 2) fetch(n2_, min(m0 + 1, m1));
     for (int m = m0; m <= m1; ++m) {
         const double* tC = st + (int64_t)min(m + 1, p.nz) * TABN + 4 * 54;
         const double* tB = st + (int64_t)m * TABN + 4 * 54 + 9;
         const double* tA = st + (int64_t)max(m - 1, 0) * TABN + 4 * 54 + 18;
-        double rv_[RY + 2], re_[RY + 2], xcen[RY];
+        double vx[RY + 2][3], ex[RY + 2][3], xcen[RY];
 #pragma unroll
         for (int q = 0; q < RY + 2; ++q) {
-            re_[q] = ne_[q];
-            rv_[q] = nv_[q] + ne_[q];   // v + u_e for the intracellular operator
+            const double sv = nv_.v[q] + nv_.e[q], hs = nv_.hv[q] + nv_.he[q];   // v + u_e (intracellular)
+            const double lv = dpp_lo(sv), rv2 = dpp_hi(sv), le = dpp_lo(nv_.e[q]), re2 = dpp_hi(nv_.e[q]);
+            vx[q][0] = lane == 0 ? hs : lv;
+            vx[q][1] = sv;
+            vx[q][2] = lane == 63 ? hs : rv2;
+            ex[q][0] = lane == 0 ? nv_.he[q] : le;
+            ex[q][1] = nv_.e[q];
+            ex[q][2] = lane == 63 ? nv_.he[q] : re2;
         }
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            xcen[r] = nv_[r + 1];
+            xcen[r] = nv_.v[r + 1];
             ocur[r] = onx[r];
         }
         fetch_out(m);
-        fetch(min(m + 1, m1));
-        double vx[RY + 2][3], ex[RY + 2][3];
-#pragma unroll
-        for (int q = 0; q < RY + 2; ++q) {
-            vx[q][0] = dpp_lo(rv_[q]); vx[q][1] = rv_[q]; vx[q][2] = dpp_hi(rv_[q]);
-            ex[q][0] = dpp_lo(re_[q]); ex[q][1] = re_[q]; ex[q][2] = dpp_hi(re_[q]);
+        if (PF == 2) {
+            nv_ = n2_;
+            fetch(n2_, min(m + 2, m1));
+        } else {
+            fetch(nv_, min(m + 1, m1));
         }
         // One target level at a time, so only its 18 coefficients are live:
         // the empty asm statements route the table pointer and the finished
@@ -608,10 +625,10 @@ void launch_stencil_shape(hipStream_t s, const FEParams& p, Args... args) {
     hipLaunchKernelGGL((k_stencil<MODE, SX, SY, SZ>), dim3((unsigned)(per * ST_XCD)), dim3(SX, SY), 0, s, p, args...);
 }
 
-template <int MODE, int RY, int W, int SZ, typename... Args>
+template <int MODE, int RY, int W, int SZ, int PF, typename... Args>
 void launch_stencil_zm(hipStream_t s, const FEParams& p, Args... args) {
     const ZmGrid g = zm_grid<RY, W, SZ>(p);
-    hipLaunchKernelGGL((k_stencil_zm<MODE, RY, W, SZ>), dim3((unsigned)(g.per * ST_XCD)), dim3(64, W), 0, s, p,
+    hipLaunchKernelGGL((k_stencil_zm<MODE, RY, W, SZ, PF>), dim3((unsigned)(g.per * ST_XCD)), dim3(64, W), 0, s, p,
                        args...);
 }
 
@@ -624,10 +641,10 @@ void launch_stencil(hipStream_t s, const FEParams& p, Args... args) {
         case 4: launch_stencil_shape<MODE, 16, 16, 8>(s, p, args...); break;
         case 5: launch_stencil_shape<MODE, 32, 8, 4>(s, p, args...); break;
         case 6: launch_stencil_shape<MODE, 16, 16, 4>(s, p, args...); break;
-        case 7: launch_stencil_zm<MODE, 1, 4, 8>(s, p, args...); break;
-        case 8: launch_stencil_zm<MODE, 2, 4, 8>(s, p, args...); break;
-        case 9: launch_stencil_zm<MODE, 2, 4, 16>(s, p, args...); break;
-        case 10: launch_stencil_zm<MODE, 4, 4, 8>(s, p, args...); break;
+        case 7: launch_stencil_zm<MODE, 1, 4, 8, 1>(s, p, args...); break;
+        case 8: launch_stencil_zm<MODE, 1, 4, 16, 2>(s, p, args...); break;
+        case 9: launch_stencil_zm<MODE, 2, 4, 16, 1>(s, p, args...); break;
+        case 10: launch_stencil_zm<MODE, 2, 4, 16, 2>(s, p, args...); break;
         default: launch_stencil_shape<MODE, 32, 8, 8>(s, p, args...);
     }
 }
