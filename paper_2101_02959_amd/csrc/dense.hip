@@ -631,26 +631,76 @@ __global__ __launch_bounds__(kWG) void k_extract(BatchDesc d, const T* __restric
     }
 }
 
+// Row streaming of the single-RHS solves over a packed factor: TS_SEG
+// entries (16 bytes) per lane, TS_LPR lanes per row, TS_RPI rows per wave
+// load instruction, TS_U row groups per wave in flight.
+template <typename T>
+struct TSGeom {
+    static constexpr int SEG = 16 / (int)sizeof(T), LPR = NB / SEG, RPI = 64 / LPR, U = 4;
+};
+
+// Loads of a packed factor row (NB entries) or of a contiguous M-entry
+// segment of one, as 16-byte vector loads; p is 16-byte aligned (rows start
+// on PP_NB-entry boundaries, segments on multiples of 4 floats / 2 doubles).
+template <typename T, int M>
+__device__ __forceinline__ void load_pseg(const T* __restrict__ p, T (&v)[M]) {
+    if constexpr (sizeof(T) == 4) {
+        static_assert(M % 4 == 0, "segment of whole float4");
+#pragma unroll
+        for (int q = 0; q < M / 4; ++q) {
+            const float4 f = reinterpret_cast<const float4*>(p)[q];
+            v[4 * q] = f.x; v[4 * q + 1] = f.y; v[4 * q + 2] = f.z; v[4 * q + 3] = f.w;
+        }
+    } else {
+        static_assert(M % 2 == 0, "segment of whole double2");
+#pragma unroll
+        for (int q = 0; q < M / 2; ++q) {
+            const double2 f = reinterpret_cast<const double2*>(p)[q];
+            v[2 * q] = f.x; v[2 * q + 1] = f.y;
+        }
+    }
+}
+template <typename T>
+__device__ __forceinline__ void load_prow(const T* __restrict__ p, T (&v)[NB]) {
+    load_pseg<T, NB>(p, v);
+}
+
 // Copy the lower triangles of the Dirichlet factor L_II and the Neumann
-// factor L_rr out of the chunk workspace into compact square storage (the
-// strict upper parts are never read).  Waves run over columns, lanes down a
-// column.
+// factor L_rr out of the chunk workspace into their panel-packed storage.
+// Each 64-row slab of a column block goes through LDS: read down the columns
+// (coalesced in the workspace), written along the packed rows.
+static_assert(NB == PP_NB, "the packed factor blocks are the solve blocks");
+template <typename T>
+__device__ void pack_lower(const T* __restrict__ A, int64_t ld, int n, T* __restrict__ P, T (*tile)[NB + 1]) {
+    const int tid = threadIdx.x;
+    for (int j0 = 0, b = 0; j0 < n; j0 += NB, ++b) {
+        T* Pb = P + pp_block(n, b);
+        for (int r0 = j0; r0 < n; r0 += 64) {
+            for (int idx = tid; idx < 64 * NB; idx += kWG) {
+                const int rr = idx % 64, c = idx / 64, r = r0 + rr, col = j0 + c;
+                tile[rr][c] = (r < n && col < n && col <= r) ? A[r + (int64_t)col * ld] : (T)0;
+            }
+            __syncthreads();
+            for (int idx = tid; idx < 64 * NB; idx += kWG) {
+                const int rr = idx / NB, c = idx % NB, r = r0 + rr;
+                if (r < n) Pb[(int64_t)(r - j0) * NB + c] = tile[rr][c];
+            }
+            __syncthreads();
+        }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_copy_out(BatchDesc d, const T* __restrict__ K, T* __restrict__ LII,
                                                  const int64_t* __restrict__ LIIoff, T* __restrict__ Lrr,
                                                  const int64_t* __restrict__ Lrroff) {
+    __shared__ T tile[64][NB + 1];
     const int s = d.sub0 + blockIdx.x;
     const int64_t ld = d.n[s];
     const int nI = d.nI[s], nr = d.nr[s];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const T* A = K + d.K_off[s];
-    T* a = LII + LIIoff[s];
-    for (int j = wv; j < nI; j += kWG / 64)
-        for (int i = j + lane; i < nI; i += 64) a[i + (int64_t)j * nI] = A[i + (int64_t)j * ld];
-    const T* B = A + (int64_t)nI * (ld + 1);
-    T* b = Lrr + Lrroff[s];
-    for (int j = wv; j < nr; j += kWG / 64)
-        for (int i = j + lane; i < nr; i += 64) b[i + (int64_t)j * nr] = B[i + (int64_t)j * ld];
+    pack_lower(A, ld, nI, LII + LIIoff[s], tile);
+    pack_lower(A + (int64_t)nI * (ld + 1), ld, nr, Lrr + Lrroff[s], tile);
 }
 
 // Zero the lower triangle (diagonal included) of every local matrix of a
@@ -669,26 +719,27 @@ __global__ __launch_bounds__(kWG) void k_clear_lower(BatchDesc d, T* __restrict_
 }
 
 // ----------------------------------------------------- multi-RHS forward
-// L X = B in place (L lower n x n, B n x k, k <= 64).
+// L X = B in place (L lower n x n, panel-packed; B n x k, k <= 64).
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_trsm_fwd(const T* __restrict__ Lb, const int64_t* __restrict__ Loff,
-                                                 const int* __restrict__ nv, const int* __restrict__ ldv,
-                                                 T* __restrict__ Bb, const int64_t* __restrict__ Boff,
-                                                 const int* __restrict__ ldbv, const int* __restrict__ kv) {
+                                                 const int* __restrict__ nv, T* __restrict__ Bb,
+                                                 const int64_t* __restrict__ Boff, const int* __restrict__ ldbv,
+                                                 const int* __restrict__ kv) {
     const int s = blockIdx.x;
     const T* L = Lb + Loff[s];
     T* B = Bb + Boff[s];
     const int n = nv[s], k = kv[s];
-    const int64_t ld = ldv[s], ldb = ldbv[s];
+    const int64_t ldb = ldbv[s];
     const int tid = threadIdx.x;
     __shared__ T D[NB][NB + 1];
     __shared__ T X[NB][64 + 1];
     __shared__ int live[64];
     for (int j0 = 0; j0 < n; j0 += NB) {
         const int jb = min(NB, n - j0);
+        const T* Lp = L + pp_block(n, j0 / NB);   // row r of the block at Lp + (r - j0) NB
         for (int idx = tid; idx < NB * NB; idx += kWG) {
-            const int i = idx % NB, j = idx / NB;
-            D[i][j] = (i < jb && j <= i) ? L[(j0 + i) + (j0 + j) * ld] : (T)0;
+            const int i = idx / NB, j = idx % NB;
+            D[i][j] = (i < jb && j <= i) ? Lp[i * NB + j] : (T)0;
         }
         for (int idx = tid; idx < NB * 64; idx += kWG) {
             const int i = idx % NB, c = idx / NB;
@@ -721,8 +772,7 @@ __global__ __launch_bounds__(kWG) void k_trsm_fwd(const T* __restrict__ Lb, cons
         const int t0 = j0 + jb;
         for (int r = t0 + tid; r < n; r += kWG) {
             T lv[NB];
-#pragma unroll
-            for (int m = 0; m < NB; ++m) lv[m] = (m < jb) ? L[r + (j0 + m) * ld] : (T)0;
+            load_prow(Lp + (int64_t)(r - j0) * NB, lv);   // entries past column n-1 are zero
             for (int c = 0; c < k; ++c) {
                 if (!live[c]) continue;
                 T acc = (T)0;
@@ -884,31 +934,32 @@ __device__ inline int next_item(const int* __restrict__ order, int* __restrict__
 
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_trsv_fwd(const T* __restrict__ Lb, const int64_t* __restrict__ Loff,
-                                                 const int* __restrict__ nv, const int* __restrict__ ldv,
-                                                 T* __restrict__ xb, const int64_t* __restrict__ xoff, int nb,
+                                                 const int* __restrict__ nv, T* __restrict__ xb,
+                                                 const int64_t* __restrict__ xoff, int nb,
                                                  const int* __restrict__ order, int* __restrict__ ctr) {
     extern __shared__ double trsv_lds[];
     T* xl = reinterpret_cast<T*>(trsv_lds);
     __shared__ T xs[NB];
+    constexpr int TS_SEG = TSGeom<T>::SEG, TS_LPR = TSGeom<T>::LPR, TS_RPI = TSGeom<T>::RPI, TS_U = TSGeom<T>::U;
     for (int pass = 0;; ++pass) {
     const int s = next_item(order, ctr, nb, pass);
     if (s < 0) break;
     const T* L = Lb + Loff[s];
     T* x = xb + xoff[s];
     const int n = nv[s];
-    const int64_t ld = ldv[s];
     const int tid = threadIdx.x, lane = tid & 63;
-    // wave 0 holds the diagonal block of the current step in drow.  FP32:
-    // loaded during the previous step's update so that its latency is hidden
-    // (at no cost in occupancy); FP64: loaded at the step itself, which keeps
-    // the register count down.
+    // wave 0 holds the diagonal block of the current step in drow (lane i:
+    // row i of the block, one packed row).  FP32: loaded during the previous
+    // step's update so that its latency is hidden (at no cost in occupancy);
+    // FP64: loaded at the step itself, which keeps the register count down.
     constexpr bool early = sizeof(T) == 4;
     T drow[NB], rdiag = (T)1;
     auto load_diag = [&](int j0) {
         const int jb = min(NB, n - j0), i = min(lane, jb - 1);
+        load_prow(L + pp_block(n, j0 / NB) + (int64_t)i * NB, drow);
+        rdiag = drow[0];
 #pragma unroll
-        for (int c = 0; c < NB; ++c) drow[c] = L[(j0 + i) + (j0 + min(c, jb - 1)) * ld];
-        rdiag = L[(j0 + i) + (j0 + i) * ld];
+        for (int c = 1; c < NB; ++c) rdiag = (c == i) ? drow[c] : rdiag;
     };
     if (early && tid < 64) load_diag(0);
     for (int i = tid; i < n; i += kWG) xl[i] = x[i];
@@ -931,15 +982,35 @@ __global__ __launch_bounds__(kWG) void k_trsv_fwd(const T* __restrict__ Lb, cons
         }
         __syncthreads();
         if (early && tid < 64 && j0 + NB < n) load_diag(j0 + NB);
-        for (int r = j0 + jb + tid; r < n; r += kWG) {
-            // branch-free, fully unrolled so all column loads are in flight together
-            T lv[NB];
+        // Rows below the block: LPR lanes share a packed row, one 16-byte
+        // chunk each, so a load instruction reads RPI whole rows; TU row
+        // groups per wave are in flight together.  Each lane dots its chunk
+        // with x and the row's lanes sum by xor shuffles.  (xs and the
+        // padding past column n-1 are zero.)
+        const T* Lp = L + pp_block(n, j0 / NB);
+        {
+            const int q = lane % TS_LPR, rr = lane / TS_LPR;
+            T xq[TS_SEG];
 #pragma unroll
-            for (int c = 0; c < NB; ++c) lv[c] = L[r + (j0 + min(c, jb - 1)) * ld];
-            T acc = (T)0;
+            for (int k = 0; k < TS_SEG; ++k) xq[k] = xs[q * TS_SEG + k];
+            for (int r0 = j0 + jb + (tid >> 6) * TS_RPI * TS_U; r0 < n; r0 += (kWG / 64) * TS_RPI * TS_U) {
+                T v[TS_U][TS_SEG];
 #pragma unroll
-            for (int c = 0; c < NB; ++c) acc += (c < jb ? lv[c] : (T)0) * xs[c];
-            xl[r] -= acc;
+                for (int u = 0; u < TS_U; ++u) {
+                    const int rc = min(r0 + u * TS_RPI + rr, n - 1);
+                    load_pseg<T, TS_SEG>(Lp + (int64_t)(rc - j0) * NB + q * TS_SEG, v[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < TS_U; ++u) {
+                    T acc = (T)0;
+#pragma unroll
+                    for (int k = 0; k < TS_SEG; ++k) acc += v[u][k] * xq[k];
+#pragma unroll
+                    for (int m = 1; m < TS_LPR; m <<= 1) acc += __shfl_xor(acc, m);
+                    const int r = r0 + u * TS_RPI + rr;
+                    if (q == 0 && r < n) xl[r] -= acc;
+                }
+            }
         }
         __syncthreads();
     }
@@ -949,53 +1020,65 @@ __global__ __launch_bounds__(kWG) void k_trsv_fwd(const T* __restrict__ Lb, cons
 
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_trsv_bwd(const T* __restrict__ Lb, const int64_t* __restrict__ Loff,
-                                                 const int* __restrict__ nv, const int* __restrict__ ldv,
-                                                 T* __restrict__ xb, const int64_t* __restrict__ xoff, int nb,
+                                                 const int* __restrict__ nv, T* __restrict__ xb,
+                                                 const int64_t* __restrict__ xoff, int nb,
                                                  const int* __restrict__ order, int* __restrict__ ctr) {
     extern __shared__ double trsv_lds[];
     T* xl = reinterpret_cast<T*>(trsv_lds);
-    __shared__ T red[1][NB];
+    __shared__ T red[kWG / 64][NB];
+    constexpr int TS_SEG = TSGeom<T>::SEG, TS_LPR = TSGeom<T>::LPR, TS_RPI = TSGeom<T>::RPI, TS_U = TSGeom<T>::U;
     for (int pass = 0;; ++pass) {
     const int s = next_item(order, ctr, nb, pass);
     if (s < 0) break;
     const T* L = Lb + Loff[s];
     T* x = xb + xoff[s];
     const int n = nv[s];
-    const int64_t ld = ldv[s];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int i = tid; i < n; i += kWG) xl[i] = x[i];
     __syncthreads();
     const int nblk = (n + NB - 1) / NB;
     for (int bi = nblk - 1; bi >= 0; --bi) {
         const int j0 = bi * NB, jb = min(NB, n - j0);
-        // wave wv owns columns [8 wv, 8 wv + 8) of the block: coalesced column
-        // segments below the block, dotted with x, one wave reduction each
-        constexpr int CW = NB / (kWG / 64);
-        T acc[CW];
+        const T* Lp = L + pp_block(n, bi);
+        // L_blk^T x_below: the rows below the block as in the forward solve
+        // (LPR lanes per packed row, one 16-byte chunk each, TU row groups in
+        // flight); each lane accumulates its chunk's columns times x_r, the
+        // lanes of one chunk position sum by xor shuffles, and the waves'
+        // sums meet in LDS.
+        {
+            const int q = lane % TS_LPR, rr = lane / TS_LPR;
+            T acc[TS_SEG];
 #pragma unroll
-        for (int k = 0; k < CW; ++k) acc[k] = (T)0;
-        for (int r = j0 + jb + lane; r < n; r += 64) {
-            const T xr = xl[r];
+            for (int k = 0; k < TS_SEG; ++k) acc[k] = (T)0;
+            for (int r0 = j0 + jb + wv * TS_RPI * TS_U; r0 < n; r0 += (kWG / 64) * TS_RPI * TS_U) {
+                T v[TS_U][TS_SEG], xr[TS_U];
 #pragma unroll
-            for (int k = 0; k < CW; ++k) {
-                const int c = min(CW * wv + k, jb - 1);
-                acc[k] += L[r + (j0 + c) * ld] * xr;
+                for (int u = 0; u < TS_U; ++u) {
+                    const int r = r0 + u * TS_RPI + rr, rc = min(r, n - 1);
+                    load_pseg<T, TS_SEG>(Lp + (int64_t)(rc - j0) * NB + q * TS_SEG, v[u]);
+                    xr[u] = r < n ? xl[rc] : (T)0;
+                }
+#pragma unroll
+                for (int u = 0; u < TS_U; ++u)
+#pragma unroll
+                    for (int k = 0; k < TS_SEG; ++k) acc[k] += v[u][k] * xr[u];
             }
-        }
 #pragma unroll
-        for (int k = 0; k < CW; ++k) {
-            const T sred = wave_sum(acc[k]);
-            if (lane == 0) red[0][CW * wv + k] = sred;
+            for (int k = 0; k < TS_SEG; ++k) {
+#pragma unroll
+                for (int m = TS_LPR; m < 64; m <<= 1) acc[k] += __shfl_xor(acc[k], m);
+                if (rr == 0) red[wv][q * TS_SEG + k] = acc[k];
+            }
         }
         __syncthreads();
         if (tid < 64) {
             const int i = min(lane, jb - 1);
             T dcol[NB];   // dcol[c] = L[j0 + c][j0 + i], used for c > i only
 #pragma unroll
-            for (int c = 0; c < NB; ++c) dcol[c] = L[(j0 + min(c, jb - 1)) + (j0 + i) * ld];
-            const T rinv = (lane < jb) ? (T)1 / L[(j0 + i) + (j0 + i) * ld] : (T)0;
+            for (int c = 0; c < NB; ++c) dcol[c] = Lp[(int64_t)min(c, jb - 1) * NB + i];
+            const T rinv = (lane < jb) ? (T)1 / Lp[(int64_t)i * NB + i] : (T)0;
             T rhs = (T)0;
-            if (lane < jb) rhs = xl[j0 + lane] - red[0][lane];
+            if (lane < jb) rhs = xl[j0 + lane] - ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]));
 #pragma unroll
             for (int c = NB - 1; c >= 0; --c) {
                 if (c < jb) {
@@ -1344,9 +1427,9 @@ void launch_copy_out(hipStream_t s, const BatchDesc& d, int nb, const T* K, T* L
     hipLaunchKernelGGL(k_copy_out<T>, dim3(nb), dim3(kWG), 0, s, d, K, LII, LIIoff, Lrr, Lrroff);
 }
 template <typename T>
-void launch_trsm_fwd(hipStream_t s, int nb, const T* L, const int64_t* Loff, const int* n, const int* ld,
-                     T* B, const int64_t* Boff, const int* ldb, const int* k) {
-    hipLaunchKernelGGL(k_trsm_fwd<T>, dim3(nb), dim3(kWG), 0, s, L, Loff, n, ld, B, Boff, ldb, k);
+void launch_trsm_fwd(hipStream_t s, int nb, const T* L, const int64_t* Loff, const int* n, T* B,
+                     const int64_t* Boff, const int* ldb, const int* k) {
+    hipLaunchKernelGGL(k_trsm_fwd<T>, dim3(nb), dim3(kWG), 0, s, L, Loff, n, B, Boff, ldb, k);
 }
 template <typename T>
 void launch_coarse_local(hipStream_t s, const BatchDesc& d, const T* F, const double* Svv, T* Z, T* Gi,
@@ -1354,8 +1437,8 @@ void launch_coarse_local(hipStream_t s, const BatchDesc& d, const T* F, const do
     hipLaunchKernelGGL(k_coarse_local<T>, dim3(d.nsub), dim3(kWG), 0, s, d, F, Svv, Z, Gi, Sp, info);
 }
 template <typename T>
-void launch_trsv(hipStream_t s, int nb, bool trans, const T* L, const int64_t* Loff, const int* n,
-                 const int* ld, T* x, const int64_t* xoff, int maxn, const WorkQueue& q) {
+void launch_trsv(hipStream_t s, int nb, bool trans, const T* L, const int64_t* Loff, const int* n, T* x,
+                 const int64_t* xoff, int maxn, const WorkQueue& q) {
     if (nb <= 0 || maxn <= 0) return;
     const size_t lds = (size_t)maxn * sizeof(T);
     auto kern = trans ? k_trsv_bwd<T> : k_trsv_fwd<T>;
@@ -1370,7 +1453,7 @@ void launch_trsv(hipStream_t s, int nb, bool trans, const T* L, const int64_t* L
     }
     const int* ord = q.order;
     int* ctr = (q.order && q.counter) ? q.counter : nullptr;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWG), lds, s, L, Loff, n, ld, x, xoff, nb, ord, ctr);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWG), lds, s, L, Loff, n, x, xoff, nb, ord, ctr);
 }
 template <typename T>
 void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, int ob0, int nob, int maxn, const T* slots, T* fac, T* dmat,
@@ -1411,12 +1494,12 @@ int deluxe_max_object() { return DLX_MAXN; }
     template void launch_clear_lower<T>(hipStream_t, const BatchDesc&, int, T*);                       \
     template void launch_copy_out<T>(hipStream_t, const BatchDesc&, int, const T*, T*, const int64_t*, T*,    \
                                      const int64_t*);                                                    \
-    template void launch_trsm_fwd<T>(hipStream_t, int, const T*, const int64_t*, const int*, const int*, \
-                                     T*, const int64_t*, const int*, const int*);                        \
+    template void launch_trsm_fwd<T>(hipStream_t, int, const T*, const int64_t*, const int*, T*,         \
+                                     const int64_t*, const int*, const int*);                            \
     template void launch_coarse_local<T>(hipStream_t, const BatchDesc&, const T*, const double*, T*, T*, \
                                          double*, int*);                                                 \
-    template void launch_trsv<T>(hipStream_t, int, bool, const T*, const int64_t*, const int*,          \
-                                 const int*, T*, const int64_t*, int, const WorkQueue&);                 \
+    template void launch_trsv<T>(hipStream_t, int, bool, const T*, const int64_t*, const int*, T*,      \
+                                 const int64_t*, int, const WorkQueue&);                                 \
     template void launch_deluxe_setup<T>(hipStream_t, const ObjDesc&, int, int, int, const T*, T*, T*, int*);
 BDM_INST(double)
 BDM_INST(float)

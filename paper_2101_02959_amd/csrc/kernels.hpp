@@ -90,12 +90,27 @@ void launch_extract(hipStream_t s, const BatchDesc& d, const T* K, T* slots, T* 
 // Zero the lower triangles of the chunk's local matrices (maxn bounds n).
 template <typename T>
 void launch_clear_lower(hipStream_t s, const BatchDesc& d, int maxn, T* K);
+// Panel-packed storage of the Dirichlet and Neumann factors, which the
+// per-iteration solves stream: column blocks of PP_NB; block b holds the rows
+// b PP_NB .. n-1, each as PP_NB consecutive entries (the row's part of the
+// block's columns; entries right of the diagonal or past column n-1 are
+// zero).  Every row starts on a PP_NB-entry boundary, so the solves read
+// whole cache lines only, and the storage holds the lower triangle only.
+constexpr int PP_NB = 32;
+__host__ __device__ inline int64_t pp_block(int n, int b) {   // first entry of block b
+    return (int64_t)PP_NB * ((int64_t)b * n - (int64_t)PP_NB * b * (b - 1) / 2);
+}
+__host__ __device__ inline int64_t pp_size(int n) { return pp_block(n, (n + PP_NB - 1) / PP_NB); }
+
+// Copy the factors L_II and L_rr out of the chunk workspace into their
+// panel-packed storage.
 template <typename T>
 void launch_copy_out(hipStream_t s, const BatchDesc& d, int nb, const T* K, T* LII, const int64_t* LIIoff, T* Lrr,
                      const int64_t* Lrroff);
+// Multi-right-hand-side forward solve L X = B with panel-packed L.
 template <typename T>
 void launch_trsm_fwd(hipStream_t s, int nb, const T* L, const int64_t* Loff, const int* n,
-                     const int* ld, T* B, const int64_t* Boff, const int* ldb, const int* k);
+                     T* B, const int64_t* Boff, const int* ldb, const int* k);
 template <typename T>
 void launch_coarse_local(hipStream_t s, const BatchDesc& d, const T* F, const double* Svv, T* Z,
                          T* Gi, double* Sp, int* info);
@@ -109,11 +124,11 @@ struct WorkQueue {
     const int* order = nullptr;   // device: nb matrix indices, decreasing cost
     int* counter = nullptr;       // device: 2 ints (next item, finished workgroups), zero between launches
 };
-// Batched triangular solves with the n x n lower factor of each matrix
-// (leading dimension ld), in place on x; maxn bounds n over the batch.
+// Batched triangular solves with the panel-packed n x n lower factor of each
+// matrix, in place on x; maxn bounds n over the batch.
 template <typename T>
 void launch_trsv(hipStream_t s, int nb, bool trans, const T* L, const int64_t* Loff, const int* n,
-                 const int* ld, T* x, const int64_t* xoff, int maxn, const WorkQueue& q);
+                 T* x, const int64_t* xoff, int maxn, const WorkQueue& q);
 
 // Deluxe objects (faces and edges), one workgroup per object.
 struct ObjDesc {

@@ -188,8 +188,8 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
         lmap_off[q] = (int64_t)lmap.size();
         lmap.insert(lmap.end(), sb.lmap.begin(), sb.lmap.end());
         K_off[q] = accK; accK += (int64_t)sb.n() * sb.n();
-        LII[q] = accLII; accLII += (int64_t)sb.nI * sb.nI;
-        Lrr[q] = accLrr; accLrr += (int64_t)sb.nr * sb.nr;
+        LII[q] = accLII; accLII += pp_size(sb.nI);
+        Lrr[q] = accLrr; accLrr += pp_size(sb.nr);
         F_off[q] = accF; accF += (int64_t)sb.nr * (sb.nc + sb.nV);
         Z_off[q] = accZ; accZ += (int64_t)sb.nr * sb.nP;
         P_off[q] = accP; accP += sb.nP;
@@ -788,7 +788,7 @@ int Context::linearize_t() {
         eliminate<T>(K, s0, cnt, plan_rr_, nullptr);
         launch_copy_out<T>(stream_, cd, cnt, K, (T*)LIIs_, LII_off_, (T*)Lrrs_, Lrr_off_);
     }
-    launch_trsm_fwd<T>(stream_, nsub, (const T*)Lrrs_, Lrr_off_, nr_, nr_, (T*)F_, bd_.F_off, nr_, kF_);
+    launch_trsm_fwd<T>(stream_, nsub, (const T*)Lrrs_, Lrr_off_, nr_, (T*)F_, bd_.F_off, nr_, kF_);
     launch_coarse_local<T>(stream_, bd_, (const T*)F_, Svv_, (T*)Z_, (T*)Gi_, Sp_, info_sub_);
     // faces and edges separately: each launch reserves LDS for its own largest object
     launch_deluxe_setup<T>(stream_, od_, 0, nface_obj_, maxface_n_, (const T*)slots_, (T*)fac_, (T*)dmat_, info_obj_);
@@ -830,8 +830,8 @@ template <typename T>
 void Context::dirichlet(const double* r, const double* q, double* out) {
     T* xI = (T*)xI_;
     launch_gather_I<T>(stream_, nInodes_, Ilist_, N, r, q, xI);
-    launch_trsv<T>(stream_, bd_.nsub, false, (const T*)LIIs_, LII_off_, nI_, nI_, xI, xI_off_, maxnI_, qI_);
-    launch_trsv<T>(stream_, bd_.nsub, true, (const T*)LIIs_, LII_off_, nI_, nI_, xI, xI_off_, maxnI_, qI_);
+    launch_trsv<T>(stream_, bd_.nsub, false, (const T*)LIIs_, LII_off_, nI_, xI, xI_off_, maxnI_, qI_);
+    launch_trsv<T>(stream_, bd_.nsub, true, (const T*)LIIs_, LII_off_, nI_, xI, xI_off_, maxnI_, qI_);
     launch_scatter_I<T>(stream_, nInodes_, Ilist_, N, xI, out);
 }
 
@@ -848,13 +848,13 @@ void Context::condense(const double* r, double* g) {
 // backward solve for the Neumann correction plus the coarse prolongation.
 template <typename T>
 void Context::stilde_inv(T* xr, const double* gvert, double* uc) {
-    launch_trsv<T>(stream_, bd_.nsub, false, (const T*)Lrrs_, Lrr_off_, nr_, nr_, xr, xr_off_, maxnr_, qr_);
+    launch_trsv<T>(stream_, bd_.nsub, false, (const T*)Lrrs_, Lrr_off_, nr_, xr, xr_off_, maxnr_, qr_);
     launch_coarse_rhs_local<T>(stream_, sv_, xr, (const T*)F_, (const T*)Z_, (const T*)Gi_, cP_, mu_);
     launch_coarse_rhs_gather(stream_, cd_, N, gvert, cP_, uc);
     launch_coarse_project(stream_, cd_.np, pin_, uc);
     coarse_.solve(stream_, uc);
     launch_neumann_rhs<T>(stream_, sv_, (const T*)F_, (const T*)Z_, mu_, uc, xr, 1);
-    launch_trsv<T>(stream_, bd_.nsub, true, (const T*)Lrrs_, Lrr_off_, nr_, nr_, xr, xr_off_, maxnr_, qr_);
+    launch_trsv<T>(stream_, bd_.nsub, true, (const T*)Lrrs_, Lrr_off_, nr_, xr, xr_off_, maxnr_, qr_);
 }
 
 // zbuf holds interface values (zero interior); fill the interior by the
@@ -1202,7 +1202,7 @@ int Context::profile_t(int kernel, int reps, double* avg_ms, double* work) {
                 launch_jac_apply(stream_, fp, st_, dg_, kp_, kq_);
             else
                 launch_trsv<T>(stream_, nsub, kernel == BDM_KERNEL_TRSV_DIRICHLET_T, (const T*)LIIs_, LII_off_, nI_,
-                               nI_, (T*)xI_, xI_off_, maxnI_, qI_);
+                               (T*)xI_, xI_off_, maxnI_, qI_);
             HIPOK(hipEventRecord(e1, stream_));
             HIPOK(hipEventSynchronize(e1));
             float ms = 0.f;
