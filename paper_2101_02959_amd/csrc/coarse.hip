@@ -125,31 +125,42 @@ __global__ __launch_bounds__(256) void k_nd_gemv_t(const int64_t* __restrict__ f
     }
 }
 
-// out[r] = base[r] + sgn * sum_c B[r][c] x[c] over the n_e columns, 64 rows
-// per workgroup, the four waves splitting the columns; rows of blk 1 land at
-// the front's boundary part.
+// out[r] = base[r] + sgn * sum_c B[r][c] x[c] over the n_e columns, GN_RB
+// rows per workgroup and GN_CS column slices (a wave reads four columns of
+// 16 rows, four columns in flight per thread), the slices summed in LDS in a
+// fixed order; rows of blk 1 land at the front's boundary part.  Narrow row
+// blocks keep enough workgroups in flight on the few large fronts near the
+// root of the tree.
+constexpr int GN_RB = 16, GN_CS = 256 / GN_RB;
 __global__ __launch_bounds__(256) void k_nd_gemv_n(const int64_t* __restrict__ foff, const int* __restrict__ nev,
                                                    const int* __restrict__ mv, const int* __restrict__ ldv, int blk,
                                                    const double* __restrict__ F, const int64_t* __restrict__ zoff,
                                                    const double* __restrict__ xv, const double* __restrict__ base,
                                                    double* __restrict__ out, double sgn) {
-    __shared__ double red[4][64];
+    __shared__ double red[GN_CS][GN_RB + 1];
     const int f = blockIdx.y;
     const int ne = nev[f], m = mv[f];
     int r0, R;
     nd_block(blk, ne, m, r0, R);
-    const int row = blockIdx.x * 64 + (threadIdx.x & 63), wv = threadIdx.x >> 6;
-    if (blockIdx.x * 64 >= R) return;
+    if ((int)blockIdx.x * GN_RB >= R) return;
+    const int rl = threadIdx.x % GN_RB, cs = threadIdx.x / GN_RB;
+    const int row = blockIdx.x * GN_RB + rl, rc = min(row, R - 1);
     const int64_t ld = ldv[f];
-    const double* A = F + foff[f] + r0;
+    const double* A = F + foff[f] + r0 + rc;
     const double* x = xv + zoff[f];
-    double acc = 0.0;
-    if (row < R)
-        for (int c = wv; c < ne; c += 4) acc += A[row + c * ld] * x[c];
-    red[wv][threadIdx.x & 63] = acc;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int c = cs;
+    for (; c + 3 * GN_CS < ne; c += 4 * GN_CS) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += A[(int64_t)(c + u * GN_CS) * ld] * x[c + u * GN_CS];
+    }
+    for (; c < ne; c += GN_CS) acc[0] += A[(int64_t)c * ld] * x[c];
+    red[cs][rl] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     __syncthreads();
-    if (wv == 0 && row < R) {
-        const double d = red[0][row & 63] + red[1][row & 63] + red[2][row & 63] + red[3][row & 63];
+    if (threadIdx.x < GN_RB && row < R) {
+        double d = 0.0;
+#pragma unroll
+        for (int q = 0; q < GN_CS; ++q) d += red[q][rl];
         const int64_t k = zoff[f] + (blk ? ne : 0) + row;
         out[k] = (base ? base[k] : 0.0) + sgn * d;
     }
@@ -505,7 +516,7 @@ void CoarseSolver::solve(hipStream_t s, double* b) {
         hipLaunchKernelGGL(k_nd_gemv_t, dim3(nb(maxne[h], 4), nf), dim3(256), 0, s, d_foff + f0, d_ne + f0, d_m + f0,
                            d_ld + f0, 0, F, d_zoff + f0, z, nullptr, z2, 1.0);
         if (maxm[h] > 0)
-            hipLaunchKernelGGL(k_nd_gemv_n, dim3(nb(maxm[h], 64), nf), dim3(256), 0, s, d_foff + f0, d_ne + f0,
+            hipLaunchKernelGGL(k_nd_gemv_n, dim3(nb(maxm[h], GN_RB), nf), dim3(256), 0, s, d_foff + f0, d_ne + f0,
                                d_m + f0, d_ld + f0, 1, F, d_zoff + f0, z2, z, z, -1.0);
     }
     for (int h = H - 1; h >= 0; --h) {
@@ -516,7 +527,7 @@ void CoarseSolver::solve(hipStream_t s, double* b) {
                            d_ne + f0, d_m + f0, d_vars, b, z);
         hipLaunchKernelGGL(k_nd_gemv_t, dim3(nb(maxne[h], 4), nf), dim3(256), 0, s, d_foff + f0, d_ne + f0, d_m + f0,
                            d_ld + f0, 1, F, d_zoff + f0, z, z2, z, -1.0);
-        hipLaunchKernelGGL(k_nd_gemv_n, dim3(nb(maxne[h], 64), nf), dim3(256), 0, s, d_foff + f0, d_ne + f0, d_m + f0,
+        hipLaunchKernelGGL(k_nd_gemv_n, dim3(nb(maxne[h], GN_RB), nf), dim3(256), 0, s, d_foff + f0, d_ne + f0, d_m + f0,
                            d_ld + f0, 0, F, d_zoff + f0, z, nullptr, z2, 1.0);
         hipLaunchKernelGGL(k_nd_scatter_e, dim3(nb(maxne[h], 256), nf), dim3(256), 0, s, d_zoff + f0, d_ne + f0,
                            d_vars, z2, b);
