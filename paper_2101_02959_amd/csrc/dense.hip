@@ -191,31 +191,79 @@ __device__ __forceinline__ void potrf_body(T* __restrict__ A, int64_t ld, int cb
             D[i][j] = (i < jb && j < jb && j <= i) ? A[(j0 + i) + (j0 + j) * ld] : (T)(i == j);
         }
         __syncthreads();
+        // One barrier per pivot: step k updates the trailing block with the
+        // unscaled column, a_ij -= a_ik a_jk / a_kk (every thread reads the
+        // pivot itself), and the columns are scaled once at the end,
+        // l_kk = sqrt(a_kk), l_ik = a_ik / l_kk.  A pivot that is not positive
+        // flags the matrix and is replaced by 1.
         for (int k = 0; k < jb; ++k) {
-            if (tid == 0) {
-                T dk = D[k][k];
-                if (!(dk > (T)0)) { bad = 1; dk = (T)1; }
-                D[k][k] = sqrt(dk);
-            }
-            __syncthreads();
-            const T piv = D[k][k];
-            for (int i = k + 1 + tid; i < jb; i += kWG) D[i][k] /= piv;
-            __syncthreads();
-            const int m = jb - k - 1;
-            for (int idx = tid; idx < m * m; idx += kWG) {
-                const int i = k + 1 + idx % m, j = k + 1 + idx / m;
-                if (j <= i) D[i][j] -= D[i][k] * D[j][k];
+            T dk = D[k][k];
+            if (!(dk > (T)0)) dk = (T)1;
+            const T rk = (T)1 / dk;
+            // thread (row NB-slot, column group): no division by the
+            // trailing size
+            const int i = tid % NB;
+            if (i > k && i < jb) {
+                const T lik = D[i][k] * rk;
+                for (int j = k + 1 + tid / NB; j <= i; j += kWG / NB) D[i][j] -= lik * D[j][k];
             }
             __syncthreads();
         }
-        // W = D^{-1} (lower triangular), one column per thread
         if (tid < NB) {
-            const int c = tid;
-            for (int i = 0; i < NB; ++i) {
-                T acc = (i == c) ? (T)1 : (T)0;
-                for (int k = c; k < i; ++k) acc -= D[i][k] * W[k][c];
-                W[i][c] = (i >= c) ? acc / D[i][i] : (T)0;
+            T dk = D[tid][tid];
+            if (tid < jb && !(dk > (T)0)) { bad = 1; dk = (T)1; }
+            W[tid][0] = sqrt(dk);   // pivots (W is rewritten below)
+        }
+        __syncthreads();
+        for (int idx = tid; idx < NB * NB; idx += kWG) {
+            const int i = idx % NB, k = idx / NB;
+            if (i > k) D[i][k] /= W[k][0];
+        }
+        __syncthreads();
+        if (tid < NB) D[tid][tid] = W[tid][0];
+        __syncthreads();
+        // W = D^{-1} (lower triangular), one column per thread, the column
+        // in registers (no store-to-load dependence through LDS)
+        // W = D^{-1} (lower triangular) by forward substitution.  FP32: column
+        // c by the 8 lanes 8c .. 8c + 7: lane t keeps W[k][c] for k = t (mod 8)
+        // in registers; per row, the lanes' partial dots are summed by xor
+        // shuffles and the owning lane keeps the new entry.  FP64: one thread
+        // per column through LDS (the register form costs FP64 occupancy
+        // here).
+        static_assert(kWG == 8 * NB, "eight lanes per column of the inverse");
+        if constexpr (sizeof(T) == 8) {
+            if (tid < NB) {
+                const int c = tid;
+                for (int i = 0; i < NB; ++i) {
+                    T acc = (i == c) ? (T)1 : (T)0;
+                    for (int k = c; k < i; ++k) acc -= D[i][k] * W[k][c];
+                    W[i][c] = (i >= c) ? acc / D[i][i] : (T)0;
+                }
             }
+        } else {
+            const int c = tid / 8, t = tid % 8;
+            T w[NB / 8];
+#pragma unroll
+            for (int q = 0; q < NB / 8; ++q) w[q] = (T)0;
+#pragma unroll 1
+            for (int i0 = 0; i0 < NB; i0 += 8) {
+#pragma unroll
+                for (int ii = 0; ii < 8; ++ii) {
+                    const int i = i0 + ii;
+                    T part = (T)0;
+#pragma unroll
+                    for (int q = 0; q < NB / 8; ++q)
+                        if (8 * q + t < i) part += D[i][8 * q + t] * w[q];
+                    part += __shfl_xor(part, 1);
+                    part += __shfl_xor(part, 2);
+                    part += __shfl_xor(part, 4);
+                    const T wi = (i >= c) ? (((i == c) ? (T)1 : (T)0) - part) / D[i][i] : (T)0;
+#pragma unroll
+                    for (int q = 0; q < NB / 8; ++q) w[q] = (t == ii && 8 * q == i0) ? wi : w[q];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NB / 8; ++q) W[8 * q + t][c] = w[q];
         }
         for (int idx = tid; idx < jb * jb; idx += kWG) {
             const int i = idx % jb, j = idx / jb;
