@@ -833,6 +833,20 @@ __global__ __launch_bounds__(kWG) void k_trsm_fwd(const T* __restrict__ Lb, cons
     }
 }
 
+// Dot product of two length-n columns by one wave (lanes down the rows, two
+// accumulators, one wave sum); every lane returns the sum.
+template <typename T>
+__device__ __forceinline__ double wave_dot(const T* __restrict__ a, const T* __restrict__ b, int n, int lane) {
+    double s0 = 0.0, s1 = 0.0;
+    int r = lane;
+    for (; r + 64 < n; r += 128) {
+        s0 += (double)a[r] * (double)b[r];
+        s1 += (double)a[r + 64] * (double)b[r + 64];
+    }
+    if (r < n) s0 += (double)a[r] * (double)b[r];
+    return wave_sum(s0 + s1);
+}
+
 // ------------------------------------------------------- coarse algebra
 // With Y = L_rr^{-1} C^T and X = -L_rr^{-1} S_rV (from k_trsm_fwd), the
 // energy-minimising coarse basis of Sec. 4.4 under the edge-average
@@ -856,20 +870,23 @@ __global__ __launch_bounds__(kWG) void k_coarse_local(BatchDesc d, const T* __re
     __shared__ double Gi[MAXC][MAXC + 1];
     __shared__ double YtX[MAXC][MAXV + 1];
     __shared__ double muV[MAXC][MAXV + 1];
-    // G = Y^T Y
-    for (int idx = tid; idx < nc * nc; idx += kWG) {
-        const int i = idx % nc, j = idx / nc;
-        if (j > i) continue;
-        double acc = 0.0;
-        for (int r = 0; r < nr; ++r) acc += (double)Y[r + (int64_t)i * nr] * (double)Y[r + (int64_t)j * nr];
-        G[i][j] = acc;
-        G[j][i] = acc;
-    }
-    for (int idx = tid; idx < nc * nV; idx += kWG) {
-        const int i = idx % nc, q = idx / nc;
-        double acc = 0.0;
-        for (int r = 0; r < nr; ++r) acc += (double)Y[r + (int64_t)i * nr] * (double)X[r + (int64_t)q * nr];
-        YtX[i][q] = acc;
+    // G = Y^T Y and Y^T X: one wave per column pair, lanes down the rows
+    // (coalesced), pairs spread over the waves
+    const int wv = tid >> 6, lane = tid & 63;
+    for (int idx = wv; idx < nc * nc + nc * nV; idx += kWG / 64) {
+        if (idx < nc * nc) {
+            const int i = idx % nc, j = idx / nc;
+            if (j > i) continue;
+            const double acc = wave_dot(Y + (int64_t)i * nr, Y + (int64_t)j * nr, nr, lane);
+            if (lane == 0) {
+                G[i][j] = acc;
+                G[j][i] = acc;
+            }
+        } else {
+            const int i = (idx - nc * nc) % nc, q = (idx - nc * nc) / nc;
+            const double acc = wave_dot(Y + (int64_t)i * nr, X + (int64_t)q * nr, nr, lane);
+            if (lane == 0) YtX[i][q] = acc;
+        }
     }
     __syncthreads();
     if (tid == 0) {   // Cholesky of the small constraint matrix
@@ -926,12 +943,10 @@ __global__ __launch_bounds__(kWG) void k_coarse_local(BatchDesc d, const T* __re
     __syncthreads();
     double* Sp = Spb + (int64_t)s * SP_STRIDE;
     const double* sv = Svv + (int64_t)s * SVV_STRIDE;
-    for (int idx = tid; idx < nV * nP; idx += kWG) {
+    for (int idx = wv; idx < nV * nP; idx += kWG / 64) {
         const int q = idx % nV, pcol = idx / nV;
-        double acc = 0.0;
-        for (int r = 0; r < nr; ++r) acc += (double)X[r + (int64_t)q * nr] * (double)Z[r + (int64_t)pcol * nr];
-        double val = -acc + (pcol < nV ? sv[q + pcol * nV] : 0.0);
-        Sp[q + (int64_t)pcol * nP] = val;
+        const double acc = wave_dot(X + (int64_t)q * nr, Z + (int64_t)pcol * nr, nr, lane);
+        if (lane == 0) Sp[q + (int64_t)pcol * nP] = -acc + (pcol < nV ? sv[q + pcol * nV] : 0.0);
     }
     for (int idx = tid; idx < nc * nP; idx += kWG) {
         const int e = idx % nc, pcol = idx / nc;
