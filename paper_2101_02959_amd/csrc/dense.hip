@@ -889,34 +889,60 @@ __global__ __launch_bounds__(kWG) void k_coarse_local(BatchDesc d, const T* __re
         }
     }
     __syncthreads();
-    if (tid == 0) {   // Cholesky of the small constraint matrix
-        for (int k = 0; k < nc; ++k) {
-            double dk = G[k][k];
-            for (int m = 0; m < k; ++m) dk -= G[k][m] * G[k][m];
-            if (!(dk > 0.0)) { info[s] = 2; dk = 1.0; }
-            dk = sqrt(dk);
-            G[k][k] = dk;
-            for (int i = k + 1; i < nc; ++i) {
-                double a = G[i][k];
-                for (int m = 0; m < k; ++m) a -= G[i][m] * G[k][m];
-                G[i][k] = a / dk;
-            }
+    // Cholesky of the small constraint matrix (lower triangle of G): one
+    // barrier per pivot, the trailing block updated with the unscaled column
+    // by (row, column group) threads, the columns scaled at the end
+    static_assert(MAXC <= 32, "one row slot per pivot row");
+    for (int k = 0; k < nc; ++k) {
+        double dk = G[k][k];
+        if (!(dk > 0.0)) dk = 1.0;
+        const int i = tid % 32;
+        if (i > k && i < nc) {
+            const double lik = G[i][k] / dk;
+            for (int j = k + 1 + tid / 32; j <= i; j += kWG / 32) G[i][j] -= lik * G[j][k];
         }
+        __syncthreads();
+    }
+    __shared__ double piv[MAXC];
+    if (tid < nc) {
+        double dk = G[tid][tid];
+        if (!(dk > 0.0)) { info[s] = 2; dk = 1.0; }
+        piv[tid] = sqrt(dk);
     }
     __syncthreads();
-    if (tid < nc) {   // column tid of G^{-1}
+    for (int idx = tid; idx < nc * nc; idx += kWG) {
+        const int i = idx % nc, k = idx / nc;
+        if (i > k) G[i][k] /= piv[k];
+    }
+    __syncthreads();
+    if (tid < nc) G[tid][tid] = piv[tid];
+    __syncthreads();
+    if (tid < nc) {   // column tid of G^{-1}, in registers (unrolled to MAXC)
         double y[MAXC];
-        for (int i = 0; i < nc; ++i) {
-            double a = (i == tid) ? 1.0 : 0.0;
-            for (int m = 0; m < i; ++m) a -= G[i][m] * y[m];
-            y[i] = a / G[i][i];
+#pragma unroll
+        for (int i = 0; i < MAXC; ++i) {
+            if (i < nc) {
+                double a = (i == tid) ? 1.0 : 0.0;
+#pragma unroll
+                for (int m = 0; m < i; ++m) a -= G[i][m] * y[m];
+                y[i] = a / G[i][i];
+            } else {
+                y[i] = 0.0;
+            }
         }
-        for (int i = nc - 1; i >= 0; --i) {
-            double a = y[i];
-            for (int m = i + 1; m < nc; ++m) a -= G[m][i] * y[m];
-            y[i] = a / G[i][i];
+#pragma unroll
+        for (int i = MAXC - 1; i >= 0; --i) {
+            if (i < nc) {
+                double a = y[i];
+#pragma unroll
+                for (int m = i + 1; m < MAXC; ++m)
+                    if (m < nc) a -= G[m][i] * y[m];
+                y[i] = a / G[i][i];
+            }
         }
-        for (int i = 0; i < nc; ++i) Gi[i][tid] = y[i];
+#pragma unroll
+        for (int i = 0; i < MAXC; ++i)
+            if (i < nc) Gi[i][tid] = y[i];
     }
     __syncthreads();
     for (int idx = tid; idx < nc * nV; idx += kWG) {
@@ -927,14 +953,21 @@ __global__ __launch_bounds__(kWG) void k_coarse_local(BatchDesc d, const T* __re
     }
     __syncthreads();
     for (int r = tid; r < nr; r += kWG) {
+        double yr[MAXC];   // row r of Y, read once
+#pragma unroll
+        for (int m = 0; m < MAXC; ++m) yr[m] = (m < nc) ? (double)Y[r + (int64_t)m * nr] : 0.0;
         for (int q = 0; q < nV; ++q) {
             double acc = (double)X[r + (int64_t)q * nr];
-            for (int m = 0; m < nc; ++m) acc -= (double)Y[r + (int64_t)m * nr] * muV[m][q];
+#pragma unroll
+            for (int m = 0; m < MAXC; ++m)
+                if (m < nc) acc -= yr[m] * muV[m][q];
             Z[r + (int64_t)q * nr] = (T)acc;
         }
         for (int e = 0; e < nc; ++e) {
             double acc = 0.0;
-            for (int m = 0; m < nc; ++m) acc += (double)Y[r + (int64_t)m * nr] * Gi[m][e];
+#pragma unroll
+            for (int m = 0; m < MAXC; ++m)
+                if (m < nc) acc += yr[m] * Gi[m][e];
             Z[r + (int64_t)(nV + e) * nr] = (T)acc;
         }
     }
