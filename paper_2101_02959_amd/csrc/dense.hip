@@ -715,29 +715,10 @@ __device__ __forceinline__ void load_prow(const T* __restrict__ p, T (&v)[NB]) {
 
 // Copy the lower triangles of the Dirichlet factor L_II and the Neumann
 // factor L_rr out of the chunk workspace into their panel-packed storage.
-// Each 64-row slab of a column block goes through LDS: read down the columns
-// (coalesced in the workspace), written along the packed rows.
+// One workgroup per (matrix, column block of either factor); each 64-row
+// slab of the block goes through LDS: read down the columns (coalesced in
+// the workspace), written along the packed rows (contiguous).
 static_assert(NB == PP_NB, "the packed factor blocks are the solve blocks");
-template <typename T>
-__device__ void pack_lower(const T* __restrict__ A, int64_t ld, int n, T* __restrict__ P, T (*tile)[NB + 1]) {
-    const int tid = threadIdx.x;
-    for (int j0 = 0, b = 0; j0 < n; j0 += NB, ++b) {
-        T* Pb = P + pp_block(n, b);
-        for (int r0 = j0; r0 < n; r0 += 64) {
-            for (int idx = tid; idx < 64 * NB; idx += kWG) {
-                const int rr = idx % 64, c = idx / 64, r = r0 + rr, col = j0 + c;
-                tile[rr][c] = (r < n && col < n && col <= r) ? A[r + (int64_t)col * ld] : (T)0;
-            }
-            __syncthreads();
-            for (int idx = tid; idx < 64 * NB; idx += kWG) {
-                const int rr = idx / NB, c = idx % NB, r = r0 + rr;
-                if (r < n) Pb[(int64_t)(r - j0) * NB + c] = tile[rr][c];
-            }
-            __syncthreads();
-        }
-    }
-}
-
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_copy_out(BatchDesc d, const T* __restrict__ K, T* __restrict__ LII,
                                                  const int64_t* __restrict__ LIIoff, T* __restrict__ Lrr,
@@ -746,9 +727,35 @@ __global__ __launch_bounds__(kWG) void k_copy_out(BatchDesc d, const T* __restri
     const int s = d.sub0 + blockIdx.x;
     const int64_t ld = d.n[s];
     const int nI = d.nI[s], nr = d.nr[s];
+    const int nbI = (nI + NB - 1) / NB, nbr = (nr + NB - 1) / NB;
+    int b = blockIdx.y, n;
     const T* A = K + d.K_off[s];
-    pack_lower(A, ld, nI, LII + LIIoff[s], tile);
-    pack_lower(A + (int64_t)nI * (ld + 1), ld, nr, Lrr + Lrroff[s], tile);
+    T* P;
+    if (b < nbI) {
+        n = nI;
+        P = LII + LIIoff[s];
+    } else if (b < nbI + nbr) {
+        b -= nbI;
+        n = nr;
+        A += (int64_t)nI * (ld + 1);
+        P = Lrr + Lrroff[s];
+    } else {
+        return;
+    }
+    const int tid = threadIdx.x, j0 = b * NB;
+    T* Pb = P + pp_block(n, b);
+    for (int r0 = j0; r0 < n; r0 += 64) {
+        for (int idx = tid; idx < 64 * NB; idx += kWG) {
+            const int rr = idx % 64, c = idx / 64, r = r0 + rr, col = j0 + c;
+            tile[rr][c] = (r < n && col < n && col <= r) ? A[r + (int64_t)col * ld] : (T)0;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < 64 * NB; idx += kWG) {
+            const int rr = idx / NB, c = idx % NB, r = r0 + rr;
+            if (r < n) Pb[(int64_t)(r - j0) * NB + c] = tile[rr][c];
+        }
+        __syncthreads();
+    }
 }
 
 // Zero the lower triangle (diagonal included) of every local matrix of a
@@ -756,14 +763,26 @@ __global__ __launch_bounds__(kWG) void k_copy_out(BatchDesc d, const T* __restri
 // and write lower-triangle entries only.  Grid: (column blocks of CL_COLS,
 // matrices).
 constexpr int CL_COLS = 16;
+// Each column segment [j, n) is written with 16-byte stores over its
+// 16-byte aligned middle and single stores at the two ends.
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_clear_lower(BatchDesc d, T* __restrict__ K) {
+    constexpr int V = 16 / (int)sizeof(T);
     const int s = d.sub0 + blockIdx.y;
     const int n = d.n[s];
     T* A = K + d.K_off[s];
+    const int tid = threadIdx.x;
     const int j1 = min(n, ((int)blockIdx.x + 1) * CL_COLS);
-    for (int j = blockIdx.x * CL_COLS; j < j1; ++j)
-        for (int i = j + (int)threadIdx.x; i < n; i += kWG) A[i + (int64_t)j * n] = (T)0;
+    for (int j = blockIdx.x * CL_COLS; j < j1; ++j) {
+        T* c = A + (int64_t)j * n;
+        const int head = (int)(((16 - ((uintptr_t)(c + j) & 15)) & 15) / sizeof(T));   // entries to the next 16-byte boundary
+        const int a0 = min(j + head, n);            // first entry of the aligned middle
+        const int nv = (n - a0) / V;                // 16-byte groups in it
+        if (tid < a0 - j) c[j + tid] = (T)0;
+        for (int q = tid; q < nv; q += kWG) reinterpret_cast<float4*>(c + a0)[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int t0 = a0 + nv * V;
+        if (tid < n - t0) c[t0 + tid] = (T)0;
+    }
 }
 
 // ----------------------------------------------------- multi-RHS forward
@@ -1518,9 +1537,11 @@ void launch_clear_lower(hipStream_t s, const BatchDesc& d, int maxn, T* K) {
                        dim3(kWG), 0, s, d, K);
 }
 template <typename T>
-void launch_copy_out(hipStream_t s, const BatchDesc& d, int nb, const T* K, T* LII, const int64_t* LIIoff, T* Lrr,
-                     const int64_t* Lrroff) {
-    hipLaunchKernelGGL(k_copy_out<T>, dim3(nb), dim3(kWG), 0, s, d, K, LII, LIIoff, Lrr, Lrroff);
+void launch_copy_out(hipStream_t s, const BatchDesc& d, int nb, int maxnI, int maxnr, const T* K, T* LII,
+                     const int64_t* LIIoff, T* Lrr, const int64_t* Lrroff) {
+    const int nblk = (maxnI + NB - 1) / NB + (maxnr + NB - 1) / NB;
+    if (nb <= 0 || nblk <= 0) return;
+    hipLaunchKernelGGL(k_copy_out<T>, dim3(nb, nblk), dim3(kWG), 0, s, d, K, LII, LIIoff, Lrr, Lrroff);
 }
 template <typename T>
 void launch_trsm_fwd(hipStream_t s, int nb, const T* L, const int64_t* Loff, const int* n, T* B,
@@ -1588,7 +1609,8 @@ int deluxe_max_object() { return DLX_MAXN; }
                                         const int*, bool, int, int, int);                                \
     template void launch_extract<T>(hipStream_t, const BatchDesc&, const T*, T*, T*, double*, T*);      \
     template void launch_clear_lower<T>(hipStream_t, const BatchDesc&, int, T*);                       \
-    template void launch_copy_out<T>(hipStream_t, const BatchDesc&, int, const T*, T*, const int64_t*, T*,    \
+    template void launch_copy_out<T>(hipStream_t, const BatchDesc&, int, int, int, const T*, T*,          \
+                                     const int64_t*, T*,                                                 \
                                      const int64_t*);                                                    \
     template void launch_trsm_fwd<T>(hipStream_t, int, const T*, const int64_t*, const int*, T*,         \
                                      const int64_t*, const int*, const int*);                            \

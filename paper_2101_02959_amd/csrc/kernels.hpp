@@ -105,8 +105,8 @@ __host__ __device__ inline int64_t pp_size(int n) { return pp_block(n, (n + PP_N
 // Copy the factors L_II and L_rr out of the chunk workspace into their
 // panel-packed storage.
 template <typename T>
-void launch_copy_out(hipStream_t s, const BatchDesc& d, int nb, const T* K, T* LII, const int64_t* LIIoff, T* Lrr,
-                     const int64_t* Lrroff);
+void launch_copy_out(hipStream_t s, const BatchDesc& d, int nb, int maxnI, int maxnr, const T* K, T* LII,
+                     const int64_t* LIIoff, T* Lrr, const int64_t* Lrroff);
 // Multi-right-hand-side forward solve L X = B with panel-packed L.
 template <typename T>
 void launch_trsm_fwd(hipStream_t s, int nb, const T* L, const int64_t* Loff, const int* n,

@@ -786,7 +786,7 @@ int Context::linearize_t() {
         launch_extract<T>(stream_, cd, K, (T*)slots_, (T*)F_, Svv_, (T*)Srr_);
         // constrained Neumann factor L_rr of S_rr (the leading r-block of S_Gamma)
         eliminate<T>(K, s0, cnt, plan_rr_, nullptr);
-        launch_copy_out<T>(stream_, cd, cnt, K, (T*)LIIs_, LII_off_, (T*)Lrrs_, Lrr_off_);
+        launch_copy_out<T>(stream_, cd, cnt, maxnI_, maxnr_, K, (T*)LIIs_, LII_off_, (T*)Lrrs_, Lrr_off_);
     }
     launch_trsm_fwd<T>(stream_, nsub, (const T*)Lrrs_, Lrr_off_, nr_, (T*)F_, bd_.F_off, nr_, kF_);
     launch_coarse_local<T>(stream_, bd_, (const T*)F_, Svv_, (T*)Z_, (T*)Gi_, Sp_, info_sub_);
