@@ -101,6 +101,9 @@ Context::~Context() {
     for (auto& g : kry_exec_)
         if (g) hipGraphExecDestroy(g);
     if (kry_stream_) hipStreamDestroy(kry_stream_);
+    if (side_stream_) hipStreamDestroy(side_stream_);
+    if (ev_fork_) hipEventDestroy(ev_fork_);
+    if (ev_join_) hipEventDestroy(ev_join_);
     for (void* p : allocs_) hipFree(p);
 }
 
@@ -788,14 +791,27 @@ int Context::linearize_t() {
         eliminate<T>(K, s0, cnt, plan_rr_, nullptr);
         launch_copy_out<T>(stream_, cd, cnt, maxnI_, maxnr_, K, (T*)LIIs_, LII_off_, (T*)Lrrs_, Lrr_off_);
     }
+    // The deluxe factors need only the extracted blocks: they run on the side
+    // stream while the coarse chain (whose upper tree levels leave most of
+    // the device idle) runs here; the two join before the status read-back.
+    if (!side_stream_) {
+        HIPOK(hipStreamCreateWithFlags(&side_stream_, hipStreamNonBlocking));
+        HIPOK(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming));
+        HIPOK(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming));
+    }
+    HIPOK(hipEventRecord(ev_fork_, stream_));
+    HIPOK(hipStreamWaitEvent(side_stream_, ev_fork_, 0));
+    // faces and edges separately: each launch reserves LDS for its own largest object
+    launch_deluxe_setup<T>(side_stream_, od_, 0, nface_obj_, maxface_n_, (const T*)slots_, (T*)fac_, (T*)dmat_,
+                           info_obj_);
+    launch_deluxe_setup<T>(side_stream_, od_, nface_obj_, od_.nobj - nface_obj_, maxedge_n_, (const T*)slots_,
+                           (T*)fac_, (T*)dmat_, info_obj_);
+    launch_deluxe_transpose<T>(side_stream_, od_, (const T*)dmat_, (T*)dmatT_);
+    HIPOK(hipEventRecord(ev_join_, side_stream_));
     launch_trsm_fwd<T>(stream_, nsub, (const T*)Lrrs_, Lrr_off_, nr_, (T*)F_, bd_.F_off, nr_, kF_);
     launch_coarse_local<T>(stream_, bd_, (const T*)F_, Svv_, (T*)Z_, (T*)Gi_, Sp_, info_sub_);
-    // faces and edges separately: each launch reserves LDS for its own largest object
-    launch_deluxe_setup<T>(stream_, od_, 0, nface_obj_, maxface_n_, (const T*)slots_, (T*)fac_, (T*)dmat_, info_obj_);
-    launch_deluxe_setup<T>(stream_, od_, nface_obj_, od_.nobj - nface_obj_, maxedge_n_, (const T*)slots_, (T*)fac_,
-                           (T*)dmat_, info_obj_);
-    launch_deluxe_transpose<T>(stream_, od_, (const T*)dmat_, (T*)dmatT_);
     coarse_.factor(stream_, color_list_, color_ptr_, nP_, Sp_, SP_STRIDE);
+    HIPOK(hipStreamWaitEvent(stream_, ev_join_, 0));
     int hb = 0, hc = 0;
     std::vector<int> hs(nsub), ho(od_.nobj);
     HIPOK(hipMemcpyAsync(&hb, bad_, sizeof(int), hipMemcpyDeviceToHost, stream_));

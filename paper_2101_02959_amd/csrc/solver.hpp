@@ -171,6 +171,10 @@ class Context {
     int* qctr_ = nullptr;
     WorkQueue qI_, qr_;
     hipStream_t kry_stream_ = nullptr;
+    // side stream of the setup: the deluxe factors run on it concurrently
+    // with the coarse chain (forward solves, local products, factorization)
+    hipStream_t side_stream_ = nullptr;
+    hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;
 };
 
 void set_error(const std::string& msg);
