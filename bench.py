@@ -65,11 +65,11 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_path(P, wl, precision, guess, warmup, steps, predictor=None):
+def run_path(P, wl, precision, guess, warmup, steps, predictor=None, krylov_graph=False):
     import torch
     N = wl.mesh.nnodes
     from workload import initial_state, stimulus_nodal
-    S = P.Solver(wl.mesh, wl.physics, wl.solver, precision=precision, guess=guess)
+    S = P.Solver(wl.mesh, wl.physics, wl.solver, precision=precision, guess=guess, krylov_graph=krylov_graph)
     if predictor is not None:
         S.bdm_predictor_set(*predictor)
     v0, ue0, w0 = initial_state(wl.mesh, wl.physics, wl.perturb_seed)
@@ -187,6 +187,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="slab256")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--krylov-graph", action="store_true",
+                    help="replay each PCG iteration as captured HIP graphs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is designed, not built"}))
@@ -198,7 +200,8 @@ def main():
     dofs = 2 * wl.mesh.nnodes
     log(f"workload {args.workload}: {dofs} dofs, {wl.mesh.nsub} subdomains")
     log("plain FP64 path")
-    S64, plain, st64 = run_path(P, wl, P.BDM_PREC_FP64, P.BDM_GUESS_PREV, args.warmup, args.steps)
+    S64, plain, st64 = run_path(P, wl, P.BDM_PREC_FP64, P.BDM_GUESS_PREV, args.warmup, args.steps,
+                                krylov_graph=args.krylov_graph)
     roof64 = kernel_rooflines(P, S64, "f64", args.workload)
     tune64 = S64.bdm_tune_report()["entries"]
     st64 = tuple(t.cpu() if hasattr(t, "cpu") else t for t in st64)
@@ -207,7 +210,7 @@ def main():
     log("mixed FP32-local path, learned Newton guess judged against extrapolation")
     from paper_2101_02959_amd import predictor as PR
     S32, mixed, st32 = run_path(P, wl, P.BDM_PREC_MIXED, P.BDM_GUESS_CNN, args.warmup, args.steps,
-                                predictor=PR.load())
+                                predictor=PR.load(), krylov_graph=args.krylov_graph)
     roof32 = kernel_rooflines(P, S32, "f32", args.workload)
     tune32 = S32.bdm_tune_report()["entries"]
     st32 = tuple(t.cpu() if hasattr(t, "cpu") else t for t in st32)
