@@ -1,0 +1,148 @@
+"""Checks at the benchmark size (the 256 x 256 x 128 slab, 17,040,642 dofs,
+32 x 32 x 16 subdomains), in the configuration bench.py times (FP32 local
+factors, FP64 outer iteration).
+
+The oracle cannot assemble the full problem in seconds, so:
+  * residual and Jacobian rows are sampled and computed by the oracle one
+    node at a time: the operator is translation invariant in x and y (the
+    fibre angle depends on z only, Sec. 6), so the row of node (i, j, k)
+    equals the row of the matching node of a 4 x 4 x nz slab with the same
+    h and height (interior, face or edge in x and y), with the node's
+    3 x 3 x 3 neighbourhood of the state copied there;
+  * the preconditioner is checked by properties that hold at any size:
+    symmetry and positivity of M on the range of J;
+  * one time step must converge, each Newton linear solve to the Krylov
+    tolerance in the FP64 residual of the full system.
+"""
+import numpy as np
+import pytest
+
+from oracle import bidomain, newton
+from workload import Mesh, initial_state, stimulus_nodal, workload
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+W = workload("slab256")
+M = W.mesh
+NX1, NY1, NZ1 = M.nx + 1, M.ny + 1, M.nz + 1
+N = NX1 * NY1 * NZ1
+PATCH = Mesh(4, 4, M.nz, M.h, (0, 4), (0, 4), (0, M.nz))
+PN = 5 * 5 * NZ1
+
+
+def _samples():
+    """Corners, edges and faces in x and y, interior nodes next to the
+    boundary and deep inside, at the bottom, one level up, mid-height and
+    the top."""
+    return [(i, j, k) for k in (0, 1, M.nz // 2, M.nz)
+            for i, j in ((0, 0), (M.nx, M.ny), (0, 97), (131, M.ny), (1, 1), (M.nx - 1, 200), (77, 154))]
+
+
+def _patch_index(i, n):
+    return 0 if i == 0 else (4 if i == n else 2)
+
+
+def _copy_neigh(fields_big, i, j, k):
+    """Patch arrays holding the big fields on the 3x3x3 neighbourhood of
+    (i, j, k), placed around the matching patch node (zeros elsewhere)."""
+    ip, jp = _patch_index(i, M.nx), _patch_index(j, M.ny)
+    out = [np.zeros(PN) for _ in fields_big]
+    for dz in (-1, 0, 1):
+        kk = k + dz
+        if kk < 0 or kk > M.nz:
+            continue
+        for dy in (-1, 0, 1):
+            jj, jq = j + dy, jp + dy
+            if jj < 0 or jj > M.ny or jq < 0 or jq > 4:
+                continue
+            for dx in (-1, 0, 1):
+                ii, iq = i + dx, ip + dx
+                if ii < 0 or ii > M.nx or iq < 0 or iq > 4:
+                    continue
+                nb = ii + NX1 * (jj + NY1 * kk)
+                npch = iq + 5 * (jq + 5 * kk)
+                for o, f in zip(out, fields_big):
+                    o[npch] = f[nb]
+    return out, ip + 5 * (jp + 5 * k)
+
+
+@pytest.fixture(scope="module")
+def big():
+    import paper_2101_02959_amd as P
+    S = P.Solver(M, W.physics, W.solver, precision=P.BDM_PREC_MIXED)
+    yield P, S
+    S.close()
+
+
+def test_residual_and_jacobian_rows(big):
+    P, S = big
+    rng = np.random.default_rng(21)
+    v0, ue0, w0 = initial_state(M, W.physics, 3)
+    vn = v0 + rng.uniform(-2, 2, N)
+    v = vn + rng.uniform(-3, 3, N)
+    ue = ue0 + rng.uniform(-1, 1, N)
+    w = np.clip(w0 + rng.uniform(0, 0.05, N), 0, None)
+    Is = stimulus_nodal(M, W.stim_block, W.stim_amplitude)
+    S.bdm_set_state(vn, np.zeros(N), w)
+    S.bdm_set_stimulus(Is, 0, 1)
+    R = S.bdm_residual(v, ue).cpu().numpy()
+    S.bdm_linearize(v, w)
+    x = rng.standard_normal(2 * N)
+    y = S.bdm_jacobian_apply(x).cpu().numpy()
+    ueg = ue - ue.mean()
+    patch = bidomain.Problem(PATCH, W.physics, W.solver.dt)
+    for (i, j, k) in _samples():
+        n = i + NX1 * (j + NY1 * k)
+        (pv, pue, pvn, pw, pIs, pxv, pxe), npch = _copy_neigh((v, ueg, vn, w, Is, x[:N], x[N:]), i, j, k)
+        # Jacobian rows: the reaction part of row n depends on (v_n, w_n) only
+        J = patch.jacobian(np.full(PN, v[n]), np.full(PN, w[n])).tocsr()
+        # residual rows (local: the node's neighbourhood of v, u_e and its own
+        # v_n, w, I_s); tolerance relative to the size of the row's terms
+        Rp = patch.residual(pv, pue, pvn, pw, pIs)
+        rscale = abs(J) @ np.abs(np.concatenate([pv, pue]))
+        for blk in (0, 1):
+            r = blk * PN + npch
+            assert abs(R[blk * N + n] - Rp[r]) <= 1e-10 * (rscale[r] + abs(Rp[r])), \
+                (i, j, k, blk, R[blk * N + n], Rp[r])
+        xp = np.concatenate([pxv, pxe])
+        ref = J @ xp
+        scale = abs(J) @ np.abs(xp)
+        for blk in (0, 1):
+            r = blk * PN + npch
+            assert abs(y[blk * N + n] - ref[r]) <= 1e-11 * scale[r], (i, j, k, blk, y[blk * N + n], ref[r])
+
+
+def test_preconditioner_symmetric_positive(big):
+    P, S = big
+    v0, ue0, w0 = initial_state(M, W.physics, 5)
+    S.bdm_linearize(v0, w0)
+    rng = np.random.default_rng(7)
+    r1, r2 = (newton.project_range(rng.standard_normal(2 * N), N) for _ in range(2))
+    z1 = S.bdm_bddc_apply(r1).cpu().numpy()
+    z2 = S.bdm_bddc_apply(r2).cpu().numpy()
+    z1, z2 = newton.project_range(z1, N), newton.project_range(z2, N)
+    a, b = float(z1 @ r2), float(r1 @ z2)
+    norm = np.sqrt(float(z1 @ r1) * float(z2 @ r2))
+    assert float(z1 @ r1) > 0 and float(z2 @ r2) > 0
+    # FP32 local factors: symmetric to the FP32 round-off of the local solves
+    # (a single application is within 5e-5 of the FP64 oracle on small meshes)
+    assert abs(a - b) <= 2e-4 * norm, (a, b, norm)
+
+
+def test_time_step_converges(big):
+    P, S = big
+    v0, ue0, w0 = initial_state(M, W.physics, W.perturb_seed)
+    S.bdm_set_state(v0, ue0, w0)
+    S.bdm_set_stimulus(stimulus_nodal(M, W.stim_block, W.stim_amplitude), 0, W.stim_steps)
+    st = S.bdm_step(1)
+    nit = st.newton_its
+    assert 1 <= nit <= W.solver.newton_maxit
+    res = list(st.res_hist)[:nit + 1]
+    assert res[-1] <= W.solver.newton_rtol * res[0] * 10, res
+    for q in range(nit):
+        assert 0 < st.krylov_its[q] < W.solver.krylov_maxit
+        assert st.krylov_true_res[q] <= 10 * W.solver.krylov_rtol, (q, st.krylov_true_res[q])
+    v, ue, w, _ = S.bdm_get_state()
+    assert torch.isfinite(v).all() and torch.isfinite(ue).all()
