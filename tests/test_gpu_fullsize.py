@@ -10,7 +10,8 @@ The oracle cannot assemble the full problem in seconds, so:
     h and height (interior, face or edge in x and y), with the node's
     3 x 3 x 3 neighbourhood of the state copied there;
   * the preconditioner is checked by properties that hold at any size:
-    symmetry and positivity of M on the range of J;
+    symmetry and positivity of M on the range of J, and a residual r - J M r
+    that vanishes on the subdomain-interior dofs;
   * one time step must converge, each Newton linear solve to the Krylov
     tolerance in the FP64 residual of the full system.
 """
@@ -129,6 +130,28 @@ def test_preconditioner_symmetric_positive(big):
     # FP32 local factors: symmetric to the FP32 round-off of the local solves
     # (a single application is within 5e-5 of the FP64 oracle on small meshes)
     assert abs(a - b) <= 2e-4 * norm, (a, b, norm)
+
+
+def test_preconditioner_leaves_no_interior_residual(big):
+    """The last step of the BDDC application is the interior correction
+    z_I += K_II^{-1} (r - K z)_I in every subdomain (Sec. 4.1), so r - J z
+    vanishes on the subdomain-interior dofs up to the round-off of the FP32
+    local solves, while it stays of the order of r on the interface."""
+    P, S = big
+    v0, ue0, w0 = initial_state(M, W.physics, 6)
+    S.bdm_linearize(v0, w0)
+    r = newton.project_range(np.random.default_rng(8).standard_normal(2 * N), N)
+    z = S.bdm_bddc_apply(r).cpu().numpy()
+    t = r - S.bdm_jacobian_apply(z).cpu().numpy()
+    i = np.arange(NX1)
+    on_cut = lambda idx, cuts: np.isin(idx, np.asarray(cuts[1:-1]))
+    gx, gy, gz = on_cut(i, M.cuts_x), on_cut(np.arange(NY1), M.cuts_y), on_cut(np.arange(NZ1), M.cuts_z)
+    iface = (gx[None, None, :] | gy[None, :, None] | gz[:, None, None]).ravel()   # node order x fastest
+    interior = np.concatenate([~iface, ~iface])
+    ri, ti = np.linalg.norm(r[interior]), np.linalg.norm(t[interior])
+    rg, tg = np.linalg.norm(r[~interior]), np.linalg.norm(t[~interior])
+    assert ti <= 1e-3 * ri, (ti, ri)
+    assert tg >= 1e-2 * rg, (tg, rg)
 
 
 def test_time_step_converges(big):
