@@ -192,7 +192,12 @@ int bdm_fetidp_apply(bdm_ctx* ctx, int op, const double* in, double* out);
 
 /* Advance nsteps time steps: Step 1 then Newton (line search on ||R||^2,
  * Armijo alpha = 1e-4) with PCG preconditioned by BDDC, or FETI-DP PCG on
- * the multipliers plus recovery, per opts.solver.  stats may be NULL. */
+ * the multipliers plus recovery, per opts.solver.  stats may be NULL.
+ * BDM_E_ARG for FETI-DP with FP32 local factors: the multiplier operator
+ * B S~^{-1} B^T contains the local solves, and their FP32 round-off makes it
+ * indefinite at scale (PCG breaks down); BDDC keeps the FP64 Jacobian as
+ * its operator and takes FP32 factors in the preconditioner only.  The
+ * FETI-DP operators themselves (bdm_fetidp_apply) work in either precision. */
 int bdm_step(bdm_ctx* ctx, int nsteps, bdm_step_stats* stats);
 
 /* Learned Newton initial guess (an addition to the paper's method: it only

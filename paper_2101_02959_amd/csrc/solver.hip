@@ -1315,6 +1315,12 @@ int Context::predictor_train(const double* samples, int nsamples, const int* ord
 int Context::step(int nsteps, bdm_step_stats* st) {
     using clk = std::chrono::steady_clock;
     const size_t vb = (size_t)N * sizeof(double);
+    if (opts.solver == BDM_SOLVER_FETIDP && prec_) {
+        // the multiplier operator holds the local solves: with FP32 factors it
+        // loses definiteness (negative Lanczos estimates, PCG breakdown)
+        set_error("FETI-DP Newton solves need FP64 local factors (precision BDM_PREC_FP64)");
+        return BDM_E_ARG;
+    }
     for (int ks = 0; ks < nsteps; ++ks) {
         bdm_step_stats S{};
         S.bad_subdomain = -1;

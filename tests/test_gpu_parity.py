@@ -154,6 +154,22 @@ def test_time_steps_match_direct_newton(method, prec):
         v, ue, w = vg, ueg, wg
 
 
+def test_fetidp_step_needs_fp64_local_factors():
+    """FETI-DP's multiplier operator contains the local solves; with FP32
+    factors it loses definiteness at scale, so a Newton step is refused
+    (the operators themselves are checked in FP32 above)."""
+    P = _solver_mod()
+    wl = workload("slab8_supra")
+    S = P.Solver(wl.mesh, wl.physics, wl.solver, precision=P.BDM_PREC_MIXED, method=P.BDM_SOLVER_FETIDP)
+    try:
+        N = wl.mesh.nnodes
+        S.bdm_set_state(np.zeros(N), np.zeros(N), np.zeros(N))
+        with pytest.raises(P.BidomainError, match="BDM_E_ARG"):
+            S.bdm_step(1)
+    finally:
+        S.close()
+
+
 def test_bddc_chunked_setup(lin, monkeypatch):
     """Setup in chunks of a few subdomains gives the same operator."""
     P = _solver_mod()
