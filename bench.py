@@ -65,11 +65,12 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_path(P, wl, precision, guess, warmup, steps, predictor=None, krylov_graph=False):
+def run_path(P, wl, precision, guess, warmup, steps, predictor=None, krylov_graph=False, krylov_reduced=True):
     import torch
     N = wl.mesh.nnodes
     from workload import initial_state, stimulus_nodal
-    S = P.Solver(wl.mesh, wl.physics, wl.solver, precision=precision, guess=guess, krylov_graph=krylov_graph)
+    S = P.Solver(wl.mesh, wl.physics, wl.solver, precision=precision, guess=guess, krylov_graph=krylov_graph,
+                 krylov_reduced=krylov_reduced)
     if predictor is not None:
         S.bdm_predictor_set(*predictor)
     v0, ue0, w0 = initial_state(wl.mesh, wl.physics, wl.perturb_seed)
@@ -189,6 +190,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--krylov-graph", action="store_true",
                     help="replay each PCG iteration as captured HIP graphs")
+    ap.add_argument("--krylov-full", action="store_true",
+                    help="PCG on the full Newton system from zero (no interior reduction)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is designed, not built"}))
@@ -201,7 +204,7 @@ def main():
     log(f"workload {args.workload}: {dofs} dofs, {wl.mesh.nsub} subdomains")
     log("plain FP64 path")
     S64, plain, st64 = run_path(P, wl, P.BDM_PREC_FP64, P.BDM_GUESS_PREV, args.warmup, args.steps,
-                                krylov_graph=args.krylov_graph)
+                                krylov_graph=args.krylov_graph, krylov_reduced=not args.krylov_full)
     roof64 = kernel_rooflines(P, S64, "f64", args.workload)
     tune64 = S64.bdm_tune_report()["entries"]
     st64 = tuple(t.cpu() if hasattr(t, "cpu") else t for t in st64)
@@ -210,7 +213,8 @@ def main():
     log("mixed FP32-local path, learned Newton guess judged against extrapolation")
     from paper_2101_02959_amd import predictor as PR
     S32, mixed, st32 = run_path(P, wl, P.BDM_PREC_MIXED, P.BDM_GUESS_CNN, args.warmup, args.steps,
-                                predictor=PR.load(), krylov_graph=args.krylov_graph)
+                                predictor=PR.load(), krylov_graph=args.krylov_graph,
+                                krylov_reduced=not args.krylov_full)
     roof32 = kernel_rooflines(P, S32, "f32", args.workload)
     tune32 = S32.bdm_tune_report()["entries"]
     st32 = tuple(t.cpu() if hasattr(t, "cpu") else t for t in st32)

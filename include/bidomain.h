@@ -90,8 +90,10 @@ typedef struct bdm_opts {
     double newton_rtol;         /* stop: ||R(u^k)|| <= rtol ||R(u^n)||       */
     double newton_atol;         /*   or  ||R(u^k)|| <= atol                  */
     int newton_maxit;
-    double krylov_rtol;         /* ||r_k||_2 <= rtol ||r_0||_2               */
-    double krylov_dtol;         /* divergence when ||r_k|| > dtol ||r_0||    */
+    double krylov_rtol;         /* ||r_k||_2 <= rtol ||b||_2, b the Newton   */
+                                /* right-hand side (BDDC), or the multiplier */
+                                /* system's right-hand side (FETI-DP)        */
+    double krylov_dtol;         /* divergence when ||r_k|| > dtol ||b||      */
     int krylov_maxit;
     int solver;                 /* BDM_SOLVER_*                              */
     int precision;              /* BDM_PREC_*: local factors in FP64 or FP32 */
@@ -102,6 +104,15 @@ typedef struct bdm_opts {
                                 /* device scalars, same arithmetic and       */
                                 /* iterates; 0: host-driven loop             */
     int schedule;               /* BDM_SCHED_*                               */
+    int krylov_reduced;         /* BDDC only.  1: each Newton solve first    */
+                                /* solves the subdomain interiors of its     */
+                                /* right-hand side exactly (zero on the      */
+                                /* interface, Sec. 4.1), so every PCG        */
+                                /* residual vanishes on the interiors and    */
+                                /* the preconditioner skips its condensation */
+                                /* of r_I; the stopping test stays relative  */
+                                /* to ||b||.  0: PCG on J s = b from zero.   */
+                                /* Must be 0 or 1 (BDM_E_ARG otherwise).     */
 } bdm_opts;
 
 /* Per-step statistics filled by bdm_step (for its last step). */

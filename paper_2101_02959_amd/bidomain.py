@@ -60,7 +60,8 @@ class bdm_opts(C.Structure):
     _fields_ = [("dt", C.c_double), ("newton_rtol", C.c_double), ("newton_atol", C.c_double),
                 ("newton_maxit", C.c_int), ("krylov_rtol", C.c_double), ("krylov_dtol", C.c_double),
                 ("krylov_maxit", C.c_int), ("solver", C.c_int), ("precision", C.c_int),
-                ("guess", C.c_int), ("krylov_graph", C.c_int), ("schedule", C.c_int)]
+                ("guess", C.c_int), ("krylov_graph", C.c_int), ("schedule", C.c_int),
+                ("krylov_reduced", C.c_int)]
 
 
 class bdm_step_stats(C.Structure):
@@ -127,7 +128,7 @@ def _ptr(t):
 
 
 def make_structs(mesh, physics, solver, precision=BDM_PREC_FP64, method=BDM_SOLVER_BDDC,
-                 guess=BDM_GUESS_PREV, krylov_graph=False, schedule=0):
+                 guess=BDM_GUESS_PREV, krylov_graph=False, schedule=0, krylov_reduced=True):
     """Build the C structs from workload descriptions (duck-typed)."""
     cx = (C.c_int * len(mesh.cuts_x))(*mesh.cuts_x)
     cy = (C.c_int * len(mesh.cuts_y))(*mesh.cuts_y)
@@ -139,7 +140,7 @@ def make_structs(mesh, physics, solver, precision=BDM_PREC_FP64, method=BDM_SOLV
                      physics.eta1, physics.eta2, physics.vth, physics.vp)
     op = bdm_opts(solver.dt, solver.newton_rtol, solver.newton_atol, solver.newton_maxit,
                   solver.krylov_rtol, solver.krylov_dtol, solver.krylov_maxit, method, precision,
-                  guess, int(bool(krylov_graph)), schedule)
+                  guess, int(bool(krylov_graph)), schedule, int(bool(krylov_reduced)))
     return m, ph, op, (cx, cy, cz)
 
 
@@ -147,12 +148,13 @@ class Solver:
     """One libbidomain context on the current torch CUDA device and stream."""
 
     def __init__(self, mesh, physics, solver, precision=BDM_PREC_FP64, method=BDM_SOLVER_BDDC,
-                 guess=BDM_GUESS_PREV, stream=None, krylov_graph=False, schedule=0):
+                 guess=BDM_GUESS_PREV, stream=None, krylov_graph=False, schedule=0, krylov_reduced=True):
         import torch
         self.torch = torch
         L = lib()
         self.m, self.ph, self.op, self._keep = make_structs(mesh, physics, solver, precision,
-                                                            method, guess, krylov_graph, schedule)
+                                                            method, guess, krylov_graph, schedule,
+                                                            krylov_reduced)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream

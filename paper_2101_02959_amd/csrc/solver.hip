@@ -140,7 +140,8 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
     opts = *o;
     phys = *ph;
     if (!(o->dt > 0) || o->newton_maxit < 1 || o->krylov_maxit < 1 ||
-        (o->schedule != BDM_SCHED_QUEUE && o->schedule != BDM_SCHED_GRID)) {
+        (o->schedule != BDM_SCHED_QUEUE && o->schedule != BDM_SCHED_GRID) ||
+        (o->krylov_reduced != 0 && o->krylov_reduced != 1)) {
         set_error("invalid options");
         return BDM_E_ARG;
     }
@@ -892,11 +893,17 @@ int Context::bddc_apply(const double* r, double* z) {
     return sync();
 }
 
+// interior_free: r vanishes on the subdomain interiors, so the condensation
+// r_G - K_GI K_II^{-1} r_I leaves r unchanged and is skipped.
 template <typename T>
-int Context::bddc_apply_t(const double* r, double* z) {
-    condense<T>(r, t2_);
-    launch_deluxe_res<T>(stream_, od_, N, t2_, (const T*)dmat_, (T*)xr_, xr_off_);
-    stilde_inv<T>((T*)xr_, t2_, cb_);
+int Context::bddc_apply_t(const double* r, double* z, bool interior_free) {
+    const double* g = r;
+    if (!interior_free) {
+        condense<T>(r, t2_);
+        g = t2_;
+    }
+    launch_deluxe_res<T>(stream_, od_, N, g, (const T*)dmat_, (T*)xr_, xr_off_);
+    stilde_inv<T>((T*)xr_, g, cb_);
     launch_fill(stream_, 2 * N, 0.0, t3_);
     launch_deluxe_val<T>(stream_, od_, N, (const T*)dmatT_, (const T*)xr_, xr_off_, t3_);
     launch_vertex_val(stream_, cd_.nverts, cd_.vnode, N, cb_, t3_);
@@ -966,7 +973,7 @@ int Context::fetidp_apply_t(int op, const double* in, double* out) {
 // state) stay on the device, neither half holds a host synchronisation or a
 // memset node, and the host reads the state back once per iteration.
 // Identical arithmetic, kernels and order to pcg().
-int Context::pcg_graph(int n, const double* b, double* x, bool feti, KrylovOut& out) {
+int Context::pcg_graph(int n, const double* b, double* x, bool feti, KrylovOut& out, bool reduced, double rref) {
     out = KrylovOut();
     const int maxit = opts.krylov_maxit;
     if (maxit > kry_hcap_) {
@@ -982,12 +989,13 @@ int Context::pcg_graph(int n, const double* b, double* x, bool feti, KrylovOut& 
         if (feti)
             return prec_ ? fetidp_apply_t<float>(BDM_FETI_PRECOND, in, o)
                          : fetidp_apply_t<double>(BDM_FETI_PRECOND, in, o);
-        return prec_ ? bddc_apply_t<float>(in, o) : bddc_apply_t<double>(in, o);
+        return prec_ ? bddc_apply_t<float>(in, o, reduced) : bddc_apply_t<double>(in, o, reduced);
     };
     // set-up, eager
     launch_fill(stream_, n, 0.0, x);
     launch_copy_kernel(stream_, n, b, kr_);
     const double r0 = std::sqrt(dot(n, kr_, kr_));
+    const double ref = rref > 0.0 ? rref : r0;
     out.hist.push_back(r0);
     if (r0 == 0.0) return 0;
     int rc = M(kr_, kz_);
@@ -998,15 +1006,15 @@ int Context::pcg_graph(int n, const double* b, double* x, bool feti, KrylovOut& 
         double init[PCG_NSLOT] = {0};
         init[PCG_STATE] = PCG_RUNNING;
         init[PCG_IT] = 0;
-        init[PCG_TOL] = opts.krylov_rtol * r0;
-        init[PCG_DTOL] = opts.krylov_dtol * r0;
+        init[PCG_TOL] = opts.krylov_rtol * ref;
+        init[PCG_DTOL] = opts.krylov_dtol * ref;
         // keep PCG_RZ (computed on the device above): copy the other slots only
         HIPOK(hipMemcpyAsync(kry_sc_ + PCG_PQ, init + PCG_PQ, (PCG_NSLOT - PCG_PQ) * sizeof(double),
                              hipMemcpyHostToDevice, stream_));
         HIPOK(hipStreamSynchronize(stream_));   // init lives on this host stack
     }
     // capture both halves once per (operator, size)
-    const int key = (feti ? 1 : 0) + 2 * n;
+    const int key = (feti ? 1 : 0) + (reduced ? 2 : 0) + 4 * n;
     if (!kry_exec_[0] || !kry_exec_[1] || kry_key_ != key) {
         for (auto& g : kry_exec_)
             if (g) {
@@ -1087,12 +1095,13 @@ int Context::pcg_graph(int n, const double* b, double* x, bool feti, KrylovOut& 
 
 // PCG (zero initial guess, unpreconditioned residual norm test, Polak-Ribiere
 // beta), on the full Jacobian with BDDC or on the FETI-DP multiplier system.
-int Context::pcg(int n, const double* b, double* x, bool feti, KrylovOut& out) {
+int Context::pcg(int n, const double* b, double* x, bool feti, KrylovOut& out, bool reduced, double rref) {
     out = KrylovOut();
     const size_t bytes = (size_t)n * sizeof(double);
     HIPOK(hipMemsetAsync(x, 0, bytes, stream_));
     HIPOK(hipMemcpyAsync(kr_, b, bytes, hipMemcpyDeviceToDevice, stream_));
     const double r0 = std::sqrt(dot(n, kr_, kr_));
+    const double ref = rref > 0.0 ? rref : r0;
     out.hist.push_back(r0);
     if (r0 == 0.0) return 0;
     auto A = [&](const double* in, double* o) -> int {
@@ -1104,7 +1113,7 @@ int Context::pcg(int n, const double* b, double* x, bool feti, KrylovOut& out) {
         if (feti)
             return prec_ ? fetidp_apply_t<float>(BDM_FETI_PRECOND, in, o)
                          : fetidp_apply_t<double>(BDM_FETI_PRECOND, in, o);
-        return prec_ ? bddc_apply_t<float>(in, o) : bddc_apply_t<double>(in, o);
+        return prec_ ? bddc_apply_t<float>(in, o, reduced) : bddc_apply_t<double>(in, o, reduced);
     };
     int rc = M(kr_, kz_);
     if (rc) return rc;
@@ -1123,8 +1132,8 @@ int Context::pcg(int n, const double* b, double* x, bool feti, KrylovOut& out) {
         const double rn = std::sqrt(dot(n, kr_, kr_));
         out.hist.push_back(rn);
         if (!(rn == rn)) { out.status = 2; break; }
-        if (rn <= opts.krylov_rtol * r0) { out.status = 0; break; }
-        if (rn > opts.krylov_dtol * r0) { out.status = 2; break; }
+        if (rn <= opts.krylov_rtol * ref) { out.status = 0; break; }
+        if (rn > opts.krylov_dtol * ref) { out.status = 2; break; }
         if ((rc = M(kr_, kz_))) return rc;
         const double zr = dot(n, kz_, kr_);
         const double zro = dot(n, kz_, kro_);
@@ -1137,8 +1146,8 @@ int Context::pcg(int n, const double* b, double* x, bool feti, KrylovOut& out) {
     return 0;
 }
 
-int Context::krylov(int n, const double* b, double* x, bool feti, KrylovOut& out) {
-    return opts.krylov_graph ? pcg_graph(n, b, x, feti, out) : pcg(n, b, x, feti, out);
+int Context::krylov(int n, const double* b, double* x, bool feti, KrylovOut& out, bool reduced, double rref) {
+    return opts.krylov_graph ? pcg_graph(n, b, x, feti, out, reduced, rref) : pcg(n, b, x, feti, out, reduced, rref);
 }
 
 // J s = b with the configured preconditioner.
@@ -1146,7 +1155,26 @@ int Context::newton_solve(const double* b, double* s, KrylovOut& out) {
     // project the u_e block of b onto the range (zero sum)
     HIPOK(hipMemcpyAsync(Rt_, b, 2 * N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
     launch_sub_mean(stream_, N, Rt_ + N, part_, scal_);
-    if (opts.solver != BDM_SOLVER_FETIDP) return krylov((int)(2 * N), Rt_, s, false, out);
+    if (opts.solver != BDM_SOLVER_FETIDP) {
+        if (!opts.krylov_reduced) return krylov((int)(2 * N), Rt_, s, false, out);
+        // s0 = interior solves of b, zero on the interface (Sec. 4.1); the
+        // residual b - J s0 vanishes on every subdomain interior, and so do
+        // all later PCG residuals, since each preconditioned direction ends
+        // with the interior correction.  PCG then solves J s' = b - J s0 and
+        // s = s0 + s'.  The stopping test is relative to ||b||, so the final
+        // residual b - J s meets the same bound as the unreduced solve.
+        // kx_ is unused by BDDC; pcg copies its right-hand side (kq_ here)
+        // before it first writes kq_.
+        const double bn = std::sqrt(dot(2 * N, Rt_, Rt_));
+        launch_fill(stream_, 2 * N, 0.0, kx_);
+        if (prec_) dirichlet<float>(Rt_, nullptr, kx_);
+        else dirichlet<double>(Rt_, nullptr, kx_);
+        launch_res_minus_jac(stream_, fp, st_, dg_, kx_, Rt_, kq_);
+        const int rc = krylov((int)(2 * N), kq_, s, false, out, true, bn);
+        if (rc) return rc;
+        launch_axpy(stream_, 2 * N, 1.0, kx_, s);
+        return 0;
+    }
     // FETI-DP: d = B S~^{-1} f~, PCG on F lambda = d, then recovery.
     int rc = prec_ ? fetidp_apply_t<float>(BDM_FETI_RHS, Rt_, kq_) : fetidp_apply_t<double>(BDM_FETI_RHS, Rt_, kq_);
     if (rc) return rc;

@@ -89,11 +89,11 @@ class Context {
     template <typename T> void condense(const double* r, double* g);
     template <typename T> void stilde_inv(T* xr, const double* gvert, double* uc);
     template <typename T> void interior_extend(const double* r, double* zbuf);
-    template <typename T> int bddc_apply_t(const double* r, double* z);
+    template <typename T> int bddc_apply_t(const double* r, double* z, bool interior_free = false);
     template <typename T> int fetidp_apply_t(int op, const double* in, double* out);
-    int pcg(int n, const double* b, double* x, bool feti, KrylovOut& out);
-    int pcg_graph(int n, const double* b, double* x, bool feti, KrylovOut& out);
-    int krylov(int n, const double* b, double* x, bool feti, KrylovOut& out);
+    int pcg(int n, const double* b, double* x, bool feti, KrylovOut& out, bool reduced = false, double rref = 0.0);
+    int pcg_graph(int n, const double* b, double* x, bool feti, KrylovOut& out, bool reduced = false, double rref = 0.0);
+    int krylov(int n, const double* b, double* x, bool feti, KrylovOut& out, bool reduced = false, double rref = 0.0);
     int newton_solve(const double* b, double* s, KrylovOut& out);
     int sync();
     double dot(int64_t n, const double* x, const double* y);

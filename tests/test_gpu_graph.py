@@ -29,16 +29,19 @@ def _shared_tuning(tmp_path_factory):
     mp.undo()
 
 
+UNEVEN442 = Mesh(20, 18, 12, 0.01, (0, 4, 9, 13, 20), (0, 5, 9, 14, 18), (0, 5, 12))
+# (mesh, precision, method, interior-reduced BDDC Newton solve)
 CASES = {
-    "bddc_fp64_ragged": (Mesh(11, 9, 10, 0.01, (0, 3, 7, 11), (0, 5, 9), (0, 4, 10)), 0, 0),
-    "bddc_mixed_uneven442": (Mesh(20, 18, 12, 0.01, (0, 4, 9, 13, 20), (0, 5, 9, 14, 18), (0, 5, 12)), 1, 0),
-    "fetidp_fp64_cube8": (Mesh(8, 8, 8, 0.01, (0, 4, 8), (0, 4, 8), (0, 4, 8)), 0, 1),
+    "bddc_fp64_ragged": (Mesh(11, 9, 10, 0.01, (0, 3, 7, 11), (0, 5, 9), (0, 4, 10)), 0, 0, True),
+    "bddc_mixed_uneven442": (UNEVEN442, 1, 0, True),
+    "bddc_mixed_uneven442_full": (UNEVEN442, 1, 0, False),
+    "fetidp_fp64_cube8": (Mesh(8, 8, 8, 0.01, (0, 4, 8), (0, 4, 8), (0, 4, 8)), 0, 1, True),
 }
 
 
-def _run(P, mesh, prec, method, graph, steps=4):
+def _run(P, mesh, prec, method, reduced, graph, steps=4):
     S = P.Solver(mesh, Physics(), SolverOpts(), precision=prec, method=method, guess=P.BDM_GUESS_EXTRAP,
-                 krylov_graph=graph)
+                 krylov_graph=graph, krylov_reduced=reduced)
     v0, ue0, w0 = initial_state(mesh, Physics(), 1)
     S.bdm_set_state(v0, ue0, w0)
     S.bdm_set_stimulus(stimulus_nodal(mesh, (2, 2, 2), 1e5), 0, 20)
@@ -56,9 +59,9 @@ def _run(P, mesh, prec, method, graph, steps=4):
 @pytest.mark.parametrize("case", list(CASES))
 def test_graph_pcg_matches_host_loop(case):
     import paper_2101_02959_amd as P
-    mesh, prec, method = CASES[case]
-    eager = _run(P, mesh, prec, method, False)
-    graph = _run(P, mesh, prec, method, True)
+    mesh, prec, method, reduced = CASES[case]
+    eager = _run(P, mesh, prec, method, reduced, False)
+    graph = _run(P, mesh, prec, method, reduced, True)
     for k, (a, b) in enumerate(zip(eager, graph)):
         assert a[0] == b[0], (k, "Newton iterations", a[0], b[0])
         assert a[1] == b[1], (k, "PCG iterations", a[1], b[1])

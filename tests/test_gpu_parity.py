@@ -121,16 +121,20 @@ def test_fetidp_operators(lin, prec, tol):
     assert _rel(_gauge(z, N), _gauge(zref, N)) < tol
 
 
-@pytest.mark.parametrize("method,prec", [(0, 0), (1, 0), (0, 1)])
-def test_time_steps_match_direct_newton(method, prec):
+@pytest.mark.parametrize("method,prec,reduced", [(0, 0, True), (1, 0, True), (0, 1, True),
+                                                 (0, 0, False), (0, 1, False)])
+def test_time_steps_match_direct_newton(method, prec, reduced):
     """Newton solution of each step within 1e-8 relative per field of the
-    oracle's direct sparse Newton root, the oracle fed the GPU's u^n."""
+    oracle's direct sparse Newton root, the oracle fed the GPU's u^n.  BDDC
+    runs both with the interior-reduced Newton solve (PCG from the interior
+    solves of the right-hand side, no condensation inside the
+    preconditioner) and with PCG on the full system from zero."""
     P = _solver_mod()
     wl = workload("slab8_supra")
     mesh = MESHES["ragged"] if method == 0 and prec == 0 else wl.mesh
     prob = bidomain.Problem(mesh, wl.physics, wl.solver.dt)
     N = prob.N
-    S = P.Solver(mesh, wl.physics, wl.solver, precision=prec, method=method)
+    S = P.Solver(mesh, wl.physics, wl.solver, precision=prec, method=method, krylov_reduced=reduced)
     Is = stimulus_nodal(mesh, (2, 2, 2), 1e5)
     S.bdm_set_state(np.zeros(N), np.zeros(N), np.zeros(N))
     S.bdm_set_stimulus(Is, 0, 20)
@@ -149,7 +153,7 @@ def test_time_steps_match_direct_newton(method, prec):
         # PCG stops at 1e-10 on its own residual (BDDC: the full system; FETI-DP:
         # the multiplier system, whose recovery adds the local solves' rounding)
         true_res = [st.krylov_true_res[k] for k in range(st.newton_its)]
-        print(step, method, prec, true_res)
+        print(step, method, prec, reduced, true_res)
         assert all(0 <= t <= (1e-9 if method == 0 else 1e-6) for t in true_res), true_res
         v, ue, w = vg, ueg, wg
 

@@ -95,3 +95,36 @@ def test_library_exports_every_declared_entry_point():
     assert set(bidomain.EXPORTS) == set(names)
     lib.bdm_last_error.restype = ctypes.c_char_p
     assert lib.bdm_last_error() is not None
+
+
+def _header_fields(hdr, name):
+    """(field, C type, array length) of `typedef struct name {...} name;`."""
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), hdr, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    out = []
+    for decl in filter(None, (d.strip() for d in body.split(";"))):
+        m = re.match(r"((?:const\s+)?(?:int|double)\s*\**)\s*(.*)", decl, re.S)
+        ctype = m.group(1).replace("const", "").replace(" ", "")
+        for item in m.group(2).split(","):
+            a = re.match(r"\s*(\w+)\s*(?:\[(\d+)\])?\s*$", item)
+            out.append((a.group(1), ctype, int(a.group(2)) if a.group(2) else None))
+    return out
+
+
+@pytest.mark.parametrize("name", ["bdm_mesh", "bdm_physics", "bdm_opts", "bdm_step_stats"])
+def test_binding_structs_mirror_header(name):
+    """The ctypes structures of the binding declare the header's fields in
+    the header's order with the same C types, so that the library reads
+    every option where the caller wrote it."""
+    with open(os.path.join(ROOT, "include", "bidomain.h")) as f:
+        hdr = f.read()
+    from paper_2101_02959_amd import bidomain
+    cmap = {"int": ctypes.c_int, "double": ctypes.c_double, "int*": ctypes.POINTER(ctypes.c_int)}
+    want = _header_fields(hdr, name)
+    got = getattr(bidomain, name)._fields_
+    assert [f for f, _, _ in want] == [f for f, _ in got]
+    for (f, ct, n), (_, t) in zip(want, got):
+        if n is None:
+            assert t is cmap[ct], f
+        else:
+            assert t._type_ is cmap[ct] and t._length_ == n, f
