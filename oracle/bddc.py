@@ -1,14 +1,22 @@
-"""BDDC with deluxe scaling and a vertex + edge-average primal space
-(paper Sec. 4.2 and 4.4), applied to the full Jacobian system.
+"""BDDC with deluxe or rho scaling and a vertex, vertex + edge-average or
+vertex + edge + face-average primal space (paper Sec. 4.2 and 4.4), applied
+to the full Jacobian system.
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
 Readings taken where the paper is silent or garbled:
-  * Edge averages are imposed as constraints (Lagrange multipliers) in the
-    local Neumann problems; vertex values are eliminated as primal dofs.
-  * The deluxe average of Sec. 4.2 acts on the values,
-        u_F = (S_F^j + S_F^k)^{-1} (S_F^j u_F^j + S_F^k u_F^k),
-    and its transpose on the residual, so M^{-1}_Gamma = E_D S~^{-1} E_D^T.
+  * Edge and face averages are imposed as constraints (Lagrange
+    multipliers) in the local Neumann problems; vertex values are eliminated
+    as primal dofs.
+  * Both scalings act on an object's values through matrices D^(m), one per
+    sharing subdomain, with sum_m D^(m) = I:  u_* = sum_m D^(m) u_*^(m), and
+    by the transpose on the residual, so M^{-1}_Gamma = E_D S~^{-1} E_D^T.
+    Deluxe (Sec. 4.2): D^(m) = (sum_k S_*^(k))^{-1} S_*^(m).
+    rho (Sec. 4.2, eq. for the pseudoinverses): D^(m) is diagonal with
+    sigma_M^(m) / sum_k sigma_M^(k) on the dofs of each field, sigma_M the
+    largest principal conductivity of subdomain m, taken from sigma^i for
+    the v dofs and from sigma^e for the u_e dofs.  The tissue here has the
+    same conductivities in every subdomain, so every weight is 1/|N_x|.
   * The coarse matrix is singular (kernel: u_e constant, v = 0).  Its
     right-hand side is projected onto the complement of that kernel and the
     u_e value of the first vertex is pinned to zero.
@@ -24,11 +32,17 @@ import scipy.linalg as sla
 from .dd import Decomposition, LocalOps
 
 
+SCALINGS = ("deluxe", "rho")
+
+
 class BDDC:
-    def __init__(self, prob, dec: Decomposition, v_lin, w_lin):
+    def __init__(self, prob, dec: Decomposition, v_lin, w_lin, scaling="deluxe"):
+        if scaling not in SCALINGS:
+            raise ValueError(f"scaling must be one of {SCALINGS}")
         self.prob = prob
         self.dec = dec
         self.N = prob.N
+        self.scaling = scaling
         self.loc = [LocalOps(prob, dec, s, v_lin, w_lin) for s in range(dec.nsub)]
         self._deluxe_setup()
         self._coarse_setup()
@@ -59,47 +73,65 @@ class BDDC:
     def obj_dofs(obj, N):
         return np.array([f * N + n for n in obj.nodes for f in (0, 1)], dtype=np.int64)
 
+    def sigma_max(self, s):
+        """(sigma_M^i, sigma_M^e) of subdomain s: the largest principal
+        conductivity of each medium (the same in every subdomain here)."""
+        ph = self.prob.ph
+        return max(ph.sigma_i), max(ph.sigma_e)
+
+    def D(self, kind, oid, m):
+        """Scaling matrix D^(m) of subdomain m on object (kind, oid), dofs
+        in the object's (node, field) order (Sec. 4.2)."""
+        obj = self.dec.faces[oid] if kind == "F" else self.dec.edges[oid]
+        if self.scaling == "deluxe":
+            return np.linalg.solve(self.Ssum[(kind, oid)], self._block(m, kind, oid))
+        num = self.sigma_max(m)
+        den = [sum(self.sigma_max(k)[f] for k in obj.subs) for f in (0, 1)]
+        w = [num[0] / den[0], num[1] / den[1]]
+        return np.diag(np.tile(w, len(obj.nodes)))
+
     def deluxe_residual(self, gG):
         """E_D^T: split an assembled interface vector (global 2N layout, only
-        face and edge dofs read) into local r-vectors g^(j)_* =
-        S_*^(j) (sum_m S_*^(m))^{-1} g_*.  Vertex dofs are not split; they go
-        to the coarse right-hand side directly."""
+        face and edge dofs read) into local r-vectors g^(j)_* = D^(j)T g_*
+        (deluxe: S_*^(j) (sum_m S_*^(m))^{-1} g_*).  Vertex dofs are not
+        split; they go to the coarse right-hand side directly."""
         out = [np.zeros(self.dec.sub[s].nr) for s in range(self.dec.nsub)]
         for kind, oid, obj in self._objects():
             gd = gG[self.obj_dofs(obj, self.N)]
-            h = np.linalg.solve(self.Ssum[(kind, oid)], gd)
             for s in obj.subs:
                 off = self.dec.sub[s].obj_offset[(kind, oid)]
-                out[s][off:off + len(gd)] = self._block(s, kind, oid) @ h
+                out[s][off:off + len(gd)] = self.D(kind, oid, s).T @ gd
         return out
 
     def deluxe_values(self, wloc, z):
-        """E_D on the values: u_* = (sum_m S_*^(m))^{-1} sum_m S_*^(m) u_*^(m),
-        written into the global vector z at the object's dofs (Sec. 4.2)."""
+        """E_D on the values: u_* = sum_m D^(m) u_*^(m) (deluxe:
+        (sum_m S_*^(m))^{-1} sum_m S_*^(m) u_*^(m)), written into the global
+        vector z at the object's dofs (Sec. 4.2)."""
         for kind, oid, obj in self._objects():
             acc = 0.0
             for s in obj.subs:
                 off = self.dec.sub[s].obj_offset[(kind, oid)]
                 n = 2 * len(obj.nodes)
-                acc = acc + self._block(s, kind, oid) @ wloc[s][off:off + n]
-            z[self.obj_dofs(obj, self.N)] = np.linalg.solve(self.Ssum[(kind, oid)], acc)
+                acc = acc + self.D(kind, oid, s) @ wloc[s][off:off + n]
+            z[self.obj_dofs(obj, self.N)] = acc
 
     # ---------------------------------------------------------------- coarse
     def _constraints(self, s):
-        """C^(s): two rows per local edge (average of v, average of u_e) on
-        the local r-dofs."""
+        """C^(s): two rows per constrained local object (average of v,
+        average of u_e over its nodes) on the local r-dofs: edges, then
+        faces, as the primal space includes them."""
         info = self.dec.sub[s]
-        C = np.zeros((2 * len(info.edges), info.nr))
-        for t, e in enumerate(info.edges):
-            off = info.obj_offset[("E", e)]
-            ne = len(self.dec.edges[e].nodes)
+        C = np.zeros((2 * len(info.cons), info.nr))
+        for t, (kind, o) in enumerate(info.cons):
+            off = info.obj_offset[(kind, o)]
+            ne = len((self.dec.edges if kind == "E" else self.dec.faces)[o].nodes)
             for f in (0, 1):
                 C[2 * t + f, off + f: off + 2 * ne: 2] = 1.0 / ne
         return C
 
     def _coarse_setup(self):
         """Coarse basis Phi^(j) (energy-minimising extension of the primal
-        values under the edge-average constraints) and
+        values under the average constraints) and
         S_PiPi = sum_j R_Pi^T Phi^T S_Gamma Phi R_Pi (Sec. 4.4)."""
         dec = self.dec
         self.C, self.Phi, self.KKT = [], [], []

@@ -13,6 +13,13 @@ Local dofs of subdomain j are ordered [I | r | V]: interior nodes, then the
 nodes of j's faces and edges (object by object, nodes ascending), then j's
 vertex nodes; every node carries (v, u_e).  Global dof of (node, f) is
 f * N + node.
+
+Primal spaces (Sec. 4.4 and the optimality test of Sec. 6): "V" (vertex
+values only), "VE" (plus the average of each field over every edge) and
+"VEF" (plus the averages over every face).  Vertex values are primal dofs;
+edge and face averages are constraints on the r-dofs.  Global primal
+numbering: (v, u_e) per vertex, then the two averages per edge, then per face
+(only for the objects the primal space includes).
 """
 from __future__ import annotations
 
@@ -38,12 +45,20 @@ class Obj:
         self.nodes = np.array(sorted(nodes), dtype=np.int64)
 
 
+PRIMAL_SPACES = ("V", "VE", "VEF")
+
+
 class Decomposition:
-    def __init__(self, mesh):
+    def __init__(self, mesh, primal="VE"):
+        if primal not in PRIMAL_SPACES:
+            raise ValueError(f"primal space must be one of {PRIMAL_SPACES}")
         self.mesh = mesh
+        self.primal_space = primal
+        self.cons_edges = "E" in primal
+        self.cons_faces = "F" in primal
         ps = (len(mesh.cuts_x) - 1, len(mesh.cuts_y) - 1, len(mesh.cuts_z) - 1)
         if min(ps) < 2:
-            raise ValueError("the vertex + edge primal space needs >= 2 subdomains per axis")
+            raise ValueError("the primal spaces need >= 2 subdomains per axis (interior cross points)")
         self.ps = ps
         self.nsub = ps[0] * ps[1] * ps[2]
         N = mesh.nnodes
@@ -70,8 +85,11 @@ class Decomposition:
         self.verts = sorted([o for o in objs if o.kind == "V"], key=lambda o: o.nodes[0])
         for o in self.verts:
             assert len(o.nodes) == 1
-        # global primal numbering: (vertex v, vertex u_e), ..., then (edge avg v, avg u_e)
-        self.nprimal = 2 * (len(self.verts) + len(self.edges))
+        # global primal numbering: (vertex v, vertex u_e), ..., then (edge avg v,
+        # avg u_e) per edge, then per face, for the constrained object kinds
+        self.edge_p0 = 2 * len(self.verts)
+        self.face_p0 = self.edge_p0 + (2 * len(self.edges) if self.cons_edges else 0)
+        self.nprimal = self.face_p0 + (2 * len(self.faces) if self.cons_faces else 0)
         # per-subdomain boxes and local orderings
         self.sub = []
         for s in range(self.nsub):
@@ -124,9 +142,14 @@ class _SubInfo:
         self.G = np.concatenate([self.r, self.V])
         self.nI, self.nr, self.nV = len(self.I), len(self.r), len(self.V)
         self.nG = self.nr + self.nV
+        # constrained objects, in the order of their constraint rows and
+        # primal dofs: edges, then faces
+        self.cons = ([("E", e) for e in self.edges] if dec.cons_edges else []) \
+            + ([("F", f) for f in self.faces] if dec.cons_faces else [])
         # local primal -> global primal
+        p0 = {"E": dec.edge_p0, "F": dec.face_p0}
         self.primal = np.array([2 * v + f for v in self.verts for f in (0, 1)]
-                               + [2 * len(dec.verts) + 2 * e + f for e in self.edges for f in (0, 1)],
+                               + [p0[k] + 2 * o + f for k, o in self.cons for f in (0, 1)],
                                dtype=np.int64)
 
 

@@ -1,5 +1,5 @@
-"""FETI-DP with deluxe scaling (paper Sec. 4.3), on the same local
-operators, deluxe blocks and coarse space as the BDDC oracle.
+"""FETI-DP with deluxe or rho scaling (paper Sec. 4.3), on the same local
+operators, scaling matrices and coarse space as the BDDC oracle.
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
@@ -9,7 +9,8 @@ in object order, dofs in node order with (v, u_e) per node; then edges in
 object order, pairs in lexicographic order, dofs as for faces.
     (B w)_{ab} = w^(a) - w^(b)
     B_D^T lambda gives subdomain a the value D^(b) lambda_ab and subdomain b
-    the value -D^(a) lambda_ab, with D^(m) = (sum S)^{-1} S^(m) (Sec. 4.2),
+    the value -D^(a) lambda_ab, with D^(m) the scaling matrices of Sec. 4.2
+    (deluxe: (sum S)^{-1} S^(m); rho: the diagonal weights),
 so that B_D^T B equals the complementary projection P_D = I - E_D.
 """
 from __future__ import annotations
@@ -55,7 +56,7 @@ class FETIDP:
         return out
 
     def _D(self, kind, oid, m):
-        return np.linalg.solve(self.b.Ssum[(kind, oid)], self.b._block(m, kind, oid))
+        return self.b.D(kind, oid, m)
 
     def BDT(self, lam):
         out = self._loc_zero()

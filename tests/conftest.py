@@ -26,3 +26,16 @@ def read_remarks():
             key, val = line.split()[:2]
             out[key] = float(val)
     return out
+
+
+def read_test3():
+    """{(scaling, primal, H/h): (lit, cond)} of the paper's Test 3 slab
+    table (None where the paper reports out of memory)."""
+    out = {}
+    with open(golden("paper_test3_slab.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            sc, pr, hh, lit, cond = line.split()[:5]
+            out[(sc, pr, int(hh))] = None if lit == "oom" else (float(lit), float(cond))
+    return out
