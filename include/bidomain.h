@@ -58,6 +58,18 @@ enum { BDM_GUESS_PREV = 0, BDM_GUESS_EXTRAP = 1, BDM_GUESS_CNN = 2 };
  * Both give bitwise identical results. */
 enum { BDM_SCHED_QUEUE = 0, BDM_SCHED_GRID = 1 };
 enum { BDM_FETI_F = 0, BDM_FETI_PRECOND = 1, BDM_FETI_RHS = 2, BDM_FETI_RECOVER = 3 };
+/* Scaling of the dual (face and edge) dofs, Sec. 4.2:
+ * DELUXE  u_* = (sum_m S_*^(m))^{-1} sum_m S_*^(m) u_*^(m) per face / edge;
+ * RHO     u(x) = sum_j delta_j(x) u^(j)(x), with the pseudoinverse weights
+ *         delta_j = sigma_M^(j) / sum_{k in N_x} sigma_M^(k) (sigma_M the
+ *         largest principal conductivity, sigma^i for the v dofs and sigma^e
+ *         for the u_e dofs); with the same tissue in every subdomain each
+ *         weight is 1/|N_x|. */
+enum { BDM_SCALING_DELUXE = 0, BDM_SCALING_RHO = 1 };
+/* Primal space of BDDC and FETI-DP, Sec. 4.4 and the optimality test of
+ * Sec. 6: the (v, u_e) values at the subdomain vertices, plus the averages
+ * of v and of u_e over every edge (VE), or over every edge and face (VEF). */
+enum { BDM_PRIMAL_VE = 0, BDM_PRIMAL_V = 1, BDM_PRIMAL_VEF = 2 };
 
 /* Structured hexahedral Q1 mesh of nx*ny*nz cubes of side h (Sec. 3a) and a
  * tensor-product partition into non-overlapping box subdomains (Sec. 4.1):
@@ -113,6 +125,8 @@ typedef struct bdm_opts {
                                 /* of r_I; the stopping test stays relative  */
                                 /* to ||b||.  0: PCG on J s = b from zero.   */
                                 /* Must be 0 or 1 (BDM_E_ARG otherwise).     */
+    int scaling;                /* BDM_SCALING_* (BDM_E_ARG otherwise)       */
+    int primal;                 /* BDM_PRIMAL_* (BDM_E_ARG otherwise)        */
 } bdm_opts;
 
 /* Per-step statistics filled by bdm_step (for its last step). */

@@ -70,11 +70,11 @@ class StepStats:
         self.lambdas = []
 
 
-def solve_linear(prob, dec, v, w, b, method, krtol, kmaxit):
+def solve_linear(prob, dec, v, w, b, method, krtol, kmaxit, scaling="deluxe"):
     """Solve J s = b with PCG preconditioned by BDDC, or by FETI-DP on the
     multiplier system followed by recovery.  Returns (s, KrylovResult)."""
     N = prob.N
-    bd = BDDC(prob, dec, v, w)
+    bd = BDDC(prob, dec, v, w, scaling=scaling)
     J = prob.jacobian(v, w)
     if method == "bddc":
         res = pcg(lambda x: J @ x, bd.apply, b, rtol=krtol, maxit=kmaxit,
@@ -90,7 +90,7 @@ def solve_linear(prob, dec, v, w, b, method, krtol, kmaxit):
 
 
 def time_step(prob, dec, v_n, ue_n, w_n, Is, method="bddc", rtol=1e-8, atol=0.0,
-              krtol=1e-10, kmaxit=1000, maxit=20, guess=None, stats=None):
+              krtol=1e-10, kmaxit=1000, maxit=20, guess=None, stats=None, scaling="deluxe"):
     """One decoupled BE step: Step 1 gating update, then Newton on Step 2."""
     N = prob.N
     st = stats if stats is not None else StepStats()
@@ -106,7 +106,7 @@ def time_step(prob, dec, v_n, ue_n, w_n, Is, method="bddc", rtol=1e-8, atol=0.0,
     for _ in range(maxit):
         if np.linalg.norm(R) <= max(rtol * ref, atol):
             break
-        s, kres = solve_linear(prob, dec, u[:N], w, -R, method, krtol, kmaxit)
+        s, kres = solve_linear(prob, dec, u[:N], w, -R, method, krtol, kmaxit, scaling)
         st.krylov_its.append(kres.its)
         st.conds.append(kres.cond())
         u, R, lam = linesearch(resfun, u, s, R)

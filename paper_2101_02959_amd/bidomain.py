@@ -20,6 +20,8 @@ BDM_PREC_FP64, BDM_PREC_MIXED = 0, 1
 BDM_GUESS_PREV, BDM_GUESS_EXTRAP, BDM_GUESS_CNN = 0, 1, 2
 BDM_SCHED_QUEUE, BDM_SCHED_GRID = 0, 1
 BDM_FETI_F, BDM_FETI_PRECOND, BDM_FETI_RHS, BDM_FETI_RECOVER = 0, 1, 2, 3
+BDM_SCALING_DELUXE, BDM_SCALING_RHO = 0, 1
+BDM_PRIMAL_VE, BDM_PRIMAL_V, BDM_PRIMAL_VEF = 0, 1, 2
 (BDM_KERNEL_JACOBIAN, BDM_KERNEL_TRSV_DIRICHLET, BDM_KERNEL_POTRF_INTERIOR, BDM_KERNEL_SYRK_UPDATE,
  BDM_KERNEL_TRSV_DIRICHLET_T) = 0, 1, 2, 3, 4
 
@@ -61,7 +63,7 @@ class bdm_opts(C.Structure):
                 ("newton_maxit", C.c_int), ("krylov_rtol", C.c_double), ("krylov_dtol", C.c_double),
                 ("krylov_maxit", C.c_int), ("solver", C.c_int), ("precision", C.c_int),
                 ("guess", C.c_int), ("krylov_graph", C.c_int), ("schedule", C.c_int),
-                ("krylov_reduced", C.c_int)]
+                ("krylov_reduced", C.c_int), ("scaling", C.c_int), ("primal", C.c_int)]
 
 
 class bdm_step_stats(C.Structure):
@@ -128,7 +130,8 @@ def _ptr(t):
 
 
 def make_structs(mesh, physics, solver, precision=BDM_PREC_FP64, method=BDM_SOLVER_BDDC,
-                 guess=BDM_GUESS_PREV, krylov_graph=False, schedule=0, krylov_reduced=True):
+                 guess=BDM_GUESS_PREV, krylov_graph=False, schedule=0, krylov_reduced=True,
+                 scaling=0, primal=0):
     """Build the C structs from workload descriptions (duck-typed)."""
     cx = (C.c_int * len(mesh.cuts_x))(*mesh.cuts_x)
     cy = (C.c_int * len(mesh.cuts_y))(*mesh.cuts_y)
@@ -140,7 +143,7 @@ def make_structs(mesh, physics, solver, precision=BDM_PREC_FP64, method=BDM_SOLV
                      physics.eta1, physics.eta2, physics.vth, physics.vp)
     op = bdm_opts(solver.dt, solver.newton_rtol, solver.newton_atol, solver.newton_maxit,
                   solver.krylov_rtol, solver.krylov_dtol, solver.krylov_maxit, method, precision,
-                  guess, int(bool(krylov_graph)), schedule, int(bool(krylov_reduced)))
+                  guess, int(bool(krylov_graph)), schedule, int(bool(krylov_reduced)), scaling, primal)
     return m, ph, op, (cx, cy, cz)
 
 
@@ -148,13 +151,14 @@ class Solver:
     """One libbidomain context on the current torch CUDA device and stream."""
 
     def __init__(self, mesh, physics, solver, precision=BDM_PREC_FP64, method=BDM_SOLVER_BDDC,
-                 guess=BDM_GUESS_PREV, stream=None, krylov_graph=False, schedule=0, krylov_reduced=True):
+                 guess=BDM_GUESS_PREV, stream=None, krylov_graph=False, schedule=0, krylov_reduced=True,
+                 scaling=0, primal=0):
         import torch
         self.torch = torch
         L = lib()
         self.m, self.ph, self.op, self._keep = make_structs(mesh, physics, solver, precision,
                                                             method, guess, krylov_graph, schedule,
-                                                            krylov_reduced)
+                                                            krylov_reduced, scaling, primal)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream

@@ -10,8 +10,6 @@
 namespace bdm {
 
 constexpr int MAXO = 512;       // largest face / edge object (dofs)
-constexpr int MAXC = 24;
-constexpr int MAXP = 40;
 
 namespace {
 
@@ -162,9 +160,32 @@ __global__ __launch_bounds__(kWG) void k_deluxe_transpose(ObjDesc o, const T* __
     }
 }
 
+// rho scaling (Sec. 4.2): the scaling matrix of share q of an object is
+// diagonal, w_q^v on the v dofs and w_q^e on the u_e dofs (dofs interleaved
+// per node), so the residual split and the value average run through the
+// same per-share matrices as the deluxe scaling.  Written into both the
+// matrix and its transpose (equal); one workgroup per object.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_rho_fill(ObjDesc o, const double* __restrict__ w, T* __restrict__ dmat,
+                                                 T* __restrict__ dmatT) {
+    const int ob = blockIdx.x, tid = threadIdx.x;
+    const int n = o.n[ob];
+    for (int q = o.sh_ptr[ob]; q < o.sh_ptr[ob + 1]; ++q) {
+        const T wv = (T)w[2 * q], we = (T)w[2 * q + 1];
+        T* E = dmat + o.sh_slot[q];
+        T* F = dmatT + o.sh_slot[q];
+        for (int64_t idx = tid; idx < (int64_t)n * n; idx += kWG) {
+            const int i = (int)(idx % n), j = (int)(idx / n);
+            const T v = (i == j) ? ((i & 1) ? we : wv) : (T)0;
+            E[idx] = v;
+            F[idx] = v;
+        }
+    }
+}
+
 // Per subdomain after the forward Neumann solve x1 = L_rr^{-1} g_r:
 //   cP = Z^T x1 (the local coarse right-hand side Phi^T g),
-//   mu = G^{-1} Y^T x1 (edge-average multipliers).
+//   mu = G^{-1} Y^T x1 (multipliers of the average constraints).
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_coarse_rhs_local(SubVecDesc d, const T* __restrict__ xr,
                                                          const T* __restrict__ Fb, const T* __restrict__ Zb,
@@ -429,6 +450,11 @@ void launch_deluxe_transpose(hipStream_t s, const ObjDesc& o, const T* dmat, T* 
 }
 int deluxe_max_shares() { return DV_SH; }
 template <typename T>
+void launch_rho_fill(hipStream_t s, const ObjDesc& o, const double* w, T* dmat, T* dmatT) {
+    if (o.nobj <= 0) return;
+    hipLaunchKernelGGL(k_rho_fill<T>, dim3(o.nobj), dim3(kWG), 0, s, o, w, dmat, dmatT);
+}
+template <typename T>
 void launch_coarse_rhs_local(hipStream_t s, const SubVecDesc& d, const T* xr, const T* F, const T* Z,
                              const T* Gi, double* cP, double* mu) {
     hipLaunchKernelGGL(k_coarse_rhs_local<T>, dim3(d.nsub), dim3(kWG), 0, s, d, xr, F, Z, Gi, cP, mu);
@@ -489,6 +515,7 @@ void launch_take_first(hipStream_t s, const ObjDesc& o, int64_t N, const T* xr, 
     template void launch_deluxe_val<T>(hipStream_t, const ObjDesc&, int64_t, const T*, const T*,            \
                                        const int64_t*, double*);                                            \
     template void launch_deluxe_transpose<T>(hipStream_t, const ObjDesc&, const T*, T*);                   \
+    template void launch_rho_fill<T>(hipStream_t, const ObjDesc&, const double*, T*, T*);                    \
     template void launch_coarse_rhs_local<T>(hipStream_t, const SubVecDesc&, const T*, const T*, const T*,  \
                                              const T*, double*, double*);                                   \
     template void launch_neumann_rhs<T>(hipStream_t, const SubVecDesc&, const T*, const T*, const double*,  \

@@ -58,6 +58,10 @@ void launch_deluxe_val(hipStream_t s, const ObjDesc& o, int64_t N, const T* dmat
 template <typename T>
 void launch_deluxe_transpose(hipStream_t s, const ObjDesc& o, const T* dmat, T* dmatT);
 int deluxe_max_shares();
+// rho scaling: every share's matrix (and its transpose) set to the diagonal
+// of its weights, w[2q] on the v dofs and w[2q + 1] on the u_e dofs.
+template <typename T>
+void launch_rho_fill(hipStream_t s, const ObjDesc& o, const double* w, T* dmat, T* dmatT);
 template <typename T>
 void launch_coarse_rhs_local(hipStream_t s, const SubVecDesc& d, const T* xr, const T* F, const T* Z,
                              const T* Gi, double* cP, double* mu);

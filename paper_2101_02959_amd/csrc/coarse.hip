@@ -1,9 +1,9 @@
 // FP64 coarse problem of BDDC / FETI-DP (paper Sec. 4.4): the assembled
-// primal matrix S_PiPi over vertex values and edge averages.
+// primal matrix S_PiPi over vertex values and the edge (and face) averages.
 //
 // The matrix couples two primal objects when they share a subdomain, so the
 // cut planes of the subdomain grid are separators: the objects lying on the
-// plane x = X (vertices, y- and z-edges there) separate those of the
+// plane x = X (vertices, y- and z-edges, x-faces there) separate those of the
 // subdomain columns left of X from those right of it.  Recursive bisection of
 // the subdomain grid along its longest axis gives a nested-dissection order
 // and its elimination tree of fronts; boxes of at most 8 subdomains are the
@@ -225,9 +225,8 @@ std::string CoarseSolver::init(const Topology& t, int pin_, int maxp_) {
     np = t.nprimal;
     pin = pin_;
     maxp = maxp_;
-    const int nv = (int)t.verts.size(), ne_obj = (int)t.edges.size();
-    const int nobj = nv + ne_obj;
-    if (2 * nobj != np) return "internal error: primal numbering is not two dofs per vertex and edge";
+    const int nobj = (int)t.pobj_node.size();
+    if (2 * nobj != np) return "internal error: primal numbering is not two dofs per primal object";
     if (np == 0) return "no primal unknowns";
     // doubled subdomain-grid coordinates: cut plane a -> 2a, slab a -> 2a + 1
     auto dbl = [](int n, const std::vector<int>& cuts) {
@@ -242,7 +241,7 @@ std::string CoarseSolver::init(const Topology& t, int pin_, int maxp_) {
     const std::vector<int> dx = dbl(t.nx, t.cx), dy = dbl(t.ny, t.cy), dz = dbl(t.nz, t.cz);
     std::vector<int> oc(3 * (size_t)nobj);
     for (int o = 0; o < nobj; ++o) {
-        const int node = o < nv ? t.verts[o].nodes[0] : t.edges[o - nv].nodes[0];
+        const int node = t.pobj_node[o];
         const int i = node % (t.nx + 1), j = (node / (t.nx + 1)) % (t.ny + 1), k = node / ((t.nx + 1) * (t.ny + 1));
         oc[3 * o] = dx[i];
         oc[3 * o + 1] = dy[j];

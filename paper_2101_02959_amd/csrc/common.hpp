@@ -10,6 +10,16 @@ namespace bdm {
 // Threads per workgroup for batched per-subdomain kernels (4 wave64).
 constexpr int kWG = 256;
 
+// Primal unknowns of one box subdomain (Sec. 4.4): the (v, u_e) values at
+// its 8 vertices, and two averages over each of its 12 edges and 6 faces
+// (the richest primal space, vertices + edges + faces).
+constexpr int MAXV = 16;                    // vertex dofs
+constexpr int MAXC = 36;                    // average constraints
+constexpr int MAXP = MAXC + MAXV;           // primal dofs
+constexpr int SVV_STRIDE = MAXV * MAXV;     // per-subdomain S_VV block
+constexpr int GI_STRIDE = MAXC * MAXC;      // per-subdomain G^{-1}
+constexpr int SP_STRIDE = MAXP * MAXP;      // per-subdomain coarse block
+
 // Pointwise and stencil parameters of the Bidomain step.
 struct FEParams {
     int nx, ny, nz;             // elements per axis

@@ -18,12 +18,6 @@
 namespace bdm {
 
 constexpr int NB = 32;          // panel / block width
-constexpr int MAXC = 24;        // edge constraints per subdomain (12 edges x 2)
-constexpr int MAXV = 16;        // vertex dofs per subdomain (8 vertices x 2)
-constexpr int MAXP = MAXC + MAXV;
-constexpr int SVV_STRIDE = MAXV * MAXV;
-constexpr int GI_STRIDE = MAXC * MAXC;
-constexpr int SP_STRIDE = MAXP * MAXP;
 
 namespace {
 
@@ -650,7 +644,7 @@ __global__ __launch_bounds__(kWG) void k_extract(BatchDesc d, const T* __restric
             const int i = idx % no, j = idx / no;
             dst[idx] = Sat(ro + i, ro + j);
         }
-        const int e = d.so_eidx[q];
+        const int e = d.so_eidx[q];   // constraint index of the object, or -1
         if (e >= 0) {
             const int nn = d.so_nnode[q];
             T* Fc = F + d.F_off[s];
@@ -868,12 +862,13 @@ __device__ __forceinline__ double wave_dot(const T* __restrict__ a, const T* __r
 
 // ------------------------------------------------------- coarse algebra
 // With Y = L_rr^{-1} C^T and X = -L_rr^{-1} S_rV (from k_trsm_fwd), the
-// energy-minimising coarse basis of Sec. 4.4 under the edge-average
-// constraints is Phi_r = L_rr^{-T} Z with
+// energy-minimising coarse basis of Sec. 4.4 under the average constraints
+// (edges, and faces when the primal space has them) is Phi_r = L_rr^{-T} Z with
 //   G = Y^T Y = C S_rr^{-1} C^T,  mu_V = G^{-1} Y^T X,
-//   Z = [X - Y mu_V | Y G^{-1}]   (vertex primals, then edge primals),
+//   Z = [X - Y mu_V | Y G^{-1}]   (vertex primals, then average primals),
 // and the local coarse matrix Phi^T S_Gamma Phi is
-//   vertex rows: [-X^T Z + [S_VV | 0]],   edge rows: [-mu_V | G^{-1}].
+//   vertex rows: [-X^T Z + [S_VV | 0]],   average rows: [-mu_V | G^{-1}].
+// With vertex primals only (no constraints) Z = X.
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_coarse_local(BatchDesc d, const T* __restrict__ Fb,
                                                      const double* __restrict__ Svv, T* __restrict__ Zb,
@@ -911,14 +906,14 @@ __global__ __launch_bounds__(kWG) void k_coarse_local(BatchDesc d, const T* __re
     // Cholesky of the small constraint matrix (lower triangle of G): one
     // barrier per pivot, the trailing block updated with the unscaled column
     // by (row, column group) threads, the columns scaled at the end
-    static_assert(MAXC <= 32, "one row slot per pivot row");
+    static_assert(MAXC <= 64, "one row slot per pivot row");
     for (int k = 0; k < nc; ++k) {
         double dk = G[k][k];
         if (!(dk > 0.0)) dk = 1.0;
-        const int i = tid % 32;
+        const int i = tid % 64;
         if (i > k && i < nc) {
             const double lik = G[i][k] / dk;
-            for (int j = k + 1 + tid / 32; j <= i; j += kWG / 32) G[i][j] -= lik * G[j][k];
+            for (int j = k + 1 + tid / 64; j <= i; j += kWG / 64) G[i][j] -= lik * G[j][k];
         }
         __syncthreads();
     }

@@ -51,8 +51,9 @@ struct BatchDesc {
     const int* so_n;       //   object dofs
     const int64_t* so_slot;//   start of this subdomain's copy of the object block
     const int* so_kind;    //   0 face, 1 edge
-    const int* so_nnode;   //   edge nodes (for the constraint rows)
-    const int* so_eidx;    //   local edge index (constraint rows 2e, 2e+1) or -1
+    const int* so_nnode;   //   object nodes (for the constraint rows)
+    const int* so_eidx;    //   constraint index c of the object (rows 2c, 2c+1
+                           //   of C) or -1 when the primal space leaves it free
     const int64_t* Srr_off;// start of the saved S_rr copy (FETI-DP) or null
 };
 

@@ -19,8 +19,6 @@ namespace bdm {
 namespace {
 thread_local std::string g_err;
 
-constexpr int MAXC = 24, MAXV = 16, MAXP = 40;
-constexpr int SVV_STRIDE = MAXV * MAXV, GI_STRIDE = MAXC * MAXC, SP_STRIDE = MAXP * MAXP;
 
 // Device allocation recorded in the context list c (freed with the context).
 static void* ctx_alloc(void* c, size_t bytes) {
@@ -141,12 +139,14 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
     phys = *ph;
     if (!(o->dt > 0) || o->newton_maxit < 1 || o->krylov_maxit < 1 ||
         (o->schedule != BDM_SCHED_QUEUE && o->schedule != BDM_SCHED_GRID) ||
-        (o->krylov_reduced != 0 && o->krylov_reduced != 1)) {
+        (o->krylov_reduced != 0 && o->krylov_reduced != 1) ||
+        (o->scaling != BDM_SCALING_DELUXE && o->scaling != BDM_SCALING_RHO) ||
+        (o->primal != BDM_PRIMAL_VE && o->primal != BDM_PRIMAL_V && o->primal != BDM_PRIMAL_VEF)) {
         set_error("invalid options");
         return BDM_E_ARG;
     }
     std::string err = topo.build(m->nx, m->ny, m->nz, m->h, m->px, m->py, m->pz, m->cuts_x, m->cuts_y,
-                                 m->cuts_z);
+                                 m->cuts_z, o->primal);
     if (!err.empty()) {
         set_error(err);
         return BDM_E_ARG;
@@ -295,6 +295,22 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
         sh_ptr[ob + 1] = (int)sh_sub.size();
     }
     nslot_ = accSlot; nfac_ = accFac; nyb_ = accY;
+    // rho scaling weights (Sec. 4.2): share m of an object gets
+    // sigma_M^(m) / sum_k sigma_M^(k) per field, sigma_M the largest principal
+    // conductivity (sigma^i for v, sigma^e for u_e).  The tissue parameters
+    // are the same in every subdomain, so each weight is 1 / (shares).
+    std::vector<double> rho_w(2 * sh_sub.size());
+    {
+        const double sMi = std::max({phys.sigma_i[0], phys.sigma_i[1], phys.sigma_i[2]});
+        const double sMe = std::max({phys.sigma_e[0], phys.sigma_e[1], phys.sigma_e[2]});
+        for (int ob = 0; ob < nobj; ++ob) {
+            const int nsh = sh_ptr[ob + 1] - sh_ptr[ob];
+            for (int q = sh_ptr[ob]; q < sh_ptr[ob + 1]; ++q) {
+                rho_w[2 * q] = sMi / (nsh * sMi);
+                rho_w[2 * q + 1] = sMe / (nsh * sMe);
+            }
+        }
+    }
     if (maxobjn_ > deluxe_max_object()) {
         set_error("a face or edge has more than " + std::to_string(deluxe_max_object()) + " dofs");
         return BDM_E_ARG;
@@ -308,13 +324,13 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
             const int ob = sb.faces[t];
             so_roff.push_back(sb.face_off[t]); so_n.push_back(on[ob]);
             so_slot.push_back(slot_of.at({ob, q})); so_kind.push_back(0);
-            so_nnode.push_back(on[ob] / 2); so_eidx.push_back(-1);
+            so_nnode.push_back(on[ob] / 2); so_eidx.push_back(sb.face_con[t]);
         }
         for (size_t t = 0; t < sb.edges.size(); ++t) {
             const int ob = nF + sb.edges[t];
             so_roff.push_back(sb.edge_off[t]); so_n.push_back(on[ob]);
             so_slot.push_back(slot_of.at({ob, q})); so_kind.push_back(1);
-            so_nnode.push_back(on[ob] / 2); so_eidx.push_back((int)t);
+            so_nnode.push_back(on[ob] / 2); so_eidx.push_back(sb.edge_con[t]);
         }
         so_ptr[q + 1] = (int64_t)so_roff.size();
     }
@@ -378,6 +394,7 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
     fd_.pr_ptr = upload(pr_ptr); fd_.pr_a = upload(pr_a); fd_.pr_b = upload(pr_b);
     fd_.pr_qa = upload(pr_qa); fd_.pr_qb = upload(pr_qb); fd_.pr_off = upload(pr_off);
     fd_.sh_yoff = upload(sh_yoff);
+    rho_w_ = upload(rho_w);
     Ilist_ = upload(Ilist);
     LII_off_ = upload(LII); Lrr_off_ = upload(Lrr); xI_off_ = upload(xI_off); Srr_off_ = bd_.Srr_off;
     nI_ = bd_.nI; nr_ = bd_.nr; ld_ = bd_.n; kF_ = upload(kF); nP_ = upload(nP);
@@ -802,12 +819,16 @@ int Context::linearize_t() {
     }
     HIPOK(hipEventRecord(ev_fork_, stream_));
     HIPOK(hipStreamWaitEvent(side_stream_, ev_fork_, 0));
-    // faces and edges separately: each launch reserves LDS for its own largest object
-    launch_deluxe_setup<T>(side_stream_, od_, 0, nface_obj_, maxface_n_, (const T*)slots_, (T*)fac_, (T*)dmat_,
-                           info_obj_);
-    launch_deluxe_setup<T>(side_stream_, od_, nface_obj_, od_.nobj - nface_obj_, maxedge_n_, (const T*)slots_,
-                           (T*)fac_, (T*)dmat_, info_obj_);
-    launch_deluxe_transpose<T>(side_stream_, od_, (const T*)dmat_, (T*)dmatT_);
+    if (opts.scaling == BDM_SCALING_RHO) {
+        launch_rho_fill<T>(side_stream_, od_, rho_w_, (T*)dmat_, (T*)dmatT_);
+    } else {
+        // faces and edges separately: each launch reserves LDS for its own largest object
+        launch_deluxe_setup<T>(side_stream_, od_, 0, nface_obj_, maxface_n_, (const T*)slots_, (T*)fac_,
+                               (T*)dmat_, info_obj_);
+        launch_deluxe_setup<T>(side_stream_, od_, nface_obj_, od_.nobj - nface_obj_, maxedge_n_,
+                               (const T*)slots_, (T*)fac_, (T*)dmat_, info_obj_);
+        launch_deluxe_transpose<T>(side_stream_, od_, (const T*)dmat_, (T*)dmatT_);
+    }
     HIPOK(hipEventRecord(ev_join_, side_stream_));
     launch_trsm_fwd<T>(stream_, nsub, (const T*)Lrrs_, Lrr_off_, nr_, (T*)F_, bd_.F_off, nr_, kF_);
     launch_coarse_local<T>(stream_, bd_, (const T*)F_, Svv_, (T*)Z_, (T*)Gi_, Sp_, info_sub_);

@@ -36,8 +36,11 @@ void sort_objects(std::vector<Object>& v) {
 }  // namespace
 
 std::string Topology::build(int nx_, int ny_, int nz_, double h_, int px_, int py_, int pz_,
-                            const int* cuts_x, const int* cuts_y, const int* cuts_z) {
+                            const int* cuts_x, const int* cuts_y, const int* cuts_z, int primal_space) {
     nx = nx_; ny = ny_; nz = nz_; h = h_; px = px_; py = py_; pz = pz_;
+    if (primal_space < 0 || primal_space > 2) return "unknown primal space";
+    cons_edges = primal_space != 1;
+    cons_faces = primal_space == 2;
     if (nx < 2 || ny < 2 || nz < 2 || !(h > 0)) return "mesh sizes must be >= 2 and h > 0";
     if (px < 2 || py < 2 || pz < 2) return "need >= 2 subdomains per axis";
     cx.assign(cuts_x, cuts_x + px + 1);
@@ -126,7 +129,15 @@ std::string Topology::build(int nx_, int ny_, int nz_, double h_, int px_, int p
     sort_objects(faces);
     sort_objects(edges);
     sort_objects(verts);
-    nprimal = 2 * (int)(verts.size() + edges.size());
+    const int edge_p0 = 2 * (int)verts.size();
+    const int face_p0 = edge_p0 + (cons_edges ? 2 * (int)edges.size() : 0);
+    nprimal = face_p0 + (cons_faces ? 2 * (int)faces.size() : 0);
+    pobj_node.clear();
+    for (auto& o : verts) pobj_node.push_back(o.nodes[0]);
+    if (cons_edges)
+        for (auto& o : edges) pobj_node.push_back(o.nodes[0]);
+    if (cons_faces)
+        for (auto& o : faces) pobj_node.push_back(o.nodes[0]);
 
     const int nsub = px * py * pz;
     subs.assign(nsub, SubInfo());
@@ -146,7 +157,6 @@ std::string Topology::build(int nx_, int ny_, int nz_, double h_, int px_, int p
     for (int v = 0; v < (int)verts.size(); ++v)
         for (int s : verts[v].subs) subs[s].verts.push_back(v);
 
-    const int nverts = (int)verts.size();
     const std::vector<char> mx = cut_mask(cx, nx), my = cut_mask(cy, ny), mz = cut_mask(cz, nz);
     for (int sidx = 0; sidx < nsub; ++sidx) {
         SubInfo& s = subs[sidx];
@@ -173,14 +183,25 @@ std::string Topology::build(int nx_, int ny_, int nz_, double h_, int px_, int p
         s.nr = 2 * (int)s.r_nodes.size();
         s.nV = 2 * (int)s.V_nodes.size();
         s.nG = s.nr + s.nV;
-        s.nc = 2 * (int)s.edges.size();
-        s.nP = s.nV + s.nc;
         s.primal.clear();
         for (int v : s.verts) { s.primal.push_back(2 * v); s.primal.push_back(2 * v + 1); }
-        for (int e : s.edges) {
-            s.primal.push_back(2 * nverts + 2 * e);
-            s.primal.push_back(2 * nverts + 2 * e + 1);
-        }
+        int ncon = 0;
+        s.edge_con.assign(s.edges.size(), -1);
+        s.face_con.assign(s.faces.size(), -1);
+        if (cons_edges)
+            for (size_t t = 0; t < s.edges.size(); ++t) {
+                s.edge_con[t] = ncon++;
+                s.primal.push_back(edge_p0 + 2 * s.edges[t]);
+                s.primal.push_back(edge_p0 + 2 * s.edges[t] + 1);
+            }
+        if (cons_faces)
+            for (size_t t = 0; t < s.faces.size(); ++t) {
+                s.face_con[t] = ncon++;
+                s.primal.push_back(face_p0 + 2 * s.faces[t]);
+                s.primal.push_back(face_p0 + 2 * s.faces[t] + 1);
+            }
+        s.nc = 2 * ncon;
+        s.nP = s.nV + s.nc;
         // box-local map
         const int Lx1 = s.Lx() + 1, Ly1 = s.Ly() + 1, Lz1 = s.Lz() + 1;
         s.lmap.assign((size_t)Lx1 * Ly1 * Lz1, -1);

@@ -1,7 +1,7 @@
 // Host-side check of the partition / N_x classification of libbidomain:
 // builds bdm::Topology for a mesh given on the command line and prints the
 // objects and per-subdomain dof counts in a line format the tests parse.
-//   topo_dump nx ny nz px py pz cuts_x... cuts_y... cuts_z...
+//   topo_dump nx ny nz px py pz cuts_x... cuts_y... cuts_z... [primal_space]
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -13,13 +13,15 @@ int main(int argc, char** argv) {
     int a = 1;
     const int nx = atoi(argv[a++]), ny = atoi(argv[a++]), nz = atoi(argv[a++]);
     const int px = atoi(argv[a++]), py = atoi(argv[a++]), pz = atoi(argv[a++]);
-    if (argc != 7 + (px + 1) + (py + 1) + (pz + 1)) return 2;
+    const int nargs = 7 + (px + 1) + (py + 1) + (pz + 1);
+    if (argc != nargs && argc != nargs + 1) return 2;
     std::vector<int> cx, cy, cz;
     for (int i = 0; i <= px; ++i) cx.push_back(atoi(argv[a++]));
     for (int i = 0; i <= py; ++i) cy.push_back(atoi(argv[a++]));
     for (int i = 0; i <= pz; ++i) cz.push_back(atoi(argv[a++]));
     bdm::Topology t;
-    const std::string err = t.build(nx, ny, nz, 0.01, px, py, pz, cx.data(), cy.data(), cz.data());
+    const int primal = argc == nargs + 1 ? atoi(argv[nargs]) : 0;
+    const std::string err = t.build(nx, ny, nz, 0.01, px, py, pz, cx.data(), cy.data(), cz.data(), primal);
     if (!err.empty()) {
         printf("ERROR %s\n", err.c_str());
         return 1;

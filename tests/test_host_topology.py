@@ -26,9 +26,13 @@ def topo_exe():
     return EXE
 
 
-def _dump(exe, mesh):
+PRIMAL_CODE = {"VE": 0, "V": 1, "VEF": 2}
+
+
+def _dump(exe, mesh, primal="VE"):
     args = [mesh.nx, mesh.ny, mesh.nz, len(mesh.cuts_x) - 1, len(mesh.cuts_y) - 1,
-            len(mesh.cuts_z) - 1] + list(mesh.cuts_x) + list(mesh.cuts_y) + list(mesh.cuts_z)
+            len(mesh.cuts_z) - 1] + list(mesh.cuts_x) + list(mesh.cuts_y) + list(mesh.cuts_z) \
+        + [PRIMAL_CODE[primal]]
     out = subprocess.run([exe] + [str(a) for a in args], capture_output=True, text=True, check=True).stdout
     objs, subs = [], []
     for line in out.splitlines():
@@ -51,13 +55,15 @@ MESHES = [
 ]
 
 
+@pytest.mark.parametrize("primal", ["VE", "V", "VEF"])
 @pytest.mark.parametrize("mesh", MESHES, ids=["cube8", "ragged", "uneven3x3x2"])
-def test_partition_matches_oracle(topo_exe, mesh):
+def test_partition_matches_oracle(topo_exe, mesh, primal):
     """Same faces / edges / vertices (sharing subdomains and nodes, in the same
     order), same interior and interface node lists per subdomain, same primal
-    numbering as the oracle's N_x classification (Sec. 4.1)."""
-    objs, subs = _dump(topo_exe, mesh)
-    dec = dd.Decomposition(mesh)
+    numbering as the oracle's N_x classification (Sec. 4.1), for each primal
+    space (Sec. 4.4)."""
+    objs, subs = _dump(topo_exe, mesh, primal)
+    dec = dd.Decomposition(mesh, primal)
     ref = ([("F", o.subs, tuple(o.nodes)) for o in dec.faces]
            + [("E", o.subs, tuple(o.nodes)) for o in dec.edges]
            + [("V", o.subs, tuple(o.nodes)) for o in dec.verts])
@@ -66,7 +72,7 @@ def test_partition_matches_oracle(topo_exe, mesh):
     for s, (h, I, r, prim) in enumerate(subs):
         info = dec.sub[s]
         assert h[0] == s
-        assert h[1:6] == [info.nI, info.nr, info.nV, 2 * len(info.edges), info.nV + 2 * len(info.edges)]
+        assert h[1:6] == [info.nI, info.nr, info.nV, 2 * len(info.cons), info.nV + 2 * len(info.cons)]
         assert I == list(info.I_nodes)
         assert r == list(info.r_nodes)
         assert prim == list(info.primal)
