@@ -170,5 +170,20 @@ def workload(name: str) -> Workload:
     raise KeyError(name)
 
 
+TEST3_SIDE = 0.32   # cm: 4 subdomains of H/h elements per axis, h = 0.01 cm at H/h = 8
+
+
+def test3(Hh: int, steps: int = 40) -> Workload:
+    """Slab of the optimality test (Sec. 6, Test 3): 4 x 4 x 4 subdomains of
+    H/h elements per axis in a cube of fixed side, so h = side / (4 H/h);
+    the stimulus covers a corner cube of side / 8 (H/h / 2 elements per axis)
+    for the first 20 steps, and the run covers 2 ms of activation (40 steps
+    of 0.05 ms) by default.  H/h must be even."""
+    if Hh < 2 or Hh % 2:
+        raise ValueError("H/h must be even and >= 2")
+    m = box_mesh(4 * Hh, 4 * Hh, 4 * Hh, TEST3_SIDE / (4 * Hh), 4, 4, 4)
+    return Workload(f"test3_Hh{Hh}", m, Physics(), Solver(), PAPER_STIM, (Hh // 2,) * 3, 20, steps, None)
+
+
 def small_mesh(n: Sequence[int], parts: Sequence[int], h: float = 0.01) -> Mesh:
     return box_mesh(n[0], n[1], n[2], h, parts[0], parts[1], parts[2])
