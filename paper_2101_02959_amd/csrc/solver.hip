@@ -1196,12 +1196,12 @@ int Context::newton_solve(const double* b, double* s, KrylovOut& out) {
         launch_axpy(stream_, 2 * N, 1.0, kx_, s);
         return 0;
     }
-    // FETI-DP: d = B S~^{-1} f~, PCG on F lambda = d, then recovery.
+    // FETI-DP: d = B S~^{-1} f~, PCG on F lambda = d, then recovery.  d
+    // (n_lambda values, which exceed 2N when the subdomains are small) stays
+    // in kq_: pcg copies its right-hand side before it first writes kq_.
     int rc = prec_ ? fetidp_apply_t<float>(BDM_FETI_RHS, Rt_, kq_) : fetidp_apply_t<double>(BDM_FETI_RHS, Rt_, kq_);
     if (rc) return rc;
-    double* d = S_;   // S_ is free until the solution is written
-    HIPOK(hipMemcpyAsync(d, kq_, nlam_ * sizeof(double), hipMemcpyDeviceToDevice, stream_));
-    rc = krylov((int)nlam_, d, kx_, true, out);
+    rc = krylov((int)nlam_, kq_, kx_, true, out);
     if (rc) return rc;
     // recover: input [b ; lambda]
     HIPOK(hipMemcpyAsync(kq_, Rt_, 2 * N * sizeof(double), hipMemcpyDeviceToDevice, stream_));

@@ -41,6 +41,8 @@ def run_case(P, wl, precision, scaling, primal):
         for k in range(wl.steps):
             st = S.bdm_step(1)
             nit = st.newton_its
+            print(f"  step {k}: newton {nit} pcg {list(st.krylov_its)[:nit]} {st.t_step_ms:.1f} ms",
+                  file=sys.stderr, flush=True)
             nits.append(nit)
             lits += list(st.krylov_its)[:nit]
             conds += list(st.cond)[:nit]

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from oracle import bddc, bidomain, dd, fetidp, newton
-from workload import Mesh, Physics, Solver as SolverOpts, stimulus_nodal, workload
+from workload import Mesh, Physics, Solver as SolverOpts, small_mesh, stimulus_nodal, workload
 
 pytestmark = pytest.mark.gpu
 
@@ -156,6 +156,33 @@ def test_time_steps_match_direct_newton(method, prec, reduced):
         print(step, method, prec, reduced, true_res)
         assert all(0 <= t <= (1e-9 if method == 0 else 1e-6) for t in true_res), true_res
         v, ue, w = vg, ueg, wg
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_fetidp_step_with_more_multipliers_than_dofs(graph):
+    """FETI-DP on subdomains of 2 x 2 x 2 elements: the fully redundant edge
+    multipliers outnumber the 2N dofs (2592 against 1458 here), so every
+    multiplier-sized work vector must be sized by n_lambda.  The Newton
+    solution matches the oracle's direct root."""
+    P = _solver_mod()
+    wl = workload("slab8_supra")
+    mesh = small_mesh((8, 8, 8), (4, 4, 4))
+    prob = bidomain.Problem(mesh, wl.physics, wl.solver.dt)
+    N = prob.N
+    S = P.Solver(mesh, wl.physics, wl.solver, precision=0, method=P.BDM_SOLVER_FETIDP, krylov_graph=graph)
+    try:
+        assert S.bdm_fetidp_size() > 2 * N
+        Is = stimulus_nodal(mesh, (2, 2, 2), 1e5)
+        S.bdm_set_state(np.zeros(N), np.zeros(N), np.zeros(N))
+        S.bdm_set_stimulus(Is, 0, 20)
+        st = S.bdm_step(1)
+        vg, ueg, _, _ = S.bdm_get_state()
+        z = np.zeros(N)
+        vr, uer, _, _ = bidomain.time_step_direct(prob, z, z, z, Is)
+        assert _rel(vg.cpu().numpy(), vr) <= 1e-8 and _rel(ueg.cpu().numpy(), uer) <= 1e-8
+        assert all(st.krylov_true_res[k] <= 1e-6 for k in range(st.newton_its))
+    finally:
+        S.close()
 
 
 def test_fetidp_step_needs_fp64_local_factors():

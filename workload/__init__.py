@@ -185,5 +185,21 @@ def test3(Hh: int, steps: int = 40) -> Workload:
     return Workload(f"test3_Hh{Hh}", m, Physics(), Solver(), PAPER_STIM, (Hh // 2,) * 3, 20, steps, None)
 
 
+TEST2_PARTS = ((12, 12, 2), (16, 16, 2), (16, 16, 4), (24, 24, 4), (32, 32, 4), (48, 48, 8))
+
+
+def test2(parts, steps: int = 40) -> Workload:
+    """The strong-scaling slab of Sec. 6, Test 2 (192 x 192 x 32 elements,
+    2,458,434 dofs, h = 0.01 cm) cut into parts = (px, py, pz) equal boxes,
+    corner stimulus as in the other slabs, 2 ms from rest by default.  The
+    partitions in TEST2_PARTS range from 288 subdomains of 16 x 16 x 16
+    elements to 18,432 of 4 x 4 x 4."""
+    px, py, pz = parts
+    if 192 % px or 192 % py or 32 % pz:
+        raise ValueError("parts must divide 192 x 192 x 32")
+    m = box_mesh(192, 192, 32, 0.01, px, py, pz)
+    return Workload(f"test2_{px}x{py}x{pz}", m, Physics(), Solver(), PAPER_STIM, (2, 2, 2), 20, steps, None)
+
+
 def small_mesh(n: Sequence[int], parts: Sequence[int], h: float = 0.01) -> Mesh:
     return box_mesh(n[0], n[1], n[2], h, parts[0], parts[1], parts[2])
