@@ -9,7 +9,6 @@
 
 namespace bdm {
 
-constexpr int MAXO = 512;       // largest face / edge object (dofs)
 
 namespace {
 
@@ -58,14 +57,21 @@ __global__ void k_scatter_I(int n, const int* __restrict__ list, int64_t N, cons
 // row) pair, four independent accumulators along the row, so a face's two
 // shares keep two thirds of the workgroup busy and the reads of E_m are
 // coalesced across the rows.
-template <typename T>
+// Objects of at most DLX_SMALL dofs (every face and edge of subdomains up to
+// H/h = 16) stage their vectors in static LDS of fixed stride; BIG launches
+// take dynamic LDS sized by the largest object of the mesh.
+constexpr int DLX_SMALL = 512;
+
+template <typename T, bool BIG>
 __global__ __launch_bounds__(kWG) void k_deluxe_res(ObjDesc o, int64_t N, const double* __restrict__ g,
                                                    const T* __restrict__ dmat, T* __restrict__ xr,
                                                    const int64_t* __restrict__ xoff) {
     constexpr int NA = 4;   // independent accumulators along the row
     const int ob = blockIdx.x, tid = threadIdx.x;
     const int n = o.n[ob];
-    __shared__ double h[MAXO];
+    extern __shared__ double h_dyn[];   // BIG: o.maxn values
+    __shared__ double h_st[BIG ? 1 : DLX_SMALL];
+    double* h = BIG ? h_dyn : h_st;
     const int* nodes = o.nodes + o.node_off[ob];
     for (int i = tid; i < n; i += kWG) h[i] = g[(i & 1) * N + nodes[i >> 1]];
     __syncthreads();
@@ -89,10 +95,11 @@ __global__ __launch_bounds__(kWG) void k_deluxe_res(ObjDesc o, int64_t N, const 
 // Value side of the deluxe scaling, E_D: u = (sum S)^{-1} sum_m S^(m) u^(m)
 // = sum_m E_m^T u^(m), with the transposes E_m^T stored beside E_m (Et), so
 // the reads are coalesced across the output rows.  The shares' u^(m) are
-// staged in LDS; threads take (row, half of the inner range), four
-// accumulators each, and the two halves are added through LDS.
+// staged in LDS (DV_SH rows of o.maxn values); threads take (row, half of
+// the inner range), four accumulators each, and the two halves are added
+// through LDS.
 constexpr int DV_SH = 4;   // shares per object: 2 on a face, up to 4 on an edge
-template <typename T>
+template <typename T, bool BIG>
 __global__ __launch_bounds__(kWG) void k_deluxe_val(ObjDesc o, int64_t N, const T* __restrict__ Et,
                                                    const T* __restrict__ xr, const int64_t* __restrict__ xoff,
                                                    double* __restrict__ z) {
@@ -101,11 +108,14 @@ __global__ __launch_bounds__(kWG) void k_deluxe_val(ObjDesc o, int64_t N, const 
     const int n = o.n[ob];
     const int* nodes = o.nodes + o.node_off[ob];
     const int q0 = o.sh_ptr[ob], nsh = o.sh_ptr[ob + 1] - q0;
-    __shared__ double us[DV_SH][MAXO];
+    extern __shared__ double us_dyn[];   // BIG: [DV_SH][o.maxn]
+    __shared__ double us_st[BIG ? 1 : DV_SH * DLX_SMALL];
     __shared__ double part[kWG];
+    double* us = BIG ? us_dyn : us_st;
+    const int64_t ld = BIG ? (int64_t)o.maxn : (int64_t)DLX_SMALL;
     for (int t = tid; t < nsh * n; t += kWG) {
         const int q = t / n, j = t % n;
-        us[q][j] = (double)xr[xoff[o.sh_sub[q0 + q]] + o.sh_roff[q0 + q] + j];
+        us[q * ld + j] = (double)xr[xoff[o.sh_sub[q0 + q]] + o.sh_roff[q0 + q] + j];
     }
     __syncthreads();
     const int half = (n + 1) / 2, hp = tid / (kWG / 2), il = tid % (kWG / 2);
@@ -118,7 +128,7 @@ __global__ __launch_bounds__(kWG) void k_deluxe_val(ObjDesc o, int64_t N, const 
             const int jb = hp * half, je = min(n, jb + half);
             for (int q = 0; q < nsh; ++q) {
                 const T* F = Et + o.sh_slot[q0 + q] + i;
-                const double* u = us[q];
+                const double* u = us + q * ld;
                 int j = jb;
                 for (; j + NA <= je; j += NA) {
 #pragma unroll
@@ -437,12 +447,20 @@ void launch_scatter_I(hipStream_t s, int n, const int* list, int64_t N, const T*
 template <typename T>
 void launch_deluxe_res(hipStream_t s, const ObjDesc& o, int64_t N, const double* g, const T* dmat, T* xr,
                        const int64_t* xoff) {
-    hipLaunchKernelGGL(k_deluxe_res<T>, dim3(o.nobj), dim3(kWG), 0, s, o, N, g, dmat, xr, xoff);
+    if (o.maxn <= DLX_SMALL)
+        hipLaunchKernelGGL((k_deluxe_res<T, false>), dim3(o.nobj), dim3(kWG), 0, s, o, N, g, dmat, xr, xoff);
+    else
+        hipLaunchKernelGGL((k_deluxe_res<T, true>), dim3(o.nobj), dim3(kWG), (size_t)o.maxn * sizeof(double), s,
+                           o, N, g, dmat, xr, xoff);
 }
 template <typename T>
 void launch_deluxe_val(hipStream_t s, const ObjDesc& o, int64_t N, const T* dmatT, const T* xr,
                        const int64_t* xoff, double* z) {
-    hipLaunchKernelGGL(k_deluxe_val<T>, dim3(o.nobj), dim3(kWG), 0, s, o, N, dmatT, xr, xoff, z);
+    if (o.maxn <= DLX_SMALL)
+        hipLaunchKernelGGL((k_deluxe_val<T, false>), dim3(o.nobj), dim3(kWG), 0, s, o, N, dmatT, xr, xoff, z);
+    else
+        hipLaunchKernelGGL((k_deluxe_val<T, true>), dim3(o.nobj), dim3(kWG), (size_t)DV_SH * o.maxn * sizeof(double),
+                           s, o, N, dmatT, xr, xoff, z);
 }
 template <typename T>
 void launch_deluxe_transpose(hipStream_t s, const ObjDesc& o, const T* dmat, T* dmatT) {

@@ -142,6 +142,7 @@ struct ObjDesc {
     const int* sh_sub;     // sharing subdomain
     const int* sh_roff;    // offset of the object in that subdomain's r-dofs
     const int64_t* sh_slot;// that subdomain's block S^(m) (n x n)
+    int maxn = 0;          // largest object (dofs): sizes the LDS of the deluxe applies
 };
 // Deluxe setup of the objects [ob0, ob0 + nob): E_m = S^(m) (sum S)^{-1}
 // into dmat; maxn bounds their sizes (at most deluxe_max_object()) and sets

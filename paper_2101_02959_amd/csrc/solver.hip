@@ -27,7 +27,7 @@ static void* ctx_alloc(void* c, size_t bytes) {
     static_cast<std::vector<void*>*>(c)->push_back(p);
     return p;
 }
-constexpr int MAXOBJ = 512;
+constexpr int MAXOBJ = 1024;   // largest face / edge (dofs)
 
 template <typename T>
 __global__ void k_sub_t(int64_t n, const T* __restrict__ x, T* __restrict__ y) {
@@ -383,7 +383,7 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
     bd_.so_ptr = upload(so_ptr); bd_.so_roff = upload(so_roff); bd_.so_n = upload(so_n);
     bd_.so_slot = upload(so_slot); bd_.so_kind = upload(so_kind); bd_.so_nnode = upload(so_nnode);
     bd_.so_eidx = upload(so_eidx); bd_.Srr_off = upload(Srr_off);
-    od_.nobj = nobj; od_.n = upload(on); od_.node_off = upload(onode_off); od_.nodes = upload(onodes);
+    od_.nobj = nobj; od_.maxn = maxobjn_; od_.n = upload(on); od_.node_off = upload(onode_off); od_.nodes = upload(onodes);
     od_.fac_off = upload(ofac); od_.sh_ptr = upload(sh_ptr); od_.sh_sub = upload(sh_sub);
     od_.sh_roff = upload(sh_roff); od_.sh_slot = upload(sh_slot);
     sv_.nsub = nsub; sv_.nr = bd_.nr; sv_.nV = bd_.nV; sv_.nc = bd_.nc;

@@ -125,3 +125,30 @@ def test_time_step_matches_oracle_on_4x4x4(scaling, primal):
         assert abs(st.krylov_its[k] - ost.krylov_its[k]) <= 1, (k, st.krylov_its[k], ost.krylov_its[k])
         assert st.cond[k] == pytest.approx(ost.conds[k], rel=2e-2)
         assert st.krylov_true_res[k] <= 1e-9
+
+
+@pytest.mark.parametrize("scaling", list(SCALING))
+def test_objects_above_512_dofs(scaling):
+    """Faces of more than 512 dofs (289 nodes, boundary rows included, on
+    the z-cut of a 34 x 34 x 4 slab in 2 x 2 x 2 subdomains): the deluxe
+    factorisation works on the matrix in global memory and the applies stage
+    their vectors in LDS sized by the largest object.  One BDDC application
+    in FP64 against the oracle."""
+    import paper_2101_02959_amd as P
+    mesh = Mesh(34, 34, 4, 0.01, (0, 17, 34), (0, 17, 34), (0, 2, 4))
+    ph, so = Physics(), SolverOpts()
+    prob = bidomain.Problem(mesh, ph, so.dt)
+    N = prob.N
+    dec = dd.Decomposition(mesh)
+    assert max(2 * len(o.nodes) for o in dec.faces) > 512
+    v, w = _state(N, 4)
+    B = bddc.BDDC(prob, dec, v, w, scaling=scaling)
+    r = newton.project_range(np.random.default_rng(5).standard_normal(2 * N), N)
+    zref = _gauge(B.apply(r), N)
+    S = P.Solver(mesh, ph, so, precision=0, scaling=SCALING[scaling])
+    try:
+        S.bdm_linearize(v, w)
+        z = _gauge(S.bdm_bddc_apply(r).cpu().numpy(), N)
+        assert _rel(z, zref) < 1e-11, _rel(z, zref)
+    finally:
+        S.close()

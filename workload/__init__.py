@@ -201,5 +201,19 @@ def test2(parts, steps: int = 40) -> Workload:
     return Workload(f"test2_{px}x{py}x{pz}", m, Physics(), Solver(), PAPER_STIM, (2, 2, 2), 20, steps, None)
 
 
+def test4(parts=(24, 12, 3), steps: int = 2400) -> Workload:
+    """The whole-beat slab of Sec. 6, Test 4: 192 x 96 x 24 elements in equal
+    box subdomains (the paper uses 8 x 8 x 2), corner stimulus, 2400 steps
+    of 0.05 ms (120 ms: activation and recovery).  The mesh keeps cubic
+    elements of h = 0.01 cm (1.92 x 0.96 x 0.24 cm); the paper's slab of
+    1.92 x 1.92 x 0.48 cm on the same element counts has elements of
+    0.01 x 0.02 x 0.02 cm, which a single h cannot express."""
+    px, py, pz = parts
+    if 192 % px or 96 % py or 24 % pz:
+        raise ValueError("parts must divide 192 x 96 x 24")
+    m = box_mesh(192, 96, 24, 0.01, px, py, pz)
+    return Workload(f"test4_{px}x{py}x{pz}", m, Physics(), Solver(), PAPER_STIM, (2, 2, 2), 20, steps, None)
+
+
 def small_mesh(n: Sequence[int], parts: Sequence[int], h: float = 0.01) -> Mesh:
     return box_mesh(n[0], n[1], n[2], h, parts[0], parts[1], parts[2])
