@@ -10,6 +10,7 @@
 // float (local factors in FP32 under the FP64 outer iteration).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <type_traits>
 
 #include "common.hpp"
@@ -1580,7 +1581,24 @@ void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, int ob0, int nob, int 
         lds_max = v;
     }
     if (maxn > DS_MIN && maxn <= DS_N) {
-        const int avail = lds_max - (int)(2 * DS_N * sizeof(T)) - 64;
+        // The register sweep is latency-bound, so the LDS kept for the inverse
+        // is sized for several resident workgroups per CU rather than for the
+        // largest face: objects whose inverse does not fit keep it in their
+        // global workspace (same arithmetic).  BDM_DELUXE_WG_PER_CU (1-16)
+        // overrides the target.
+        static int lds_cu = -1, per_cu = -1;
+        if (lds_cu < 0) {
+            int dev = 0, v = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+                v <= 0)
+                v = lds_max;
+            lds_cu = v;
+            per_cu = 4;
+            if (const char* e = std::getenv("BDM_DELUXE_WG_PER_CU")) per_cu = std::min(16, std::max(1, std::atoi(e)));
+        }
+        const int stat = (int)(2 * DS_N * sizeof(T)) + 64;
+        const int avail = std::min(lds_max, lds_cu / per_cu) - stat;
         const int cap = std::max(0, std::min(maxn * maxn, avail / (int)sizeof(T)));
         hipLaunchKernelGGL(k_deluxe_small<T>, dim3(nob), dim3(kWG), (size_t)cap * sizeof(T), s, o, slots, fac, dmat,
                            info, cap, ob0);
