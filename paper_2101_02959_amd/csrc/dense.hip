@@ -43,15 +43,6 @@ template <> struct Mfma<double> {
     static __device__ inline int row(int lane, int v) { return (lane >> 4) + 4 * v; }
 };
 
-__device__ inline double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-__device__ inline float wave_sum(float v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
 // -------------------------------------------------------------- assembly
 // K^(j) of the Jacobian bilinear form restricted to Omega_j (Sec. 4.1) in
 // the congruent (v, u_e) form: per node pair (P, Q) the 2x2 block
@@ -847,20 +838,6 @@ __global__ __launch_bounds__(kWG) void k_trsm_fwd(const T* __restrict__ Lb, cons
     }
 }
 
-// Dot product of two length-n columns by one wave (lanes down the rows, two
-// accumulators, one wave sum); every lane returns the sum.
-template <typename T>
-__device__ __forceinline__ double wave_dot(const T* __restrict__ a, const T* __restrict__ b, int n, int lane) {
-    double s0 = 0.0, s1 = 0.0;
-    int r = lane;
-    for (; r + 64 < n; r += 128) {
-        s0 += (double)a[r] * (double)b[r];
-        s1 += (double)a[r + 64] * (double)b[r + 64];
-    }
-    if (r < n) s0 += (double)a[r] * (double)b[r];
-    return wave_sum(s0 + s1);
-}
-
 // ------------------------------------------------------- coarse algebra
 // With Y = L_rr^{-1} C^T and X = -L_rr^{-1} S_rV (from k_trsm_fwd), the
 // energy-minimising coarse basis of Sec. 4.4 under the average constraints
@@ -869,7 +846,10 @@ __device__ __forceinline__ double wave_dot(const T* __restrict__ a, const T* __r
 //   Z = [X - Y mu_V | Y G^{-1}]   (vertex primals, then average primals),
 // and the local coarse matrix Phi^T S_Gamma Phi is
 //   vertex rows: [-X^T Z + [S_VV | 0]],   average rows: [-mu_V | G^{-1}].
-// With vertex primals only (no constraints) Z = X.
+// With vertex primals only (no constraints) Z = X.  Every inner product the
+// algebra needs is an entry of the Gram matrix of W = [Y | X]: G = Y^T Y,
+// Y^T X, and X^T Z = [X^T X - (Y^T X)^T mu_V | (Y^T X)^T G^{-1}], so one pass
+// over the rows of W (in FP64) replaces a pass per product.
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_coarse_local(BatchDesc d, const T* __restrict__ Fb,
                                                      const double* __restrict__ Svv, T* __restrict__ Zb,
@@ -885,22 +865,59 @@ __global__ __launch_bounds__(kWG) void k_coarse_local(BatchDesc d, const T* __re
     __shared__ double Gi[MAXC][MAXC + 1];
     __shared__ double YtX[MAXC][MAXV + 1];
     __shared__ double muV[MAXC][MAXV + 1];
-    // G = Y^T Y and Y^T X: one wave per column pair, lanes down the rows
-    // (coalesced), pairs spread over the waves
-    const int wv = tid >> 6, lane = tid & 63;
-    for (int idx = wv; idx < nc * nc + nc * nV; idx += kWG / 64) {
-        if (idx < nc * nc) {
-            const int i = idx % nc, j = idx / nc;
-            if (j > i) continue;
-            const double acc = wave_dot(Y + (int64_t)i * nr, Y + (int64_t)j * nr, nr, lane);
-            if (lane == 0) {
-                G[i][j] = acc;
-                G[j][i] = acc;
+    __shared__ double XtX[MAXV][MAXV + 1];
+    // Gram matrix of W = [Y | X] (nr x nP, column-major: X follows Y): rows
+    // in chunks of GR staged in LDS, each thread accumulating up to GP
+    // lower-triangle entries in FP64, the rows in order.
+    {
+        constexpr int GR = 32, GP = (MAXP * (MAXP + 1) / 2 + kWG - 1) / kWG;
+        __shared__ double wc[GR][MAXP + 1];
+        const int npair = nP * (nP + 1) / 2;
+        int pi[GP], pj[GP];
+        double g[GP];
+#pragma unroll
+        for (int u = 0; u < GP; ++u) {
+            const int p = tid + kWG * u;
+            int i = 0;
+            if (p < npair) {
+                i = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+                while (i * (i + 1) / 2 > p) --i;
+                while ((i + 1) * (i + 2) / 2 <= p) ++i;
             }
-        } else {
-            const int i = (idx - nc * nc) % nc, q = (idx - nc * nc) / nc;
-            const double acc = wave_dot(Y + (int64_t)i * nr, X + (int64_t)q * nr, nr, lane);
-            if (lane == 0) YtX[i][q] = acc;
+            pi[u] = i;
+            pj[u] = p < npair ? p - i * (i + 1) / 2 : 0;
+            g[u] = 0.0;
+        }
+        for (int r0 = 0; r0 < nr; r0 += GR) {
+            const int rows = min(GR, nr - r0);
+            __syncthreads();   // the previous chunk has been consumed
+            for (int idx = tid; idx < GR * nP; idx += kWG) {
+                const int rr = idx % GR, c = idx / GR;
+                wc[rr][c] = (rr < rows) ? (double)Y[(int64_t)c * nr + r0 + rr] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < GP; ++u) {
+                if (tid + kWG * u < npair) {
+                    double a = g[u];
+                    for (int rr = 0; rr < GR; ++rr) a += wc[rr][pi[u]] * wc[rr][pj[u]];
+                    g[u] = a;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < GP; ++u) {
+            if (tid + kWG * u >= npair) continue;
+            const int i = pi[u], j = pj[u];   // i >= j
+            if (i < nc) {
+                G[i][j] = g[u];
+                G[j][i] = g[u];
+            } else if (j < nc) {
+                YtX[j][i - nc] = g[u];
+            } else {
+                XtX[i - nc][j - nc] = g[u];
+                XtX[j - nc][i - nc] = g[u];
+            }
         }
     }
     __syncthreads();
@@ -991,10 +1008,17 @@ __global__ __launch_bounds__(kWG) void k_coarse_local(BatchDesc d, const T* __re
     __syncthreads();
     double* Sp = Spb + (int64_t)s * SP_STRIDE;
     const double* sv = Svv + (int64_t)s * SVV_STRIDE;
-    for (int idx = wv; idx < nV * nP; idx += kWG / 64) {
+    for (int idx = tid; idx < nV * nP; idx += kWG) {
         const int q = idx % nV, pcol = idx / nV;
-        const double acc = wave_dot(X + (int64_t)q * nr, Z + (int64_t)pcol * nr, nr, lane);
-        if (lane == 0) Sp[q + (int64_t)pcol * nP] = -acc + (pcol < nV ? sv[q + pcol * nV] : 0.0);
+        double acc;   // X^T Z, column pcol
+        if (pcol < nV) {
+            acc = XtX[q][pcol];
+            for (int m = 0; m < nc; ++m) acc -= YtX[m][q] * muV[m][pcol];
+        } else {
+            acc = 0.0;
+            for (int m = 0; m < nc; ++m) acc += YtX[m][q] * Gi[m][pcol - nV];
+        }
+        Sp[q + (int64_t)pcol * nP] = -acc + (pcol < nV ? sv[q + pcol * nV] : 0.0);
     }
     for (int idx = tid; idx < nc * nP; idx += kWG) {
         const int e = idx % nc, pcol = idx / nc;
