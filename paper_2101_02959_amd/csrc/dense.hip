@@ -1618,7 +1618,7 @@ void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, int ob0, int nob, int 
                 v <= 0)
                 v = lds_max;
             lds_cu = v;
-            per_cu = 4;
+            per_cu = 6;
             if (const char* e = std::getenv("BDM_DELUXE_WG_PER_CU")) per_cu = std::min(16, std::max(1, std::atoi(e)));
         }
         const int stat = (int)(2 * DS_N * sizeof(T)) + 64;
