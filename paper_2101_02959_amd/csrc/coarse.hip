@@ -6,7 +6,7 @@
 // plane x = X (vertices, y- and z-edges, x-faces there) separate those of the
 // subdomain columns left of X from those right of it.  Recursive bisection of
 // the subdomain grid along its longest axis gives a nested-dissection order
-// and its elimination tree of fronts; boxes of at most 8 subdomains are the
+// and its elimination tree of fronts; boxes of at most 64 subdomains are the
 // leaves.  Each front holds its eliminated objects (the separator, or all
 // objects inside a leaf box) followed by its boundary objects (those on the
 // box faces that belong to its subdomains).
@@ -29,6 +29,7 @@
 //                        z_b then travels to the parent (extend-add);
 //   backward (top down)  x_e = L_ee^{-T} (y - L_be^T x_b) = X t.
 #include <algorithm>
+#include <cstdlib>
 #include <functional>
 #include <vector>
 
@@ -262,6 +263,11 @@ std::string CoarseSolver::init(const Topology& t, int pin_, int maxp_) {
     };
     std::vector<Tmp> tf;
     std::vector<int> mark(nobj, -1), leaf_of(nsub, -1);
+    // largest leaf box (subdomains): 4 x 4 x 4 leaves, measured against 2 x 2 x 2
+    // (12 against 9 tree levels at 32 x 32 x 16 subdomains, whose per-level
+    // launches dominate the upper levels); BDM_COARSE_LEAF_SUBS overrides
+    int64_t leaf_max = 64;
+    if (const char* e = std::getenv("BDM_COARSE_LEAF_SUBS")) leaf_max = std::max(1, std::atoi(e));
     int stampc = 0;
     std::function<int(const int*, const int*, std::vector<int>&)> nd =
         [&](const int* lo, const int* hi, std::vector<int>& inner) -> int {
@@ -270,7 +276,7 @@ std::string CoarseSolver::init(const Topology& t, int pin_, int maxp_) {
         for (int d = 1; d < 3; ++d)
             if (ext[d] > ext[ax]) ax = d;
         Tmp fr;
-        if ((int64_t)ext[0] * ext[1] * ext[2] <= 8 || ext[ax] < 2) {
+        if ((int64_t)ext[0] * ext[1] * ext[2] <= leaf_max || ext[ax] < 2) {
             fr.elim = inner;
             const int st = stampc++;
             for (int o : inner) mark[o] = st;

@@ -201,6 +201,30 @@ def test_fetidp_step_needs_fp64_local_factors():
         S.close()
 
 
+@pytest.mark.parametrize("mname,leaf", [("uneven442", "8"), ("uneven442", "64")])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 5e-5)])
+def test_coarse_tree_shapes(mname, leaf, prec, tol, monkeypatch):
+    """The coarse nested dissection with leaf boxes of at most 8 subdomains
+    (a multi-level elimination tree on the 4 x 4 x 2 grid) and 64 (the
+    default: one dense front there): the same BDDC application against the
+    oracle."""
+    P = _solver_mod()
+    monkeypatch.setenv("BDM_COARSE_LEAF_SUBS", leaf)
+    mesh = MESHES[mname]
+    prob = bidomain.Problem(mesh, Physics(), SolverOpts().dt)
+    N = prob.N
+    v, ue, w = _state(N, 12)
+    B = bddc.BDDC(prob, dd.Decomposition(mesh), v, w)
+    r = newton.project_range(np.random.default_rng(13).standard_normal(2 * N), N)
+    zref = _gauge(B.apply(r), N)
+    S = P.Solver(mesh, Physics(), SolverOpts(), precision=prec)
+    try:
+        S.bdm_linearize(v, w)
+        assert _rel(_gauge(S.bdm_bddc_apply(r).cpu().numpy(), N), zref) < tol
+    finally:
+        S.close()
+
+
 def test_bddc_chunked_setup(lin, monkeypatch):
     """Setup in chunks of a few subdomains gives the same operator."""
     P = _solver_mod()
