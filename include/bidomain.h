@@ -75,7 +75,7 @@ enum { BDM_PRIMAL_VE = 0, BDM_PRIMAL_V = 1, BDM_PRIMAL_VEF = 2 };
  * tensor-product partition into non-overlapping box subdomains (Sec. 4.1):
  * cuts_x[0..px] are element indices with cuts_x[0] = 0, cuts_x[px] = nx,
  * strictly increasing; likewise y, z.  px, py, pz >= 2 (every subdomain must
- * touch an interior cross point for the vertex + edge primal space). */
+ * touch an interior cross point: every primal space holds the vertex values). */
 typedef struct bdm_mesh {
     int nx, ny, nz;
     double h;
@@ -186,10 +186,11 @@ int bdm_residual(bdm_ctx* ctx, const double* v, const double* ue, double* Rv, do
 
 /* Build the Jacobian (Sec. 3c) at (v_lin, w_lin) (device, N each) and every
  * preconditioner factor: local Dirichlet factors of K_II, local Schur
- * complements, constrained Neumann factors with edge-average constraints,
- * the coarse basis and coarse matrix (Sec. 4.4), and the deluxe face / edge
- * factors (Sec. 4.2).  Returns BDM_E_COERCIVITY if a reaction diagonal is
- * not positive and BDM_E_NOT_SPD if a factorisation fails. */
+ * complements, constrained Neumann factors with the average constraints of
+ * the primal space (opts.primal), the coarse basis and coarse matrix
+ * (Sec. 4.4), and the face / edge scaling matrices (Sec. 4.2: deluxe
+ * factors, or the rho weights).  Returns BDM_E_COERCIVITY if a reaction
+ * diagonal is not positive and BDM_E_NOT_SPD if a factorisation fails. */
 int bdm_linearize(bdm_ctx* ctx, const double* v_lin, const double* w_lin);
 
 /* y = J x for 2N device vectors (matrix-free Q1 stencils, Sec. 3a-c). */

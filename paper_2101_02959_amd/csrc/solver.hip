@@ -426,7 +426,7 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
     std::vector<int> zi(1, 0), npv(1, np);
     zero64_ = upload(z64); cpin_ = upload(zi); np_ = upload(npv);
     one_ = upload(npv);
-    // pin: the u_e dof of the first vertex (or of the first edge average)
+    // pin: the u_e dof of the first vertex (every primal space has vertices)
     pin_ = 1;
     // coarse problem: nested dissection of the subdomain grid
     {
