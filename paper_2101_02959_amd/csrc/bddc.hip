@@ -53,14 +53,16 @@ __global__ void k_scatter_I(int n, const int* __restrict__ list, int64_t N, cons
 }
 
 // Residual side of the deluxe scaling, E_D^T: for every share m of the
-// object, y^(m) = E_m g (g gathered once into LDS).  One thread per (share,
-// row) pair, four independent accumulators along the row, so a face's two
-// shares keep two thirds of the workgroup busy and the reads of E_m are
-// coalesced across the rows.
+// object, y^(m) = E_m g (g gathered once into LDS).  The scaling matrices of
+// an object sum to the identity, so the last share's split is g minus the
+// others' and its matrix is never read (half the matrix traffic of a face).
+// One thread per (share, row) pair, four independent accumulators along the
+// row, so the reads of E_m are coalesced across the rows.
 // Objects of at most DLX_SMALL dofs (every face and edge of subdomains up to
 // H/h = 16) stage their vectors in static LDS of fixed stride; BIG launches
 // take dynamic LDS sized by the largest object of the mesh.
 constexpr int DLX_SMALL = 512;
+constexpr int DV_SH = 4;   // shares per object: 2 on a face, up to 4 on an edge
 
 template <typename T, bool BIG>
 __global__ __launch_bounds__(kWG) void k_deluxe_res(ObjDesc o, int64_t N, const double* __restrict__ g,
@@ -69,15 +71,17 @@ __global__ __launch_bounds__(kWG) void k_deluxe_res(ObjDesc o, int64_t N, const 
     constexpr int NA = 4;   // independent accumulators along the row
     const int ob = blockIdx.x, tid = threadIdx.x;
     const int n = o.n[ob];
-    extern __shared__ double h_dyn[];   // BIG: o.maxn values
-    __shared__ double h_st[BIG ? 1 : DLX_SMALL];
-    double* h = BIG ? h_dyn : h_st;
+    extern __shared__ double r_dyn[];   // BIG: DV_SH rows of o.maxn values (g, then the splits)
+    __shared__ double r_st[BIG ? 1 : DV_SH * DLX_SMALL];
+    double* h = BIG ? r_dyn : r_st;
+    const int64_t ld = BIG ? (int64_t)o.maxn : (int64_t)DLX_SMALL;
+    double* ys = h + ld;                // splits of the shares before the last
     const int* nodes = o.nodes + o.node_off[ob];
     for (int i = tid; i < n; i += kWG) h[i] = g[(i & 1) * N + nodes[i >> 1]];
     __syncthreads();
-    const int q0 = o.sh_ptr[ob], nsh = o.sh_ptr[ob + 1] - q0;
-    for (int t = tid; t < nsh * n; t += kWG) {
-        const int q = q0 + t / n, i = t % n;
+    const int q0 = o.sh_ptr[ob], nm = o.sh_ptr[ob + 1] - q0 - 1;
+    for (int t = tid; t < nm * n; t += kWG) {
+        const int qq = t / n, i = t % n, q = q0 + qq;
         const T* E = dmat + o.sh_slot[q] + i;
         double a[NA];
 #pragma unroll
@@ -88,17 +92,26 @@ __global__ __launch_bounds__(kWG) void k_deluxe_res(ObjDesc o, int64_t N, const 
             for (int u = 0; u < NA; ++u) a[u] += (double)E[(int64_t)(j + u) * n] * h[j + u];
         }
         for (; j < n; ++j) a[0] += (double)E[(int64_t)j * n] * h[j];
-        xr[xoff[o.sh_sub[q]] + o.sh_roff[q] + i] = (T)tree_sum<NA>(a);
+        const double y = tree_sum<NA>(a);
+        ys[qq * ld + i] = y;
+        xr[xoff[o.sh_sub[q]] + o.sh_roff[q] + i] = (T)y;
+    }
+    __syncthreads();
+    const int ql = q0 + nm;
+    for (int i = tid; i < n; i += kWG) {
+        double y = h[i];
+        for (int qq = 0; qq < nm; ++qq) y -= ys[qq * ld + i];
+        xr[xoff[o.sh_sub[ql]] + o.sh_roff[ql] + i] = (T)y;
     }
 }
 
 // Value side of the deluxe scaling, E_D: u = (sum S)^{-1} sum_m S^(m) u^(m)
-// = sum_m E_m^T u^(m), with the transposes E_m^T stored beside E_m (Et), so
-// the reads are coalesced across the output rows.  The shares' u^(m) are
-// staged in LDS (DV_SH rows of o.maxn values); threads take (row, half of
-// the inner range), four accumulators each, and the two halves are added
-// through LDS.
-constexpr int DV_SH = 4;   // shares per object: 2 on a face, up to 4 on an edge
+// = sum_m E_m^T u^(m) = u^(last) + sum_{m < last} E_m^T (u^(m) - u^(last)),
+// since the matrices sum to the identity; the transposes E_m^T are stored
+// beside E_m (Et), so the reads are coalesced across the output rows.  The
+// differences and u^(last) are staged in LDS (DV_SH rows of o.maxn values);
+// threads take (row, half of the inner range), four accumulators each, and
+// the two halves are added through LDS.
 template <typename T, bool BIG>
 __global__ __launch_bounds__(kWG) void k_deluxe_val(ObjDesc o, int64_t N, const T* __restrict__ Et,
                                                    const T* __restrict__ xr, const int64_t* __restrict__ xoff,
@@ -113,9 +126,13 @@ __global__ __launch_bounds__(kWG) void k_deluxe_val(ObjDesc o, int64_t N, const 
     __shared__ double part[kWG];
     double* us = BIG ? us_dyn : us_st;
     const int64_t ld = BIG ? (int64_t)o.maxn : (int64_t)DLX_SMALL;
-    for (int t = tid; t < nsh * n; t += kWG) {
+    const int nm = nsh - 1;
+    double* ul = us + nm * ld;   // u^(last)
+    for (int j = tid; j < n; j += kWG) ul[j] = (double)xr[xoff[o.sh_sub[q0 + nm]] + o.sh_roff[q0 + nm] + j];
+    __syncthreads();
+    for (int t = tid; t < nm * n; t += kWG) {
         const int q = t / n, j = t % n;
-        us[q * ld + j] = (double)xr[xoff[o.sh_sub[q0 + q]] + o.sh_roff[q0 + q] + j];
+        us[q * ld + j] = (double)xr[xoff[o.sh_sub[q0 + q]] + o.sh_roff[q0 + q] + j] - ul[j];
     }
     __syncthreads();
     const int half = (n + 1) / 2, hp = tid / (kWG / 2), il = tid % (kWG / 2);
@@ -126,7 +143,7 @@ __global__ __launch_bounds__(kWG) void k_deluxe_val(ObjDesc o, int64_t N, const 
         for (int v = 0; v < NA; ++v) a[v] = 0.0;
         if (i < n) {
             const int jb = hp * half, je = min(n, jb + half);
-            for (int q = 0; q < nsh; ++q) {
+            for (int q = 0; q < nm; ++q) {
                 const T* F = Et + o.sh_slot[q0 + q] + i;
                 const double* u = us + q * ld;
                 int j = jb;
@@ -139,7 +156,7 @@ __global__ __launch_bounds__(kWG) void k_deluxe_val(ObjDesc o, int64_t N, const 
         }
         part[tid] = tree_sum<NA>(a);
         __syncthreads();
-        if (hp == 0 && i < n) z[(i & 1) * N + nodes[i >> 1]] = part[tid] + part[tid + kWG / 2];
+        if (hp == 0 && i < n) z[(i & 1) * N + nodes[i >> 1]] = (part[tid] + part[tid + kWG / 2]) + ul[i];
         __syncthreads();
     }
 }
@@ -450,7 +467,7 @@ void launch_deluxe_res(hipStream_t s, const ObjDesc& o, int64_t N, const double*
     if (o.maxn <= DLX_SMALL)
         hipLaunchKernelGGL((k_deluxe_res<T, false>), dim3(o.nobj), dim3(kWG), 0, s, o, N, g, dmat, xr, xoff);
     else
-        hipLaunchKernelGGL((k_deluxe_res<T, true>), dim3(o.nobj), dim3(kWG), (size_t)o.maxn * sizeof(double), s,
+        hipLaunchKernelGGL((k_deluxe_res<T, true>), dim3(o.nobj), dim3(kWG), (size_t)DV_SH * o.maxn * sizeof(double), s,
                            o, N, g, dmat, xr, xoff);
 }
 template <typename T>
