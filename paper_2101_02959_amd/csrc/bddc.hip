@@ -213,19 +213,18 @@ __global__ __launch_bounds__(kWG) void k_rho_fill(ObjDesc o, const double* __res
 // Per subdomain after the forward Neumann solve x1 = L_rr^{-1} g_r:
 //   cP = Z^T x1 (the local coarse right-hand side Phi^T g),
 //   mu = G^{-1} Y^T x1 (multipliers of the average constraints).
+// The constraint columns of Z are Y G^{-1}, so mu is the constraint part of
+// cP and Y is not read.
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_coarse_rhs_local(SubVecDesc d, const T* __restrict__ xr,
-                                                         const T* __restrict__ Fb, const T* __restrict__ Zb,
-                                                         const T* __restrict__ Gib, double* __restrict__ cP,
+                                                         const T* __restrict__ Zb, double* __restrict__ cP,
                                                          double* __restrict__ mu) {
     const int s = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nr = d.nr[s], nV = d.nV[s], nc = d.nc[s], nP = nV + nc;
     const T* x = xr + d.xoff[s];
-    const T* Y = Fb + d.F_off[s];
     const T* Z = Zb + d.Z_off[s];
-    __shared__ double ytx[MAXC];
-    for (int o = wv; o < nP + nc; o += kWG / 64) {
-        const T* col = (o < nP) ? Z + (int64_t)o * nr : Y + (int64_t)(o - nP) * nr;
+    for (int o = wv; o < nP; o += kWG / 64) {
+        const T* col = Z + (int64_t)o * nr;
         // rows of the lane in flight: four in FP32 (0.61 against 0.87 ms per
         // apply at 17M dofs); FP64 is no faster with more
         constexpr int U = sizeof(T) == 4 ? 4 : 1;
@@ -240,16 +239,9 @@ __global__ __launch_bounds__(kWG) void k_coarse_rhs_local(SubVecDesc d, const T*
         for (; r < nr; r += 64) a[0] += (double)col[r] * (double)x[r];
         double acc = wsum(tree_sum<U>(a));
         if (lane == 0) {
-            if (o < nP) cP[(int64_t)s * MAXP + o] = acc;
-            else ytx[o - nP] = acc;
+            cP[(int64_t)s * MAXP + o] = acc;
+            if (o >= nV) mu[(int64_t)s * MAXC + (o - nV)] = acc;
         }
-    }
-    __syncthreads();
-    const T* Gi = Gib + (int64_t)s * MAXC * MAXC;
-    if (tid < nc) {
-        double acc = 0.0;
-        for (int m = 0; m < nc; ++m) acc += (double)Gi[tid + m * nc] * ytx[m];
-        mu[(int64_t)s * MAXC + tid] = acc;
     }
 }
 
@@ -490,9 +482,8 @@ void launch_rho_fill(hipStream_t s, const ObjDesc& o, const double* w, T* dmat, 
     hipLaunchKernelGGL(k_rho_fill<T>, dim3(o.nobj), dim3(kWG), 0, s, o, w, dmat, dmatT);
 }
 template <typename T>
-void launch_coarse_rhs_local(hipStream_t s, const SubVecDesc& d, const T* xr, const T* F, const T* Z,
-                             const T* Gi, double* cP, double* mu) {
-    hipLaunchKernelGGL(k_coarse_rhs_local<T>, dim3(d.nsub), dim3(kWG), 0, s, d, xr, F, Z, Gi, cP, mu);
+void launch_coarse_rhs_local(hipStream_t s, const SubVecDesc& d, const T* xr, const T* Z, double* cP, double* mu) {
+    hipLaunchKernelGGL(k_coarse_rhs_local<T>, dim3(d.nsub), dim3(kWG), 0, s, d, xr, Z, cP, mu);
 }
 void launch_coarse_rhs_gather(hipStream_t s, const CoarseDesc& c, int64_t N, const double* g,
                               const double* cP, double* b) {
@@ -551,8 +542,7 @@ void launch_take_first(hipStream_t s, const ObjDesc& o, int64_t N, const T* xr, 
                                        const int64_t*, double*);                                            \
     template void launch_deluxe_transpose<T>(hipStream_t, const ObjDesc&, const T*, T*);                   \
     template void launch_rho_fill<T>(hipStream_t, const ObjDesc&, const double*, T*, T*);                    \
-    template void launch_coarse_rhs_local<T>(hipStream_t, const SubVecDesc&, const T*, const T*, const T*,  \
-                                             const T*, double*, double*);                                   \
+    template void launch_coarse_rhs_local<T>(hipStream_t, const SubVecDesc&, const T*, const T*, double*, double*); \
     template void launch_neumann_rhs<T>(hipStream_t, const SubVecDesc&, const T*, const T*, const double*,  \
                                         const double*, T*, int);                                            \
     template void launch_feti_BT<T>(hipStream_t, const ObjDesc&, const FetiDesc&, const double*, T*,        \

@@ -63,8 +63,7 @@ int deluxe_max_shares();
 template <typename T>
 void launch_rho_fill(hipStream_t s, const ObjDesc& o, const double* w, T* dmat, T* dmatT);
 template <typename T>
-void launch_coarse_rhs_local(hipStream_t s, const SubVecDesc& d, const T* xr, const T* F, const T* Z,
-                             const T* Gi, double* cP, double* mu);
+void launch_coarse_rhs_local(hipStream_t s, const SubVecDesc& d, const T* xr, const T* Z, double* cP, double* mu);
 void launch_coarse_rhs_gather(hipStream_t s, const CoarseDesc& c, int64_t N, const double* g,
                               const double* cP, double* b);
 void launch_coarse_project(hipStream_t s, int np, int pin, double* b);

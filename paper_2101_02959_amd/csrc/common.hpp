@@ -17,7 +17,6 @@ constexpr int MAXV = 16;                    // vertex dofs
 constexpr int MAXC = 36;                    // average constraints
 constexpr int MAXP = MAXC + MAXV;           // primal dofs
 constexpr int SVV_STRIDE = MAXV * MAXV;     // per-subdomain S_VV block
-constexpr int GI_STRIDE = MAXC * MAXC;      // per-subdomain G^{-1}
 constexpr int SP_STRIDE = MAXP * MAXP;      // per-subdomain coarse block
 
 // Pointwise and stencil parameters of the Bidomain step.

@@ -853,7 +853,7 @@ __global__ __launch_bounds__(kWG) void k_trsm_fwd(const T* __restrict__ Lb, cons
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_coarse_local(BatchDesc d, const T* __restrict__ Fb,
                                                      const double* __restrict__ Svv, T* __restrict__ Zb,
-                                                     T* __restrict__ Gib, double* __restrict__ Spb,
+                                                     double* __restrict__ Spb,
                                                      int* __restrict__ info) {
     const int s = d.sub0 + blockIdx.x;
     const int tid = threadIdx.x;
@@ -1003,8 +1003,6 @@ __global__ __launch_bounds__(kWG) void k_coarse_local(BatchDesc d, const T* __re
             Z[r + (int64_t)(nV + e) * nr] = (T)acc;
         }
     }
-    T* gi = Gib + (int64_t)s * GI_STRIDE;
-    for (int idx = tid; idx < nc * nc; idx += kWG) gi[idx] = (T)Gi[idx % nc][idx / nc];
     __syncthreads();
     double* Sp = Spb + (int64_t)s * SP_STRIDE;
     const double* sv = Svv + (int64_t)s * SVV_STRIDE;
@@ -1569,9 +1567,9 @@ void launch_trsm_fwd(hipStream_t s, int nb, const T* L, const int64_t* Loff, con
     hipLaunchKernelGGL(k_trsm_fwd<T>, dim3(nb), dim3(kWG), 0, s, L, Loff, n, B, Boff, ldb, k);
 }
 template <typename T>
-void launch_coarse_local(hipStream_t s, const BatchDesc& d, const T* F, const double* Svv, T* Z, T* Gi,
+void launch_coarse_local(hipStream_t s, const BatchDesc& d, const T* F, const double* Svv, T* Z,
                          double* Sp, int* info) {
-    hipLaunchKernelGGL(k_coarse_local<T>, dim3(d.nsub), dim3(kWG), 0, s, d, F, Svv, Z, Gi, Sp, info);
+    hipLaunchKernelGGL(k_coarse_local<T>, dim3(d.nsub), dim3(kWG), 0, s, d, F, Svv, Z, Sp, info);
 }
 template <typename T>
 void launch_trsv(hipStream_t s, int nb, bool trans, const T* L, const int64_t* Loff, const int* n, T* x,
@@ -1651,7 +1649,7 @@ int deluxe_max_object() { return DLX_MAXN; }
                                      const int64_t*);                                                    \
     template void launch_trsm_fwd<T>(hipStream_t, int, const T*, const int64_t*, const int*, T*,         \
                                      const int64_t*, const int*, const int*);                            \
-    template void launch_coarse_local<T>(hipStream_t, const BatchDesc&, const T*, const double*, T*, T*, \
+    template void launch_coarse_local<T>(hipStream_t, const BatchDesc&, const T*, const double*, T*, \
                                          double*, int*);                                                 \
     template void launch_trsv<T>(hipStream_t, int, bool, const T*, const int64_t*, const int*, T*,      \
                                  const int64_t*, int, const WorkQueue&);                                 \

@@ -114,7 +114,7 @@ void launch_trsm_fwd(hipStream_t s, int nb, const T* L, const int64_t* Loff, con
                      T* B, const int64_t* Boff, const int* ldb, const int* k);
 template <typename T>
 void launch_coarse_local(hipStream_t s, const BatchDesc& d, const T* F, const double* Svv, T* Z,
-                         T* Gi, double* Sp, int* info);
+                         double* Sp, int* info);
 // Schedule of a batched one-workgroup-per-matrix kernel over uneven matrices.
 // With order and counter set, the launch is persistent (as many workgroups
 // as fit on the device) and each workgroup draws the next matrix from the

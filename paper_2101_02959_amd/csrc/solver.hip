@@ -504,7 +504,6 @@ int Context::alloc_local() {
     slots_ = dalloc(nslot_ * sizeof(T));
     F_ = dalloc(nF_ * sizeof(T));
     Z_ = dalloc(nZ_ * sizeof(T));
-    Gi_ = dalloc((size_t)nsub * GI_STRIDE * sizeof(T));
     fac_ = dalloc(nfac_ * sizeof(T));
     inv_ = dalloc(nfac_ * sizeof(T));
     dmat_ = dalloc(nslot_ * sizeof(T));
@@ -530,7 +529,7 @@ int Context::alloc_local() {
     info_sub_ = (int*)dalloc(nsub * sizeof(int));
     info_obj_ = (int*)dalloc((size_t)od_.nobj * sizeof(int));
     info_c_ = (int*)dalloc(sizeof(int));
-    if (!K_ || !Wbuf_ || !LIIs_ || !Lrrs_ || !slots_ || !inv_ || !dmat_ || !dmatT_ || !F_ || !Z_ || !Gi_ || !fac_ || (feti && !Srr_) || !xI_ || !xr_ ||
+    if (!K_ || !Wbuf_ || !LIIs_ || !Lrrs_ || !slots_ || !inv_ || !dmat_ || !dmatT_ || !F_ || !Z_ || !fac_ || (feti && !Srr_) || !xI_ || !xr_ ||
         !xr2_ || !Svv_ || !Sp_ || !cP_ || !mu_ || !cb_ || !ybuf_ || !info_sub_ || !info_obj_ || !info_c_) {
         set_error("device allocation failed (local factors)");
         return BDM_E_OOM;
@@ -831,7 +830,7 @@ int Context::linearize_t() {
     }
     HIPOK(hipEventRecord(ev_join_, side_stream_));
     launch_trsm_fwd<T>(stream_, nsub, (const T*)Lrrs_, Lrr_off_, nr_, (T*)F_, bd_.F_off, nr_, kF_);
-    launch_coarse_local<T>(stream_, bd_, (const T*)F_, Svv_, (T*)Z_, (T*)Gi_, Sp_, info_sub_);
+    launch_coarse_local<T>(stream_, bd_, (const T*)F_, Svv_, (T*)Z_, Sp_, info_sub_);
     coarse_.factor(stream_, color_list_, color_ptr_, nP_, Sp_, SP_STRIDE);
     HIPOK(hipStreamWaitEvent(stream_, ev_join_, 0));
     int hb = 0, hc = 0;
@@ -887,7 +886,7 @@ void Context::condense(const double* r, double* g) {
 template <typename T>
 void Context::stilde_inv(T* xr, const double* gvert, double* uc) {
     launch_trsv<T>(stream_, bd_.nsub, false, (const T*)Lrrs_, Lrr_off_, nr_, xr, xr_off_, maxnr_, qr_);
-    launch_coarse_rhs_local<T>(stream_, sv_, xr, (const T*)F_, (const T*)Z_, (const T*)Gi_, cP_, mu_);
+    launch_coarse_rhs_local<T>(stream_, sv_, xr, (const T*)Z_, cP_, mu_);
     launch_coarse_rhs_gather(stream_, cd_, N, gvert, cP_, uc);
     launch_coarse_project(stream_, cd_.np, pin_, uc);
     coarse_.solve(stream_, uc);

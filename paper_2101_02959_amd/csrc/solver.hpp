@@ -117,7 +117,7 @@ class Context {
     double t_ = 0.0;
 
     // batched local storage (element type per precision)
-    void *K_ = nullptr, *slots_ = nullptr, *F_ = nullptr, *Z_ = nullptr, *Gi_ = nullptr;
+    void *K_ = nullptr, *slots_ = nullptr, *F_ = nullptr, *Z_ = nullptr;
     void *fac_ = nullptr, *Srr_ = nullptr, *xI_ = nullptr, *xr_ = nullptr, *xr2_ = nullptr;
     double *Svv_ = nullptr, *Sp_ = nullptr, *cP_ = nullptr, *mu_ = nullptr;
     double *cb_ = nullptr, *ybuf_ = nullptr;
