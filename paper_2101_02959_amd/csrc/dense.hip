@@ -1065,21 +1065,11 @@ __device__ inline int next_item(const int* __restrict__ order, int* __restrict__
     return item;
 }
 
+// Forward and backward solves of one subdomain on x staged in LDS (xl);
+// every thread of the workgroup calls them, and each ends with a barrier.
 template <typename T>
-__global__ __launch_bounds__(kWG) void k_trsv_fwd(const T* __restrict__ Lb, const int64_t* __restrict__ Loff,
-                                                 const int* __restrict__ nv, T* __restrict__ xb,
-                                                 const int64_t* __restrict__ xoff, int nb,
-                                                 const int* __restrict__ order, int* __restrict__ ctr) {
-    extern __shared__ double trsv_lds[];
-    T* xl = reinterpret_cast<T*>(trsv_lds);
-    __shared__ T xs[NB];
+__device__ __forceinline__ void trsv_fwd_solve(const T* __restrict__ L, int n, T* xl, T* xs) {
     constexpr int TS_SEG = TSGeom<T>::SEG, TS_LPR = TSGeom<T>::LPR, TS_RPI = TSGeom<T>::RPI, TS_U = TSGeom<T>::U;
-    for (int pass = 0;; ++pass) {
-    const int s = next_item(order, ctr, nb, pass);
-    if (s < 0) break;
-    const T* L = Lb + Loff[s];
-    T* x = xb + xoff[s];
-    const int n = nv[s];
     const int tid = threadIdx.x, lane = tid & 63;
     // wave 0 holds the diagonal block of the current step in drow (lane i:
     // row i of the block, one packed row).  FP32: loaded during the previous
@@ -1095,8 +1085,6 @@ __global__ __launch_bounds__(kWG) void k_trsv_fwd(const T* __restrict__ Lb, cons
         for (int c = 1; c < NB; ++c) rdiag = (c == i) ? drow[c] : rdiag;
     };
     if (early && tid < 64) load_diag(0);
-    for (int i = tid; i < n; i += kWG) xl[i] = x[i];
-    __syncthreads();
     for (int j0 = 0; j0 < n; j0 += NB) {
         const int jb = min(NB, n - j0);
         if (tid < 64) {
@@ -1147,28 +1135,12 @@ __global__ __launch_bounds__(kWG) void k_trsv_fwd(const T* __restrict__ Lb, cons
         }
         __syncthreads();
     }
-    for (int i = tid; i < n; i += kWG) x[i] = xl[i];
-    }
 }
 
 template <typename T>
-__global__ __launch_bounds__(kWG) void k_trsv_bwd(const T* __restrict__ Lb, const int64_t* __restrict__ Loff,
-                                                 const int* __restrict__ nv, T* __restrict__ xb,
-                                                 const int64_t* __restrict__ xoff, int nb,
-                                                 const int* __restrict__ order, int* __restrict__ ctr) {
-    extern __shared__ double trsv_lds[];
-    T* xl = reinterpret_cast<T*>(trsv_lds);
-    __shared__ T red[kWG / 64][NB];
+__device__ __forceinline__ void trsv_bwd_solve(const T* __restrict__ L, int n, T* xl, T (*red)[NB]) {
     constexpr int TS_SEG = TSGeom<T>::SEG, TS_LPR = TSGeom<T>::LPR, TS_RPI = TSGeom<T>::RPI, TS_U = TSGeom<T>::U;
-    for (int pass = 0;; ++pass) {
-    const int s = next_item(order, ctr, nb, pass);
-    if (s < 0) break;
-    const T* L = Lb + Loff[s];
-    T* x = xb + xoff[s];
-    const int n = nv[s];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (int i = tid; i < n; i += kWG) xl[i] = x[i];
-    __syncthreads();
     const int nblk = (n + NB - 1) / NB;
     for (int bi = nblk - 1; bi >= 0; --bi) {
         const int j0 = bi * NB, jb = min(NB, n - j0);
@@ -1223,7 +1195,32 @@ __global__ __launch_bounds__(kWG) void k_trsv_bwd(const T* __restrict__ Lb, cons
         }
         __syncthreads();
     }
-    for (int i = tid; i < n; i += kWG) x[i] = xl[i];
+}
+
+// One launch per solve: forward (FWD), backward (BWD) or both in turn on the
+// same subdomain (FWD && BWD: the backward pass starts on the panels the
+// forward pass streamed last, and x stays in LDS between them).  The
+// arithmetic of each pass is the same in every form.
+template <typename T, bool FWD, bool BWD>
+__global__ __launch_bounds__(kWG) void k_trsv(const T* __restrict__ Lb, const int64_t* __restrict__ Loff,
+                                             const int* __restrict__ nv, T* __restrict__ xb,
+                                             const int64_t* __restrict__ xoff, int nb,
+                                             const int* __restrict__ order, int* __restrict__ ctr) {
+    extern __shared__ double trsv_lds[];
+    T* xl = reinterpret_cast<T*>(trsv_lds);
+    __shared__ T xs[FWD ? NB : 1];
+    __shared__ T red[BWD ? kWG / 64 : 1][NB];
+    for (int pass = 0;; ++pass) {
+        const int s = next_item(order, ctr, nb, pass);
+        if (s < 0) break;
+        const T* L = Lb + Loff[s];
+        T* x = xb + xoff[s];
+        const int n = nv[s];
+        for (int i = threadIdx.x; i < n; i += kWG) xl[i] = x[i];
+        __syncthreads();
+        if constexpr (FWD) trsv_fwd_solve<T>(L, n, xl, xs);
+        if constexpr (BWD) trsv_bwd_solve<T>(L, n, xl, red);
+        for (int i = threadIdx.x; i < n; i += kWG) x[i] = xl[i];
     }
 }
 
@@ -1571,12 +1568,12 @@ void launch_coarse_local(hipStream_t s, const BatchDesc& d, const T* F, const do
                          double* Sp, int* info) {
     hipLaunchKernelGGL(k_coarse_local<T>, dim3(d.nsub), dim3(kWG), 0, s, d, F, Svv, Z, Sp, info);
 }
-template <typename T>
-void launch_trsv(hipStream_t s, int nb, bool trans, const T* L, const int64_t* Loff, const int* n, T* x,
-                 const int64_t* xoff, int maxn, const WorkQueue& q) {
+template <typename T, bool FWD, bool BWD>
+void launch_trsv_kern(hipStream_t s, int nb, const T* L, const int64_t* Loff, const int* n, T* x,
+                      const int64_t* xoff, int maxn, const WorkQueue& q) {
     if (nb <= 0 || maxn <= 0) return;
     const size_t lds = (size_t)maxn * sizeof(T);
-    auto kern = trans ? k_trsv_bwd<T> : k_trsv_fwd<T>;
+    auto kern = k_trsv<T, FWD, BWD>;
     int grid = nb;
     if (q.order && q.counter) {
         // persistent: as many workgroups as are resident at once (at least one)
@@ -1589,6 +1586,17 @@ void launch_trsv(hipStream_t s, int nb, bool trans, const T* L, const int64_t* L
     const int* ord = q.order;
     int* ctr = (q.order && q.counter) ? q.counter : nullptr;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kWG), lds, s, L, Loff, n, x, xoff, nb, ord, ctr);
+}
+template <typename T>
+void launch_trsv(hipStream_t s, int nb, bool trans, const T* L, const int64_t* Loff, const int* n, T* x,
+                 const int64_t* xoff, int maxn, const WorkQueue& q) {
+    if (trans) launch_trsv_kern<T, false, true>(s, nb, L, Loff, n, x, xoff, maxn, q);
+    else launch_trsv_kern<T, true, false>(s, nb, L, Loff, n, x, xoff, maxn, q);
+}
+template <typename T>
+void launch_trsv_fb(hipStream_t s, int nb, const T* L, const int64_t* Loff, const int* n, T* x,
+                    const int64_t* xoff, int maxn, const WorkQueue& q) {
+    launch_trsv_kern<T, true, true>(s, nb, L, Loff, n, x, xoff, maxn, q);
 }
 template <typename T>
 void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, int ob0, int nob, int maxn, const T* slots, T* fac, T* dmat,
@@ -1652,6 +1660,8 @@ int deluxe_max_object() { return DLX_MAXN; }
     template void launch_coarse_local<T>(hipStream_t, const BatchDesc&, const T*, const double*, T*, \
                                          double*, int*);                                                 \
     template void launch_trsv<T>(hipStream_t, int, bool, const T*, const int64_t*, const int*, T*,      \
+                                 const int64_t*, int, const WorkQueue&);                                 \
+    template void launch_trsv_fb<T>(hipStream_t, int, const T*, const int64_t*, const int*, T*,      \
                                  const int64_t*, int, const WorkQueue&);                                 \
     template void launch_deluxe_setup<T>(hipStream_t, const ObjDesc&, int, int, int, const T*, T*, T*, int*);
 BDM_INST(double)

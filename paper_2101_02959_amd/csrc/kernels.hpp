@@ -130,6 +130,11 @@ struct WorkQueue {
 template <typename T>
 void launch_trsv(hipStream_t s, int nb, bool trans, const T* L, const int64_t* Loff, const int* n,
                  T* x, const int64_t* xoff, int maxn, const WorkQueue& q);
+// Forward then backward solve of every subdomain in one launch (x kept in
+// LDS between the two passes); the same arithmetic as the two launches.
+template <typename T>
+void launch_trsv_fb(hipStream_t s, int nb, const T* L, const int64_t* Loff, const int* n,
+                 T* x, const int64_t* xoff, int maxn, const WorkQueue& q);
 
 // Deluxe objects (faces and edges), one workgroup per object.
 struct ObjDesc {

@@ -137,6 +137,9 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
     stream_ = s;
     opts = *o;
     phys = *ph;
+    // The Dirichlet solves run as one fused forward/backward launch unless
+    // BDM_DIRICHLET_FUSED=0 (the same arithmetic either way).
+    if (const char* e = std::getenv("BDM_DIRICHLET_FUSED")) fused_dirichlet_ = std::atoi(e) != 0;
     if (!(o->dt > 0) || o->newton_maxit < 1 || o->krylov_maxit < 1 ||
         (o->schedule != BDM_SCHED_QUEUE && o->schedule != BDM_SCHED_GRID) ||
         (o->krylov_reduced != 0 && o->krylov_reduced != 1) ||
@@ -867,8 +870,12 @@ template <typename T>
 void Context::dirichlet(const double* r, const double* q, double* out) {
     T* xI = (T*)xI_;
     launch_gather_I<T>(stream_, nInodes_, Ilist_, N, r, q, xI);
-    launch_trsv<T>(stream_, bd_.nsub, false, (const T*)LIIs_, LII_off_, nI_, xI, xI_off_, maxnI_, qI_);
-    launch_trsv<T>(stream_, bd_.nsub, true, (const T*)LIIs_, LII_off_, nI_, xI, xI_off_, maxnI_, qI_);
+    if (fused_dirichlet_) {
+        launch_trsv_fb<T>(stream_, bd_.nsub, (const T*)LIIs_, LII_off_, nI_, xI, xI_off_, maxnI_, qI_);
+    } else {
+        launch_trsv<T>(stream_, bd_.nsub, false, (const T*)LIIs_, LII_off_, nI_, xI, xI_off_, maxnI_, qI_);
+        launch_trsv<T>(stream_, bd_.nsub, true, (const T*)LIIs_, LII_off_, nI_, xI, xI_off_, maxnI_, qI_);
+    }
     launch_scatter_I<T>(stream_, nInodes_, Ilist_, N, xI, out);
 }
 

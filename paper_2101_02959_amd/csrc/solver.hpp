@@ -141,6 +141,7 @@ class Context {
     int maxbox_ = 0, maxG_ = 0, maxnI_ = 0, maxnr_ = 0, maxobjn_ = 0, nInodes_ = 0;
     int nface_obj_ = 0, maxface_n_ = 0, maxedge_n_ = 0;   // objects: faces [0, nface_obj_), then edges
     double* rho_w_ = nullptr;   // rho scaling weights per share: (v, u_e)
+    bool fused_dirichlet_ = true;   // forward and backward Dirichlet solves in one launch
     int maxn_ = 0;                                         // largest local matrix (n = nI + nGamma)
     void* Wbuf_ = nullptr;
     int *Ilist_ = nullptr;
