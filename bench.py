@@ -141,8 +141,8 @@ def kernel_rooflines(P, S, prec_name, workload_name, reps=5):
         out["syrk"]["traffic_unit"] = "bytes per launch (HBM read + write, calibrated counters)"
     mfma("panel", P.BDM_KERNEL_POTRF_INTERIOR,
          f"k_panel_diag<{tname}> + k_panel_trsm<{tname}> (first setup chunk)")
-    hbm("trsv_fwd", P.BDM_KERNEL_TRSV_DIRICHLET, f"k_trsv_fwd<{tname}> (Dirichlet, all subdomains)", 20)
-    hbm("trsv_bwd", P.BDM_KERNEL_TRSV_DIRICHLET_T, f"k_trsv_bwd<{tname}> (Dirichlet, all subdomains)", 20)
+    hbm("trsv_fwd", P.BDM_KERNEL_TRSV_DIRICHLET, f"k_trsv<{tname}, true, false> (forward Dirichlet solve, all subdomains)", 20)
+    hbm("trsv_bwd", P.BDM_KERNEL_TRSV_DIRICHLET_T, f"k_trsv<{tname}, false, true> (backward Dirichlet solve, all subdomains)", 20)
     hbm("jacobian", P.BDM_KERNEL_JACOBIAN, "k_stencil<0> (Jacobian apply, autotuned tile shape)", 50)
     return out
 
