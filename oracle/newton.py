@@ -32,18 +32,34 @@ def project_range(b, N):
     return b
 
 
-def linesearch(resfun, u, s, R, alpha=1e-4, maxit=20):
-    """Backtracking on f = ||R||^2/2 along s: returns (u_new, R_new, lambda)."""
+def linesearch(resfun, u, s, R, alpha=1e-4, maxit=20, trace=None):
+    """Backtracking on f = ||R||^2/2 along the Newton direction s (Sec. 6,
+    the nonlinear solver's cubic backtracking line search).
+
+    f'(0) = R.(J s) = -||R||^2 for a Newton direction.  The full step is
+    tried first; while the Armijo test f(l) <= f(0) + alpha l f'(0) fails, the
+    next l minimises a model of f along s: after the first failure the
+    quadratic through f(0), f'(0), f(1); after later failures the cubic
+    through f(0), f'(0) and the last two trial values.  Each new l is kept in
+    [0.1 l, 0.5 l] of the previous one.  A trial with a non-finite f is not
+    modelled: l is halved.  Every l tried is appended to ``trace`` when one
+    is given.  Returns (u_new, R_new, lambda, ok); ok is False when no l
+    passed the test within ``maxit`` trials (the last trial is returned)."""
     f0 = 0.5 * R @ R
     g0 = -2.0 * f0
     lam = 1.0
     lam_prev = f_prev = None
     for _ in range(maxit):
+        if trace is not None:
+            trace.append(lam)
         un = u + lam * s
         Rn = resfun(un)
         f = 0.5 * Rn @ Rn
-        if f <= f0 + alpha * lam * g0:
-            return un, Rn, lam
+        if np.isfinite(f) and f <= f0 + alpha * lam * g0:
+            return un, Rn, lam, True
+        if not np.isfinite(f):
+            lam = 0.5 * lam
+            continue
         if lam_prev is None:
             lt = -g0 / (2.0 * (f - f0 - g0))
         else:
@@ -58,7 +74,7 @@ def linesearch(resfun, u, s, R, alpha=1e-4, maxit=20):
                 lt = (-b + np.sqrt(disc)) / (3.0 * a)
         lam_prev, f_prev = lam, f
         lam = min(max(lt, 0.1 * lam), 0.5 * lam)
-    return un, Rn, lam
+    return un, Rn, lam, False
 
 
 class StepStats:
@@ -109,7 +125,9 @@ def time_step(prob, dec, v_n, ue_n, w_n, Is, method="bddc", rtol=1e-8, atol=0.0,
         s, kres = solve_linear(prob, dec, u[:N], w, -R, method, krtol, kmaxit, scaling)
         st.krylov_its.append(kres.its)
         st.conds.append(kres.cond())
-        u, R, lam = linesearch(resfun, u, s, R)
+        u, R, lam, ok = linesearch(resfun, u, s, R)
+        if not ok:
+            raise RuntimeError("line search found no step that decreases ||R||")
         u[N:] = gauge(u[N:])
         st.lambdas.append(lam)
         st.newton_its += 1
