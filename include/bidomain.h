@@ -45,7 +45,9 @@ enum {
     BDM_E_KRYLOV_MAXIT = -6,     /* Krylov iteration limit reached           */
     BDM_E_NEWTON_MAXIT = -7,     /* Newton iteration limit reached           */
     BDM_E_COERCIVITY = -8,       /* reaction diagonal <= 0 (Sec. 3c lemma)   */
-    BDM_E_STATE = -9             /* call order violated (e.g. no linearize)  */
+    BDM_E_STATE = -9,            /* call order violated (e.g. no linearize)  */
+    BDM_E_LINESEARCH = -10       /* no step along a Newton direction passed  */
+                                 /* the Armijo test within 20 trials         */
 };
 
 enum { BDM_SOLVER_BDDC = 0, BDM_SOLVER_FETIDP = 1 };
@@ -71,18 +73,21 @@ enum { BDM_SCALING_DELUXE = 0, BDM_SCALING_RHO = 1 };
  * of v and of u_e over every edge (VE), or over every edge and face (VEF). */
 enum { BDM_PRIMAL_VE = 0, BDM_PRIMAL_V = 1, BDM_PRIMAL_VEF = 2 };
 
-/* Structured hexahedral Q1 mesh of nx*ny*nz cubes of side h (Sec. 3a) and a
- * tensor-product partition into non-overlapping box subdomains (Sec. 4.1):
- * cuts_x[0..px] are element indices with cuts_x[0] = 0, cuts_x[px] = nx,
- * strictly increasing; likewise y, z.  px, py, pz >= 2 (every subdomain must
- * touch an interior cross point: every primal space holds the vertex values). */
+/* Structured hexahedral Q1 mesh of nx*ny*nz box elements of size
+ * h x hy x hz (Sec. 3a; hy <= 0 or hz <= 0 means h, i.e. cubes of side h)
+ * and a tensor-product partition into non-overlapping box subdomains
+ * (Sec. 4.1): cuts_x[0..px] are element indices with cuts_x[0] = 0,
+ * cuts_x[px] = nx, strictly increasing; likewise y, z.  px, py, pz >= 2
+ * (every subdomain must touch an interior cross point: every primal space
+ * holds the vertex values). */
 typedef struct bdm_mesh {
     int nx, ny, nz;
-    double h;
+    double h;                   /* element size along x (cm)                 */
     int px, py, pz;
     const int* cuts_x;
     const int* cuts_y;
     const int* cuts_z;
+    double hy, hz;              /* element sizes along y and z (cm; <= 0: h) */
 } bdm_mesh;
 
 /* Conductivities along (l, t, n) (Sec. 2, D = sum sigma a a^T), fibre angle
@@ -148,6 +153,9 @@ typedef struct bdm_step_stats {
                                 /* on the full system after the solve (the   */
                                 /* error of the result under FP32 local      */
                                 /* factors; b is the projected -R)           */
+    double step_length[32];     /* per Newton iteration: the accepted step   */
+                                /* length of the line search (1 = full       */
+                                /* Newton step; Sec. 6 backtracking)         */
 } bdm_step_stats;
 
 typedef struct bdm_ctx bdm_ctx;
@@ -216,9 +224,16 @@ int bdm_fetidp_size(bdm_ctx* ctx, long* n_lambda);
  *                     w = S~^{-1}(f~ - B^T lambda), z_I by a Dirichlet solve */
 int bdm_fetidp_apply(bdm_ctx* ctx, int op, const double* in, double* out);
 
-/* Advance nsteps time steps: Step 1 then Newton (line search on ||R||^2,
- * Armijo alpha = 1e-4) with PCG preconditioned by BDDC, or FETI-DP PCG on
- * the multipliers plus recovery, per opts.solver.  stats may be NULL.
+/* Advance nsteps time steps: Step 1 then Newton with PCG preconditioned by
+ * BDDC, or FETI-DP PCG on the multipliers plus recovery, per opts.solver.
+ * Globalisation (Sec. 6, cubic backtracking): with f = ||R||^2 / 2 and
+ * f'(0) = -||R||^2 along the Newton direction s, the step u + l s is
+ * accepted when f(l) <= f(0) + 1e-4 l f'(0); the full step l = 1 is tried
+ * first, then the minimiser of the quadratic model through f(0), f'(0),
+ * f(l), then of the cubic model through f(0), f'(0) and the last two
+ * trials, each new l clamped to [0.1, 0.5] of the previous; a trial whose
+ * f is not finite halves l.  BDM_E_LINESEARCH after 20 failed trials.
+ * stats may be NULL.
  * BDM_E_ARG for FETI-DP with FP32 local factors: the multiplier operator
  * B S~^{-1} B^T contains the local solves, and their FP32 round-off makes it
  * indefinite at scale (PCG breaks down); BDDC keeps the FP64 Jacobian as

@@ -64,24 +64,34 @@ def _q1_basis(s, t, u):
     return val, grad
 
 
+def _sizes(h):
+    """(hx, hy, hz) from a cube side or a 3-tuple of box sizes."""
+    return (h, h, h) if np.isscalar(h) else tuple(h)
+
+
 def element_stiffness(D, h):
-    """{A}_nm = int_e grad(phi_n)^T D grad(phi_m) on a cube of side h, with
-    2x2x2 Gauss quadrature (exact for constant D on a cube)."""
+    """{A}_nm = int_e grad(phi_n)^T D grad(phi_m) on a box element of sizes
+    h = (hx, hy, hz) (or a cube of side h), with 2x2x2 Gauss quadrature
+    (exact for constant D on a box): the map from the unit cube scales the
+    gradients by 1/h_d per axis and the volume by hx hy hz."""
+    hx, hy, hz = _sizes(h)
     A = np.zeros((8, 8))
-    w = (h / 2.0) ** 3
+    w = hx * hy * hz / 8.0
     for s in _GP:
         for t in _GP:
             for u in _GP:
                 _, g = _q1_basis(s, t, u)
-                g = g / h
+                g = g / np.array([hx, hy, hz])
                 A += w * g @ D @ g.T
     return A
 
 
 def element_mass(h):
-    """Consistent Q1 element mass {M}_nm = int_e phi_n phi_m (2x2x2 Gauss)."""
+    """Consistent Q1 element mass {M}_nm = int_e phi_n phi_m (2x2x2 Gauss) on
+    a box element of sizes h = (hx, hy, hz) (or a cube of side h)."""
+    hx, hy, hz = _sizes(h)
     Me = np.zeros((8, 8))
-    w = (h / 2.0) ** 3
+    w = hx * hy * hz / 8.0
     for s in _GP:
         for t in _GP:
             for u in _GP:
@@ -92,12 +102,13 @@ def element_mass(h):
 
 def layer_stiffness(mesh, physics):
     """Per z-layer element stiffness matrices for the two media."""
-    Lz = mesh.nz * mesh.h
+    hs = mesh.spacing
+    Lz = mesh.nz * hs[2]
     Ai, Ae = [], []
     for ez in range(mesh.nz):
-        th = fibre_angle(physics, (ez + 0.5) * mesh.h, Lz)
-        Ai.append(element_stiffness(conductivity(physics.sigma_i, th), mesh.h))
-        Ae.append(element_stiffness(conductivity(physics.sigma_e, th), mesh.h))
+        th = fibre_angle(physics, (ez + 0.5) * hs[2], Lz)
+        Ai.append(element_stiffness(conductivity(physics.sigma_i, th), hs))
+        Ae.append(element_stiffness(conductivity(physics.sigma_e, th), hs))
     return Ai, Ae
 
 
@@ -134,7 +145,7 @@ def assemble(mesh, physics, box=None):
     of the consistent mass ("usual mass lumping", Sec. 3a).  Matrices are
     over all mesh nodes; rows of nodes outside the box are empty."""
     Ai_l, Ae_l = layer_stiffness(mesh, physics)
-    Me = element_mass(mesh.h)
+    Me = element_mass(mesh.spacing)
     en, lay = element_node_table(mesh, box)
     rows = np.repeat(en, 8, axis=1).ravel()          # (e, a, b) -> node a
     cols = np.tile(en, (1, 8)).ravel()               # (e, a, b) -> node b

@@ -30,6 +30,8 @@ def main(argv=None):
     ap.add_argument("--guess", choices=["prev", "extrap", "cnn"], default="cnn")
     ap.add_argument("--every", type=int, default=100)
     ap.add_argument("--out", default=None, help="also write the window records as JSON")
+    ap.add_argument("--cubic", action="store_true",
+                    help="cubic elements of 0.01 cm (1.92 x 0.96 x 0.24 cm) instead of the paper's slab")
     args = ap.parse_args(argv)
     import numpy as np
     import torch
@@ -37,7 +39,7 @@ def main(argv=None):
     import paper_2101_02959_amd as P
     from workload import stimulus_nodal, test4
     parts = tuple(int(v) for v in args.parts.split("x"))
-    wl = test4(parts, args.steps)
+    wl = test4(parts, args.steps, paper_geometry=not args.cubic)
     N = wl.mesh.nnodes
     guess = {"prev": P.BDM_GUESS_PREV, "extrap": P.BDM_GUESS_EXTRAP, "cnn": P.BDM_GUESS_CNN}[args.guess]
     S = P.Solver(wl.mesh, wl.physics, wl.solver,

@@ -28,7 +28,7 @@ BDM_PRIMAL_VE, BDM_PRIMAL_V, BDM_PRIMAL_VEF = 0, 1, 2
 ERRORS = {
     -1: "BDM_E_ARG", -2: "BDM_E_OOM", -3: "BDM_E_HIP", -4: "BDM_E_NOT_SPD",
     -5: "BDM_E_KRYLOV_DIVERGED", -6: "BDM_E_KRYLOV_MAXIT", -7: "BDM_E_NEWTON_MAXIT",
-    -8: "BDM_E_COERCIVITY", -9: "BDM_E_STATE",
+    -8: "BDM_E_COERCIVITY", -9: "BDM_E_STATE", -10: "BDM_E_LINESEARCH",
 }
 
 EXPORTS = ("bdm_create", "bdm_destroy", "bdm_set_state", "bdm_get_state", "bdm_set_stimulus",
@@ -48,7 +48,7 @@ class bdm_mesh(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("h", C.c_double),
                 ("px", C.c_int), ("py", C.c_int), ("pz", C.c_int),
                 ("cuts_x", C.POINTER(C.c_int)), ("cuts_y", C.POINTER(C.c_int)),
-                ("cuts_z", C.POINTER(C.c_int))]
+                ("cuts_z", C.POINTER(C.c_int)), ("hy", C.c_double), ("hz", C.c_double)]
 
 
 class bdm_physics(C.Structure):
@@ -71,7 +71,7 @@ class bdm_step_stats(C.Structure):
                 ("cond", C.c_double * 32), ("t_setup_ms", C.c_double), ("t_krylov_ms", C.c_double),
                 ("t_step_ms", C.c_double), ("bad_subdomain", C.c_int), ("guess_used", C.c_int),
                 ("guess_res_extrap", C.c_double), ("guess_res_cnn", C.c_double), ("res_ref", C.c_double),
-                ("krylov_true_res", C.c_double * 32)]
+                ("krylov_true_res", C.c_double * 32), ("step_length", C.c_double * 32)]
 
 
 _lib = None
@@ -137,7 +137,7 @@ def make_structs(mesh, physics, solver, precision=BDM_PREC_FP64, method=BDM_SOLV
     cy = (C.c_int * len(mesh.cuts_y))(*mesh.cuts_y)
     cz = (C.c_int * len(mesh.cuts_z))(*mesh.cuts_z)
     m = bdm_mesh(mesh.nx, mesh.ny, mesh.nz, mesh.h, len(mesh.cuts_x) - 1, len(mesh.cuts_y) - 1,
-                 len(mesh.cuts_z) - 1, cx, cy, cz)
+                 len(mesh.cuts_z) - 1, cx, cy, cz, getattr(mesh, "hy", 0.0), getattr(mesh, "hz", 0.0))
     ph = bdm_physics((C.c_double * 3)(*physics.sigma_i), (C.c_double * 3)(*physics.sigma_e),
                      physics.theta0, physics.theta1, physics.chi, physics.Cm, physics.G,
                      physics.eta1, physics.eta2, physics.vth, physics.vp)
@@ -314,3 +314,4 @@ class Solver:
         rc = lib().bdm_step(self.h, nsteps, C.byref(st))
         _check(rc)
         return st
+

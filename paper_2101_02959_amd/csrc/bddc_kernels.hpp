@@ -91,21 +91,28 @@ template <typename T>
 void launch_take_first(hipStream_t s, const ObjDesc& o, int64_t N, const T* xr, const int64_t* xoff, double* z);
 
 // ---- vec.hip: FP64 vector kernels with deterministic two-stage reductions
-void launch_dot(hipStream_t s, int64_t n, const double* x, const double* y, double* partial, double* out);
+// Reductions take a partial buffer of dot_partials() doubles and a ticket
+// array of vec_tickets() zero-initialised unsigned ints (vec.hip).
+void launch_dot(hipStream_t s, int64_t n, const double* x, const double* y, double* partial, unsigned* tickets,
+                double* out);
 void launch_axpy(hipStream_t s, int64_t n, double a, const double* x, double* y);
 void launch_copy(hipStream_t s, int64_t n, const double* x, double* y);
-// device-scalar and capture-safe vector operations (graph-captured PCG)
+// device-scalar and capture-safe vector operations (PCG)
 void launch_axpy_dev(hipStream_t s, int64_t n, const double* a, double sgn, const double* x, double* y);
 void launch_scale_add_dev(hipStream_t s, int64_t n, const double* z, const double* b, double* p);
 void launch_fill(hipStream_t s, int64_t n, double v, double* x);
 template <typename T>
 void launch_fill_t(hipStream_t s, int64_t n, T v, T* x);
 void launch_copy_kernel(hipStream_t s, int64_t n, const double* x, double* y);
-void launch_pcg_alpha(hipStream_t s, double* sc);
-void launch_pcg_check(hipStream_t s, double* sc, double* hist, double* ah, int maxit);
-void launch_pcg_beta(hipStream_t s, double* sc, double* bh);
+// x += alpha p, r -= alpha q, ||r||^2 and the stopping test (slots sc)
+void launch_pcg_update(hipStream_t s, int64_t n, double* sc, const double* p, const double* q, double* x, double* r,
+                       double* partial, unsigned* tickets, double* hist, double* ah, int maxit);
+// z.r, z.q and the Polak-Ribiere beta (slots sc)
+void launch_pcg_beta(hipStream_t s, int64_t n, double* sc, const double* z, const double* r, const double* q,
+                     double* partial, unsigned* tickets, double* bh);
 void launch_scale_add(hipStream_t s, int64_t n, const double* z, double b, double* p);  // p = z + b p
-void launch_sub_mean(hipStream_t s, int64_t n, double* x, double* partial, double* tmp);
+void launch_sub_mean(hipStream_t s, int64_t n, double* x, double* partial, unsigned* tickets, double* tmp);
 int dot_partials();
+int vec_tickets();
 
 }  // namespace bdm

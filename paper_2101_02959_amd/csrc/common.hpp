@@ -24,7 +24,8 @@ struct FEParams {
     int nx, ny, nz;             // elements per axis
     int nx1, ny1;               // nodes per axis (x, y)
     int64_t N;                  // nodes
-    double h, tau, c;           // mesh size, time step, chi*C_m
+    double h, tau, c;           // element size along x, time step, chi*C_m
+    double hy = 0.0, hz = 0.0;  // element sizes along y and z
     double chiG, chieta1, eta2, vth, vp;
     int stencil_variant = 0;    // tile shape of the stencil kernel (autotuned)
 };

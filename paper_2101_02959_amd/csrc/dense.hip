@@ -83,7 +83,7 @@ __global__ void k_assemble(BatchDesc d, FEParams p, const double* __restrict__ k
     double dP = 0.0;
     if (dd == 13) {
         const int64_t g = (int64_t)(ex0 + pi) + (int64_t)p.nx1 * ((ey0 + pj) + (int64_t)p.ny1 * (ez0 + pk));
-        const double m = p.h * p.h * p.h * 0.125 * nel;
+        const double m = p.h * p.hy * p.hz * 0.125 * nel;
         dP = m * (p.c + p.tau * rmc_diion(p, v[g], w[g]));
     }
     const int* lm = d.lmap + d.lmap_off[s];

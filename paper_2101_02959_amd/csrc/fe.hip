@@ -16,11 +16,11 @@
 namespace bdm {
 
 // ---------------------------------------------------------------- host side
-// Closed-form Q1 element stiffness on a cube of side h for a constant tensor
-// D: integrals factor per axis into
-//   int psi_a' psi_b' = s_a s_b / h,  int psi_a psi_b = h/3 (a==b) or h/6,
-//   int psi_a' psi_b  = s_a / 2,       s_0 = -1, s_1 = +1.
-void element_stiffness(const double D[3][3], double h, double Ke[8][8]) {
+// Closed-form Q1 element stiffness on a box of sizes hd[0..2] for a constant
+// tensor D: integrals factor per axis d into
+//   int psi_a' psi_b' = s_a s_b / h_d,  int psi_a psi_b = h_d/3 (a==b) or h_d/6,
+//   int psi_a' psi_b  = s_a / 2,        s_0 = -1, s_1 = +1.
+void element_stiffness(const double D[3][3], const double hd[3], double Ke[8][8]) {
     for (int a = 0; a < 8; ++a)
         for (int b = 0; b < 8; ++b) {
             const int ad[3] = {a & 1, (a >> 1) & 1, (a >> 2) & 1};
@@ -32,10 +32,10 @@ void element_stiffness(const double D[3][3], double h, double Ke[8][8]) {
                     for (int d = 0; d < 3; ++d) {
                         const double sa = ad[d] ? 1.0 : -1.0, sb = bd[d] ? 1.0 : -1.0;
                         double f;
-                        if (d == p && d == q) f = sa * sb / h;
+                        if (d == p && d == q) f = sa * sb / hd[d];
                         else if (d == p) f = 0.5 * sa;
                         else if (d == q) f = 0.5 * sb;
-                        else f = (ad[d] == bd[d]) ? h / 3.0 : h / 6.0;
+                        else f = (ad[d] == bd[d]) ? hd[d] / 3.0 : hd[d] / 6.0;
                         prod *= f;
                     }
                     acc += D[p][q] * prod;
@@ -54,26 +54,33 @@ void conductivity_tensor(const double sig[3], double theta, double D[3][3]) {
 }
 
 // tau-scaled element matrices per z-layer: ke[(layer*2 + medium)*64 + a*8 + b]
-std::vector<double> layer_matrices(int nz, double h, double tau, const double sig_i[3],
-                                   const double sig_e[3], double th0, double th1) {
-    std::vector<double> ke((size_t)nz * 128);
+// (nz * 128 doubles, caller's buffer), box elements of sizes hd[0..2]
+void layer_matrices_into(int nz, const double hd[3], double tau, const double sig_i[3], const double sig_e[3],
+                         double th0, double th1, double* ke) {
     for (int L = 0; L < nz; ++L) {
         const double th = th0 + (th1 - th0) * (L + 0.5) / nz;
         for (int m = 0; m < 2; ++m) {
             double D[3][3], K[8][8];
             conductivity_tensor(m == 0 ? sig_i : sig_e, th, D);
-            element_stiffness(D, h, K);
+            element_stiffness(D, hd, K);
             for (int a = 0; a < 8; ++a)
                 for (int b = 0; b < 8; ++b) ke[((size_t)L * 2 + m) * 64 + a * 8 + b] = tau * K[a][b];
         }
     }
+}
+
+std::vector<double> layer_matrices(int nz, const double hd[3], double tau, const double sig_i[3],
+                                   const double sig_e[3], double th0, double th1) {
+    std::vector<double> ke((size_t)nz * 128);
+    layer_matrices_into(nz, hd, tau, sig_i, sig_e, th0, th1, ke.data());
     return ke;
 }
 
 // 27-point tables st[((k*9 + xc + 3*yc)*2 + m)*27 + d], d = (dx+1) + 3(dy+1) + 9(dz+1):
-// the sum over the elements adjacent to both the node and its neighbour.
-std::vector<double> stencil_tables(int nz, const std::vector<double>& ke) {
-    std::vector<double> st((size_t)(nz + 1) * 9 * 2 * 27, 0.0);
+// the sum over the elements adjacent to both the node and its neighbour
+// ((nz + 1) * 486 doubles, caller's buffer).
+void stencil_tables_into(int nz, const double* ke, double* st) {
+    for (size_t i = 0; i < (size_t)(nz + 1) * 9 * 2 * 27; ++i) st[i] = 0.0;
     for (int k = 0; k <= nz; ++k)
         for (int yc = 0; yc < 3; ++yc)
             for (int xc = 0; xc < 3; ++xc)
@@ -100,6 +107,11 @@ std::vector<double> stencil_tables(int nz, const std::vector<double>& ke) {
                         }
                     }
                 }
+}
+
+std::vector<double> stencil_tables(int nz, const std::vector<double>& ke) {
+    std::vector<double> st((size_t)(nz + 1) * 9 * 2 * 27);
+    stencil_tables_into(nz, ke.data(), st.data());
     return st;
 }
 
@@ -111,7 +123,7 @@ __device__ inline double lumped_mass(const FEParams& p, int i, int j, int k) {
     const double fx = (i == 0 || i == p.nx) ? 0.5 : 1.0;
     const double fy = (j == 0 || j == p.ny) ? 0.5 : 1.0;
     const double fz = (k == 0 || k == p.nz) ? 0.5 : 1.0;
-    return p.h * p.h * p.h * fx * fy * fz;
+    return p.h * p.hy * p.hz * fx * fy * fz;
 }
 
 enum { ST_JAC = 0, ST_RES_MINUS_JAC = 1, ST_RESIDUAL = 2 };
@@ -389,6 +401,71 @@ __host__ __device__ inline ZmGrid zm_grid(const FEParams& p) {
     return g;
 }
 
+// One boundary node column (x or y face) of the register march: thread b
+// of the boundary columns walks levels [ZM_ZB bzi, ZM_ZB (bzi + 1)) and
+// reads the coefficients of its boundary class per lane.
+template <int MODE>
+__device__ void zm_boundary(const FEParams& p, const double* __restrict__ st, int b, int bzi, int nbnd,
+                            const double* __restrict__ dg, const double* __restrict__ xv,
+                            const double* __restrict__ xe, const double* __restrict__ rv,
+                            const double* __restrict__ re, const double* __restrict__ vn,
+                            const double* __restrict__ w, const double* __restrict__ Is, double stim,
+                            double* __restrict__ yv, double* __restrict__ ye) {
+    constexpr int TABN = 9 * 2 * 27;
+    const int64_t plane = (int64_t)p.nx1 * p.ny1;
+    const bool act = b < nbnd;
+    const int bb = act ? b : 0;
+    int i, j;
+    if (bb < p.ny + 1) {
+        i = 0; j = bb;
+    } else if (bb < 2 * (p.ny + 1)) {
+        i = p.nx; j = bb - (p.ny + 1);
+    } else if (bb < 2 * (p.ny + 1) + (p.nx - 1)) {
+        j = 0; i = 1 + bb - 2 * (p.ny + 1);
+    } else {
+        j = p.ny; i = 1 + bb - 2 * (p.ny + 1) - (p.nx - 1);
+    }
+    const int xc = (i == 0) ? 0 : (i == p.nx ? 2 : 1);
+    const int yc = (j == 0) ? 0 : (j == p.ny ? 2 : 1);
+    const int c54 = (xc + 3 * yc) * 54;
+    const int kbeg = bzi * ZM_ZB, kend = min(kbeg + ZM_ZB, p.nz + 1);
+    double aAi = 0.0, aAe = 0.0, aBi = 0.0, aBe = 0.0, aCi = 0.0, aCe = 0.0;   // nodes m - 1, m, m + 1
+    for (int m = max(kbeg - 1, 0); m <= min(kend, p.nz); ++m) {
+        const double* tC = st + (int64_t)min(m + 1, p.nz) * TABN + c54;
+        const double* tB = st + (int64_t)m * TABN + c54 + 9;
+        const double* tA = st + (int64_t)max(m - 1, 0) * TABN + c54 + 18;
+#pragma unroll 1
+        for (int dy = 0; dy < 3; ++dy) {
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int d = dx + 3 * dy;
+                const int gi = i - 1 + dx, gj = j - 1 + dy;
+                const bool ok = gi >= 0 && gi <= p.nx && gj >= 0 && gj <= p.ny;
+                const int64_t n = ok ? gi + (int64_t)p.nx1 * gj + plane * m : 0;
+                const double e0 = xe[n], v0 = xv[n];
+                const double e = ok ? e0 : 0.0, v = ok ? v0 + e0 : 0.0;
+                aCi = fma(tC[d], v, aCi);
+                aCe = fma(tC[27 + d], e, aCe);
+                aBi = fma(tB[d], v, aBi);
+                aBe = fma(tB[27 + d], e, aBe);
+                aAi = fma(tA[d], v, aAi);
+                aAe = fma(tA[27 + d], e, aAe);
+            }
+        }
+        const int k = m - 1;
+        if (act && k >= kbeg && k < kend)
+            stencil_out<MODE>(p, i, j, k, i + (int64_t)p.nx1 * j + plane * k, aAi, aAe, dg, xv, rv, re, vn, w,
+                              Is, stim, yv, ye);
+        aAi = aBi; aAe = aBe;
+        aBi = aCi; aBe = aCe;
+        aCi = 0.0; aCe = 0.0;
+    }
+    // the top node of the mesh has no plane above it
+    if (act && kend == p.nz + 1)
+        stencil_out<MODE>(p, i, j, p.nz, i + (int64_t)p.nx1 * j + plane * p.nz, aAi, aAe, dg, xv, rv, re, vn, w,
+                          Is, stim, yv, ye);
+}
+
 template <int MODE, int RY, int W, int SZ, int PF>
 __global__ __launch_bounds__(64 * W) void k_stencil_zm(FEParams p, const double* __restrict__ st,
                                                        const double* __restrict__ dg, const double* __restrict__ xv,
@@ -405,59 +482,8 @@ __global__ __launch_bounds__(64 * W) void k_stencil_zm(FEParams p, const double*
     if (tile >= g.ntile) return;
     const int64_t plane = (int64_t)p.nx1 * p.ny1;
     if (tile < g.nboundary) {
-        const int b = (tile % g.nbt) * (64 * W) + (int)(threadIdx.x + 64 * threadIdx.y);
-        const int bzi = tile / g.nbt;
-        const bool act = b < g.nbnd;
-        const int bb = act ? b : 0;
-        int i, j;
-        if (bb < p.ny + 1) {
-            i = 0; j = bb;
-        } else if (bb < 2 * (p.ny + 1)) {
-            i = p.nx; j = bb - (p.ny + 1);
-        } else if (bb < 2 * (p.ny + 1) + (p.nx - 1)) {
-            j = 0; i = 1 + bb - 2 * (p.ny + 1);
-        } else {
-            j = p.ny; i = 1 + bb - 2 * (p.ny + 1) - (p.nx - 1);
-        }
-        const int xc = (i == 0) ? 0 : (i == p.nx ? 2 : 1);
-        const int yc = (j == 0) ? 0 : (j == p.ny ? 2 : 1);
-        const int c54 = (xc + 3 * yc) * 54;
-        const int kbeg = bzi * ZM_ZB, kend = min(kbeg + ZM_ZB, p.nz + 1);
-        double aAi = 0.0, aAe = 0.0, aBi = 0.0, aBe = 0.0, aCi = 0.0, aCe = 0.0;   // nodes m - 1, m, m + 1
-        for (int m = max(kbeg - 1, 0); m <= min(kend, p.nz); ++m) {
-            const double* tC = st + (int64_t)min(m + 1, p.nz) * TABN + c54;
-            const double* tB = st + (int64_t)m * TABN + c54 + 9;
-            const double* tA = st + (int64_t)max(m - 1, 0) * TABN + c54 + 18;
-#pragma unroll 1
-            for (int dy = 0; dy < 3; ++dy) {
-#pragma unroll
-                for (int dx = 0; dx < 3; ++dx) {
-                    const int d = dx + 3 * dy;
-                    const int gi = i - 1 + dx, gj = j - 1 + dy;
-                    const bool ok = gi >= 0 && gi <= p.nx && gj >= 0 && gj <= p.ny;
-                    const int64_t n = ok ? gi + (int64_t)p.nx1 * gj + plane * m : 0;
-                    const double e0 = xe[n], v0 = xv[n];
-                    const double e = ok ? e0 : 0.0, v = ok ? v0 + e0 : 0.0;
-                    aCi = fma(tC[d], v, aCi);
-                    aCe = fma(tC[27 + d], e, aCe);
-                    aBi = fma(tB[d], v, aBi);
-                    aBe = fma(tB[27 + d], e, aBe);
-                    aAi = fma(tA[d], v, aAi);
-                    aAe = fma(tA[27 + d], e, aAe);
-                }
-            }
-            const int k = m - 1;
-            if (act && k >= kbeg && k < kend)
-                stencil_out<MODE>(p, i, j, k, i + (int64_t)p.nx1 * j + plane * k, aAi, aAe, dg, xv, rv, re, vn, w,
-                                  Is, stim, yv, ye);
-            aAi = aBi; aAe = aBe;
-            aBi = aCi; aBe = aCe;
-            aCi = 0.0; aCe = 0.0;
-        }
-        // the top node of the mesh has no plane above it
-        if (act && kend == p.nz + 1)
-            stencil_out<MODE>(p, i, j, p.nz, i + (int64_t)p.nx1 * j + plane * p.nz, aAi, aAe, dg, xv, rv, re, vn, w,
-                              Is, stim, yv, ye);
+        zm_boundary<MODE>(p, st, (tile % g.nbt) * (64 * W) + (int)(threadIdx.x + 64 * threadIdx.y), tile / g.nbt,
+                          g.nbnd, dg, xv, xe, rv, re, vn, w, Is, stim, yv, ye);
         return;
     }
     const int t = tile - g.nboundary;
@@ -591,6 +617,137 @@ __global__ __launch_bounds__(64 * W) void k_stencil_zm(FEParams p, const double*
     }
 }
 
+// The z-march with the x-y neighbours staged in LDS.  Boundary node columns
+// (x and y faces) are the register march's boundary threads.  An interior
+// tile is an SX x SY block of the x-y interior 1..nx-1 x 1..ny-1 walking SZ
+// levels: per plane, the (SX + 2) x (SY + 2) values of (v + u_e) and u_e
+// (halo included) go through a two-slot LDS ring with one barrier per plane
+// (the slot written next was last read before the previous barrier), and
+// each thread adds its 9 neighbours of the plane to the running sums of the
+// three nodes the plane touches (below, at, above), so a node's values are
+// read from LDS 18 times instead of 54.  Coefficients of the one interior
+// class are read at wave-uniform addresses (scalar loads), one target level
+// at a time.  Each sum takes the 27 products in the order of k_stencil, and
+// planes outside the mesh (zero values) are skipped, which leaves the
+// +0-started sums unchanged, so all variants agree bitwise.
+template <int SX, int SY, int SZ>
+struct ZlGrid {
+    int nbnd, nbt, nboundary, gx, gy, gz, ntile, per;
+    __host__ __device__ explicit ZlGrid(const FEParams& p) {
+        nbnd = 2 * (p.ny + 1) + 2 * (p.nx - 1);
+        nbt = (nbnd + SX * SY - 1) / (SX * SY);
+        nboundary = nbt * ((p.nz + 1 + ZM_ZB - 1) / ZM_ZB);
+        gx = (p.nx - 1 + SX - 1) / SX;
+        gy = (p.ny - 1 + SY - 1) / SY;
+        gz = (p.nz + 1 + SZ - 1) / SZ;
+        ntile = nboundary + gx * gy * gz;
+        per = (ntile + ST_XCD - 1) / ST_XCD;
+    }
+};
+
+template <int MODE, int SX, int SY, int SZ>
+__global__ __launch_bounds__(SX * SY) void k_stencil_zl(FEParams p, const double* __restrict__ st,
+                                                       const double* __restrict__ dg, const double* __restrict__ xv,
+                                                       const double* __restrict__ xe, const double* __restrict__ rv,
+                                                       const double* __restrict__ re, const double* __restrict__ vn,
+                                                       const double* __restrict__ w, const double* __restrict__ Is,
+                                                       double stim, double* __restrict__ yv,
+                                                       double* __restrict__ ye) {
+    constexpr int TABN = 9 * 2 * 27;
+    constexpr int PX = SX + 2, PY = SY + 2, NT = SX * SY, NPT = (PX * PY + NT - 1) / NT;
+    __shared__ double ps[2][PY][PX];
+    __shared__ double pe[2][PY][PX];
+    const ZlGrid<SX, SY, SZ> g(p);
+    // consecutive ids go round robin to the 8 XCDs; XCD x takes the run of
+    // tiles [x * per, (x + 1) * per) so neighbouring tiles share its L2
+    const int tile = ((int)blockIdx.x % ST_XCD) * g.per + (int)blockIdx.x / ST_XCD;
+    if (tile >= g.ntile) return;
+    const int tid = threadIdx.x;
+    if (tile < g.nboundary) {
+        zm_boundary<MODE>(p, st, (tile % g.nbt) * NT + tid, tile / g.nbt, g.nbnd, dg, xv, xe, rv, re, vn, w, Is,
+                          stim, yv, ye);
+        return;
+    }
+    const int t = tile - g.nboundary;
+    const int bxi = t % g.gx, byi = (t / g.gx) % g.gy, bzi = t / (g.gx * g.gy);
+    const int tx = tid % SX, ty = tid / SX;
+    const int i0 = 1 + bxi * SX, j0 = 1 + byi * SY;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool act = i <= p.nx - 1 && j <= p.ny - 1;
+    const int64_t plane = (int64_t)p.nx1 * p.ny1;
+    const int kbeg = bzi * SZ, kend = min(kbeg + SZ, p.nz + 1);
+    const int m0 = max(kbeg - 1, 0), m1 = min(kend, p.nz);
+    // plane m into registers (branch-free clamped loads, mask kept for the store)
+    double ra[NPT], rb[NPT];
+    bool rok[NPT];
+    auto fetch = [&](int m) {
+#pragma unroll
+        for (int q = 0; q < NPT; ++q) {
+            const int tt = tid + q * NT;
+            const int lx = tt % PX, ly = tt / PX;
+            const int gi = i0 - 1 + lx, gj = j0 - 1 + ly;
+            const bool ok = tt < PX * PY && gi <= p.nx && gj <= p.ny;
+            const int64_t n = ok ? gi + (int64_t)p.nx1 * gj + plane * m : 0;
+            ra[q] = xv[n];
+            rb[q] = xe[n];
+            rok[q] = ok;
+        }
+    };
+    double aAi = 0.0, aAe = 0.0, aBi = 0.0, aBe = 0.0, aCi = 0.0, aCe = 0.0;   // nodes m - 1, m, m + 1
+    fetch(m0);
+    for (int m = m0; m <= m1; ++m) {
+        const int sl = m & 1;
+#pragma unroll
+        for (int q = 0; q < NPT; ++q) {
+            const int tt = tid + q * NT;
+            if (tt < PX * PY) {
+                ps[sl][tt / PX][tt % PX] = rok[q] ? ra[q] + rb[q] : 0.0;
+                pe[sl][tt / PX][tt % PX] = rok[q] ? rb[q] : 0.0;
+            }
+        }
+        if (m < m1) fetch(m + 1);
+        __syncthreads();
+        double vx[3][3], ex[3][3];
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                vx[dy][dx] = ps[sl][ty + dy][tx + dx];
+                ex[dy][dx] = pe[sl][ty + dy][tx + dx];
+            }
+        // one target level at a time, so only its 18 coefficients are live
+        // in scalar registers (the empty asm statements order the groups)
+        auto add = [&](const double* tb, double& si, double& se) {
+            asm volatile("" : "+s"(tb));
+            const __attribute__((address_space(4))) double* tk =
+                (const __attribute__((address_space(4))) double*)tb;
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    const int d = dx + 3 * dy;
+                    si = fma(tk[d], vx[dy][dx], si);
+                    se = fma(tk[27 + d], ex[dy][dx], se);
+                }
+            asm volatile("" : "+v"(si), "+v"(se));
+        };
+        add(st + (int64_t)min(m + 1, p.nz) * TABN + 4 * 54, aCi, aCe);
+        add(st + (int64_t)m * TABN + 4 * 54 + 9, aBi, aBe);
+        add(st + (int64_t)max(m - 1, 0) * TABN + 4 * 54 + 18, aAi, aAe);
+        const int k = m - 1;
+        if (act && k >= kbeg && k < kend)
+            stencil_out<MODE>(p, i, j, k, i + (int64_t)p.nx1 * j + plane * k, aAi, aAe, dg, xv, rv, re, vn, w, Is,
+                              stim, yv, ye);
+        aAi = aBi; aAe = aBe;
+        aBi = aCi; aBe = aCe;
+        aCi = 0.0; aCe = 0.0;
+    }
+    // the top node of the mesh has no plane above it
+    if (act && kend == p.nz + 1)
+        stencil_out<MODE>(p, i, j, p.nz, i + (int64_t)p.nx1 * j + plane * p.nz, aAi, aAe, dg, xv, rv, re, vn, w,
+                          Is, stim, yv, ye);
+}
+
 __global__ void k_ionic_update(int64_t N, double tau, double eta2, double vp,
                                const double* __restrict__ v, double* __restrict__ w) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -615,8 +772,9 @@ __global__ void k_reaction_diag(FEParams p, const double* __restrict__ v, const 
 // Variants: 0-6 the LDS kernel with tiles (SX, SY, SZ) = (32, 8, 8),
 // (32, 8, 16), (64, 4, 8), (32, 4, 16), (16, 16, 8), (32, 8, 4), (16, 16, 4);
 // 7-10 the register march with (RY, W, SZ) = (1, 4, 8), (2, 4, 8),
-// (2, 4, 16), (4, 4, 8).
-constexpr int ST_NVAR = 11;
+// (2, 4, 16), (4, 4, 8); 11-13 the LDS z-march with (SX, SY, SZ) =
+// (32, 8, 16), (64, 4, 16), (32, 8, 32).
+constexpr int ST_NVAR = 14;
 
 template <int MODE, int SX, int SY, int SZ, typename... Args>
 void launch_stencil_shape(hipStream_t s, const FEParams& p, Args... args) {
@@ -629,6 +787,13 @@ template <int MODE, int RY, int W, int SZ, int PF, typename... Args>
 void launch_stencil_zm(hipStream_t s, const FEParams& p, Args... args) {
     const ZmGrid g = zm_grid<RY, W, SZ>(p);
     hipLaunchKernelGGL((k_stencil_zm<MODE, RY, W, SZ, PF>), dim3((unsigned)(g.per * ST_XCD)), dim3(64, W), 0, s, p,
+                       args...);
+}
+
+template <int MODE, int SX, int SY, int SZ, typename... Args>
+void launch_stencil_zl(hipStream_t s, const FEParams& p, Args... args) {
+    const ZlGrid<SX, SY, SZ> g(p);
+    hipLaunchKernelGGL((k_stencil_zl<MODE, SX, SY, SZ>), dim3((unsigned)(g.per * ST_XCD)), dim3(SX * SY), 0, s, p,
                        args...);
 }
 
@@ -645,6 +810,9 @@ void launch_stencil(hipStream_t s, const FEParams& p, Args... args) {
         case 8: launch_stencil_zm<MODE, 1, 4, 16, 2>(s, p, args...); break;
         case 9: launch_stencil_zm<MODE, 2, 4, 16, 1>(s, p, args...); break;
         case 10: launch_stencil_zm<MODE, 2, 4, 16, 2>(s, p, args...); break;
+        case 11: launch_stencil_zl<MODE, 32, 8, 16>(s, p, args...); break;
+        case 12: launch_stencil_zl<MODE, 64, 4, 16>(s, p, args...); break;
+        case 13: launch_stencil_zl<MODE, 32, 8, 32>(s, p, args...); break;
         default: launch_stencil_shape<MODE, 32, 8, 8>(s, p, args...);
     }
 }

@@ -10,9 +10,14 @@
 namespace bdm {
 
 // ---- fe.hip
-std::vector<double> layer_matrices(int nz, double h, double tau, const double sig_i[3],
+// element sizes hd = (hx, hy, hz)
+std::vector<double> layer_matrices(int nz, const double hd[3], double tau, const double sig_i[3],
                                    const double sig_e[3], double th0, double th1);
 std::vector<double> stencil_tables(int nz, const std::vector<double>& ke);
+// the same into caller buffers: ke of nz * 128 doubles, st of (nz + 1) * 486
+void layer_matrices_into(int nz, const double hd[3], double tau, const double sig_i[3], const double sig_e[3],
+                         double th0, double th1, double* ke);
+void stencil_tables_into(int nz, const double* ke, double* st);
 void launch_ionic_update(hipStream_t s, const FEParams& p, const double* v, double* w);
 void launch_residual(hipStream_t s, const FEParams& p, const double* st, const double* v,
                      const double* ue, const double* vn, const double* w, const double* Is,

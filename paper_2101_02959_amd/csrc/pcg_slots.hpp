@@ -1,4 +1,4 @@
-// Device scalar slots of the graph-captured PCG iteration (vec.hip, solver.hip).
+// Device scalar slots of the PCG iteration (vec.hip, solver.hip).
 #pragma once
 
 namespace bdm {
@@ -9,7 +9,7 @@ enum PcgSlot {
     PCG_ALPHA,
     PCG_RN2,         // r . r after the update
     PCG_ZR,          // z_new . r_new
-    PCG_ZRO,         // z_new . r_old
+    PCG_ZQ,          // z_new . q
     PCG_BETA,
     PCG_STATE,       // PCG_RUNNING, PCG_CONVERGED, PCG_DIVERGED, PCG_MAXIT
     PCG_IT,          // completed iterations

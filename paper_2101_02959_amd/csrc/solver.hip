@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <functional>
 #include <chrono>
+#include <limits>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -125,11 +126,19 @@ int Context::sync() {
     return 0;
 }
 
+// x . y read back to the host (a synchronisation).  A HIP failure sets
+// hip_err_ and the message and returns NaN, which every caller treats as a
+// failed step; callers return BDM_E_HIP when hip_err_ is set.
 double Context::dot(int64_t n, const double* x, const double* y) {
-    launch_dot(stream_, n, x, y, part_, scal_);
+    launch_dot(stream_, n, x, y, part_, tick_, scal_);
     double h = 0.0;
-    hipMemcpyAsync(&h, scal_, sizeof(double), hipMemcpyDeviceToHost, stream_);
-    hipStreamSynchronize(stream_);
+    hipError_t e = hipMemcpyAsync(&h, scal_, sizeof(double), hipMemcpyDeviceToHost, stream_);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream_);
+    if (e != hipSuccess) {
+        hip_err_ = true;
+        set_error(std::string("HIP error in a reduction: ") + hipGetErrorString(e));
+        return std::numeric_limits<double>::quiet_NaN();
+    }
     return h;
 }
 
@@ -161,10 +170,13 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
     fp.nx1 = m->nx + 1; fp.ny1 = m->ny + 1;
     fp.N = N;
     fp.h = m->h; fp.tau = o->dt; fp.c = ph->chi * ph->Cm;
+    fp.hy = m->hy > 0.0 ? m->hy : m->h;
+    fp.hz = m->hz > 0.0 ? m->hz : m->h;
     fp.chiG = ph->chi * ph->G; fp.chieta1 = ph->chi * ph->eta1; fp.eta2 = ph->eta2;
     fp.vth = ph->vth; fp.vp = ph->vp;
 
-    std::vector<double> ke = layer_matrices(m->nz, m->h, o->dt, ph->sigma_i, ph->sigma_e, ph->theta0, ph->theta1);
+    const double hd[3] = {fp.h, fp.hy, fp.hz};
+    std::vector<double> ke = layer_matrices(m->nz, hd, o->dt, ph->sigma_i, ph->sigma_e, ph->theta0, ph->theta1);
     std::vector<double> st = stencil_tables(m->nz, ke);
     ke_ = upload(ke);
     st_ = upload(st);
@@ -448,13 +460,18 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
     bad_ = (int*)dalloc(sizeof(int));
     const size_t kb = (size_t)std::max<int64_t>(2 * N, nlam_ + 2 * N) * sizeof(double);
     kx_ = (double*)dalloc(kb); kr_ = (double*)dalloc(kb); kz_ = (double*)dalloc(kb);
-    kp_ = (double*)dalloc(kb); kq_ = (double*)dalloc(kb); kro_ = (double*)dalloc(kb);
+    kp_ = (double*)dalloc(kb); kq_ = (double*)dalloc(kb);
     t1_ = (double*)dalloc(2 * vb); t2_ = (double*)dalloc(2 * vb); t3_ = (double*)dalloc(2 * vb);
     gzero_ = (double*)dalloc(2 * vb);
     R_ = (double*)dalloc(2 * vb); S_ = (double*)dalloc(2 * vb); U_ = (double*)dalloc(2 * vb);
     Rt_ = (double*)dalloc(2 * vb);
     part_ = (double*)dalloc(dot_partials() * sizeof(double));
     scal_ = (double*)dalloc(8 * sizeof(double));
+    tick_ = (unsigned*)dalloc(vec_tickets() * sizeof(unsigned));
+    if (!tick_ || hipMemset(tick_, 0, vec_tickets() * sizeof(unsigned)) != hipSuccess) {
+        set_error("device allocation failed (reduction tickets)");
+        return BDM_E_OOM;
+    }
     kry_hcap_ = std::max(opts.krylov_maxit, 1) + 1;
     kry_sc_ = (double*)dalloc(PCG_NSLOT * sizeof(double));
     kry_hist_ = (double*)dalloc((kry_hcap_ + 1) * sizeof(double));
@@ -546,7 +563,7 @@ int Context::set_state(const double* v, const double* ue, const double* w, doubl
     if (v) HIPOK(hipMemcpyAsync(v_, v, vb, k, stream_)); else HIPOK(hipMemsetAsync(v_, 0, vb, stream_));
     if (ue) HIPOK(hipMemcpyAsync(ue_, ue, vb, k, stream_)); else HIPOK(hipMemsetAsync(ue_, 0, vb, stream_));
     if (w) HIPOK(hipMemcpyAsync(w_, w, vb, k, stream_)); else HIPOK(hipMemsetAsync(w_, 0, vb, stream_));
-    launch_sub_mean(stream_, N, ue_, part_, scal_);
+    launch_sub_mean(stream_, N, ue_, part_, tick_, scal_);
     HIPOK(hipMemcpyAsync(vn_, v_, vb, hipMemcpyDeviceToDevice, stream_));
     t_ = t;
     have_prev_ = false;
@@ -993,18 +1010,24 @@ int Context::fetidp_apply_t(int op, const double* in, double* out) {
     }
 }
 
-// The same PCG with one iteration captured as two HIP graphs and replayed:
-// the operator half (A p, alpha, the updates of x and r, the stopping test)
-// and the preconditioner half (z = M r, beta, the update of p), which runs
-// only while the iteration continues.  The scalars (alpha, beta, norms,
-// state) stay on the device, neither half holds a host synchronisation or a
-// memset node, and the host reads the state back once per iteration.
-// Identical arithmetic, kernels and order to pcg().
-int Context::pcg_graph(int n, const double* b, double* x, bool feti, KrylovOut& out, bool reduced, double rref) {
+// PCG (zero initial guess, unpreconditioned residual norm test, Polak-Ribiere
+// beta; Sec. 4.1 and the Sec. 6 tolerances), on the full Jacobian with BDDC
+// or on the FETI-DP multiplier system.  One iteration is two halves of
+// device work: the operator half (q = A p, p.q, the fused x / r update with
+// ||r||^2 and the stopping test) and the preconditioner half (z = M r, the
+// fused z.r / z.q pass with beta, p = z + beta p).  The scalars alpha, beta,
+// the dots and the state (running, converged, diverged, iteration limit)
+// live in device slots; the host reads back the state and iteration count
+// (16 bytes) once per iteration.  With opts.krylov_graph the two halves are
+// captured once per operator and size, on a private non-blocking stream, as
+// two HIP graphs and replayed (no memset nodes and no host synchronisation
+// inside); the kernels, their order and the arithmetic are the same, so the
+// iterates are bitwise equal.
+int Context::pcg(int n, const double* b, double* x, bool feti, KrylovOut& out, bool reduced, double rref) {
     out = KrylovOut();
     const int maxit = opts.krylov_maxit;
     if (maxit > kry_hcap_) {
-        set_error("krylov_maxit exceeds the graph iteration history");
+        set_error("krylov_maxit exceeds the Krylov iteration history");
         return BDM_E_ARG;
     }
     auto A = [&](const double* in, double* o) -> int {
@@ -1018,17 +1041,32 @@ int Context::pcg_graph(int n, const double* b, double* x, bool feti, KrylovOut& 
                          : fetidp_apply_t<double>(BDM_FETI_PRECOND, in, o);
         return prec_ ? bddc_apply_t<float>(in, o, reduced) : bddc_apply_t<double>(in, o, reduced);
     };
+    auto op_half = [&]() -> int {
+        const int rc = A(kp_, kq_);
+        if (rc) return rc;
+        launch_dot(stream_, n, kp_, kq_, part_, tick_, kry_sc_ + PCG_PQ);
+        launch_pcg_update(stream_, n, kry_sc_, kp_, kq_, x, kr_, part_, tick_, kry_hist_, kry_ah_, maxit);
+        return 0;
+    };
+    auto prec_half = [&]() -> int {
+        const int rc = M(kr_, kz_);
+        if (rc) return rc;
+        launch_pcg_beta(stream_, n, kry_sc_, kz_, kr_, kq_, part_, tick_, kry_bh_);
+        launch_scale_add_dev(stream_, n, kz_, kry_sc_ + PCG_BETA, kp_);
+        return 0;
+    };
     // set-up, eager
     launch_fill(stream_, n, 0.0, x);
     launch_copy_kernel(stream_, n, b, kr_);
     const double r0 = std::sqrt(dot(n, kr_, kr_));
+    if (hip_err_) return BDM_E_HIP;
     const double ref = rref > 0.0 ? rref : r0;
     out.hist.push_back(r0);
     if (r0 == 0.0) return 0;
     int rc = M(kr_, kz_);
     if (rc) return rc;
     launch_copy_kernel(stream_, n, kz_, kp_);
-    launch_dot(stream_, n, kr_, kz_, part_, kry_sc_ + PCG_RZ);
+    launch_dot(stream_, n, kr_, kz_, part_, tick_, kry_sc_ + PCG_RZ);
     {
         double init[PCG_NSLOT] = {0};
         init[PCG_STATE] = PCG_RUNNING;
@@ -1040,69 +1078,54 @@ int Context::pcg_graph(int n, const double* b, double* x, bool feti, KrylovOut& 
                              hipMemcpyHostToDevice, stream_));
         HIPOK(hipStreamSynchronize(stream_));   // init lives on this host stack
     }
-    // capture both halves once per (operator, size)
-    const int key = (feti ? 1 : 0) + (reduced ? 2 : 0) + 4 * n;
-    if (!kry_exec_[0] || !kry_exec_[1] || kry_key_ != key) {
-        for (auto& g : kry_exec_)
-            if (g) {
-                hipGraphExecDestroy(g);
-                g = nullptr;
-            }
-        kry_key_ = -1;
-        if (!kry_stream_) HIPOK(hipStreamCreateWithFlags(&kry_stream_, hipStreamNonBlocking));
-        HIPOK(hipStreamSynchronize(stream_));
-        for (int half = 0; half < 2; ++half) {
-            hipStream_t saved = stream_;
-            stream_ = kry_stream_;
-            HIPOK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
-            int brc = 0;
-            if (half == 0) {
-                brc = A(kp_, kq_);
-                if (!brc) {
-                    launch_dot(stream_, n, kp_, kq_, part_, kry_sc_ + PCG_PQ);
-                    launch_pcg_alpha(stream_, kry_sc_);
-                    launch_axpy_dev(stream_, n, kry_sc_ + PCG_ALPHA, 1.0, kp_, x);
-                    launch_copy_kernel(stream_, n, kr_, kro_);
-                    launch_axpy_dev(stream_, n, kry_sc_ + PCG_ALPHA, -1.0, kq_, kr_);
-                    launch_dot(stream_, n, kr_, kr_, part_, kry_sc_ + PCG_RN2);
-                    launch_pcg_check(stream_, kry_sc_, kry_hist_, kry_ah_, maxit);
+    const bool graph = opts.krylov_graph != 0;
+    if (graph) {
+        // capture both halves once per (operator, size)
+        const int key = (feti ? 1 : 0) + (reduced ? 2 : 0) + 4 * n;
+        if (!kry_exec_[0] || !kry_exec_[1] || kry_key_ != key) {
+            for (auto& g : kry_exec_)
+                if (g) {
+                    hipGraphExecDestroy(g);
+                    g = nullptr;
                 }
-            } else {
-                brc = M(kr_, kz_);
-                if (!brc) {
-                    launch_dot(stream_, n, kz_, kr_, part_, kry_sc_ + PCG_ZR);
-                    launch_dot(stream_, n, kz_, kro_, part_, kry_sc_ + PCG_ZRO);
-                    launch_pcg_beta(stream_, kry_sc_, kry_bh_);
-                    launch_scale_add_dev(stream_, n, kz_, kry_sc_ + PCG_BETA, kp_);
+            kry_key_ = -1;
+            if (!kry_stream_) HIPOK(hipStreamCreateWithFlags(&kry_stream_, hipStreamNonBlocking));
+            HIPOK(hipStreamSynchronize(stream_));
+            for (int half = 0; half < 2; ++half) {
+                hipStream_t saved = stream_;
+                stream_ = kry_stream_;
+                HIPOK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
+                const int brc = half == 0 ? op_half() : prec_half();
+                hipGraph_t g = nullptr;
+                const hipError_t ce = hipStreamEndCapture(stream_, &g);
+                stream_ = saved;
+                if (brc) {
+                    if (g) hipGraphDestroy(g);
+                    return brc;
                 }
+                HIPOK(ce);
+                const hipError_t ie = hipGraphInstantiate(&kry_exec_[half], g, nullptr, nullptr, 0);
+                hipGraphDestroy(g);
+                HIPOK(ie);
             }
-            hipGraph_t g = nullptr;
-            const hipError_t ce = hipStreamEndCapture(stream_, &g);
-            stream_ = saved;
-            if (brc) {
-                if (g) hipGraphDestroy(g);
-                return brc;
-            }
-            HIPOK(ce);
-            const hipError_t ie = hipGraphInstantiate(&kry_exec_[half], g, nullptr, nullptr, 0);
-            hipGraphDestroy(g);
-            HIPOK(ie);
+            kry_key_ = key;
+            kry_x_ = x;
         }
-        kry_key_ = key;
-        kry_x_ = x;
-    }
-    // the operator half writes x: its pointer is part of the captured graph
-    if (x != kry_x_) {
-        set_error("internal error: graph PCG called with a different solution vector");
-        return BDM_E_STATE;
+        // the operator half writes x: its pointer is part of the captured graph
+        if (x != kry_x_) {
+            set_error("internal error: graph PCG called with a different solution vector");
+            return BDM_E_STATE;
+        }
     }
     double st[2] = {PCG_RUNNING, 0.0};
     for (int it = 0; it < maxit; ++it) {
-        HIPOK(hipGraphLaunch(kry_exec_[0], stream_));
+        if (graph) HIPOK(hipGraphLaunch(kry_exec_[0], stream_));
+        else if ((rc = op_half())) return rc;
         HIPOK(hipMemcpyAsync(st, kry_sc_ + PCG_STATE, 2 * sizeof(double), hipMemcpyDeviceToHost, stream_));
         HIPOK(hipStreamSynchronize(stream_));
         if (st[0] != PCG_RUNNING) break;
-        HIPOK(hipGraphLaunch(kry_exec_[1], stream_));
+        if (graph) HIPOK(hipGraphLaunch(kry_exec_[1], stream_));
+        else if ((rc = prec_half())) return rc;
     }
     const int its = (int)st[1];
     out.its = its;
@@ -1120,68 +1143,15 @@ int Context::pcg_graph(int n, const double* b, double* x, bool feti, KrylovOut& 
     return 0;
 }
 
-// PCG (zero initial guess, unpreconditioned residual norm test, Polak-Ribiere
-// beta), on the full Jacobian with BDDC or on the FETI-DP multiplier system.
-int Context::pcg(int n, const double* b, double* x, bool feti, KrylovOut& out, bool reduced, double rref) {
-    out = KrylovOut();
-    const size_t bytes = (size_t)n * sizeof(double);
-    HIPOK(hipMemsetAsync(x, 0, bytes, stream_));
-    HIPOK(hipMemcpyAsync(kr_, b, bytes, hipMemcpyDeviceToDevice, stream_));
-    const double r0 = std::sqrt(dot(n, kr_, kr_));
-    const double ref = rref > 0.0 ? rref : r0;
-    out.hist.push_back(r0);
-    if (r0 == 0.0) return 0;
-    auto A = [&](const double* in, double* o) -> int {
-        if (feti) return prec_ ? fetidp_apply_t<float>(BDM_FETI_F, in, o) : fetidp_apply_t<double>(BDM_FETI_F, in, o);
-        launch_jac_apply(stream_, fp, st_, dg_, in, o);
-        return 0;
-    };
-    auto M = [&](const double* in, double* o) -> int {
-        if (feti)
-            return prec_ ? fetidp_apply_t<float>(BDM_FETI_PRECOND, in, o)
-                         : fetidp_apply_t<double>(BDM_FETI_PRECOND, in, o);
-        return prec_ ? bddc_apply_t<float>(in, o, reduced) : bddc_apply_t<double>(in, o, reduced);
-    };
-    int rc = M(kr_, kz_);
-    if (rc) return rc;
-    HIPOK(hipMemcpyAsync(kp_, kz_, bytes, hipMemcpyDeviceToDevice, stream_));
-    double rz = dot(n, kr_, kz_);
-    out.status = 1;
-    for (int it = 0; it < opts.krylov_maxit; ++it) {
-        if ((rc = A(kp_, kq_))) return rc;
-        const double pq = dot(n, kp_, kq_);
-        const double alpha = rz / pq;
-        launch_axpy(stream_, n, alpha, kp_, x);
-        HIPOK(hipMemcpyAsync(kro_, kr_, bytes, hipMemcpyDeviceToDevice, stream_));
-        launch_axpy(stream_, n, -alpha, kq_, kr_);
-        out.alpha.push_back(alpha);
-        out.its = it + 1;
-        const double rn = std::sqrt(dot(n, kr_, kr_));
-        out.hist.push_back(rn);
-        if (!(rn == rn)) { out.status = 2; break; }
-        if (rn <= opts.krylov_rtol * ref) { out.status = 0; break; }
-        if (rn > opts.krylov_dtol * ref) { out.status = 2; break; }
-        if ((rc = M(kr_, kz_))) return rc;
-        const double zr = dot(n, kz_, kr_);
-        const double zro = dot(n, kz_, kro_);
-        const double beta = (zr - zro) / rz;
-        rz = zr;
-        out.beta.push_back(beta);
-        launch_scale_add(stream_, n, kz_, beta, kp_);
-    }
-    out.cond = lanczos_cond(out.alpha, out.beta);
-    return 0;
-}
-
 int Context::krylov(int n, const double* b, double* x, bool feti, KrylovOut& out, bool reduced, double rref) {
-    return opts.krylov_graph ? pcg_graph(n, b, x, feti, out, reduced, rref) : pcg(n, b, x, feti, out, reduced, rref);
+    return pcg(n, b, x, feti, out, reduced, rref);
 }
 
 // J s = b with the configured preconditioner.
 int Context::newton_solve(const double* b, double* s, KrylovOut& out) {
     // project the u_e block of b onto the range (zero sum)
     HIPOK(hipMemcpyAsync(Rt_, b, 2 * N * sizeof(double), hipMemcpyDeviceToDevice, stream_));
-    launch_sub_mean(stream_, N, Rt_ + N, part_, scal_);
+    launch_sub_mean(stream_, N, Rt_ + N, part_, tick_, scal_);
     if (opts.solver != BDM_SOLVER_FETIDP) {
         if (!opts.krylov_reduced) return krylov((int)(2 * N), Rt_, s, false, out);
         // s0 = interior solves of b, zero on the interface (Sec. 4.1); the
@@ -1387,7 +1357,9 @@ int Context::step(int nsteps, bdm_step_stats* st) {
         const double stim = (have_stim_ && nstep_ >= stim_on_ && nstep_ < stim_off_) ? 1.0 : 0.0;
         // reference residual ||R(u^n)||
         launch_residual(stream_, fp, st_, v_, ue_, vn_, w_, Is_, stim, R_, R_ + N);
+        hip_err_ = false;
         const double ref = std::sqrt(dot(2 * N, R_, R_));
+        if (hip_err_) return BDM_E_HIP;
         S.res_ref = ref;
         // initial guess: u^n, extrapolation, or the better (smaller ||R||) of the
         // learned and the extrapolated guess
@@ -1451,18 +1423,31 @@ int Context::step(int nsteps, bdm_step_stats* st) {
                 break;
             }
             if (ko.status == 1) status = BDM_E_KRYLOV_MAXIT;
-            // line search on f = ||R||^2 / 2 (Armijo, quadratic then cubic backtracking)
+            // line search on f = ||R||^2 / 2 (Sec. 6: Armijo test, then
+            // backtracking by the minimiser of a quadratic model after the
+            // first failure and of a cubic model after later ones, each new
+            // step kept in [0.1, 0.5] of the previous; a non-finite f is not
+            // modelled but halves the step)
             const double f0 = 0.5 * rn * rn, g0 = -2.0 * f0, alpha = 1e-4;
             double lam = 1.0, lam_prev = 0.0, f_prev = 0.0, f = 0.0;
+            bool accepted = false, modelled = false;
             for (int ls = 0; ls < 20; ++ls) {
                 HIPOK(hipMemcpyAsync(Rt_, U_, 2 * vb, hipMemcpyDeviceToDevice, stream_));
                 launch_axpy(stream_, 2 * N, lam, S_, Rt_);
                 launch_residual(stream_, fp, st_, Rt_, Rt_ + N, vn_, w_, Is_, stim, kq_, kq_ + N);
                 f = 0.5 * dot(2 * N, kq_, kq_);
-                if (f <= f0 + alpha * lam * g0) break;
+                if (std::isfinite(f) && f <= f0 + alpha * lam * g0) {
+                    accepted = true;
+                    break;
+                }
+                if (!std::isfinite(f)) {
+                    lam *= 0.5;
+                    continue;
+                }
                 double lt;
-                if (ls == 0) {
+                if (!modelled) {
                     lt = -g0 / (2.0 * (f - f0 - g0));
+                    modelled = true;
                 } else {
                     const double r1 = f - f0 - lam * g0, r2 = f_prev - f0 - lam_prev * g0;
                     const double a = (r1 / (lam * lam) - r2 / (lam_prev * lam_prev)) / (lam - lam_prev);
@@ -1474,9 +1459,17 @@ int Context::step(int nsteps, bdm_step_stats* st) {
                 f_prev = f;
                 lam = std::min(std::max(lt, 0.1 * lam), 0.5 * lam);
             }
+            S.step_length[it] = lam;
+            if (hip_err_) return BDM_E_HIP;
+            if (!accepted) {
+                set_error("line search: no step along the Newton direction passed the Armijo test in 20 trials");
+                status = BDM_E_LINESEARCH;
+                ++it;
+                break;
+            }
             HIPOK(hipMemcpyAsync(U_, Rt_, 2 * vb, hipMemcpyDeviceToDevice, stream_));
             HIPOK(hipMemcpyAsync(R_, kq_, 2 * vb, hipMemcpyDeviceToDevice, stream_));
-            launch_sub_mean(stream_, N, U_ + N, part_, scal_);
+            launch_sub_mean(stream_, N, U_ + N, part_, tick_, scal_);
             rn = std::sqrt(2.0 * f);
             S.res_hist[it + 1] = rn;
         }

@@ -92,7 +92,6 @@ class Context {
     template <typename T> int bddc_apply_t(const double* r, double* z, bool interior_free = false);
     template <typename T> int fetidp_apply_t(int op, const double* in, double* out);
     int pcg(int n, const double* b, double* x, bool feti, KrylovOut& out, bool reduced = false, double rref = 0.0);
-    int pcg_graph(int n, const double* b, double* x, bool feti, KrylovOut& out, bool reduced = false, double rref = 0.0);
     int krylov(int n, const double* b, double* x, bool feti, KrylovOut& out, bool reduced = false, double rref = 0.0);
     int newton_solve(const double* b, double* s, KrylovOut& out);
     int sync();
@@ -160,11 +159,13 @@ class Context {
     long nlam_ = 0;
 
     // Krylov / Newton workspace (2N or n_lambda doubles)
-    double *kx_ = nullptr, *kr_ = nullptr, *kz_ = nullptr, *kp_ = nullptr, *kq_ = nullptr, *kro_ = nullptr;
+    double *kx_ = nullptr, *kr_ = nullptr, *kz_ = nullptr, *kp_ = nullptr, *kq_ = nullptr;
     double *t1_ = nullptr, *t2_ = nullptr, *t3_ = nullptr, *gzero_ = nullptr;
     double *R_ = nullptr, *S_ = nullptr, *U_ = nullptr, *Rt_ = nullptr;
     double *part_ = nullptr, *scal_ = nullptr;
-    // graph-captured PCG: device scalars and histories, the cached graph
+    unsigned* tick_ = nullptr;   // reduction tickets (vec.hip), zero between launches
+    bool hip_err_ = false;       // a host read-back of a reduction failed
+    // PCG: device scalars and histories, the cached graphs
     double *kry_sc_ = nullptr, *kry_hist_ = nullptr, *kry_ah_ = nullptr, *kry_bh_ = nullptr;
     int kry_hcap_ = 0, kry_key_ = -1;
     double* kry_x_ = nullptr;

@@ -1,14 +1,30 @@
-// FP64 vector kernels of the Krylov and Newton loops.  Dot products use a
-// fixed two-stage reduction (per-block partial sums, then one block), so
-// they are deterministic.
+// FP64 vector kernels of the Krylov and Newton loops.
+//
+// Reductions are single launches: each workgroup sums its grid-stride share
+// (64-lane shuffles, then the four waves in order) and stores a partial; the
+// last workgroup to take a ticket (an integer atomic) adds the partials in
+// workgroup order and writes the total.  The order of every floating-point
+// addition is fixed by the grid size alone, so results are deterministic.
+// The ticket is back at zero when the kernel ends, so the kernels can be
+// replayed from a captured graph without a reset.
+//
+// One PCG iteration (Sec. 4.1 CG on the Newton system, or on the FETI-DP
+// multiplier system, Sec. 4.3) is, besides the operator and the
+// preconditioner: p.q (one pass), the fused update x += alpha p,
+// r -= alpha q with ||r||^2 and the stopping test (one pass), the fused
+// z.r and z.q with the Polak-Ribiere beta = -alpha (z.q) / (z_old.r_old)
+// (one pass; r_new - r_old = -alpha q, so r_old need not be kept), and
+// p = z + beta p.  The scalars live in device slots (pcg_slots.hpp).
 #include "bddc_kernels.hpp"
 #include "common.hpp"
 #include "pcg_slots.hpp"
 
 namespace bdm {
 
-constexpr int kDotBlocks = 1024;
-int dot_partials() { return kDotBlocks; }
+constexpr int kVecBlocks = 2048;   // workgroups of the reducing kernels
+int dot_partials() { return 2 * kVecBlocks; }
+int vec_tickets() { return 4; }
+enum { TK_DOT = 0, TK_UPDATE = 1, TK_BETA = 2, TK_SUM = 3 };
 
 namespace {
 
@@ -28,21 +44,126 @@ __device__ inline double block_sum(double v) {
     return t;
 }
 
-__global__ __launch_bounds__(kWG) void k_dot_partial(int64_t n, const double* __restrict__ x,
-                                                    const double* __restrict__ y, double* __restrict__ part) {
-    double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG)
-        acc = fma(x[i], y[i], acc);
-    acc = block_sum(acc);
-    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+// K workgroup partial sums: stored at part[k * gridDim.x + blockIdx.x]; the
+// last workgroup to arrive returns true with the K totals in tot (in every
+// one of its threads).  Every thread of the workgroup calls it.
+template <int K>
+__device__ bool reduce_last(const double (&acc)[K], double* __restrict__ part, unsigned* __restrict__ ticket,
+                            double (&tot)[K]) {
+    __shared__ double red[K][kWG / 64];
+    __shared__ int last;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double v = wsum(acc[k]);
+        if ((threadIdx.x & 63) == 0) red[k][threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double t = 0.0;
+            for (int q = 0; q < kWG / 64; ++q) t += red[k][q];
+            part[(int64_t)k * gridDim.x + blockIdx.x] = t;
+        }
+        __threadfence();                               // partials visible device-wide
+        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();                                   // see every workgroup's partial
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double a = 0.0;
+        for (int i = threadIdx.x; i < (int)gridDim.x; i += kWG)
+            a += __hip_atomic_load(part + (int64_t)k * gridDim.x + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        tot[k] = block_sum(a);
+    }
+    if (threadIdx.x == 0) atomicExch(ticket, 0u);
+    return true;
 }
 
-__global__ __launch_bounds__(kWG) void k_sum_partials(int np, const double* __restrict__ part,
-                                                     double* __restrict__ out) {
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < np; i += kWG) acc += part[i];
-    acc = block_sum(acc);
-    if (threadIdx.x == 0) out[0] = acc;
+__global__ __launch_bounds__(kWG) void k_dot(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+                                            double* __restrict__ part, unsigned* __restrict__ ticket,
+                                            double* __restrict__ out) {
+    double acc[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG)
+        acc[0] = fma(x[i], y[i], acc[0]);
+    double tot[1];
+    if (reduce_last<1>(acc, part, ticket, tot) && threadIdx.x == 0) out[0] = tot[0];
+}
+
+__global__ __launch_bounds__(kWG) void k_sum(int64_t n, const double* __restrict__ x, double* __restrict__ part,
+                                            unsigned* __restrict__ ticket, double* __restrict__ out) {
+    double acc[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG)
+        acc[0] += x[i];
+    double tot[1];
+    if (reduce_last<1>(acc, part, ticket, tot) && threadIdx.x == 0) out[0] = tot[0];
+}
+
+// x += alpha p, r -= alpha q with alpha = (z.r) / (p.q) from the slots, then
+// ||r||^2 and the stopping test: the iteration count, residual and alpha
+// histories and the state (diverged on a non-finite or too large residual,
+// converged, iteration limit).  Once the state is not PCG_RUNNING the
+// kernel leaves x, r and the slots unchanged.
+__global__ __launch_bounds__(kWG) void k_pcg_update(int64_t n, double* __restrict__ sc, const double* __restrict__ p,
+                                                   const double* __restrict__ q, double* __restrict__ x,
+                                                   double* __restrict__ r, double* __restrict__ part,
+                                                   unsigned* __restrict__ ticket, double* __restrict__ hist,
+                                                   double* __restrict__ ah, int maxit) {
+    const bool run = sc[PCG_STATE] == PCG_RUNNING;
+    // a breakdown (p . q = 0) gives a non-finite alpha and residual, which the
+    // test reports as divergence
+    const double alpha = run ? sc[PCG_RZ] / sc[PCG_PQ] : 0.0;
+    double acc[1] = {0.0};
+    if (run) {
+        for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG) {
+            x[i] = fma(alpha, p[i], x[i]);
+            const double ri = fma(-alpha, q[i], r[i]);
+            r[i] = ri;
+            acc[0] = fma(ri, ri, acc[0]);
+        }
+    }
+    double tot[1];
+    if (reduce_last<1>(acc, part, ticket, tot) && threadIdx.x == 0 && run) {
+        const int it = (int)sc[PCG_IT];
+        const double rn = sqrt(tot[0]);
+        sc[PCG_ALPHA] = alpha;
+        sc[PCG_RN2] = tot[0];
+        ah[it] = alpha;
+        hist[it + 1] = rn;
+        sc[PCG_IT] = it + 1;
+        if (!(rn == rn) || rn > sc[PCG_DTOL]) sc[PCG_STATE] = PCG_DIVERGED;
+        else if (rn <= sc[PCG_TOL]) sc[PCG_STATE] = PCG_CONVERGED;
+        else if (it + 1 >= maxit) sc[PCG_STATE] = PCG_MAXIT;
+    }
+}
+
+// z.r and z.q in one pass, then the Polak-Ribiere beta
+//   z_new.(r_new - r_old) / (z_old.r_old) = -alpha (z_new.q) / (z_old.r_old)
+// (r_new = r_old - alpha q), its history, and z.r for the next alpha.
+__global__ __launch_bounds__(kWG) void k_pcg_beta(int64_t n, double* __restrict__ sc, const double* __restrict__ z,
+                                                 const double* __restrict__ r, const double* __restrict__ q,
+                                                 double* __restrict__ part, unsigned* __restrict__ ticket,
+                                                 double* __restrict__ bh) {
+    double acc[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG) {
+        const double zi = z[i];
+        acc[0] = fma(zi, r[i], acc[0]);
+        acc[1] = fma(zi, q[i], acc[1]);
+    }
+    double tot[2];
+    if (reduce_last<2>(acc, part, ticket, tot) && threadIdx.x == 0) {
+        double b = 0.0;
+        if (sc[PCG_STATE] == PCG_RUNNING) {
+            b = -sc[PCG_ALPHA] * tot[1] / sc[PCG_RZ];
+            sc[PCG_RZ] = tot[0];
+            bh[(int)sc[PCG_IT] - 1] = b;
+        }
+        sc[PCG_ZR] = tot[0];
+        sc[PCG_ZQ] = tot[1];
+        sc[PCG_BETA] = b;
+    }
 }
 
 __global__ void k_axpy(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
@@ -58,15 +179,6 @@ __global__ void k_scale_add(int64_t n, const double* __restrict__ z, double b, d
 __global__ void k_sub_scalar(int64_t n, const double* __restrict__ sum, double* __restrict__ x) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) x[i] -= sum[0] / (double)n;
-}
-
-__global__ __launch_bounds__(kWG) void k_sum_partial(int64_t n, const double* __restrict__ x,
-                                                    double* __restrict__ part) {
-    double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG)
-        acc += x[i];
-    acc = block_sum(acc);
-    if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
 // Device-scalar variants for the graph-captured Krylov iteration.
@@ -98,39 +210,6 @@ __global__ void k_copy(int64_t n, const double* __restrict__ x, double* __restri
     if (i < n) y[i] = x[i];
 }
 
-// PCG scalar steps on device (slots in pcg_slots.hpp order).  Once the state
-// is no longer PCG_RUNNING the iteration is frozen: alpha = beta = 0, so a
-// replay after the stop leaves x and r unchanged.
-__global__ void k_pcg_alpha(double* __restrict__ sc) {
-    // a breakdown (p . q = 0) gives a non-finite alpha and residual, which the
-    // check below reports as divergence, as the host-driven loop does
-    sc[PCG_ALPHA] = (sc[PCG_STATE] == PCG_RUNNING) ? sc[PCG_RZ] / sc[PCG_PQ] : 0.0;
-}
-
-__global__ void k_pcg_check(double* __restrict__ sc, double* __restrict__ hist, double* __restrict__ ah,
-                            int maxit) {
-    if (sc[PCG_STATE] != PCG_RUNNING) return;
-    const int it = (int)sc[PCG_IT];
-    const double rn = sqrt(sc[PCG_RN2]);
-    ah[it] = sc[PCG_ALPHA];
-    hist[it + 1] = rn;
-    sc[PCG_IT] = it + 1;
-    if (!(rn == rn) || rn > sc[PCG_DTOL]) sc[PCG_STATE] = PCG_DIVERGED;
-    else if (rn <= sc[PCG_TOL]) sc[PCG_STATE] = PCG_CONVERGED;
-    else if (it + 1 >= maxit) sc[PCG_STATE] = PCG_MAXIT;
-}
-
-__global__ void k_pcg_beta(double* __restrict__ sc, double* __restrict__ bh) {
-    double b = 0.0;
-    if (sc[PCG_STATE] == PCG_RUNNING) {
-        // Polak-Ribiere: (z_new . r_new - z_new . r_old) / (z_old . r_old)
-        b = (sc[PCG_ZR] - sc[PCG_ZRO]) / sc[PCG_RZ];
-        sc[PCG_RZ] = sc[PCG_ZR];
-        bh[(int)sc[PCG_IT] - 1] = b;
-    }
-    sc[PCG_BETA] = b;
-}
-
 }  // namespace
 
 static inline unsigned nb(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -153,17 +232,19 @@ template void launch_fill_t<double>(hipStream_t, int64_t, double, double*);
 void launch_copy_kernel(hipStream_t s, int64_t n, const double* x, double* y) {
     if (n > 0) hipLaunchKernelGGL(k_copy, dim3(nb(n, 256)), dim3(256), 0, s, n, x, y);
 }
-void launch_pcg_alpha(hipStream_t s, double* sc) { hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(1), 0, s, sc); }
-void launch_pcg_check(hipStream_t s, double* sc, double* hist, double* ah, int maxit) {
-    hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(1), 0, s, sc, hist, ah, maxit);
+void launch_pcg_update(hipStream_t s, int64_t n, double* sc, const double* p, const double* q, double* x, double* r,
+                       double* partial, unsigned* tickets, double* hist, double* ah, int maxit) {
+    hipLaunchKernelGGL(k_pcg_update, dim3(kVecBlocks), dim3(kWG), 0, s, n, sc, p, q, x, r, partial,
+                       tickets + TK_UPDATE, hist, ah, maxit);
 }
-void launch_pcg_beta(hipStream_t s, double* sc, double* bh) {
-    hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(1), 0, s, sc, bh);
+void launch_pcg_beta(hipStream_t s, int64_t n, double* sc, const double* z, const double* r, const double* q,
+                     double* partial, unsigned* tickets, double* bh) {
+    hipLaunchKernelGGL(k_pcg_beta, dim3(kVecBlocks), dim3(kWG), 0, s, n, sc, z, r, q, partial, tickets + TK_BETA, bh);
 }
 
-void launch_dot(hipStream_t s, int64_t n, const double* x, const double* y, double* partial, double* out) {
-    hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(kWG), 0, s, n, x, y, partial);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kWG), 0, s, kDotBlocks, partial, out);
+void launch_dot(hipStream_t s, int64_t n, const double* x, const double* y, double* partial, unsigned* tickets,
+                double* out) {
+    hipLaunchKernelGGL(k_dot, dim3(kVecBlocks), dim3(kWG), 0, s, n, x, y, partial, tickets + TK_DOT, out);
 }
 void launch_axpy(hipStream_t s, int64_t n, double a, const double* x, double* y) {
     hipLaunchKernelGGL(k_axpy, dim3(nb(n, 256)), dim3(256), 0, s, n, a, x, y);
@@ -175,9 +256,8 @@ void launch_scale_add(hipStream_t s, int64_t n, const double* z, double b, doubl
     hipLaunchKernelGGL(k_scale_add, dim3(nb(n, 256)), dim3(256), 0, s, n, z, b, p);
 }
 // x <- x - mean(x)
-void launch_sub_mean(hipStream_t s, int64_t n, double* x, double* partial, double* tmp) {
-    hipLaunchKernelGGL(k_sum_partial, dim3(kDotBlocks), dim3(kWG), 0, s, n, x, partial);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kWG), 0, s, kDotBlocks, partial, tmp);
+void launch_sub_mean(hipStream_t s, int64_t n, double* x, double* partial, unsigned* tickets, double* tmp) {
+    hipLaunchKernelGGL(k_sum, dim3(kVecBlocks), dim3(kWG), 0, s, n, x, partial, tickets + TK_SUM, tmp);
     hipLaunchKernelGGL(k_sub_scalar, dim3(nb(n, 256)), dim3(256), 0, s, n, tmp, x);
 }
 

@@ -1,16 +1,18 @@
 """Parity of the HIP path (through the C ABI) against the FP64 oracle.
 
-Sizes span several tiles and ragged (uneven) subdomains; comparisons are
-element by element.  FP64 path: relative 1e-11 on operator outputs and 1e-8
-on the Newton solution.  Mixed path (FP32 local factors): relative 5e-5 on a
-single preconditioner application (FP32 round-off amplified by the local
-condition numbers, ~1e3), and 1e-8 on the Newton solution, which the FP64
-outer iteration corrects.
+Sizes span several tiles and ragged (uneven) subdomains.  Comparisons are
+per field (v, u_e) in the relative 2-norm and element by element
+(max |a - b| <= tol max |b|, tests/parity_util.py).  FP64 path: 1e-11 on
+operator outputs and 1e-8 on the Newton solution.  Mixed path (FP32 local
+factors): 5e-5 on a single preconditioner application (FP32 round-off
+amplified by the local condition numbers, ~1e3), and 1e-8 on the Newton
+solution, which the FP64 outer iteration corrects.
 """
 import numpy as np
 import pytest
 
 from oracle import bddc, bidomain, dd, fetidp, newton
+from parity_util import assert_close
 from workload import Mesh, Physics, Solver as SolverOpts, small_mesh, stimulus_nodal, workload
 
 pytestmark = pytest.mark.gpu
@@ -28,11 +30,9 @@ MESHES = {
     "ragged": Mesh(11, 9, 10, 0.01, (0, 3, 7, 11), (0, 5, 9), (0, 4, 10)),
     # 4x4x2 uneven subdomains: a coarse elimination tree of several levels
     "uneven442": Mesh(20, 18, 12, 0.01, (0, 4, 9, 13, 20), (0, 5, 9, 14, 18), (0, 5, 12)),
+    # box elements of 0.01 x 0.02 x 0.02 cm (the Test 4 slab's element shape, Sec. 6)
+    "box": Mesh(12, 8, 6, 0.01, (0, 5, 12), (0, 4, 8), (0, 3, 6), hy=0.02, hz=0.02),
 }
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def _gauge(x, N):
@@ -62,12 +62,12 @@ def test_residual_and_jacobian(mname):
     S.bdm_set_stimulus(Is, 0, 1)
     R = S.bdm_residual(v, ue).cpu().numpy()
     Rref = prob.residual(v, ue - ue.mean(), vn, w, Is)
-    assert _rel(R, Rref) < 1e-12
+    assert_close(R, Rref, 1e-12, N, "residual")
     S.bdm_linearize(v, w)
     x = np.random.default_rng(3).standard_normal(2 * N)
     y = S.bdm_jacobian_apply(x).cpu().numpy()
     yref = prob.jacobian(v, w) @ x
-    assert _rel(y, yref) < 1e-12
+    assert_close(y, yref, 1e-12, N, "jacobian")
 
 
 @pytest.fixture(scope="module", params=list(MESHES))
@@ -94,7 +94,7 @@ def test_bddc_apply(lin, prec, tol):
         r = newton.project_range(np.random.default_rng(seed).standard_normal(2 * N), N)
         z = _gauge(S.bdm_bddc_apply(r).cpu().numpy(), N)
         zref = _gauge(B.apply(r), N)
-        assert _rel(z, zref) < tol, (seed, _rel(z, zref))
+        assert_close(z, zref, tol, N, f"bddc seed {seed}")
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 5e-5)])
@@ -109,16 +109,16 @@ def test_fetidp_operators(lin, prec, tol):
     rng = np.random.default_rng(7)
     lam = rng.standard_normal(F.nlam)
     out = S.bdm_fetidp_apply(P.BDM_FETI_F, lam).cpu().numpy()
-    assert _rel(out, F.F(lam)) < tol
+    assert_close(out, F.F(lam), tol, None, "F")
     out = S.bdm_fetidp_apply(P.BDM_FETI_PRECOND, lam).cpu().numpy()
-    assert _rel(out, F.precond(lam)) < tol
+    assert_close(out, F.precond(lam), tol, None, "precond")
     r = newton.project_range(rng.standard_normal(2 * N), N)
     g = F.condense(r)
     d = S.bdm_fetidp_apply(P.BDM_FETI_RHS, r).cpu().numpy()
-    assert _rel(d, F.rhs(g)) < tol
+    assert_close(d, F.rhs(g), tol, None, "rhs")
     z = S.bdm_fetidp_apply(P.BDM_FETI_RECOVER, np.concatenate([r, lam])).cpu().numpy()
     zref = F.expand(r, F.recover(g, lam))
-    assert _rel(_gauge(z, N), _gauge(zref, N)) < tol
+    assert_close(_gauge(z, N), _gauge(zref, N), tol, N, "recover")
 
 
 @pytest.mark.parametrize("method,prec,reduced", [(0, 0, True), (1, 0, True), (0, 1, True),
@@ -144,9 +144,9 @@ def test_time_steps_match_direct_newton(method, prec, reduced):
         vg, ueg, wg, _ = S.bdm_get_state()
         vg, ueg, wg = vg.cpu().numpy(), ueg.cpu().numpy(), wg.cpu().numpy()
         vr, uer, wr, _ = bidomain.time_step_direct(prob, v, ue, w, Is)
-        assert _rel(vg, vr) <= 1e-8, (step, _rel(vg, vr))
-        assert _rel(ueg, uer) <= 1e-8, (step, _rel(ueg, uer))
-        assert _rel(wg, wr) <= 1e-14
+        assert_close(vg, vr, 1e-8, None, f"v step {step}")
+        assert_close(ueg, uer, 1e-8, None, f"u_e step {step}")
+        assert_close(wg, wr, 1e-14, None, f"w step {step}")
         assert 1 <= st.newton_its <= 5
         assert all(3 <= st.krylov_its[k] <= 60 for k in range(st.newton_its))
         # error of each Newton linear solve, recomputed in FP64 after the solve:
@@ -179,7 +179,8 @@ def test_fetidp_step_with_more_multipliers_than_dofs(graph):
         vg, ueg, _, _ = S.bdm_get_state()
         z = np.zeros(N)
         vr, uer, _, _ = bidomain.time_step_direct(prob, z, z, z, Is)
-        assert _rel(vg.cpu().numpy(), vr) <= 1e-8 and _rel(ueg.cpu().numpy(), uer) <= 1e-8
+        assert_close(vg.cpu().numpy(), vr, 1e-8, None, "v")
+        assert_close(ueg.cpu().numpy(), uer, 1e-8, None, "u_e")
         assert all(st.krylov_true_res[k] <= 1e-6 for k in range(st.newton_its))
     finally:
         S.close()
@@ -220,7 +221,7 @@ def test_coarse_tree_shapes(mname, leaf, prec, tol, monkeypatch):
     S = P.Solver(mesh, Physics(), SolverOpts(), precision=prec)
     try:
         S.bdm_linearize(v, w)
-        assert _rel(_gauge(S.bdm_bddc_apply(r).cpu().numpy(), N), zref) < tol
+        assert_close(_gauge(S.bdm_bddc_apply(r).cpu().numpy(), N), zref, tol, N, f"leaf {leaf}")
     finally:
         S.close()
 
@@ -235,4 +236,72 @@ def test_bddc_chunked_setup(lin, monkeypatch):
     S.bdm_linearize(v, w)
     r = newton.project_range(np.random.default_rng(8).standard_normal(2 * N), N)
     z = _gauge(S.bdm_bddc_apply(r).cpu().numpy(), N)
-    assert _rel(z, _gauge(B.apply(r), N)) < 1e-11
+    assert_close(z, _gauge(B.apply(r), N), 1e-11, N, "chunked")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_backtracking_step_matches_oracle(prec):
+    """A Newton step that needs the line search (Sec. 6: cubic backtracking):
+    tau = 0.3 ms (inside the 0.366 ms coercivity bound of Sec. 3c) from v
+    near (v_th + v_p)/3, where dI_ion/dv is most negative, so the first
+    Newton directions overshoot and the full step fails the Armijo test.
+    The accepted step lengths per Newton iteration equal the oracle's
+    (quadratic, then cubic model minimisers, clamped), and the Newton
+    solution matches the direct root per field."""
+    import dataclasses
+    P = _solver_mod()
+    wl = workload("slab8_supra")
+    so = dataclasses.replace(wl.solver, dt=0.3)
+    mesh = wl.mesh
+    prob = bidomain.Problem(mesh, wl.physics, so.dt)
+    N = prob.N
+    v0 = 37.67 + np.random.default_rng(3).uniform(-1, 1, N)
+    z = np.zeros(N)
+    ost = newton.StepStats()
+    newton.time_step(prob, dd.Decomposition(mesh), v0, z, z, z, stats=ost)
+    assert min(ost.lambdas) < 1.0
+    S = P.Solver(mesh, wl.physics, so, precision=prec)
+    try:
+        S.bdm_set_state(v0, z, z)
+        st = S.bdm_step(1)
+        lam = list(st.step_length)[:st.newton_its]
+        print(prec, lam, ost.lambdas)
+        assert st.newton_its == ost.newton_its
+        np.testing.assert_allclose(lam, ost.lambdas, rtol=1e-6)
+        vg, ueg, _, _ = S.bdm_get_state()
+        vg, ueg = vg.cpu().numpy(), ueg.cpu().numpy()
+        vr, uer, _, _ = bidomain.time_step_direct(prob, v0, z, z, z)
+        assert_close(vg, vr, 1e-8, None, "v")
+        assert_close(ueg, uer, 1e-8, None, "u_e")
+    finally:
+        S.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_time_steps_on_box_elements(prec):
+    """Box elements of 0.01 x 0.02 x 0.02 cm (the element shape of the Test 4
+    slab, Sec. 6): three time steps from rest with the corner stimulus, the
+    Newton solution within 1e-8 per field of the oracle's direct root."""
+    P = _solver_mod()
+    wl = workload("slab8_supra")
+    mesh = MESHES["box"]
+    prob = bidomain.Problem(mesh, wl.physics, wl.solver.dt)
+    N = prob.N
+    S = P.Solver(mesh, wl.physics, wl.solver, precision=prec, guess=P.BDM_GUESS_EXTRAP)
+    try:
+        Is = stimulus_nodal(mesh, (2, 2, 2), 1e5)
+        z = np.zeros(N)
+        S.bdm_set_state(z, z, z)
+        S.bdm_set_stimulus(Is, 0, 20)
+        v, ue, w = z, z, z
+        for step in range(3):
+            st = S.bdm_step(1)
+            vg, ueg, wg, _ = S.bdm_get_state()
+            vg, ueg, wg = vg.cpu().numpy(), ueg.cpu().numpy(), wg.cpu().numpy()
+            vr, uer, wr, _ = bidomain.time_step_direct(prob, v, ue, w, Is)
+            assert_close(vg, vr, 1e-8, None, f"v step {step}")
+            assert_close(ueg, uer, 1e-8, None, f"u_e step {step}")
+            assert all(st.krylov_true_res[k] <= 1e-9 for k in range(st.newton_its))
+            v, ue, w = vg, ueg, wg
+    finally:
+        S.close()

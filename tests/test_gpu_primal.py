@@ -1,7 +1,8 @@
 """Primal spaces (V, V+E, V+E+F; Sec. 4.4) and scalings (deluxe, rho;
 Sec. 4.2) of the HIP path against the FP64 oracle, through the C ABI.
 
-  * One BDDC application, element by element: FP64 local factors within
+  * One BDDC application, per field (v, u_e) in the relative 2-norm and
+    element by element (tests/parity_util.py): FP64 local factors within
     1e-11 relative; FP32 ones within 5e-5 for V+E and V+E+F (FP32 round-off
     times local condition numbers of about 1e3, as for deluxe V+E), and
     within 5e-4 for V alone, whose preconditioned spectrum is more than ten
@@ -19,6 +20,7 @@ import numpy as np
 import pytest
 
 from oracle import bddc, bidomain, dd, fetidp, newton
+from parity_util import assert_close
 from workload import Mesh, Physics, Solver as SolverOpts, stimulus_nodal, small_mesh
 
 pytestmark = pytest.mark.gpu
@@ -31,10 +33,6 @@ MESHES = {
 }
 PRIMAL = {"V": 1, "VE": 0, "VEF": 2}
 SCALING = {"deluxe": 0, "rho": 1}
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def _gauge(x, N):
@@ -67,8 +65,7 @@ def test_bddc_apply_matches_oracle(mname, scaling, primal):
             S.bdm_linearize(v, w)
             for r, zref in zip(rs, refs):
                 z = _gauge(S.bdm_bddc_apply(r).cpu().numpy(), N)
-                print(mname, scaling, primal, prec, _rel(z, zref))
-                assert _rel(z, zref) < tol, (prec, _rel(z, zref))
+                print(mname, scaling, primal, prec, assert_close(z, zref, tol, N, f"bddc prec {prec}"))
         finally:
             S.close()
 
@@ -91,7 +88,7 @@ def test_fetidp_operators_match_oracle(scaling, primal):
         lam = np.random.default_rng(8).standard_normal(F.nlam)
         for op, ref in ((P.BDM_FETI_F, F.F(lam)), (P.BDM_FETI_PRECOND, F.precond(lam))):
             got = S.bdm_fetidp_apply(op, lam).cpu().numpy()
-            assert _rel(got, ref) < 1e-11, (op, _rel(got, ref))
+            assert_close(got, ref, 1e-11, None, f"op {op}")
     finally:
         S.close()
 
@@ -119,7 +116,8 @@ def test_time_step_matches_oracle_on_4x4x4(scaling, primal):
     z = np.zeros(N)
     vr, uer, _, ost = newton.time_step(prob, dec, z, z, z, Is, rtol=so.newton_rtol, krtol=so.krylov_rtol,
                                        scaling=scaling)
-    assert _rel(vg, vr) <= 1e-8 and _rel(ueg, uer) <= 1e-8
+    assert_close(vg, vr, 1e-8, None, "v")
+    assert_close(ueg, uer, 1e-8, None, "u_e")
     assert st.newton_its == ost.newton_its
     for k in range(st.newton_its):
         assert abs(st.krylov_its[k] - ost.krylov_its[k]) <= 1, (k, st.krylov_its[k], ost.krylov_its[k])
@@ -149,6 +147,6 @@ def test_objects_above_512_dofs(scaling):
     try:
         S.bdm_linearize(v, w)
         z = _gauge(S.bdm_bddc_apply(r).cpu().numpy(), N)
-        assert _rel(z, zref) < 1e-11, _rel(z, zref)
+        assert_close(z, zref, 1e-11, N, "bddc")
     finally:
         S.close()

@@ -150,3 +150,63 @@ def test_jacobian_finite_differences_and_symmetry():
     dg = p.reaction_diag(v, w)
     assert np.allclose((J - J.T).diagonal(), 0)
     assert np.allclose(J.diagonal()[:p.N], dg + p.tau * p.Ai.diagonal(), rtol=1e-13)
+
+
+def _kron_box_stiffness(D, hs):
+    """Q1 box stiffness by separation of variables, an independent route to
+    the oracle's Gauss quadrature: with per-axis 1-D matrices
+    K1 = int psi_a' psi_b' = [[1, -1], [-1, 1]] / h_d,
+    M1 = int psi_a psi_b = h_d [[2, 1], [1, 2]] / 6 and
+    C1 = int psi_a' psi_b = [[-1, -1], [1, 1]] / 2 (rows a),
+    A = sum_pq D_pq (F_z (x) F_y (x) F_x), F_d = K1 if d = p = q, C1 if
+    d = p != q, C1^T if d = q != p, else M1 (local node a + 2b + 4c: x
+    fastest, so z is the outer Kronecker factor)."""
+    K1 = lambda h: np.array([[1.0, -1.0], [-1.0, 1.0]]) / h
+    M1 = lambda h: h * np.array([[2.0, 1.0], [1.0, 2.0]]) / 6.0
+    C1 = np.array([[-1.0, -1.0], [1.0, 1.0]]) / 2.0
+    A = np.zeros((8, 8))
+    for p in range(3):
+        for q in range(3):
+            F = []
+            for d in range(3):
+                if d == p and d == q:
+                    F.append(K1(hs[d]))
+                elif d == p:
+                    F.append(C1)
+                elif d == q:
+                    F.append(C1.T)
+                else:
+                    F.append(M1(hs[d]))
+            A += D[p, q] * np.kron(F[2], np.kron(F[1], F[0]))
+    return A
+
+
+def test_box_element_stiffness_and_mass_separable_form():
+    """Box elements of sizes (0.01, 0.02, 0.02) cm (the Test 4 slab of
+    Sec. 6: 1.92 x 1.92 x 0.48 cm on 192 x 96 x 24 elements): the quadrature
+    stiffness equals the separable form for a rotated anisotropic tensor,
+    kills constants, and the element mass sums to the element volume."""
+    hs = (0.01, 0.02, 0.02)
+    D = fem.conductivity((3.0, 0.31525, 0.031525), 0.7)
+    A = fem.element_stiffness(D, hs)
+    assert np.allclose(A, _kron_box_stiffness(D, hs), rtol=1e-13, atol=1e-18)
+    assert np.abs(A @ np.ones(8)).max() < 1e-15
+    Me = fem.element_mass(hs)
+    assert Me.sum() == pytest.approx(0.01 * 0.02 * 0.02, rel=1e-14)
+    # the cube case of the same route
+    assert np.allclose(fem.element_stiffness(D, 0.01), _kron_box_stiffness(D, (0.01,) * 3), rtol=1e-13)
+
+
+def test_box_mesh_lumped_mass_and_fibre_heights():
+    """On a mesh of box elements the lumped mass sums to the slab volume,
+    interior nodes carry hx hy hz, and the fibre angle of the top layer is
+    evaluated at its centroid height (nz - 1/2) hz of the slab height nz hz."""
+    from workload import Mesh
+    m = Mesh(6, 4, 3, 0.01, (0, 3, 6), (0, 2, 4), (0, 1, 3), hy=0.02, hz=0.03)
+    assert m.spacing == (0.01, 0.02, 0.03)
+    _, _, M = fem.assemble(m, Physics())
+    assert M.sum() == pytest.approx(6 * 0.01 * 4 * 0.02 * 3 * 0.03, rel=1e-14)
+    assert M[fem.node_id(m, 1, 1, 1)] == pytest.approx(0.01 * 0.02 * 0.03, rel=1e-14)
+    Ai, _ = fem.layer_stiffness(m, Physics())
+    th = Physics().theta0 + (Physics().theta1 - Physics().theta0) * 2.5 / 3
+    assert np.allclose(Ai[2], fem.element_stiffness(fem.conductivity(Physics().sigma_i, th), m.spacing))

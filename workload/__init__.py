@@ -38,6 +38,8 @@ class Physics:
 
 @dataclasses.dataclass(frozen=True)
 class Mesh:
+    """nx x ny x nz box elements of size h x hy x hz (hy, hz <= 0: equal to
+    h, i.e. cubes of side h) and the tensor partition's cut positions."""
     nx: int
     ny: int
     nz: int
@@ -45,6 +47,13 @@ class Mesh:
     cuts_x: tuple
     cuts_y: tuple
     cuts_z: tuple
+    hy: float = 0.0
+    hz: float = 0.0
+
+    @property
+    def spacing(self) -> tuple:
+        """Element sizes (hx, hy, hz)."""
+        return (self.h, self.hy if self.hy > 0 else self.h, self.hz if self.hz > 0 else self.h)
 
     @property
     def nnodes(self) -> int:
@@ -201,18 +210,22 @@ def test2(parts, steps: int = 40) -> Workload:
     return Workload(f"test2_{px}x{py}x{pz}", m, Physics(), Solver(), PAPER_STIM, (2, 2, 2), 20, steps, None)
 
 
-def test4(parts=(24, 12, 3), steps: int = 2400) -> Workload:
+def test4(parts=(24, 12, 3), steps: int = 2400, paper_geometry: bool = True) -> Workload:
     """The whole-beat slab of Sec. 6, Test 4: 192 x 96 x 24 elements in equal
-    box subdomains (the paper uses 8 x 8 x 2), corner stimulus, 2400 steps
-    of 0.05 ms (120 ms: activation and recovery).  The mesh keeps cubic
-    elements of h = 0.01 cm (1.92 x 0.96 x 0.24 cm); the paper's slab of
-    1.92 x 1.92 x 0.48 cm on the same element counts has elements of
-    0.01 x 0.02 x 0.02 cm, which a single h cannot express."""
+    box subdomains (the paper uses 8 x 8 x 2), corner stimulus of 2 x 2 x 2
+    elements, 2400 steps of 0.05 ms (120 ms: activation and recovery).  With
+    paper_geometry the slab is the paper's 1.92 x 1.92 x 0.48 cm, i.e. box
+    elements of 0.01 x 0.02 x 0.02 cm (so the paper's 8 x 8 x 2 partition
+    has subdomains that are 0.24 cm cubes of 24 x 12 x 12 elements);
+    otherwise cubic elements of 0.01 cm (a 1.92 x 0.96 x 0.24 cm slab)."""
     px, py, pz = parts
     if 192 % px or 96 % py or 24 % pz:
         raise ValueError("parts must divide 192 x 96 x 24")
     m = box_mesh(192, 96, 24, 0.01, px, py, pz)
-    return Workload(f"test4_{px}x{py}x{pz}", m, Physics(), Solver(), PAPER_STIM, (2, 2, 2), 20, steps, None)
+    if paper_geometry:
+        m = dataclasses.replace(m, hy=0.02, hz=0.02)
+    tag = "" if paper_geometry else "_cubic"
+    return Workload(f"test4_{px}x{py}x{pz}{tag}", m, Physics(), Solver(), PAPER_STIM, (2, 2, 2), 20, steps, None)
 
 
 def small_mesh(n: Sequence[int], parts: Sequence[int], h: float = 0.01) -> Mesh:
