@@ -330,6 +330,25 @@ int bdm_profile_kernel(bdm_ctx* ctx, int kernel, int reps, double* avg_ms, doubl
  * returned, so a caller can size its buffer from *len. */
 int bdm_tune_report(bdm_ctx* ctx, char* buf, long cap, long* len);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * residual of bdm_residual without a context and without any device
+ * allocation.  Inputs (device, N doubles each): the iterate v, u_e, the
+ * previous potential v^n, the gating variable w^{n+1} and, when stim_on is
+ * nonzero, the nodal stimulus Is (it may be NULL otherwise); outputs Rv, Re
+ * (device, N each); mesh and physics as for bdm_create (the partition
+ * arrays are not read) and the time step dt.  Work runs on hip_stream (a
+ * hipStream_t, NULL = default) and the call returns after synchronising
+ * it.  The coefficient tables the kernels read live in a static device
+ * array of about 4 MB per GPU, held until the process ends: nz + 1 must not
+ * exceed 1024 (BDM_E_ARG otherwise).  Calls on one GPU share that array and
+ * are serialised by a host mutex; device work enqueued concurrently by
+ * other code is not ordered against a call.  BDM_E_ARG for a null
+ * argument or non-positive sizes, h or dt; BDM_E_HIP for a runtime error. */
+int bdm_residual_noalloc(const bdm_mesh* mesh, const bdm_physics* phys, double dt, const double* v,
+                         const double* ue, const double* vn, const double* w, const double* Is, int stim_on,
+                         double* Rv, double* Re, void* hip_stream);
+
 /* Sizes for callers that allocate vectors: N, number of subdomains, global
  * primal (coarse) dimension. */
 int bdm_sizes(bdm_ctx* ctx, long* n_nodes, long* n_sub, long* n_primal);

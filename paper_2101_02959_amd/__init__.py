@@ -11,4 +11,5 @@ from .bidomain import (BDM_FETI_F, BDM_FETI_PRECOND, BDM_FETI_RECOVER, BDM_FETI_
                        BDM_KERNEL_POTRF_INTERIOR, BDM_KERNEL_SYRK_UPDATE, BDM_KERNEL_TRSV_DIRICHLET,
                        BDM_KERNEL_TRSV_DIRICHLET_T, BDM_PREC_FP64, BDM_PREC_MIXED, BDM_SCHED_GRID,
                        BDM_SCHED_QUEUE, BDM_SOLVER_BDDC, BDM_SOLVER_FETIDP, BidomainError, Solver, lib,
-                       BDM_SCALING_DELUXE, BDM_SCALING_RHO, BDM_PRIMAL_VE, BDM_PRIMAL_V, BDM_PRIMAL_VEF)
+                       BDM_SCALING_DELUXE, BDM_SCALING_RHO, BDM_PRIMAL_VE, BDM_PRIMAL_V, BDM_PRIMAL_VEF,
+                       bdm_residual_noalloc)

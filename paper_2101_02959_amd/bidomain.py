@@ -35,7 +35,8 @@ EXPORTS = ("bdm_create", "bdm_destroy", "bdm_set_state", "bdm_get_state", "bdm_s
            "bdm_ionic_update", "bdm_residual", "bdm_linearize", "bdm_jacobian_apply",
            "bdm_bddc_apply", "bdm_fetidp_size", "bdm_fetidp_apply", "bdm_step", "bdm_sizes",
            "bdm_profile_kernel", "bdm_tune_report", "bdm_predictor_size", "bdm_predictor_set", "bdm_predictor_get",
-           "bdm_predictor_guess", "bdm_predictor_loss_grad", "bdm_predictor_train", "bdm_last_error")
+           "bdm_predictor_guess", "bdm_predictor_loss_grad", "bdm_predictor_train", "bdm_residual_noalloc",
+           "bdm_last_error")
 
 
 class BidomainError(RuntimeError):
@@ -110,6 +111,8 @@ def lib():
         "bdm_predictor_guess": ([vp, vp, vp, vp, vp, vp], ci),
         "bdm_predictor_loss_grad": ([vp, vp, C.POINTER(C.c_float), C.POINTER(cd)], ci),
         "bdm_predictor_train": ([vp, vp, ci, C.POINTER(ci), ci, cd, C.POINTER(cd)], ci),
+        "bdm_residual_noalloc": ([C.POINTER(bdm_mesh), C.POINTER(bdm_physics), cd, vp, vp, vp, vp, vp, ci, vp, vp,
+                                  vp], ci),
         "bdm_last_error": ([], C.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -315,3 +318,27 @@ class Solver:
         _check(rc)
         return st
 
+
+def bdm_residual_noalloc(mesh, physics, dt, v, ue, vn, w, Is=None, stream=None):
+    """Residual of bdm_residual without a context or any device allocation
+    (C entry point of the same name).  v, ue, vn, w, Is: CUDA float64 tensors
+    of N entries (Is optional); returns (Rv, Re) allocated here by torch,
+    before the call."""
+    import torch
+    m, ph, _, keep = make_structs(mesh, physics, _SolverDt(dt))
+    dev = v.device
+    Rv = torch.empty_like(v)
+    Re = torch.empty_like(v)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    _check(lib().bdm_residual_noalloc(C.byref(m), C.byref(ph), float(dt), _ptr(v), _ptr(ue), _ptr(vn), _ptr(w),
+                                      _ptr(Is), 1 if Is is not None else 0, _ptr(Rv), _ptr(Re), C.c_void_p(stream)))
+    del keep
+    return Rv, Re
+
+
+class _SolverDt:
+    """Solver options carrying only dt, for make_structs."""
+    def __init__(self, dt):
+        self.dt, self.newton_rtol, self.newton_atol, self.newton_maxit = dt, 1e-8, 0.0, 1
+        self.krylov_rtol, self.krylov_dtol, self.krylov_maxit = 1e-10, 1e4, 1

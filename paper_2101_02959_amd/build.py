@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libbidomain.so")
 
-SOURCES = ["topology.cpp", "tune.cpp", "fe.hip", "dense.hip", "bddc.hip", "vec.hip", "coarse.hip", "learned.hip", "solver.hip", "capi.hip"]
+SOURCES = ["topology.cpp", "tune.cpp", "fe.hip", "dense.hip", "bddc.hip", "vec.hip", "coarse.hip", "learned.hip", "solver.hip", "capi.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
