@@ -1024,6 +1024,45 @@ __global__ __launch_bounds__(kWG) void k_coarse_local(BatchDesc d, const T* __re
     }
 }
 
+// The local coarse block S_PiPi^(j) = Phi^T S_Gamma^(j) Phi annihilates the
+// primal vector k with 1 on every u_e primal (vertex value or average) and
+// 0 on every v primal: Phi k is the constant u_e = 1, v = 0, which meets the
+// constraints and has zero energy (Sec. 4.4; the kernel of the Jacobian,
+// Sec. 3c).  Computed from rounded local factors the block only nearly
+// does, and the assembled coarse matrix, which has a small eigenvalue along
+// the pinned near-kernel (the u_e-constant mode of a large subdomain grid),
+// amplifies the defect.  Replacing the block by P S P, P = I - k k^T /
+// (k^T k), restores the exact kernel; it changes the block by the size of
+// the defect.  Local primal order: (v, u_e) per vertex, then (v, u_e)
+// averages per constraint object, so k is 1 on the odd local indices.
+__global__ __launch_bounds__(kWG) void k_coarse_kernel_fix(int sub0, const int* __restrict__ nVv,
+                                                          const int* __restrict__ ncv, double* __restrict__ Spb) {
+    const int s = sub0 + blockIdx.x;
+    const int nP = nVv[s] + ncv[s];
+    double* S = Spb + (int64_t)s * SP_STRIDE;
+    __shared__ double w[MAXP];
+    __shared__ double sk;
+    const int tid = threadIdx.x;
+    if (tid < nP) {
+        double a = 0.0;
+        for (int j = 1; j < nP; j += 2) a += S[tid + (int64_t)j * nP];
+        w[tid] = a;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double a = 0.0;
+        for (int i = 1; i < nP; i += 2) a += w[i];
+        sk = a;
+    }
+    __syncthreads();
+    const double kk = 0.5 * nP;
+    for (int idx = tid; idx < nP * nP; idx += kWG) {
+        const int i = idx % nP, j = idx / nP;
+        const double ki = (i & 1) ? 1.0 : 0.0, kj = (j & 1) ? 1.0 : 0.0;
+        S[i + (int64_t)j * nP] += -(w[i] * kj + ki * w[j]) / kk + sk * ki * kj / (kk * kk);
+    }
+}
+
 // ------------------------------------------------- single-RHS triangular
 // Forward L x = b or backward L^T x = b, in place, one workgroup per vector;
 // x lives in LDS (dynamic, n values) for the whole solve.  Per 32-column
@@ -1567,6 +1606,7 @@ template <typename T>
 void launch_coarse_local(hipStream_t s, const BatchDesc& d, const T* F, const double* Svv, T* Z,
                          double* Sp, int* info) {
     hipLaunchKernelGGL(k_coarse_local<T>, dim3(d.nsub), dim3(kWG), 0, s, d, F, Svv, Z, Sp, info);
+    hipLaunchKernelGGL(k_coarse_kernel_fix, dim3(d.nsub), dim3(kWG), 0, s, d.sub0, d.nV, d.nc, Sp);
 }
 template <typename T, bool FWD, bool BWD>
 void launch_trsv_kern(hipStream_t s, int nb, const T* L, const int64_t* Loff, const int* n, T* x,

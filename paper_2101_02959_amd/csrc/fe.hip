@@ -617,137 +617,6 @@ __global__ __launch_bounds__(64 * W) void k_stencil_zm(FEParams p, const double*
     }
 }
 
-// The z-march with the x-y neighbours staged in LDS.  Boundary node columns
-// (x and y faces) are the register march's boundary threads.  An interior
-// tile is an SX x SY block of the x-y interior 1..nx-1 x 1..ny-1 walking SZ
-// levels: per plane, the (SX + 2) x (SY + 2) values of (v + u_e) and u_e
-// (halo included) go through a two-slot LDS ring with one barrier per plane
-// (the slot written next was last read before the previous barrier), and
-// each thread adds its 9 neighbours of the plane to the running sums of the
-// three nodes the plane touches (below, at, above), so a node's values are
-// read from LDS 18 times instead of 54.  Coefficients of the one interior
-// class are read at wave-uniform addresses (scalar loads), one target level
-// at a time.  Each sum takes the 27 products in the order of k_stencil, and
-// planes outside the mesh (zero values) are skipped, which leaves the
-// +0-started sums unchanged, so all variants agree bitwise.
-template <int SX, int SY, int SZ>
-struct ZlGrid {
-    int nbnd, nbt, nboundary, gx, gy, gz, ntile, per;
-    __host__ __device__ explicit ZlGrid(const FEParams& p) {
-        nbnd = 2 * (p.ny + 1) + 2 * (p.nx - 1);
-        nbt = (nbnd + SX * SY - 1) / (SX * SY);
-        nboundary = nbt * ((p.nz + 1 + ZM_ZB - 1) / ZM_ZB);
-        gx = (p.nx - 1 + SX - 1) / SX;
-        gy = (p.ny - 1 + SY - 1) / SY;
-        gz = (p.nz + 1 + SZ - 1) / SZ;
-        ntile = nboundary + gx * gy * gz;
-        per = (ntile + ST_XCD - 1) / ST_XCD;
-    }
-};
-
-template <int MODE, int SX, int SY, int SZ>
-__global__ __launch_bounds__(SX * SY) void k_stencil_zl(FEParams p, const double* __restrict__ st,
-                                                       const double* __restrict__ dg, const double* __restrict__ xv,
-                                                       const double* __restrict__ xe, const double* __restrict__ rv,
-                                                       const double* __restrict__ re, const double* __restrict__ vn,
-                                                       const double* __restrict__ w, const double* __restrict__ Is,
-                                                       double stim, double* __restrict__ yv,
-                                                       double* __restrict__ ye) {
-    constexpr int TABN = 9 * 2 * 27;
-    constexpr int PX = SX + 2, PY = SY + 2, NT = SX * SY, NPT = (PX * PY + NT - 1) / NT;
-    __shared__ double ps[2][PY][PX];
-    __shared__ double pe[2][PY][PX];
-    const ZlGrid<SX, SY, SZ> g(p);
-    // consecutive ids go round robin to the 8 XCDs; XCD x takes the run of
-    // tiles [x * per, (x + 1) * per) so neighbouring tiles share its L2
-    const int tile = ((int)blockIdx.x % ST_XCD) * g.per + (int)blockIdx.x / ST_XCD;
-    if (tile >= g.ntile) return;
-    const int tid = threadIdx.x;
-    if (tile < g.nboundary) {
-        zm_boundary<MODE>(p, st, (tile % g.nbt) * NT + tid, tile / g.nbt, g.nbnd, dg, xv, xe, rv, re, vn, w, Is,
-                          stim, yv, ye);
-        return;
-    }
-    const int t = tile - g.nboundary;
-    const int bxi = t % g.gx, byi = (t / g.gx) % g.gy, bzi = t / (g.gx * g.gy);
-    const int tx = tid % SX, ty = tid / SX;
-    const int i0 = 1 + bxi * SX, j0 = 1 + byi * SY;
-    const int i = i0 + tx, j = j0 + ty;
-    const bool act = i <= p.nx - 1 && j <= p.ny - 1;
-    const int64_t plane = (int64_t)p.nx1 * p.ny1;
-    const int kbeg = bzi * SZ, kend = min(kbeg + SZ, p.nz + 1);
-    const int m0 = max(kbeg - 1, 0), m1 = min(kend, p.nz);
-    // plane m into registers (branch-free clamped loads, mask kept for the store)
-    double ra[NPT], rb[NPT];
-    bool rok[NPT];
-    auto fetch = [&](int m) {
-#pragma unroll
-        for (int q = 0; q < NPT; ++q) {
-            const int tt = tid + q * NT;
-            const int lx = tt % PX, ly = tt / PX;
-            const int gi = i0 - 1 + lx, gj = j0 - 1 + ly;
-            const bool ok = tt < PX * PY && gi <= p.nx && gj <= p.ny;
-            const int64_t n = ok ? gi + (int64_t)p.nx1 * gj + plane * m : 0;
-            ra[q] = xv[n];
-            rb[q] = xe[n];
-            rok[q] = ok;
-        }
-    };
-    double aAi = 0.0, aAe = 0.0, aBi = 0.0, aBe = 0.0, aCi = 0.0, aCe = 0.0;   // nodes m - 1, m, m + 1
-    fetch(m0);
-    for (int m = m0; m <= m1; ++m) {
-        const int sl = m & 1;
-#pragma unroll
-        for (int q = 0; q < NPT; ++q) {
-            const int tt = tid + q * NT;
-            if (tt < PX * PY) {
-                ps[sl][tt / PX][tt % PX] = rok[q] ? ra[q] + rb[q] : 0.0;
-                pe[sl][tt / PX][tt % PX] = rok[q] ? rb[q] : 0.0;
-            }
-        }
-        if (m < m1) fetch(m + 1);
-        __syncthreads();
-        double vx[3][3], ex[3][3];
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                vx[dy][dx] = ps[sl][ty + dy][tx + dx];
-                ex[dy][dx] = pe[sl][ty + dy][tx + dx];
-            }
-        // one target level at a time, so only its 18 coefficients are live
-        // in scalar registers (the empty asm statements order the groups)
-        auto add = [&](const double* tb, double& si, double& se) {
-            asm volatile("" : "+s"(tb));
-            const __attribute__((address_space(4))) double* tk =
-                (const __attribute__((address_space(4))) double*)tb;
-#pragma unroll
-            for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                for (int dx = 0; dx < 3; ++dx) {
-                    const int d = dx + 3 * dy;
-                    si = fma(tk[d], vx[dy][dx], si);
-                    se = fma(tk[27 + d], ex[dy][dx], se);
-                }
-            asm volatile("" : "+v"(si), "+v"(se));
-        };
-        add(st + (int64_t)min(m + 1, p.nz) * TABN + 4 * 54, aCi, aCe);
-        add(st + (int64_t)m * TABN + 4 * 54 + 9, aBi, aBe);
-        add(st + (int64_t)max(m - 1, 0) * TABN + 4 * 54 + 18, aAi, aAe);
-        const int k = m - 1;
-        if (act && k >= kbeg && k < kend)
-            stencil_out<MODE>(p, i, j, k, i + (int64_t)p.nx1 * j + plane * k, aAi, aAe, dg, xv, rv, re, vn, w, Is,
-                              stim, yv, ye);
-        aAi = aBi; aAe = aBe;
-        aBi = aCi; aBe = aCe;
-        aCi = 0.0; aCe = 0.0;
-    }
-    // the top node of the mesh has no plane above it
-    if (act && kend == p.nz + 1)
-        stencil_out<MODE>(p, i, j, p.nz, i + (int64_t)p.nx1 * j + plane * p.nz, aAi, aAe, dg, xv, rv, re, vn, w,
-                          Is, stim, yv, ye);
-}
-
 __global__ void k_ionic_update(int64_t N, double tau, double eta2, double vp,
                                const double* __restrict__ v, double* __restrict__ w) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -772,9 +641,8 @@ __global__ void k_reaction_diag(FEParams p, const double* __restrict__ v, const 
 // Variants: 0-6 the LDS kernel with tiles (SX, SY, SZ) = (32, 8, 8),
 // (32, 8, 16), (64, 4, 8), (32, 4, 16), (16, 16, 8), (32, 8, 4), (16, 16, 4);
 // 7-10 the register march with (RY, W, SZ) = (1, 4, 8), (2, 4, 8),
-// (2, 4, 16), (4, 4, 8); 11-13 the LDS z-march with (SX, SY, SZ) =
-// (32, 8, 16), (64, 4, 16), (32, 8, 32).
-constexpr int ST_NVAR = 14;
+// (2, 4, 16), (4, 4, 8).
+constexpr int ST_NVAR = 11;
 
 template <int MODE, int SX, int SY, int SZ, typename... Args>
 void launch_stencil_shape(hipStream_t s, const FEParams& p, Args... args) {
@@ -787,13 +655,6 @@ template <int MODE, int RY, int W, int SZ, int PF, typename... Args>
 void launch_stencil_zm(hipStream_t s, const FEParams& p, Args... args) {
     const ZmGrid g = zm_grid<RY, W, SZ>(p);
     hipLaunchKernelGGL((k_stencil_zm<MODE, RY, W, SZ, PF>), dim3((unsigned)(g.per * ST_XCD)), dim3(64, W), 0, s, p,
-                       args...);
-}
-
-template <int MODE, int SX, int SY, int SZ, typename... Args>
-void launch_stencil_zl(hipStream_t s, const FEParams& p, Args... args) {
-    const ZlGrid<SX, SY, SZ> g(p);
-    hipLaunchKernelGGL((k_stencil_zl<MODE, SX, SY, SZ>), dim3((unsigned)(g.per * ST_XCD)), dim3(SX * SY), 0, s, p,
                        args...);
 }
 
@@ -810,9 +671,6 @@ void launch_stencil(hipStream_t s, const FEParams& p, Args... args) {
         case 8: launch_stencil_zm<MODE, 1, 4, 16, 2>(s, p, args...); break;
         case 9: launch_stencil_zm<MODE, 2, 4, 16, 1>(s, p, args...); break;
         case 10: launch_stencil_zm<MODE, 2, 4, 16, 2>(s, p, args...); break;
-        case 11: launch_stencil_zl<MODE, 32, 8, 16>(s, p, args...); break;
-        case 12: launch_stencil_zl<MODE, 64, 4, 16>(s, p, args...); break;
-        case 13: launch_stencil_zl<MODE, 32, 8, 32>(s, p, args...); break;
         default: launch_stencil_shape<MODE, 32, 8, 8>(s, p, args...);
     }
 }

@@ -5,6 +5,7 @@ of activation on the slab.
 
     python3 -m paper_2101_02959_amd.optimality [--hh 4 8 12 16] [--steps 40]
                                               [--precision f64|mixed] [--out FILE]
+                                              [--scalings rho deluxe] [--primals V VE VEF]
 
 For every (H/h, scaling, primal space) it prints one JSON line with the
 columns of the paper's table: mean Newton iterations per time step (nit),
@@ -61,6 +62,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--precision", choices=["f64", "mixed"], default="f64")
     ap.add_argument("--out", default=None, help="also write the results as JSON")
+    ap.add_argument("--scalings", nargs="+", choices=SCALINGS, default=list(SCALINGS))
+    ap.add_argument("--primals", nargs="+", choices=PRIMALS, default=list(PRIMALS))
     args = ap.parse_args(argv)
     import paper_2101_02959_amd as P
     from workload import test3
@@ -68,8 +71,8 @@ def main(argv=None):
     rows = []
     for Hh in args.hh:
         wl = test3(Hh, args.steps)
-        for scaling in SCALINGS:
-            for primal in PRIMALS:
+        for scaling in args.scalings:
+            for primal in args.primals:
                 t0 = time.time()
                 rec = {"Hh": Hh, "scaling": scaling, "primal": primal, "precision": args.precision,
                        "dofs": 2 * wl.mesh.nnodes, "h_cm": wl.mesh.h}

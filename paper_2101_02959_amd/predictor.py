@@ -13,6 +13,10 @@ extrapolation that the guess corrects.
 Usage (trains on the 32^3 slab from 50 seeded stimulus sites, writes the
 default weights and evaluates on 5 held-out sites):
     python -m paper_2101_02959_amd.predictor
+On the 17M-dof slab from 12 sites x 40 steps + 20 steps (500 solver steps),
+trained on 33^3-node crops around the sites:
+    python -m paper_2101_02959_amd.predictor --from-workload slab256 --sites 12 \
+        --site-seed 3000 --extra-steps 20 --out WEIGHTS
 """
 from __future__ import annotations
 
@@ -149,6 +153,55 @@ def dataset(mesh, physics, opts, origins, steps, stim_steps=20, log=print):
     return torch.cat(samples), scales
 
 
+def crop_nodes(mesh, origin, block, size):
+    """Node ids (lexicographic, x fastest) of a size^3 cube of nodes centred
+    on the element block at ``origin``, shifted to lie inside the mesh."""
+    lo = []
+    for o, b, n in zip(origin, block, (mesh.nx, mesh.ny, mesh.nz)):
+        lo.append(min(max(o + b // 2 - size // 2, 0), n + 1 - size))
+    i = np.arange(lo[0], lo[0] + size)
+    j = np.arange(lo[1], lo[1] + size)
+    k = np.arange(lo[2], lo[2] + size)
+    return (i[None, None, :] + (mesh.nx + 1) * (j[None, :, None] + (mesh.ny + 1) * k[:, None, None])).ravel()
+
+
+def dataset_crops(mesh, physics, opts, runs, crop, stim_steps=20, log=print):
+    """Solver trajectories on a large mesh, one per (origin, steps) in runs,
+    each from rest with the stimulus on the 2 x 2 x 2-element block at
+    origin; every state is cut to the crop^3 nodes around the site, and the
+    crops are packed as samples of a crop^3-node grid (the sample that
+    straddles the stimulus switch-off is skipped).  One context serves all
+    runs.  Returns the samples (device) and the scales fitted on the first
+    run's crops."""
+    import torch
+    from workload import PAPER_STIM, initial_state, stimulus_nodal
+    S = B.Solver(mesh, physics, opts, precision=B.BDM_PREC_MIXED, guess=B.BDM_GUESS_EXTRAP)
+    samples, scales = [], None
+    try:
+        for q, (o, steps) in enumerate(runs):
+            v0, ue0, w0 = initial_state(mesh, physics, None)
+            S.bdm_set_state(v0, ue0, w0)
+            S.bdm_set_stimulus(stimulus_nodal(mesh, (2, 2, 2), PAPER_STIM, o), 0, stim_steps)
+            idx = torch.as_tensor(crop_nodes(mesh, o, (2, 2, 2), crop), device=S.device)
+            t0 = time.time()
+            v, ue, _, _ = S.bdm_get_state()
+            states = [torch.stack([v[idx], ue[idx]])]
+            nit = 0
+            for _ in range(steps):
+                st = S.bdm_step(1)
+                nit += st.newton_its
+                v, ue, _, _ = S.bdm_get_state()
+                states.append(torch.stack([v[idx], ue[idx]]))
+            states = torch.stack(states)
+            if scales is None:
+                scales = fit_scales(states)
+            samples.append(make_samples(states, skip=(stim_steps,)))
+            log(f"  run {q} site {o}: {steps} steps in {time.time() - t0:.1f} s, Newton {nit}")
+    finally:
+        S.close()
+    return torch.cat(samples), scales
+
+
 def evaluate(mesh, physics, opts, origins, steps, params, scales, stim_steps=20):
     """Held-out comparison of the extrapolated and the learned (judged) guess.
     Per step: Newton and PCG iterations, initial and final residual, the
@@ -209,15 +262,35 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--lr-final", type=float, default=1e-5)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--from-workload", default=None,
+                    help="record the trajectories on this workload's mesh (e.g. slab256) and train on "
+                         "crops of --crop^3 nodes around each site, on a crop-sized context")
+    ap.add_argument("--crop", type=int, default=33)
+    ap.add_argument("--extra-steps", type=int, default=0,
+                    help="with --from-workload: one more site (seed site-seed + 1) run this many steps")
     a = ap.parse_args(argv)
     torch.cuda.init()
     log = lambda *x: print(*x, flush=True)  # noqa: E731
-    ne = tuple(int(x) for x in a.elements.split(","))
-    pa = tuple(int(x) for x in a.parts.split(","))
-    mesh, ph, opts = small_mesh(ne, pa), Physics(), Opts()
-    sites = stimulus_sites(mesh, a.sites, a.site_seed)
-    log(f"dataset: {a.sites} sites x {a.steps_per_site} steps on {ne} elements")
-    samples, scales = dataset(mesh, ph, opts, sites, a.steps_per_site, log=log)
+    ph, opts = Physics(), Opts()
+    if a.from_workload:
+        from workload import workload as named
+        big = named(a.from_workload).mesh
+        sites = stimulus_sites(big, a.sites, a.site_seed)
+        runs = [(o, a.steps_per_site) for o in sites]
+        if a.extra_steps:
+            runs.append((stimulus_sites(big, 1, a.site_seed + 1)[0], a.extra_steps))
+        log(f"dataset: {len(runs)} runs, {sum(r[1] for r in runs)} solver steps on {a.from_workload}, "
+            f"crops of {a.crop}^3 nodes")
+        samples, scales = dataset_crops(big, ph, opts, runs, a.crop, log=log)
+        ne, pa = (a.crop - 1,) * 3, (2, 2, 2)
+        mesh = small_mesh(ne, pa)
+    else:
+        ne = tuple(int(x) for x in a.elements.split(","))
+        pa = tuple(int(x) for x in a.parts.split(","))
+        mesh = small_mesh(ne, pa)
+        sites = stimulus_sites(mesh, a.sites, a.site_seed)
+        log(f"dataset: {a.sites} sites x {a.steps_per_site} steps on {ne} elements")
+        samples, scales = dataset(mesh, ph, opts, sites, a.steps_per_site, log=log)
     log(f"  {samples.shape[0]} samples, scales {np.array2string(scales, precision=4)}")
     S = B.Solver(mesh, ph, opts)
     S.bdm_predictor_set(init_params(a.seed), scales)
@@ -235,9 +308,12 @@ def main(argv=None):
     del samples
     meta = {"elements": ne, "parts": pa, "sites": a.sites, "site_seed": a.site_seed,
             "steps_per_site": a.steps_per_site, "train_steps": a.train_steps, "lr": a.lr,
-            "lr_final": a.lr_final, "seed": a.seed}
+            "lr_final": a.lr_final, "seed": a.seed, "from_workload": a.from_workload, "crop": a.crop,
+            "extra_steps": a.extra_steps}
     save(a.out, params, sc, meta)
     log(f"wrote {a.out}")
+    if a.from_workload:
+        return
     held = stimulus_sites(mesh, a.heldout_sites, a.heldout_seed)
     rows, worst = evaluate(mesh, ph, opts, held, a.steps_per_site, params, sc)
     s = summarize(rows)

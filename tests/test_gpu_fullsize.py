@@ -167,5 +167,10 @@ def test_time_step_converges(big):
     for q in range(nit):
         assert 0 < st.krylov_its[q] < W.solver.krylov_maxit
         assert st.krylov_true_res[q] <= 10 * W.solver.krylov_rtol, (q, st.krylov_true_res[q])
+        # FP32 local factors keep the FP64 spectrum (Lanczos estimate 3.67 at
+        # this size): the local coarse blocks annihilate the u_e-constant
+        # primal vector exactly, so the rounding of the factors does not leak
+        # into the near-kernel of the 119k-dof coarse problem (5.74 without)
+        assert st.cond[q] < 4.0, (q, st.cond[q])
     v, ue, w, _ = S.bdm_get_state()
     assert torch.isfinite(v).all() and torch.isfinite(ue).all()
