@@ -58,8 +58,8 @@ def _syrk_variant(tune_entries):
     for e in tune_entries:
         if e["family"] == "syrk" and " interior " in e["class"]:
             v = e["choice"]
-            return v, (128 if v < 2 else 64), (16 if v & 1 else 32)
-    return 0, 128, 32
+            return v, (128 if v < 2 else 64), (16 if v >= 4 or v & 1 else 32), {4: ", true, true", 5: ", true"}.get(v, "")
+    return 0, 128, 32, ""
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFS = {"f32": 157.3, "f64": 78.6}
 
@@ -102,7 +102,9 @@ def run_path(P, wl, precision, guess, warmup, steps, predictor=None, krylov_grap
             f"guess {st.guess_used} r0 extrap {st.guess_res_extrap:.3e} learned {st.guess_res_cnn:.3e}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    free, total = torch.cuda.mem_get_info()
     out = {"s_per_step": wall / steps, "median_s_per_step": float(np.median(per)),
+           "device_mem_used_gb": round((total - free) / 1e9, 1),
            "newton_per_step": nit / steps, "pcg_per_newton": lit / max(nit, 1),
            "linear_solve_true_residual_max": max(true_res) if true_res else None}
     if predictor is not None:
@@ -117,7 +119,8 @@ def kernel_rooflines(P, S, prec_name, workload_name, reps=5):
     """Live HIP-event timings of the hot kernels at the current linearisation:
     mean duration of one launch and algorithmic work per launch."""
     tname = "float" if prec_name == "f32" else "double"
-    var, tm, kc = _syrk_variant(S.bdm_tune_report()["entries"])
+    var, tm, kc, db = _syrk_variant(S.bdm_tune_report()["entries"])
+    targs = f"{tname}, {tm}, {kc}{db}"
     peak = MFMA_PEAK_TFS[prec_name]
     out = {}
 
@@ -136,7 +139,7 @@ def kernel_rooflines(P, S, prec_name, workload_name, reps=5):
                     "algorithmic_bytes_per_launch": nbytes}
 
     mfma("syrk", P.BDM_KERNEL_SYRK_UPDATE,
-         f"k_syrk_batched<{tname}, {tm}, {kc}> (rank-k updates of the interior elimination, first setup chunk)")
+         f"k_syrk_batched<{targs}> (rank-k updates of the interior elimination, first setup chunk)")
     t = SYRK_TRAFFIC
     if (prec_name == t["precision"] and workload_name == t["workload"] and var == t["variant"]
             and _syrk_source_sha256() == t["kernel_source_sha256"]):

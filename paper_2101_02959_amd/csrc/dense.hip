@@ -121,21 +121,33 @@ __device__ void syrk_update(T* __restrict__ A, int64_t ld, int cb, int ce, int r
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b) acc[a][b] = (typename Mfma<T>::acc){0, 0, 0, 0};
-        for (int kk = k0; kk < k1; kk += 4) {
-            const int c = kk + lk;
-            const T* col = A + (int64_t)(c < k1 ? c : k0) * ld;
-            T av[2], bv[2];
+        // 32 inner indices at a time: every operand load of the chunk is
+        // issued (clamped addresses, masked values) before its MFMAs, so
+        // the chunk waits for global memory once rather than per step
+        for (int kb = k0; kb < k1; kb += 32) {
+            T av[8][2], bv[8][2];
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int ra = I0 + 16 * q + lr, rb = J0 + 16 * q + lr;
-                av[q] = (c < k1 && ra < re) ? col[ra] : (T)0;
-                bv[q] = (c < k1 && rb < ce) ? col[rb] : (T)0;
+            for (int u = 0; u < 8; ++u) {
+                const int c = kb + 4 * u + lk;
+                const bool cin = c < k1;
+                const T* col = A + (int64_t)(cin ? c : k0) * ld;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int ra = I0 + 16 * q + lr, rb = J0 + 16 * q + lr;
+                    const T x = col[min(ra, re - 1)], y = col[min(rb, ce - 1)];
+                    av[u][q] = (cin && ra < re) ? x : (T)0;
+                    bv[u][q] = (cin && rb < ce) ? y : (T)0;
+                }
             }
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int u = 0; u < 8; ++u) {
+                if (kb + 4 * u >= k1) break;
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
-                    if (!(ti == tj && a < b)) acc[a][b] = Mfma<T>::mac(av[a], bv[b], acc[a][b]);
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        if (!(ti == tj && a < b)) acc[a][b] = Mfma<T>::mac(av[u][a], bv[u][b], acc[a][b]);
+            }
         }
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -272,14 +284,22 @@ __device__ __forceinline__ void potrf_body(T* __restrict__ A, int64_t ld, int cb
             acc[0] = (typename Mfma<T>::acc){0, 0, 0, 0};
             acc[1] = acc[0];
             const int r = R0 + lr;
-            for (int kk = 0; kk < NB; kk += 4) {
-                const int k = kk + lk;
-                const T a = (r < c2 && k < jb) ? A[r + (int64_t)(j0 + k) * ld] : (T)0;
+            // the tile's 8 operand loads first (clamped addresses, masked values)
+            T av[NB / 4];
+#pragma unroll
+            for (int u = 0; u < NB / 4; ++u) {
+                const int k = 4 * u + lk;
+                const T x = A[min(r, c2 - 1) + (int64_t)(j0 + min(k, jb - 1)) * ld];
+                av[u] = (r < c2 && k < jb) ? x : (T)0;
+            }
+#pragma unroll
+            for (int u = 0; u < NB / 4; ++u) {
+                const int k = 4 * u + lk;
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int j = 16 * h + lr;
                     const T b = (k < jb && j < jb) ? W[j][k] : (T)0;
-                    acc[h] = Mfma<T>::mac(a, b, acc[h]);
+                    acc[h] = Mfma<T>::mac(av[u], b, acc[h]);
                 }
             }
 #pragma unroll
@@ -327,22 +347,51 @@ __global__ __launch_bounds__(kWG) void k_potrf(T* __restrict__ A, const int64_t*
 // The update of the columns right of the panel is left to k_syrk_batched.
 constexpr int PT_RB = 64, PT_XS = NBO + 4, PT_XCD = 8;
 
+static_assert(NB == PP_NB, "the packed factor blocks are the solve blocks");
+// Rows [r0, r1) (all below ne) of the panel columns [J, J + w), read by
+// get(row, column), into the panel-packed copy of the factor (the layout the
+// per-iteration solves stream, pp_block): entries right of the diagonal or
+// past column ne - 1 of a 32-column block are zero.  One workgroup.
+template <typename T, typename Get>
+__device__ inline void store_packed(T* __restrict__ P, int ne, int J, int w, int r0, int r1, Get get) {
+    const int b0 = J / NB, b1 = (J + w + NB - 1) / NB;
+    for (int b = b0; b < b1; ++b) {
+        T* Pb = P + pp_block(ne, b);
+        const int rb0 = max(r0, NB * b);
+        for (int idx = threadIdx.x; idx < (r1 - rb0) * NB; idx += kWG) {
+            const int r = rb0 + idx / NB, c = NB * b + idx % NB;
+            Pb[(int64_t)(r - NB * b) * NB + (c - NB * b)] = (c <= r && c < J + w) ? get(r, c) : (T)0;
+        }
+    }
+}
+
+// The diagonal block's factor also goes to the packed copy (P, poff) when
+// one is given: its columns are final once the panel is factored.
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_panel_diag(T* __restrict__ A, const int64_t* __restrict__ off,
                                                    const int* __restrict__ ld, const int* __restrict__ nIv, int J,
-                                                   T* __restrict__ Wbuf, int* __restrict__ info) {
+                                                   T* __restrict__ Wbuf, int* __restrict__ info,
+                                                   T* __restrict__ P, const int64_t* __restrict__ poff) {
     const int s = blockIdx.x;
     const int nI = nIv[s];
     if (J >= nI) return;
     const int w = min(NBO, nI - J);
-    potrf_body<T>(A + off[s], ld[s], J, J + w, J + w, info, Wbuf + (int64_t)s * NBO * NB);
+    T* As = A + off[s];
+    const int64_t lds = ld[s];
+    potrf_body<T>(As, lds, J, J + w, J + w, info, Wbuf + (int64_t)s * NBO * NB);
+    if (P) {
+        __syncthreads();   // the block's factor has been written by every thread
+        store_packed<T>(P + poff[s], nI, J, w, J, J + w,
+                        [&](int r, int c) { return As[r + (int64_t)c * lds]; });
+    }
 }
 
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_panel_trsm(T* __restrict__ Abase, const int64_t* __restrict__ off,
                                                    const int* __restrict__ ldv, const int* __restrict__ nIv,
                                                    const int* __restrict__ nv, int nsub, int rowblocks, int J,
-                                                   const T* __restrict__ Wbuf) {
+                                                   const T* __restrict__ Wbuf, T* __restrict__ Pk,
+                                                   const int64_t* __restrict__ poff) {
     __shared__ T Xs[PT_RB][PT_XS];
     __shared__ T Ls[NB][NB + 1];
     // all row blocks of one matrix run on one XCD (dispatch assigns
@@ -450,6 +499,10 @@ __global__ __launch_bounds__(kWG) void k_panel_trsm(T* __restrict__ Abase, const
         const int r = idx % PT_RB, c = idx / PT_RB;
         if (r < rows && c < w) A[(R0 + r) + (int64_t)(J + c) * ld] = Xs[r][c];
     }
+    // rows of the factor proper (below nI) also go to the packed copy
+    if (Pk && R0 < nI)
+        store_packed<T>(Pk + poff[s], nI, J, w, R0, min(R0 + rows, nI),
+                        [&](int r, int c) { return Xs[r - R0][c - J]; });
 }
 
 // Batched symmetric rank-k update C -= P P^T of a lower trapezoid of every
@@ -467,10 +520,13 @@ __global__ __launch_bounds__(kWG) void k_panel_trsm(T* __restrict__ Abase, const
 // robin to the 8 XCDs), which keeps P in that XCD's L2.
 constexpr int SY_XCD = 8;
 constexpr int SY_TRAIL = 0, SY_SCHUR = 1;
-// variants: 0 = (128, 32), 1 = (128, 16), 2 = (64, 32), 3 = (64, 16)
-constexpr int SY_NVAR = 4;
-__host__ __device__ constexpr int syrk_tm(int v) { return v < 2 ? 128 : 64; }
-__host__ __device__ constexpr int syrk_kc(int v) { return (v & 1) ? 16 : 32; }
+// variants (TM, KC): 0 = (128, 32), 1 = (128, 16), 2 = (64, 32), 3 = (64, 16),
+// one LDS buffer and two barriers per chunk; 4 and 5 = (64, 16) with two LDS
+// buffers and one barrier per chunk, 4 with the FP32 output tile read up
+// front.
+constexpr int SY_NVAR = 6;
+__host__ __device__ constexpr int syrk_tm(int v) { return (v < 2) ? 128 : 64; }
+__host__ __device__ constexpr int syrk_kc(int v) { return (v >= 4 || (v & 1)) ? 16 : 32; }
 
 __host__ __device__ inline int trapezoid_tiles(int cb, int ce, int re, int TM) {
     if (ce <= cb || re <= cb) return 0;
@@ -478,7 +534,7 @@ __host__ __device__ inline int trapezoid_tiles(int cb, int ce, int re, int TM) {
     return nct * nrt - nct * (nct - 1) / 2;
 }
 
-template <typename T, int TM, int KC>
+template <typename T, int TM, int KC, bool DB = false, bool CP = false>
 __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, const int64_t* __restrict__ off,
                                                       const int* __restrict__ ldv, const int* __restrict__ nIv,
                                                       const int* __restrict__ nv, int nsub, int tiles, int mode,
@@ -487,8 +543,9 @@ __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, con
     constexpr int KS = kWG / TM;               // inner indices staged per pass of the workgroup
     constexpr int EPT = TM * KC / kWG;         // staged elements per thread and operand
     constexpr int WT = TM / 2, NBK = WT / 16;  // wave tile and its MFMA blocks per side
-    __shared__ T As[KC][LS];    // P rows of the output tile's rows (i)
-    __shared__ T Bs[KC][LS];    // P rows of the output tile's columns (j)
+    constexpr int NBUF = DB ? 2 : 1;
+    __shared__ T As[NBUF][KC][LS];    // P rows of the output tile's rows (i)
+    __shared__ T Bs[NBUF][KC][LS];    // P rows of the output tile's columns (j)
     const int g = blockIdx.x;
     const int q = g / SY_XCD;
     const int s = (q / tiles) * SY_XCD + g % SY_XCD;
@@ -545,6 +602,10 @@ __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, con
         const int j = min(J0 + wc * WT + 16 * b + Mfma<T>::row(lane, v), ce - 1);
         return A[i + (int64_t)j * ld];
     };
+    // CP, FP32: the output tile is read at the start (its latency hidden
+    // behind the first chunks) instead of after the last one
+    constexpr bool cpre = CP && two_level;
+    T cv[cpre ? NBK : 1][cpre ? NBK : 1][4];
 #pragma unroll
     for (int b = 0; b < NBK; ++b)
 #pragma unroll
@@ -554,42 +615,70 @@ __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, con
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[b][a][v] = c_at(a, b, v);
             }
+            if constexpr (cpre) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) cv[b][a][v] = c_at(a, b, v);
+            }
         }
-    fetch(k0);
-    for (int kc = k0; kc < k1; kc += KC) {
-        __syncthreads();
+    auto stage = [&](int buf, int kc) {
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const bool kin = kc + lk0 + KS * e < k1;
-            As[lk0 + KS * e][lrow] = kin ? pa[e] : (T)0;
-            Bs[lk0 + KS * e][lrow] = kin ? sgn * pb[e] : (T)0;
+            As[buf][lk0 + KS * e][lrow] = kin ? pa[e] : (T)0;
+            Bs[buf][lk0 + KS * e][lrow] = kin ? sgn * pb[e] : (T)0;
         }
+    };
+    auto chunk = [&](int buf) {
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += 4) {
+            T fa[NBK], fb[NBK];
+#pragma unroll
+            for (int a = 0; a < NBK; ++a) fa[a] = As[buf][kk + lk][wr * WT + 16 * a + lr];
+#pragma unroll
+            for (int b = 0; b < NBK; ++b) fb[b] = Bs[buf][kk + lk][wc * WT + 16 * b + lr];
+            // output row index = j (A operand), column index = i (B operand), so
+            // that the 16 lanes of an accumulator row hold consecutive i
+#pragma unroll
+            for (int b = 0; b < NBK; ++b)
+#pragma unroll
+                for (int a = 0; a < NBK; ++a) acc[b][a] = Mfma<T>::mac(fb[b], fa[a], acc[b][a]);
+        }
+        if (two_level) {
+#pragma unroll
+            for (int b = 0; b < NBK; ++b)
+#pragma unroll
+                for (int a = 0; a < NBK; ++a) {
+                    tot[b][a] += acc[b][a];
+                    acc[b][a] = (typename Mfma<T>::acc){0, 0, 0, 0};
+                }
+        }
+    };
+    fetch(k0);
+    if constexpr (DB) {
+        // chunk c is staged in buffer c & 1.  Each pass computes from one
+        // buffer and stages the next chunk into the other; the single
+        // barrier both publishes that chunk and ends every wave's reads of
+        // the buffer the following pass overwrites.
+        stage(0, k0);
         __syncthreads();
-        if (kc + KC < k1) fetch(kc + KC);
-        if (active) {
-#pragma unroll
-            for (int kk = 0; kk < KC; kk += 4) {
-                T fa[NBK], fb[NBK];
-#pragma unroll
-                for (int a = 0; a < NBK; ++a) fa[a] = As[kk + lk][wr * WT + 16 * a + lr];
-#pragma unroll
-                for (int b = 0; b < NBK; ++b) fb[b] = Bs[kk + lk][wc * WT + 16 * b + lr];
-                // output row index = j (A operand), column index = i (B operand), so
-                // that the 16 lanes of an accumulator row hold consecutive i
-#pragma unroll
-                for (int b = 0; b < NBK; ++b)
-#pragma unroll
-                    for (int a = 0; a < NBK; ++a) acc[b][a] = Mfma<T>::mac(fb[b], fa[a], acc[b][a]);
+        if (k0 + KC < k1) fetch(k0 + KC);
+        int buf = 0;
+        for (int kc = k0; kc < k1; kc += KC) {
+            if (active) chunk(buf);
+            if (kc + KC < k1) {
+                stage(buf ^ 1, kc + KC);
+                __syncthreads();
+                if (kc + 2 * KC < k1) fetch(kc + 2 * KC);
             }
-            if (two_level) {
-#pragma unroll
-                for (int b = 0; b < NBK; ++b)
-#pragma unroll
-                    for (int a = 0; a < NBK; ++a) {
-                        tot[b][a] += acc[b][a];
-                        acc[b][a] = (typename Mfma<T>::acc){0, 0, 0, 0};
-                    }
-            }
+            buf ^= 1;
+        }
+    } else {
+        for (int kc = k0; kc < k1; kc += KC) {
+            __syncthreads();
+            stage(0, kc);
+            __syncthreads();
+            if (kc + KC < k1) fetch(kc + KC);
+            if (active) chunk(0);
         }
     }
     if (!active) return;
@@ -599,7 +688,12 @@ __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, con
 #pragma unroll
             for (int a = 0; a < NBK; ++a)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) tot[b][a][v] = c_at(a, b, v) - tot[b][a][v];
+                for (int v = 0; v < 4; ++v) {
+                    T c;
+                    if constexpr (cpre) c = cv[b][a][v];
+                    else c = c_at(a, b, v);
+                    tot[b][a][v] = c - tot[b][a][v];
+                }
     }
 #pragma unroll
     for (int b = 0; b < NBK; ++b)
@@ -697,51 +791,6 @@ __device__ __forceinline__ void load_pseg(const T* __restrict__ p, T (&v)[M]) {
 template <typename T>
 __device__ __forceinline__ void load_prow(const T* __restrict__ p, T (&v)[NB]) {
     load_pseg<T, NB>(p, v);
-}
-
-// Copy the lower triangles of the Dirichlet factor L_II and the Neumann
-// factor L_rr out of the chunk workspace into their panel-packed storage.
-// One workgroup per (matrix, column block of either factor); each 64-row
-// slab of the block goes through LDS: read down the columns (coalesced in
-// the workspace), written along the packed rows (contiguous).
-static_assert(NB == PP_NB, "the packed factor blocks are the solve blocks");
-template <typename T>
-__global__ __launch_bounds__(kWG) void k_copy_out(BatchDesc d, const T* __restrict__ K, T* __restrict__ LII,
-                                                 const int64_t* __restrict__ LIIoff, T* __restrict__ Lrr,
-                                                 const int64_t* __restrict__ Lrroff) {
-    __shared__ T tile[64][NB + 1];
-    const int s = d.sub0 + blockIdx.x;
-    const int64_t ld = d.n[s];
-    const int nI = d.nI[s], nr = d.nr[s];
-    const int nbI = (nI + NB - 1) / NB, nbr = (nr + NB - 1) / NB;
-    int b = blockIdx.y, n;
-    const T* A = K + d.K_off[s];
-    T* P;
-    if (b < nbI) {
-        n = nI;
-        P = LII + LIIoff[s];
-    } else if (b < nbI + nbr) {
-        b -= nbI;
-        n = nr;
-        A += (int64_t)nI * (ld + 1);
-        P = Lrr + Lrroff[s];
-    } else {
-        return;
-    }
-    const int tid = threadIdx.x, j0 = b * NB;
-    T* Pb = P + pp_block(n, b);
-    for (int r0 = j0; r0 < n; r0 += 64) {
-        for (int idx = tid; idx < 64 * NB; idx += kWG) {
-            const int rr = idx % 64, c = idx / 64, r = r0 + rr, col = j0 + c;
-            tile[rr][c] = (r < n && col < n && col <= r) ? A[r + (int64_t)col * ld] : (T)0;
-        }
-        __syncthreads();
-        for (int idx = tid; idx < 64 * NB; idx += kWG) {
-            const int rr = idx / NB, c = idx % NB, r = r0 + rr;
-            if (r < n) Pb[(int64_t)(r - j0) * NB + c] = tile[rr][c];
-        }
-        __syncthreads();
-    }
 }
 
 // Zero the lower triangle (diagonal included) of every local matrix of a
@@ -1543,13 +1592,13 @@ void launch_potrf(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld
 }
 template <typename T>
 void launch_interior_panel(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* nI,
-                           const int* n, int J, T* Wbuf, int rowblocks, int* info) {
+                           const int* n, int J, T* Wbuf, int rowblocks, int* info, T* P, const int64_t* poff) {
     if (nb <= 0) return;
-    hipLaunchKernelGGL(k_panel_diag<T>, dim3(nb), dim3(kWG), 0, s, A, off, ld, nI, J, Wbuf, info);
+    hipLaunchKernelGGL(k_panel_diag<T>, dim3(nb), dim3(kWG), 0, s, A, off, ld, nI, J, Wbuf, info, P, poff);
     if (rowblocks > 0) {
         const int groups = (nb + PT_XCD - 1) / PT_XCD;
         hipLaunchKernelGGL(k_panel_trsm<T>, dim3(groups * rowblocks * PT_XCD), dim3(kWG), 0, s, A, off, ld, nI, n, nb,
-                           rowblocks, J, Wbuf);
+                           rowblocks, J, Wbuf, P, poff);
     }
 }
 template <typename T>
@@ -1563,6 +1612,8 @@ void launch_syrk_update(hipStream_t s, int nb, T* A, const int64_t* off, const i
         case 1: hipLaunchKernelGGL((k_syrk_batched<T, 128, 16>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nb, tiles, mode, J); break;
         case 2: hipLaunchKernelGGL((k_syrk_batched<T, 64, 32>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nb, tiles, mode, J); break;
         case 3: hipLaunchKernelGGL((k_syrk_batched<T, 64, 16>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nb, tiles, mode, J); break;
+        case 4: hipLaunchKernelGGL((k_syrk_batched<T, 64, 16, true, true>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nb, tiles, mode, J); break;
+        case 5: hipLaunchKernelGGL((k_syrk_batched<T, 64, 16, true>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nb, tiles, mode, J); break;
         default: hipLaunchKernelGGL((k_syrk_batched<T, 128, 32>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nb, tiles, mode, J);
     }
 }
@@ -1589,13 +1640,6 @@ void launch_clear_lower(hipStream_t s, const BatchDesc& d, int maxn, T* K) {
     if (d.nsub <= 0 || maxn <= 0) return;
     hipLaunchKernelGGL(k_clear_lower<T>, dim3((unsigned)((maxn + CL_COLS - 1) / CL_COLS), (unsigned)d.nsub),
                        dim3(kWG), 0, s, d, K);
-}
-template <typename T>
-void launch_copy_out(hipStream_t s, const BatchDesc& d, int nb, int maxnI, int maxnr, const T* K, T* LII,
-                     const int64_t* LIIoff, T* Lrr, const int64_t* Lrroff) {
-    const int nblk = (maxnI + NB - 1) / NB + (maxnr + NB - 1) / NB;
-    if (nb <= 0 || nblk <= 0) return;
-    hipLaunchKernelGGL(k_copy_out<T>, dim3(nb, nblk), dim3(kWG), 0, s, d, K, LII, LIIoff, Lrr, Lrroff);
 }
 template <typename T>
 void launch_trsm_fwd(hipStream_t s, int nb, const T* L, const int64_t* Loff, const int* n, T* B,
@@ -1687,14 +1731,11 @@ int deluxe_max_object() { return DLX_MAXN; }
     template void launch_potrf<T>(hipStream_t, int, T*, const int64_t*, const int*, const int*,         \
                                   const int*, const int*, int*);                                         \
     template void launch_interior_panel<T>(hipStream_t, int, T*, const int64_t*, const int*, const int*, \
-                                           const int*, int, T*, int, int*);                              \
+                                           const int*, int, T*, int, int*, T*, const int64_t*);          \
     template void launch_syrk_update<T>(hipStream_t, int, T*, const int64_t*, const int*, const int*,    \
                                         const int*, bool, int, int, int);                                \
     template void launch_extract<T>(hipStream_t, const BatchDesc&, const T*, T*, T*, double*, T*);      \
     template void launch_clear_lower<T>(hipStream_t, const BatchDesc&, int, T*);                       \
-    template void launch_copy_out<T>(hipStream_t, const BatchDesc&, int, int, int, const T*, T*,          \
-                                     const int64_t*, T*,                                                 \
-                                     const int64_t*);                                                    \
     template void launch_trsm_fwd<T>(hipStream_t, int, const T*, const int64_t*, const int*, T*,         \
                                      const int64_t*, const int*, const int*);                            \
     template void launch_coarse_local<T>(hipStream_t, const BatchDesc&, const T*, const double*, T*, \

@@ -78,8 +78,11 @@ void launch_potrf(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld
 // same variant of the rank-k kernel (its output tile and inner chunk; the
 // variants are chosen by the autotuner, 0 is the default).
 template <typename T>
+// P, poff: when P is given, the rows below nI of the panel columns are also
+// written to the panel-packed copy of the factor at P + poff[matrix].
 void launch_interior_panel(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* nI,
-                           const int* n, int J, T* Wbuf, int rowblocks, int* info);
+                           const int* n, int J, T* Wbuf, int rowblocks, int* info, T* P = nullptr,
+                           const int64_t* poff = nullptr);
 template <typename T>
 void launch_syrk_update(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* nI, const int* n,
                         bool schur, int J, int tiles, int variant = 0);
@@ -108,11 +111,6 @@ __host__ __device__ inline int64_t pp_block(int n, int b) {   // first entry of 
 }
 __host__ __device__ inline int64_t pp_size(int n) { return pp_block(n, (n + PP_NB - 1) / PP_NB); }
 
-// Copy the factors L_II and L_rr out of the chunk workspace into their
-// panel-packed storage.
-template <typename T>
-void launch_copy_out(hipStream_t s, const BatchDesc& d, int nb, int maxnI, int maxnr, const T* K, T* LII,
-                     const int64_t* LIIoff, T* Lrr, const int64_t* Lrroff);
 // Multi-right-hand-side forward solve L X = B with panel-packed L.
 template <typename T>
 void launch_trsm_fwd(hipStream_t s, int nb, const T* L, const int64_t* Loff, const int* n,

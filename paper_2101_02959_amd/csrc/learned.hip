@@ -13,6 +13,7 @@
 // two-stage sums, so training is deterministic.
 #include <hip/hip_fp16.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "learned.hpp"
@@ -215,6 +216,110 @@ __global__ void k_adam(int n, float* __restrict__ w, float* __restrict__ m, floa
     else wh[i] = __float2half(wn);
 }
 
+// ------------------------------------------------- inference on MFMA
+// The inference path holds activations node-major (the CIN channels of a
+// node in consecutive halves) so that a convolution is an implicit GEMM on
+// the 16x16x16 FP16 MFMA: 16 nodes along x (M) x 16 output channels (N),
+// the inner dimension walked in blocks of 16 (K): one tap's 16 input
+// channels (CIN = 16) or four taps' 4 channels (CIN = 4).  Operand lanes:
+// A lane l holds A[l % 16][4 (l / 16) .. + 3], B lane l holds
+// B[4 (l / 16) .. + 3][l % 16], accumulator register v of lane l holds
+// C[4 (l / 16) + v][l % 16].  Taps outside the grid read zero (the network's
+// zero padding); the sums accumulate in FP32 as in the training kernels, in
+// a different order.
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef float cf4 __attribute__((ext_vector_type(4)));
+constexpr int CM_WAVES = 4;     // waves per workgroup
+constexpr int CM_G = 4;         // 16-node groups per wave and pass (independent MFMA chains)
+
+__global__ void k_cnn_input_nm(CnnGrid g, const double* __restrict__ vn, const double* __restrict__ uen,
+                               const double* __restrict__ vp, const double* __restrict__ uep, double sv, double se,
+                               double sdv, double sde, __half* __restrict__ X) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.N) return;
+    h4 x;
+    x[0] = (_Float16)(float)(vn[n] / sv);
+    x[1] = (_Float16)(float)(uen[n] / se);
+    x[2] = (_Float16)(float)((vn[n] - vp[n]) / sdv);
+    x[3] = (_Float16)(float)((uen[n] - uep[n]) / sde);
+    reinterpret_cast<h4*>(X)[n] = x;
+}
+
+// X node-major [N][CIN]; W as stored, [COUT][CIN][27]; GELU layers write H
+// node-major [N][16], the last layer writes Y channel-major [COUT][N].  The
+// node rows are cut into ngx groups of 16 nodes; the grid strides over the
+// groups, CM_G per wave and pass.
+template <int CIN, int COUT, bool GELU>
+__global__ __launch_bounds__(64 * CM_WAVES) void k_conv_mfma(CnnGrid g, int ngx, int64_t ngroups,
+                                                             const __half* __restrict__ X,
+                                                             const __half* __restrict__ W,
+                                                             const float* __restrict__ b, __half* __restrict__ H,
+                                                             float* __restrict__ Y) {
+    static_assert(CIN == 16 || CIN == 4, "input channels");
+    static_assert(COUT <= 16, "output channels");
+    constexpr int NK = CIN == 16 ? 27 : 7;   // K blocks of 16
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lr = lane & 15, lq = lane >> 4;
+    // the weights as B operands, one register pair per K block
+    h4 wb[NK];
+#pragma unroll
+    for (int q = 0; q < NK; ++q)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int t = CIN == 16 ? q : 4 * q + lq, ci = CIN == 16 ? 4 * lq + jj : jj;
+            wb[q][jj] = (lr < COUT && t < 27) ? (_Float16)__half2float(W[((int64_t)lr * CIN + ci) * 27 + t])
+                                              : (_Float16)0.0f;
+        }
+    const float bias = lr < COUT ? b[lr] : 0.0f;
+    const h4* Xv = reinterpret_cast<const h4*>(X);
+    const int64_t stride = (int64_t)gridDim.x * CM_WAVES * CM_G;
+    for (int64_t g0 = ((int64_t)blockIdx.x * CM_WAVES + wv) * CM_G; g0 < ngroups; g0 += stride) {
+        int gi[CM_G], gj[CM_G], gk[CM_G];
+        bool gon[CM_G];
+#pragma unroll
+        for (int u = 0; u < CM_G; ++u) {
+            const int64_t grp = min(g0 + u, ngroups - 1);
+            const int64_t row = grp / ngx;
+            gon[u] = g0 + u < ngroups;
+            gi[u] = 16 * (int)(grp - row * ngx);
+            gj[u] = (int)(row % g.ny1);
+            gk[u] = (int)(row / g.ny1);
+        }
+        cf4 acc[CM_G];
+#pragma unroll
+        for (int u = 0; u < CM_G; ++u) acc[u] = (cf4){0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 3
+        for (int q = 0; q < NK; ++q) {
+            const int t = CIN == 16 ? q : 4 * q + lq;
+            const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+            h4 a[CM_G];
+#pragma unroll
+            for (int u = 0; u < CM_G; ++u) {
+                const int i = gi[u] + lr + dx, j = gj[u] + dy, k = gk[u] + dz;
+                const bool ok = t < 27 && gi[u] + lr < g.nx1 && i >= 0 && i < g.nx1 && j >= 0 && j < g.ny1 &&
+                                k >= 0 && k < g.nz1;
+                const int64_t nn = ok ? i + (int64_t)g.nx1 * (j + (int64_t)g.ny1 * k) : 0;
+                const h4 x = Xv[nn * (CIN / 4) + (CIN == 16 ? lq : 0)];
+                a[u] = ok ? x : (h4){(_Float16)0.0f, (_Float16)0.0f, (_Float16)0.0f, (_Float16)0.0f};
+            }
+#pragma unroll
+            for (int u = 0; u < CM_G; ++u) acc[u] = __builtin_amdgcn_mfma_f32_16x16x16f16(a[u], wb[q], acc[u], 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < CM_G; ++u) {
+            if (!gon[u] || lr >= COUT) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int io = gi[u] + 4 * lq + v;
+                if (io >= g.nx1) continue;
+                const int64_t n = io + (int64_t)g.nx1 * (gj[u] + (int64_t)g.ny1 * gk[u]);
+                const float z = acc[u][v] + bias;
+                if constexpr (GELU) H[n * 16 + lr] = __float2half(gelu_f(z));
+                else Y[(int64_t)lr * g.N + n] = z;
+            }
+        }
+    }
+}
+
 // guess = u^n + (u^n - u^{n-1}) + scale * y
 __global__ void k_cnn_guess(CnnGrid g, const double* __restrict__ vn, const double* __restrict__ uen,
                             const double* __restrict__ vp, const double* __restrict__ uep, const float* __restrict__ Y,
@@ -330,9 +435,30 @@ void Predictor::forward(hipStream_t s, const double* vn, const double* uen, cons
                        nullptr, Y);
 }
 
+// Inference on MFMA, node-major activations in the training buffers X0,
+// H[0] and H[1] (training rewrites them on its next forward pass).
+void Predictor::forward_mfma(hipStream_t s, const double* vn, const double* uen, const double* vp,
+                             const double* uep) {
+    const int64_t N = g.N;
+    hipLaunchKernelGGL(k_cnn_input_nm, dim3(nb(N, 256)), dim3(256), 0, s, g, vn, uen, vp, uep, scale[0], scale[1],
+                       scale[2], scale[3], X0);
+    const int ngx = (g.nx1 + 15) / 16;
+    const int64_t ngroups = (int64_t)ngx * g.ny1 * g.nz1;
+    const int64_t per_wg = (int64_t)CM_WAVES * CM_G;
+    const dim3 grid((unsigned)std::min<int64_t>((ngroups + per_wg - 1) / per_wg, 4096)), blk(64 * CM_WAVES);
+    hipLaunchKernelGGL((k_conv_mfma<4, 16, true>), grid, blk, 0, s, g, ngx, ngroups, X0, wh + woff[0],
+                       bias + boff_[0], H[0], nullptr);
+    hipLaunchKernelGGL((k_conv_mfma<16, 16, true>), grid, blk, 0, s, g, ngx, ngroups, H[0], wh + woff[1],
+                       bias + boff_[1], H[1], nullptr);
+    hipLaunchKernelGGL((k_conv_mfma<16, 16, true>), grid, blk, 0, s, g, ngx, ngroups, H[1], wh + woff[2],
+                       bias + boff_[2], H[0], nullptr);
+    hipLaunchKernelGGL((k_conv_mfma<16, 2, false>), grid, blk, 0, s, g, ngx, ngroups, H[0], wh + woff[3],
+                       bias + boff_[3], nullptr, Y);
+}
+
 void Predictor::guess(hipStream_t s, const double* vn, const double* uen, const double* vp, const double* uep,
                       double* out) {
-    forward(s, vn, uen, vp, uep);
+    forward_mfma(s, vn, uen, vp, uep);
     hipLaunchKernelGGL(k_cnn_guess, dim3(nb(g.N, 256)), dim3(256), 0, s, g, vn, uen, vp, uep, Y, scale[4], scale[5],
                        out);
 }

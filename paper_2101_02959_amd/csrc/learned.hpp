@@ -36,7 +36,10 @@ struct Predictor {
     std::string init(int64_t N, int nx1, int ny1, int nz1, void* (*alloc)(void*, size_t), void* ctx);
     void set(hipStream_t s, const float* host_params, const double sc[kScales]);
     void get(hipStream_t s, float* host_params, double sc[kScales]);
+    // training forward pass (channel-major activations, kept for the backward pass)
     void forward(hipStream_t s, const double* vn, const double* uen, const double* vp, const double* uep);
+    // inference forward pass on MFMA (node-major activations)
+    void forward_mfma(hipStream_t s, const double* vn, const double* uen, const double* vp, const double* uep);
     void guess(hipStream_t s, const double* vn, const double* uen, const double* vp, const double* uep, double* out);
     double loss_grad(hipStream_t s, const double* s6);
     double train_step(hipStream_t s, const double* s6, double lr);

@@ -521,6 +521,10 @@ int Context::alloc_local() {
     }
     LIIs_ = dalloc(nLII_ * sizeof(T));
     Lrrs_ = dalloc(nLrr_ * sizeof(T));
+    plan_int_.packed = LIIs_;
+    plan_int_.poff = LII_off_;
+    plan_rr_.packed = Lrrs_;
+    plan_rr_.poff = Lrr_off_;
     slots_ = dalloc(nslot_ * sizeof(T));
     F_ = dalloc(nF_ * sizeof(T));
     Z_ = dalloc(nZ_ * sizeof(T));
@@ -771,7 +775,7 @@ int Context::eliminate(T* K, int s0, int cnt, const ElimPlan& pl, double* tm) {
         const int J = q * w;
         mark(0);
         launch_interior_panel<T>(stream_, cnt, K, pl.off + s0, ld_ + s0, pl.ne + s0, pl.n + s0, J, (T*)Wbuf_,
-                                 pl.rows[q], info_sub_ + s0);
+                                 pl.rows[q], info_sub_ + s0, (T*)pl.packed, pl.poff ? pl.poff + s0 : nullptr);
         mark(1);
         launch_syrk_update<T>(stream_, cnt, K, pl.off + s0, ld_ + s0, pl.ne + s0, pl.n + s0, false, J, pl.trail[q],
                               pl.variant);
@@ -824,9 +828,10 @@ int Context::linearize_t() {
         // interior elimination: L_II, L_GI and S_Gamma in the trailing block (Sec. 4.1)
         eliminate<T>(K, s0, cnt, plan_int_, nullptr);
         launch_extract<T>(stream_, cd, K, (T*)slots_, (T*)F_, Svv_, (T*)Srr_);
-        // constrained Neumann factor L_rr of S_rr (the leading r-block of S_Gamma)
+        // constrained Neumann factor L_rr of S_rr (the leading r-block of S_Gamma);
+        // the panel kernels of both eliminations also write the factors into
+        // their panel-packed storage
         eliminate<T>(K, s0, cnt, plan_rr_, nullptr);
-        launch_copy_out<T>(stream_, cd, cnt, maxnI_, maxnr_, K, (T*)LIIs_, LII_off_, (T*)Lrrs_, Lrr_off_);
     }
     // The deluxe factors need only the extracted blocks: they run on the side
     // stream while the coarse chain (whose upper tree levels leave most of

@@ -52,6 +52,8 @@ class Context {
         std::vector<int> trail, rows;
         int schur = 0;
         int variant = 0;        // rank-k kernel variant (autotuned)
+        void* packed = nullptr;             // panel-packed copy of the factor (element type T)
+        const int64_t* poff = nullptr;      // its per-subdomain offsets
     };
     ElimPlan plan_int_, plan_rr_;
     void build_plan(ElimPlan& pl, bool interior, int variant);

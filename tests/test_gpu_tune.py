@@ -27,7 +27,7 @@ MESHES = {
     "ragged": Mesh(11, 9, 10, 0.01, (0, 3, 7, 11), (0, 5, 9), (0, 4, 10)),
     "uneven442": Mesh(20, 18, 12, 0.01, (0, 4, 9, 13, 20), (0, 5, 9, 14, 18), (0, 5, 12)),
 }
-NSTENCIL, NSYRK = 11, 4
+NSTENCIL, NSYRK = 11, 6
 
 
 def _gauge(x, N):
