@@ -391,7 +391,7 @@ __global__ __launch_bounds__(kWG) void k_panel_trsm(T* __restrict__ Abase, const
                                                    const int* __restrict__ ldv, const int* __restrict__ nIv,
                                                    const int* __restrict__ nv, int nsub, int rowblocks, int J,
                                                    const T* __restrict__ Wbuf, T* __restrict__ Pk,
-                                                   const int64_t* __restrict__ poff) {
+                                                   const int64_t* __restrict__ poff, const int* __restrict__ nIcv) {
     __shared__ T Xs[PT_RB][PT_XS];
     __shared__ T Ls[NB][NB + 1];
     // all row blocks of one matrix run on one XCD (dispatch assigns
@@ -406,6 +406,8 @@ __global__ __launch_bounds__(kWG) void k_panel_trsm(T* __restrict__ Abase, const
     const int w = min(NBO, nI - J);
     const int R0 = J + w + rb * PT_RB;
     if (R0 >= n) return;
+    // rows in [nI, n) of a panel inside the core: zero before, zero after
+    if (nIcv && R0 >= nI && J + w <= nIcv[s]) return;
     const int rows = min(PT_RB, n - R0);
     T* A = Abase + off[s];
     const int64_t ld = ldv[s];
@@ -537,8 +539,8 @@ __host__ __device__ inline int trapezoid_tiles(int cb, int ce, int re, int TM) {
 template <typename T, int TM, int KC, bool DB = false, bool CP = false>
 __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, const int64_t* __restrict__ off,
                                                       const int* __restrict__ ldv, const int* __restrict__ nIv,
-                                                      const int* __restrict__ nv, int nsub, int tiles, int mode,
-                                                      int J) {
+                                                      const int* __restrict__ nv, const int* __restrict__ nIcv,
+                                                      int nsub, int tiles, int mode, int J) {
     constexpr int LS = TM + 16;                // padded LDS row
     constexpr int KS = kWG / TM;               // inner indices staged per pass of the workgroup
     constexpr int EPT = TM * KC / kWG;         // staged elements per thread and operand
@@ -566,6 +568,13 @@ __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, con
     while (tile >= nrt - tj) { tile -= nrt - tj; ++tj; }
     const int ti = tj + tile;
     const int I0 = cb + ti * TM, J0 = cb + tj * TM;
+    // rows of the tile all in [nI, n): their operand is zero left of the
+    // core boundary nIc (the interface does not couple with the core), so
+    // the inner indices start there, and a tile with none left keeps C
+    if (nIcv && I0 >= nI) {
+        k0 = max(k0, nIcv[s]);
+        if (k0 >= k1) return;
+    }
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
     const int wr = wv & 1, wc = wv >> 1;                 // wave's quadrant (rows i, cols j)
     const bool active = !(ti == tj && wr < wc);          // strictly upper quadrant of a diagonal tile
@@ -1592,29 +1601,30 @@ void launch_potrf(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld
 }
 template <typename T>
 void launch_interior_panel(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* nI,
-                           const int* n, int J, T* Wbuf, int rowblocks, int* info, T* P, const int64_t* poff) {
+                           const int* n, int J, T* Wbuf, int rowblocks, int* info, T* P, const int64_t* poff,
+                           const int* nIc) {
     if (nb <= 0) return;
     hipLaunchKernelGGL(k_panel_diag<T>, dim3(nb), dim3(kWG), 0, s, A, off, ld, nI, J, Wbuf, info, P, poff);
     if (rowblocks > 0) {
         const int groups = (nb + PT_XCD - 1) / PT_XCD;
         hipLaunchKernelGGL(k_panel_trsm<T>, dim3(groups * rowblocks * PT_XCD), dim3(kWG), 0, s, A, off, ld, nI, n, nb,
-                           rowblocks, J, Wbuf, P, poff);
+                           rowblocks, J, Wbuf, P, poff, nIc);
     }
 }
 template <typename T>
 void launch_syrk_update(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* nI, const int* n,
-                        bool schur, int J, int tiles, int variant) {
+                        bool schur, int J, int tiles, int variant, const int* nIc) {
     if (nb <= 0 || tiles <= 0) return;
     const int groups = (nb + SY_XCD - 1) / SY_XCD;
     const dim3 grid(groups * tiles * SY_XCD);
     const int mode = schur ? SY_SCHUR : SY_TRAIL;
     switch (variant) {
-        case 1: hipLaunchKernelGGL((k_syrk_batched<T, 128, 16>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nb, tiles, mode, J); break;
-        case 2: hipLaunchKernelGGL((k_syrk_batched<T, 64, 32>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nb, tiles, mode, J); break;
-        case 3: hipLaunchKernelGGL((k_syrk_batched<T, 64, 16>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nb, tiles, mode, J); break;
-        case 4: hipLaunchKernelGGL((k_syrk_batched<T, 64, 16, true, true>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nb, tiles, mode, J); break;
-        case 5: hipLaunchKernelGGL((k_syrk_batched<T, 64, 16, true>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nb, tiles, mode, J); break;
-        default: hipLaunchKernelGGL((k_syrk_batched<T, 128, 32>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nb, tiles, mode, J);
+        case 1: hipLaunchKernelGGL((k_syrk_batched<T, 128, 16>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nIc, nb, tiles, mode, J); break;
+        case 2: hipLaunchKernelGGL((k_syrk_batched<T, 64, 32>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nIc, nb, tiles, mode, J); break;
+        case 3: hipLaunchKernelGGL((k_syrk_batched<T, 64, 16>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nIc, nb, tiles, mode, J); break;
+        case 4: hipLaunchKernelGGL((k_syrk_batched<T, 64, 16, true, true>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nIc, nb, tiles, mode, J); break;
+        case 5: hipLaunchKernelGGL((k_syrk_batched<T, 64, 16, true>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nIc, nb, tiles, mode, J); break;
+        default: hipLaunchKernelGGL((k_syrk_batched<T, 128, 32>), grid, dim3(kWG), 0, s, A, off, ld, nI, n, nIc, nb, tiles, mode, J);
     }
 }
 int syrk_variants() { return SY_NVAR; }
@@ -1731,9 +1741,10 @@ int deluxe_max_object() { return DLX_MAXN; }
     template void launch_potrf<T>(hipStream_t, int, T*, const int64_t*, const int*, const int*,         \
                                   const int*, const int*, int*);                                         \
     template void launch_interior_panel<T>(hipStream_t, int, T*, const int64_t*, const int*, const int*, \
-                                           const int*, int, T*, int, int*, T*, const int64_t*);          \
+                                           const int*, int, T*, int, int*, T*, const int64_t*,           \
+                                           const int*);                                                   \
     template void launch_syrk_update<T>(hipStream_t, int, T*, const int64_t*, const int*, const int*,    \
-                                        const int*, bool, int, int, int);                                \
+                                        const int*, bool, int, int, int, const int*);                    \
     template void launch_extract<T>(hipStream_t, const BatchDesc&, const T*, T*, T*, double*, T*);      \
     template void launch_clear_lower<T>(hipStream_t, const BatchDesc&, int, T*);                       \
     template void launch_trsm_fwd<T>(hipStream_t, int, const T*, const int64_t*, const int*, T*,         \

@@ -80,12 +80,17 @@ void launch_potrf(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld
 template <typename T>
 // P, poff: when P is given, the rows below nI of the panel columns are also
 // written to the panel-packed copy of the factor at P + poff[matrix].
+// nIc (optional): per matrix, the leading columns [0, nIc[m]) whose rows
+// [nI, n) are zero in the assembled matrix; they stay zero in the factor,
+// so row blocks wholly in [nI, n) skip panels inside [0, nIc).
 void launch_interior_panel(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* nI,
                            const int* n, int J, T* Wbuf, int rowblocks, int* info, T* P = nullptr,
-                           const int64_t* poff = nullptr);
+                           const int64_t* poff = nullptr, const int* nIc = nullptr);
+// nIc as above: tiles whose rows lie in [nI, n) take only the inner
+// indices k >= nIc[m], where their operand is not zero.
 template <typename T>
 void launch_syrk_update(hipStream_t s, int nb, T* A, const int64_t* off, const int* ld, const int* nI, const int* n,
-                        bool schur, int J, int tiles, int variant = 0);
+                        bool schur, int J, int tiles, int variant = 0, const int* nIc = nullptr);
 int interior_panel_width();
 int panel_wbuf_stride();
 int panel_rowblocks(int J, int nI, int n);

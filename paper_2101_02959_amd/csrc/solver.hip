@@ -187,7 +187,7 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
     std::vector<int64_t> lmap_off(nsub), K_off(nsub), F_off(nsub), Z_off(nsub), P_off(nsub);
     std::vector<int64_t> xI_off(nsub), xr_off(nsub), LII(nsub), Lrr(nsub), Srr_off(nsub);
     std::vector<int> lmap, primal, Ilist;
-    std::vector<int> st1c0(nsub, 0), st1c1(nsub), st1c2(nsub), st2c1(nsub);
+    std::vector<int> st1c0(nsub, 0), st1c1(nsub), st1c2(nsub), st2c1(nsub), nIcv(nsub);
     int64_t accK = 0, accF = 0, accZ = 0, accP = 0, accI = 0, accR = 0, accS = 0, accLII = 0, accLrr = 0;
     for (int q = 0; q < nsub; ++q) {
         const SubInfo& sb = topo.subs[q];
@@ -196,6 +196,7 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
             return BDM_E_ARG;
         }
         n[q] = sb.n(); nI[q] = sb.nI; nr[q] = sb.nr; nV[q] = sb.nV; nc[q] = sb.nc; nP[q] = sb.nP;
+        nIcv[q] = sb.nIc;
         kF[q] = sb.nc + sb.nV;
         box[6 * q + 0] = sb.ex0; box[6 * q + 1] = sb.ey0; box[6 * q + 2] = sb.ez0;
         box[6 * q + 3] = sb.Lx(); box[6 * q + 4] = sb.Ly(); box[6 * q + 5] = sb.Lz();
@@ -265,6 +266,7 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
         std::vector<int64_t> kr(nsub);
         for (int q = 0; q < nsub; ++q) kr[q] = kc[q] + (int64_t)nI[q] + (int64_t)nI[q] * n[q];
         plan_int_.off = Kc_off_;
+        plan_int_.nIc = upload(nIcv);
         plan_rr_.off = upload(kr);
         build_plan(plan_int_, true, 0);
         build_plan(plan_rr_, false, 0);
@@ -710,10 +712,10 @@ int Context::tune_syrk() {
             return time_launches(stream_, 3, [&] {
                 if (tp.trail[0] > 0)
                     launch_syrk_update<T>(stream_, cnt, K, tp.off + s0, ld_ + s0, tp.ne + s0, tp.n + s0, false, 0,
-                                          tp.trail[0], var);
+                                          tp.trail[0], var, tp.nIc ? tp.nIc + s0 : nullptr);
                 if (tp.schur > 0)
                     launch_syrk_update<T>(stream_, cnt, K, tp.off + s0, ld_ + s0, tp.ne + s0, tp.n + s0, true, 0,
-                                          tp.schur, var);
+                                          tp.schur, var, tp.nIc ? tp.nIc + s0 : nullptr);
             });
         });
         const int64_t* off = pl.off;
@@ -775,10 +777,11 @@ int Context::eliminate(T* K, int s0, int cnt, const ElimPlan& pl, double* tm) {
         const int J = q * w;
         mark(0);
         launch_interior_panel<T>(stream_, cnt, K, pl.off + s0, ld_ + s0, pl.ne + s0, pl.n + s0, J, (T*)Wbuf_,
-                                 pl.rows[q], info_sub_ + s0, (T*)pl.packed, pl.poff ? pl.poff + s0 : nullptr);
+                                 pl.rows[q], info_sub_ + s0, (T*)pl.packed, pl.poff ? pl.poff + s0 : nullptr,
+                                 pl.nIc ? pl.nIc + s0 : nullptr);
         mark(1);
         launch_syrk_update<T>(stream_, cnt, K, pl.off + s0, ld_ + s0, pl.ne + s0, pl.n + s0, false, J, pl.trail[q],
-                              pl.variant);
+                              pl.variant, pl.nIc ? pl.nIc + s0 : nullptr);
         mark(2);
         if (tm) {
             lap(0, 1, tm[0]);
@@ -790,7 +793,7 @@ int Context::eliminate(T* K, int s0, int cnt, const ElimPlan& pl, double* tm) {
     if (pl.schur > 0) {
         mark(0);
         launch_syrk_update<T>(stream_, cnt, K, pl.off + s0, ld_ + s0, pl.ne + s0, pl.n + s0, true, 0, pl.schur,
-                              pl.variant);
+                              pl.variant, pl.nIc ? pl.nIc + s0 : nullptr);
         mark(1);
         if (tm) {
             lap(0, 1, tm[1]);
@@ -1221,21 +1224,29 @@ int Context::profile_t(int kernel, int reps, double* avg_ms, double* work) {
     } else {
         // interior elimination flops: the panel kernel (divisions and the
         // updates inside each panel) and the update kernel (trailing updates
-        // right of each panel and the Schur update), 2 flops per updated entry
+        // right of each panel and the Schur update), 2 flops per updated
+        // entry.  Entries of the interface rows [nI, n) in the core columns
+        // [0, nIc) are zero and stay zero, so neither they nor the products
+        // they enter count.
         const int wp = interior_panel_width();
         auto tri = [](double c0, double c1, double n) {     // sum over columns [c0, c1) of (n - c)
             const double m = c1 - c0;
             return m > 0 ? m * n - (c0 + c1 - 1) * m / 2.0 : 0.0;
         };
         for (int q = s0; q < s0 + cnt; ++q) {
-            const double n = topo.subs[q].n(), nI = topo.subs[q].nI;
+            const double n = topo.subs[q].n(), nI = topo.subs[q].nI, nIc = topo.subs[q].nIc, nG = n - nI;
             double wpanel = 0, wupd = 0;
             for (int J = 0; J < nI; J += wp) {
                 const double pe = std::min<double>(J + wp, nI);
-                for (int j = J; j < pe; ++j) wpanel += (n - j - 1) + 2.0 * tri(j + 1, pe, n);
-                wupd += 2.0 * (pe - J) * tri(J + wp, nI, n);
+                for (int j = J; j < pe; ++j) {
+                    const double g = j >= nIc ? nG : 0.0;      // interface rows of column j
+                    wpanel += (nI - j - 1) + g + 2.0 * (tri(j + 1, pe, nI) + g * (pe - j - 1));
+                }
+                const double kg = std::max(0.0, pe - std::max<double>(J, nIc));   // inner indices for them
+                const double cols = std::max(0.0, nI - (J + wp));
+                wupd += 2.0 * ((pe - J) * tri(J + wp, nI, nI) + kg * cols * nG);
             }
-            wupd += nI * (n - nI) * (n - nI + 1.0);
+            wupd += (nI - nIc) * nG * (nG + 1.0);
             w += (kernel == BDM_KERNEL_POTRF_INTERIOR) ? wpanel : wupd;
         }
     }

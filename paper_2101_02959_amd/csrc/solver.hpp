@@ -49,6 +49,7 @@ class Context {
         const int64_t* off = nullptr;
         const int* ne = nullptr;
         const int* n = nullptr;
+        const int* nIc = nullptr;           // core columns (interior plan), see launch_syrk_update
         std::vector<int> trail, rows;
         int schur = 0;
         int variant = 0;        // rank-k kernel variant (autotuned)

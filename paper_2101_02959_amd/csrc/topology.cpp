@@ -160,12 +160,27 @@ std::string Topology::build(int nx_, int ny_, int nz_, double h_, int px_, int p
     const std::vector<char> mx = cut_mask(cx, nx), my = cut_mask(cy, ny), mz = cut_mask(cz, nz);
     for (int sidx = 0; sidx < nsub; ++sidx) {
         SubInfo& s = subs[sidx];
+        // An interior node couples (through the elements around it) with its 26
+        // neighbours only, all inside the box; a core node has none of them on
+        // a cut plane, so its rows of K_IG are zero.
         s.I_nodes.clear();
+        std::vector<int> shell;
         for (int k = s.ez0; k <= s.ez1; ++k)
             for (int j = s.ey0; j <= s.ey1; ++j)
-                for (int i = s.ex0; i <= s.ex1; ++i)
-                    if (!mx[i] && !my[j] && !mz[k])
-                        s.I_nodes.push_back((int)node(i, j, k));
+                for (int i = s.ex0; i <= s.ex1; ++i) {
+                    if (mx[i] || my[j] || mz[k]) continue;
+                    bool core = true;
+                    for (int dz = -1; dz <= 1 && core; ++dz)
+                        for (int dy = -1; dy <= 1 && core; ++dy)
+                            for (int dx = -1; dx <= 1 && core; ++dx) {
+                                const int ii = i + dx, jj = j + dy, kk = k + dz;
+                                if (ii < 0 || ii > nx || jj < 0 || jj > ny || kk < 0 || kk > nz) continue;
+                                if (mx[ii] || my[jj] || mz[kk]) core = false;
+                            }
+                    (core ? s.I_nodes : shell).push_back((int)node(i, j, k));
+                }
+        s.nIc = 2 * (int)s.I_nodes.size();
+        s.I_nodes.insert(s.I_nodes.end(), shell.begin(), shell.end());
         s.r_nodes.clear();
         s.face_off.clear();
         s.edge_off.clear();

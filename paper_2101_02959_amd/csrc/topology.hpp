@@ -17,7 +17,10 @@ struct Object {
 struct SubInfo {
     int a, b, c;                // position in the subdomain grid
     int ex0, ex1, ey0, ey1, ez0, ez1;   // element box [e0, e1)
-    std::vector<int> I_nodes;   // interior nodes (|N_x| = 1), ascending
+    // interior nodes (|N_x| = 1): first the core (interior nodes none of whose
+    // 26 neighbours lies on the interface), then the rest; each part
+    // ascending
+    std::vector<int> I_nodes;
     std::vector<int> r_nodes;   // face nodes then edge nodes, object by object
     std::vector<int> V_nodes;   // vertex nodes
     std::vector<int> faces, edges, verts;     // object ids, ascending
@@ -27,6 +30,7 @@ struct SubInfo {
     // not constrain it; edges come before faces
     std::vector<int> face_con, edge_con;
     int nI = 0, nr = 0, nV = 0, nG = 0, nc = 0, nP = 0;   // dof counts
+    int nIc = 0;                // core dofs: the first nIc of the nI interior dofs
     std::vector<int> primal;    // local primal -> global primal
     // box-local node (i + (Lx+1)(j + (Ly+1)k)) -> local node index in [I|r|V]
     std::vector<int> lmap;

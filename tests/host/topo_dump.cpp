@@ -38,7 +38,7 @@ int main(int argc, char** argv) {
         }
     for (size_t s = 0; s < t.subs.size(); ++s) {
         const auto& b = t.subs[s];
-        printf("SUB %zu %d %d %d %d %d |", s, b.nI, b.nr, b.nV, b.nc, b.nP);
+        printf("SUB %zu %d %d %d %d %d %d |", s, b.nI, b.nr, b.nV, b.nc, b.nP, b.nIc);
         for (int n : b.I_nodes) printf(" %d", n);
         printf(" |");
         for (int n : b.r_nodes) printf(" %d", n);

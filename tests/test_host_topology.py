@@ -9,8 +9,10 @@ import subprocess
 import pytest
 
 from conftest import ROOT
-from oracle import dd
-from workload import Mesh
+import numpy as np
+
+from oracle import bidomain, dd
+from workload import Mesh, Physics
 
 EXE = os.path.join(ROOT, "_build", "topo_dump")
 
@@ -59,9 +61,10 @@ MESHES = [
 @pytest.mark.parametrize("mesh", MESHES, ids=["cube8", "ragged", "uneven3x3x2"])
 def test_partition_matches_oracle(topo_exe, mesh, primal):
     """Same faces / edges / vertices (sharing subdomains and nodes, in the same
-    order), same interior and interface node lists per subdomain, same primal
-    numbering as the oracle's N_x classification (Sec. 4.1), for each primal
-    space (Sec. 4.4)."""
+    order), same interior node sets and interface node lists per subdomain,
+    same primal numbering as the oracle's N_x classification (Sec. 4.1), for
+    each primal space (Sec. 4.4).  The library orders the interior nodes for
+    its elimination (core first, see the next test); the oracle ascending."""
     objs, subs = _dump(topo_exe, mesh, primal)
     dec = dd.Decomposition(mesh, primal)
     ref = ([("F", o.subs, tuple(o.nodes)) for o in dec.faces]
@@ -73,9 +76,30 @@ def test_partition_matches_oracle(topo_exe, mesh, primal):
         info = dec.sub[s]
         assert h[0] == s
         assert h[1:6] == [info.nI, info.nr, info.nV, 2 * len(info.cons), info.nV + 2 * len(info.cons)]
-        assert I == list(info.I_nodes)
+        assert sorted(I) == list(info.I_nodes)
         assert r == list(info.r_nodes)
         assert prim == list(info.primal)
+
+
+@pytest.mark.parametrize("mesh", MESHES, ids=["cube8", "ragged", "uneven3x3x2"])
+def test_interior_order_puts_the_core_first(topo_exe, mesh):
+    """The interior elimination order: first the core, the interior nodes
+    whose rows of K_IGamma (Sec. 4.1) are zero, then the other interior
+    nodes, each part ascending; nIc counts the core dofs.  The core is taken
+    here from the oracle's assembled local matrix, not from the mesh
+    geometry the library uses."""
+    _, subs = _dump(topo_exe, mesh)
+    dec = dd.Decomposition(mesh, "VE")
+    prob = bidomain.Problem(mesh, Physics(), 0.05)
+    zero = np.zeros(prob.N)
+    for s, (h, I, _, _) in enumerate(subs):
+        info = dec.sub[s]
+        KIG = dd.LocalOps(prob, dec, s, zero, zero).KIG
+        coupled = [bool(np.any(KIG[2 * q:2 * q + 2] != 0.0)) for q in range(len(info.I_nodes))]
+        core = [int(n) for n, c in zip(info.I_nodes, coupled) if not c]
+        shell = [int(n) for n, c in zip(info.I_nodes, coupled) if c]
+        assert h[6] == 2 * len(core)
+        assert I == core + shell
 
 
 def test_partition_rejects_bad_cuts(topo_exe):
