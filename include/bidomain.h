@@ -173,7 +173,10 @@ int bdm_destroy(bdm_ctx* ctx);
 
 /* Copy the state (v, u_e, w: N doubles each, host or device pointers per
  * on_device) into / out of the context.  u_e is gauged to zero mean on input.
- * The previous-step history used for extrapolated guesses is reset. */
+ * bdm_set_state starts a new trajectory: the previous-step history used for
+ * extrapolated guesses is reset, and so is the step counter n that the
+ * stimulus window of bdm_set_stimulus refers to (the next bdm_step takes
+ * step n = 0). */
 int bdm_set_state(bdm_ctx* ctx, const double* v, const double* ue, const double* w,
                   double t, int on_device);
 int bdm_get_state(bdm_ctx* ctx, double* v, double* ue, double* w, double* t, int on_device);

@@ -561,6 +561,9 @@ __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, con
         cb = nI; ce = n; re = n; k0 = 0; k1 = nI;
     } else {
         cb = J + NBO; ce = nI; re = n; k0 = J; k1 = min(J + NBO, nI);
+        // a panel inside the core leaves the interface rows as they are: the
+        // trapezoid stops at nI (the launch is sized the same way)
+        if (nIcv && k1 <= nIcv[s]) re = nI;
     }
     if (k1 <= k0 || tile >= trapezoid_tiles(cb, ce, re, TM)) return;
     const int nrt = (re - cb + TM - 1) / TM;
@@ -1632,14 +1635,17 @@ int syrk_variant_tm(int v) { return syrk_tm(v); }
 int syrk_variant_kc(int v) { return syrk_kc(v); }
 int interior_panel_width() { return NBO; }
 int panel_wbuf_stride() { return NBO * NB; }
-int panel_rowblocks(int J, int nI, int n) {
+int panel_rowblocks(int J, int nI, int n, int nIc) {
     if (J >= nI) return 0;
     const int r0 = J + std::min(NBO, nI - J);
-    return r0 < n ? (n - r0 + PT_RB - 1) / PT_RB : 0;
+    const int re = r0 <= nIc ? nI : n;   // a core panel's interface row blocks have nothing to do
+    return r0 < re ? (re - r0 + PT_RB - 1) / PT_RB : 0;
 }
-int syrk_tiles(bool schur, int J, int nI, int n, int variant) {
+int syrk_tiles(bool schur, int J, int nI, int n, int variant, int nIc) {
     const int TM = syrk_tm(variant);
-    return schur ? trapezoid_tiles(nI, n, n, TM) : (J < nI ? trapezoid_tiles(J + NBO, nI, n, TM) : 0);
+    if (schur) return trapezoid_tiles(nI, n, n, TM);
+    if (J >= nI) return 0;
+    return trapezoid_tiles(J + NBO, nI, std::min(J + NBO, nI) <= nIc ? nI : n, TM);
 }
 template <typename T>
 void launch_extract(hipStream_t s, const BatchDesc& d, const T* K, T* slots, T* F, double* Svv, T* Srr) {

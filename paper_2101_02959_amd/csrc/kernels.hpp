@@ -93,8 +93,10 @@ void launch_syrk_update(hipStream_t s, int nb, T* A, const int64_t* off, const i
                         bool schur, int J, int tiles, int variant = 0, const int* nIc = nullptr);
 int interior_panel_width();
 int panel_wbuf_stride();
-int panel_rowblocks(int J, int nI, int n);
-int syrk_tiles(bool schur, int J, int nI, int n, int variant = 0);
+// row blocks of k_panel_trsm and trailing tiles of the rank-k update for
+// the panel at J of one matrix (nIc: its core columns, 0 for none)
+int panel_rowblocks(int J, int nI, int n, int nIc = 0);
+int syrk_tiles(bool schur, int J, int nI, int n, int variant = 0, int nIc = 0);
 int syrk_variants();          // number of rank-k variants
 int syrk_variant_tm(int v);   // output tile edge of variant v
 int syrk_variant_kc(int v);   // inner chunk of variant v

@@ -572,6 +572,7 @@ int Context::set_state(const double* v, const double* ue, const double* w, doubl
     launch_sub_mean(stream_, N, ue_, part_, tick_, scal_);
     HIPOK(hipMemcpyAsync(vn_, v_, vb, hipMemcpyDeviceToDevice, stream_));
     t_ = t;
+    nstep_ = 0;
     have_prev_ = false;
     return sync();
 }
@@ -632,10 +633,10 @@ void Context::build_plan(ElimPlan& pl, bool interior, int variant) {
     pl.rows.assign(pl.trail.size(), 0);
     pl.schur = 0;
     for (const auto& sb : topo.subs) {
-        const int e = interior ? sb.nI : sb.nr, m = interior ? sb.n() : sb.nr;
+        const int e = interior ? sb.nI : sb.nr, m = interior ? sb.n() : sb.nr, c = interior ? sb.nIc : 0;
         for (size_t q = 0; q < pl.trail.size(); ++q) {
-            pl.trail[q] = std::max(pl.trail[q], syrk_tiles(false, (int)q * wp, e, m, variant));
-            pl.rows[q] = std::max(pl.rows[q], panel_rowblocks((int)q * wp, e, m));
+            pl.trail[q] = std::max(pl.trail[q], syrk_tiles(false, (int)q * wp, e, m, variant, c));
+            pl.rows[q] = std::max(pl.rows[q], panel_rowblocks((int)q * wp, e, m, c));
         }
         if (interior) pl.schur = std::max(pl.schur, syrk_tiles(true, 0, e, m, variant));
     }

@@ -193,6 +193,8 @@ def dataset_crops(mesh, physics, opts, runs, crop, stim_steps=20, log=print):
                 v, ue, _, _ = S.bdm_get_state()
                 states.append(torch.stack([v[idx], ue[idx]]))
             states = torch.stack(states)
+            if nit == 0:
+                raise RuntimeError(f"run {q} at {o}: no Newton iteration in {steps} steps (no stimulus?)")
             if scales is None:
                 scales = fit_scales(states)
             samples.append(make_samples(states, skip=(stim_steps,)))

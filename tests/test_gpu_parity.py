@@ -186,6 +186,30 @@ def test_fetidp_step_with_more_multipliers_than_dofs(graph):
         S.close()
 
 
+def test_set_state_restarts_the_stimulus_window():
+    """bdm_set_state starts a new trajectory: the stimulus window counts steps
+    from it, so a second run from rest on the same context is stimulated
+    again and repeats the first run's step exactly."""
+    P = _solver_mod()
+    wl = workload("slab8_supra")
+    N = wl.mesh.nnodes
+    z = np.zeros(N)
+    S = P.Solver(wl.mesh, wl.physics, wl.solver, precision=0)
+    try:
+        S.bdm_set_state(z, z, z)
+        S.bdm_set_stimulus(stimulus_nodal(wl.mesh, (2, 2, 2), 1e5), 0, 2)
+        runs = []
+        for _ in range(2):
+            S.bdm_set_state(z, z, z)
+            its = [S.bdm_step(1).newton_its for _ in range(3)]
+            runs.append((its, S.bdm_get_state()[0].cpu().numpy()))
+        assert runs[0][0][0] > 0 and runs[1][0][0] > 0
+        assert runs[0][0] == runs[1][0]
+        assert np.array_equal(runs[0][1], runs[1][1])
+    finally:
+        S.close()
+
+
 def test_fetidp_step_needs_fp64_local_factors():
     """FETI-DP's multiplier operator contains the local solves; with FP32
     factors it loses definiteness at scale, so a Newton step is refused
