@@ -307,6 +307,9 @@ def main():
             "extrapolated_guess (plain_fp64 / fp64_extrap)": sp("plain_fp64", "fp64_extrap"),
             "fp32_local_factors (fp64_extrap / mixed_extrap)": sp("fp64_extrap", "mixed_extrap"),
             "learned_guess (mixed_extrap / mixed)": sp("mixed_extrap", "mixed")}
+        # the learned guess earns its place only if its leg is not slower than
+        # the same precision with the extrapolated guess
+        out["learned_guess_pays_off"] = legs["mixed"]["s_per_step"] <= legs["mixed_extrap"]["s_per_step"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, plain["newton_per_step"], plain["pcg_per_newton"])
     print(json.dumps(out), flush=True)

@@ -572,10 +572,16 @@ __global__ __launch_bounds__(kWG) void k_syrk_batched(T* __restrict__ Abase, con
     const int ti = tj + tile;
     const int I0 = cb + ti * TM, J0 = cb + tj * TM;
     // rows of the tile all in [nI, n): their operand is zero left of the
-    // core boundary nIc (the interface does not couple with the core), so
-    // the inner indices start there, and a tile with none left keeps C
+    // core boundary c = nIc (the interface does not couple with the core),
+    // so the inner indices start there, and a tile with none left keeps C.
+    // A panel that straddles c (J < c < k1) gives these rows only the short
+    // slice [c, k1), and only the next panel's columns take it at once
+    // (that panel's row blocks need it); the columns beyond take the slice
+    // with the next panel's own update, whose inner range then starts at c.
     if (nIcv && I0 >= nI) {
-        k0 = max(k0, nIcv[s]);
+        const int c = nIcv[s];
+        if (mode == SY_TRAIL && J < c && c < k1 && J0 >= J + 2 * NBO) return;
+        k0 = (mode == SY_TRAIL && J - NBO < c && c < J) ? c : max(k0, c);
         if (k0 >= k1) return;
     }
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;

@@ -183,10 +183,12 @@ def test_predictor_errors():
 
 
 def test_trained_network_gain_on_held_out_site():
-    """The committed weights on a stimulus site outside the training set: the
-    judged learned guess starts Newton from a smaller residual than
-    extrapolation, never needs more Newton iterations, and reaches the same
-    state to the Newton tolerance."""
+    """The committed weights (trained on crops of the 17M-dof slab) on a
+    stimulus site of the 32^3 slab: the judged learned guess starts Newton
+    from a smaller residual than extrapolation, needs no more Newton and no
+    more PCG iterations, takes no more wall time beyond run-to-run noise, and
+    reaches the same state to the Newton tolerance.  (It saves no iteration
+    either: 25 Newton and 450 PCG iterations both ways when measured.)"""
     P = _P()
     from paper_2101_02959_amd import predictor as PR
     from workload import stimulus_sites
@@ -199,8 +201,10 @@ def test_trained_network_gain_on_held_out_site():
         print(r["step"], r["extrap"]["newton"], r["cnn"]["newton"], r["cnn"]["used"],
               "%.3e %.3e" % (r["extrap"]["r0"], r["cnn"]["r0"]))
     print(s, worst)
-    assert s["r0_gain_geomean"] > 1.5
+    assert s["r0_gain_geomean"] > 2.0
     assert s["newton"][1] <= s["newton"][0]
-    assert s["cnn_used"] >= 6
+    assert s["pcg"][1] <= s["pcg"][0]
+    assert s["ms"][1] <= 1.05 * s["ms"][0]
+    assert s["cnn_used"] >= 8
     assert worst < 1e-8
     assert all(r["cnn"]["rfinal"] <= r["cnn"]["tol"] for r in rows)
