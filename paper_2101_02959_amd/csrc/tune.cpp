@@ -267,6 +267,14 @@ int Tuner::pick(const std::string& family, const std::string& cls, int nvar,
             best = v;
         }
     }
+    // Variants within 1% of the fastest are a tie (run-to-run timing noise
+    // is about that): the lowest-numbered of them is taken, so repeated
+    // tunings of one build settle on the same variant.
+    for (int v = 0; v < best; ++v)
+        if (e.ms[v] >= 0 && e.ms[v] <= 1.01 * tbest) {
+            best = v;
+            break;
+        }
     e.choice = best;
     entries.push_back(std::move(e));
     used.push_back((int)entries.size() - 1);

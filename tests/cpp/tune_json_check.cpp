@@ -63,8 +63,14 @@ int main() {
     CHECK(t.pick("f", "c2", 3, [&](int v) { ++calls; return v == 2 ? 0.5 : (v == 0 ? -1.0 : 2.0); }) == 2);
     CHECK(calls == 3 && t.dirty);
     CHECK(t.pick("f", "c", 1, [&](int) { ++calls; return 1.0; }) == 0 && calls == 4);   // cached choice out of range
+    // within 1% of the fastest is a tie, taken by the lowest index; a failed
+    // timing (negative) never wins
+    const double tt[5] = {-1.0, 1.2, 1.009, 1.0, 1.005};
+    CHECK(t.pick("f", "tie", 5, [&](int v) { return tt[v]; }) == 2);
+    const double tu[3] = {1.02, 1.011, 1.0};
+    CHECK(t.pick("f", "notie", 3, [&](int v) { return tu[v]; }) == 2);
     std::vector<TuneEntry> rep;
-    CHECK(bdm::tune_from_json(t.report(), rep).empty() && rep.size() == 3);
+    CHECK(bdm::tune_from_json(t.report(), rep).empty() && rep.size() == 5);
     std::printf(fails ? "FAILED\n" : "OK\n");
     return fails ? 1 : 0;
 }
