@@ -955,14 +955,28 @@ __global__ __launch_bounds__(kWG) void k_coarse_local(BatchDesc d, const T* __re
             pj[u] = p < npair ? p - i * (i + 1) / 2 : 0;
             g[u] = 0.0;
         }
+        // the next chunk's rows are loaded into registers (clamped
+        // addresses, masked values) while the current one is summed
+        constexpr int GL = (GR * MAXP + kWG - 1) / kWG;
+        T nxt[GL];
+        auto load = [&](int r0) {
+#pragma unroll
+            for (int e = 0; e < GL; ++e) {
+                const int idx = tid + kWG * e, rr = idx % GR, c = min(idx / GR, nP - 1);
+                nxt[e] = Y[(int64_t)c * nr + min(r0 + rr, nr - 1)];
+            }
+        };
+        load(0);
         for (int r0 = 0; r0 < nr; r0 += GR) {
             const int rows = min(GR, nr - r0);
             __syncthreads();   // the previous chunk has been consumed
-            for (int idx = tid; idx < GR * nP; idx += kWG) {
-                const int rr = idx % GR, c = idx / GR;
-                wc[rr][c] = (rr < rows) ? (double)Y[(int64_t)c * nr + r0 + rr] : 0.0;
+#pragma unroll
+            for (int e = 0; e < GL; ++e) {
+                const int idx = tid + kWG * e, rr = idx % GR, c = idx / GR;
+                if (c < nP) wc[rr][c] = (rr < rows) ? (double)nxt[e] : 0.0;
             }
             __syncthreads();
+            if (r0 + GR < nr) load(r0 + GR);
 #pragma unroll
             for (int u = 0; u < GP; ++u) {
                 if (tid + kWG * u < npair) {

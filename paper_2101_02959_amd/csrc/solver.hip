@@ -838,13 +838,19 @@ int Context::linearize_t() {
         eliminate<T>(K, s0, cnt, plan_rr_, nullptr);
     }
     // The deluxe factors need only the extracted blocks: they run on the side
-    // stream while the coarse chain (whose upper tree levels leave most of
-    // the device idle) runs here; the two join before the status read-back.
+    // stream while the coarse factorization (whose upper tree levels leave
+    // most of the device idle) runs here; the two join before the status
+    // read-back.
     if (!side_stream_) {
         HIPOK(hipStreamCreateWithFlags(&side_stream_, hipStreamNonBlocking));
         HIPOK(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming));
         HIPOK(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming));
     }
+    // The coarse basis algebra runs before the fork: alone it takes a third
+    // of its time beside the deluxe kernels, which then overlap the coarse
+    // factorization only.
+    launch_trsm_fwd<T>(stream_, nsub, (const T*)Lrrs_, Lrr_off_, nr_, (T*)F_, bd_.F_off, nr_, kF_);
+    launch_coarse_local<T>(stream_, bd_, (const T*)F_, Svv_, (T*)Z_, Sp_, info_sub_);
     HIPOK(hipEventRecord(ev_fork_, stream_));
     HIPOK(hipStreamWaitEvent(side_stream_, ev_fork_, 0));
     if (opts.scaling == BDM_SCALING_RHO) {
@@ -858,8 +864,6 @@ int Context::linearize_t() {
         launch_deluxe_transpose<T>(side_stream_, od_, (const T*)dmat_, (T*)dmatT_);
     }
     HIPOK(hipEventRecord(ev_join_, side_stream_));
-    launch_trsm_fwd<T>(stream_, nsub, (const T*)Lrrs_, Lrr_off_, nr_, (T*)F_, bd_.F_off, nr_, kF_);
-    launch_coarse_local<T>(stream_, bd_, (const T*)F_, Svv_, (T*)Z_, Sp_, info_sub_);
     coarse_.factor(stream_, color_list_, color_ptr_, nP_, Sp_, SP_STRIDE);
     HIPOK(hipStreamWaitEvent(stream_, ev_join_, 0));
     int hb = 0, hc = 0;
