@@ -103,6 +103,8 @@ Context::~Context() {
     if (side_stream_) hipStreamDestroy(side_stream_);
     if (ev_fork_) hipEventDestroy(ev_fork_);
     if (ev_join_) hipEventDestroy(ev_join_);
+    if (ev_free_) hipEventDestroy(ev_free_);
+    if (ev_ready_) hipEventDestroy(ev_ready_);
     for (void* p : allocs_) hipFree(p);
 }
 
@@ -149,6 +151,7 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
     // The Dirichlet solves run as one fused forward/backward launch unless
     // BDM_DIRICHLET_FUSED=0 (the same arithmetic either way).
     if (const char* e = std::getenv("BDM_DIRICHLET_FUSED")) fused_dirichlet_ = std::atoi(e) != 0;
+    if (const char* e = std::getenv("BDM_SETUP_OVERLAP")) setup_overlap_ = std::atoi(e) != 0;
     if (!(o->dt > 0) || o->newton_maxit < 1 || o->krylov_maxit < 1 ||
         (o->schedule != BDM_SCHED_QUEUE && o->schedule != BDM_SCHED_GRID) ||
         (o->krylov_reduced != 0 && o->krylov_reduced != 1) ||
@@ -555,6 +558,13 @@ int Context::alloc_local() {
     info_sub_ = (int*)dalloc(nsub * sizeof(int));
     info_obj_ = (int*)dalloc((size_t)od_.nobj * sizeof(int));
     info_c_ = (int*)dalloc(sizeof(int));
+    // the second workspace only with more than one chunk and 16 GB to spare
+    // after it (Krylov vectors and the network come later)
+    if (setup_overlap_ && chunks_.size() > 1) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess && fr > (size_t)nKwork_ * sizeof(T) + ((size_t)16 << 30))
+            K2_ = dalloc(nKwork_ * sizeof(T));
+    }
     if (!K_ || !Wbuf_ || !LIIs_ || !Lrrs_ || !slots_ || !inv_ || !dmat_ || !dmatT_ || !F_ || !Z_ || !fac_ || (feti && !Srr_) || !xI_ || !xr_ ||
         !xr2_ || !Svv_ || !Sp_ || !cP_ || !mu_ || !cb_ || !ybuf_ || !info_sub_ || !info_obj_ || !info_c_) {
         set_error("device allocation failed (local factors)");
@@ -732,6 +742,14 @@ int Context::tune_syrk() {
     return save_tuning();
 }
 
+int Context::side_stream_init() {
+    if (side_stream_) return 0;
+    HIPOK(hipStreamCreateWithFlags(&side_stream_, hipStreamNonBlocking));
+    for (hipEvent_t* e : {&ev_fork_, &ev_join_, &ev_free_, &ev_ready_})
+        HIPOK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    return 0;
+}
+
 int Context::save_tuning() {
     if (tune_path_.empty() || !tuner_.dirty) return 0;
     const std::string e = tuner_.save(tune_path_);
@@ -821,31 +839,50 @@ int Context::linearize_t() {
     HIPOK(hipMemsetAsync(info_obj_, 0, od_.nobj * sizeof(int), stream_));
     HIPOK(hipMemsetAsync(info_c_, 0, sizeof(int), stream_));
     HIPOK(hipMemsetAsync(F_, 0, nF_ * sizeof(T), stream_));
-    for (const auto& ch : chunks_) {
-        const int s0 = ch.first, cnt = ch.second - ch.first;
+    // With a second workspace, chunk c + 1 is cleared and assembled on the
+    // side stream while chunk c is eliminated here: the side stream waits
+    // until the chunk that last used that workspace (c - 1) is done, and
+    // chunk c + 1 waits for its assembly.
+    const int nch = (int)chunks_.size();
+    const bool ovl = K2_ != nullptr && nch > 1;
+    if (ovl) {
+        if (const int rc = side_stream_init()) return rc;
+    }
+    T* Kbuf[2] = {K, ovl ? (T*)K2_ : K};
+    auto prepare = [&](hipStream_t st, int c, T* Kc) {
+        BatchDesc cd = bd_;
+        cd.nsub = chunks_[c].second - chunks_[c].first;
+        cd.sub0 = chunks_[c].first;
+        launch_clear_lower<T>(st, cd, maxn_, Kc);
+        launch_assemble<T>(st, cd, maxbox_, fp, ke_, vlin_, wlin_, Kc);
+    };
+    for (int c = 0; c < nch; ++c) {
+        const int s0 = chunks_[c].first, cnt = chunks_[c].second - chunks_[c].first;
         BatchDesc cd = bd_;
         cd.nsub = cnt;
         cd.sub0 = s0;
-        launch_clear_lower<T>(stream_, cd, maxn_, K);
-        launch_assemble<T>(stream_, cd, maxbox_, fp, ke_, vlin_, wlin_, K);
-        // interior elimination: L_II, and S_Gamma in the trailing block
+        T* Kc = Kbuf[c & 1];
+        if (!ovl || c == 0) prepare(stream_, c, Kc);
+        else HIPOK(hipStreamWaitEvent(stream_, ev_ready_, 0));
+        if (ovl && c + 1 < nch) {
+            HIPOK(hipEventRecord(ev_free_, stream_));
+            HIPOK(hipStreamWaitEvent(side_stream_, ev_free_, 0));
+            prepare(side_stream_, c + 1, Kbuf[(c + 1) & 1]);
+            HIPOK(hipEventRecord(ev_ready_, side_stream_));
+        }
         // interior elimination: L_II, L_GI and S_Gamma in the trailing block (Sec. 4.1)
-        eliminate<T>(K, s0, cnt, plan_int_, nullptr);
-        launch_extract<T>(stream_, cd, K, (T*)slots_, (T*)F_, Svv_, (T*)Srr_);
+        eliminate<T>(Kc, s0, cnt, plan_int_, nullptr);
+        launch_extract<T>(stream_, cd, Kc, (T*)slots_, (T*)F_, Svv_, (T*)Srr_);
         // constrained Neumann factor L_rr of S_rr (the leading r-block of S_Gamma);
         // the panel kernels of both eliminations also write the factors into
         // their panel-packed storage
-        eliminate<T>(K, s0, cnt, plan_rr_, nullptr);
+        eliminate<T>(Kc, s0, cnt, plan_rr_, nullptr);
     }
     // The deluxe factors need only the extracted blocks: they run on the side
     // stream while the coarse factorization (whose upper tree levels leave
     // most of the device idle) runs here; the two join before the status
     // read-back.
-    if (!side_stream_) {
-        HIPOK(hipStreamCreateWithFlags(&side_stream_, hipStreamNonBlocking));
-        HIPOK(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming));
-        HIPOK(hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming));
-    }
+    if (const int rc = side_stream_init()) return rc;
     // The coarse basis algebra runs before the fork: alone it takes a third
     // of its time beside the deluxe kernels, which then overlap the coarse
     // factorization only.

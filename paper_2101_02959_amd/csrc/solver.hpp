@@ -120,6 +120,11 @@ class Context {
 
     // batched local storage (element type per precision)
     void *K_ = nullptr, *slots_ = nullptr, *F_ = nullptr, *Z_ = nullptr;
+    // second setup workspace (when the device has room): the next chunk is
+    // cleared and assembled into it on the side stream while the current
+    // chunk is eliminated
+    void* K2_ = nullptr;
+    bool setup_overlap_ = true;
     void *fac_ = nullptr, *Srr_ = nullptr, *xI_ = nullptr, *xr_ = nullptr, *xr2_ = nullptr;
     double *Svv_ = nullptr, *Sp_ = nullptr, *cP_ = nullptr, *mu_ = nullptr;
     double *cb_ = nullptr, *ybuf_ = nullptr;
@@ -181,6 +186,8 @@ class Context {
     // with the coarse chain (forward solves, local products, factorization)
     hipStream_t side_stream_ = nullptr;
     hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;
+    hipEvent_t ev_free_ = nullptr, ev_ready_ = nullptr;   // workspace hand-over between the streams
+    int side_stream_init();
 };
 
 void set_error(const std::string& msg);
