@@ -392,8 +392,12 @@ __global__ __launch_bounds__(kWG) void k_panel_trsm(T* __restrict__ Abase, const
                                                    const int* __restrict__ nv, int nsub, int rowblocks, int J,
                                                    const T* __restrict__ Wbuf, T* __restrict__ Pk,
                                                    const int64_t* __restrict__ poff, const int* __restrict__ nIcv) {
+    // FP32 stages every factor block of a column block (the L_bc, c < b, and
+    // W_b) at once, two barriers per column block; FP64 stages one block at
+    // a time (its LDS would otherwise halve the resident workgroups)
+    constexpr int LSL = sizeof(T) == 4 ? NBO / NB : 1;
     __shared__ T Xs[PT_RB][PT_XS];
-    __shared__ T Ls[NB][NB + 1];
+    __shared__ T Ls[LSL][NB][NB + 1];
     // all row blocks of one matrix run on one XCD (dispatch assigns
     // consecutive ids round robin to the 8 XCDs), so its factor blocks are
     // fetched from HBM once and then served by that XCD's L2
@@ -448,53 +452,114 @@ __global__ __launch_bounds__(kWG) void k_panel_trsm(T* __restrict__ Abase, const
         const int idx = tid + e * kWG, r = idx % PT_RB, c = idx / PT_RB;
         Xs[r][c] = (r < rows && c < w) ? xr[e] : (T)0;
     }
+    if constexpr (LSL > 1) {
+        // Each wave owns rows 16 wv .. 16 wv + 15 of Xs, so between the
+        // barriers that publish the staged blocks a wave only reads back what
+        // it wrote itself (in order within the wave; the fences keep the
+        // compiler from reordering those accesses).
+        auto wave_sync = [] {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        };
+        __syncthreads();   // Xs is filled
 #pragma unroll
-    for (int b = 0; b < NBO / NB; ++b) {
-        typename Mfma<T>::acc acc[2];
-        acc[0] = (typename Mfma<T>::acc){0, 0, 0, 0};
-        acc[1] = acc[0];
-        // acc = sum_{c<b} X_c L_bc^T  (wave wv: rows 16 wv .. 16 wv + 15, 32 columns)
+        for (int b = 0; b < NBO / NB; ++b) {
+            if (b > 0) __syncthreads();   // every wave is done with the previous blocks
 #pragma unroll
-        for (int c = 0; c < b; ++c) {
-            __syncthreads();
+            for (int c = 0; c < b; ++c)
+#pragma unroll
+                for (int e = 0; e < BPT; ++e) {
+                    const int idx = tid + e * kWG, i = idx % NB, j = idx / NB;
+                    Ls[c][i][j] = (NB * b + i < w && NB * c + j < w) ? lb[b * (b - 1) / 2 + c][e] : (T)0;
+                }
 #pragma unroll
             for (int e = 0; e < BPT; ++e) {
                 const int idx = tid + e * kWG, i = idx % NB, j = idx / NB;
-                Ls[i][j] = (NB * b + i < w && NB * c + j < w) ? lb[b * (b - 1) / 2 + c][e] : (T)0;
+                Ls[LSL - 1][i][j] = (b < nb) ? wb[b][e] : (T)0;
+            }
+            __syncthreads();
+            typename Mfma<T>::acc acc[2];
+            acc[0] = (typename Mfma<T>::acc){0, 0, 0, 0};
+            acc[1] = acc[0];
+            // acc = sum_{c<b} X_c L_bc^T
+#pragma unroll
+            for (int c = 0; c < b; ++c)
+#pragma unroll
+                for (int kk = 0; kk < NB; kk += 4) {
+                    const T a = Xs[16 * wv + lr][NB * c + kk + lk];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) acc[h] = Mfma<T>::mac(a, Ls[c][16 * h + lr][kk + lk], acc[h]);
+                }
+            // Y_b = P_b - acc in place; then X_b = Y_b W_b^T
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Xs[16 * wv + Mfma<T>::row(lane, v)][NB * b + 16 * h + lr] -= acc[h][v];
+            wave_sync();
+            acc[0] = (typename Mfma<T>::acc){0, 0, 0, 0};
+            acc[1] = acc[0];
+#pragma unroll
+            for (int kk = 0; kk < NB; kk += 4) {
+                const T a = Xs[16 * wv + lr][NB * b + kk + lk];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) acc[h] = Mfma<T>::mac(a, Ls[LSL - 1][16 * h + lr][kk + lk], acc[h]);
+            }
+            wave_sync();
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Xs[16 * wv + Mfma<T>::row(lane, v)][NB * b + 16 * h + lr] = acc[h][v];
+        }
+    } else {
+#pragma unroll
+        for (int b = 0; b < NBO / NB; ++b) {
+            typename Mfma<T>::acc acc[2];
+            acc[0] = (typename Mfma<T>::acc){0, 0, 0, 0};
+            acc[1] = acc[0];
+            // acc = sum_{c<b} X_c L_bc^T  (wave wv: rows 16 wv .. 16 wv + 15, 32 columns)
+#pragma unroll
+            for (int c = 0; c < b; ++c) {
+                __syncthreads();
+#pragma unroll
+                for (int e = 0; e < BPT; ++e) {
+                    const int idx = tid + e * kWG, i = idx % NB, j = idx / NB;
+                    Ls[0][i][j] = (NB * b + i < w && NB * c + j < w) ? lb[b * (b - 1) / 2 + c][e] : (T)0;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int kk = 0; kk < NB; kk += 4) {
+                    const T a = Xs[16 * wv + lr][NB * c + kk + lk];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) acc[h] = Mfma<T>::mac(a, Ls[0][16 * h + lr][kk + lk], acc[h]);
+                }
+            }
+            __syncthreads();
+            // Y_b = P_b - acc in place; then X_b = Y_b W_b^T
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Xs[16 * wv + Mfma<T>::row(lane, v)][NB * b + 16 * h + lr] -= acc[h][v];
+#pragma unroll
+            for (int e = 0; e < BPT; ++e) {
+                const int idx = tid + e * kWG, i = idx % NB, j = idx / NB;
+                Ls[0][i][j] = (b < nb) ? wb[b][e] : (T)0;
+            }
+            __syncthreads();
+            acc[0] = (typename Mfma<T>::acc){0, 0, 0, 0};
+            acc[1] = acc[0];
+#pragma unroll
+            for (int kk = 0; kk < NB; kk += 4) {
+                const T a = Xs[16 * wv + lr][NB * b + kk + lk];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) acc[h] = Mfma<T>::mac(a, Ls[0][16 * h + lr][kk + lk], acc[h]);
             }
             __syncthreads();
 #pragma unroll
-            for (int kk = 0; kk < NB; kk += 4) {
-                const T a = Xs[16 * wv + lr][NB * c + kk + lk];
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
-                for (int h = 0; h < 2; ++h) acc[h] = Mfma<T>::mac(a, Ls[16 * h + lr][kk + lk], acc[h]);
-            }
+                for (int v = 0; v < 4; ++v) Xs[16 * wv + Mfma<T>::row(lane, v)][NB * b + 16 * h + lr] = acc[h][v];
         }
-        __syncthreads();
-        // Y_b = P_b - acc in place; then X_b = Y_b W_b^T
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) Xs[16 * wv + Mfma<T>::row(lane, v)][NB * b + 16 * h + lr] -= acc[h][v];
-#pragma unroll
-        for (int e = 0; e < BPT; ++e) {
-            const int idx = tid + e * kWG, i = idx % NB, j = idx / NB;
-            Ls[i][j] = (b < nb) ? wb[b][e] : (T)0;
-        }
-        __syncthreads();
-        acc[0] = (typename Mfma<T>::acc){0, 0, 0, 0};
-        acc[1] = acc[0];
-#pragma unroll
-        for (int kk = 0; kk < NB; kk += 4) {
-            const T a = Xs[16 * wv + lr][NB * b + kk + lk];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) acc[h] = Mfma<T>::mac(a, Ls[16 * h + lr][kk + lk], acc[h]);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) Xs[16 * wv + Mfma<T>::row(lane, v)][NB * b + 16 * h + lr] = acc[h][v];
     }
     __syncthreads();
     for (int idx = tid; idx < PT_RB * NBO; idx += kWG) {
