@@ -877,7 +877,7 @@ __device__ __forceinline__ void load_prow(const T* __restrict__ p, T (&v)[NB]) {
 }
 
 // Zero the lower triangle (diagonal included) of every local matrix of a
-// chunk before its assembly: the elimination, extraction and copy-out read
+// chunk before its assembly: the elimination and extraction read
 // and write lower-triangle entries only.  Grid: (column blocks of CL_COLS,
 // matrices).
 constexpr int CL_COLS = 16;
