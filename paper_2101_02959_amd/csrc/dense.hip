@@ -1420,7 +1420,7 @@ __global__ __launch_bounds__(kWG) void k_trsv(const T* __restrict__ Lb, const in
 // operator E_m = S^(m) (sum S)^{-1} is formed: E_m g is the residual-side
 // split and E_m^T u the value-side average term, so the per-iteration deluxe
 // scaling is a set of dense GEMVs.  A non-positive pivot flags the object.
-constexpr int DLX_MAXN = 1024;
+constexpr int DLX_MAXN = 1280;
 
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_deluxe_setup(ObjDesc o, const T* __restrict__ slots,

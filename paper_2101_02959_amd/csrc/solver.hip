@@ -28,7 +28,7 @@ static void* ctx_alloc(void* c, size_t bytes) {
     static_cast<std::vector<void*>*>(c)->push_back(p);
     return p;
 }
-constexpr int MAXOBJ = 1024;   // largest face / edge (dofs)
+constexpr int MAXOBJ = 1280;   // largest face / edge (dofs): H/h up to 26
 
 template <typename T>
 __global__ void k_sub_t(int64_t n, const T* __restrict__ x, T* __restrict__ y) {
@@ -334,6 +334,19 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
     if (maxobjn_ > deluxe_max_object()) {
         set_error("a face or edge has more than " + std::to_string(deluxe_max_object()) + " dofs");
         return BDM_E_ARG;
+    }
+    {
+        // the per-iteration triangular solves keep a subdomain's vector in LDS
+        int dev = 0, lds = 0;
+        HIPOK(hipGetDevice(&dev));
+        HIPOK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        const int64_t need = (int64_t)std::max(maxnI_, maxnr_) * (int64_t)tsize_;
+        if (need > lds) {
+            set_error("a subdomain has " + std::to_string(std::max(maxnI_, maxnr_)) + " interior or interface dofs; " +
+                      "its triangular-solve vector (" + std::to_string(need) + " bytes) exceeds the " +
+                      std::to_string(lds) + " bytes of LDS per workgroup (FP32 local factors halve it)");
+            return BDM_E_ARG;
+        }
     }
     // per-subdomain object lists
     std::vector<int64_t> so_ptr(nsub + 1, 0), so_slot;

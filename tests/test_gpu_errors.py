@@ -43,3 +43,17 @@ def test_negative_reaction_diagonal_is_reported(prec):
         assert np.all(np.isfinite(z))
     finally:
         S.close()
+
+
+def test_interior_too_large_for_the_solve_lds_is_refused():
+    """The per-iteration triangular solves keep a subdomain's vector in LDS
+    (160 KB per workgroup): the H/h = 24 slab of the optimality test has
+    interiors of up to 2 x 24^3 = 27,648 dofs, 221 KB in FP64, so creating
+    the context with FP64 local factors fails with BDM_E_ARG and a message
+    (before any large allocation), while FP32 local factors (110 KB) are
+    accepted by the same check."""
+    import paper_2101_02959_amd as P
+    from workload import test3
+    wl = test3(24, steps=1)
+    with pytest.raises(P.BidomainError, match="BDM_E_ARG.*LDS"):
+        P.Solver(wl.mesh, wl.physics, wl.solver, precision=P.BDM_PREC_FP64)

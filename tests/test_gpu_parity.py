@@ -251,16 +251,26 @@ def test_coarse_tree_shapes(mname, leaf, prec, tol, monkeypatch):
 
 
 def test_bddc_chunked_setup(lin, monkeypatch):
-    """Setup in chunks of a few subdomains gives the same operator."""
+    """Setup in chunks of one subdomain gives the same operator, both with
+    the two alternating workspaces (the next chunk assembled on the side
+    stream during the current elimination) and with one; the two schedules
+    run the same kernels on the same data, so they agree bitwise."""
     P = _solver_mod()
     mesh, ph, so, prob, dec, B, v, w = lin
     N = prob.N
     monkeypatch.setenv("BDM_SETUP_WORKSPACE_GB", "1e-6")
-    S = P.Solver(mesh, ph, so)
-    S.bdm_linearize(v, w)
     r = newton.project_range(np.random.default_rng(8).standard_normal(2 * N), N)
-    z = _gauge(S.bdm_bddc_apply(r).cpu().numpy(), N)
-    assert_close(z, _gauge(B.apply(r), N), 1e-11, N, "chunked")
+    out = {}
+    for overlap in ("1", "0"):
+        monkeypatch.setenv("BDM_SETUP_OVERLAP", overlap)
+        S = P.Solver(mesh, ph, so)
+        try:
+            S.bdm_linearize(v, w)
+            out[overlap] = S.bdm_bddc_apply(r).cpu().numpy()
+        finally:
+            S.close()
+    assert_close(_gauge(out["1"], N), _gauge(B.apply(r), N), 1e-11, N, "chunked")
+    assert np.array_equal(out["1"], out["0"])
 
 
 @pytest.mark.parametrize("prec", [0, 1])

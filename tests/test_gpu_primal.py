@@ -150,3 +150,28 @@ def test_objects_above_512_dofs(scaling):
         assert_close(z, zref, 1e-11, N, "bddc")
     finally:
         S.close()
+
+
+def test_objects_above_1024_dofs():
+    """Faces of 1058 dofs (529 nodes: the face of an H/h = 24 subdomain,
+    above the 1024 of every smaller case) on the z-cut of a 46 x 46 x 4 slab
+    in 2 x 2 x 2 subdomains: one BDDC application in FP64 with deluxe
+    scaling against the oracle."""
+    import paper_2101_02959_amd as P
+    mesh = Mesh(46, 46, 4, 0.01, (0, 23, 46), (0, 23, 46), (0, 2, 4))
+    ph, so = Physics(), SolverOpts()
+    prob = bidomain.Problem(mesh, ph, so.dt)
+    N = prob.N
+    dec = dd.Decomposition(mesh)
+    assert max(2 * len(o.nodes) for o in dec.faces) == 1058
+    v, w = _state(N, 4)
+    B = bddc.BDDC(prob, dec, v, w)
+    r = newton.project_range(np.random.default_rng(6).standard_normal(2 * N), N)
+    zref = _gauge(B.apply(r), N)
+    S = P.Solver(mesh, ph, so, precision=0)
+    try:
+        S.bdm_linearize(v, w)
+        z = _gauge(S.bdm_bddc_apply(r).cpu().numpy(), N)
+        assert_close(z, zref, 1e-11, N, "bddc")
+    finally:
+        S.close()
