@@ -11,7 +11,8 @@ by section and equation.  Arithmetic is NumPy/SciPy in float64; there is no
 blocking, fusion or reordering beyond what the definitions state.
 
 Modules
-  fem      Q1 mesh, conductivity tensors, stiffness and lumped mass (Sec. 2, 3a)
+  fem      Q1 mesh, conductivity tensors, stiffness and lumped mass (Sec. 2, 3a);
+           the truncated ellipsoid with isoparametric Q1 elements (Sec. 6)
   ionic    Rogers-McCulloch model and the Step-1 gating update (Sec. 2, 3b)
   bidomain residual, Jacobian and direct sparse Newton in (v, u_e) (Sec. 3b-c)
   dd       subdomains, N_x classes, local Schur complements (Sec. 4.1)

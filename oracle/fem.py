@@ -1,5 +1,6 @@
 """Q1 finite elements on a structured box (paper Sec. 3a) and the
-anisotropic conductivity tensors (Sec. 2).
+anisotropic conductivity tensors (Sec. 2); isoparametric Q1 elements on the
+truncated-ellipsoid geometry of Sec. 6.
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
@@ -7,6 +8,11 @@ Nodes are numbered lexicographically, x fastest:
     node(i, j, k) = i + (nx+1) * (j + (ny+1) * k).
 Element (ex, ey, ez) owns the 8 nodes (ex+a, ey+b, ez+c), local index
 a + 2b + 4c.
+
+On the ellipsoid the same logical grid is mapped to the ellipsoidal
+coordinates (phi, theta, r): node i along x sits at phi_min + i (phi_max -
+phi_min) / nx, node j along y at theta_min + j (theta_max - theta_min) / ny,
+node k along z at r = k / nz (r = 0 the inner surface, r = 1 the outer).
 """
 from __future__ import annotations
 
@@ -138,22 +144,135 @@ def element_node_table(mesh, box=None):
     return np.stack(cols, axis=1), ez
 
 
+# ------------------------------------------------------------ ellipsoid (Sec. 6)
+def ellipsoid_axes(g, r):
+    """a(r), b(r), c(r): each main axis linear in r from its inner value
+    (a_1, b_1, c_1) to its outer value (a_2, b_2, c_2)."""
+    a1, a2, b1, b2, c1, c2 = g[:6]
+    return a1 + r * (a2 - a1), b1 + r * (b2 - b1), c1 + r * (c2 - c1)
+
+
+def ellipsoid_point(g, r, theta, phi):
+    """The parametric map of the truncated ellipsoid (Sec. 6): x = a cos(theta)
+    cos(phi), y = b cos(theta) sin(phi), z = c sin(theta).  The printed
+    z-component has sin(phi); read as sin(theta), the form for which the
+    surfaces r = const are ellipsoids with axes a(r), b(r), c(r)."""
+    a, b, c = ellipsoid_axes(g, r)
+    return np.stack([a * np.cos(theta) * np.cos(phi), b * np.cos(theta) * np.sin(phi),
+                     c * np.sin(theta)], axis=-1)
+
+
+def ellipsoid_params(mesh, i, j, k):
+    """(r, theta, phi) of the (possibly fractional) grid position (i, j, k)."""
+    g = mesh.ellipsoid
+    phi = g[8] + (g[9] - g[8]) * np.asarray(i, dtype=float) / mesh.nx
+    theta = g[6] + (g[7] - g[6]) * np.asarray(j, dtype=float) / mesh.ny
+    r = np.asarray(k, dtype=float) / mesh.nz
+    return r, theta, phi
+
+
+def node_coords(mesh):
+    """(N, 3) physical node coordinates of the ellipsoid mesh."""
+    k, j, i = np.meshgrid(np.arange(mesh.nz + 1), np.arange(mesh.ny + 1), np.arange(mesh.nx + 1),
+                          indexing="ij")
+    r, th, ph = ellipsoid_params(mesh, i.ravel(), j.ravel(), k.ravel())
+    return ellipsoid_point(mesh.ellipsoid, r, th, ph)
+
+
+def ellipsoid_frame(g, r, theta, phi):
+    """Orthonormal frame (e1, e2, n) at a point: e1 along the circumferential
+    tangent dX/dphi, e2 the longitudinal tangent dX/dtheta made orthogonal to
+    e1 (Gram-Schmidt), n = e1 x e2 the transmural direction.  On a slab the
+    same construction gives (x, y, z)."""
+    a, b, c = ellipsoid_axes(g, r)
+    xp = np.stack([-a * np.cos(theta) * np.sin(phi), b * np.cos(theta) * np.cos(phi),
+                   np.zeros_like(np.asarray(theta, dtype=float))], axis=-1)
+    xt = np.stack([-a * np.sin(theta) * np.cos(phi), -b * np.sin(theta) * np.sin(phi),
+                   c * np.cos(theta)], axis=-1)
+    e1 = xp / np.linalg.norm(xp, axis=-1, keepdims=True)
+    t = xt - np.sum(xt * e1, axis=-1, keepdims=True) * e1
+    e2 = t / np.linalg.norm(t, axis=-1, keepdims=True)
+    return e1, e2, np.cross(e1, e2)
+
+
+def conductivity_in_frame(sig, alpha, e1, e2, n):
+    """D = sum sigma_* a_* a_*^T (Sec. 2) with the fibre a_l at angle alpha
+    from e1 in the tangent plane, a_t its in-plane normal and a_n = n; the
+    fibres rotate with depth as on the slab (Sec. 6)."""
+    al = np.cos(alpha)[..., None] * e1 + np.sin(alpha)[..., None] * e2
+    at = -np.sin(alpha)[..., None] * e1 + np.cos(alpha)[..., None] * e2
+    outer = lambda u: u[..., :, None] * u[..., None, :]
+    return sig[0] * outer(al) + sig[1] * outer(at) + sig[2] * outer(n)
+
+
+def iso_element_matrices(X, D_list):
+    """Isoparametric Q1 elements (Sec. 3a on a mapped hexahedron): for the
+    elements' node coordinates X (E, 8, 3) and tensors D (E, 3, 3) per
+    medium, the stiffness int_e grad(phi_a)^T D grad(phi_b) and the lumped
+    mass int_e phi_a (row sums of the consistent mass, since the basis sums
+    to one), both by 2x2x2 Gauss quadrature on the reference cube with the
+    Jacobian J = dx/dxi of the trilinear map.  Returns ([A (E, 8, 8) per
+    medium], m (E, 8)); raises on a non-positive Jacobian determinant."""
+    E = X.shape[0]
+    As = [np.zeros((E, 8, 8)) for _ in D_list]
+    m = np.zeros((E, 8))
+    for s in _GP:
+        for t in _GP:
+            for u in _GP:
+                val, g = _q1_basis(s, t, u)
+                J = np.einsum("ead,ar->edr", X, g)
+                det = np.linalg.det(J)
+                if np.any(det <= 0.0):
+                    raise ValueError("isoparametric element with a non-positive Jacobian")
+                Jinv = np.linalg.inv(J)
+                G = np.einsum("ar,erd->ead", g, Jinv)        # physical gradients
+                w = det / 8.0                                # Gauss weights 1/2 per axis
+                for A, D in zip(As, D_list):
+                    A += w[:, None, None] * np.einsum("ead,edf,ebf->eab", G, D, G)
+                m += w[:, None] * val[None, :]
+    return As, m
+
+
+def ellipsoid_elements(mesh, physics, box=None):
+    """Per-element stiffness (tau-free) of both media and lumped masses of
+    the ellipsoid mesh or of an element box: node coordinates from the
+    parametric map, the tensor of each element from the frame at its
+    parametric centre and the fibre angle at its centre depth."""
+    en, ez = element_node_table(mesh, box)
+    Xn = node_coords(mesh)
+    X = Xn[en]                                            # (E, 8, 3)
+    i0 = en[:, 0] % (mesh.nx + 1)
+    j0 = (en[:, 0] // (mesh.nx + 1)) % (mesh.ny + 1)
+    r, th, ph = ellipsoid_params(mesh, i0 + 0.5, j0 + 0.5, ez + 0.5)
+    e1, e2, n = ellipsoid_frame(mesh.ellipsoid, r, th, ph)
+    alpha = physics.theta0 + (physics.theta1 - physics.theta0) * r
+    Di = conductivity_in_frame(physics.sigma_i, alpha, e1, e2, n)
+    De = conductivity_in_frame(physics.sigma_e, alpha, e1, e2, n)
+    (Ai, Ae), m = iso_element_matrices(X, [Di, De])
+    return en, Ai, Ae, m
+
+
 def assemble(mesh, physics, box=None):
     """Global (or box-restricted) stiffness A_i, A_e and lumped mass M.
 
     A = sum_e P_e^T A^e P_e over the elements; the lumped mass is the row sum
     of the consistent mass ("usual mass lumping", Sec. 3a).  Matrices are
     over all mesh nodes; rows of nodes outside the box are empty."""
-    Ai_l, Ae_l = layer_stiffness(mesh, physics)
-    Me = element_mass(mesh.spacing)
-    en, lay = element_node_table(mesh, box)
+    if getattr(mesh, "ellipsoid", ()):
+        en, Ai_e, Ae_e, m_e = ellipsoid_elements(mesh, physics, box)
+        vi, ve, mv = Ai_e.ravel(), Ae_e.ravel(), m_e.ravel()
+    else:
+        Ai_l, Ae_l = layer_stiffness(mesh, physics)
+        Me = element_mass(mesh.spacing)
+        en, lay = element_node_table(mesh, box)
+        vi = np.stack(Ai_l)[lay].ravel()
+        ve = np.stack(Ae_l)[lay].ravel()
+        mv = np.tile(Me.sum(axis=1), len(lay))
     rows = np.repeat(en, 8, axis=1).ravel()          # (e, a, b) -> node a
     cols = np.tile(en, (1, 8)).ravel()               # (e, a, b) -> node b
-    vi = np.stack(Ai_l)[lay].ravel()
-    ve = np.stack(Ae_l)[lay].ravel()
     n = mesh.nnodes
     Ai = sp.csr_matrix((vi, (rows, cols)), shape=(n, n))
     Ae = sp.csr_matrix((ve, (rows, cols)), shape=(n, n))
     m = np.zeros(n)
-    np.add.at(m, en.ravel(), np.tile(Me.sum(axis=1), len(lay)))
+    np.add.at(m, en.ravel(), mv)
     return Ai, Ae, m

@@ -39,7 +39,12 @@ class Physics:
 @dataclasses.dataclass(frozen=True)
 class Mesh:
     """nx x ny x nz box elements of size h x hy x hz (hy, hz <= 0: equal to
-    h, i.e. cubes of side h) and the tensor partition's cut positions."""
+    h, i.e. cubes of side h) and the tensor partition's cut positions.
+
+    A non-empty ``ellipsoid`` (a1, a2, b1, b2, c1, c2, theta_min, theta_max,
+    phi_min, phi_max) maps the same logical grid onto a truncated ellipsoid
+    instead (x along phi, y along theta, z along the depth r); h, hy, hz are
+    then unused."""
     nx: int
     ny: int
     nz: int
@@ -49,6 +54,7 @@ class Mesh:
     cuts_z: tuple
     hy: float = 0.0
     hz: float = 0.0
+    ellipsoid: tuple = ()
 
     @property
     def spacing(self) -> tuple:
@@ -226,6 +232,32 @@ def test4(parts=(24, 12, 3), steps: int = 2400, paper_geometry: bool = True) -> 
         m = dataclasses.replace(m, hy=0.02, hz=0.02)
     tag = "" if paper_geometry else "_cubic"
     return Workload(f"test4_{px}x{py}x{pz}{tag}", m, Physics(), Solver(), PAPER_STIM, (2, 2, 2), 20, steps, None)
+
+
+# Axes (cm) and angular ranges of the truncated ellipsoid.  The paper gives
+# the parametric form but not its coefficients; these describe a portion of
+# an idealised left ventricle: a wall 1.2 cm thick at the equator and 0.6 cm
+# at the apex end, latitudes from -67.5 to 22.5 degrees and half the
+# circumference.
+ELLIPSOID = (1.5, 2.7, 1.5, 2.7, 4.4, 5.0, -3.0 * math.pi / 8.0, math.pi / 8.0,
+             -math.pi / 4.0, 3.0 * math.pi / 4.0)
+
+
+def ellipsoid_mesh(nx, ny, nz, px, py, pz, geometry=ELLIPSOID) -> Mesh:
+    """nx x ny x nz elements over (phi, theta, r) of the truncated ellipsoid,
+    in px x py x pz equal subdomains."""
+    return Mesh(nx, ny, nz, 1.0, uniform_cuts(nx, px), uniform_cuts(ny, py), uniform_cuts(nz, pz),
+                ellipsoid=tuple(float(x) for x in geometry))
+
+
+def ellipsoid_workload(parts=(8, 8, 4), mesh=(128, 128, 64), steps: int = 40) -> Workload:
+    """The ellipsoid of Sec. 6, Test 2 (128 x 128 x 64 elements, 2,163,330
+    dofs) or another mesh of the same geometry, in parts = (px, py, pz)
+    equal subdomains; stimulus on the 2 x 2 x 2 elements at the grid origin
+    (the inner surface at the apex end) for 20 steps, 2 ms from rest."""
+    m = ellipsoid_mesh(*mesh, *parts)
+    tag = "x".join(str(x) for x in mesh) + "_" + "x".join(str(x) for x in parts)
+    return Workload(f"ellipsoid_{tag}", m, Physics(), Solver(), PAPER_STIM, (2, 2, 2), 20, steps, None)
 
 
 def small_mesh(n: Sequence[int], parts: Sequence[int], h: float = 0.01) -> Mesh:
