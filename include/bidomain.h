@@ -79,7 +79,22 @@ enum { BDM_PRIMAL_VE = 0, BDM_PRIMAL_V = 1, BDM_PRIMAL_VEF = 2 };
  * (Sec. 4.1): cuts_x[0..px] are element indices with cuts_x[0] = 0,
  * cuts_x[px] = nx, strictly increasing; likewise y, z.  px, py, pz >= 2
  * (every subdomain must touch an interior cross point: every primal space
- * holds the vertex values). */
+ * holds the vertex values).
+ *
+ * geometry = BDM_GEOM_ELLIPSOID maps the same logical grid onto the truncated
+ * ellipsoid of Sec. 6, x = a(r) cos(theta) cos(phi), y = b(r) cos(theta)
+ * sin(phi), z = c(r) sin(theta) (the printed z-component's sin(phi) read as
+ * sin(theta)), with a(r) = a1 + r (a2 - a1) and likewise b, c; ellipsoid[] =
+ * {a1, a2, b1, b2, c1, c2, theta_min, theta_max, phi_min, phi_max} (cm,
+ * rad).  Node (i, j, k) sits at phi = phi_min + i (phi_max - phi_min) / nx,
+ * theta = theta_min + j (theta_max - theta_min) / ny, r = k / nz.  Required:
+ * 0 < a1 < a2, 0 < b1 < b2, 0 < c1 < c2, -pi/2 < theta_min < theta_max <
+ * pi/2, phi_min < phi_max <= phi_min + 2 pi; else BDM_E_ARG.  Elements are
+ * isoparametric Q1 (2x2x2 Gauss); the tensor of an element is that of
+ * bdm_physics in the orthonormal frame at its parametric centre (e1 along
+ * dX/dphi, e2 along dX/dtheta made orthogonal to e1, n = e1 x e2), with the
+ * fibre angle at the centre's depth r.  h, hy and hz are unused. */
+enum { BDM_GEOM_BOX = 0, BDM_GEOM_ELLIPSOID = 1 };
 typedef struct bdm_mesh {
     int nx, ny, nz;
     double h;                   /* element size along x (cm)                 */
@@ -88,6 +103,8 @@ typedef struct bdm_mesh {
     const int* cuts_y;
     const int* cuts_z;
     double hy, hz;              /* element sizes along y and z (cm; <= 0: h) */
+    int geometry;               /* BDM_GEOM_*                                */
+    double ellipsoid[10];       /* BDM_GEOM_ELLIPSOID parameters, see above  */
 } bdm_mesh;
 
 /* Conductivities along (l, t, n) (Sec. 2, D = sum sigma a a^T), fibre angle
@@ -346,8 +363,10 @@ int bdm_tune_report(bdm_ctx* ctx, char* buf, long cap, long* len);
  * array of about 4 MB per GPU, held until the process ends: nz + 1 must not
  * exceed 1024 (BDM_E_ARG otherwise).  Calls on one GPU share that array and
  * are serialised by a host mutex; device work enqueued concurrently by
- * other code is not ordered against a call.  BDM_E_ARG for a null
- * argument or non-positive sizes, h or dt; BDM_E_HIP for a runtime error. */
+ * other code is not ordered against a call.  Box meshes only
+ * (geometry = BDM_GEOM_BOX).  BDM_E_ARG for a null argument, another
+ * geometry, or non-positive sizes, h or dt; BDM_E_HIP for a runtime
+ * error. */
 int bdm_residual_noalloc(const bdm_mesh* mesh, const bdm_physics* phys, double dt, const double* v,
                          const double* ue, const double* vn, const double* w, const double* Is, int stim_on,
                          double* Rv, double* Re, void* hip_stream);

@@ -22,6 +22,7 @@ BDM_SCHED_QUEUE, BDM_SCHED_GRID = 0, 1
 BDM_FETI_F, BDM_FETI_PRECOND, BDM_FETI_RHS, BDM_FETI_RECOVER = 0, 1, 2, 3
 BDM_SCALING_DELUXE, BDM_SCALING_RHO = 0, 1
 BDM_PRIMAL_VE, BDM_PRIMAL_V, BDM_PRIMAL_VEF = 0, 1, 2
+BDM_GEOM_BOX, BDM_GEOM_ELLIPSOID = 0, 1
 (BDM_KERNEL_JACOBIAN, BDM_KERNEL_TRSV_DIRICHLET, BDM_KERNEL_POTRF_INTERIOR, BDM_KERNEL_SYRK_UPDATE,
  BDM_KERNEL_TRSV_DIRICHLET_T) = 0, 1, 2, 3, 4
 
@@ -49,7 +50,8 @@ class bdm_mesh(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("h", C.c_double),
                 ("px", C.c_int), ("py", C.c_int), ("pz", C.c_int),
                 ("cuts_x", C.POINTER(C.c_int)), ("cuts_y", C.POINTER(C.c_int)),
-                ("cuts_z", C.POINTER(C.c_int)), ("hy", C.c_double), ("hz", C.c_double)]
+                ("cuts_z", C.POINTER(C.c_int)), ("hy", C.c_double), ("hz", C.c_double),
+                ("geometry", C.c_int), ("ellipsoid", C.c_double * 10)]
 
 
 class bdm_physics(C.Structure):
@@ -139,8 +141,12 @@ def make_structs(mesh, physics, solver, precision=BDM_PREC_FP64, method=BDM_SOLV
     cx = (C.c_int * len(mesh.cuts_x))(*mesh.cuts_x)
     cy = (C.c_int * len(mesh.cuts_y))(*mesh.cuts_y)
     cz = (C.c_int * len(mesh.cuts_z))(*mesh.cuts_z)
+    ell = tuple(getattr(mesh, "ellipsoid", ()))
+    if ell and len(ell) != 10:
+        raise ValueError("ellipsoid takes 10 parameters")
     m = bdm_mesh(mesh.nx, mesh.ny, mesh.nz, mesh.h, len(mesh.cuts_x) - 1, len(mesh.cuts_y) - 1,
-                 len(mesh.cuts_z) - 1, cx, cy, cz, getattr(mesh, "hy", 0.0), getattr(mesh, "hz", 0.0))
+                 len(mesh.cuts_z) - 1, cx, cy, cz, getattr(mesh, "hy", 0.0), getattr(mesh, "hz", 0.0),
+                 BDM_GEOM_ELLIPSOID if ell else BDM_GEOM_BOX, (C.c_double * 10)(*(ell or (0.0,) * 10)))
     ph = bdm_physics((C.c_double * 3)(*physics.sigma_i), (C.c_double * 3)(*physics.sigma_e),
                      physics.theta0, physics.theta1, physics.chi, physics.Cm, physics.G,
                      physics.eta1, physics.eta2, physics.vth, physics.vp)

@@ -28,6 +28,14 @@ struct FEParams {
     double hy = 0.0, hz = 0.0;  // element sizes along y and z
     double chiG, chieta1, eta2, vth, vp;
     int stencil_variant = 0;    // tile shape of the stencil kernel (autotuned)
+    // Mapped (curved) meshes: per-node 27-point stencils of tau A_i and tau A_e
+    // (stn[(m * 27 + d) * N + n], d = (dx+1) + 3(dy+1) + 9(dz+1)), per-node
+    // lumped masses, and per-element corner masses mec[e * 8 + a]; the element
+    // matrices are then per element (e = ex + nx (ey + ny ez)) instead of per
+    // z-layer.  All null on box meshes.
+    const double* stn = nullptr;
+    const double* mnode = nullptr;
+    const double* mec = nullptr;
 };
 
 __host__ __device__ inline double rmc_iion(const FEParams& p, double v, double w) {

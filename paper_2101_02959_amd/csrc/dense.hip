@@ -48,7 +48,8 @@ template <> struct Mfma<double> {
 // the congruent (v, u_e) form: per node pair (P, Q) the 2x2 block
 //   [[a_i + d_P delta_PQ, a_i], [a_i, a_i + a_e]],
 // a_* = (tau A_*^(j))_PQ from the elements of the subdomain only, and
-// d_P = m_P^(j) (chi C_m + tau dI_ion/dv) with the local lumped mass.
+// d_P = m_P^(j) (chi C_m + tau dI_ion/dv) with the local lumped mass (the
+// corner masses of the subdomain's elements around P).
 template <typename T>
 __global__ void k_assemble(BatchDesc d, FEParams p, const double* __restrict__ ke,
                            const double* __restrict__ v, const double* __restrict__ w,
@@ -64,7 +65,7 @@ __global__ void k_assemble(BatchDesc d, FEParams p, const double* __restrict__ k
     const int dx = dd % 3 - 1, dy = (dd / 3) % 3 - 1, dz = dd / 9 - 1;
     const int qi = pi + dx, qj = pj + dy, qk = pk + dz;
     if (qi < 0 || qi > Lx || qj < 0 || qj > Ly || qk < 0 || qk > Lz) return;
-    double ai = 0.0, ae = 0.0;
+    double ai = 0.0, ae = 0.0, mloc = 0.0;
     int nel = 0;
     for (int oz = 0; oz < 2; ++oz)
         for (int oy = 0; oy < 2; ++oy)
@@ -72,18 +73,21 @@ __global__ void k_assemble(BatchDesc d, FEParams p, const double* __restrict__ k
                 const int ei = pi - 1 + ox, ej = pj - 1 + oy, ek = pk - 1 + oz;
                 if (ei < 0 || ei >= Lx || ej < 0 || ej >= Ly || ek < 0 || ek >= Lz) continue;
                 ++nel;
+                const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
+                // element matrices per z-layer (box mesh) or per element (mapped mesh)
+                const size_t e = p.mec ? (size_t)(ex0 + ei) + (size_t)p.nx * ((ey0 + ej) + (size_t)p.ny * (ez0 + ek))
+                                       : (size_t)(ez0 + ek);
+                if (p.mec) mloc += p.mec[e * 8 + a];
                 const int bxl = 1 - ox + dx, byl = 1 - oy + dy, bzl = 1 - oz + dz;
                 if (bxl < 0 || bxl > 1 || byl < 0 || byl > 1 || bzl < 0 || bzl > 1) continue;
-                const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
                 const int b = bxl + 2 * byl + 4 * bzl;
-                const int L = ez0 + ek;
-                ai += ke[((size_t)L * 2 + 0) * 64 + a * 8 + b];
-                ae += ke[((size_t)L * 2 + 1) * 64 + a * 8 + b];
+                ai += ke[(e * 2 + 0) * 64 + a * 8 + b];
+                ae += ke[(e * 2 + 1) * 64 + a * 8 + b];
             }
     double dP = 0.0;
     if (dd == 13) {
         const int64_t g = (int64_t)(ex0 + pi) + (int64_t)p.nx1 * ((ey0 + pj) + (int64_t)p.ny1 * (ez0 + pk));
-        const double m = p.h * p.hy * p.hz * 0.125 * nel;
+        const double m = p.mec ? mloc : p.h * p.hy * p.hz * 0.125 * nel;
         dP = m * (p.c + p.tau * rmc_diion(p, v[g], w[g]));
     }
     const int* lm = d.lmap + d.lmap_off[s];

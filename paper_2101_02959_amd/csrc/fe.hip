@@ -632,9 +632,232 @@ __global__ void k_reaction_diag(FEParams p, const double* __restrict__ v, const 
     const int i = (int)(n - t * p.nx1);
     const int k = (int)(t / p.ny1);
     const int j = (int)(t - (int64_t)k * p.ny1);
-    const double d = lumped_mass(p, i, j, k) * (p.c + p.tau * rmc_diion(p, v[n], w[n]));
+    const double m = p.mnode ? p.mnode[n] : lumped_mass(p, i, j, k);
+    const double d = m * (p.c + p.tau * rmc_diion(p, v[n], w[n]));
     dg[n] = d;
     if (!(d > 0.0)) atomicOr(bad, 1);
+}
+
+// ------------------------------------------------------ mapped (curved) meshes
+// The stencil pass of k_stencil on a mesh whose coefficients differ at every
+// node: one thread per node (x fastest), the 2 x 27 coefficients read from
+// the node-major tables (consecutive lanes read consecutive addresses), the
+// neighbour values from memory through the caches.  The coefficient tables
+// are the dominant traffic: 432 bytes per node against 40 for the vectors.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_stencil_gen(FEParams p, const double* __restrict__ dg,
+                                                     const double* __restrict__ xv, const double* __restrict__ xe,
+                                                     const double* __restrict__ rv, const double* __restrict__ re,
+                                                     const double* __restrict__ vn, const double* __restrict__ w,
+                                                     const double* __restrict__ Is, double stim,
+                                                     double* __restrict__ yv, double* __restrict__ ye) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= p.N) return;
+    const int64_t plane = (int64_t)p.nx1 * p.ny1;
+    const int k = (int)(n / plane);
+    const int64_t t = n - (int64_t)k * plane;
+    const int j = (int)(t / p.nx1), i = (int)(t - (int64_t)j * p.nx1);
+    const double* __restrict__ ci = p.stn + n;
+    const double* __restrict__ ce = p.stn + 27 * p.N + n;
+    double ai = 0.0, ae = 0.0;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (i + dx < 0 || i + dx > p.nx || j + dy < 0 || j + dy > p.ny || k + dz < 0 || k + dz > p.nz)
+                    continue;
+                const int d = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+                const int64_t q = n + dx + (int64_t)dy * p.nx1 + (int64_t)dz * plane;
+                const double xeq = xe[q];
+                ai = fma(ci[(int64_t)d * p.N], xv[q] + xeq, ai);
+                ae = fma(ce[(int64_t)d * p.N], xeq, ae);
+            }
+    if (MODE == ST_RESIDUAL) {
+        const double vv = xv[n];
+        const double is = (stim != 0.0 && Is) ? Is[n] : 0.0;
+        yv[n] = p.mnode[n] * (p.c * (vv - vn[n]) + p.tau * (rmc_iion(p, vv, w[n]) - is)) + ai;
+        ye[n] = ai + ae;
+    } else {
+        const double a = dg[n] * xv[n] + ai, b = ai + ae;
+        if (MODE == ST_JAC) {
+            yv[n] = a;
+            ye[n] = b;
+        } else {
+            yv[n] = rv[n] - a;
+            ye[n] = re[n] - b;
+        }
+    }
+}
+
+// Truncated ellipsoid (Sec. 6): point of the parametric map and the
+// orthonormal frame (e1 along dX/dphi, e2 along dX/dtheta orthogonalised
+// against e1, n = e1 x e2).
+__device__ inline void ell_axes(const EllGeom& g, double r, double& a, double& b, double& c) {
+    a = g.p[0] + r * (g.p[1] - g.p[0]);
+    b = g.p[2] + r * (g.p[3] - g.p[2]);
+    c = g.p[4] + r * (g.p[5] - g.p[4]);
+}
+
+__device__ inline void ell_node(const FEParams& p, const EllGeom& g, int i, int j, int k, double X[3]) {
+    const double ph = g.p[8] + (g.p[9] - g.p[8]) * (double)i / p.nx;
+    const double th = g.p[6] + (g.p[7] - g.p[6]) * (double)j / p.ny;
+    double a, b, c;
+    ell_axes(g, (double)k / p.nz, a, b, c);
+    X[0] = a * cos(th) * cos(ph);
+    X[1] = b * cos(th) * sin(ph);
+    X[2] = c * sin(th);
+}
+
+// Per element (one thread each): the isoparametric Q1 stiffness of both
+// media, tau-scaled, into ke[(e * 2 + m) * 64 + a * 8 + b], and the corner
+// masses int_e phi_a into mec[e * 8 + a], by 2x2x2 Gauss quadrature on the
+// trilinear map; a non-positive Jacobian determinant sets *bad.  The tensor
+// of medium m is sum sigma_* a_* a_*^T in the frame at the element's
+// parametric centre with the fibre at angle th0 + (th1 - th0) r_c.
+__global__ void k_iso_elements(FEParams p, EllGeom g, IsoMedia md, double* __restrict__ ke,
+                               double* __restrict__ mec, int* __restrict__ bad) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ne = (int64_t)p.nx * p.ny * p.nz;
+    if (e >= ne) return;
+    const int ex = (int)(e % p.nx), ey = (int)((e / p.nx) % p.ny), ez = (int)(e / ((int64_t)p.nx * p.ny));
+    double X[8][3];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) ell_node(p, g, ex + (a & 1), ey + ((a >> 1) & 1), ez + (a >> 2), X[a]);
+    // frame and tensors at the parametric centre
+    const double rc = (ez + 0.5) / p.nz;
+    const double ph = g.p[8] + (g.p[9] - g.p[8]) * (ex + 0.5) / p.nx;
+    const double th = g.p[6] + (g.p[7] - g.p[6]) * (ey + 0.5) / p.ny;
+    double aa, bb, cc;
+    ell_axes(g, rc, aa, bb, cc);
+    double e1[3] = {-aa * cos(th) * sin(ph), bb * cos(th) * cos(ph), 0.0};
+    double t2[3] = {-aa * sin(th) * cos(ph), -bb * sin(th) * sin(ph), cc * cos(th)};
+    const double n1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    for (int d = 0; d < 3; ++d) e1[d] /= n1;
+    const double pr = t2[0] * e1[0] + t2[1] * e1[1] + t2[2] * e1[2];
+    for (int d = 0; d < 3; ++d) t2[d] -= pr * e1[d];
+    const double n2 = sqrt(t2[0] * t2[0] + t2[1] * t2[1] + t2[2] * t2[2]);
+    for (int d = 0; d < 3; ++d) t2[d] /= n2;
+    const double nn[3] = {e1[1] * t2[2] - e1[2] * t2[1], e1[2] * t2[0] - e1[0] * t2[2], e1[0] * t2[1] - e1[1] * t2[0]};
+    const double al = md.th0 + (md.th1 - md.th0) * rc;
+    double fl[3], ft[3];
+    for (int d = 0; d < 3; ++d) {
+        fl[d] = cos(al) * e1[d] + sin(al) * t2[d];
+        ft[d] = -sin(al) * e1[d] + cos(al) * t2[d];
+    }
+    double D[2][3][3];
+    for (int m = 0; m < 2; ++m) {
+        const double* sg = m ? md.sig_e : md.sig_i;
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) D[m][r][c] = sg[0] * fl[r] * fl[c] + sg[1] * ft[r] * ft[c] + sg[2] * nn[r] * nn[c];
+    }
+    double* Ke = ke + e * 128;
+    double* Me = mec + e * 8;
+    for (int q = 0; q < 128; ++q) Ke[q] = 0.0;
+    for (int a = 0; a < 8; ++a) Me[a] = 0.0;
+    const double gp[2] = {0.5 - 0.5 / sqrt(3.0), 0.5 + 0.5 / sqrt(3.0)};
+    for (int qp = 0; qp < 8; ++qp) {
+        const double s = gp[qp & 1], tt = gp[(qp >> 1) & 1], u = gp[qp >> 2];
+        double val[8], gr[8][3];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
+            const double fx = ax ? s : 1.0 - s, fy = ay ? tt : 1.0 - tt, fz = az ? u : 1.0 - u;
+            const double sx = ax ? 1.0 : -1.0, sy = ay ? 1.0 : -1.0, sz = az ? 1.0 : -1.0;
+            val[a] = fx * fy * fz;
+            gr[a][0] = sx * fy * fz;
+            gr[a][1] = fx * sy * fz;
+            gr[a][2] = fx * fy * sz;
+        }
+        double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};   // J[d][r] = dx_d / dxi_r
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+            for (int d = 0; d < 3; ++d)
+                for (int r = 0; r < 3; ++r) J[d][r] += X[a][d] * gr[a][r];
+        const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+        if (!(det > 0.0)) {
+            atomicOr(bad, 1);
+            return;
+        }
+        // inverse: Ji[r][d] = cofactor(d, r) / det
+        double Ji[3][3];
+        Ji[0][0] = c00 / det;
+        Ji[1][0] = c01 / det;
+        Ji[2][0] = c02 / det;
+        Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+        Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+        Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+        Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+        Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+        Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+        double G[8][3];
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+            for (int d = 0; d < 3; ++d) G[a][d] = gr[a][0] * Ji[0][d] + gr[a][1] * Ji[1][d] + gr[a][2] * Ji[2][d];
+        const double wq = det / 8.0;
+        for (int m = 0; m < 2; ++m) {
+            double DG[8][3];
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+                for (int d = 0; d < 3; ++d)
+                    DG[b][d] = D[m][d][0] * G[b][0] + D[m][d][1] * G[b][1] + D[m][d][2] * G[b][2];
+            for (int a = 0; a < 8; ++a)
+#pragma unroll
+                for (int b = 0; b < 8; ++b)
+                    Ke[m * 64 + a * 8 + b] +=
+                        md.tau * wq * (G[a][0] * DG[b][0] + G[a][1] * DG[b][1] + G[a][2] * DG[b][2]);
+        }
+#pragma unroll
+        for (int a = 0; a < 8; ++a) Me[a] += wq * val[a];
+    }
+}
+
+// Per node (one thread each): the 27-point stencil rows of both media and the
+// lumped mass, summed over the (up to 8) elements around the node in a fixed
+// order.
+__global__ __launch_bounds__(256) void k_node_stencil(FEParams p, const double* __restrict__ ke,
+                                                      const double* __restrict__ mec, double* __restrict__ stn,
+                                                      double* __restrict__ mnode) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= p.N) return;
+    const int64_t plane = (int64_t)p.nx1 * p.ny1;
+    const int k = (int)(n / plane);
+    const int64_t t = n - (int64_t)k * plane;
+    const int j = (int)(t / p.nx1), i = (int)(t - (int64_t)j * p.nx1);
+    double acc[2][27];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int d = 0; d < 27; ++d) acc[m][d] = 0.0;
+    double mass = 0.0;
+#pragma unroll
+    for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+            for (int ox = 0; ox < 2; ++ox) {
+                const int ei = i - 1 + ox, ej = j - 1 + oy, ek = k - 1 + oz;
+                if (ei < 0 || ei >= p.nx || ej < 0 || ej >= p.ny || ek < 0 || ek >= p.nz) continue;
+                const int64_t e = ei + (int64_t)p.nx * (ej + (int64_t)p.ny * ek);
+                const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
+                mass += mec[e * 8 + a];
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const int dx = (b & 1) - (1 - ox), dy = ((b >> 1) & 1) - (1 - oy), dz = (b >> 2) - (1 - oz);
+                    const int d = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+                    acc[0][d] += ke[(e * 2 + 0) * 64 + a * 8 + b];
+                    acc[1][d] += ke[(e * 2 + 1) * 64 + a * 8 + b];
+                }
+            }
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int d = 0; d < 27; ++d) stn[(int64_t)(m * 27 + d) * p.N + n] = acc[m][d];
+    mnode[n] = mass;
 }
 
 // tile variants (SX, SY, SZ)
@@ -659,19 +882,23 @@ void launch_stencil_zm(hipStream_t s, const FEParams& p, Args... args) {
 }
 
 template <int MODE, typename... Args>
-void launch_stencil(hipStream_t s, const FEParams& p, Args... args) {
+void launch_stencil(hipStream_t s, const FEParams& p, const double* st, Args... args) {
+    if (p.stn) {
+        hipLaunchKernelGGL(k_stencil_gen<MODE>, dim3((unsigned)((p.N + 255) / 256)), dim3(256), 0, s, p, args...);
+        return;
+    }
     switch (p.stencil_variant) {
-        case 1: launch_stencil_shape<MODE, 32, 8, 16>(s, p, args...); break;
-        case 2: launch_stencil_shape<MODE, 64, 4, 8>(s, p, args...); break;
-        case 3: launch_stencil_shape<MODE, 32, 4, 16>(s, p, args...); break;
-        case 4: launch_stencil_shape<MODE, 16, 16, 8>(s, p, args...); break;
-        case 5: launch_stencil_shape<MODE, 32, 8, 4>(s, p, args...); break;
-        case 6: launch_stencil_shape<MODE, 16, 16, 4>(s, p, args...); break;
-        case 7: launch_stencil_zm<MODE, 1, 4, 8, 1>(s, p, args...); break;
-        case 8: launch_stencil_zm<MODE, 1, 4, 16, 2>(s, p, args...); break;
-        case 9: launch_stencil_zm<MODE, 2, 4, 16, 1>(s, p, args...); break;
-        case 10: launch_stencil_zm<MODE, 2, 4, 16, 2>(s, p, args...); break;
-        default: launch_stencil_shape<MODE, 32, 8, 8>(s, p, args...);
+        case 1: launch_stencil_shape<MODE, 32, 8, 16>(s, p, st, args...); break;
+        case 2: launch_stencil_shape<MODE, 64, 4, 8>(s, p, st, args...); break;
+        case 3: launch_stencil_shape<MODE, 32, 4, 16>(s, p, st, args...); break;
+        case 4: launch_stencil_shape<MODE, 16, 16, 8>(s, p, st, args...); break;
+        case 5: launch_stencil_shape<MODE, 32, 8, 4>(s, p, st, args...); break;
+        case 6: launch_stencil_shape<MODE, 16, 16, 4>(s, p, st, args...); break;
+        case 7: launch_stencil_zm<MODE, 1, 4, 8, 1>(s, p, st, args...); break;
+        case 8: launch_stencil_zm<MODE, 1, 4, 16, 2>(s, p, st, args...); break;
+        case 9: launch_stencil_zm<MODE, 2, 4, 16, 1>(s, p, st, args...); break;
+        case 10: launch_stencil_zm<MODE, 2, 4, 16, 2>(s, p, st, args...); break;
+        default: launch_stencil_shape<MODE, 32, 8, 8>(s, p, st, args...);
     }
 }
 
@@ -709,5 +936,13 @@ void launch_res_minus_jac(hipStream_t s, const FEParams& p, const double* st, co
 }
 
 int stencil_variants() { return ST_NVAR; }
+
+void launch_mapped_mesh(hipStream_t s, const FEParams& p, const EllGeom& g, const IsoMedia& md, double* ke,
+                        double* mec, double* stn, double* mnode, int* bad) {
+    const int64_t ne = (int64_t)p.nx * p.ny * p.nz;
+    hipLaunchKernelGGL(k_iso_elements, dim3(nblk(ne, 64)), dim3(64), 0, s, p, g, md, ke, mec, bad);
+    hipLaunchKernelGGL(k_node_stencil, dim3(nblk(p.N, 256)), dim3(256), 0, s, p, (const double*)ke,
+                       (const double*)mec, stn, mnode);
+}
 
 }  // namespace bdm

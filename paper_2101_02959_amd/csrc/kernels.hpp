@@ -28,6 +28,20 @@ void launch_jac_apply(hipStream_t s, const FEParams& p, const double* st, const 
                       const double* x, double* y);
 void launch_res_minus_jac(hipStream_t s, const FEParams& p, const double* st, const double* dg,
                           const double* x, const double* r, double* y);
+// Truncated-ellipsoid parameters {a1, a2, b1, b2, c1, c2, theta_min,
+// theta_max, phi_min, phi_max} and the media of the isoparametric elements.
+struct EllGeom {
+    double p[10];
+};
+struct IsoMedia {
+    double sig_i[3], sig_e[3], th0, th1, tau;
+};
+// Mapped mesh set-up: per-element tau-scaled stiffness ke (nx ny nz * 128
+// doubles) and corner masses mec (* 8), then the per-node stencils stn
+// (54 N) and lumped masses mnode (N); *bad is set on a non-positive
+// Jacobian determinant.
+void launch_mapped_mesh(hipStream_t s, const FEParams& p, const EllGeom& g, const IsoMedia& md, double* ke,
+                        double* mec, double* stn, double* mnode, int* bad);
 // Variants of the stencil pass (FEParams::stencil_variant: LDS tile shapes
 // and register z-march shapes, all with the same summation order); the
 // autotuner picks one per mesh.

@@ -51,6 +51,10 @@ extern "C" int bdm_residual_noalloc(const bdm_mesh* mesh, const bdm_physics* ph,
         set_error("bdm_residual_noalloc: mesh sizes and h must be positive, dt positive");
         return BDM_E_ARG;
     }
+    if (mesh->geometry != BDM_GEOM_BOX) {
+        set_error("bdm_residual_noalloc: box meshes only (a mapped mesh needs per-node coefficient arrays)");
+        return BDM_E_ARG;
+    }
     if (mesh->nz + 1 > NA_MAX_LEVELS) {
         set_error("bdm_residual_noalloc: nz + 1 exceeds the " + std::to_string(NA_MAX_LEVELS) +
                   " coefficient levels of the static device buffer");

@@ -160,8 +160,27 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
         set_error("invalid options");
         return BDM_E_ARG;
     }
-    std::string err = topo.build(m->nx, m->ny, m->nz, m->h, m->px, m->py, m->pz, m->cuts_x, m->cuts_y,
-                                 m->cuts_z, o->primal);
+    const bool mapped = m->geometry == BDM_GEOM_ELLIPSOID;
+    if (m->geometry != BDM_GEOM_BOX && !mapped) {
+        set_error("unknown mesh geometry");
+        return BDM_E_ARG;
+    }
+    if (mapped) {
+        const double* g = m->ellipsoid;
+        const double hpi = 0.5 * M_PI;
+        bool ok = true;
+        for (int q = 0; q < 10; ++q) ok = ok && std::isfinite(g[q]);
+        ok = ok && 0.0 < g[0] && g[0] < g[1] && 0.0 < g[2] && g[2] < g[3] && 0.0 < g[4] && g[4] < g[5];
+        ok = ok && -hpi < g[6] && g[6] < g[7] && g[7] < hpi && g[8] < g[9] && g[9] <= g[8] + 2.0 * M_PI;
+        if (!ok) {
+            set_error("ellipsoid parameters need 0 < a1 < a2, 0 < b1 < b2, 0 < c1 < c2, "
+                      "-pi/2 < theta_min < theta_max < pi/2 and phi_min < phi_max <= phi_min + 2 pi");
+            return BDM_E_ARG;
+        }
+    }
+    // the element size is unused on a mapped mesh
+    std::string err = topo.build(m->nx, m->ny, m->nz, mapped ? 1.0 : m->h, m->px, m->py, m->pz, m->cuts_x,
+                                 m->cuts_y, m->cuts_z, o->primal);
     if (!err.empty()) {
         set_error(err);
         return BDM_E_ARG;
@@ -178,11 +197,13 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
     fp.chiG = ph->chi * ph->G; fp.chieta1 = ph->chi * ph->eta1; fp.eta2 = ph->eta2;
     fp.vth = ph->vth; fp.vp = ph->vp;
 
-    const double hd[3] = {fp.h, fp.hy, fp.hz};
-    std::vector<double> ke = layer_matrices(m->nz, hd, o->dt, ph->sigma_i, ph->sigma_e, ph->theta0, ph->theta1);
-    std::vector<double> st = stencil_tables(m->nz, ke);
-    ke_ = upload(ke);
-    st_ = upload(st);
+    if (!mapped) {
+        const double hd[3] = {fp.h, fp.hy, fp.hz};
+        std::vector<double> ke = layer_matrices(m->nz, hd, o->dt, ph->sigma_i, ph->sigma_e, ph->theta0, ph->theta1);
+        std::vector<double> st = stencil_tables(m->nz, ke);
+        ke_ = upload(ke);
+        st_ = upload(st);
+    }
 
     const int nsub = (int)topo.subs.size();
     // ---------------- per-subdomain descriptors
@@ -504,6 +525,39 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
         return BDM_E_OOM;
     }
     HIPOK(hipMemsetAsync(gzero_, 0, 2 * vb, stream_));
+    if (mapped) {
+        // isoparametric element matrices, per-node stencils and masses of the
+        // ellipsoid, built on the device
+        const int64_t ne = (int64_t)m->nx * m->ny * m->nz;
+        double* ke = (double*)dalloc((size_t)ne * 128 * sizeof(double));
+        double* mec = (double*)dalloc((size_t)ne * 8 * sizeof(double));
+        double* stn = (double*)dalloc((size_t)N * 54 * sizeof(double));
+        double* mnode = (double*)dalloc(vb);
+        if (!ke || !mec || !stn || !mnode || !bad_) {
+            set_error("device allocation failed (mapped mesh)");
+            return BDM_E_OOM;
+        }
+        EllGeom g;
+        for (int q = 0; q < 10; ++q) g.p[q] = m->ellipsoid[q];
+        IsoMedia md;
+        for (int q = 0; q < 3; ++q) {
+            md.sig_i[q] = ph->sigma_i[q];
+            md.sig_e[q] = ph->sigma_e[q];
+        }
+        md.th0 = ph->theta0; md.th1 = ph->theta1; md.tau = o->dt;
+        HIPOK(hipMemsetAsync(bad_, 0, sizeof(int), stream_));
+        launch_mapped_mesh(stream_, fp, g, md, ke, mec, stn, mnode, bad_);
+        HIPOK(hipGetLastError());
+        int hb = 0;
+        HIPOK(hipMemcpyAsync(&hb, bad_, sizeof(int), hipMemcpyDeviceToHost, stream_));
+        HIPOK(hipStreamSynchronize(stream_));
+        if (hb) {
+            set_error("an ellipsoid element has a non-positive Jacobian determinant");
+            return BDM_E_ARG;
+        }
+        ke_ = ke;
+        fp.mec = mec; fp.stn = stn; fp.mnode = mnode;
+    }
     int rc = prec_ ? alloc_local<float>() : alloc_local<double>();
     if (rc) return rc;
     // autotuner: device name, optional JSON cache, stencil tile shape
@@ -521,7 +575,7 @@ int Context::create(const bdm_mesh* m, const bdm_physics* ph, const bdm_opts* o,
                 return BDM_E_ARG;
             }
         }
-        if ((rc = tune_stencil())) return rc;
+        if (!fp.stn && (rc = tune_stencil())) return rc;   // mapped meshes have one stencil kernel
         if ((rc = save_tuning())) return rc;
     }
     return set_state(nullptr, nullptr, nullptr, 0.0, false);
@@ -1273,7 +1327,9 @@ int Context::profile_t(int kernel, int reps, double* avg_ms, double* work) {
     cd.nsub = cnt;
     cd.sub0 = s0;
     if (kernel == BDM_KERNEL_JACOBIAN) {
-        w = 40.0 * (double)N;
+        // vectors: x (2), the reaction diagonal and y (2) per node; mapped
+        // meshes add the 54 per-node coefficients
+        w = (fp.stn ? 40.0 + 54.0 * 8.0 : 40.0) * (double)N;
     } else if (kernel == BDM_KERNEL_TRSV_DIRICHLET || kernel == BDM_KERNEL_TRSV_DIRICHLET_T) {
         for (const auto& sb : topo.subs) w += (0.5 * sb.nI * (sb.nI + 1.0) + 2.0 * sb.nI) * sizeof(T);
     } else {

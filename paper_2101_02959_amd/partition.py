@@ -6,6 +6,12 @@ the coarse problem and the preconditioner's iteration count.
 
     python3 -m paper_2101_02959_amd.partition [--parts 16x16x4 24x24x4 ...]
                                              [--steps 40] [--out FILE]
+                                             [--geometry slab|ellipsoid]
+
+With --geometry ellipsoid the mesh is the truncated ellipsoid of the same
+test (128 x 128 x 64 elements, 2,163,330 dofs), by default in 8 x 8 x 4,
+16 x 16 x 4 and 16 x 16 x 8 subdomains (local meshes of 16^3, 8 x 8 x 16
+and 8^3 elements).
 
 For every partition and path (BDDC with FP32 local factors, BDDC in FP64,
 FETI-DP in FP64; deluxe V+E) it prints one JSON line: mean Newton iterations
@@ -55,25 +61,37 @@ def run_case(P, wl, method, precision):
             "subdomains": int(S.nsub), "coarse_dofs": int(S.nprimal)}
 
 
+ELLIPSOID_PARTS = ((8, 8, 4), (16, 16, 4), (16, 16, 8))
+
+
 def main(argv=None):
-    from workload import TEST2_PARTS, test2
+    from workload import TEST2_PARTS, ellipsoid_workload, test2
     ap = argparse.ArgumentParser()
-    ap.add_argument("--parts", nargs="+", default=["x".join(map(str, p)) for p in TEST2_PARTS])
+    ap.add_argument("--geometry", choices=("slab", "ellipsoid"), default="slab")
+    ap.add_argument("--parts", nargs="+", default=None)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--paths", nargs="+", default=["-".join(p) for p in PATHS],
                     help="method-precision pairs, e.g. bddc-mixed fetidp-f64")
     ap.add_argument("--out", default=None, help="also write the results as JSON")
     args = ap.parse_args(argv)
     import paper_2101_02959_amd as P
+    if args.parts is None:
+        args.parts = ["x".join(map(str, p)) for p in (ELLIPSOID_PARTS if args.geometry == "ellipsoid"
+                                                      else TEST2_PARTS)]
     rows = []
     for ptxt in args.parts:
         parts = tuple(int(v) for v in ptxt.split("x"))
-        wl = test2(parts, args.steps)
+        if args.geometry == "ellipsoid":
+            wl = ellipsoid_workload(parts, steps=args.steps)
+        else:
+            wl = test2(parts, args.steps)
+        m = wl.mesh
         for path in args.paths:
             method, precision = path.split("-")
             t0 = time.time()
-            rec = {"parts": ptxt, "H/h": [192 // parts[0], 192 // parts[1], 32 // parts[2]], "method": method,
-                   "precision": precision, "dofs": 2 * wl.mesh.nnodes}
+            rec = {"geometry": args.geometry, "parts": ptxt,
+                   "H/h": [m.nx // parts[0], m.ny // parts[1], m.nz // parts[2]], "method": method,
+                   "precision": precision, "dofs": 2 * m.nnodes}
             try:
                 rec.update(run_case(P, wl, method, precision))
             except P.BidomainError as e:

@@ -1,0 +1,184 @@
+"""Parity of the HIP path on the truncated-ellipsoid geometry (Sec. 6:
+isoparametric Q1 elements on the parametric map, a fibre frame per element)
+against the FP64 oracle, through the C ABI.
+
+The device builds the element matrices, the per-node stencils and the lumped
+masses itself; the oracle assembles the same operators with NumPy.  The
+comparisons are per field (v, u_e) in the relative 2-norm and element by
+element (tests/parity_util.py):
+  * residual and Jacobian apply at 1e-12;
+  * one BDDC application and the four FETI-DP operators with FP64 local
+    factors at 1e-11, and with FP32 local factors at 3e-4 (relative 2-norm)
+    and 2e-3 (element by element), the bounds of the H/h = 8 slab tests (FP32
+    round-off amplified by the local condition numbers);
+  * time steps: each step's Newton solution within 1e-8 of the root that
+    the oracle computes from the GPU's u^n.
+Meshes: equal and uneven subdomains of a coarse 12 x 10 x 6 grid (elements
+spanning 15 degrees of the shell), and 32 x 32 x 16 elements in 4 x 4 x 2
+subdomains (H/h = 8 as in the benchmark's local problems).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import bddc, bidomain, dd, fetidp, newton
+from parity_util import assert_close, gauge
+from workload import ELLIPSOID, Mesh, Physics, Solver as SolverOpts, ellipsoid_mesh, stimulus_nodal
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+MESHES = {
+    "ell12": ellipsoid_mesh(12, 10, 6, 2, 2, 2),
+    "ell_uneven": Mesh(14, 12, 7, 1.0, (0, 4, 9, 14), (0, 5, 12), (0, 3, 7), ellipsoid=ELLIPSOID),
+    "ell_hh8": ellipsoid_mesh(32, 32, 16, 4, 4, 2),
+}
+TOL64, TOL32, ETOL32 = 1e-11, 3e-4, 2e-3
+
+
+def _P():
+    import paper_2101_02959_amd as P
+    return P
+
+
+def _state(N, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-10, 40, N), rng.uniform(-5, 5, N), rng.uniform(0, 0.2, N)
+
+
+@pytest.mark.parametrize("mname", list(MESHES))
+def test_residual_and_jacobian_ellipsoid(mname):
+    P = _P()
+    mesh = MESHES[mname]
+    ph, so = Physics(), SolverOpts()
+    print(f"ellipsoid residual/jacobian {mname}", flush=True)
+    S = P.Solver(mesh, ph, so)
+    try:
+        prob = bidomain.Problem(mesh, ph, so.dt)
+        N = prob.N
+        vn, ue, w = _state(N, 1)
+        v = vn + np.random.default_rng(2).uniform(-3, 3, N)
+        Is = stimulus_nodal(mesh, (2, 2, 2), 1e5)
+        S.bdm_set_state(vn, np.zeros(N), w)
+        S.bdm_set_stimulus(Is, 0, 1)
+        R = S.bdm_residual(v, ue).cpu().numpy()
+        assert_close(R, prob.residual(v, ue - ue.mean(), vn, w, Is), 1e-12, N, "residual")
+        S.bdm_linearize(v, w)
+        x = np.random.default_rng(3).standard_normal(2 * N)
+        y = S.bdm_jacobian_apply(x).cpu().numpy()
+        assert_close(y, prob.jacobian(v, w) @ x, 1e-12, N, "jacobian")
+    finally:
+        S.close()
+
+
+@pytest.fixture(scope="module", params=list(MESHES))
+def lin(request):
+    mesh = MESHES[request.param]
+    ph, so = Physics(), SolverOpts()
+    prob = bidomain.Problem(mesh, ph, so.dt)
+    v, _, w = _state(prob.N, 4)
+    print(f"oracle BDDC setup on {request.param}", flush=True)
+    B = bddc.BDDC(prob, dd.Decomposition(mesh), v, w)
+    return request.param, mesh, ph, so, prob, B, v, w
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_bddc_apply_ellipsoid(lin, prec):
+    P = _P()
+    name, mesh, ph, so, prob, B, v, w = lin
+    N = prob.N
+    tol, etol = (TOL64, TOL64) if prec == 0 else (TOL32, ETOL32)
+    print(f"ellipsoid bddc {name} prec {prec}", flush=True)
+    S = P.Solver(mesh, ph, so, precision=prec)
+    try:
+        S.bdm_linearize(v, w)
+        for seed in (5, 6):
+            r = newton.project_range(np.random.default_rng(seed).standard_normal(2 * N), N)
+            z = gauge(S.bdm_bddc_apply(r).cpu().numpy(), N)
+            print(name, prec, seed, assert_close(z, gauge(B.apply(r), N), tol, N, f"bddc {name}", etol))
+    finally:
+        S.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fetidp_operators_ellipsoid(lin, prec):
+    P = _P()
+    name, mesh, ph, so, prob, B, v, w = lin
+    if name == "ell_hh8":
+        pytest.skip("the FETI-DP operators are covered on the two coarse grids")
+    N = prob.N
+    tol, etol = (TOL64, TOL64) if prec == 0 else (TOL32, ETOL32)
+    F = fetidp.FETIDP(B)
+    print(f"ellipsoid fetidp {name} prec {prec}", flush=True)
+    S = P.Solver(mesh, ph, so, precision=prec, method=P.BDM_SOLVER_FETIDP)
+    try:
+        S.bdm_linearize(v, w)
+        assert S.bdm_fetidp_size() == F.nlam
+        rng = np.random.default_rng(7)
+        lam = rng.standard_normal(F.nlam)
+        assert_close(S.bdm_fetidp_apply(P.BDM_FETI_F, lam).cpu().numpy(), F.F(lam), tol, None, "F", etol)
+        assert_close(S.bdm_fetidp_apply(P.BDM_FETI_PRECOND, lam).cpu().numpy(), F.precond(lam), tol, None,
+                     "precond", etol)
+        r = newton.project_range(rng.standard_normal(2 * N), N)
+        g = F.condense(r)
+        assert_close(S.bdm_fetidp_apply(P.BDM_FETI_RHS, r).cpu().numpy(), F.rhs(g), tol, None, "rhs", etol)
+        z = S.bdm_fetidp_apply(P.BDM_FETI_RECOVER, np.concatenate([r, lam])).cpu().numpy()
+        assert_close(gauge(z, N), gauge(F.expand(r, F.recover(g, lam)), N), tol, N, "recover", etol)
+    finally:
+        S.close()
+
+
+CASES = [("ell12", 0, 0, "direct", 3), ("ell_uneven", 0, 1, "direct", 3), ("ell_hh8", 1, 0, "cg", 3)]
+
+
+@pytest.mark.parametrize("name,prec,method,linear,steps", CASES)
+def test_time_steps_ellipsoid(name, prec, method, linear, steps):
+    """Newton solution per step within 1e-8 of the oracle's root from the
+    GPU's u^n, from rest with the stimulus on the 2 x 2 x 2 elements at the
+    grid origin (inner surface, apex end); BDDC or FETI-DP, FP64 or FP32
+    local factors (FETI-DP Newton solves take FP64 ones), extrapolated Newton
+    guess."""
+    P = _P()
+    mesh = MESHES[name]
+    ph, so = Physics(), SolverOpts()
+    prob = bidomain.Problem(mesh, ph, so.dt)
+    N = prob.N
+    print(f"ellipsoid steps {name} prec {prec} method {method}", flush=True)
+    S = P.Solver(mesh, ph, so, precision=prec, method=method, guess=P.BDM_GUESS_EXTRAP)
+    try:
+        Is = stimulus_nodal(mesh, (2, 2, 2), 1e5)
+        z = np.zeros(N)
+        S.bdm_set_state(z, z, z)
+        S.bdm_set_stimulus(Is, 0, 20)
+        v, ue, w = z, z, z
+        for step in range(steps):
+            st = S.bdm_step(1)
+            vg, ueg, wg, _ = S.bdm_get_state()
+            vg, ueg, wg = vg.cpu().numpy(), ueg.cpu().numpy(), wg.cpu().numpy()
+            vr, uer, wr, hist = bidomain.time_step_direct(prob, v, ue, w, Is, linear=linear)
+            assert hist[-1] <= 1e-12 * hist[0]
+            assert_close(vg, vr, 1e-8, None, f"v step {step}")
+            assert_close(ueg, uer, 1e-8, None, f"u_e step {step}")
+            assert_close(wg, wr, 1e-12, None, f"w step {step}")
+            print(name, step, "newton", st.newton_its, "krylov", list(st.krylov_its[:st.newton_its]), flush=True)
+            v, ue, w = vg, ueg, wg
+        assert np.max(v) > 1.0      # the stimulus has raised the potential
+    finally:
+        S.close()
+
+
+@pytest.mark.parametrize("bad", [{6: -math.pi / 2}, {7: math.pi / 2}, {0: 0.0}, {1: 1.0}, {9: 7.0}])
+def test_invalid_ellipsoid_parameters_are_refused(bad):
+    """Parameters outside 0 < a1 < a2 (likewise b, c), -pi/2 < theta_min <
+    theta_max < pi/2, phi_min < phi_max <= phi_min + 2 pi give BDM_E_ARG
+    before any device work."""
+    P = _P()
+    g = list(ELLIPSOID)
+    for k, x in bad.items():
+        g[k] = x
+    mesh = ellipsoid_mesh(4, 4, 4, 2, 2, 2, geometry=g)
+    with pytest.raises(P.BidomainError) as ei:
+        P.Solver(mesh, Physics(), SolverOpts())
+    assert ei.value.code == -1 and "ellipsoid" in str(ei.value)      # BDM_E_ARG

@@ -161,8 +161,9 @@ PAPER_STIM = 1.0e5     # 100 mA/cm^3 expressed in uA/cm^3
 
 def workload(name: str) -> Workload:
     """Named workloads: the parity-size slab (8^3, 2x2x2), the 32^3 slab in
-    4x4x4 subdomains, the 128x128x64 slab with uneven cuts, and the
-    256x256x128 slab in 32x32x16 subdomains (about 17.04M dofs)."""
+    4x4x4 subdomains, the 128x128x64 slab with uneven cuts, the
+    256x256x128 slab in 32x32x16 subdomains (about 17.04M dofs), and the
+    128x128x64 truncated ellipsoid in 8x8x4 subdomains (2,163,330 dofs)."""
     ph = Physics()
     if name == "slab8":
         m = box_mesh(8, 8, 8, 0.01, 2, 2, 2)
@@ -182,6 +183,8 @@ def workload(name: str) -> Workload:
     if name == "slab256":
         m = box_mesh(256, 256, 128, 0.01, 32, 32, 16)
         return Workload(name, m, ph, Solver(), PAPER_STIM, (2, 2, 2), 20, 50, None)
+    if name == "ellipsoid128":
+        return dataclasses.replace(ellipsoid_workload((8, 8, 4)), name=name)
     raise KeyError(name)
 
 
