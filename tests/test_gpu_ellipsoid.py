@@ -75,13 +75,8 @@ def test_residual_and_jacobian_ellipsoid(mname):
 
 @pytest.fixture(scope="module", params=list(MESHES))
 def lin(request):
-    mesh = MESHES[request.param]
-    ph, so = Physics(), SolverOpts()
-    prob = bidomain.Problem(mesh, ph, so.dt)
-    v, _, w = _state(prob.N, 4)
     print(f"oracle BDDC setup on {request.param}", flush=True)
-    B = bddc.BDDC(prob, dd.Decomposition(mesh), v, w)
-    return request.param, mesh, ph, so, prob, B, v, w
+    return _lin(request.param)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -102,12 +97,27 @@ def test_bddc_apply_ellipsoid(lin, prec):
         S.close()
 
 
+@pytest.fixture(scope="module", params=["ell12", "ell_uneven"])
+def lin_coarse(request):
+    """The oracle BDDC of the two coarse grids (the FETI-DP operators are
+    compared there; the time steps cover FETI-DP on the finer grid)."""
+    print(f"oracle BDDC setup on {request.param}", flush=True)
+    return _lin(request.param)
+
+
+def _lin(name):
+    mesh = MESHES[name]
+    ph, so = Physics(), SolverOpts()
+    prob = bidomain.Problem(mesh, ph, so.dt)
+    v, _, w = _state(prob.N, 4)
+    B = bddc.BDDC(prob, dd.Decomposition(mesh), v, w)
+    return name, mesh, ph, so, prob, B, v, w
+
+
 @pytest.mark.parametrize("prec", [0, 1])
-def test_fetidp_operators_ellipsoid(lin, prec):
+def test_fetidp_operators_ellipsoid(lin_coarse, prec):
     P = _P()
-    name, mesh, ph, so, prob, B, v, w = lin
-    if name == "ell_hh8":
-        pytest.skip("the FETI-DP operators are covered on the two coarse grids")
+    name, mesh, ph, so, prob, B, v, w = lin_coarse
     N = prob.N
     tol, etol = (TOL64, TOL64) if prec == 0 else (TOL32, ETOL32)
     F = fetidp.FETIDP(B)
