@@ -1426,20 +1426,12 @@ __global__ __launch_bounds__(kWG) void k_trsv(const T* __restrict__ Lb, const in
 // scaling is a set of dense GEMVs.  A non-positive pivot flags the object.
 constexpr int DLX_MAXN = 1280;
 
+// M = sum_m S^(m) over the shares of object ob (n x n, column-major), DS_U
+// entries per thread and pass with all their loads issued together (clamped
+// addresses, masked stores); called by the whole workgroup.
 template <typename T>
-__global__ __launch_bounds__(kWG) void k_deluxe_setup(ObjDesc o, const T* __restrict__ slots,
-                                                     T* __restrict__ fac, T* __restrict__ dmat,
-                                                     int* __restrict__ info, int lds_cap, int ob0) {
-    extern __shared__ double dlx_lds[];
-    __shared__ T ck[DLX_MAXN];
-    __shared__ int bad;
-    const int ob = ob0 + blockIdx.x;
-    const int n = o.n[ob];
-    const int tid = threadIdx.x, wv0 = tid >> 6, lane0 = tid & 63;
-    T* M = (n * n <= lds_cap) ? reinterpret_cast<T*>(dlx_lds) : fac + o.fac_off[ob];
-    if (tid == 0) bad = 0;
-    // sum of the shares, DS_U entries per thread and pass with all their
-    // loads issued together (clamped addresses, masked stores)
+__device__ void deluxe_sum(const ObjDesc& o, int ob, int n, T* M, const T* __restrict__ slots) {
+    const int tid = threadIdx.x;
     {
         constexpr int DS_U = 8;
         const int nn = n * n;
@@ -1457,31 +1449,14 @@ __global__ __launch_bounds__(kWG) void k_deluxe_setup(ObjDesc o, const T* __rest
                 if (base + tid + u * kWG < nn) M[base + tid + u * kWG] = acc[u];
         }
     }
-    __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        for (int i = tid; i < n; i += kWG) ck[i] = M[i + k * n];
-        __syncthreads();
-        T d = ck[k];
-        if (!(d > (T)0)) {
-            if (tid == 0) bad = 1;
-            d = (T)1;
-        }
-        const T rd = (T)1 / d;
-        // waves over columns, lanes over rows (no integer division per entry)
-        for (int j = wv0; j < n; j += kWG / 64) {
-            const T cj = ck[j];
-            T* Mj = M + (int64_t)j * n;
-            for (int i = lane0; i < n; i += 64) {
-                const T ci = ck[i];
-                T v;
-                if (i == k) v = (j == k) ? -rd : cj * rd;
-                else if (j == k) v = ci * rd;
-                else v = Mj[i] - ci * cj * rd;
-                Mj[i] = v;
-            }
-        }
-        __syncthreads();
-    }
+}
+
+// E_m = S^(m) (sum S)^{-1} = -S^(m) M for the shares of object ob, given M =
+// -(sum S)^{-1} (in LDS or global memory); called by the whole workgroup.
+template <typename T, bool STRIP = true>
+__device__ void deluxe_products(const ObjDesc& o, int ob, int n, const T* M, const T* __restrict__ slots,
+                                T* __restrict__ dmat) {
+    const int tid = threadIdx.x, wv0 = tid >> 6, lane0 = tid & 63;
     // M = -(sum S)^{-1};  E_m = S^(m) (sum S)^{-1} = -S^(m) M on MFMA 16x16x4
     // tiles (one wave per tile, S^(m) streamed from L2, M from LDS), for all
     // shares but the last; the E_m sum to the identity, which gives the last.
@@ -1492,7 +1467,7 @@ __global__ __launch_bounds__(kWG) void k_deluxe_setup(ObjDesc o, const T* __rest
     for (int q = q0; q < q1 - 1; ++q) {
         const T* S = slots + o.sh_slot[q];
         T* E = dmat + o.sh_slot[q];
-        if (n <= 4 * DS_K) {
+        if (STRIP && n <= 4 * DS_K) {
             // one 16-row strip of S^(m) per wave, loaded into registers once
             // (one exposed latency) and reused for every column tile of E_m
             for (int ti = wv; ti < nt; ti += kWG / 64) {
@@ -1548,6 +1523,178 @@ __global__ __launch_bounds__(kWG) void k_deluxe_setup(ObjDesc o, const T* __rest
                 E[idx] = acc;
             }
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_deluxe_setup(ObjDesc o, const T* __restrict__ slots,
+                                                     T* __restrict__ fac, T* __restrict__ dmat,
+                                                     int* __restrict__ info, int lds_cap, int ob0) {
+    extern __shared__ double dlx_lds[];
+    __shared__ T ck[DLX_MAXN];
+    __shared__ int bad;
+    const int ob = ob0 + blockIdx.x;
+    const int n = o.n[ob];
+    const int tid = threadIdx.x, wv0 = tid >> 6, lane0 = tid & 63;
+    T* M = (n * n <= lds_cap) ? reinterpret_cast<T*>(dlx_lds) : fac + o.fac_off[ob];
+    if (tid == 0) bad = 0;
+    deluxe_sum<T>(o, ob, n, M, slots);
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        for (int i = tid; i < n; i += kWG) ck[i] = M[i + k * n];
+        __syncthreads();
+        T d = ck[k];
+        if (!(d > (T)0)) {
+            if (tid == 0) bad = 1;
+            d = (T)1;
+        }
+        const T rd = (T)1 / d;
+        // waves over columns, lanes over rows (no integer division per entry)
+        for (int j = wv0; j < n; j += kWG / 64) {
+            const T cj = ck[j];
+            T* Mj = M + (int64_t)j * n;
+            for (int i = lane0; i < n; i += 64) {
+                const T ci = ck[i];
+                T v;
+                if (i == k) v = (j == k) ? -rd : cj * rd;
+                else if (j == k) v = ci * rd;
+                else v = Mj[i] - ci * cj * rd;
+                Mj[i] = v;
+            }
+        }
+        __syncthreads();
+    }
+    deluxe_products<T>(o, ob, n, M, slots, dmat);
+    if (tid == 0 && bad) info[ob] = 1;
+}
+
+// Objects of more than DS_N dofs (faces of subdomains from H/h = 10 up):
+// M = -(sum S)^{-1} by the sweep taken DB_W pivots at a time, with M in the
+// object's global workspace.  For the pivot block K (D = M_KK, C = M_RK the
+// rows R outside K) the sweep of all its pivots at once is
+//   M_KK <- -D^{-1},  M_RK <- C D^{-1},  M_RR <- M_RR - C D^{-1} C^T,
+// the composition of the single-pivot sweeps of K.  -D^{-1} comes from the
+// scalar sweep of the small block in LDS; H = C (-D^{-1}) is staged in LDS
+// (n x DB_W); M_RR gets the rank-DB_W update H C^T on MFMA 16x16x4 tiles
+// (one wave per tile, C read from the untouched columns K), then the pivot
+// rows and columns are written.  Each block reads and writes M once, where
+// the single-pivot sweep does so per pivot.
+template <typename T>
+constexpr int deluxe_block_width() { return 64 / (int)sizeof(T); }   // 16 (FP32), 8 (FP64)
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_deluxe_blocked(ObjDesc o, const T* __restrict__ slots,
+                                                       T* __restrict__ fac, T* __restrict__ dmat,
+                                                       int* __restrict__ info, int ob0) {
+    constexpr int BW = deluxe_block_width<T>();
+    extern __shared__ double dlx_lds[];
+    T* H = reinterpret_cast<T*>(dlx_lds);            // [n][BW]
+    __shared__ T Dk[BW][BW + 1];
+    __shared__ int bad;
+    const int ob = ob0 + blockIdx.x;
+    const int n = o.n[ob];
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+    T* M = fac + o.fac_off[ob];
+    if (tid == 0) bad = 0;
+    deluxe_sum<T>(o, ob, n, M, slots);
+    __syncthreads();
+    const int nt = (n + 15) / 16;
+    for (int k0 = 0; k0 < n; k0 += BW) {
+        const int b = min(BW, n - k0);
+        // D, padded with the identity beyond the object
+        for (int e = tid; e < BW * BW; e += kWG) {
+            const int i = e % BW, j = e / BW;
+            Dk[i][j] = (i < b && j < b) ? M[(k0 + i) + (int64_t)(k0 + j) * n] : (i == j ? (T)1 : (T)0);
+        }
+        __syncthreads();
+        // Dk <- -D^{-1}: one entry per thread (BW * BW <= kWG), two barriers per pivot
+        {
+            const int i = tid % BW, j = tid / BW;
+            const bool mine = tid < BW * BW;
+            for (int k = 0; k < BW; ++k) {
+                T d = Dk[k][k], ci = mine ? Dk[i][k] : (T)0, cj = mine ? Dk[j][k] : (T)0, mij = mine ? Dk[i][j] : (T)0;
+                if (!(d > (T)0)) {
+                    if (tid == 0) bad = 1;
+                    d = (T)1;
+                }
+                const T rd = (T)1 / d;
+                __syncthreads();
+                if (mine) {
+                    T v;
+                    if (i == k) v = (j == k) ? -rd : cj * rd;
+                    else if (j == k) v = ci * rd;
+                    else v = mij - ci * cj * rd;
+                    Dk[i][j] = v;
+                }
+                __syncthreads();
+            }
+        }
+        // H = C Dk (rows in K included; they are overwritten below)
+        for (int r = tid; r < n; r += kWG) {
+            T cr[BW];
+#pragma unroll
+            for (int j = 0; j < BW; ++j) cr[j] = j < b ? M[r + (int64_t)(k0 + j) * n] : (T)0;
+#pragma unroll 1
+            for (int c = 0; c < BW; ++c) {
+                T acc = (T)0;
+#pragma unroll
+                for (int j = 0; j < BW; ++j) acc += cr[j] * Dk[j][c];
+                H[r * BW + c] = acc;
+            }
+        }
+        __syncthreads();
+        // M_RR += H C^T on 16 x 16 tiles; entries in the rows or columns K are
+        // left for the pivot write below (the columns K are only read here)
+        // two tiles per wave and pass, their loads issued together
+        constexpr int TP = 2, NW = kWG / 64;
+        for (int t0 = wv; t0 < nt * nt; t0 += TP * NW) {
+            typename Mfma<T>::acc acc[TP];
+            T bk[TP][BW / 4];
+#pragma unroll
+            for (int u = 0; u < TP; ++u) {
+                const int t = min(t0 + u * NW, nt * nt - 1);
+                const int I0 = (t % nt) * 16, col = (t / nt) * 16 + lr;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = I0 + Mfma<T>::row(lane, v);
+                    acc[u][v] = M[min(row, n - 1) + (int64_t)min(col, n - 1) * n];
+                }
+#pragma unroll
+                for (int kq = 0; kq < BW / 4; ++kq) {
+                    const int k = 4 * kq + lk;
+                    bk[u][kq] = M[min(col, n - 1) + (int64_t)(k0 + min(k, b - 1)) * n];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < TP; ++u) {
+                const int t = t0 + u * NW;
+                if (t >= nt * nt) continue;
+                const int I0 = (t % nt) * 16, col = (t / nt) * 16 + lr;
+#pragma unroll
+                for (int kq = 0; kq < BW / 4; ++kq) {
+                    const int k = 4 * kq + lk;
+                    const T a = (I0 + lr < n) ? H[(I0 + lr) * BW + k] : (T)0;
+                    const T bb = (k < b && col < n) ? bk[u][kq] : (T)0;
+                    acc[u] = Mfma<T>::mac(a, bb, acc[u]);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = I0 + Mfma<T>::row(lane, v);
+                    const bool rk = row >= k0 && row < k0 + b, ck = col >= k0 && col < k0 + b;
+                    if (row < n && col < n && !rk && !ck) M[row + (int64_t)col * n] = acc[u][v];
+                }
+            }
+        }
+        __syncthreads();
+        // pivot rows and columns: M_RK = -H, M_KR = -H^T, M_KK = Dk
+        for (int e = tid; e < n * b; e += kWG) {
+            const int r = e % n, c = e / n;
+            const T v = (r >= k0 && r < k0 + b) ? Dk[r - k0][c] : -H[r * BW + c];
+            M[r + (int64_t)(k0 + c) * n] = v;
+            M[(k0 + c) + (int64_t)r * n] = v;
+        }
+        __syncthreads();
+    }
+    deluxe_products<T, false>(o, ob, n, M, slots, dmat);
     if (tid == 0 && bad) info[ob] = 1;
 }
 
@@ -1787,6 +1934,17 @@ void launch_trsv_fb(hipStream_t s, int nb, const T* L, const int64_t* Loff, cons
                     const int64_t* xoff, int maxn, const WorkQueue& q) {
     launch_trsv_kern<T, true, true>(s, nb, L, Loff, n, x, xoff, maxn, q);
 }
+// Objects above DS_N dofs take the blocked sweep unless BDM_DELUXE_SCALAR=1
+// (the single-pivot sweep of k_deluxe_setup, kept for comparison).
+static bool deluxe_scalar_sweep() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = std::getenv("BDM_DELUXE_SCALAR");
+        v = (e && std::atoi(e) != 0) ? 1 : 0;
+    }
+    return v == 1;
+}
+
 template <typename T>
 void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, int ob0, int nob, int maxn, const T* slots, T* fac, T* dmat,
                          int* info) {
@@ -1821,6 +1979,11 @@ void launch_deluxe_setup(hipStream_t s, const ObjDesc& o, int ob0, int nob, int 
         const int cap = std::max(0, std::min(maxn * maxn, avail / (int)sizeof(T)));
         hipLaunchKernelGGL(k_deluxe_small<T>, dim3(nob), dim3(kWG), (size_t)cap * sizeof(T), s, o, slots, fac, dmat,
                            info, cap, ob0);
+        return;
+    }
+    if (maxn > DS_N && !deluxe_scalar_sweep()) {
+        hipLaunchKernelGGL(k_deluxe_blocked<T>, dim3(nob), dim3(kWG),
+                           (size_t)maxn * deluxe_block_width<T>() * sizeof(T), s, o, slots, fac, dmat, info, ob0);
         return;
     }
     const int avail = lds_max - (int)(DLX_MAXN * sizeof(T)) - 64;

@@ -152,6 +152,33 @@ def test_objects_above_512_dofs(scaling):
         S.close()
 
 
+@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 5e-5)])
+def test_blocked_deluxe_sweep_mixed_face_sizes(prec, tol):
+    """Faces of 198 dofs (above the 128 of the register sweep, not a
+    multiple of the 16- or 8-pivot blocks) beside faces of 36 and 44 dofs in
+    one launch: the blocked sweep inverts sum S with partial last blocks.
+    One BDDC application with deluxe scaling against the oracle, FP64 and
+    FP32 local factors."""
+    import paper_2101_02959_amd as P
+    mesh = Mesh(22, 18, 4, 0.01, (0, 11, 22), (0, 9, 18), (0, 2, 4))
+    ph, so = Physics(), SolverOpts()
+    prob = bidomain.Problem(mesh, ph, so.dt)
+    N = prob.N
+    dec = dd.Decomposition(mesh)
+    assert sorted({2 * len(o.nodes) for o in dec.faces}) == [36, 44, 198]
+    v, w = _state(N, 4)
+    B = bddc.BDDC(prob, dec, v, w)
+    S = P.Solver(mesh, ph, so, precision=prec)
+    try:
+        S.bdm_linearize(v, w)
+        for seed in (5, 6):
+            r = newton.project_range(np.random.default_rng(seed).standard_normal(2 * N), N)
+            z = _gauge(S.bdm_bddc_apply(r).cpu().numpy(), N)
+            assert_close(z, _gauge(B.apply(r), N), tol, N, f"bddc prec {prec}")
+    finally:
+        S.close()
+
+
 def test_objects_above_1024_dofs():
     """Faces of 1058 dofs (529 nodes: the face of an H/h = 24 subdomain,
     above the 1024 of every smaller case) on the z-cut of a 46 x 46 x 4 slab
