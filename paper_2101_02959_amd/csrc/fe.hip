@@ -644,15 +644,22 @@ __global__ void k_reaction_diag(FEParams p, const double* __restrict__ v, const 
 // the node-major tables (consecutive lanes read consecutive addresses), the
 // neighbour values from memory through the caches.  The coefficient tables
 // are the dominant traffic: 432 bytes per node against 40 for the vectors.
+// Consecutive workgroup ids go round robin to the 8 XCDs, so XCD x takes the
+// contiguous run of node blocks [x * per, (x + 1) * per): the y and z
+// neighbours of its nodes are then mostly its own, already in its L2.
+constexpr int GEN_WG = 256;
+
 template <int MODE>
-__global__ __launch_bounds__(256) void k_stencil_gen(FEParams p, const double* __restrict__ dg,
+__global__ __launch_bounds__(GEN_WG) void k_stencil_gen(FEParams p, const double* __restrict__ dg,
                                                      const double* __restrict__ xv, const double* __restrict__ xe,
                                                      const double* __restrict__ rv, const double* __restrict__ re,
                                                      const double* __restrict__ vn, const double* __restrict__ w,
                                                      const double* __restrict__ Is, double stim,
                                                      double* __restrict__ yv, double* __restrict__ ye) {
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= p.N) return;
+    const int64_t nblk = (p.N + GEN_WG - 1) / GEN_WG, per = (nblk + ST_XCD - 1) / ST_XCD;
+    const int64_t blk = (int64_t)(blockIdx.x % ST_XCD) * per + blockIdx.x / ST_XCD;
+    const int64_t n = blk * GEN_WG + threadIdx.x;
+    if (blk >= nblk || n >= p.N) return;
     const int64_t plane = (int64_t)p.nx1 * p.ny1;
     const int k = (int)(n / plane);
     const int64_t t = n - (int64_t)k * plane;
@@ -884,7 +891,8 @@ void launch_stencil_zm(hipStream_t s, const FEParams& p, Args... args) {
 template <int MODE, typename... Args>
 void launch_stencil(hipStream_t s, const FEParams& p, const double* st, Args... args) {
     if (p.stn) {
-        hipLaunchKernelGGL(k_stencil_gen<MODE>, dim3((unsigned)((p.N + 255) / 256)), dim3(256), 0, s, p, args...);
+        const int64_t nblk = (p.N + GEN_WG - 1) / GEN_WG, per = (nblk + ST_XCD - 1) / ST_XCD;
+        hipLaunchKernelGGL(k_stencil_gen<MODE>, dim3((unsigned)(per * ST_XCD)), dim3(GEN_WG), 0, s, p, args...);
         return;
     }
     switch (p.stencil_variant) {
