@@ -17,8 +17,6 @@ Meshes: equal and uneven subdomains of a coarse 12 x 10 x 6 grid (elements
 spanning 15 degrees of the shell), and 32 x 32 x 16 elements in 4 x 4 x 2
 subdomains (H/h = 8 as in the benchmark's local problems).
 """
-import math
-
 import numpy as np
 import pytest
 
@@ -177,18 +175,3 @@ def test_time_steps_ellipsoid(name, prec, method, linear, steps):
         assert np.max(v) > 1.0      # the stimulus has raised the potential
     finally:
         S.close()
-
-
-@pytest.mark.parametrize("bad", [{6: -math.pi / 2}, {7: math.pi / 2}, {0: 0.0}, {1: 1.0}, {9: 7.0}])
-def test_invalid_ellipsoid_parameters_are_refused(bad):
-    """Parameters outside 0 < a1 < a2 (likewise b, c), -pi/2 < theta_min <
-    theta_max < pi/2, phi_min < phi_max <= phi_min + 2 pi give BDM_E_ARG
-    before any device work."""
-    P = _P()
-    g = list(ELLIPSOID)
-    for k, x in bad.items():
-        g[k] = x
-    mesh = ellipsoid_mesh(4, 4, 4, 2, 2, 2, geometry=g)
-    with pytest.raises(P.BidomainError) as ei:
-        P.Solver(mesh, Physics(), SolverOpts())
-    assert ei.value.code == -1 and "ellipsoid" in str(ei.value)      # BDM_E_ARG
