@@ -1419,8 +1419,11 @@ __global__ __launch_bounds__(kWG) void k_trsv(const T* __restrict__ Lb, const in
 // pivoting for an SPD matrix: sweeping pivot k maps
 //   a_ij -> a_ij - a_ik a_kj / a_kk,  a_ik, a_kj -> a_ik / a_kk,  a_kk -> -1 / a_kk,
 // and sweeping every pivot leaves -(sum S)^{-1}; each step is one parallel
-// pass over the matrix (the matrix is symmetric, so row k equals column k).  The matrix lives in LDS when it fits (else in the
-// object's global workspace).  Then, for every sharing subdomain m, the
+// pass over the matrix (the matrix is symmetric, so row k equals column k).
+// Objects of up to 128 dofs sweep in registers (k_deluxe_small), edges and
+// other small objects in LDS or, when the matrix does not fit, in the
+// object's global workspace (k_deluxe_setup); larger faces sweep a block of
+// pivots per pass (k_deluxe_blocked).  Then, for every sharing subdomain m, the
 // operator E_m = S^(m) (sum S)^{-1} is formed: E_m g is the residual-side
 // split and E_m^T u the value-side average term, so the per-iteration deluxe
 // scaling is a set of dense GEMVs.  A non-positive pivot flags the object.
