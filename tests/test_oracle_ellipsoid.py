@@ -138,3 +138,36 @@ def test_ellipsoid_operators_symmetric_semidefinite_with_constant_kernel():
         ev = np.linalg.eigvalsh(A)
         assert ev[0] > -1e-12 * ev[-1] and ev[1] > 1e-8 * ev[-1]
     assert mass.min() > 0
+
+
+def test_ellipsoid_bddc_theory():
+    """The theory of Sec. 5 on the curved mesh: the local matrices sum to the
+    Jacobian, the BDDC-preconditioned spectrum is >= 1 on the range, and the
+    BDDC (interface) and FETI-DP deluxe spectra coincide apart from 0 and 1."""
+    from oracle import bddc, bidomain, dd, fetidp
+    m = ellipsoid_mesh(8, 8, 4, 2, 2, 2)
+    p = bidomain.Problem(m, Physics(), 0.05)
+    rng = np.random.default_rng(0)
+    v, w = rng.uniform(-10, 40, p.N), rng.uniform(0, 0.2, p.N)
+    dec = dd.Decomposition(m)
+    B = bddc.BDDC(p, dec, v, w)
+    J = p.jacobian(v, w)
+    assert abs(sum(B.loc[s].K_full for s in range(dec.nsub)) - J).max() < 1e-12 * abs(J).max()
+    n = 2 * p.N
+    Minv = np.column_stack([B.apply(e) for e in np.eye(n)])
+    ev = np.sort(np.linalg.eigvals(Minv @ J.toarray()).real)
+    assert abs(ev[0]) < 1e-9 and ev[1] > 1 - 1e-9
+    Sh, gd = B.schur_assembled()
+    cols = []
+    for i in range(len(gd)):
+        e = np.zeros(n)
+        e[gd[i]] = 1.0
+        cols.append(B.apply_interface(e)[gd])
+    evs = np.sort(np.linalg.eigvals(np.column_stack(cols) @ Sh).real)
+    F = fetidp.FETIDP(B)
+    Fm = np.column_stack([F.F(e) for e in np.eye(F.nlam)])
+    Mm = np.column_stack([F.precond(e) for e in np.eye(F.nlam)])
+    evf = np.sort(np.linalg.eigvals(Mm @ Fm).real)
+    bb, bf = evs[evs > 1 + 1e-8], evf[evf > 1 + 1e-8]
+    assert len(bb) == len(bf) and len(bb) > 10
+    np.testing.assert_allclose(bb, bf, rtol=1e-9)
