@@ -171,3 +171,16 @@ def test_ellipsoid_bddc_theory():
     bb, bf = evs[evs > 1 + 1e-8], evf[evf > 1 + 1e-8]
     assert len(bb) == len(bf) and len(bb) > 10
     np.testing.assert_allclose(bb, bf, rtol=1e-9)
+
+
+def test_ellipsoid_workload_is_the_test2_ellipsoid_mesh():
+    """The ellipsoid workload has the element counts and dof count of the
+    paper's Test 2 ellipsoid table (128 x 128 x 64 elements, 2,163,330 dofs,
+    also in tests/golden/paper_dof_counts.txt), and the paper's 256-process
+    partition cuts it into 16^3-element subdomains."""
+    from workload import ellipsoid_workload
+    wl = ellipsoid_workload((8, 8, 4))
+    m = wl.mesh
+    assert (m.nx, m.ny, m.nz) == (128, 128, 64) and 2 * m.nnodes == 2163330
+    assert m.nsub == 256 and {m.cuts_x[1], m.cuts_y[1], m.cuts_z[1]} == {16}
+    assert m.ellipsoid == ELLIPSOID
